@@ -1,0 +1,32 @@
+"""Choose the initial Hartree-Fock logit bias of a workload.
+
+Runs the oracle's tree sampler on the workload's model for a few bias values
+and prints the number of unique samples each gives.  The workloads' ``hf_bias``
+values were picked from this output (target: about 3e3 unique samples at 20
+spin-orbitals / 1e5 samples, about 2e4 at 30 spin-orbitals / 1e6 samples).
+
+    python -m oracle.calibrate_hf_bias fp32 2.5 3.0 3.5
+"""
+import sys
+import time
+
+from oracle.model import build_model
+from oracle.sampler import sample_tree
+from synth import make_transformer_params, workload
+
+
+def unique_count(name, bias, seed=0):
+    cfg, _, _, _ = workload(name)
+    params = make_transformer_params(cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg["d"],
+                                     cfg["n_layers"], seed=cfg["seed"], hf_bias=bias,
+                                     round_to=cfg.get("round_to"))
+    model = build_model(cfg, params)
+    configs, counts, _ = sample_tree(model, cfg["n_samples"], seed)
+    return len(configs)
+
+
+if __name__ == "__main__":
+    name = sys.argv[1]
+    for b in sys.argv[2:]:
+        t = time.time()
+        print(name, b, unique_count(name, float(b)), f"{time.time() - t:.1f}s", flush=True)

@@ -1,0 +1,18 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This package only *draws numbers*: one- and two-electron integrals shaped like
+small molecules, the workload descriptions, and the initial parameters of the
+amplitude networks.  It contains none of the method's arithmetic (no
+Hamiltonian construction, no amplitudes, no sampling), so that the oracle and
+the HIP path can both read the same inputs without sharing any computation.
+"""
+from .integrals import make_integrals
+from .params import (mlp_param_spec, transformer_param_spec, make_mlp_params,
+                     make_transformer_params, flatten_params, unflatten_params)
+from .workloads import WORKLOADS, workload, batching_molecules
+
+__all__ = [
+    "make_integrals", "mlp_param_spec", "transformer_param_spec",
+    "make_mlp_params", "make_transformer_params", "flatten_params",
+    "unflatten_params", "WORKLOADS", "workload", "batching_molecules",
+]

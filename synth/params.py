@@ -1,0 +1,103 @@
+"""Seeded initial parameters of the two amplitude networks, and their flat order.
+
+The flat order returned by ``*_param_spec`` is the canonical parameter vector
+layout that the C ABI takes (``amp_model_create``) and that ``amp_backward``
+writes gradients in.  Matrices are stored row-major with shape (in, out), so a
+layer computes ``y = x @ W + b``.
+
+Initial values: weights N(0, std), biases 0, layer-norm gains 1 and shifts 0,
+and for the transformer a per-position logit bias that is ``hf_bias`` on the
+Hartree-Fock token of each position and 0 elsewhere (the knob that sets how
+peaked the initial distribution is).  Every value is representable in float32;
+with ``round_to="bf16"`` every weight is also representable in bfloat16.
+"""
+import numpy as np
+
+
+def mlp_param_spec(n, hidden=64):
+    """Per-token MLP (one subnetwork per spatial orbital, NADE-like).
+
+    Subnetwork p reads the one-hot codes of tokens 0..p-1 (4p inputs) and
+    produces 4 logits followed by 4 phases.
+    """
+    spec = []
+    for p in range(n):
+        spec += [(f"mlp{p}.w1", (4 * p, hidden)), (f"mlp{p}.b1", (hidden,)),
+                 (f"mlp{p}.w2", (hidden, hidden)), (f"mlp{p}.b2", (hidden,)),
+                 (f"mlp{p}.w3", (hidden, 8)), (f"mlp{p}.b3", (8,))]
+    return spec
+
+
+def transformer_param_spec(n, d, n_layers, ffn, phase_hidden=256):
+    """Decoder-only transformer over n orbital tokens plus a phase MLP."""
+    spec = [("tok_emb", (5, d)), ("pos_emb", (n, d))]
+    for l in range(n_layers):
+        spec += [(f"l{l}.ln1_g", (d,)), (f"l{l}.ln1_b", (d,)),
+                 (f"l{l}.wqkv", (d, 3 * d)), (f"l{l}.bqkv", (3 * d,)),
+                 (f"l{l}.wo", (d, d)), (f"l{l}.bo", (d,)),
+                 (f"l{l}.ln2_g", (d,)), (f"l{l}.ln2_b", (d,)),
+                 (f"l{l}.w1", (d, ffn)), (f"l{l}.b1", (ffn,)),
+                 (f"l{l}.w2", (ffn, d)), (f"l{l}.b2", (d,))]
+    spec += [("lnf_g", (d,)), ("lnf_b", (d,)), ("whead", (d, 4)), ("bhead", (4,)),
+             ("logit_bias", (n, 4)),
+             ("ph_w1", (4 * n, phase_hidden)), ("ph_b1", (phase_hidden,)),
+             ("ph_w2", (phase_hidden, phase_hidden)), ("ph_b2", (phase_hidden,)),
+             ("ph_w3", (phase_hidden, 1)), ("ph_b3", (1,))]
+    return spec
+
+
+def _round(a, round_to):
+    a = np.asarray(a, dtype=np.float32)
+    if round_to == "bf16":
+        u = a.view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16   # round to nearest even
+        a = u.astype(np.uint32).view(np.float32)
+    return a.astype(np.float64)
+
+
+def _init(spec, seed, std, round_to, special):
+    rng = np.random.default_rng([seed, 0x5EED])
+    out = {}
+    for name, shape in spec:
+        base = name.split(".")[-1]
+        if name in special:
+            val = special[name]
+        elif base.endswith("_g"):
+            val = np.ones(shape)
+        elif base.startswith("b") or base.endswith("_b") or "_b" in base:
+            val = np.zeros(shape)
+        else:
+            val = rng.normal(0.0, std, size=shape)
+        out[name] = _round(val, round_to).reshape(shape)
+    return out
+
+
+def make_mlp_params(n, hidden=64, seed=0, std=0.02, round_to=None):
+    return _init(mlp_param_spec(n, hidden), seed, std, round_to, {})
+
+
+def make_transformer_params(n, n_alpha, n_beta, d, n_layers, ffn=None,
+                            phase_hidden=256, seed=0, std=0.02, hf_bias=0.0,
+                            round_to=None):
+    ffn = 4 * d if ffn is None else ffn
+    bias = np.zeros((n, 4))
+    for p in range(n):
+        hf_tok = int(p < n_alpha) + 2 * int(p < n_beta)
+        bias[p, hf_tok] = hf_bias
+    spec = transformer_param_spec(n, d, n_layers, ffn, phase_hidden)
+    return _init(spec, seed, std, round_to, {"logit_bias": bias})
+
+
+def flatten_params(params, spec, dtype=np.float64):
+    return np.concatenate([np.asarray(params[k], dtype=dtype).reshape(-1)
+                           for k, _ in spec]) if spec else np.zeros(0, dtype)
+
+
+def unflatten_params(flat, spec):
+    out, o = {}, 0
+    for name, shape in spec:
+        size = int(np.prod(shape))
+        out[name] = np.asarray(flat[o:o + size]).reshape(shape)
+        o += size
+    assert o == len(flat), (o, len(flat))
+    return out
