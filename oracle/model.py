@@ -101,7 +101,8 @@ class MLPModel(AmplitudeModel):
             inp = F.one_hot(toks[:, :p], 4).to(torch.float64).reshape(B, 4 * p)
             t = self.t
             h1 = torch.tanh(inp @ t[f"mlp{p}.w1"] + t[f"mlp{p}.b1"])
-            h2 = F.leaky_relu(h1 @ t[f"mlp{p}.w2"] + t[f"mlp{p}.b2"], 0.01)
+            z = h1 @ t[f"mlp{p}.w2"] + t[f"mlp{p}.b2"]
+            h2 = torch.where(z >= 0, z, 0.01 * z)     # the x >= 0 branch owns x = 0
             outs.append(h2 @ t[f"mlp{p}.w3"] + t[f"mlp{p}.b3"])
         return torch.stack(outs, 1)          # [B, n, 8]
 

@@ -5,7 +5,8 @@ layout that the C ABI takes (``amp_model_create``) and that ``amp_backward``
 writes gradients in.  Matrices are stored row-major with shape (in, out), so a
 layer computes ``y = x @ W + b``.
 
-Initial values: weights N(0, std), biases 0, layer-norm gains 1 and shifts 0,
+Initial values: weights N(0, std), biases and layer-norm shifts 0 (or
+N(0, bias_std) when asked, for tests away from activation kinks), gains 1,
 and for the transformer a per-position logit bias that is ``hf_bias`` on the
 Hartree-Fock token of each position and 0 elsewhere (the knob that sets how
 peaked the initial distribution is).  Every value is representable in float32;
@@ -55,7 +56,7 @@ def _round(a, round_to):
     return a.astype(np.float64)
 
 
-def _init(spec, seed, std, round_to, special):
+def _init(spec, seed, std, round_to, special, bias_std=0.0):
     rng = np.random.default_rng([seed, 0x5EED])
     out = {}
     for name, shape in spec:
@@ -65,27 +66,27 @@ def _init(spec, seed, std, round_to, special):
         elif base.endswith("_g"):
             val = np.ones(shape)
         elif base.startswith("b") or base.endswith("_b") or "_b" in base:
-            val = np.zeros(shape)
+            val = rng.normal(0.0, bias_std, size=shape) if bias_std else np.zeros(shape)
         else:
             val = rng.normal(0.0, std, size=shape)
         out[name] = _round(val, round_to).reshape(shape)
     return out
 
 
-def make_mlp_params(n, hidden=64, seed=0, std=0.02, round_to=None):
-    return _init(mlp_param_spec(n, hidden), seed, std, round_to, {})
+def make_mlp_params(n, hidden=64, seed=0, std=0.02, round_to=None, bias_std=0.0):
+    return _init(mlp_param_spec(n, hidden), seed, std, round_to, {}, bias_std)
 
 
 def make_transformer_params(n, n_alpha, n_beta, d, n_layers, ffn=None,
                             phase_hidden=256, seed=0, std=0.02, hf_bias=0.0,
-                            round_to=None):
+                            round_to=None, bias_std=0.0):
     ffn = 4 * d if ffn is None else ffn
     bias = np.zeros((n, 4))
     for p in range(n):
         hf_tok = int(p < n_alpha) + 2 * int(p < n_beta)
         bias[p, hf_tok] = hf_bias
     spec = transformer_param_spec(n, d, n_layers, ffn, phase_hidden)
-    return _init(spec, seed, std, round_to, {"logit_bias": bias})
+    return _init(spec, seed, std, round_to, {"logit_bias": bias}, bias_std)
 
 
 def flatten_params(params, spec, dtype=np.float64):

@@ -86,7 +86,7 @@ def _fd_check(model_factory, spec, h, eri, basis, H, idx, eps=1e-6):
 def test_gradient_matches_finite_differences_mlp(tiny):
     h, eri, sec, basis, H = tiny
     spec = mlp_param_spec(6, 64)
-    base = make_mlp_params(6, 64, seed=6, std=0.5)
+    base = make_mlp_params(6, 64, seed=6, std=0.5, bias_std=0.1)
 
     def factory(rg, flat=None):
         params = base
@@ -97,13 +97,15 @@ def test_gradient_matches_finite_differences_mlp(tiny):
 
     rng = np.random.default_rng(0)
     P = sum(int(np.prod(s)) for _, s in spec)
-    _fd_check(factory, spec, h, eri, basis, H, rng.choice(P, 12, replace=False))
+    # first subnetwork (bias-only input) plus random parameters elsewhere
+    idx = np.concatenate([[0, 1, 64, 4200], rng.choice(P, 12, replace=False)])
+    _fd_check(factory, spec, h, eri, basis, H, idx)
 
 
 def test_gradient_matches_finite_differences_transformer(tiny):
     h, eri, sec, basis, H = tiny
     spec = transformer_param_spec(6, 16, 1, 64, 32)
-    base = make_transformer_params(6, 2, 2, 16, 1, phase_hidden=32, seed=7, std=0.3)
+    base = make_transformer_params(6, 2, 2, 16, 1, phase_hidden=32, seed=7, std=0.3, bias_std=0.1)
 
     def factory(rg, flat=None):
         params = base
