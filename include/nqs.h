@@ -1,0 +1,256 @@
+/*
+ * nqs.h - C ABI of the MI355X (gfx950) hot path of symmetry-constrained
+ * autoregressive neural-quantum-state VMC for molecular Hamiltonians
+ * (A. Malyshev, J. M. Arrazola, A. I. Lvovsky, arXiv 2310.04166).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: NQS_OK (0) or a negative status.  No C++ exception or abort
+ *   crosses this boundary.  nqs_last_error() gives a message for the calling
+ *   thread's most recent failure.
+ * - Configurations are uint64 bit strings: bit j is the occupation of
+ *   spin-orbital j = 2p + s (p spatial orbital, s = 0 alpha, s = 1 beta), so
+ *   N = 2 n_spatial <= 64 qubits.  Token p of a configuration is
+ *   bit(2p) + 2 bit(2p+1) in {0 empty, 1 alpha, 2 beta, 3 both}.
+ * - "dev" pointers are device memory of the current HIP device, "host"
+ *   pointers host memory.  The caller owns every array it passes; the library
+ *   owns its handles (create / destroy) and its internal workspaces.
+ * - Work is ordered on the given stream (NULL = default stream).  Calls that
+ *   return a size on the host (sample_unique, local_energy, connected_pairs)
+ *   synchronise that stream before returning.
+ * - A handle may be used from one host thread at a time.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NQS_OK            0
+#define NQS_EINVAL       -1   /* bad argument (null pointer, size, mismatch)      */
+#define NQS_ECAPACITY    -2   /* output buffer too small; required size reported */
+#define NQS_EUNSUPPORTED -3   /* N > 64, sequence > 32 tokens, unknown kind, ...  */
+#define NQS_EHIP         -4   /* HIP runtime error or no usable gfx950 device     */
+#define NQS_ENOMEM       -5   /* device or host allocation failed                 */
+
+typedef struct nqs_ham nqs_ham;
+typedef struct nqs_model nqs_model;
+typedef void *nqs_stream;     /* a hipStream_t */
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *nqs_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Hamiltonian compiler                                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * ham_compile - second-quantised molecular Hamiltonian to Jordan-Wigner
+ * Pauli strings grouped by X/Y flip mask (paper: "System description",
+ * equation for H_SQ and the Jordan-Wigner encoding of the HF state).
+ *
+ *   H = sum_{pq,s} h1[p,q] a+_ps a_qs
+ *     + 1/2 sum_{pqrs,s,t} eri[p,q,r,s] a+_ps a+_rt a_st a_qs + e_core
+ *
+ * h1 (host, n_spatial^2 doubles, row-major, symmetric) and eri (host,
+ * n_spatial^4 doubles, chemists' (pq|rs), 8-fold symmetric) are read only.
+ * Each term is mapped with a_j = (prod_{k<j} Z_k)(X_j + iY_j)/2; Pauli
+ * strings with the same X/Y support f are one "flip group".  A string acts as
+ * P|x> = c (-1)^popcount(x & z) |x ^ f>, with the i-factors of its Y's folded
+ * into the real coefficient c, so that
+ *     <x ^ f| H |x> = sum_{t in group f} coef[t] (-1)^popcount(x & zmask[t]).
+ * Strings whose coefficients cancel (odd number of Y's, which vanish for a
+ * real symmetric H) are dropped; a magnitude above 1e-12 relative to the
+ * largest coefficient there means asymmetric integrals (NQS_EINVAL).
+ * Groups are sorted by flip ascending (the diagonal group, f = 0, first).
+ * Host work only; the tables go to the device on first use.
+ * (n_alpha, n_beta) is the target sector, that of the HF determinant.
+ * Errors: NQS_EINVAL (null, n_spatial < 1, electrons out of range,
+ * asymmetric integrals), NQS_EUNSUPPORTED (n_spatial > 32).
+ */
+int ham_compile(const double *h1, const double *eri, int n_spatial, double e_core,
+                int n_alpha, int n_beta, nqs_ham **out);
+
+/* Number of flip groups G and Pauli terms T of a compiled Hamiltonian. */
+int ham_info(const nqs_ham *ham, int64_t *n_groups, int64_t *n_terms);
+
+/* Host copies of the tables: flip[G] (ascending), off[G+1] (CSR offsets into
+ * the term arrays), zmask[T], coef[T].  Any pointer may be NULL. */
+int ham_tables(const nqs_ham *ham, uint64_t *flip, int64_t *off, uint64_t *zmask, double *coef);
+
+void ham_destroy(nqs_ham *ham);
+
+/* ------------------------------------------------------------------------ */
+/* Amplitude model                                                           */
+/* ------------------------------------------------------------------------ */
+
+#define NQS_MODEL_MLP         1   /* per-token NADE-like MLPs (Appendix B)      */
+#define NQS_MODEL_TRANSFORMER 2   /* decoder-only transformer + phase MLP       */
+
+#define NQS_FP64 1   /* every operation in double                            */
+#define NQS_FP32 2   /* every operation in float                             */
+#define NQS_BF16 3   /* forward GEMMs bf16 x bf16 -> fp32 on MFMA; LN, softmax,
+                        residual, log-softmax in fp32; backward in fp32       */
+
+#define NQS_MU  0    /* Mask-Unphysical on every level ("Pruning strategies") */
+#define NQS_DU  1    /* Discard-Unphysical on every level                     */
+#define NQS_MUD 2    /* MU on levels p < n - d, DU on the last d levels       */
+
+/*
+ * amp_model_create - an autoregressive amplitude psi(x) = prod_p psi_p(x_p|x_<p)
+ * (paper: ANQS product rule) over the n = dims[0] orbital tokens, with the
+ * conditionals masked by the (n_alpha, n_beta) sector according to
+ * strategy / d (paper: "Pruning strategies"; Algorithm 1 gives the mask).
+ *
+ * dims (host):
+ *   MLP:         {n, n_alpha, n_beta, hidden}
+ *   TRANSFORMER: {n, n_alpha, n_beta, d_model, n_layers, n_heads, ffn, phase_hidden}
+ * params (host, n_params doubles) is the canonical parameter vector: the
+ * concatenation of the tensors below, each row-major, matrices (in, out) so
+ * that a layer computes y = x W + b.
+ *   MLP, for p = 0..n-1:  w1 (4p, hidden), b1 (hidden), w2 (hidden, hidden),
+ *                         b2 (hidden), w3 (hidden, 8), b3 (8)
+ *      outputs 0..3 are the logits of tokens 0..3, outputs 4..7 their phases;
+ *      layer 1 tanh, layer 2 leaky ReLU (slope 0.01).
+ *   TRANSFORMER: tok_emb (5, d) [row 4 = BOS], pos_emb (n, d), then per layer
+ *      ln1_g (d), ln1_b (d), wqkv (d, 3d) [q | k | v], bqkv (3d), wo (d, d),
+ *      bo (d), ln2_g (d), ln2_b (d), w1 (d, ffn), b1 (ffn), w2 (ffn, d),
+ *      b2 (d); then lnf_g (d), lnf_b (d), whead (d, 4), bhead (4),
+ *      logit_bias (n, 4), ph_w1 (4n, ph), ph_b1 (ph), ph_w2 (ph, ph),
+ *      ph_b2 (ph), ph_w3 (ph, 1), ph_b3 (1).
+ *      Pre-LN blocks (eps 1e-5), causal attention with scale 1/sqrt(d/heads),
+ *      tanh-form GELU, input [BOS, x_0 .. x_{n-2}], output p = logits of
+ *      token p; phase = MLP(one-hot of all n tokens) with GELU.
+ * log|psi(x)| = 1/2 sum_p log softmax over allowed tokens; phase separate.
+ * Errors: NQS_EINVAL (sizes, n_params mismatch), NQS_EUNSUPPORTED (n > 32,
+ * d_model not a multiple of n_heads, unknown kind / precision / strategy),
+ * NQS_EHIP / NQS_ENOMEM (device).
+ */
+int amp_model_create(int kind, const int32_t *dims, int n_dims, const double *params,
+                     int64_t n_params, int precision, int strategy, int d,
+                     nqs_model **out);
+
+/* Number of parameters and the element size (8 or 4 bytes) of the model's
+ * device master parameter vector. */
+int amp_model_info(const nqs_model *m, int64_t *n_params, int32_t *param_bytes);
+
+/* Device pointer of the master parameter vector (canonical layout, double in
+ * FP64 mode, float otherwise).  After writing it, call amp_model_sync. */
+int amp_model_params(nqs_model *m, void **dev_params);
+
+/* Rebuild the model's derived device buffers (packed / bf16 weights) from the
+ * master parameters, on the stream. */
+int amp_model_sync(nqs_model *m, nqs_stream stream);
+
+/* Copy the master parameters to / from host doubles (n_params of them),
+ * converting to the master type; set also rebuilds the derived buffers.
+ * Both synchronise the device. */
+int amp_model_get_params(const nqs_model *m, double *host_out);
+int amp_model_set_params(nqs_model *m, const double *host_in);
+
+void amp_model_destroy(nqs_model *m);
+
+/*
+ * amp_forward - log|psi(x)| and phase phi(x) for n configurations.
+ * x (dev, n uint64), logabs / phase (dev, n doubles each, written).  A
+ * configuration outside the sector gets logabs = -inf.  n = 0 is a no-op.
+ */
+int amp_forward(nqs_model *m, const uint64_t *x, int64_t n, double *logabs,
+                double *phase, nqs_stream stream);
+
+/*
+ * amp_backward - parameter gradient of L = sum_l g_logabs[l] log|psi(x_l)|
+ *                                        + g_phase[l] phi(x_l)
+ * (the VMC gradient of the gradient equation in "Variational Monte Carlo" when
+ * g = 2 n_l / W (Re, Im)(E_loc,l - E); see vmc_weights).  Activations are
+ * recomputed internally, in chunks, from x.  x (dev, n), g_logabs / g_phase
+ * (dev, n doubles), grad (dev, n_params elements of the master parameter type,
+ * overwritten).  Accumulation is in double for every precision.
+ */
+int amp_backward(nqs_model *m, const uint64_t *x, int64_t n, const double *g_logabs,
+                 const double *g_phase, void *grad, nqs_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Sampler                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * sample_unique - autoregressive statistics sampling with symmetry pruning
+ * (paper: "Autoregressive statistics sampling"; "Pruning strategies").
+ * The tree is expanded one token (4 children) per level; a node's n_in
+ * samples are split by sequential conditional binomials
+ * n_k ~ B(rest, e_k / (e_k + ... + e_3)), e_k = exp(l_k - max) over the
+ * allowed tokens (0 otherwise); zero-count children are dropped.  Random
+ * numbers: Philox4x32-10 keyed by seed, counter (prefix lo32, prefix hi32,
+ * level + 64 j, block); binomials by inversion (n p < 10) or BTRS (Hormann
+ * 1993), all in double without contraction, so a draw depends only on
+ * (seed, node) and the node's logits.
+ * Outputs (dev): configs[capacity], counts[capacity], unique configurations in
+ * tree order (lexicographic in tokens).  n_unique and lost (host) receive the
+ * number written and the samples lost to unphysical children (0 under MU).
+ * Errors: NQS_ECAPACITY with *n_unique = required size, NQS_EINVAL.
+ */
+int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, uint64_t *configs,
+                  uint64_t *counts, int64_t capacity, int64_t *n_unique, uint64_t *lost,
+                  nqs_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Local energy and the counts-weighted reducer                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * connected_pairs - the bit kernel alone: for each x (dev, n), every flip
+ * group f != 0 with x ^ f inside the sector, in group order, and its matrix
+ * element <x^f|H|x>.  Writes offsets (dev, n+1 int64), xp / hval (dev,
+ * capacity each) and hdiag (dev, n doubles, <x|H|x>).  *n_pairs (host)
+ * receives the total.  NQS_ECAPACITY if capacity < total (nothing written but
+ * offsets and *n_pairs).  Any of xp, hval, hdiag may be NULL.
+ */
+int connected_pairs(nqs_ham *ham, const uint64_t *x, int64_t n, int64_t *offsets,
+                    uint64_t *xp, double *hval, double *hdiag, int64_t capacity,
+                    int64_t *n_pairs, nqs_stream stream);
+
+/*
+ * local_energy - E_loc(x) = sum_{x'} H_{x x'} psi(x') / psi(x) (paper:
+ * "Variational Monte Carlo", local-energy equation) over x itself and its
+ * structurally connected x' = x ^ f inside the sector.  psi(x') comes from
+ * the model (amplitude network on the x' batch); the ratio exp(dlog|psi| +
+ * i dphi) is formed per pair and accumulated in double.
+ * x, counts (dev, n uint64; counts may be NULL = all 1); logabs_x / phase_x
+ * (dev, n; may both be NULL, then computed here); eloc (dev, 2n doubles,
+ * re/im interleaved, written); sums (dev, 4 doubles, written):
+ *   W = sum n_l, sum n_l Re E_loc, sum n_l Im E_loc, sum n_l |E_loc|^2
+ * (the counts-weighted estimator of the energy-estimator equation).
+ * *n_pairs (host, may be NULL) receives the number of (x, x') pairs.
+ */
+int local_energy(nqs_ham *ham, nqs_model *m, const uint64_t *x, const uint64_t *counts,
+                 int64_t n, const double *logabs_x, const double *phase_x, double *eloc,
+                 double *sums, int64_t *n_pairs, nqs_stream stream);
+
+/*
+ * vmc_weights - upstream weights of the VMC gradient (paper: gradient
+ * equation in "Variational Monte Carlo"): with W = sums[0] and E =
+ * (sums[1] + i sums[2]) / W, g_logabs[l] = 2 n_l / W Re(E_loc,l - E) and
+ * g_phase[l] = 2 n_l / W Im(E_loc,l - E).  All dev arrays.
+ */
+int vmc_weights(const double *eloc, const uint64_t *counts, int64_t n, const double *sums,
+                double *g_logabs, double *g_phase, nqs_stream stream);
+
+/*
+ * adam_update - one Adam step (paper: optimisation with ADAM, default
+ * hyper-parameters) on n parameters of element size elem_bytes (4 or 8):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr mhat / (sqrt(vhat) + eps),
+ * with bias corrections for step t >= 1.  params, grad, m, v are dev arrays of
+ * that element type.
+ */
+int adam_update(void *params, const void *grad, void *m, void *v, int64_t n,
+                int elem_bytes, double lr, double b1, double b2, double eps,
+                int64_t t, nqs_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

@@ -1,0 +1,341 @@
+// C-ABI entry points: model handles, amplitudes, local energy, reducer, Adam.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ham.h"
+#include "model.h"
+#include "ops.h"
+
+namespace nqs {
+
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+// defined in eloc.hip
+void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const double *la_p,
+                       const double *ph_p, const double *la_x, const double *ph_x,
+                       const double *hdiag, double *eloc, hipStream_t s);
+void launch_reduce(const double *eloc, const uint64_t *counts, int64_t n, double *sums,
+                   hipStream_t s);
+void launch_weights(const double *eloc, const uint64_t *counts, int64_t n, const double *sums,
+                    double *gl, double *gp, hipStream_t s);
+void launch_adam(void *p, const void *g, void *m, void *v, int64_t n, int elem, double lr,
+                 double b1, double b2, double eps, int64_t t, hipStream_t s);
+
+namespace {
+
+void check_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+    throw Error(NQS_EHIP, "no HIP device available");
+}
+
+// Algorithm 1 evaluated bottom-up over token levels: phys[p][a][b] holds the
+// 4-bit set of tokens k whose child prefix (a + k&1, b + k>>1) at level p+1
+// can still reach (n_alpha, n_beta) at level n.
+std::vector<uint8_t> physical_children(int n, int na, int nb) {
+  const int S = n + 1;
+  std::vector<uint8_t> reach(size_t(S + 1) * S * S, 0);  // reach[p][a][b]
+  auto R = [&](int p, int a, int b) -> uint8_t & { return reach[(size_t(p) * S + a) * S + b]; };
+  for (int a = 0; a <= n; ++a)
+    for (int b = 0; b <= n; ++b) R(n, a, b) = (a == na && b == nb);
+  std::vector<uint8_t> kids(size_t(S) * S * S, 0);
+  for (int p = n - 1; p >= 0; --p)
+    for (int a = 0; a <= n; ++a)
+      for (int b = 0; b <= n; ++b) {
+        uint8_t mask = 0;
+        for (int k = 0; k < 4; ++k) {
+          const int a2 = a + (k & 1), b2 = b + (k >> 1);
+          if (a2 <= n && b2 <= n && R(p + 1, a2, b2)) mask |= uint8_t(1u << k);
+        }
+        kids[(size_t(p) * S + a) * S + b] = mask;
+        R(p, a, b) = mask != 0;
+      }
+  return kids;
+}
+
+}  // namespace
+}  // namespace nqs
+
+using namespace nqs;
+
+extern "C" const char *nqs_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const double *params,
+                                int64_t n_params, int precision, int strategy, int dlev,
+                                nqs_model **out) {
+  return guarded([&] {
+    NQS_REQUIRE(out && dims && params, NQS_EINVAL, "amp_model_create: null argument");
+    *out = nullptr;
+    NQS_REQUIRE(kind == NQS_MODEL_MLP || kind == NQS_MODEL_TRANSFORMER, NQS_EUNSUPPORTED,
+                "amp_model_create: unknown model kind");
+    NQS_REQUIRE(precision == NQS_FP64 || precision == NQS_FP32 || precision == NQS_BF16,
+                NQS_EUNSUPPORTED, "amp_model_create: unknown precision");
+    NQS_REQUIRE(strategy == NQS_MU || strategy == NQS_DU || strategy == NQS_MUD, NQS_EUNSUPPORTED,
+                "amp_model_create: unknown strategy");
+    NQS_REQUIRE(n_dims == (kind == NQS_MODEL_MLP ? 4 : 8), NQS_EINVAL,
+                "amp_model_create: wrong number of dims");
+    auto m = std::make_unique<nqs_model>();
+    m->kind = kind;
+    m->precision = precision;
+    m->strategy = strategy;
+    m->dlev = dlev;
+    m->n = dims[0];
+    m->na = dims[1];
+    m->nb = dims[2];
+    const int n = m->n;
+    NQS_REQUIRE(n >= 1, NQS_EINVAL, "amp_model_create: n < 1");
+    NQS_REQUIRE(n <= 32, NQS_EUNSUPPORTED, "amp_model_create: more than 32 tokens");
+    NQS_REQUIRE(m->na >= 0 && m->na <= n && m->nb >= 0 && m->nb <= n, NQS_EINVAL,
+                "amp_model_create: electron counts out of range");
+    NQS_REQUIRE(strategy != NQS_MUD || (dlev >= 0 && dlev <= n), NQS_EINVAL,
+                "amp_model_create: d out of range");
+    m->mask_levels = strategy == NQS_MU ? n : strategy == NQS_DU ? 0 : n - dlev;
+    int64_t o = 0;
+    auto add = [&](int64_t size) {
+      m->off.push_back(o);
+      o += size;
+    };
+    if (kind == NQS_MODEL_MLP) {
+      m->hid = dims[3];
+      NQS_REQUIRE(m->hid >= 1, NQS_EINVAL, "amp_model_create: hidden < 1");
+      NQS_REQUIRE(precision != NQS_BF16, NQS_EUNSUPPORTED, "amp_model_create: MLP has no bf16 mode");
+      const int h = m->hid;
+      for (int p = 0; p < n; ++p) {
+        add(int64_t(4) * p * h); add(h); add(int64_t(h) * h); add(h); add(int64_t(h) * 8); add(8);
+      }
+    } else {
+      m->d = dims[3];
+      m->L = dims[4];
+      m->H = dims[5];
+      m->F = dims[6];
+      m->PH = dims[7];
+      NQS_REQUIRE(m->d >= 1 && m->L >= 1 && m->H >= 1 && m->F >= 1 && m->PH >= 1, NQS_EINVAL,
+                  "amp_model_create: non-positive transformer dimension");
+      NQS_REQUIRE(m->d % m->H == 0 && m->d / m->H <= 64, NQS_EUNSUPPORTED,
+                  "amp_model_create: d_model must split into heads of at most 64");
+      const int d = m->d, F = m->F, PH = m->PH;
+      add(5 * d); add(int64_t(n) * d);
+      for (int l = 0; l < m->L; ++l) {
+        add(d); add(d); add(int64_t(d) * 3 * d); add(3 * d); add(int64_t(d) * d); add(d);
+        add(d); add(d); add(int64_t(d) * F); add(F); add(int64_t(F) * d); add(d);
+      }
+      add(d); add(d); add(int64_t(d) * 4); add(4); add(int64_t(n) * 4);
+      add(int64_t(4) * n * PH); add(PH); add(int64_t(PH) * PH); add(PH); add(PH); add(1);
+      if (precision == NQS_BF16)
+        NQS_REQUIRE(fused_supported(*m), NQS_EUNSUPPORTED,
+                    "amp_model_create: bf16 mode needs d_model 64 or 128, ffn 4 d_model, "
+                    "head dim 16, at most 16 tokens");
+    }
+    m->P = o;
+    NQS_REQUIRE(n_params == m->P, NQS_EINVAL,
+                "amp_model_create: n_params does not match the dimensions (expected " +
+                    std::to_string(m->P) + ")");
+    m->phys_host = physical_children(n, m->na, m->nb);
+    check_device();
+    HIP_OK(hipMemcpy(m->phys.reserve(m->phys_host.size()), m->phys_host.data(),
+                     m->phys_host.size(), hipMemcpyHostToDevice));
+    if (m->fp64()) {
+      HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 8), params, size_t(m->P) * 8,
+                       hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(params, params + m->P);
+      HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 4), f.data(), size_t(m->P) * 4,
+                       hipMemcpyHostToDevice));
+    }
+    if (precision == NQS_BF16) fused_pack(*m, nullptr);
+    HIP_OK(hipDeviceSynchronize());
+    *out = m.release();
+  });
+}
+
+extern "C" int amp_model_info(const nqs_model *m, int64_t *n_params, int32_t *param_bytes) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_info: null handle");
+    if (n_params) *n_params = m->P;
+    if (param_bytes) *param_bytes = int32_t(m->elem());
+  });
+}
+
+extern "C" int amp_model_params(nqs_model *m, void **dev_params) {
+  return guarded([&] {
+    NQS_REQUIRE(m && dev_params, NQS_EINVAL, "amp_model_params: null argument");
+    *dev_params = m->master.ptr;
+  });
+}
+
+extern "C" int amp_model_sync(nqs_model *m, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_sync: null handle");
+    if (m->precision == NQS_BF16) fused_pack(*m, as_stream(stream));
+  });
+}
+
+extern "C" int amp_model_get_params(const nqs_model *m, double *host_out) {
+  return guarded([&] {
+    NQS_REQUIRE(m && host_out, NQS_EINVAL, "amp_model_get_params: null argument");
+    HIP_OK(hipDeviceSynchronize());
+    if (m->fp64()) {
+      HIP_OK(hipMemcpy(host_out, m->master.ptr, size_t(m->P) * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> f(size_t(m->P));
+      HIP_OK(hipMemcpy(f.data(), m->master.ptr, size_t(m->P) * 4, hipMemcpyDeviceToHost));
+      std::copy(f.begin(), f.end(), host_out);
+    }
+  });
+}
+
+extern "C" int amp_model_set_params(nqs_model *m, const double *host_in) {
+  return guarded([&] {
+    NQS_REQUIRE(m && host_in, NQS_EINVAL, "amp_model_set_params: null argument");
+    HIP_OK(hipDeviceSynchronize());
+    if (m->fp64()) {
+      HIP_OK(hipMemcpy(m->master.ptr, host_in, size_t(m->P) * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(host_in, host_in + m->P);
+      HIP_OK(hipMemcpy(m->master.ptr, f.data(), size_t(m->P) * 4, hipMemcpyHostToDevice));
+    }
+    if (m->precision == NQS_BF16) fused_pack(*m, nullptr);
+    HIP_OK(hipDeviceSynchronize());
+  });
+}
+
+extern "C" void amp_model_destroy(nqs_model *m) { delete m; }
+
+extern "C" int amp_forward(nqs_model *m, const uint64_t *x, int64_t n, double *logabs,
+                           double *phase, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_forward: null handle");
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "amp_forward: negative n");
+    if (n == 0) return;
+    NQS_REQUIRE(x && (logabs || phase), NQS_EINVAL, "amp_forward: null pointer");
+    if (m->precision == NQS_BF16)
+      fused_forward(*m, x, n, logabs, phase, nullptr, -1, as_stream(stream));
+    else
+      model_forward(*m, x, n, logabs, phase, nullptr, as_stream(stream));
+  });
+}
+
+extern "C" int amp_backward(nqs_model *m, const uint64_t *x, int64_t n, const double *g_logabs,
+                            const double *g_phase, void *grad, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(m && grad, NQS_EINVAL, "amp_backward: null argument");
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "amp_backward: negative n");
+    NQS_REQUIRE(n == 0 || (x && g_logabs && g_phase), NQS_EINVAL, "amp_backward: null pointer");
+    model_backward(*m, x, n, g_logabs, g_phase, grad, as_stream(stream));
+  });
+}
+
+extern "C" int connected_pairs(nqs_ham *H, const uint64_t *x, int64_t n, int64_t *offsets,
+                               uint64_t *xp, double *hval, double *hdiag, int64_t capacity,
+                               int64_t *n_pairs, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(H && offsets && n_pairs, NQS_EINVAL, "connected_pairs: null argument");
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "connected_pairs: negative n");
+    hipStream_t s = as_stream(stream);
+    check_device();
+    H->upload();
+    int64_t *cnt = static_cast<int64_t *>(H->w_cnt.reserve(size_t(n > 0 ? n : 1) * 8));
+    if (n > 0) launch_count_pairs(*H, x, n, cnt, s);
+    launch_exclusive_scan(cnt, offsets, n, s);
+    int64_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, offsets + n, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *n_pairs = total;
+    NQS_REQUIRE(total <= capacity, NQS_ECAPACITY, "connected_pairs: capacity too small");
+    if (n > 0) launch_emit_pairs(*H, x, n, offsets, xp, hval, nullptr, hdiag, 0, s);
+  });
+}
+
+extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const uint64_t *counts,
+                            int64_t n, const double *logabs_x, const double *phase_x,
+                            double *eloc, double *sums, int64_t *n_pairs, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(H && m && sums, NQS_EINVAL, "local_energy: null argument");
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "local_energy: negative n");
+    NQS_REQUIRE(n == 0 || (x && eloc), NQS_EINVAL, "local_energy: null array");
+    NQS_REQUIRE((logabs_x == nullptr) == (phase_x == nullptr), NQS_EINVAL,
+                "local_energy: give both or neither of logabs_x, phase_x");
+    NQS_REQUIRE(H->n == m->n && H->n_alpha == m->na && H->n_beta == m->nb, NQS_EINVAL,
+                "local_energy: Hamiltonian and model describe different systems");
+    hipStream_t s = as_stream(stream);
+    check_device();
+    H->upload();
+    if (n_pairs) *n_pairs = 0;
+    if (n == 0) {
+      zero_async(sums, 4 * 8, s);
+      return;
+    }
+    int64_t *cnt = static_cast<int64_t *>(H->w_cnt.reserve(size_t(n) * 8));
+    int64_t *off = static_cast<int64_t *>(H->w_off.reserve(size_t(n + 1) * 8));
+    launch_count_pairs(*H, x, n, cnt, s);
+    launch_exclusive_scan(cnt, off, n, s);
+    std::vector<int64_t> off_h(size_t(n) + 1);
+    HIP_OK(hipMemcpyAsync(off_h.data(), off, size_t(n + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (n_pairs) *n_pairs = off_h[n];
+    double *hdiag = static_cast<double *>(H->w_diag.reserve(size_t(n) * 8));
+    const double *lax = logabs_x, *phx = phase_x;
+    if (!lax) {
+      double *a = static_cast<double *>(H->w_lax.reserve(size_t(n) * 8));
+      double *b = static_cast<double *>(H->w_phx.reserve(size_t(n) * 8));
+      if (m->precision == NQS_BF16) fused_forward(*m, x, n, a, b, nullptr, -1, s);
+      else model_forward(*m, x, n, a, b, nullptr, s);
+      lax = a;
+      phx = b;
+    }
+    // pairs are processed in slices of whole configurations
+    const int64_t cap = int64_t(1) << 24;
+    int64_t maxk = 0;
+    for (int64_t i = 0; i < n; ++i) maxk = std::max(maxk, off_h[i + 1] - off_h[i]);
+    const int64_t slice = std::max(cap, maxk);
+    auto *xp = static_cast<uint64_t *>(H->w_xp.reserve(size_t(slice) * 8));
+    auto *hv = static_cast<double *>(H->w_h.reserve(size_t(slice) * 8));
+    auto *la = static_cast<double *>(H->w_la.reserve(size_t(slice) * 8));
+    auto *ph = static_cast<double *>(H->w_ph.reserve(size_t(slice) * 8));
+    int64_t i0 = 0;
+    while (i0 < n) {
+      int64_t i1 = i0 + 1;
+      while (i1 < n && off_h[i1 + 1] - off_h[i0] <= slice) ++i1;
+      const int64_t np = off_h[i1] - off_h[i0];
+      launch_emit_pairs(*H, x + i0, i1 - i0, off + i0, xp, hv, nullptr, hdiag + i0, 0, s);
+      if (np > 0) {
+        if (m->precision == NQS_BF16) fused_forward(*m, xp, np, la, ph, nullptr, -1, s);
+        else model_forward(*m, xp, np, la, ph, nullptr, s);
+      }
+      launch_accumulate(i1 - i0, off + i0, hv, la, ph, lax + i0, phx + i0, hdiag + i0,
+                        eloc + 2 * i0, s);
+      i0 = i1;
+    }
+    launch_reduce(eloc, counts, n, sums, s);
+  });
+}
+
+extern "C" int vmc_weights(const double *eloc, const uint64_t *counts, int64_t n,
+                           const double *sums, double *g_logabs, double *g_phase,
+                           nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "vmc_weights: negative n");
+    if (n == 0) return;
+    NQS_REQUIRE(eloc && sums && g_logabs && g_phase, NQS_EINVAL, "vmc_weights: null pointer");
+    launch_weights(eloc, counts, n, sums, g_logabs, g_phase, as_stream(stream));
+  });
+}
+
+extern "C" int adam_update(void *params, const void *grad, void *mom, void *vel, int64_t n,
+                           int elem_bytes, double lr, double b1, double b2, double eps, int64_t t,
+                           nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(n >= 0 && t >= 1, NQS_EINVAL, "adam_update: n < 0 or t < 1");
+    NQS_REQUIRE(elem_bytes == 4 || elem_bytes == 8, NQS_EINVAL, "adam_update: elem_bytes not 4/8");
+    if (n == 0) return;
+    NQS_REQUIRE(params && grad && mom && vel, NQS_EINVAL, "adam_update: null pointer");
+    launch_adam(params, grad, mom, vel, n, elem_bytes, lr, b1, b2, eps, t, as_stream(stream));
+  });
+}

@@ -1,0 +1,261 @@
+// Local-energy bit work and the counts-weighted reducer (paper: "Variational
+// Monte Carlo": local-energy, energy-estimator and gradient equations).
+//
+// One 64-lane wavefront owns one sampled configuration x and sweeps the flip
+// groups of the compiled Hamiltonian 64 at a time.  For each group f the lane
+// forms x' = x ^ f and keeps it when x' has the sector's alpha and beta
+// electron counts (popcounts of the even and odd bits).  A wave ballot and a
+// popcount of the lanes below give each kept pair its output slot, so pairs
+// come out in group order without atomics.  A kept lane then sums its group's
+// Pauli terms, coef * (-1)^popcount(x & zmask), in double.
+#include "ham.h"
+
+namespace nqs {
+namespace {
+
+constexpr uint64_t kAlphaBits = 0x5555555555555555ull;
+constexpr uint64_t kBetaBits = 0xAAAAAAAAAAAAAAAAull;
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+
+__device__ inline bool in_sector(uint64_t xp, int na, int nb) {
+  return __popcll(xp & kAlphaBits) == na && __popcll(xp & kBetaBits) == nb;
+}
+
+__device__ inline double group_value(uint64_t x, int64_t t0, int64_t t1, const uint64_t *zmask,
+                                     const double *coef) {
+  double h = 0.0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const double c = coef[t];
+    h += (__popcll(x & zmask[t]) & 1) ? -c : c;
+  }
+  return h;
+}
+
+__global__ void __launch_bounds__(256) count_pairs_kernel(
+    const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip, int64_t G,
+    int na, int nb, int64_t *__restrict__ cnt) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  if (i >= n) return;
+  const uint64_t xi = x[i];
+  int64_t c = 0;
+  for (int64_t g0 = 1; g0 < G; g0 += kWave) {
+    const int64_t g = g0 + lane;
+    const bool keep = g < G && in_sector(xi ^ flip[g], na, nb);
+    c += __popcll(__ballot(keep));
+  }
+  if (lane == 0) cnt[i] = c;
+}
+
+__global__ void __launch_bounds__(256) emit_pairs_kernel(
+    const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip,
+    const int64_t *__restrict__ goff, const uint64_t *__restrict__ zmask,
+    const double *__restrict__ coef, int64_t G, int na, int nb, const int64_t *__restrict__ off,
+    uint64_t *__restrict__ xp, double *__restrict__ hval, int32_t *__restrict__ owner,
+    double *__restrict__ hdiag, int64_t owner_base) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  if (i >= n) return;
+  const uint64_t xi = x[i];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  int64_t base = off[i] - off[0];
+  for (int64_t g0 = 1; g0 < G; g0 += kWave) {
+    const int64_t g = g0 + lane;
+    const uint64_t f = (g < G) ? flip[g] : 0ull;
+    const bool keep = g < G && in_sector(xi ^ f, na, nb);
+    const uint64_t mask = __ballot(keep);
+    if (keep) {
+      const int64_t slot = base + __popcll(mask & below);
+      if (xp) xp[slot] = xi ^ f;
+      if (hval) hval[slot] = group_value(xi, goff[g], goff[g + 1], zmask, coef);
+      if (owner) owner[slot] = int32_t(owner_base + i);
+    }
+    base += __popcll(mask);
+  }
+  if (hdiag) {
+    // diagonal group: lanes split its terms, then a fixed-order wave reduction
+    double h = 0.0;
+    for (int64_t t = goff[0] + lane; t < goff[1]; t += kWave) {
+      const double c = coef[t];
+      h += (__popcll(xi & zmask[t]) & 1) ? -c : c;
+    }
+    for (int s = kWave / 2; s > 0; s >>= 1) h += __shfl_xor(h, s);
+    if (lane == 0) hdiag[i] = h;
+  }
+}
+
+// Exclusive scan of int64 counts; out has n+1 entries (out[n] = total).
+__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ in,
+                                                    int64_t *__restrict__ out, int64_t n) {
+  __shared__ int64_t warp_sums[16];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  for (int64_t b0 = 0; b0 < n; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = (i < n) ? in[i] : 0;
+    int64_t s = v;  // inclusive scan within the wave
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int64_t o = __shfl_up(s, d);
+      if (lane >= d) s += o;
+    }
+    if (lane == kWave - 1) warp_sums[w] = s;
+    __syncthreads();
+    int64_t prefix = carry;
+    for (int k = 0; k < w; ++k) prefix += warp_sums[k];
+    if (i < n) out[i] = prefix + s - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = prefix + s;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+// E_loc(x_i) = hdiag_i + sum_j H_ij exp((la'_j - la_i) + i (ph'_j - ph_i)), one
+// wave per x over its contiguous pairs, fixed-order reduction, double.
+__global__ void __launch_bounds__(256) accumulate_kernel(
+    int64_t n, const int64_t *__restrict__ off, const double *__restrict__ hval,
+    const double *__restrict__ la_p, const double *__restrict__ ph_p,
+    const double *__restrict__ la_x, const double *__restrict__ ph_x,
+    const double *__restrict__ hdiag, double *__restrict__ eloc) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  if (i >= n) return;
+  const int64_t j0 = off[i] - off[0], j1 = off[i + 1] - off[0];
+  const double lx = la_x[i], px = ph_x[i];
+  double re = 0.0, im = 0.0;
+  for (int64_t j = j0 + lane; j < j1; j += kWave) {
+    const double a = exp(la_p[j] - lx);
+    double s, c;
+    sincos(ph_p[j] - px, &s, &c);
+    re += hval[j] * a * c;
+    im += hval[j] * a * s;
+  }
+  for (int s = kWave / 2; s > 0; s >>= 1) {
+    re += __shfl_xor(re, s);
+    im += __shfl_xor(im, s);
+  }
+  if (lane == 0) {
+    eloc[2 * i] = hdiag[i] + re;
+    eloc[2 * i + 1] = im;
+  }
+}
+
+// sums = {W, sum n Re E, sum n Im E, sum n |E|^2}; one block, fixed order.
+__global__ void __launch_bounds__(1024) reduce_kernel(const double *__restrict__ eloc,
+                                                      const uint64_t *__restrict__ counts,
+                                                      int64_t n, double *__restrict__ sums) {
+  __shared__ double part[4][1024];
+  double a[4] = {0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double w = counts ? double(counts[i]) : 1.0;
+    const double re = eloc[2 * i], im = eloc[2 * i + 1];
+    a[0] += w;
+    a[1] += w * re;
+    a[2] += w * im;
+    a[3] += w * (re * re + im * im);
+  }
+  for (int k = 0; k < 4; ++k) part[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) sums[threadIdx.x] = part[threadIdx.x][0];
+}
+
+__global__ void weights_kernel(const double *__restrict__ eloc, const uint64_t *__restrict__ counts,
+                               int64_t n, const double *__restrict__ sums,
+                               double *__restrict__ gl, double *__restrict__ gp) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double W = sums[0];
+  const double er = sums[1] / W, ei = sums[2] / W;
+  const double w = 2.0 * (counts ? double(counts[i]) : 1.0) / W;
+  gl[i] = w * (eloc[2 * i] - er);
+  gp[i] = w * (eloc[2 * i + 1] - ei);
+}
+
+template <class T>
+__global__ void adam_kernel(T *__restrict__ p, const T *__restrict__ g, T *__restrict__ m,
+                            T *__restrict__ v, int64_t n, double lr, double b1, double b2,
+                            double eps, double c1, double c2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double gi = double(g[i]);
+  const double mi = b1 * double(m[i]) + (1.0 - b1) * gi;
+  const double vi = b2 * double(v[i]) + (1.0 - b2) * gi * gi;
+  m[i] = T(mi);
+  v[i] = T(vi);
+  p[i] = T(double(p[i]) - lr * (mi / c1) / (sqrt(vi / c2) + eps));
+}
+
+}  // namespace
+
+void launch_count_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, int64_t *cnt,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = ceil_div(n, kWavesPerBlock);
+  hipLaunchKernelGGL(count_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, n,
+                     H.d_flip.as<uint64_t>(), int64_t(H.flip.size()), H.n_alpha, H.n_beta, cnt);
+  HIP_LAUNCH_OK();
+}
+
+void launch_emit_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, const int64_t *off,
+                       uint64_t *xp, double *hval, int32_t *owner, double *hdiag,
+                       int64_t owner_base, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = ceil_div(n, kWavesPerBlock);
+  hipLaunchKernelGGL(emit_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, n,
+                     H.d_flip.as<uint64_t>(), H.d_off.as<int64_t>(), H.d_zmask.as<uint64_t>(),
+                     H.d_coef.as<double>(), int64_t(H.flip.size()), H.n_alpha, H.n_beta, off, xp,
+                     hval, owner, hdiag, owner_base);
+  HIP_LAUNCH_OK();
+}
+
+void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, in, out, n);
+  HIP_LAUNCH_OK();
+}
+
+void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const double *la_p,
+                       const double *ph_p, const double *la_x, const double *ph_x,
+                       const double *hdiag, double *eloc, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(ceil_div(n, kWavesPerBlock))), dim3(256), 0,
+                     s, n, off, hval, la_p, ph_p, la_x, ph_x, hdiag, eloc);
+  HIP_LAUNCH_OK();
+}
+
+void launch_reduce(const double *eloc, const uint64_t *counts, int64_t n, double *sums,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, eloc, counts, n, sums);
+  HIP_LAUNCH_OK();
+}
+
+void launch_weights(const double *eloc, const uint64_t *counts, int64_t n, const double *sums,
+                    double *gl, double *gp, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(weights_kernel, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s, eloc,
+                     counts, n, sums, gl, gp);
+  HIP_LAUNCH_OK();
+}
+
+void launch_adam(void *p, const void *g, void *m, void *v, int64_t n, int elem, double lr,
+                 double b1, double b2, double eps, int64_t t, hipStream_t s) {
+  if (n <= 0) return;
+  const double c1 = 1.0 - pow(b1, double(t)), c2 = 1.0 - pow(b2, double(t));
+  const dim3 grid(unsigned(ceil_div(n, 256)));
+  if (elem == 8)
+    hipLaunchKernelGGL(adam_kernel<double>, grid, dim3(256), 0, s, (double *)p, (const double *)g,
+                       (double *)m, (double *)v, n, lr, b1, b2, eps, c1, c2);
+  else
+    hipLaunchKernelGGL(adam_kernel<float>, grid, dim3(256), 0, s, (float *)p, (const float *)g,
+                       (float *)m, (float *)v, n, lr, b1, b2, eps, c1, c2);
+  HIP_LAUNCH_OK();
+}
+
+}  // namespace nqs

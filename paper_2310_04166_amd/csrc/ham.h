@@ -1,0 +1,36 @@
+// The compiled Hamiltonian: flip-grouped Pauli tables on the host and, after
+// first use, on the device.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+struct nqs_ham {
+  int n = 0;        // spatial orbitals
+  int N = 0;        // spin-orbitals (qubits)
+  int n_alpha = 0, n_beta = 0;
+  double e_core = 0.0;
+  std::vector<uint64_t> flip;   // [G] ascending; flip[0] == 0 (diagonal group)
+  std::vector<int64_t> off;     // [G+1]
+  std::vector<uint64_t> zmask;  // [T]
+  std::vector<double> coef;     // [T]
+
+  // device copies (uploaded on first use, on the device current at that time)
+  int device = -1;
+  nqs::DevBuf d_flip, d_off, d_zmask, d_coef;
+  // local_energy workspaces
+  nqs::DevBuf w_cnt, w_off, w_xp, w_h, w_owner, w_la, w_ph, w_diag, w_lax, w_phx;
+
+  void upload();
+};
+
+namespace nqs {
+// Device side of the bit work (eloc.hip).
+void launch_count_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, int64_t *cnt,
+                        hipStream_t s);
+void launch_emit_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, const int64_t *off,
+                       uint64_t *xp, double *hval, int32_t *owner, double *hdiag,
+                       int64_t owner_base, hipStream_t s);
+void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+}  // namespace nqs

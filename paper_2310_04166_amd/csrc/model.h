@@ -1,0 +1,62 @@
+// The amplitude model handle: dimensions, parameter layout, device buffers.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+struct nqs_model {
+  int kind = 0, precision = 0, strategy = 0, dlev = 0;
+  int n = 0, na = 0, nb = 0;          // tokens, sector
+  int d = 0, L = 0, H = 0, F = 0, PH = 0;  // transformer
+  int hid = 0;                        // MLP
+  int mask_levels = 0;                // positions p < mask_levels use masked conditionals
+  int64_t P = 0;                      // parameter count
+  std::vector<int64_t> off;           // parameter offsets, see param_index()
+  std::vector<uint8_t> phys_host;     // [(n+1)^3] 4-bit physical-child masks
+
+  nqs::DevBuf master;                 // canonical parameters (double in FP64, float otherwise)
+  nqs::DevBuf phys;                   // device copy of phys_host
+  nqs::DevBuf packed;                 // bf16 weights of the fused kernel
+  bool packed_valid = false;
+  nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
+  nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
+
+  bool fp64() const { return precision == NQS_FP64; }
+  size_t elem() const { return fp64() ? 8 : 4; }
+};
+
+namespace nqs {
+
+// Index of a named tensor in nqs_model::off (transformer layout).
+enum TfParam : int {
+  TF_TOK = 0, TF_POS = 1,
+  // per layer l: base 2 + 12 l + k
+  TF_LN1G = 0, TF_LN1B, TF_WQKV, TF_BQKV, TF_WO, TF_BO, TF_LN2G, TF_LN2B, TF_W1, TF_B1, TF_W2, TF_B2,
+};
+inline int tf_layer(int l, int k) { return 2 + 12 * l + k; }
+// after the layers: base 2 + 12 L + k
+enum TfTail : int { TF_LNFG = 0, TF_LNFB, TF_WHEAD, TF_BHEAD, TF_LBIAS, TF_PW1, TF_PB1, TF_PW2,
+                    TF_PB2, TF_PW3, TF_PB3, TF_NTAIL };
+inline int tf_tail(int L, int k) { return 2 + 12 * L + k; }
+// MLP: per position p: 6 p + k
+enum MlpParam : int { MLP_W1 = 0, MLP_B1, MLP_W2, MLP_B2, MLP_W3, MLP_B3 };
+
+// Forward of the layer-by-layer path.  logits (optional, [B*n*4] in T) keeps
+// the head outputs for the sampler; logabs / phase (optional, double).
+void model_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
+                   void *logits, hipStream_t s);
+// Conditional logits of token p for B prefixes (tokens >= p ignored), as
+// double [B*4] (host-order: node-major).
+void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, double *out4,
+                       hipStream_t s);
+void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
+                    const double *gp, void *grad, hipStream_t s);
+// Fused bf16 forward (tf_fused.hip).
+int64_t model_chunk(const nqs_model &m, bool bwd);
+void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
+                   double *cond_out, int cond_p, hipStream_t s);
+void fused_pack(nqs_model &m, hipStream_t s);
+bool fused_supported(const nqs_model &m);
+
+}  // namespace nqs

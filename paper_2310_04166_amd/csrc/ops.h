@@ -1,0 +1,61 @@
+// Building blocks of the layer-by-layer amplitude path (FP64 and FP32 modes,
+// and every backward pass): a tiled GEMM with fused epilogues, layer norm,
+// causal attention for short sequences, and column reductions.
+#pragma once
+
+#include "common.h"
+
+namespace nqs {
+
+enum Epi : int {
+  EPI_STORE = 0,   // C = AB + bias
+  EPI_GELU = 1,    // aux = AB + bias, C = gelu_tanh(aux)
+  EPI_TANH = 2,    // C = tanh(AB + bias)
+  EPI_LRELU = 3,   // aux = AB + bias, C = leaky_relu(aux, 0.01)
+  EPI_ADD = 4,     // C += AB + bias
+};
+
+// C[M,N] = op(A)[M,K] op(B)[K,N]; op(A)(i,k) = TA ? A[k*lda+i] : A[i*lda+k],
+// op(B)(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  With ksplit > 0 the K range is
+// cut into slices of ksplit, slice z writing C + z*slice_stride (EPI_STORE).
+template <class TI, class TO, bool TA, bool TB>
+void gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t lda, const TI *B, int64_t ldb,
+          TO *C, int64_t ldc, const TI *bias, TO *aux, int epi, hipStream_t s,
+          int64_t ksplit = 0, int64_t slice_stride = 0);
+
+// Deterministic column sums: acc[j] += sum_r Y[r*ld + j] (double accumulator).
+template <class T>
+void colsum_acc(const T *Y, int64_t R, int64_t N, int64_t ld, double *acc, double *scratch,
+                hipStream_t s);
+// acc[i] += sum_z part[z*len + i]
+void slices_acc(const double *part, int64_t nslices, int64_t len, double *acc, hipStream_t s);
+
+// Row-wise layer norm over d columns; mean/rstd may be null.
+template <class T>
+void layernorm(const T *x, int64_t R, int d, const T *g, const T *b, T *y, T *mean, T *rstd,
+               hipStream_t s);
+// dx (+)= LN backward; dyxh = dy * xhat (for the gain gradient).
+template <class T>
+void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
+                   const T *dy, T *dx, bool accumulate, T *dyxh, hipStream_t s);
+
+// Causal attention for B sequences of T tokens: qkv [B*T, 3d] -> o [B*T, d],
+// probs [B, H, T, T] (if non-null).
+template <class T>
+void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s);
+template <class T>
+void attention_bwd(const T *qkv, const T *probs, const T *dout, int64_t B, int T_, int d, int H,
+                   T *dqkv, hipStream_t s);
+
+// Elementwise helpers.
+template <class T>
+void gelu_bwd(const T *pre, T *dy, int64_t n, hipStream_t s);   // dy *= gelu'(pre)
+template <class T>
+void tanh_bwd(const T *y, T *dy, int64_t n, hipStream_t s);     // dy *= 1 - y^2
+template <class T>
+void lrelu_bwd(const T *pre, T *dy, int64_t n, hipStream_t s);  // dy *= (pre>=0 ? 1 : 0.01)
+template <class TS, class TD>
+void convert(const TS *src, TD *dst, int64_t n, hipStream_t s);
+void zero_async(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace nqs

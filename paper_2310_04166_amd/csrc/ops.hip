@@ -1,0 +1,427 @@
+// Layer-by-layer building blocks (see ops.h).  These kernels favour clarity:
+// they serve the FP64 and FP32 forward modes, every backward pass and the
+// sampler's conditionals in those modes; the bf16 forward has its own fused
+// kernel.
+#include "ops.h"
+
+namespace nqs {
+namespace {
+
+constexpr int kTile = 64, kTK = 16;
+
+template <class T>
+__device__ inline T gelu_tanh(T x) {
+  const T c = T(0.7978845608028654);  // sqrt(2/pi)
+  return T(0.5) * x * (T(1) + tanh(c * (x + T(0.044715) * x * x * x)));
+}
+template <class T>
+__device__ inline T gelu_tanh_grad(T x) {
+  const T c = T(0.7978845608028654);
+  const T u = c * (x + T(0.044715) * x * x * x);
+  const T t = tanh(u);
+  return T(0.5) * (T(1) + t) + T(0.5) * x * (T(1) - t * t) * c * (T(1) + T(3 * 0.044715) * x * x);
+}
+
+template <class TI, class TO, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, const TI *A,
+                                                   int64_t lda, const TI *B, int64_t ldb, TO *C,
+                                                   int64_t ldc, const TI *bias, TO *aux, int epi,
+                                                   int64_t ksplit, int64_t slice_stride) {
+  using Acc = TO;
+  __shared__ TI As[kTK][kTile + 1];
+  __shared__ TI Bs[kTK][kTile + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t m0 = int64_t(blockIdx.y) * kTile, n0 = int64_t(blockIdx.x) * kTile;
+  int64_t kb = 0, ke = K;
+  if (ksplit > 0) {
+    kb = int64_t(blockIdx.z) * ksplit;
+    ke = kb + ksplit < K ? kb + ksplit : K;
+    C += int64_t(blockIdx.z) * slice_stride;
+  }
+  Acc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = Acc(0);
+  for (int64_t k0 = kb; k0 < ke; k0 += kTK) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      int r, kk;
+      if (TA) { kk = idx / kTile; r = idx % kTile; } else { r = idx / kTK; kk = idx % kTK; }
+      const int64_t gi = m0 + r, gk = k0 + kk;
+      TI v = TI(0);
+      if (gi < M && gk < ke) v = TA ? A[gk * lda + gi] : A[gi * lda + gk];
+      As[kk][r] = v;
+      int c;
+      if (TB) { c = idx / kTK; kk = idx % kTK; } else { kk = idx / kTile; c = idx % kTile; }
+      const int64_t gj = n0 + c, gk2 = k0 + kk;
+      TI w = TI(0);
+      if (gj < N && gk2 < ke) w = TB ? B[gj * ldb + gk2] : B[gk2 * ldb + gj];
+      Bs[kk][c] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; ++kk) {
+      Acc a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Acc(As[kk][ty + 16 * i]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Acc(Bs[kk][tx + 16 * j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gi = m0 + ty + 16 * i;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gj = n0 + tx + 16 * j;
+      if (gj >= N) continue;
+      Acc v = acc[i][j] + (bias ? Acc(bias[gj]) : Acc(0));
+      TO *dst = C + gi * ldc + gj;
+      switch (epi) {
+        case EPI_GELU: aux[gi * ldc + gj] = TO(v); *dst = TO(gelu_tanh(v)); break;
+        case EPI_TANH: *dst = TO(tanh(v)); break;
+        case EPI_LRELU: aux[gi * ldc + gj] = TO(v); *dst = TO(v >= Acc(0) ? v : Acc(0.01) * v); break;
+        case EPI_ADD: *dst = TO(*dst + v); break;
+        default: *dst = TO(v);
+      }
+    }
+  }
+}
+
+// partial[y][j] = sum over rows of slice y of Y[r, j]; 64 columns x 4 row lanes per block
+template <class T>
+__global__ void __launch_bounds__(256) colsum_kernel(const T *Y, int64_t R, int64_t N, int64_t ld,
+                                                     int64_t rows_per, double *partial) {
+  __shared__ double red[4][64];
+  const int c = threadIdx.x % 64, q = threadIdx.x / 64;
+  const int64_t j = int64_t(blockIdx.x) * 64 + c;
+  const int64_t r0 = int64_t(blockIdx.y) * rows_per;
+  const int64_t r1 = r0 + rows_per < R ? r0 + rows_per : R;
+  double a = 0.0;
+  if (j < N)
+    for (int64_t r = r0 + q; r < r1; r += 4) a += double(Y[r * ld + j]);
+  red[q][c] = a;
+  __syncthreads();
+  if (q == 0 && j < N)
+    partial[int64_t(blockIdx.y) * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void slices_acc_kernel(const double *part, int64_t nslices, int64_t len, double *acc) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double a = 0.0;
+  for (int64_t z = 0; z < nslices; ++z) a += part[z * len + i];
+  acc[i] += a;
+}
+
+// one wave per row
+template <class T>
+__global__ void __launch_bounds__(256) layernorm_kernel(const T *x, int64_t R, int d, const T *g,
+                                                        const T *b, T *y, T *mean, T *rstd) {
+  const int lane = threadIdx.x % 64;
+  const int64_t r = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  if (r >= R) return;
+  const T *xr = x + r * d;
+  T s = 0;
+  for (int j = lane; j < d; j += 64) s += xr[j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const T mu = s / T(d);
+  T v = 0;
+  for (int j = lane; j < d; j += 64) v += (xr[j] - mu) * (xr[j] - mu);
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const T rs = T(1) / sqrt(v / T(d) + T(1e-5));
+  for (int j = lane; j < d; j += 64) y[r * d + j] = (xr[j] - mu) * rs * g[j] + b[j];
+  if (lane == 0) {
+    if (mean) mean[r] = mu;
+    if (rstd) rstd[r] = rs;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) layernorm_bwd_kernel(const T *x, const T *mean,
+                                                            const T *rstd, int64_t R, int d,
+                                                            const T *g, const T *dy, T *dx,
+                                                            bool accumulate, T *dyxh) {
+  const int lane = threadIdx.x % 64;
+  const int64_t r = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  if (r >= R) return;
+  const T mu = mean[r], rs = rstd[r];
+  T s1 = 0, s2 = 0;
+  for (int j = lane; j < d; j += 64) {
+    const T xh = (x[r * d + j] - mu) * rs;
+    const T gy = dy[r * d + j] * g[j];
+    s1 += gy;
+    s2 += gy * xh;
+    if (dyxh) dyxh[r * d + j] = dy[r * d + j] * xh;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  s1 /= T(d);
+  s2 /= T(d);
+  for (int j = lane; j < d; j += 64) {
+    const T xh = (x[r * d + j] - mu) * rs;
+    const T v = rs * (dy[r * d + j] * g[j] - s1 - xh * s2);
+    dx[r * d + j] = accumulate ? dx[r * d + j] + v : v;
+  }
+}
+
+// One 64-lane block per (sequence, head); T_ <= 32, dh <= 64.
+template <class T>
+__global__ void __launch_bounds__(64) attention_fwd_kernel(const T *qkv, int T_, int d, int H,
+                                                           T *o, T *probs) {
+  const int64_t b = blockIdx.x / H;
+  const int h = blockIdx.x % H, dh = d / H;
+  __shared__ T q[32][65], k[32][65], v[32][65];
+  const T *base = qkv + b * T_ * 3 * d;
+  for (int idx = threadIdx.x; idx < T_ * dh; idx += 64) {
+    const int t = idx / dh, j = idx % dh;
+    q[t][j] = base[t * 3 * d + h * dh + j];
+    k[t][j] = base[t * 3 * d + d + h * dh + j];
+    v[t][j] = base[t * 3 * d + 2 * d + h * dh + j];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= T_) return;
+  const T scale = T(1) / sqrt(T(dh));
+  T sc[32];
+  T mx = T(-1e300);
+  for (int s = 0; s <= t; ++s) {
+    T a = 0;
+    for (int j = 0; j < dh; ++j) a += q[t][j] * k[s][j];
+    sc[s] = a * scale;
+    mx = sc[s] > mx ? sc[s] : mx;
+  }
+  T z = 0;
+  for (int s = 0; s <= t; ++s) {
+    sc[s] = exp(sc[s] - mx);
+    z += sc[s];
+  }
+  for (int s = 0; s <= t; ++s) sc[s] /= z;
+  if (probs) {
+    T *pr = probs + ((b * H + h) * T_ + t) * T_;
+    for (int s = 0; s < T_; ++s) pr[s] = s <= t ? sc[s] : T(0);
+  }
+  T *orow = o + (b * T_ + t) * d + h * dh;
+  for (int j = 0; j < dh; ++j) {
+    T a = 0;
+    for (int s = 0; s <= t; ++s) a += sc[s] * v[s][j];
+    orow[j] = a;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(64) attention_bwd_kernel(const T *qkv, const T *probs,
+                                                           const T *dout, int T_, int d, int H,
+                                                           T *dqkv) {
+  const int64_t b = blockIdx.x / H;
+  const int h = blockIdx.x % H, dh = d / H;
+  __shared__ T q[32][65], k[32][65], v[32][65], dO[32][65];
+  __shared__ T P[32][33], dS[32][33];
+  const T *base = qkv + b * T_ * 3 * d;
+  for (int idx = threadIdx.x; idx < T_ * dh; idx += 64) {
+    const int t = idx / dh, j = idx % dh;
+    q[t][j] = base[t * 3 * d + h * dh + j];
+    k[t][j] = base[t * 3 * d + d + h * dh + j];
+    v[t][j] = base[t * 3 * d + 2 * d + h * dh + j];
+    dO[t][j] = dout[(b * T_ + t) * d + h * dh + j];
+  }
+  for (int idx = threadIdx.x; idx < T_ * T_; idx += 64)
+    P[idx / T_][idx % T_] = probs[(b * H + h) * T_ * T_ + idx];
+  __syncthreads();
+  const T scale = T(1) / sqrt(T(dh));
+  const int t = threadIdx.x;
+  if (t < T_) {
+    T dp[32];
+    T rowdot = 0;
+    for (int s = 0; s <= t; ++s) {
+      T a = 0;
+      for (int j = 0; j < dh; ++j) a += dO[t][j] * v[s][j];
+      dp[s] = a;
+      rowdot += a * P[t][s];
+    }
+    for (int s = 0; s < T_; ++s) dS[t][s] = s <= t ? P[t][s] * (dp[s] - rowdot) : T(0);
+  }
+  __syncthreads();
+  T *drow = dqkv + b * T_ * 3 * d;
+  if (t < T_) {
+    for (int j = 0; j < dh; ++j) {
+      T aq = 0, ak = 0, av = 0;
+      for (int s = 0; s < T_; ++s) {
+        aq += dS[t][s] * k[s][j];   // dQ[t] = sum_s dS[t,s] K[s]
+        ak += dS[s][t] * q[s][j];   // dK[t] = sum_s dS[s,t] Q[s]
+        av += P[s][t] * dO[s][j];   // dV[t] = sum_s P[s,t] dO[s]
+      }
+      drow[t * 3 * d + h * dh + j] = aq * scale;
+      drow[t * 3 * d + d + h * dh + j] = ak * scale;
+      drow[t * 3 * d + 2 * d + h * dh + j] = av;
+    }
+  }
+}
+
+template <class T>
+__global__ void gelu_bwd_kernel(const T *pre, T *dy, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dy[i] *= gelu_tanh_grad(pre[i]);
+}
+template <class T>
+__global__ void tanh_bwd_kernel(const T *y, T *dy, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dy[i] *= T(1) - y[i] * y[i];
+}
+template <class T>
+__global__ void lrelu_bwd_kernel(const T *pre, T *dy, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dy[i] *= pre[i] >= T(0) ? T(1) : T(0.01);
+}
+template <class TS, class TD>
+__global__ void convert_kernel(const TS *src, TD *dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = TD(src[i]);
+}
+__global__ void zero_kernel(uint32_t *p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline dim3 grid1(int64_t n, int b = 256) { return dim3(unsigned(ceil_div(n, b))); }
+
+}  // namespace
+
+template <class TI, class TO, bool TA, bool TB>
+void gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t lda, const TI *B, int64_t ldb,
+          TO *C, int64_t ldc, const TI *bias, TO *aux, int epi, hipStream_t s, int64_t ksplit,
+          int64_t slice_stride) {
+  if (M <= 0 || N <= 0) return;
+  const unsigned z = ksplit > 0 ? unsigned(ceil_div(K, ksplit)) : 1u;
+  dim3 grid(unsigned(ceil_div(N, kTile)), unsigned(ceil_div(M, kTile)), z);
+  hipLaunchKernelGGL((gemm_kernel<TI, TO, TA, TB>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                     C, ldc, bias, aux, epi, ksplit, slice_stride);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void colsum_acc(const T *Y, int64_t R, int64_t N, int64_t ld, double *acc, double *scratch,
+                hipStream_t s) {
+  if (R <= 0 || N <= 0) return;
+  const int64_t slices = R < 4096 ? 1 : 64;
+  const int64_t rows_per = ceil_div(R, slices);
+  hipLaunchKernelGGL(colsum_kernel<T>, dim3(unsigned(ceil_div(N, 64)), unsigned(slices)), dim3(256),
+                     0, s, Y, R, N, ld, rows_per, scratch);
+  HIP_LAUNCH_OK();
+  slices_acc(scratch, slices, N, acc, s);
+}
+
+void slices_acc(const double *part, int64_t nslices, int64_t len, double *acc, hipStream_t s) {
+  if (len <= 0) return;
+  hipLaunchKernelGGL(slices_acc_kernel, grid1(len), dim3(256), 0, s, part, nslices, len, acc);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void layernorm(const T *x, int64_t R, int d, const T *g, const T *b, T *y, T *mean, T *rstd,
+               hipStream_t s) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(layernorm_kernel<T>, grid1(R, 4), dim3(256), 0, s, x, R, d, g, b, y, mean, rstd);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
+                   const T *dy, T *dx, bool accumulate, T *dyxh, hipStream_t s) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(layernorm_bwd_kernel<T>, grid1(R, 4), dim3(256), 0, s, x, mean, rstd, R, d, g,
+                     dy, dx, accumulate, dyxh);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s) {
+  if (B <= 0) return;
+  NQS_REQUIRE(T_ <= 32 && d / H <= 64, NQS_EUNSUPPORTED, "attention: sequence > 32 or head dim > 64");
+  hipLaunchKernelGGL(attention_fwd_kernel<T>, dim3(unsigned(B * H)), dim3(64), 0, s, qkv, T_, d, H,
+                     o, probs);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void attention_bwd(const T *qkv, const T *probs, const T *dout, int64_t B, int T_, int d, int H,
+                   T *dqkv, hipStream_t s) {
+  if (B <= 0) return;
+  NQS_REQUIRE(T_ <= 32 && d / H <= 64, NQS_EUNSUPPORTED, "attention: sequence > 32 or head dim > 64");
+  hipLaunchKernelGGL(attention_bwd_kernel<T>, dim3(unsigned(B * H)), dim3(64), 0, s, qkv, probs,
+                     dout, T_, d, H, dqkv);
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+void gelu_bwd(const T *pre, T *dy, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gelu_bwd_kernel<T>, grid1(n), dim3(256), 0, s, pre, dy, n);
+  HIP_LAUNCH_OK();
+}
+template <class T>
+void tanh_bwd(const T *y, T *dy, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(tanh_bwd_kernel<T>, grid1(n), dim3(256), 0, s, y, dy, n);
+  HIP_LAUNCH_OK();
+}
+template <class T>
+void lrelu_bwd(const T *pre, T *dy, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(lrelu_bwd_kernel<T>, grid1(n), dim3(256), 0, s, pre, dy, n);
+  HIP_LAUNCH_OK();
+}
+template <class TS, class TD>
+void convert(const TS *src, TD *dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((convert_kernel<TS, TD>), grid1(n), dim3(256), 0, s, src, dst, n);
+  HIP_LAUNCH_OK();
+}
+void zero_async(void *p, size_t bytes, hipStream_t s) {
+  // a fill kernel rather than a memset node, so that graph capture stays safe
+  const int64_t words = int64_t((bytes + 3) / 4);
+  if (words <= 0) return;
+  hipLaunchKernelGGL(zero_kernel, grid1(words), dim3(256), 0, s, static_cast<uint32_t *>(p), words);
+  HIP_LAUNCH_OK();
+}
+
+#define INST_T(T)                                                                               \
+  template void colsum_acc<T>(const T *, int64_t, int64_t, int64_t, double *, double *,         \
+                              hipStream_t);                                                      \
+  template void layernorm<T>(const T *, int64_t, int, const T *, const T *, T *, T *, T *,      \
+                             hipStream_t);                                                       \
+  template void layernorm_bwd<T>(const T *, const T *, const T *, int64_t, int, const T *,      \
+                                 const T *, T *, bool, T *, hipStream_t);                        \
+  template void attention_fwd<T>(const T *, int64_t, int, int, int, T *, T *, hipStream_t);     \
+  template void attention_bwd<T>(const T *, const T *, const T *, int64_t, int, int, int, T *,  \
+                                 hipStream_t);                                                   \
+  template void gelu_bwd<T>(const T *, T *, int64_t, hipStream_t);                              \
+  template void tanh_bwd<T>(const T *, T *, int64_t, hipStream_t);                              \
+  template void lrelu_bwd<T>(const T *, T *, int64_t, hipStream_t);                             \
+  template void gemm<T, T, false, false>(int64_t, int64_t, int64_t, const T *, int64_t,         \
+                                         const T *, int64_t, T *, int64_t, const T *, T *, int, \
+                                         hipStream_t, int64_t, int64_t);                         \
+  template void gemm<T, T, false, true>(int64_t, int64_t, int64_t, const T *, int64_t,          \
+                                        const T *, int64_t, T *, int64_t, const T *, T *, int,  \
+                                        hipStream_t, int64_t, int64_t);                          \
+  template void gemm<T, double, true, false>(int64_t, int64_t, int64_t, const T *, int64_t,     \
+                                             const T *, int64_t, double *, int64_t, const T *,  \
+                                             double *, int, hipStream_t, int64_t, int64_t);
+
+INST_T(float)
+INST_T(double)
+template void convert<double, float>(const double *, float *, int64_t, hipStream_t);
+template void convert<float, double>(const float *, double *, int64_t, hipStream_t);
+template void convert<double, double>(const double *, double *, int64_t, hipStream_t);
+
+}  // namespace nqs

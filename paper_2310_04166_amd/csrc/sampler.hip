@@ -1,0 +1,256 @@
+// Autoregressive statistics sampling with symmetry pruning (paper:
+// "Autoregressive statistics sampling"; "Pruning strategies"; Algorithm 1 for
+// the physicality table).
+//
+// The whole tree walk stays on the GPU: per level, the model gives the four
+// logits of every frontier node, one thread per node splits the node's samples
+// over its children with sequential conditional binomials, and a scan
+// compacts the children that received samples into the next frontier (children
+// of node i in order k = 0..3, so the frontier stays in tree order).
+//
+// Random numbers are Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed
+// by the 64-bit seed with counter (prefix lo32, prefix hi32, level + 64 j,
+// block), j being which of the node's three binomials is drawn.  Binomials:
+// inversion by sequential search for n p < 10, otherwise BTRS (W. Hormann,
+// J. Statist. Comput. Simul. 46, 1993).  All of this is double precision
+// without contraction, so a draw depends only on (seed, node, logits).
+#include <cmath>
+
+#include "ham.h"
+#include "model.h"
+
+#pragma clang fp contract(off)
+
+namespace nqs {
+namespace {
+
+constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+constexpr uint64_t kAlphaBits = 0x5555555555555555ull;
+constexpr uint64_t kBetaBits = 0xAAAAAAAAAAAAAAAAull;
+
+struct Uniforms {
+  uint32_t c0, c1, c2, c3, k0, k1;
+  double buf[2];
+  int nbuf;
+
+  __device__ Uniforms(uint64_t seed, uint64_t prefix, int level, int j)
+      : c0(uint32_t(prefix)), c1(uint32_t(prefix >> 32)), c2(uint32_t(level + 64 * j)), c3(0),
+        k0(uint32_t(seed)), k1(uint32_t(seed >> 32)), nbuf(0) {}
+
+  __device__ static double unit(uint32_t hi, uint32_t lo) {
+    return ((double(hi >> 6) * 67108864.0 + double(lo >> 6)) + 0.5) * (1.0 / 4503599627370496.0);
+  }
+
+  __device__ double operator()() {
+    if (nbuf == 0) {
+      uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3, a = k0, b = k1;
+      for (int r = 0; r < 10; ++r) {
+        if (r) {
+          a += kW0;
+          b += kW1;
+        }
+        const uint64_t p0 = uint64_t(kM0) * x0, p1 = uint64_t(kM1) * x2;
+        const uint32_t y0 = uint32_t(p1 >> 32) ^ x1 ^ a, y1 = uint32_t(p1);
+        const uint32_t y2 = uint32_t(p0 >> 32) ^ x3 ^ b, y3 = uint32_t(p0);
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+      }
+      ++c3;
+      buf[0] = unit(x2, x3);  // second draw of the block
+      buf[1] = unit(x0, x1);  // first draw of the block
+      nbuf = 2;
+    }
+    return buf[--nbuf];
+  }
+};
+
+__device__ double log_factorial(int64_t k) {
+  if (k < 10) {
+    double f = 1.0;
+    for (int64_t i = 2; i <= k; ++i) f *= double(i);
+    return log(f);
+  }
+  const double k1 = double(k) + 1.0;
+  const double r = 1.0 / (k1 * k1);
+  return (((double(k) + 0.5) * log(k1) - k1) + 0.5 * log(2.0 * 3.141592653589793)) +
+         (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0) * r) * r) / k1;
+}
+
+__device__ int64_t binomial_inversion(int64_t n, double p, Uniforms &uni) {
+  const double q = 1.0 - p;
+  const double s = p / q;
+  const double a = double(n + 1) * s;
+  const double r0 = pow(q, double(n));
+  while (true) {
+    double r = r0;
+    double u = uni();
+    int64_t k = 0;
+    while (u >= r) {
+      u -= r;
+      ++k;
+      if (k > n) break;
+      r *= a / double(k) - s;
+    }
+    if (k <= n) return k;
+  }
+}
+
+__device__ int64_t binomial_btrs(int64_t n, double p, Uniforms &uni) {
+  const double q = 1.0 - p;
+  const double spq = sqrt((double(n) * p) * q);
+  const double b = 1.15 + 2.53 * spq;
+  const double a = (-0.0873 + 0.0248 * b) + 0.01 * p;
+  const double c = double(n) * p + 0.5;
+  const double vr = 0.92 - 4.2 / b;
+  const double alpha = (2.83 + 5.1 / b) * spq;
+  const double lpq = log(p / q);
+  const int64_t m = int64_t(floor(double(n + 1) * p));
+  const double h = log_factorial(m) + log_factorial(n - m);
+  while (true) {
+    const double u = uni() - 0.5;
+    double v = uni();
+    const double us = 0.5 - fabs(u);
+    const double kf = floor(((2.0 * a) / us + b) * u + c);
+    if (kf < 0.0 || kf > double(n)) continue;
+    const int64_t k = int64_t(kf);
+    if (us >= 0.07 && v <= vr) return k;
+    v = log((v * alpha) / (a / (us * us) + b));
+    if (v <= ((h - log_factorial(k)) - log_factorial(n - k)) + double(k - m) * lpq) return k;
+  }
+}
+
+__device__ int64_t binomial(int64_t n, double p, Uniforms &uni) {
+  if (n == 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  const bool flip = p > 0.5;
+  const double pp = flip ? 1.0 - p : p;
+  const int64_t k = (double(n) * pp < 10.0) ? binomial_inversion(n, pp, uni)
+                                            : binomial_btrs(n, pp, uni);
+  return flip ? n - k : k;
+}
+
+// One thread per frontier node: split its samples over the four tokens.
+__global__ void split_kernel(const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ cnt,
+                             const double *__restrict__ logits, int64_t B, int p, int n,
+                             int mask_levels, const uint8_t *__restrict__ phys, uint64_t seed,
+                             uint64_t *__restrict__ child, uint64_t *__restrict__ flag,
+                             unsigned long long *__restrict__ lost) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t x = prefix[i];
+  const int a = __popcll(x & kAlphaBits), b = __popcll(x & kBetaBits);
+  const int ph = phys[(p * (n + 1) + a) * (n + 1) + b];
+  const int allow = p < mask_levels ? ph : 0xF;
+  const double *l = logits + 4 * i;
+  double mx = -INFINITY;
+  for (int k = 0; k < 4; ++k)
+    if ((allow >> k) & 1) mx = fmax(mx, l[k]);
+  double e[4];
+  for (int k = 0; k < 4; ++k) e[k] = ((allow >> k) & 1) ? exp(l[k] - mx) : 0.0;
+  int64_t out[4] = {0, 0, 0, 0};
+  int64_t rest = int64_t(cnt[i]);
+  for (int k = 0; k < 3; ++k) {
+    if (rest == 0) break;
+    double tail = e[k];
+    for (int j = k + 1; j < 4; ++j) tail = tail + e[j];
+    if (e[k] == tail) {
+      out[k] = rest;
+    } else {
+      Uniforms uni(seed, x, p, k);
+      out[k] = binomial(rest, e[k] / tail, uni);
+    }
+    rest -= out[k];
+  }
+  out[3] += rest;
+  unsigned long long dropped = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (!((ph >> k) & 1)) {
+      dropped += uint64_t(out[k]);
+      out[k] = 0;
+    }
+    child[4 * i + k] = uint64_t(out[k]);
+    flag[4 * i + k] = out[k] > 0 ? 1 : 0;
+  }
+  if (dropped) atomicAdd(lost, dropped);
+}
+
+__global__ void compact_kernel(const uint64_t *__restrict__ prefix,
+                               const uint64_t *__restrict__ child, const int64_t *__restrict__ off,
+                               int64_t B4, int p, uint64_t *__restrict__ npre,
+                               uint64_t *__restrict__ ncnt) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= B4) return;
+  const uint64_t c = child[j];
+  if (c == 0) return;
+  const int k = int(j & 3);
+  const int64_t o = off[j];
+  npre[o] = prefix[j >> 2] | (uint64_t(k) << (2 * p));
+  ncnt[o] = c;
+}
+
+__global__ void init_kernel(uint64_t *pre, uint64_t *cnt, uint64_t n_samples,
+                            unsigned long long *lost) {
+  pre[0] = 0;
+  cnt[0] = n_samples;
+  *lost = 0;
+}
+
+}  // namespace
+}  // namespace nqs
+
+using namespace nqs;
+
+extern "C" int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, uint64_t *configs,
+                             uint64_t *counts, int64_t capacity, int64_t *n_unique, uint64_t *lost,
+                             nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(m && n_unique, NQS_EINVAL, "sample_unique: null argument");
+    NQS_REQUIRE(capacity >= 0, NQS_EINVAL, "sample_unique: negative capacity");
+    hipStream_t s = as_stream(stream);
+    int64_t B = 1;
+    auto *lost_d = static_cast<unsigned long long *>(m->s_lost.reserve(8));
+    int cur = 0;
+    m->s_pre[0].reserve(8);
+    m->s_cnt[0].reserve(8);
+    hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1), 0, s, m->s_pre[0].as<uint64_t>(),
+                       m->s_cnt[0].as<uint64_t>(), n_samples, lost_d);
+    HIP_LAUNCH_OK();
+    if (n_samples == 0) B = 0;
+    for (int p = 0; p < m->n && B > 0; ++p) {
+      double *cond = static_cast<double *>(m->s_cond.reserve(size_t(B) * 4 * 8));
+      model_cond_logits(*m, m->s_pre[cur].as<uint64_t>(), B, p, cond, s);
+      auto *child = static_cast<uint64_t *>(m->s_child.reserve(size_t(B) * 4 * 8));
+      auto *flag = static_cast<int64_t *>(m->s_flag.reserve(size_t(B) * 4 * 8));
+      auto *off = static_cast<int64_t *>(m->s_off.reserve(size_t(B * 4 + 1) * 8));
+      hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
+                         m->s_pre[cur].as<uint64_t>(), m->s_cnt[cur].as<uint64_t>(), cond, B, p,
+                         m->n, m->mask_levels, m->phys.as<uint8_t>(), seed, child,
+                         reinterpret_cast<uint64_t *>(flag), lost_d);
+      HIP_LAUNCH_OK();
+      launch_exclusive_scan(flag, off, B * 4, s);
+      int64_t nb = 0;
+      HIP_OK(hipMemcpyAsync(&nb, off + B * 4, 8, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      const int nxt = 1 - cur;
+      m->s_pre[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
+      m->s_cnt[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
+      hipLaunchKernelGGL(compact_kernel, dim3(unsigned(ceil_div(B * 4, 256))), dim3(256), 0, s,
+                         m->s_pre[cur].as<uint64_t>(), child, off, B * 4, p,
+                         m->s_pre[nxt].as<uint64_t>(), m->s_cnt[nxt].as<uint64_t>());
+      HIP_LAUNCH_OK();
+      cur = nxt;
+      B = nb;
+    }
+    uint64_t lost_h = 0;
+    HIP_OK(hipMemcpyAsync(&lost_h, lost_d, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (lost) *lost = lost_h;
+    *n_unique = B;
+    NQS_REQUIRE(B <= capacity, NQS_ECAPACITY, "sample_unique: capacity too small");
+    NQS_REQUIRE(B == 0 || (configs && counts), NQS_EINVAL, "sample_unique: null output");
+    if (B > 0) {
+      HIP_OK(hipMemcpyAsync(configs, m->s_pre[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(counts, m->s_cnt[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
+    }
+  });
+}

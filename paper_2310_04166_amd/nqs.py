@@ -1,0 +1,276 @@
+"""Thin Python binding of the C ABI in ``include/nqs.h`` (ctypes).
+
+Argument marshalling only: every step of the hot path runs in the HIP library
+``libnqs.so``.  Device arrays are torch tensors on the current HIP device;
+configurations travel as ``torch.int64`` tensors holding the uint64 bit
+strings.  The library must be built (``python -m paper_2310_04166_amd.build``);
+loading fails loudly if it is missing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnqs.so")
+
+MODEL_MLP, MODEL_TRANSFORMER = 1, 2
+FP64, FP32, BF16 = 1, 2, 3
+MU, DU, MUD = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+STRATEGIES = {"MU": MU, "DU": DU, "MUd": MUD}
+
+_STATUS = {-1: "EINVAL", -2: "ECAPACITY", -3: "EUNSUPPORTED", -4: "EHIP", -5: "ENOMEM"}
+
+
+class NQSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_vp, _i64, _i32, _u64, _dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_double
+_SIGS = {
+    "nqs_last_error": ([], C.c_char_p),
+    "ham_compile": ([_vp, _vp, C.c_int, _dbl, C.c_int, C.c_int, C.POINTER(_vp)], C.c_int),
+    "ham_info": ([_vp, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
+    "ham_tables": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ham_destroy": ([_vp], None),
+    "amp_model_create": ([C.c_int, _vp, C.c_int, _vp, _i64, C.c_int, C.c_int, C.c_int,
+                          C.POINTER(_vp)], C.c_int),
+    "amp_model_info": ([_vp, C.POINTER(_i64), C.POINTER(_i32)], C.c_int),
+    "amp_model_params": ([_vp, C.POINTER(_vp)], C.c_int),
+    "amp_model_sync": ([_vp, _vp], C.c_int),
+    "amp_model_get_params": ([_vp, _vp], C.c_int),
+    "amp_model_set_params": ([_vp, _vp], C.c_int),
+    "amp_model_destroy": ([_vp], None),
+    "amp_forward": ([_vp, _vp, _i64, _vp, _vp, _vp], C.c_int),
+    "amp_backward": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
+    "sample_unique": ([_vp, _u64, _u64, _vp, _vp, _i64, C.POINTER(_i64), C.POINTER(_u64), _vp],
+                      C.c_int),
+    "connected_pairs": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(_i64), _vp], C.c_int),
+    "local_energy": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.POINTER(_i64), _vp],
+                     C.c_int),
+    "vmc_weights": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
+    "adam_update": ([_vp, _vp, _vp, _vp, _i64, C.c_int, _dbl, _dbl, _dbl, _dbl, _i64, _vp],
+                    C.c_int),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2310_04166_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes, f.restype = args, res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise NQSError(status, lib().nqs_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype):
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+    return t
+
+
+class Hamiltonian:
+    """A compiled Hamiltonian (``ham_compile``)."""
+
+    def __init__(self, h1, eri, n_alpha, n_beta, e_core=0.0):
+        h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        self.n = h1.shape[0]
+        self.n_alpha, self.n_beta = n_alpha, n_beta
+        h = _vp()
+        _check(lib().ham_compile(_ptr(h1), _ptr(eri), self.n, float(e_core), n_alpha, n_beta,
+                                 C.byref(h)))
+        self.handle = h
+
+    def info(self):
+        G, T = _i64(), _i64()
+        _check(lib().ham_info(self.handle, C.byref(G), C.byref(T)))
+        return G.value, T.value
+
+    def tables(self):
+        G, T = self.info()
+        flip = np.zeros(G, np.uint64)
+        off = np.zeros(G + 1, np.int64)
+        z = np.zeros(T, np.uint64)
+        c = np.zeros(T, np.float64)
+        _check(lib().ham_tables(self.handle, _ptr(flip), _ptr(off), _ptr(z), _ptr(c)))
+        return flip, off, z, c
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ham_destroy(self.handle)
+            self.handle = None
+
+
+def ham_compile(h1, eri, n_alpha, n_beta, e_core=0.0):
+    return Hamiltonian(h1, eri, n_alpha, n_beta, e_core)
+
+
+class Model:
+    """An amplitude model (``amp_model_create``)."""
+
+    def __init__(self, kind, dims, params, precision="fp32", strategy="MU", d=0):
+        dims_a = np.ascontiguousarray(dims, dtype=np.int32)
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        h = _vp()
+        _check(lib().amp_model_create(kind, _ptr(dims_a), len(dims_a), _ptr(p), len(p),
+                                      PRECISIONS[precision], STRATEGIES[strategy], d, C.byref(h)))
+        self.handle, self.kind, self.dims = h, kind, list(dims)
+        self.precision, self.strategy = precision, strategy
+        n, bytes_ = _i64(), _i32()
+        _check(lib().amp_model_info(h, C.byref(n), C.byref(bytes_)))
+        self.n_params, self.param_bytes = n.value, bytes_.value
+        self.param_dtype = torch.float64 if self.param_bytes == 8 else torch.float32
+
+    def params_ptr(self):
+        p = _vp()
+        _check(lib().amp_model_params(self.handle, C.byref(p)))
+        return p.value
+
+    def sync(self, stream=None):
+        _check(lib().amp_model_sync(self.handle, _stream(stream)))
+
+    def get_params(self):
+        out = np.zeros(self.n_params, np.float64)
+        _check(lib().amp_model_get_params(self.handle, _ptr(out)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        assert len(p) == self.n_params
+        _check(lib().amp_model_set_params(self.handle, _ptr(p)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.amp_model_destroy(self.handle)
+            self.handle = None
+
+
+def amp_model_create(kind, dims, params, precision="fp32", strategy="MU", d=0):
+    return Model(kind, dims, params, precision, strategy, d)
+
+
+def amp_forward(model, x, logabs=None, phase=None, stream=None):
+    x = _dev(x, torch.int64)
+    n = x.numel()
+    logabs = torch.empty(n, dtype=torch.float64, device=x.device) if logabs is None else logabs
+    phase = torch.empty(n, dtype=torch.float64, device=x.device) if phase is None else phase
+    _check(lib().amp_forward(model.handle, _ptr(x), n, _ptr(logabs), _ptr(phase), _stream(stream)))
+    return logabs, phase
+
+
+def amp_backward(model, x, g_logabs, g_phase, grad=None, stream=None):
+    x = _dev(x, torch.int64)
+    grad = torch.empty(model.n_params, dtype=model.param_dtype, device=x.device) if grad is None else grad
+    _check(lib().amp_backward(model.handle, _ptr(x), x.numel(), _ptr(_dev(g_logabs, torch.float64)),
+                              _ptr(_dev(g_phase, torch.float64)), _ptr(grad), _stream(stream)))
+    return grad
+
+
+def sample_unique(model, n_samples, seed, capacity=None, stream=None, device="cuda"):
+    """Returns (configs int64 tensor, counts int64 tensor, lost)."""
+    cap = int(capacity if capacity is not None else min(int(n_samples), 1 << 24))
+    configs = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    counts = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    nu, lost = _i64(), _u64()
+    st = lib().sample_unique(model.handle, int(n_samples), int(seed) & ((1 << 64) - 1),
+                             _ptr(configs), _ptr(counts), cap, C.byref(nu), C.byref(lost),
+                             _stream(stream))
+    if st == -2 and capacity is None:
+        return sample_unique(model, n_samples, seed, nu.value, stream, device)
+    _check(st)
+    return configs[:nu.value], counts[:nu.value], lost.value
+
+
+def connected_pairs(ham, x, capacity=None, stream=None):
+    """Returns (offsets, xp, hval, hdiag) for configurations x."""
+    x = _dev(x, torch.int64)
+    n = x.numel()
+    off = torch.empty(n + 1, dtype=torch.int64, device=x.device)
+    total = _i64()
+    if capacity is None:
+        st = lib().connected_pairs(ham.handle, _ptr(x), n, _ptr(off), None, None, None, 0,
+                                   C.byref(total), _stream(stream))
+        if st not in (0, -2):
+            _check(st)
+        capacity = total.value
+    xp = torch.empty(max(capacity, 1), dtype=torch.int64, device=x.device)
+    hv = torch.empty(max(capacity, 1), dtype=torch.float64, device=x.device)
+    hd = torch.empty(max(n, 1), dtype=torch.float64, device=x.device)
+    _check(lib().connected_pairs(ham.handle, _ptr(x), n, _ptr(off), _ptr(xp), _ptr(hv), _ptr(hd),
+                                 capacity, C.byref(total), _stream(stream)))
+    return off, xp[:total.value], hv[:total.value], hd[:n]
+
+
+def local_energy(ham, model, x, counts=None, logabs_x=None, phase_x=None, stream=None):
+    """Returns (eloc complex128 tensor [n], sums float64 [4], n_pairs)."""
+    x = _dev(x, torch.int64)
+    n = x.numel()
+    eloc = torch.empty((max(n, 1), 2), dtype=torch.float64, device=x.device)
+    sums = torch.empty(4, dtype=torch.float64, device=x.device)
+    npairs = _i64()
+    _check(lib().local_energy(ham.handle, model.handle, _ptr(x), _ptr(counts), n, _ptr(logabs_x),
+                              _ptr(phase_x), _ptr(eloc), _ptr(sums), C.byref(npairs),
+                              _stream(stream)))
+    return torch.view_as_complex(eloc[:n]), sums, npairs.value
+
+
+def vmc_weights(eloc, counts, sums, stream=None):
+    er = torch.view_as_real(eloc).contiguous()
+    n = eloc.numel()
+    gl = torch.empty(n, dtype=torch.float64, device=eloc.device)
+    gp = torch.empty(n, dtype=torch.float64, device=eloc.device)
+    _check(lib().vmc_weights(_ptr(er), _ptr(counts), n, _ptr(sums), _ptr(gl), _ptr(gp),
+                             _stream(stream)))
+    return gl, gp
+
+
+def adam_update(params_ptr, grad, m, v, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, t=1, stream=None):
+    n = grad.numel()
+    _check(lib().adam_update(C.c_void_p(params_ptr), _ptr(grad), _ptr(m), _ptr(v), n,
+                             grad.element_size(), lr, b1, b2, eps, t, _stream(stream)))
+
+
+# ---------------------------------------------------------------- models ---
+
+def model_dims(cfg):
+    """dims vector of amp_model_create for a workload description."""
+    if cfg["model"] == "mlp":
+        return [cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg.get("hidden", 64)]
+    d = cfg["d"]
+    return [cfg["n"], cfg["n_alpha"], cfg["n_beta"], d, cfg["n_layers"], cfg["n_heads"],
+            cfg.get("ffn", 4 * d), cfg.get("phase_hidden", 256)]
+
+
+def model_kind(cfg):
+    return MODEL_MLP if cfg["model"] == "mlp" else MODEL_TRANSFORMER
