@@ -1,0 +1,212 @@
+"""Benchmark: full VMC steps of the 30-spin-orbital workload on one MI355X.
+
+A step is one pass of the whole hot path over one batch:
+    sample_unique (1e6 samples -> ~2e4 unique, Mask-Unphysical tree on the GPU)
+    amp_forward   (log|psi|, phase of the unique samples)
+    local_energy  (bit kernel -> ~9e7 connected (x, x') pairs -> fused bf16
+                   amplitude kernel on every x' -> ratios, double accumulation)
+    vmc_weights + amp_backward (hand-written backward, activations recomputed)
+    adam_update + repack of the bf16 weights
+Inputs are seeded synthetic integrals and a random-initialised transformer
+(d_model 128, 4 layers, 8 heads), resident in HBM before the timed region.
+
+Prints one JSON line.  `value` = connected (x, x') pairs per second of the
+whole step (the E_loc evals/s metric measured over complete steps).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic multiply-adds of one amplitude evaluation of the 30-qubit model:
+# 15 tokens x 4 layers x 12 d^2 + causal attention 4 x 2 x d T(T+1)/2
+# + head 15 x 4 d + phase MLP 256^2 + 256
+FLOP_PER_CONFIG = 2 * (15 * 4 * 12 * 128 ** 2 + 4 * 2 * 128 * 120 + 15 * 4 * 128 + 256 * 256 + 256)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def setup(workload_name, precision):
+    from paper_2310_04166_amd import nqs
+    from synth import flatten_params, transformer_param_spec, workload
+    cfg, h, eri, params = workload(workload_name)
+    spec = transformer_param_spec(cfg["n"], cfg["d"], cfg["n_layers"], 4 * cfg["d"], 256)
+    ham = nqs.ham_compile(h, eri, cfg["n_alpha"], cfg["n_beta"])
+    model = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg), flatten_params(params, spec),
+                      precision)
+    return cfg, ham, model, params
+
+
+def vmc_step(nqs, ham, model, cfg, seed, state, t):
+    x, cnt, lost = nqs.sample_unique(model, cfg["n_samples"], seed)
+    la, ph = nqs.amp_forward(model, x)
+    eloc, sums, npairs = nqs.local_energy(ham, model, x, cnt, la, ph)
+    gl, gp = nqs.vmc_weights(eloc, cnt, sums)
+    grad = nqs.amp_backward(model, x, gl, gp, grad=state["grad"])
+    nqs.adam_update(model.params_ptr(), grad, state["m"], state["v"], lr=state["lr"], t=t)
+    model.sync()
+    return x, cnt, eloc, sums, npairs
+
+
+def precision_check(nqs, torch, args, cfg, ham, model):
+    """bf16 vs fp32 GPU paths on the same samples at the same (initial) parameters:
+    the 1024 unique samples with the largest counts plus 1024 drawn uniformly."""
+    x, c, _ = nqs.sample_unique(model, cfg["n_samples"], 7)
+    order = torch.argsort(c, descending=True)
+    rng = np.random.default_rng(0)
+    pick = np.unique(np.concatenate([order[:args.fp32_sample].cpu().numpy(),
+                                     rng.choice(x.numel(), min(args.fp32_sample, x.numel()),
+                                                replace=False)]))
+    idx = torch.as_tensor(pick, device=x.device)
+    xs, cs = x[idx].contiguous(), c[idx].contiguous()
+    _, _, m32, _ = setup(args.workload, "fp32")
+    m32.set_params(model.get_params())
+    out = {}
+    for name, m in (("fp32", m32), ("bf16", model)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        e, s, npairs = nqs.local_energy(ham, m, xs, cs)
+        torch.cuda.synchronize()
+        out[name] = (e, s.cpu().numpy(), npairs, time.perf_counter() - a)
+    e32, s32, np32, t32 = out["fp32"]
+    e16, s16, np16, t16 = out["bf16"]
+    d = (e16 - e32).abs().cpu().numpy()
+    w = cs.cpu().numpy().astype(np.float64)
+    return {"samples": len(pick), "counts_covered": int(w.sum()), "pairs": int(np32),
+            "E_bf16": float(s16[1] / s16[0]), "E_fp32": float(s32[1] / s32[0]),
+            "abs_diff_ha": float(abs(s16[1] / s16[0] - s32[1] / s32[0])),
+            "count_weighted_mean_abs_eloc_diff": float((w * d).sum() / w.sum()),
+            "fp32_pairs_per_s": np32 / t32, "bf16_pairs_per_s": np16 / t16,
+            "speedup_bf16_over_fp32": (np16 / t16) / (np32 / t32)}
+
+
+def cpu_baseline(cfg, params, x_sample):
+    """The FP64 oracle's local energy on a bounded sample of unique configurations."""
+    import torch
+    from oracle.model import build_model
+    from oracle.vmc import local_energy
+    from synth import make_integrals
+    h, eri = make_integrals(cfg["n"], cfg["rank"], cfg["seed"])
+    model = build_model(cfg, params)
+    pairs = 0
+    t0 = time.perf_counter()
+    for x in x_sample:
+        _, xs, _ = local_energy(model, h, eri, int(x))
+        pairs += len(xs) - 1
+    dt = time.perf_counter() - t0
+    return {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(x_sample)} unique configurations of step 0 (largest counts) with all "
+                      f"their {pairs} connected x' (FP64 torch CPU forward + Slater-Condon "
+                      f"matrix elements), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="precision")
+    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--fp32-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--lr", type=float, default=1e-5,
+                    help="Adam step size; small so every timed step sees the calibrated workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_04166_amd import nqs
+    cfg, ham, model, params = setup(args.workload, "bf16")
+    dev = torch.device("cuda:0")
+    log(f"workload {args.workload}: n={cfg['n']} N_s={cfg['n_samples']} params={model.n_params}")
+    precision = None if args.no_fp32 else precision_check(nqs, torch, args, cfg, ham, model)
+    if precision:
+        log(f"precision: {precision}")
+
+    state = {"grad": torch.empty(model.n_params, dtype=torch.float32, device=dev),
+             "m": torch.zeros(model.n_params, dtype=torch.float32, device=dev),
+             "v": torch.zeros(model.n_params, dtype=torch.float32, device=dev), "lr": args.lr}
+    t = 1
+    for w in range(args.warmup):
+        out = vmc_step(nqs, ham, model, cfg, 1000 + w, state, t)
+        t += 1
+        log(f"warmup {w}: unique={out[0].numel()} pairs={out[4]}")
+    torch.cuda.synchronize()
+    nqs.timing_enable(True)
+    nqs.timing_read()
+    total_pairs, total_unique, step_ms, energies = 0, 0, [], []
+    first = None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        s0 = time.perf_counter()
+        x, cnt, eloc, sums, npairs = vmc_step(nqs, ham, model, cfg, k, state, t)
+        t += 1
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+        s = sums.cpu().numpy()
+        energies.append(float(s[1] / s[0]))
+        total_pairs += npairs
+        total_unique += x.numel()
+        if first is None:
+            first = (x.clone(), cnt.clone())
+        log(f"step {k}: unique={x.numel()} pairs={npairs} E={s[1] / s[0]:.6f} "
+            f"{step_ms[-1]:.0f} ms")
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+    k_ms, k_launches, k_cfgs = nqs.timing_read()
+    nqs.timing_enable(False)
+
+    value = total_pairs / elapsed
+    achieved = (k_cfgs * FLOP_PER_CONFIG) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "fused_kernel<128> (bf16 amplitude network)",
+                "avg_launch_ms": round(k_ms / max(k_launches, 1), 3), "launches": k_launches,
+                "configs": k_cfgs, "flop_per_config": FLOP_PER_CONFIG,
+                "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        x0, c0 = first
+        top = torch.argsort(c0, descending=True)[:args.cpu_sample]
+        xs_cpu = [int(v) for v in x0[top].cpu().numpy().view(np.uint64)]
+        cpu = cpu_baseline(cfg, params, xs_cpu)
+
+    out = {"metric": "connected-config E_loc evals/s over full VMC steps (30 qubits)",
+           "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": f"{args.workload}: 30 spin-orbitals 7a+7b, sector 41,409,225, "
+                                  "1e6 samples/step, transformer d128 L4 h8 + phase MLP 256",
+                      "unique_per_step": total_unique / args.steps,
+                      "pairs_per_step": total_pairs / args.steps,
+                      "gpu_ms_per_step": round(gpu_ms / args.steps, 2),
+                      "step_ms": [round(v, 1) for v in step_ms],
+                      "energy_per_step": energies},
+           "roofline": roofline, "cpu_baseline": cpu, "precision": precision}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

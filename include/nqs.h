@@ -250,6 +250,21 @@ int adam_update(void *params, const void *grad, void *m, void *v, int64_t n,
                 int elem_bytes, double lr, double b1, double b2, double eps,
                 int64_t t, nqs_stream stream);
 
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Kernel timing of the dominant kernel (the fused bf16 amplitude kernel).
+ * While enabled, every launch of it is bracketed by two HIP events recorded on
+ * the launch's own stream.  nqs_timing_read synchronises those events and
+ * returns the summed kernel time in milliseconds, the number of launches and
+ * the number of configurations they evaluated, then clears the record.
+ * Not thread-safe; intended for benchmarks.
+ */
+int nqs_timing_enable(int on);
+int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,8 @@ struct nqs_model {
 
   nqs::DevBuf master;                 // canonical parameters (double in FP64, float otherwise)
   nqs::DevBuf phys;                   // device copy of phys_host
-  nqs::DevBuf packed;                 // bf16 weights of the fused kernel
+  nqs::DevBuf packed;                 // bf16 weight fragments of the fused kernel
+  nqs::DevBuf packed_vec;             // permuted fp32 vectors of the fused kernel
   bool packed_valid = false;
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler

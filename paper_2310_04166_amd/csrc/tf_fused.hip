@@ -1,17 +1,604 @@
-// Fused bf16 transformer forward on MFMA (placeholder until the kernel lands).
+// Fused bf16 transformer forward on MFMA (gfx950): log|psi|, phase, or the
+// sampler's conditional logits, for a batch of configurations.  Paper: ANQS
+// product rule and Mask-Unphysical conditionals ("Pruning strategies").
+//
+// Design.  One 64-lane wave owns 32 rows = 2 configurations x 16 positions
+// (sequences are padded to 16 tokens) and carries them through every layer in
+// registers; there is no LDS traffic for activations.  All GEMMs use
+// v_mfma_f32_32x32x16_bf16 (bf16 operands, fp32 accumulation).  Activations
+// are kept "feature-major": an accumulator block holds 32 features x 32 rows,
+// lane l owning row l%32 and, for j = 0..15, feature
+//     (j/4)*8 + (l/32)*4 + j%4.
+// Read as an MFMA operand, lane l supplies row l%32 and 8 consecutive k-slots
+// (l/32)*8 .. +7.  So the accumulator of one GEMM is, after conversion to
+// bf16, already the activation operand of the next one, provided the k index
+// inside every 16-wide step is permuted the same way in the weights:
+//     slot i of lane-half h  <->  feature pi_h(i) = (i/4)*8 + h*4 + i%4.
+// Weights are packed once into that fragment order (fused_pack).  Value and
+// attention-output products are computed in the transposed orientation
+// (activations as the A operand) so that no transpose is ever needed:
+//     S^T = K Q^T,  P^T = softmax over keys,  O^T = V^T P^T,
+// where V comes out key-major and O^T feature-major again.
+//
+// Per 32 rows and layer: Q, K (2 x 8 x 8), V (8 x 4), S (8), O (16),
+// out-projection (32), FFN (128 + 128) MFMAs.  After 16 passes (32
+// configurations) the phase MLP of those 32 configurations runs as one
+// 256 x 256 GEMM with the configurations as the 32 columns.
+#include <cmath>
+#include <vector>
+
 #include "model.h"
+#include "ops.h"
 
 namespace nqs {
+namespace {
 
-bool fused_supported(const nqs_model &) { return false; }
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-void fused_pack(nqs_model &, hipStream_t) {
-  throw Error(NQS_EUNSUPPORTED, "bf16 fused forward not available");
+struct TimingRecord {
+  hipEvent_t start, stop;
+  int64_t configs;
+};
+bool g_timing = false;
+std::vector<TimingRecord> g_records;
+
+constexpr int kMaxLayers = 8;
+constexpr int kSeq = 16;          // padded sequence length
+constexpr int kPairs = 16;        // passes per group of 32 configurations
+
+__device__ __host__ inline int perm_feature(int b, int h, int j) {
+  return 32 * b + (j / 4) * 8 + h * 4 + (j % 4);
 }
 
-void fused_forward(nqs_model &, const uint64_t *, int64_t, double *, double *, double *, int,
-                   hipStream_t) {
-  throw Error(NQS_EUNSUPPORTED, "bf16 fused forward not available");
+struct FusedArgs {
+  const bf16x8 *pk;                 // packed weight fragments
+  const float *vec;                 // permuted fp32 vectors
+  int64_t q[kMaxLayers], k[kMaxLayers], v[kMaxLayers], o[kMaxLayers], w1[kMaxLayers],
+      w2[kMaxLayers];               // fragment offsets (units of bf16x8)
+  int64_t ln1g[kMaxLayers], ln1b[kMaxLayers], bq[kMaxLayers], bk[kMaxLayers], bv[kMaxLayers],
+      bo[kMaxLayers], ln2g[kMaxLayers], ln2b[kMaxLayers], b1[kMaxLayers], b2[kMaxLayers];
+  int64_t p2;                       // phase W2 fragments
+  int64_t lnfg, lnfb, whead, bhead, lbias, tok, pos, pb1, pb2, pw3, pb3, pw1;  // vec offsets
+  const uint8_t *phys;
+  const uint64_t *x;
+  int64_t B;
+  int n, L, mask_levels, cond_p;
+  double *logabs, *phase, *cond;
+};
+
+__device__ inline bf16x8 to_bf16(const f32x16 &c, int half) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; i += 2) {
+    f32x2 p = {c[half * 8 + i], c[half * 8 + i + 1]};
+    bf16x2 q = __builtin_convertvector(p, bf16x2);
+    r[i] = q[0];
+    r[i + 1] = q[1];
+  }
+  return r;
+}
+
+__device__ inline f32x16 mfma(const bf16x8 &a, const bf16x8 &b, const f32x16 &c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f32x16 load16(const float *p) {
+  const f32x4 *q = reinterpret_cast<const f32x4 *>(p);
+  f32x4 a = q[0], b = q[1], c = q[2], d = q[3];
+  f32x16 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = a[i];
+    r[4 + i] = b[i];
+    r[8 + i] = c[i];
+    r[12 + i] = d[i];
+  }
+  return r;
+}
+
+__device__ inline float gelu(float x) {
+  // 0.5 x (1 + tanh(u)) = x * sigmoid(2u), u = sqrt(2/pi) (x + 0.044715 x^3);
+  // hardware exp2 and reciprocal (about 1 ulp each), far below bf16 rounding
+  const float u2 = 1.5957691216057308f * x * (1.0f + 0.044715f * x * x);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * u2));
+}
+
+// acc = W-fragments(block) x X  (weights as A operand, activations as B)
+template <int KS>
+__device__ inline f32x16 wx(const bf16x8 *__restrict__ w, const bf16x8 (&X)[KS], f32x16 acc) {
+  bf16x8 f[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) f[s] = w[s * 64];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) acc = mfma(f[s], X[s], acc);
+  return acc;
+}
+
+// acc = X x W-fragments(block)  (activations as A operand: row-major output)
+template <int KS>
+__device__ inline f32x16 xw(const bf16x8 (&X)[KS], const bf16x8 *__restrict__ w, f32x16 acc) {
+  bf16x8 f[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) f[s] = w[s * 64];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) acc = mfma(X[s], f[s], acc);
+  return acc;
+}
+
+// Layer norm of the feature-major residual into a bf16 operand.
+template <int NB>
+__device__ inline void layer_norm(const f32x16 (&res)[NB], const float *g, const float *b, int h,
+                                  bf16x8 (&X)[2 * NB]) {
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s += res[q][j];
+  s += __shfl_xor(s, 32);
+  const float mu = s * (1.0f / (32 * NB));
+  float v = 0.f;
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float d = res[q][j] - mu;
+      v += d * d;
+    }
+  v += __shfl_xor(v, 32);
+  const float rs = rsqrtf(v * (1.0f / (32 * NB)) + 1e-5f);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const f32x16 gg = load16(g + (q * 2 + h) * 16), bb = load16(b + (q * 2 + h) * 16);
+    f32x16 y;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) y[j] = (res[q][j] - mu) * rs * gg[j] + bb[j];
+    X[2 * q] = to_bf16(y, 0);
+    X[2 * q + 1] = to_bf16(y, 1);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
+  constexpr int NB = D / 32, KS = D / 16, F = 4 * D, FB = F / 32;
+  const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
+  const int64_t group = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  const int64_t c_base = group * 32;
+  if (c_base >= a.B) return;
+  const int t = r % kSeq;            // position of this lane's row
+  const int n = a.n;
+  const bf16x8 *pk = a.pk + lane;
+  const float *vec = a.vec;
+
+  for (int pair = 0; pair < kPairs; ++pair) {
+    const int64_t cfg = c_base + 2 * pair + r / kSeq;
+    if (c_base + 2 * pair >= a.B) break;
+    const bool live = cfg < a.B;
+    const uint64_t x = live ? a.x[cfg] : 0ull;
+
+    // embedding: token of the previous position (BOS at position 0)
+    f32x16 res[NB];
+    {
+      const int in = (t == 0) ? 4 : int((x >> (2 * (t - 1))) & 3ull);
+      const bool pad = t >= n;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const f32x16 te = load16(vec + a.tok + in * D + (q * 2 + h) * 16);
+        const f32x16 pe = pad ? f32x16{} : load16(vec + a.pos + t * D + (q * 2 + h) * 16);
+        res[q] = te + pe;
+      }
+    }
+
+    for (int l = 0; l < a.L; ++l) {
+      // ---- attention block
+      bf16x8 X[KS];
+      layer_norm<NB>(res, vec + a.ln1g[l], vec + a.ln1b[l], h, X);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) res[q] += load16(vec + a.bo[l] + (q * 2 + h) * 16);
+      for (int b = 0; b < NB; ++b) {
+        const f32x16 bq = load16(vec + a.bq[l] + (b * 2 + h) * 16);
+        const f32x16 bk = load16(vec + a.bk[l] + (b * 2 + h) * 16);
+        const float bvv = vec[a.bv[l] + 32 * b + r];
+        const f32x16 Qc = wx<KS>(pk + a.q[l] + int64_t(b) * KS * 64, X, bq);
+        const f32x16 Kc = wx<KS>(pk + a.k[l] + int64_t(b) * KS * 64, X, bk);
+        f32x16 Vb;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Vb[j] = bvv;
+        const f32x16 Vc = xw<KS>(X, pk + a.v[l] + int64_t(b) * KS * 64, Vb);
+        const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
+        f32x16 O = {};
+        // S[j] = score(key (j/4)*8 + h*4 + j%4, query r).  Keys of the other
+        // configuration (j >= 8 for r < 16, j < 8 for r >= 16) are masked, so
+        // only the 8 slots of this lane's own configuration are worked on.
+        const bool upper = r >= kSeq;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const f32x16 S = mfma(to_bf16(Kc, e), to_bf16(Qc, e), f32x16{});
+          float p[8];
+          float mx = -INFINITY;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int kk = (i / 4) * 8 + h * 4 + (i % 4);  // key position in the config
+            const float s = upper ? S[8 + i] : S[i];
+            p[i] = kk <= t ? s * (0.25f * 1.4426950408889634f) : -INFINITY;
+            mx = fmaxf(mx, p[i]);
+          }
+          mx = fmaxf(mx, __shfl_xor(mx, 32));
+          float sum = 0.f;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            p[i] = __builtin_amdgcn_exp2f(p[i] - mx);
+            sum += p[i];
+          }
+          sum += __shfl_xor(sum, 32);
+          const float inv = __builtin_amdgcn_rcpf(sum);
+          f32x16 P;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float v = p[i] * inv;
+            P[i] = upper ? 0.f : v;
+            P[8 + i] = upper ? v : 0.f;
+          }
+          f32x16 Oe = mfma(V0, to_bf16(P, 0), f32x16{});
+          Oe = mfma(V1, to_bf16(P, 1), Oe);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) O[e * 8 + j] = Oe[e * 8 + j];
+        }
+        const bf16x8 O0 = to_bf16(O, 0), O1 = to_bf16(O, 1);
+        const bf16x8 *wo = pk + a.o[l];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          res[q] = mfma(wo[(int64_t(q) * KS + 2 * b) * 64], O0, res[q]);
+          res[q] = mfma(wo[(int64_t(q) * KS + 2 * b + 1) * 64], O1, res[q]);
+        }
+      }
+      // ---- feed-forward block
+      layer_norm<NB>(res, vec + a.ln2g[l], vec + a.ln2b[l], h, X);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) res[q] += load16(vec + a.b2[l] + (q * 2 + h) * 16);
+      const bf16x8 *w2 = pk + a.w2[l];
+      for (int fb = 0; fb < FB; ++fb) {
+        f32x16 Hc = wx<KS>(pk + a.w1[l] + int64_t(fb) * KS * 64, X,
+                           load16(vec + a.b1[l] + (fb * 2 + h) * 16));
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
+        const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          res[q] = mfma(w2[(int64_t(q) * (F / 16) + 2 * fb) * 64], H0, res[q]);
+          res[q] = mfma(w2[(int64_t(q) * (F / 16) + 2 * fb + 1) * 64], H1, res[q]);
+        }
+      }
+    }
+
+    // ---- final layer norm, head, masked log-softmax
+    float lg[4] = {0.f, 0.f, 0.f, 0.f};
+    {
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += res[q][j];
+      s += __shfl_xor(s, 32);
+      const float mu = s * (1.0f / D);
+      float v = 0.f;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const float d = res[q][j] - mu;
+          v += d * d;
+        }
+      v += __shfl_xor(v, 32);
+      const float rs = rsqrtf(v * (1.0f / D) + 1e-5f);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const f32x16 gg = load16(vec + a.lnfg + (q * 2 + h) * 16);
+        const f32x16 bb = load16(vec + a.lnfb + (q * 2 + h) * 16);
+        const f32x4 *wh = reinterpret_cast<const f32x4 *>(vec + a.whead) + (q * 2 + h) * 16;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const float y = (res[q][j] - mu) * rs * gg[j] + bb[j];
+          const f32x4 w = wh[j];
+          lg[0] += y * w[0];
+          lg[1] += y * w[1];
+          lg[2] += y * w[2];
+          lg[3] += y * w[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) lg[k] += __shfl_xor(lg[k], 32);
+    }
+    float logp = 0.f;
+    if (t < n) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) lg[k] += vec[a.bhead + k] + vec[a.lbias + t * 4 + k];
+      const uint64_t below = (t == 0) ? 0ull : (~0ull >> (64 - 2 * t));
+      const int na = __popcll(x & below & 0x5555555555555555ull);
+      const int nb = __popcll(x & below & 0xAAAAAAAAAAAAAAAAull);
+      const int allow = t < a.mask_levels ? a.phys[(t * (n + 1) + na) * (n + 1) + nb] : 0xF;
+      const int tk = int((x >> (2 * t)) & 3ull);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((allow >> k) & 1) mx = fmaxf(mx, lg[k]);
+      float z = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((allow >> k) & 1) z += expf(lg[k] - mx);
+      logp = ((allow >> tk) & 1) ? lg[tk] - mx - logf(z) : -INFINITY;
+      if (a.cond && t == a.cond_p && h == 0 && live) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
+      }
+    }
+    if (a.logabs) {
+      logp += __shfl_xor(logp, 1);
+      logp += __shfl_xor(logp, 2);
+      logp += __shfl_xor(logp, 4);
+      logp += __shfl_xor(logp, 8);
+      if (t == 0 && h == 0 && live) a.logabs[cfg] = 0.5 * double(logp);
+    }
+  }
+
+  // ---- phase MLP for the group's 32 configurations (column = configuration)
+  if (a.phase) {
+    constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
+    const int64_t cfg = c_base + r;
+    const bool live = cfg < a.B;
+    const uint64_t x = live ? a.x[cfg] : 0ull;
+    bf16x8 Z[PKS];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      f32x16 z = load16(vec + a.pb1 + (b * 2 + h) * 16);
+      for (int tt = 0; tt < n; ++tt) {
+        const int row = 4 * tt + int((x >> (2 * tt)) & 3ull);
+        z += load16(vec + a.pw1 + int64_t(row) * PH + (b * 2 + h) * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) z[j] = gelu(z[j]);
+      Z[2 * b] = to_bf16(z, 0);
+      Z[2 * b + 1] = to_bf16(z, 1);
+    }
+    float ph = 0.f;
+    for (int b = 0; b < PB; ++b) {
+      f32x16 z = wx<PKS>(pk + a.p2 + int64_t(b) * PKS * 64, Z, load16(vec + a.pb2 + (b * 2 + h) * 16));
+      const f32x16 w3 = load16(vec + a.pw3 + (b * 2 + h) * 16);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) ph += gelu(z[j]) * w3[j];
+    }
+    ph += __shfl_xor(ph, 32);
+    if (h == 0 && live) a.phase[cfg] = double(ph + vec[a.pb3]);
+  }
+}
+
+// ----------------------------------------------------------------- packing
+
+// Fragment order: (block ob, k-step s, lane l, slot i) <- W[16 s + pi_h(i)][32 ob + l%32],
+// W row-major with leading dimension ld, starting at column col0.
+__global__ void pack_frag_kernel(const float *W, int64_t ld, int col0, int n_ob, int n_ks,
+                                 __bf16 *out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(n_ob) * n_ks * 64 * 8) return;
+  const int i = int(idx % 8), l = int((idx / 8) % 64);
+  const int64_t s = (idx / 512) % n_ks, ob = idx / (512 * int64_t(n_ks));
+  const int hh = l / 32;
+  const int krow = int(16 * s) + (i / 4) * 8 + hh * 4 + (i % 4);
+  out[idx] = __bf16(W[int64_t(krow) * ld + col0 + 32 * ob + (l % 32)]);
+}
+
+// Permuted vector: out[(b*2+h)*16 + j] = v[perm_feature(b, h, j)], for `rows`
+// vectors of length N (stride N) -- the feature order of an accumulator block.
+__global__ void perm_vec_kernel(const float *v, int N, int rows, float *out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(rows) * N) return;
+  const int c = int(idx % N);
+  const int64_t row = idx / N;
+  const int j = c % 16, hh = (c / 16) % 2, b = c / 32;
+  out[idx] = v[row * N + perm_feature(b, hh, j)];
+}
+
+// whead (D x 4) in permuted row order: out[(b*2+h)*16 + j][k] = W[perm_feature(b,h,j)][k]
+__global__ void perm_head_kernel(const float *W, int D, float *out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D * 4) return;
+  const int k = idx % 4, c = idx / 4;
+  const int j = c % 16, hh = (c / 16) % 2, b = c / 32;
+  out[idx] = W[perm_feature(b, hh, j) * 4 + k];
+}
+
+__global__ void copy_f32_kernel(const float *src, int64_t n, float *dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+struct Layout {
+  FusedArgs a;
+  int64_t frag_total = 0, vec_total = 0;
+};
+
+Layout plan(const nqs_model &m) {
+  Layout L{};
+  const int D = m.d, F = m.F, NB = D / 32, KS = D / 16, PH = m.PH;
+  auto frag = [&](int n_ob, int n_ks) {
+    const int64_t o = L.frag_total;
+    L.frag_total += int64_t(n_ob) * n_ks * 64;
+    return o;
+  };
+  auto vec = [&](int64_t len) {
+    const int64_t o = L.vec_total;
+    L.vec_total += (len + 15) / 16 * 16;
+    return o;
+  };
+  for (int l = 0; l < m.L; ++l) {
+    L.a.q[l] = frag(NB, KS);
+    L.a.k[l] = frag(NB, KS);
+    L.a.v[l] = frag(NB, KS);
+    L.a.o[l] = frag(NB, KS);
+    L.a.w1[l] = frag(F / 32, KS);
+    L.a.w2[l] = frag(NB, F / 16);
+    L.a.ln1g[l] = vec(D);
+    L.a.ln1b[l] = vec(D);
+    L.a.bq[l] = vec(D);
+    L.a.bk[l] = vec(D);
+    L.a.bv[l] = vec(D);
+    L.a.bo[l] = vec(D);
+    L.a.ln2g[l] = vec(D);
+    L.a.ln2b[l] = vec(D);
+    L.a.b1[l] = vec(F);
+    L.a.b2[l] = vec(D);
+  }
+  L.a.p2 = frag(PH / 32, PH / 16);
+  L.a.lnfg = vec(D);
+  L.a.lnfb = vec(D);
+  L.a.whead = vec(4 * D);
+  L.a.bhead = vec(4);
+  L.a.lbias = vec(4 * m.n);
+  L.a.tok = vec(5 * D);
+  L.a.pos = vec(int64_t(m.n) * D);
+  L.a.pb1 = vec(PH);
+  L.a.pb2 = vec(PH);
+  L.a.pw3 = vec(PH);
+  L.a.pb3 = vec(1);
+  L.a.pw1 = vec(int64_t(4) * m.n * PH);
+  return L;
+}
+
+inline dim3 g1(int64_t n) { return dim3(unsigned(ceil_div(n, 256))); }
+
+}  // namespace
+
+bool fused_supported(const nqs_model &m) {
+  return m.kind == NQS_MODEL_TRANSFORMER && (m.d == 64 || m.d == 128) && m.F == 4 * m.d &&
+         m.H * 16 == m.d && m.PH == 256 && m.n <= kSeq && m.L <= kMaxLayers;
+}
+
+void fused_pack(nqs_model &m, hipStream_t s) {
+  NQS_REQUIRE(fused_supported(m), NQS_EUNSUPPORTED, "fused forward: unsupported dimensions");
+  Layout L = plan(m);
+  static_assert(sizeof(bf16x8) == 16, "fragment size");
+  __bf16 *pk = static_cast<__bf16 *>(m.packed.reserve(size_t(L.frag_total) * 16));
+  const float *W = m.master.as<float>();
+  const int D = m.d, F = m.F, NB = D / 32, KS = D / 16, PH = m.PH, n = m.n;
+  auto P = [&](int idx) { return W + m.off[idx]; };
+  float *vb = static_cast<float *>(m.packed_vec.reserve(size_t(L.vec_total) * 4));
+  auto pack = [&](const float *src, int64_t ld, int col0, int n_ob, int n_ks, int64_t o) {
+    hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(n_ob) * n_ks * 512), dim3(256), 0, s, src, ld,
+                       col0, n_ob, n_ks, pk + o * 8);
+    HIP_LAUNCH_OK();
+  };
+  auto perm = [&](const float *src, int N, int rows, int64_t o) {
+    hipLaunchKernelGGL(perm_vec_kernel, g1(int64_t(N) * rows), dim3(256), 0, s, src, N, rows, vb + o);
+    HIP_LAUNCH_OK();
+  };
+  auto copy = [&](const float *src, int64_t len, int64_t o) {
+    hipLaunchKernelGGL(copy_f32_kernel, g1(len), dim3(256), 0, s, src, len, vb + o);
+    HIP_LAUNCH_OK();
+  };
+  for (int l = 0; l < m.L; ++l) {
+    const float *wqkv = P(tf_layer(l, TF_WQKV)), *bqkv = P(tf_layer(l, TF_BQKV));
+    pack(wqkv, 3 * D, 0, NB, KS, L.a.q[l]);
+    pack(wqkv, 3 * D, D, NB, KS, L.a.k[l]);
+    pack(wqkv, 3 * D, 2 * D, NB, KS, L.a.v[l]);
+    pack(P(tf_layer(l, TF_WO)), D, 0, NB, KS, L.a.o[l]);
+    pack(P(tf_layer(l, TF_W1)), F, 0, F / 32, KS, L.a.w1[l]);
+    pack(P(tf_layer(l, TF_W2)), D, 0, NB, F / 16, L.a.w2[l]);
+    perm(P(tf_layer(l, TF_LN1G)), D, 1, L.a.ln1g[l]);
+    perm(P(tf_layer(l, TF_LN1B)), D, 1, L.a.ln1b[l]);
+    perm(bqkv, D, 1, L.a.bq[l]);
+    perm(bqkv + D, D, 1, L.a.bk[l]);
+    copy(bqkv + 2 * D, D, L.a.bv[l]);
+    perm(P(tf_layer(l, TF_BO)), D, 1, L.a.bo[l]);
+    perm(P(tf_layer(l, TF_LN2G)), D, 1, L.a.ln2g[l]);
+    perm(P(tf_layer(l, TF_LN2B)), D, 1, L.a.ln2b[l]);
+    perm(P(tf_layer(l, TF_B1)), F, 1, L.a.b1[l]);
+    perm(P(tf_layer(l, TF_B2)), D, 1, L.a.b2[l]);
+  }
+  const int Lm = m.L;
+  pack(P(tf_tail(Lm, TF_PW2)), PH, 0, PH / 32, PH / 16, L.a.p2);
+  perm(P(tf_tail(Lm, TF_LNFG)), D, 1, L.a.lnfg);
+  perm(P(tf_tail(Lm, TF_LNFB)), D, 1, L.a.lnfb);
+  hipLaunchKernelGGL(perm_head_kernel, g1(4 * D), dim3(256), 0, s, P(tf_tail(Lm, TF_WHEAD)), D,
+                     vb + L.a.whead);
+  HIP_LAUNCH_OK();
+  copy(P(tf_tail(Lm, TF_BHEAD)), 4, L.a.bhead);
+  copy(P(tf_tail(Lm, TF_LBIAS)), 4 * n, L.a.lbias);
+  perm(P(TF_TOK), D, 5, L.a.tok);
+  perm(P(TF_POS), D, n, L.a.pos);
+  perm(P(tf_tail(Lm, TF_PB1)), PH, 1, L.a.pb1);
+  perm(P(tf_tail(Lm, TF_PB2)), PH, 1, L.a.pb2);
+  perm(P(tf_tail(Lm, TF_PW3)), PH, 1, L.a.pw3);
+  copy(P(tf_tail(Lm, TF_PB3)), 1, L.a.pb3);
+  perm(P(tf_tail(Lm, TF_PW1)), PH, 4 * n, L.a.pw1);
+  m.packed_valid = true;
+}
+
+void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
+                   double *cond_out, int cond_p, hipStream_t s) {
+  NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
+  if (B <= 0) return;
+  Layout L = plan(m);
+  FusedArgs a = L.a;
+  a.pk = m.packed.as<bf16x8>();
+  a.vec = m.packed_vec.as<float>();
+  a.phys = m.phys.as<uint8_t>();
+  a.x = x;
+  a.B = B;
+  a.n = m.n;
+  a.L = m.L;
+  a.mask_levels = m.mask_levels;
+  a.cond_p = cond_p;
+  a.logabs = logabs;
+  a.phase = phase;
+  a.cond = cond_out;
+  const int64_t groups = ceil_div(B, 32);
+  const dim3 grid(unsigned(ceil_div(groups, 4)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_timing) {
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+  }
+  if (m.d == 128)
+    hipLaunchKernelGGL(fused_kernel<128>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(fused_kernel<64>, grid, dim3(256), 0, s, a);
+  HIP_LAUNCH_OK();
+  if (g_timing) {
+    HIP_OK(hipEventRecord(e1, s));
+    g_records.push_back({e0, e1, B});
+  }
 }
 
 }  // namespace nqs
+
+using namespace nqs;
+
+extern "C" int nqs_timing_enable(int on) {
+  return guarded([&] { g_timing = on != 0; });
+}
+
+extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) {
+  return guarded([&] {
+    double total = 0.0;
+    int64_t cfgs = 0;
+    for (const TimingRecord &r : g_records) {
+      HIP_OK(hipEventSynchronize(r.stop));
+      float t = 0.f;
+      HIP_OK(hipEventElapsedTime(&t, r.start, r.stop));
+      total += t;
+      cfgs += r.configs;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = int64_t(g_records.size());
+    if (configs) *configs = cfgs;
+    for (const TimingRecord &r : g_records) {
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.stop);
+    }
+    g_records.clear();
+  });
+}

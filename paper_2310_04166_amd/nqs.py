@@ -56,6 +56,8 @@ _SIGS = {
     "vmc_weights": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "adam_update": ([_vp, _vp, _vp, _vp, _i64, C.c_int, _dbl, _dbl, _dbl, _dbl, _i64, _vp],
                     C.c_int),
+    "nqs_timing_enable": ([C.c_int], C.c_int),
+    "nqs_timing_read": ([C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -259,6 +261,17 @@ def adam_update(params_ptr, grad, m, v, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, t=1
     n = grad.numel()
     _check(lib().adam_update(C.c_void_p(params_ptr), _ptr(grad), _ptr(m), _ptr(v), n,
                              grad.element_size(), lr, b1, b2, eps, t, _stream(stream)))
+
+
+def timing_enable(on=True):
+    _check(lib().nqs_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """(milliseconds, launches, configurations) of the fused amplitude kernel."""
+    ms, nl, nc = _dbl(), _i64(), _i64()
+    _check(lib().nqs_timing_read(C.byref(ms), C.byref(nl), C.byref(nc)))
+    return ms.value, nl.value, nc.value
 
 
 # ---------------------------------------------------------------- models ---

@@ -1,0 +1,123 @@
+"""GPU parity of the fused bf16 amplitude kernel and of full-size steps of the
+30-spin-orbital workload against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.model import TransformerModel, build_model
+from oracle.sector import Sector, hf_config
+from oracle.vmc import local_energy as oracle_eloc
+from synth import (flatten_params, make_transformer_params, transformer_param_spec, workload)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    from paper_2310_04166_amd import nqs as mod
+    mod.lib()
+    return mod
+
+
+def dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def sector_sample(n, na, nb, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        a = rng.choice(n, na, replace=False)
+        b = rng.choice(n, nb, replace=False)
+        out.append(int(sum(1 << (2 * int(p)) for p in a) | sum(1 << (2 * int(p) + 1) for p in b)))
+    return out
+
+
+@pytest.mark.parametrize("n,na,nb,d,L,std,count", [
+    (10, 5, 5, 64, 2, 0.05, 3001),      # many groups of 32 and a ragged tail
+    (15, 7, 7, 128, 4, 0.05, 1000),
+    (7, 3, 2, 64, 1, 0.1, 77),
+])
+def test_fused_forward_vs_oracle(nqs, n, na, nb, d, L, std, count):
+    log(f"fused forward n={n} d={d} L={L}")
+    params = make_transformer_params(n, na, nb, d, L, seed=7 + n, std=std, hf_bias=1.0,
+                                     round_to="bf16", bias_std=0.02)
+    spec = transformer_param_spec(n, d, L, 4 * d, 256)
+    ref = TransformerModel(params, Sector(n, na, nb), d // 16)
+    flat = flatten_params(params, spec)
+    dims = [n, na, nb, d, L, d // 16, 4 * d, 256]
+    m16 = nqs.Model(nqs.MODEL_TRANSFORMER, dims, flat, "bf16")
+    m32 = nqs.Model(nqs.MODEL_TRANSFORMER, dims, flat, "fp32")
+    xs = sector_sample(n, na, nb, count, n)
+    la, ph = nqs.amp_forward(m16, dev(xs))
+    la32, ph32 = nqs.amp_forward(m32, dev(xs))
+    rla, rph = (v.detach().numpy() for v in ref.amplitudes(xs))
+    e_la = np.max(np.abs(la.cpu().numpy() - rla))
+    e_ph = np.max(np.abs(ph.cpu().numpy() - rph))
+    e32 = np.max(np.abs(la32.cpu().numpy() - rla))
+    log(f"  max |dlogabs| bf16={e_la:.2e} fp32={e32:.2e}  max |dphase| bf16={e_ph:.2e}  "
+        f"logabs range {rla.min():.2f}..{rla.max():.2f}")
+    assert e32 < 1e-4
+    assert e_la < 2e-2 and e_ph < 2e-2
+    # the bf16 error is noise around the exact value, not a bias
+    assert abs(np.mean(la.cpu().numpy() - rla)) < 5e-3
+
+
+def test_fused_outside_sector_and_empty(nqs):
+    n, na, nb, d = 6, 2, 2, 64
+    params = make_transformer_params(n, na, nb, d, 1, seed=1, std=0.05, round_to="bf16")
+    spec = transformer_param_spec(n, d, 1, 4 * d, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, 1, 4, 4 * d, 256],
+                  flatten_params(params, spec), "bf16")
+    la, _ = nqs.amp_forward(m, dev([0, 0b111111, hf_config(n, na, nb)]))
+    la = la.cpu().numpy()
+    assert np.isinf(la[0]) and la[0] < 0 and np.isinf(la[1]) and np.isfinite(la[2])
+    la, _ = nqs.amp_forward(m, torch.zeros(0, dtype=torch.int64, device="cuda"))
+    assert la.numel() == 0
+
+
+def test_fused_sampler_in_sector_and_counts(nqs):
+    cfg, h, eri, params = workload("fp32")
+    params = make_transformer_params(10, 5, 5, 64, 2, seed=2, hf_bias=2.7, round_to="bf16")
+    spec = transformer_param_spec(10, 64, 2, 256, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, nqs.model_dims(cfg), flatten_params(params, spec), "bf16")
+    x, c, lost = nqs.sample_unique(m, 100_000, 3)
+    xv = x.cpu().numpy().view(np.uint64)
+    sec = Sector(10, 5, 5)
+    assert lost == 0 and int(c.sum()) == 100_000 and int(c.min()) >= 1
+    assert len(set(xv.tolist())) == len(xv)
+    assert all(sec.contains(int(v)) for v in xv)
+
+
+def test_precision_workload_full_step_sampled_parity(nqs):
+    """30 spin-orbitals at full size: sample 1e6, E_loc of all ~2e4 unique samples
+    in bf16; sampled configurations checked against the FP64 oracle one by one."""
+    log("precision workload: full step")
+    cfg, h, eri, params = workload("precision")
+    spec = transformer_param_spec(15, 128, 4, 512, 256)
+    flat = flatten_params(params, spec)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, nqs.model_dims(cfg), flat, "bf16")
+    H = nqs.ham_compile(h, eri, 7, 7)
+    x, c, lost = nqs.sample_unique(m, cfg["n_samples"], 11)
+    log(f"  unique={x.numel()}")
+    assert lost == 0 and int(c.sum()) == cfg["n_samples"]
+    assert 5_000 < x.numel() < 80_000
+    eloc, sums, npairs = nqs.local_energy(H, m, x, c)
+    assert npairs == x.numel() * 4424
+    s = sums.cpu().numpy()
+    assert s[0] == cfg["n_samples"]
+    ref = build_model(cfg, params)
+    xv = x.cpu().numpy().view(np.uint64)
+    cv = c.cpu().numpy()
+    rng = np.random.default_rng(0)
+    picks = [int(np.argmax(cv))] + list(rng.choice(len(xv), 2, replace=False))
+    e = eloc.cpu().numpy()
+    for i in picks:
+        want, _, _ = oracle_eloc(ref, h, eri, int(xv[i]))
+        err = abs(e[i] - want)
+        log(f"  x={int(xv[i]):#x} count={cv[i]} eloc gpu={e[i]:.6f} oracle={want:.6f} err={err:.2e}")
+        assert err < 5e-3 * max(1.0, abs(want))
