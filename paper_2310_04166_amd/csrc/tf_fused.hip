@@ -100,81 +100,182 @@ __device__ inline f32x16 load16(const float *p) {
   return r;
 }
 
+// Sum / max over the two lanes that hold the same row (l and l ^ 32).
+__device__ inline float pair_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float pair_max(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
 __device__ inline float gelu(float x) {
-  // 0.5 x (1 + tanh(u)) = x * sigmoid(2u), u = sqrt(2/pi) (x + 0.044715 x^3);
+  // 0.5 x (1 + tanh(u)) = x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3);
   // hardware exp2 and reciprocal (about 1 ulp each), far below bf16 rounding
-  const float u2 = 1.5957691216057308f * x * (1.0f + 0.044715f * x * x);
-  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * u2));
+  constexpr float c1 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+  constexpr float c3 = c1 * 0.044715f;
+  const float e = __builtin_amdgcn_exp2f(x * fmaf(x * x, c3, c1));
+  return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
-// acc = W-fragments(block) x X  (weights as A operand, activations as B)
-template <int KS>
-__device__ inline f32x16 wx(const bf16x8 *__restrict__ w, const bf16x8 (&X)[KS], f32x16 acc) {
-  bf16x8 f[KS];
+__device__ inline bf16x8 pack8(const float (&v)[8]) {
+  bf16x8 r;
 #pragma unroll
-  for (int s = 0; s < KS; ++s) f[s] = w[s * 64];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) acc = mfma(f[s], X[s], acc);
-  return acc;
+  for (int i = 0; i < 8; i += 2) {
+    f32x2 p = {v[i], v[i + 1]};
+    bf16x2 q = __builtin_convertvector(p, bf16x2);
+    r[i] = q[0];
+    r[i + 1] = q[1];
+  }
+  return r;
 }
 
-// acc = X x W-fragments(block)  (activations as A operand: row-major output)
-template <int KS>
-__device__ inline f32x16 xw(const bf16x8 (&X)[KS], const bf16x8 *__restrict__ w, f32x16 acc) {
-  bf16x8 f[KS];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) f[s] = w[s * 64];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) acc = mfma(X[s], f[s], acc);
-  return acc;
-}
+struct View;
+__device__ inline f32x16 vec16_at(const View &v, uint32_t byte_off);
 
-// Layer norm of the feature-major residual into a bf16 operand.
+// Layer norm of the feature-major residual into a bf16 operand; gain and shift
+// are permuted vectors read through V (byte offsets g_off, b_off).
 template <int NB>
-__device__ inline void layer_norm(const f32x16 (&res)[NB], const float *g, const float *b, int h,
-                                  bf16x8 (&X)[2 * NB]) {
-  float s = 0.f;
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) s += res[q][j];
-  s += __shfl_xor(s, 32);
-  const float mu = s * (1.0f / (32 * NB));
-  float v = 0.f;
+__device__ inline void layer_norm(const f32x16 (&res)[NB], const View &V, uint32_t g_off,
+                                  uint32_t b_off, bf16x8 (&X)[2 * NB]) {
+  float s = 0.f, s2 = 0.f;
 #pragma unroll
   for (int q = 0; q < NB; ++q)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const float d = res[q][j] - mu;
-      v += d * d;
+      s += res[q][j];
+      s2 = fmaf(res[q][j], res[q][j], s2);
     }
-  v += __shfl_xor(v, 32);
-  const float rs = rsqrtf(v * (1.0f / (32 * NB)) + 1e-5f);
+  s = pair_sum(s);
+  s2 = pair_sum(s2);
+  const float mu = s * (1.0f / (32 * NB));
+  const float rs = rsqrtf(fmaxf(s2 * (1.0f / (32 * NB)) - mu * mu, 0.f) + 1e-5f);
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const f32x16 gg = load16(g + (q * 2 + h) * 16), bb = load16(b + (q * 2 + h) * 16);
+    const f32x16 gg = vec16_at(V, g_off + q * 128), bb = vec16_at(V, b_off + q * 128);
     f32x16 y;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) y[j] = (res[q][j] - mu) * rs * gg[j] + bb[j];
+    for (int j = 0; j < 16; ++j) y[j] = fmaf((res[q][j] - mu) * rs, gg[j], bb[j]);
     X[2 * q] = to_bf16(y, 0);
     X[2 * q + 1] = to_bf16(y, 1);
   }
 }
 
+// The weight stream of one layer is a fixed sequence of steps of KS fragments
+// each: for every head pair b the Q, K, V and output-projection fragments, then
+// for every hidden block fb the two feed-forward fragments.  The next step is
+// always loaded while the current one is multiplied.
+// Every layer occupies the same-sized slice of the packed buffers, so all
+// offsets inside a layer are compile-time constants (in bf16x8 entries, 64 per
+// fragment, and in floats for the permuted vectors).
 template <int D>
-__global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
-  constexpr int NB = D / 32, KS = D / 16, F = 4 * D, FB = F / 32;
+struct Shape {
+  static constexpr int NB = D / 32, KS = D / 16, F = 4 * D, FB = F / 32, FKS = F / 16;
+  static constexpr int STEPS = 4 * NB + 2 * FB;
+  static constexpr int64_t OQ = 0, OK = int64_t(NB) * KS * 64, OV = 2 * OK, OO = 3 * OK,
+                           OW1 = 4 * OK, OW2 = OW1 + int64_t(FB) * KS * 64,
+                           FRAG_L = OW2 + int64_t(NB) * FKS * 64;
+  static constexpr int64_t VLN1G = 0, VLN1B = D, VBQ = 2 * D, VBK = 3 * D, VBV = 4 * D,
+                           VBO = 5 * D, VLN2G = 6 * D, VLN2B = 7 * D, VB1 = 8 * D,
+                           VB2 = 8 * D + F, VEC_L = 9 * D + F;
+};
+
+// Per-layer slices are read through buffer resources: the layer's base goes
+// into the resource, the lane's part of the address into a fixed VGPR and the
+// compile-time offset into the scalar offset, so no 64-bit addresses stay live.
+struct View {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t voff;
+};
+typedef __attribute__((ext_vector_type(4))) int i32x4;
+
+__device__ inline View make_view(const void *base, uint32_t bytes, uint32_t voff) {
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000),
+          voff};
+}
+__device__ inline bf16x8 frag_at(const View &v, uint32_t byte_off) {
+  return __builtin_bit_cast(bf16x8,
+                            __builtin_amdgcn_raw_buffer_load_b128(v.rsrc, v.voff, byte_off, 0));
+}
+__device__ inline f32x16 vec16_at(const View &v, uint32_t byte_off) {
+  f32x16 r;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const f32x4 q = __builtin_bit_cast(
+        f32x4, __builtin_amdgcn_raw_buffer_load_b128(v.rsrc, v.voff, byte_off + 16 * c, 0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[4 * c + i] = q[i];
+  }
+  return r;
+}
+
+// W = the layer's fragments (voff = 16 * lane); s = step index
+template <int D>
+__device__ inline void load_step(bf16x8 (&f)[Shape<D>::KS], const View &W, int s) {
+  using S = Shape<D>;
+  constexpr int KS = S::KS;
+  int64_t base;
+  int kind;
+  if (s < 4 * S::NB) {
+    const int b = s / 4;
+    kind = s % 4;
+    base = kind == 0 ? S::OQ + int64_t(b) * KS * 64
+         : kind == 1 ? S::OK + int64_t(b) * KS * 64
+         : kind == 2 ? S::OV + int64_t(b) * KS * 64
+                     : S::OO + int64_t(2 * b) * 64;
+    kind = kind == 3 ? 1 : 0;
+  } else {
+    const int fb = (s - 4 * S::NB) / 2;
+    if ((s - 4 * S::NB) % 2 == 0) {
+      base = S::OW1 + int64_t(fb) * KS * 64;
+      kind = 0;
+    } else {
+      base = S::OW2 + int64_t(2 * fb) * 64;
+      kind = 2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KS; ++i) {
+    // kind 0: KS consecutive k-steps of one output block; kind 1 (output
+    // projection) / 2 (second FFN layer): output block i/2, k-step 2b + i%2
+    const int64_t o = kind == 0 ? int64_t(i) * 64
+                    : kind == 1 ? (int64_t(i / 2) * KS + (i % 2)) * 64
+                                : (int64_t(i / 2) * S::FKS + (i % 2)) * 64;
+    f[i] = frag_at(W, uint32_t((base + o) * 16));
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+fused_kernel(FusedArgs a) {
+  using S = Shape<D>;
+  constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
   const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
   const int64_t group = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
   const int64_t c_base = group * 32;
   if (c_base >= a.B) return;
   const int t = r % kSeq;            // position of this lane's row
+  const bool upper = r >= kSeq;      // second configuration of the pair
   const int n = a.n;
   const bf16x8 *pk = a.pk + lane;
   const float *vec = a.vec;
 
+  const uint32_t upmask = upper ? 0xFFFFFFFFu : 0u;
+  // causal mask of this lane's 8 key slots (the same in every head and layer)
+  float madd[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) madd[i] = ((i / 4) * 8 + h * 4 + (i % 4)) <= t ? 0.f : -INFINITY;
+
+  constexpr uint32_t kFragBytes = uint32_t(S::FRAG_L * 16), kVecBytes = uint32_t(S::VEC_L * 4);
+  auto wview = [&](int l) {
+    return make_view(a.pk + int64_t(l) * S::FRAG_L, kFragBytes, uint32_t(lane) * 16u);
+  };
+  bf16x8 fr[2][KS];
+  load_step<D>(fr[0], wview(0), 0);
+
   for (int pair = 0; pair < kPairs; ++pair) {
-    const int64_t cfg = c_base + 2 * pair + r / kSeq;
+    const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
     if (c_base + 2 * pair >= a.B) break;
     const bool live = cfg < a.B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
@@ -193,83 +294,100 @@ __global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
     }
 
     for (int l = 0; l < a.L; ++l) {
-      // ---- attention block
+      const View W = wview(l), Wn = wview(l + 1 < a.L ? l + 1 : 0);
+      // permuted vectors of the layer: lane-half h reads 16 floats at (2q+h)*16
+      const View V16 = make_view(vec + int64_t(l) * S::VEC_L, kVecBytes, uint32_t(h) * 64u);
+      const float *lv = vec + int64_t(l) * S::VEC_L;
       bf16x8 X[KS];
-      layer_norm<NB>(res, vec + a.ln1g[l], vec + a.ln1b[l], h, X);
+      // ---- attention block
+      layer_norm<NB>(res, V16, uint32_t(S::VLN1G * 4), uint32_t(S::VLN1B * 4), X);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) res[q] += load16(vec + a.bo[l] + (q * 2 + h) * 16);
+      for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VBO + q * 32) * 4));
+#pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const f32x16 bq = load16(vec + a.bq[l] + (b * 2 + h) * 16);
-        const f32x16 bk = load16(vec + a.bk[l] + (b * 2 + h) * 16);
-        const float bvv = vec[a.bv[l] + 32 * b + r];
-        const f32x16 Qc = wx<KS>(pk + a.q[l] + int64_t(b) * KS * 64, X, bq);
-        const f32x16 Kc = wx<KS>(pk + a.k[l] + int64_t(b) * KS * 64, X, bk);
-        f32x16 Vb;
+        // step 4b: Q (fr[0]); 4b+1: K (fr[1]); 4b+2: V (fr[0]); 4b+3: O (fr[1])
+        load_step<D>(fr[1], W, 4 * b + 1);
+        f32x16 Qc = vec16_at(V16, uint32_t((S::VBQ + b * 32) * 4));
 #pragma unroll
-        for (int j = 0; j < 16; ++j) Vb[j] = bvv;
-        const f32x16 Vc = xw<KS>(X, pk + a.v[l] + int64_t(b) * KS * 64, Vb);
+        for (int s = 0; s < KS; ++s) Qc = mfma(fr[0][s], X[s], Qc);
+        load_step<D>(fr[0], W, 4 * b + 2);
+        f32x16 Kc = vec16_at(V16, uint32_t((S::VBK + b * 32) * 4));
+#pragma unroll
+        for (int s = 0; s < KS; ++s) Kc = mfma(fr[1][s], X[s], Kc);
+        load_step<D>(fr[1], W, 4 * b + 3);
+        f32x16 Vc;
+        const float bvv = lv[S::VBV + 32 * b + r];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Vc[j] = bvv;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) Vc = mfma(X[s], fr[0][s], Vc);
+        load_step<D>(fr[0], W, 4 * b + 4);   // next Q, or the first FFN step
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
-        f32x16 O = {};
-        // S[j] = score(key (j/4)*8 + h*4 + j%4, query r).  Keys of the other
-        // configuration (j >= 8 for r < 16, j < 8 for r >= 16) are masked, so
-        // only the 8 slots of this lane's own configuration are worked on.
-        const bool upper = r >= kSeq;
+        f32x16 O;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          const f32x16 S = mfma(to_bf16(Kc, e), to_bf16(Qc, e), f32x16{});
+          // S[j] = score(key (j/4)*8 + h*4 + j%4, query r); the lane's own
+          // configuration holds slots j = 0..7 (lower) or 8..15 (upper)
+          const f32x16 Sc = mfma(to_bf16(Kc, e), to_bf16(Qc, e), f32x16{});
           float p[8];
           float mx = -INFINITY;
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
-            const int kk = (i / 4) * 8 + h * 4 + (i % 4);  // key position in the config
-            const float s = upper ? S[8 + i] : S[i];
-            p[i] = kk <= t ? s * (0.25f * 1.4426950408889634f) : -INFINITY;
+            // bitwise select of the lane's half (keeps the compiler from
+            // turning it into a dynamically indexed vector)
+            const float s = __uint_as_float((__float_as_uint(Sc[8 + i]) & upmask) |
+                                            (__float_as_uint(Sc[i]) & ~upmask));
+            p[i] = fmaf(s, 0.25f * 1.4426950408889634f, madd[i]);
             mx = fmaxf(mx, p[i]);
           }
-          mx = fmaxf(mx, __shfl_xor(mx, 32));
+          mx = pair_max(mx);
           float sum = 0.f;
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             p[i] = __builtin_amdgcn_exp2f(p[i] - mx);
             sum += p[i];
           }
-          sum += __shfl_xor(sum, 32);
-          const float inv = __builtin_amdgcn_rcpf(sum);
-          f32x16 P;
+          const float inv = __builtin_amdgcn_rcpf(pair_sum(sum));
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float v = p[i] * inv;
-            P[i] = upper ? 0.f : v;
-            P[8 + i] = upper ? v : 0.f;
-          }
-          f32x16 Oe = mfma(V0, to_bf16(P, 0), f32x16{});
-          Oe = mfma(V1, to_bf16(P, 1), Oe);
+          for (int i = 0; i < 8; ++i) p[i] *= inv;
+          const i32x4 pp = __builtin_bit_cast(i32x4, pack8(p));
+          const int m = int(upmask);
+          const i32x4 plo = {pp[0] & ~m, pp[1] & ~m, pp[2] & ~m, pp[3] & ~m};
+          const i32x4 phi = {pp[0] & m, pp[1] & m, pp[2] & m, pp[3] & m};
+          f32x16 Oe = mfma(V0, __builtin_bit_cast(bf16x8, plo), f32x16{});
+          Oe = mfma(V1, __builtin_bit_cast(bf16x8, phi), Oe);
 #pragma unroll
           for (int j = 0; j < 8; ++j) O[e * 8 + j] = Oe[e * 8 + j];
         }
         const bf16x8 O0 = to_bf16(O, 0), O1 = to_bf16(O, 1);
-        const bf16x8 *wo = pk + a.o[l];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          res[q] = mfma(wo[(int64_t(q) * KS + 2 * b) * 64], O0, res[q]);
-          res[q] = mfma(wo[(int64_t(q) * KS + 2 * b + 1) * 64], O1, res[q]);
+          res[q] = mfma(fr[1][2 * q], O0, res[q]);
+          res[q] = mfma(fr[1][2 * q + 1], O1, res[q]);
         }
       }
-      // ---- feed-forward block
-      layer_norm<NB>(res, vec + a.ln2g[l], vec + a.ln2b[l], h, X);
+      // ---- feed-forward block: step 4NB + 2fb = W1 (fr[0]), +1 = W2 (fr[1])
+      layer_norm<NB>(res, V16, uint32_t(S::VLN2G * 4), uint32_t(S::VLN2B * 4), X);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) res[q] += load16(vec + a.b2[l] + (q * 2 + h) * 16);
-      const bf16x8 *w2 = pk + a.w2[l];
+      for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VB2 + q * 32) * 4));
+#pragma unroll
       for (int fb = 0; fb < FB; ++fb) {
-        f32x16 Hc = wx<KS>(pk + a.w1[l] + int64_t(fb) * KS * 64, X,
-                           load16(vec + a.b1[l] + (fb * 2 + h) * 16));
+        const int s = 4 * NB + 2 * fb;
+        load_step<D>(fr[1], W, s + 1);
+        f32x16 Hc = vec16_at(V16, uint32_t((S::VB1 + fb * 32) * 4));
+#pragma unroll
+        for (int k = 0; k < KS; ++k) Hc = mfma(fr[0][k], X[k], Hc);
+        if (s + 2 < STEPS)
+          load_step<D>(fr[0], W, s + 2);
+        else
+          load_step<D>(fr[0], Wn, 0);
 #pragma unroll
         for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
         const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          res[q] = mfma(w2[(int64_t(q) * (F / 16) + 2 * fb) * 64], H0, res[q]);
-          res[q] = mfma(w2[(int64_t(q) * (F / 16) + 2 * fb + 1) * 64], H1, res[q]);
+          res[q] = mfma(fr[1][2 * q], H0, res[q]);
+          res[q] = mfma(fr[1][2 * q + 1], H1, res[q]);
         }
       }
     }
@@ -277,23 +395,18 @@ __global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
     // ---- final layer norm, head, masked log-softmax
     float lg[4] = {0.f, 0.f, 0.f, 0.f};
     {
-      float s = 0.f;
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s += res[q][j];
-      s += __shfl_xor(s, 32);
-      const float mu = s * (1.0f / D);
-      float v = 0.f;
+      float s = 0.f, s2 = 0.f;
 #pragma unroll
       for (int q = 0; q < NB; ++q)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const float d = res[q][j] - mu;
-          v += d * d;
+          s += res[q][j];
+          s2 = fmaf(res[q][j], res[q][j], s2);
         }
-      v += __shfl_xor(v, 32);
-      const float rs = rsqrtf(v * (1.0f / D) + 1e-5f);
+      s = pair_sum(s);
+      s2 = pair_sum(s2);
+      const float mu = s * (1.0f / D);
+      const float rs = rsqrtf(fmaxf(s2 * (1.0f / D) - mu * mu, 0.f) + 1e-5f);
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const f32x16 gg = load16(vec + a.lnfg + (q * 2 + h) * 16);
@@ -301,16 +414,16 @@ __global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
         const f32x4 *wh = reinterpret_cast<const f32x4 *>(vec + a.whead) + (q * 2 + h) * 16;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const float y = (res[q][j] - mu) * rs * gg[j] + bb[j];
+          const float y = fmaf((res[q][j] - mu) * rs, gg[j], bb[j]);
           const f32x4 w = wh[j];
-          lg[0] += y * w[0];
-          lg[1] += y * w[1];
-          lg[2] += y * w[2];
-          lg[3] += y * w[3];
+          lg[0] = fmaf(y, w[0], lg[0]);
+          lg[1] = fmaf(y, w[1], lg[1]);
+          lg[2] = fmaf(y, w[2], lg[2]);
+          lg[3] = fmaf(y, w[3], lg[3]);
         }
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) lg[k] += __shfl_xor(lg[k], 32);
+      for (int k = 0; k < 4; ++k) lg[k] = pair_sum(lg[k]);
     }
     float logp = 0.f;
     if (t < n) {
@@ -365,12 +478,15 @@ __global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
     }
     float ph = 0.f;
     for (int b = 0; b < PB; ++b) {
-      f32x16 z = wx<PKS>(pk + a.p2 + int64_t(b) * PKS * 64, Z, load16(vec + a.pb2 + (b * 2 + h) * 16));
+      f32x16 z = load16(vec + a.pb2 + (b * 2 + h) * 16);
+      const bf16x8 *w = pk + a.p2 + int64_t(b) * PKS * 64;
+#pragma unroll
+      for (int s = 0; s < PKS; ++s) z = mfma(w[s * 64], Z[s], z);
       const f32x16 w3 = load16(vec + a.pw3 + (b * 2 + h) * 16);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) ph += gelu(z[j]) * w3[j];
+      for (int j = 0; j < 16; ++j) ph = fmaf(gelu(z[j]), w3[j], ph);
     }
-    ph += __shfl_xor(ph, 32);
+    ph = pair_sum(ph);
     if (h == 0 && live) a.phase[cfg] = double(ph + vec[a.pb3]);
   }
 }
@@ -480,6 +596,24 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   NQS_REQUIRE(fused_supported(m), NQS_EUNSUPPORTED, "fused forward: unsupported dimensions");
   Layout L = plan(m);
   static_assert(sizeof(bf16x8) == 16, "fragment size");
+  // the kernel addresses layer l at l * FRAG_L / l * VEC_L with constant offsets
+  auto check = [&](auto shape) {
+    using S = decltype(shape);
+    for (int l = 0; l < m.L; ++l) {
+      const int64_t f = l * S::FRAG_L, v = l * S::VEC_L;
+      NQS_REQUIRE(L.a.q[l] == f + S::OQ && L.a.k[l] == f + S::OK && L.a.v[l] == f + S::OV &&
+                      L.a.o[l] == f + S::OO && L.a.w1[l] == f + S::OW1 &&
+                      L.a.w2[l] == f + S::OW2 && L.a.ln1g[l] == v + S::VLN1G &&
+                      L.a.ln1b[l] == v + S::VLN1B && L.a.bq[l] == v + S::VBQ &&
+                      L.a.bk[l] == v + S::VBK && L.a.bv[l] == v + S::VBV &&
+                      L.a.bo[l] == v + S::VBO && L.a.ln2g[l] == v + S::VLN2G &&
+                      L.a.ln2b[l] == v + S::VLN2B && L.a.b1[l] == v + S::VB1 &&
+                      L.a.b2[l] == v + S::VB2,
+                  NQS_EINVAL, "fused forward: packed layout mismatch");
+    }
+  };
+  if (m.d == 128) check(Shape<128>{});
+  else check(Shape<64>{});
   __bf16 *pk = static_cast<__bf16 *>(m.packed.reserve(size_t(L.frag_total) * 16));
   const float *W = m.master.as<float>();
   const int D = m.d, F = m.F, NB = D / 32, KS = D / 16, PH = m.PH, n = m.n;
