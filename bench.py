@@ -149,7 +149,7 @@ def main():
     torch.cuda.synchronize()
     nqs.timing_enable(True)
     nqs.timing_read()
-    total_pairs, total_unique, step_ms, energies = 0, 0, [], []
+    total_pairs, total_unique, total_distinct, step_ms, energies = 0, 0, 0, [], []
     first = None
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -165,6 +165,7 @@ def main():
         energies.append(float(s[1] / s[0]))
         total_pairs += npairs
         total_unique += x.numel()
+        total_distinct += nqs.local_energy_stats(ham)[1]
         if first is None:
             first = (x.clone(), cnt.clone())
         log(f"step {k}: unique={x.numel()} pairs={npairs} E={s[1] / s[0]:.6f} "
@@ -201,6 +202,7 @@ def main():
                                   "1e6 samples/step, transformer d128 L4 h8 + phase MLP 256",
                       "unique_per_step": total_unique / args.steps,
                       "pairs_per_step": total_pairs / args.steps,
+                      "distinct_xprime_per_step": total_distinct / args.steps,
                       "gpu_ms_per_step": round(gpu_ms / args.steps, 2),
                       "step_ms": [round(v, 1) for v in step_ms],
                       "energy_per_step": energies},

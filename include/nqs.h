@@ -231,6 +231,14 @@ int local_energy(nqs_ham *ham, nqs_model *m, const uint64_t *x, const uint64_t *
                  double *sums, int64_t *n_pairs, nqs_stream stream);
 
 /*
+ * local_energy_stats - work of the last local_energy call on this Hamiltonian:
+ * the number of (x, x') pairs and the number of distinct x' on which the
+ * amplitude network ran (local_energy evaluates psi once per distinct x' of a
+ * slice of at most 2^27 pairs; the sum over pairs is unchanged).
+ */
+int local_energy_stats(const nqs_ham *ham, int64_t *n_pairs, int64_t *n_distinct);
+
+/*
  * vmc_weights - upstream weights of the VMC gradient (paper: gradient
  * equation in "Variational Monte Carlo"): with W = sums[0] and E =
  * (sums[1] + i sums[2]) / W, g_logabs[l] = 2 n_l / W Re(E_loc,l - E) and

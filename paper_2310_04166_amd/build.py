@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnqs.so")
-SOURCES = ["ham_compile.cpp", "eloc.hip", "ops.hip", "model.hip", "sampler.hip", "api.hip",
+SOURCES = ["ham_compile.cpp", "eloc.hip", "ops.hip", "model.hip", "sampler.hip", "api.hip", "dedupe.hip",
            "tf_fused.hip"]
 ARCH = os.environ.get("NQS_OFFLOAD_ARCH", "gfx950")
 

@@ -18,9 +18,13 @@ thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 // defined in eloc.hip
-void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const double *la_p,
-                       const double *ph_p, const double *la_x, const double *ph_x,
-                       const double *hdiag, double *eloc, hipStream_t s);
+void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,
+                       const double *la_p, const double *ph_p, const double *la_x,
+                       const double *ph_x, const double *hdiag, double *eloc, hipStream_t s);
+// defined in dedupe.hip
+int64_t dedupe_pairs(const uint64_t *xp, int64_t n, int key_bits, uint64_t *keys_sorted,
+                     uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
+                     uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s);
 void launch_reduce(const double *eloc, const uint64_t *counts, int64_t n, double *sums,
                    hipStream_t s);
 void launch_weights(const double *eloc, const uint64_t *counts, int64_t n, const double *sums,
@@ -280,6 +284,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
     HIP_OK(hipMemcpyAsync(off_h.data(), off, size_t(n + 1) * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (n_pairs) *n_pairs = off_h[n];
+    H->last_pairs = off_h[n];
     double *hdiag = static_cast<double *>(H->w_diag.reserve(size_t(n) * 8));
     const double *lax = logabs_x, *phx = phase_x;
     if (!lax) {
@@ -290,30 +295,48 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
       lax = a;
       phx = b;
     }
-    // pairs are processed in slices of whole configurations
-    const int64_t cap = int64_t(1) << 24;
+    // Pairs are processed in slices of whole configurations (at most 2^27
+    // pairs); inside a slice the amplitude network runs once per distinct x'.
+    const int64_t cap = int64_t(1) << 27;
     int64_t maxk = 0;
     for (int64_t i = 0; i < n; ++i) maxk = std::max(maxk, off_h[i + 1] - off_h[i]);
-    const int64_t slice = std::max(cap, maxk);
+    const int64_t slice = std::min(std::max(cap, maxk), std::max<int64_t>(off_h[n], 1));
     auto *xp = static_cast<uint64_t *>(H->w_xp.reserve(size_t(slice) * 8));
     auto *hv = static_cast<double *>(H->w_h.reserve(size_t(slice) * 8));
     auto *la = static_cast<double *>(H->w_la.reserve(size_t(slice) * 8));
     auto *ph = static_cast<double *>(H->w_ph.reserve(size_t(slice) * 8));
+    auto *keys = static_cast<uint64_t *>(H->w_keys.reserve(size_t(slice) * 8));
+    auto *ukeys = static_cast<uint64_t *>(H->w_ukeys.reserve(size_t(slice) * 8));
+    auto *u32 = static_cast<uint32_t *>(H->w_u32.reserve(size_t(slice) * 4 * 5));
+    uint32_t *vin = u32, *vsort = u32 + slice, *head = u32 + 2 * slice,
+             *run = u32 + 3 * slice, *uid = u32 + 4 * slice;
     int64_t i0 = 0;
+    H->last_distinct = 0;
     while (i0 < n) {
       int64_t i1 = i0 + 1;
       while (i1 < n && off_h[i1 + 1] - off_h[i0] <= slice) ++i1;
       const int64_t np = off_h[i1] - off_h[i0];
       launch_emit_pairs(*H, x + i0, i1 - i0, off + i0, xp, hv, nullptr, hdiag + i0, 0, s);
-      if (np > 0) {
-        if (m->precision == NQS_BF16) fused_forward(*m, xp, np, la, ph, nullptr, -1, s);
-        else model_forward(*m, xp, np, la, ph, nullptr, s);
+      const int64_t nu = dedupe_pairs(xp, np, H->N, keys, vin, vsort, head, run, ukeys, uid,
+                                      H->w_tmp, s);
+      H->last_distinct += nu;
+      if (nu > 0) {
+        if (m->precision == NQS_BF16) fused_forward(*m, ukeys, nu, la, ph, nullptr, -1, s);
+        else model_forward(*m, ukeys, nu, la, ph, nullptr, s);
       }
-      launch_accumulate(i1 - i0, off + i0, hv, la, ph, lax + i0, phx + i0, hdiag + i0,
-                        eloc + 2 * i0, s);
+      launch_accumulate(i1 - i0, off + i0, hv, np > 0 ? uid : nullptr, la, ph, lax + i0,
+                        phx + i0, hdiag + i0, eloc + 2 * i0, s);
       i0 = i1;
     }
     launch_reduce(eloc, counts, n, sums, s);
+  });
+}
+
+extern "C" int local_energy_stats(const nqs_ham *H, int64_t *n_pairs, int64_t *n_distinct) {
+  return guarded([&] {
+    NQS_REQUIRE(H, NQS_EINVAL, "local_energy_stats: null handle");
+    if (n_pairs) *n_pairs = H->last_pairs;
+    if (n_distinct) *n_distinct = H->last_distinct;
   });
 }
 

@@ -1,0 +1,74 @@
+// Distinct connected configurations of a slice of (x, x') pairs.  Many sampled
+// x share connected x' (they cluster around the dominant determinants), and
+// psi(x') does not depend on which x it is connected to, so the amplitude
+// network runs once per distinct x' (the local-energy sum itself is unchanged).
+//
+// keys = x' of every pair; radix sort (key, pair index) over the 2n used bits;
+// a head flag marks the first of each run of equal keys; an inclusive scan of
+// the flags numbers the runs; run heads write the distinct keys in ascending
+// order and every pair learns its run number through the sorted pair index.
+#include <algorithm>
+
+#include <hipcub/hipcub.hpp>
+
+#include "common.h"
+
+namespace nqs {
+namespace {
+
+__global__ void iota_kernel(uint32_t *v, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = uint32_t(i);
+}
+
+__global__ void head_kernel(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ head) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ void scatter_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                               const uint32_t *__restrict__ head, const uint32_t *__restrict__ run,
+                               int64_t n, uint64_t *__restrict__ ukeys,
+                               uint32_t *__restrict__ pair_uid) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t id = run[i] - 1u;
+  if (head[i]) ukeys[id] = keys[i];
+  pair_uid[vals[i]] = id;
+}
+
+inline dim3 g1(int64_t n) { return dim3(unsigned(ceil_div(n, 256))); }
+
+}  // namespace
+
+// Returns the number of distinct keys U; ukeys[0..U) ascending, pair_uid[p] =
+// index of xp[p] in ukeys.  All buffers are caller-provided workspaces sized
+// for n pairs; tmp is grown as needed.
+int64_t dedupe_pairs(const uint64_t *xp, int64_t n, int key_bits, uint64_t *keys_sorted,
+                     uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
+                     uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s) {
+  if (n <= 0) return 0;
+  NQS_REQUIRE(n < (int64_t(1) << 31), NQS_EUNSUPPORTED, "dedupe: slice too large");
+  const int ni = int(n);
+  hipLaunchKernelGGL(iota_kernel, g1(n), dim3(256), 0, s, vals_in, n);
+  HIP_LAUNCH_OK();
+  size_t sort_bytes = 0, scan_bytes = 0;
+  HIP_OK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, xp, keys_sorted, vals_in,
+                                            vals_sorted, ni, 0, key_bits, s));
+  HIP_OK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, head, run, ni, s));
+  void *t = tmp.reserve(std::max(sort_bytes, scan_bytes) + 256);
+  HIP_OK(hipcub::DeviceRadixSort::SortPairs(t, sort_bytes, xp, keys_sorted, vals_in, vals_sorted,
+                                            ni, 0, key_bits, s));
+  hipLaunchKernelGGL(head_kernel, g1(n), dim3(256), 0, s, keys_sorted, n, head);
+  HIP_LAUNCH_OK();
+  HIP_OK(hipcub::DeviceScan::InclusiveSum(t, scan_bytes, head, run, ni, s));
+  hipLaunchKernelGGL(scatter_kernel, g1(n), dim3(256), 0, s, keys_sorted, vals_sorted, head, run,
+                     n, ukeys, pair_uid);
+  HIP_LAUNCH_OK();
+  uint32_t u = 0;
+  HIP_OK(hipMemcpyAsync(&u, run + (n - 1), 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return int64_t(u);
+}
+
+}  // namespace nqs

@@ -114,12 +114,14 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ 
 }
 
 // E_loc(x_i) = hdiag_i + sum_j H_ij exp((la'_j - la_i) + i (ph'_j - ph_i)), one
-// wave per x over its contiguous pairs, fixed-order reduction, double.
+// wave per x over its contiguous pairs, fixed-order reduction, double.  With
+// uid, the amplitudes of pair j are those of distinct configuration uid[j].
 __global__ void __launch_bounds__(256) accumulate_kernel(
     int64_t n, const int64_t *__restrict__ off, const double *__restrict__ hval,
-    const double *__restrict__ la_p, const double *__restrict__ ph_p,
-    const double *__restrict__ la_x, const double *__restrict__ ph_x,
-    const double *__restrict__ hdiag, double *__restrict__ eloc) {
+    const uint32_t *__restrict__ uid, const double *__restrict__ la_p,
+    const double *__restrict__ ph_p, const double *__restrict__ la_x,
+    const double *__restrict__ ph_x, const double *__restrict__ hdiag,
+    double *__restrict__ eloc) {
   const int lane = threadIdx.x % kWave;
   const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   if (i >= n) return;
@@ -127,9 +129,10 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
   const double lx = la_x[i], px = ph_x[i];
   double re = 0.0, im = 0.0;
   for (int64_t j = j0 + lane; j < j1; j += kWave) {
-    const double a = exp(la_p[j] - lx);
+    const int64_t u = uid ? int64_t(uid[j]) : j;
+    const double a = exp(la_p[u] - lx);
     double s, c;
-    sincos(ph_p[j] - px, &s, &c);
+    sincos(ph_p[u] - px, &s, &c);
     re += hval[j] * a * c;
     im += hval[j] * a * s;
   }
@@ -221,12 +224,12 @@ void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream
   HIP_LAUNCH_OK();
 }
 
-void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const double *la_p,
-                       const double *ph_p, const double *la_x, const double *ph_x,
-                       const double *hdiag, double *eloc, hipStream_t s) {
+void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,
+                       const double *la_p, const double *ph_p, const double *la_x,
+                       const double *ph_x, const double *hdiag, double *eloc, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(ceil_div(n, kWavesPerBlock))), dim3(256), 0,
-                     s, n, off, hval, la_p, ph_p, la_x, ph_x, hdiag, eloc);
+                     s, n, off, hval, uid, la_p, ph_p, la_x, ph_x, hdiag, eloc);
   HIP_LAUNCH_OK();
 }
 

@@ -21,6 +21,9 @@ struct nqs_ham {
   nqs::DevBuf d_flip, d_off, d_zmask, d_coef;
   // local_energy workspaces
   nqs::DevBuf w_cnt, w_off, w_xp, w_h, w_owner, w_la, w_ph, w_diag, w_lax, w_phx;
+  nqs::DevBuf w_keys, w_ukeys, w_u32, w_tmp;   // distinct-x' workspaces
+  int64_t last_distinct = 0;                   // distinct x' of the last local_energy call
+  int64_t last_pairs = 0;                      // (x, x') pairs of the last local_energy call
 
   void upload();
 };

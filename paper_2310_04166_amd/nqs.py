@@ -53,6 +53,7 @@ _SIGS = {
     "connected_pairs": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(_i64), _vp], C.c_int),
     "local_energy": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.POINTER(_i64), _vp],
                      C.c_int),
+    "local_energy_stats": ([_vp, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "vmc_weights": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "adam_update": ([_vp, _vp, _vp, _vp, _i64, C.c_int, _dbl, _dbl, _dbl, _dbl, _i64, _vp],
                     C.c_int),
@@ -245,6 +246,13 @@ def local_energy(ham, model, x, counts=None, logabs_x=None, phase_x=None, stream
                               _ptr(phase_x), _ptr(eloc), _ptr(sums), C.byref(npairs),
                               _stream(stream)))
     return torch.view_as_complex(eloc[:n]), sums, npairs.value
+
+
+def local_energy_stats(ham):
+    """(pairs, distinct x') of the last local_energy call on ``ham``."""
+    p, d = _i64(), _i64()
+    _check(lib().local_energy_stats(ham.handle, C.byref(p), C.byref(d)))
+    return p.value, d.value
 
 
 def vmc_weights(eloc, counts, sums, stream=None):

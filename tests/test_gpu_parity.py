@@ -163,6 +163,23 @@ def test_local_energy_fp64_tiny(nqs):
     assert abs(s[1] / W - E.real) < 1e-10 * abs(E) and abs(s[2] / W - E.imag) < 1e-10 * abs(E)
 
 
+def test_local_energy_distinct_count(nqs):
+    """The amplitude network runs on exactly the distinct connected x'."""
+    cfg, h, eri, params = workload("fp32")
+    m = gpu_model(nqs, nqs.MODEL_TRANSFORMER, nqs.model_dims(cfg), params,
+                  transformer_param_spec(10, 64, 2, 256, 256), "fp32")
+    H = nqs.ham_compile(h, eri, 5, 5)
+    x, c, _ = nqs.sample_unique(m, 100_000, 4)
+    eloc, sums, npairs = nqs.local_energy(H, m, x, c)
+    pairs, distinct = nqs.local_energy_stats(H)
+    xs = [int(v) for v in x.cpu().numpy().view(np.uint64)]
+    ref = set()
+    for xx in xs:
+        ref.update(slater_condon_row(h, eri, xx)[0][1:])
+    assert pairs == npairs == len(xs) * 875
+    assert distinct == len(ref)
+
+
 def test_local_energy_fp32_workload(nqs):
     """fp32 transformer at 20 spin-orbitals on sampled configurations."""
     log("local_energy fp32 workload")
