@@ -214,52 +214,16 @@ __global__ void mlp_dphase_kernel(const uint64_t *x, int64_t B, int n, const dou
   d8[r * 8 + 4 + k] = tok_of(x[b], t) == k ? T(gp[b]) : T(0);
 }
 
+// one-hot input class of every row (BOS = class 4 at position 0), [B*n, 5]
 template <class T>
-__global__ void tok_emb_grad_kernel(const uint64_t *x, int64_t B, int n, int d, const T *dh,
-                                    double *acc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 5 * d) return;
-  const int c = idx / d, j = idx % d;
-  double a = 0.0;
-  for (int64_t r = 0; r < B * n; ++r) {
-    const int t = int(r % n);
-    const int in = t == 0 ? 4 : tok_of(x[r / n], t - 1);
-    if (in == c) a += double(dh[r * d + j]);
-  }
-  acc[idx] += a;
-}
-
-template <class T>
-__global__ void pos_emb_grad_kernel(int64_t B, int n, int d, const T *dh, double *acc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * d) return;
-  const int t = idx / d, j = idx % d;
-  double a = 0.0;
-  for (int64_t b = 0; b < B; ++b) a += double(dh[(b * n + t) * d + j]);
-  acc[idx] += a;
-}
-
-// per-position sums over configurations: acc[t*w + k] += sum_b Y[(b n + t) w + k]
-template <class T>
-__global__ void pos_sum_kernel(const T *Y, int64_t B, int n, int w, double *acc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * w) return;
-  double a = 0.0;
-  for (int64_t b = 0; b < B; ++b) a += double(Y[b * n * w + idx]);
-  acc[idx] += a;
-}
-
-template <class T>
-__global__ void phase_w1_grad_kernel(const uint64_t *x, int64_t B, int n, int PH, const T *dpre,
-                                     double *acc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 4 * n * PH) return;
-  const int row = idx / PH, j = idx % PH;
-  const int t = row / 4, k = row % 4;
-  double a = 0.0;
-  for (int64_t b = 0; b < B; ++b)
-    if (tok_of(x[b], t) == k) a += double(dpre[b * PH + j]);
-  acc[idx] += a;
+__global__ void in_class_kernel(const uint64_t *x, int64_t B, int n, T *E) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= B * n * 5) return;
+  const int c = int(idx % 5);
+  const int64_t r = idx / 5;
+  const int t = int(r % n);
+  const int in = t == 0 ? 4 : tok_of(x[r / n], t - 1);
+  E[idx] = in == c ? T(1) : T(0);
 }
 
 template <class T>
@@ -351,19 +315,19 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
     Layer<T> &y = A.layer[l];
     auto W = [&](int k) { return P<T>(m, tf_layer(l, k)); };
     layernorm<T>(y.h_in, R, d, W(TF_LN1G), W(TF_LN1B), y.a1, y.m1, y.r1, s);
-    gemm<T, T, false, false>(R, 3 * d, d, y.a1, d, W(TF_WQKV), 3 * d, y.qkv, 3 * d, W(TF_BQKV),
+    gemm<T, false, false>(R, 3 * d, d, y.a1, d, W(TF_WQKV), 3 * d, y.qkv, 3 * d, W(TF_BQKV),
                              nullptr, EPI_STORE, s);
     attention_fwd<T>(y.qkv, B, n, d, H, y.o, y.probs, s);
     if (y.h_mid != y.h_in)
       HIP_OK(hipMemcpyAsync(y.h_mid, y.h_in, R * d * sizeof(T), hipMemcpyDeviceToDevice, s));
-    gemm<T, T, false, false>(R, d, d, y.o, d, W(TF_WO), d, y.h_mid, d, W(TF_BO), nullptr, EPI_ADD,
+    gemm<T, false, false>(R, d, d, y.o, d, W(TF_WO), d, y.h_mid, d, W(TF_BO), nullptr, EPI_ADD,
                              s);
     layernorm<T>(y.h_mid, R, d, W(TF_LN2G), W(TF_LN2B), y.a2, y.m2, y.r2, s);
-    gemm<T, T, false, false>(R, F, d, y.a2, d, W(TF_W1), F, y.f, F, W(TF_B1), y.fpre, EPI_GELU, s);
+    gemm<T, false, false>(R, F, d, y.a2, d, W(TF_W1), F, y.f, F, W(TF_B1), y.fpre, EPI_GELU, s);
     T *h_next = (l + 1 < L) ? A.layer[l + 1].h_in : A.h_out;
     if (h_next != y.h_mid)
       HIP_OK(hipMemcpyAsync(h_next, y.h_mid, R * d * sizeof(T), hipMemcpyDeviceToDevice, s));
-    gemm<T, T, false, false>(R, d, F, y.f, F, W(TF_W2), d, h_next, d, W(TF_B2), nullptr, EPI_ADD,
+    gemm<T, false, false>(R, d, F, y.f, F, W(TF_W2), d, h_next, d, W(TF_B2), nullptr, EPI_ADD,
                              s);
   }
   hipLaunchKernelGGL(head_kernel<T>, g1(R, 4), dim3(256), 0, s, A.h_out, R, n, d,
@@ -380,7 +344,7 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
     hipLaunchKernelGGL(phase_in_kernel<T>, g1(B * PH), dim3(256), 0, s, x, B, n, PH,
                        P<T>(m, tf_tail(L, TF_PW1)), P<T>(m, tf_tail(L, TF_PB1)), A.z1pre, A.z1);
     HIP_LAUNCH_OK();
-    gemm<T, T, false, false>(B, PH, PH, A.z1, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, A.z2, PH,
+    gemm<T, false, false>(B, PH, PH, A.z1, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, A.z2, PH,
                              P<T>(m, tf_tail(L, TF_PB2)), A.z2pre, EPI_GELU, s);
     if (phase) {
       hipLaunchKernelGGL(phase_out_kernel<T>, g1(B, 4), dim3(256), 0, s, A.z2, B, PH,
@@ -394,12 +358,9 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
 template <class T>
 void wgrad(nqs_model &m, int64_t Mi, int64_t No, int64_t R, const T *X, int64_t ldx, const T *dY,
            int64_t ldy, int pidx, hipStream_t s) {
-  const int64_t ks = 2048;
-  const int64_t ns = ceil_div(R, ks);
-  double *part = static_cast<double *>(m.part.reserve(size_t(ns * Mi * No) * 8));
-  gemm<T, double, true, false>(Mi, No, R, X, ldx, dY, ldy, part, No, nullptr, nullptr, EPI_STORE,
-                               s, ks, Mi * No);
-  slices_acc(part, ns, Mi * No, m.grad_acc.as<double>() + m.off[pidx], s);
+  T *part = static_cast<T *>(m.part.reserve(size_t(Mi * No) * sizeof(T)));
+  gemm<T, true, false>(Mi, No, R, X, ldx, dY, ldy, part, No, nullptr, nullptr, EPI_STORE, s);
+  add_into<T>(part, Mi * No, m.grad_acc.as<double>() + m.off[pidx], s);
 }
 
 template <class T>
@@ -446,10 +407,8 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   HIP_LAUNCH_OK();
   wgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), s);
   bgrad<T>(m, dl, R, 4, 4, tf_tail(L, TF_BHEAD), s);
-  hipLaunchKernelGGL(pos_sum_kernel<T>, g1(n * 4), dim3(256), 0, s, dl, B, n, 4,
-                     m.grad_acc.as<double>() + m.off[tf_tail(L, TF_LBIAS)]);
-  HIP_LAUNCH_OK();
-  gemm<T, T, false, true>(R, d, 4, dl, 4, P<T>(m, tf_tail(L, TF_WHEAD)), 4, da, d, nullptr,
+  bgrad<T>(m, dl, B, int64_t(n) * 4, int64_t(n) * 4, tf_tail(L, TF_LBIAS), s);
+  gemm<T, false, true>(R, d, 4, dl, 4, P<T>(m, tf_tail(L, TF_WHEAD)), 4, da, d, nullptr,
                           nullptr, EPI_STORE, s);
   layernorm_bwd<T>(A.h_out, A.mf, A.rf, R, d, P<T>(m, tf_tail(L, TF_LNFG)), da, dh, false, tmp, s);
   bgrad<T>(m, tmp, R, d, d, tf_tail(L, TF_LNFG), s);
@@ -461,33 +420,32 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
     // h_out = h_mid + gelu(a2 W1 + b1) W2 + b2
     wgrad<T>(m, F, d, R, y.f, F, dh, d, tf_layer(l, TF_W2), s);
     bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_B2), s);
-    gemm<T, T, false, true>(R, F, d, dh, d, W(TF_W2), d, df, F, nullptr, nullptr, EPI_STORE, s);
+    gemm<T, false, true>(R, F, d, dh, d, W(TF_W2), d, df, F, nullptr, nullptr, EPI_STORE, s);
     gelu_bwd<T>(y.fpre, df, R * F, s);
     wgrad<T>(m, d, F, R, y.a2, d, df, F, tf_layer(l, TF_W1), s);
     bgrad<T>(m, df, R, F, F, tf_layer(l, TF_B1), s);
-    gemm<T, T, false, true>(R, d, F, df, F, W(TF_W1), F, da, d, nullptr, nullptr, EPI_STORE, s);
+    gemm<T, false, true>(R, d, F, df, F, W(TF_W1), F, da, d, nullptr, nullptr, EPI_STORE, s);
     layernorm_bwd<T>(y.h_mid, y.m2, y.r2, R, d, W(TF_LN2G), da, dh, true, tmp, s);
     bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN2G), s);
     bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN2B), s);
     // h_mid = h_in + attn(a1) Wo + bo
     wgrad<T>(m, d, d, R, y.o, d, dh, d, tf_layer(l, TF_WO), s);
     bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_BO), s);
-    gemm<T, T, false, true>(R, d, d, dh, d, W(TF_WO), d, da, d, nullptr, nullptr, EPI_STORE, s);
+    gemm<T, false, true>(R, d, d, dh, d, W(TF_WO), d, da, d, nullptr, nullptr, EPI_STORE, s);
     attention_bwd<T>(y.qkv, y.probs, da, B, n, d, H, dq, s);
     wgrad<T>(m, d, 3 * d, R, y.a1, d, dq, 3 * d, tf_layer(l, TF_WQKV), s);
     bgrad<T>(m, dq, R, 3 * d, 3 * d, tf_layer(l, TF_BQKV), s);
-    gemm<T, T, false, true>(R, d, 3 * d, dq, 3 * d, W(TF_WQKV), 3 * d, da, d, nullptr, nullptr,
+    gemm<T, false, true>(R, d, 3 * d, dq, 3 * d, W(TF_WQKV), 3 * d, da, d, nullptr, nullptr,
                             EPI_STORE, s);
     layernorm_bwd<T>(y.h_in, y.m1, y.r1, R, d, W(TF_LN1G), da, dh, true, tmp, s);
     bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN1G), s);
     bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN1B), s);
   }
-  hipLaunchKernelGGL(tok_emb_grad_kernel<T>, g1(5 * d), dim3(256), 0, s, x, B, n, d, dh,
-                     m.grad_acc.as<double>() + m.off[TF_TOK]);
+  // embeddings: token table through the one-hot input classes, positions by column sums
+  hipLaunchKernelGGL(in_class_kernel<T>, g1(R * 5), dim3(256), 0, s, x, B, n, tmp);
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(pos_emb_grad_kernel<T>, g1(n * d), dim3(256), 0, s, B, n, d, dh,
-                     m.grad_acc.as<double>() + m.off[TF_POS]);
-  HIP_LAUNCH_OK();
+  wgrad<T>(m, 5, d, R, tmp, 5, dh, d, TF_TOK, s);
+  bgrad<T>(m, dh, B, int64_t(n) * d, int64_t(n) * d, TF_POS, s);
 
   // phase MLP: phi = gelu(gelu(onehot W1 + b1) W2 + b2) w3 + b3
   T *dz2 = dz, *dz1 = dz + B * PH;
@@ -499,13 +457,13 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   gelu_bwd<T>(A.z2pre, dz2, B * PH, s);
   wgrad<T>(m, PH, PH, B, A.z1, PH, dz2, PH, tf_tail(L, TF_PW2), s);
   bgrad<T>(m, dz2, B, PH, PH, tf_tail(L, TF_PB2), s);
-  gemm<T, T, false, true>(B, PH, PH, dz2, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, dz1, PH, nullptr,
+  gemm<T, false, true>(B, PH, PH, dz2, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, dz1, PH, nullptr,
                           nullptr, EPI_STORE, s);
   gelu_bwd<T>(A.z1pre, dz1, B * PH, s);
   bgrad<T>(m, dz1, B, PH, PH, tf_tail(L, TF_PB1), s);
-  hipLaunchKernelGGL(phase_w1_grad_kernel<T>, g1(4 * n * PH), dim3(256), 0, s, x, B, n, PH, dz1,
-                     m.grad_acc.as<double>() + m.off[tf_tail(L, TF_PW1)]);
+  hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * n), dim3(256), 0, s, x, B, n, tmp);
   HIP_LAUNCH_OK();
+  wgrad<T>(m, 4 * n, PH, B, tmp, 4 * n, dz1, PH, tf_tail(L, TF_PW1), s);
 }
 
 // ------------------------------------------------------------------- MLP ---
@@ -524,11 +482,11 @@ void mlp_position(nqs_model &m, const uint64_t *x, int64_t B, int p, T *X, T *h1
   }
   auto W = [&](int k) { return P<T>(m, 6 * p + k); };
   // p == 0: no input, h1 = tanh(b1)
-  gemm<T, T, false, false>(B, hid, 4 * p, X, 4 * p > 0 ? 4 * p : 1, W(MLP_W1), hid, h1, hid,
+  gemm<T, false, false>(B, hid, 4 * p, X, 4 * p > 0 ? 4 * p : 1, W(MLP_W1), hid, h1, hid,
                            W(MLP_B1), nullptr, EPI_TANH, s);
-  gemm<T, T, false, false>(B, hid, hid, h1, hid, W(MLP_W2), hid, h2, hid, W(MLP_B2), pre2,
+  gemm<T, false, false>(B, hid, hid, h1, hid, W(MLP_W2), hid, h2, hid, W(MLP_B2), pre2,
                            EPI_LRELU, s);
-  gemm<T, T, false, false>(B, 8, hid, h2, hid, W(MLP_W3), 8, o, 8, W(MLP_B3), nullptr, EPI_STORE,
+  gemm<T, false, false>(B, 8, hid, h2, hid, W(MLP_W3), 8, o, 8, W(MLP_B3), nullptr, EPI_STORE,
                            s);
 }
 
@@ -603,12 +561,12 @@ void mlp_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double
     auto W = [&](int k) { return P<T>(m, 6 * p + k); };
     wgrad<T>(m, hid, 8, B, h2, hid, dp, 8, 6 * p + MLP_W3, s);
     bgrad<T>(m, dp, B, 8, 8, 6 * p + MLP_B3, s);
-    gemm<T, T, false, true>(B, hid, 8, dp, 8, W(MLP_W3), 8, dh2, hid, nullptr, nullptr, EPI_STORE,
+    gemm<T, false, true>(B, hid, 8, dp, 8, W(MLP_W3), 8, dh2, hid, nullptr, nullptr, EPI_STORE,
                             s);
     lrelu_bwd<T>(pre2, dh2, B * hid, s);
     wgrad<T>(m, hid, hid, B, h1, hid, dh2, hid, 6 * p + MLP_W2, s);
     bgrad<T>(m, dh2, B, hid, hid, 6 * p + MLP_B2, s);
-    gemm<T, T, false, true>(B, hid, hid, dh2, hid, W(MLP_W2), hid, dh1, hid, nullptr, nullptr,
+    gemm<T, false, true>(B, hid, hid, dh2, hid, W(MLP_W2), hid, dh1, hid, nullptr, nullptr,
                             EPI_STORE, s);
     tanh_bwd<T>(h1, dh1, B * hid, s);
     if (p > 0) wgrad<T>(m, 4 * p, hid, B, X, 4 * p, dh1, hid, 6 * p + MLP_W1, s);

@@ -15,13 +15,15 @@ enum Epi : int {
   EPI_ADD = 4,     // C += AB + bias
 };
 
-// C[M,N] = op(A)[M,K] op(B)[K,N]; op(A)(i,k) = TA ? A[k*lda+i] : A[i*lda+k],
-// op(B)(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  With ksplit > 0 the K range is
-// cut into slices of ksplit, slice z writing C + z*slice_stride (EPI_STORE).
-template <class TI, class TO, bool TA, bool TB>
-void gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t lda, const TI *B, int64_t ldb,
-          TO *C, int64_t ldc, const TI *bias, TO *aux, int epi, hipStream_t s,
-          int64_t ksplit = 0, int64_t slice_stride = 0);
+// C[M,N] = op(A)[M,K] op(B)[K,N] (row-major); op(A)(i,k) = TA ? A[k*lda+i] :
+// A[i*lda+k], op(B)(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  A plain library GEMM
+// (rocBLAS) followed by the bias / activation epilogue.
+template <class T, bool TA, bool TB>
+void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb, T *C,
+          int64_t ldc, const T *bias, T *aux, int epi, hipStream_t s);
+// dst[i] += src[i] (into a double accumulator)
+template <class T>
+void add_into(const T *src, int64_t n, double *dst, hipStream_t s);
 
 // Deterministic column sums: acc[j] += sum_r Y[r*ld + j] (double accumulator).
 template <class T>

@@ -4,10 +4,10 @@
 // kernel.
 #include "ops.h"
 
+#include <rocblas/rocblas.h>
+
 namespace nqs {
 namespace {
-
-constexpr int kTile = 64, kTK = 16;
 
 template <class T>
 __device__ inline T gelu_tanh(T x) {
@@ -22,78 +22,55 @@ __device__ inline T gelu_tanh_grad(T x) {
   return T(0.5) * (T(1) + t) + T(0.5) * x * (T(1) - t * t) * c * (T(1) + T(3 * 0.044715) * x * x);
 }
 
-template <class TI, class TO, bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, const TI *A,
-                                                   int64_t lda, const TI *B, int64_t ldb, TO *C,
-                                                   int64_t ldc, const TI *bias, TO *aux, int epi,
-                                                   int64_t ksplit, int64_t slice_stride) {
-  using Acc = TO;
-  __shared__ TI As[kTK][kTile + 1];
-  __shared__ TI Bs[kTK][kTile + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int64_t m0 = int64_t(blockIdx.y) * kTile, n0 = int64_t(blockIdx.x) * kTile;
-  int64_t kb = 0, ke = K;
-  if (ksplit > 0) {
-    kb = int64_t(blockIdx.z) * ksplit;
-    ke = kb + ksplit < K ? kb + ksplit : K;
-    C += int64_t(blockIdx.z) * slice_stride;
+// Epilogue of the library GEMM: bias and activation, in place on C (M x N, ldc).
+template <class T>
+__global__ void epilogue_kernel(T *C, int64_t M, int64_t N, int64_t ldc, const T *bias, T *aux,
+                                int epi) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx / N, j = idx % N;
+  T *c = C + i * ldc + j;
+  const T v = *c + (bias ? bias[j] : T(0));
+  switch (epi) {
+    case EPI_GELU: aux[i * ldc + j] = v; *c = gelu_tanh(v); break;
+    case EPI_TANH: *c = tanh(v); break;
+    case EPI_LRELU: aux[i * ldc + j] = v; *c = v >= T(0) ? v : T(0.01) * v; break;
+    default: *c = v;
   }
-  Acc acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = Acc(0);
-  for (int64_t k0 = kb; k0 < ke; k0 += kTK) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      int r, kk;
-      if (TA) { kk = idx / kTile; r = idx % kTile; } else { r = idx / kTK; kk = idx % kTK; }
-      const int64_t gi = m0 + r, gk = k0 + kk;
-      TI v = TI(0);
-      if (gi < M && gk < ke) v = TA ? A[gk * lda + gi] : A[gi * lda + gk];
-      As[kk][r] = v;
-      int c;
-      if (TB) { c = idx / kTK; kk = idx % kTK; } else { kk = idx / kTile; c = idx % kTile; }
-      const int64_t gj = n0 + c, gk2 = k0 + kk;
-      TI w = TI(0);
-      if (gj < N && gk2 < ke) w = TB ? B[gj * ldb + gk2] : B[gk2 * ldb + gj];
-      Bs[kk][c] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kTK; ++kk) {
-      Acc a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Acc(As[kk][ty + 16 * i]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Acc(Bs[kk][tx + 16 * j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t gi = m0 + ty + 16 * i;
-    if (gi >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t gj = n0 + tx + 16 * j;
-      if (gj >= N) continue;
-      Acc v = acc[i][j] + (bias ? Acc(bias[gj]) : Acc(0));
-      TO *dst = C + gi * ldc + gj;
-      switch (epi) {
-        case EPI_GELU: aux[gi * ldc + gj] = TO(v); *dst = TO(gelu_tanh(v)); break;
-        case EPI_TANH: *dst = TO(tanh(v)); break;
-        case EPI_LRELU: aux[gi * ldc + gj] = TO(v); *dst = TO(v >= Acc(0) ? v : Acc(0.01) * v); break;
-        case EPI_ADD: *dst = TO(*dst + v); break;
-        default: *dst = TO(v);
-      }
-    }
-  }
+}
+
+template <class T>
+__global__ void add_into_kernel(const T *src, int64_t n, double *dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += double(src[i]);
+}
+
+#define BLAS_OK(expr)                                                                   \
+  do {                                                                                  \
+    rocblas_status st_ = (expr);                                                        \
+    if (st_ != rocblas_status_success)                                                  \
+      throw Error(NQS_EHIP, std::string(#expr " failed: ") + rocblas_status_to_string(st_)); \
+  } while (0)
+
+rocblas_handle blas(hipStream_t s) {
+  static rocblas_handle handles[64] = {};
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  NQS_REQUIRE(dev >= 0 && dev < 64, NQS_EHIP, "device index out of range");
+  if (!handles[dev]) BLAS_OK(rocblas_create_handle(&handles[dev]));
+  BLAS_OK(rocblas_set_stream(handles[dev], s));
+  return handles[dev];
+}
+
+void blas_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+               float alpha, const float *A, int lda, const float *B, int ldb, float beta,
+               float *C, int ldc) {
+  BLAS_OK(rocblas_sgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc));
+}
+void blas_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+               double alpha, const double *A, int lda, const double *B, int ldb, double beta,
+               double *C, int ldc) {
+  BLAS_OK(rocblas_dgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc));
 }
 
 // partial[y][j] = sum over rows of slice y of Y[r, j]; 64 columns x 4 row lanes per block
@@ -297,15 +274,27 @@ inline dim3 grid1(int64_t n, int b = 256) { return dim3(unsigned(ceil_div(n, b))
 
 }  // namespace
 
-template <class TI, class TO, bool TA, bool TB>
-void gemm(int64_t M, int64_t N, int64_t K, const TI *A, int64_t lda, const TI *B, int64_t ldb,
-          TO *C, int64_t ldc, const TI *bias, TO *aux, int epi, hipStream_t s, int64_t ksplit,
-          int64_t slice_stride) {
+template <class T, bool TA, bool TB>
+void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb, T *C,
+          int64_t ldc, const T *bias, T *aux, int epi, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  const unsigned z = ksplit > 0 ? unsigned(ceil_div(K, ksplit)) : 1u;
-  dim3 grid(unsigned(ceil_div(N, kTile)), unsigned(ceil_div(M, kTile)), z);
-  hipLaunchKernelGGL((gemm_kernel<TI, TO, TA, TB>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                     C, ldc, bias, aux, epi, ksplit, slice_stride);
+  NQS_REQUIRE(M < (int64_t(1) << 31) && N < (int64_t(1) << 31) && K < (int64_t(1) << 31),
+              NQS_EUNSUPPORTED, "gemm: dimension too large");
+  // row-major C = op(A) op(B) is column-major C^T = op(B)^T op(A)^T
+  blas_gemm(blas(s), TB ? rocblas_operation_transpose : rocblas_operation_none,
+            TA ? rocblas_operation_transpose : rocblas_operation_none, int(N), int(M), int(K),
+            T(1), B, int(ldb), A, int(lda), epi == EPI_ADD ? T(1) : T(0), C, int(ldc));
+  if (bias || (epi != EPI_STORE && epi != EPI_ADD)) {
+    hipLaunchKernelGGL(epilogue_kernel<T>, grid1(M * N), dim3(256), 0, s, C, M, N, ldc, bias, aux,
+                       epi);
+    HIP_LAUNCH_OK();
+  }
+}
+
+template <class T>
+void add_into(const T *src, int64_t n, double *dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(add_into_kernel<T>, grid1(n), dim3(256), 0, s, src, n, dst);
   HIP_LAUNCH_OK();
 }
 
@@ -408,15 +397,13 @@ void zero_async(void *p, size_t bytes, hipStream_t s) {
   template void gelu_bwd<T>(const T *, T *, int64_t, hipStream_t);                              \
   template void tanh_bwd<T>(const T *, T *, int64_t, hipStream_t);                              \
   template void lrelu_bwd<T>(const T *, T *, int64_t, hipStream_t);                             \
-  template void gemm<T, T, false, false>(int64_t, int64_t, int64_t, const T *, int64_t,         \
-                                         const T *, int64_t, T *, int64_t, const T *, T *, int, \
-                                         hipStream_t, int64_t, int64_t);                         \
-  template void gemm<T, T, false, true>(int64_t, int64_t, int64_t, const T *, int64_t,          \
-                                        const T *, int64_t, T *, int64_t, const T *, T *, int,  \
-                                        hipStream_t, int64_t, int64_t);                          \
-  template void gemm<T, double, true, false>(int64_t, int64_t, int64_t, const T *, int64_t,     \
-                                             const T *, int64_t, double *, int64_t, const T *,  \
-                                             double *, int, hipStream_t, int64_t, int64_t);
+  template void gemm<T, false, false>(int64_t, int64_t, int64_t, const T *, int64_t, const T *, \
+                                      int64_t, T *, int64_t, const T *, T *, int, hipStream_t);  \
+  template void gemm<T, false, true>(int64_t, int64_t, int64_t, const T *, int64_t, const T *,  \
+                                     int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
+  template void gemm<T, true, false>(int64_t, int64_t, int64_t, const T *, int64_t, const T *,  \
+                                     int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
+  template void add_into<T>(const T *, int64_t, double *, hipStream_t);
 
 INST_T(float)
 INST_T(double)

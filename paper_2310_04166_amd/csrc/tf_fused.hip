@@ -67,6 +67,7 @@ struct FusedArgs {
   const uint64_t *x;
   int64_t B;
   int n, L, mask_levels, cond_p;
+  int pairs;                        // passes per wave (configurations per wave / 2), <= 16
   double *logabs, *phase, *cond;
 };
 
@@ -253,7 +254,7 @@ fused_kernel(FusedArgs a) {
   constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
   const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
   const int64_t group = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
-  const int64_t c_base = group * 32;
+  const int64_t c_base = group * 2 * a.pairs;
   if (c_base >= a.B) return;
   const int t = r % kSeq;            // position of this lane's row
   const bool upper = r >= kSeq;      // second configuration of the pair
@@ -274,7 +275,7 @@ fused_kernel(FusedArgs a) {
   bf16x8 fr[2][KS];
   load_step<D>(fr[0], wview(0), 0);
 
-  for (int pair = 0; pair < kPairs; ++pair) {
+  for (int pair = 0; pair < a.pairs; ++pair) {
     const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
     if (c_base + 2 * pair >= a.B) break;
     const bool live = cfg < a.B;
@@ -461,7 +462,7 @@ fused_kernel(FusedArgs a) {
   if (a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
     const int64_t cfg = c_base + r;
-    const bool live = cfg < a.B;
+    const bool live = r < 2 * a.pairs && cfg < a.B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
     bf16x8 Z[PKS];
 #pragma unroll
@@ -688,7 +689,11 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   a.logabs = logabs;
   a.phase = phase;
   a.cond = cond_out;
-  const int64_t groups = ceil_div(B, 32);
+  // up to 16 passes (32 configurations) per wave; fewer when the batch is too
+  // small to give every SIMD of the chip two waves
+  const int64_t target_waves = 2048;
+  a.pairs = int(std::min<int64_t>(kPairs, std::max<int64_t>(1, ceil_div(B, 2 * target_waves))));
+  const int64_t groups = ceil_div(B, 2 * a.pairs);
   const dim3 grid(unsigned(ceil_div(groups, 4)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_timing) {
