@@ -365,8 +365,16 @@ void wgrad(nqs_model &m, int64_t Mi, int64_t No, int64_t R, const T *X, int64_t 
 
 template <class T>
 void bgrad(nqs_model &m, const T *dY, int64_t R, int64_t N, int64_t ld, int pidx, hipStream_t s) {
-  double *scratch = static_cast<double *>(m.ws2.reserve(size_t(64 * N) * 8 + 256));
-  colsum_acc<T>(dY, R, N, ld, m.grad_acc.as<double>() + m.off[pidx], scratch, s);
+  // column sums as a GEMM with a vector of ones: dY^T 1
+  if (m.ones_rows < R || m.ones_bytes != sizeof(T)) {
+    T *o = static_cast<T *>(m.ones.reserve(size_t(R) * sizeof(T)));
+    fill_ones<T>(o, R, s);
+    m.ones_rows = R;
+    m.ones_bytes = sizeof(T);
+  }
+  T *part = static_cast<T *>(m.part.reserve(size_t(N) * sizeof(T)));
+  gemm<T, true, false>(N, 1, R, dY, ld, m.ones.as<T>(), 1, part, 1, nullptr, nullptr, EPI_STORE, s);
+  add_into<T>(part, N, m.grad_acc.as<double>() + m.off[pidx], s);
 }
 
 template <class T>

@@ -24,6 +24,8 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
 // dst[i] += src[i] (into a double accumulator)
 template <class T>
 void add_into(const T *src, int64_t n, double *dst, hipStream_t s);
+template <class T>
+void fill_ones(T *dst, int64_t n, hipStream_t s);
 
 // Deterministic column sums: acc[j] += sum_r Y[r*ld + j] (double accumulator).
 template <class T>

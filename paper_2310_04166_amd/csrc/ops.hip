@@ -45,6 +45,12 @@ __global__ void add_into_kernel(const T *src, int64_t n, double *dst) {
   if (i < n) dst[i] += double(src[i]);
 }
 
+template <class T>
+__global__ void fill_kernel(T *dst, int64_t n, T v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
 #define BLAS_OK(expr)                                                                   \
   do {                                                                                  \
     rocblas_status st_ = (expr);                                                        \
@@ -299,6 +305,13 @@ void add_into(const T *src, int64_t n, double *dst, hipStream_t s) {
 }
 
 template <class T>
+void fill_ones(T *dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<T>, grid1(n), dim3(256), 0, s, dst, n, T(1));
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
 void colsum_acc(const T *Y, int64_t R, int64_t N, int64_t ld, double *acc, double *scratch,
                 hipStream_t s) {
   if (R <= 0 || N <= 0) return;
@@ -403,7 +416,8 @@ void zero_async(void *p, size_t bytes, hipStream_t s) {
                                      int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
   template void gemm<T, true, false>(int64_t, int64_t, int64_t, const T *, int64_t, const T *,  \
                                      int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
-  template void add_into<T>(const T *, int64_t, double *, hipStream_t);
+  template void add_into<T>(const T *, int64_t, double *, hipStream_t);                         \
+  template void fill_ones<T>(T *, int64_t, hipStream_t);
 
 INST_T(float)
 INST_T(double)

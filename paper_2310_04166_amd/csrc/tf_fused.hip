@@ -211,9 +211,10 @@ __device__ inline f32x16 vec16_at(const View &v, uint32_t byte_off) {
   return r;
 }
 
-// W = the layer's fragments (voff = 16 * lane); s = step index
+// W = the layer's fragments (voff = 16 * lane); s = step index; fragments
+// half * KS/2 .. half * KS/2 + KS/2 - 1 of the step go to f[0 .. KS/2)
 template <int D>
-__device__ inline void load_step(bf16x8 (&f)[Shape<D>::KS], const View &W, int s) {
+__device__ inline void load_half(bf16x8 (&f)[Shape<D>::KS / 2], const View &W, int s, int half) {
   using S = Shape<D>;
   constexpr int KS = S::KS;
   int64_t base;
@@ -237,18 +238,19 @@ __device__ inline void load_step(bf16x8 (&f)[Shape<D>::KS], const View &W, int s
     }
   }
 #pragma unroll
-  for (int i = 0; i < KS; ++i) {
+  for (int ii = 0; ii < KS / 2; ++ii) {
     // kind 0: KS consecutive k-steps of one output block; kind 1 (output
     // projection) / 2 (second FFN layer): output block i/2, k-step 2b + i%2
+    const int i = half * (KS / 2) + ii;
     const int64_t o = kind == 0 ? int64_t(i) * 64
                     : kind == 1 ? (int64_t(i / 2) * KS + (i % 2)) * 64
                                 : (int64_t(i / 2) * S::FKS + (i % 2)) * 64;
-    f[i] = frag_at(W, uint32_t((base + o) * 16));
+    f[ii] = frag_at(W, uint32_t((base + o) * 16));
   }
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 fused_kernel(FusedArgs a) {
   using S = Shape<D>;
   constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
@@ -272,8 +274,9 @@ fused_kernel(FusedArgs a) {
   auto wview = [&](int l) {
     return make_view(a.pk + int64_t(l) * S::FRAG_L, kFragBytes, uint32_t(lane) * 16u);
   };
-  bf16x8 fr[2][KS];
-  load_step<D>(fr[0], wview(0), 0);
+  constexpr int HS = KS / 2;
+  bf16x8 fr[2][HS];
+  load_half<D>(fr[0], wview(0), 0, 0);
 
   for (int pair = 0; pair < a.pairs; ++pair) {
     const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
@@ -300,29 +303,41 @@ fused_kernel(FusedArgs a) {
       const View V16 = make_view(vec + int64_t(l) * S::VEC_L, kVecBytes, uint32_t(h) * 64u);
       const float *lv = vec + int64_t(l) * S::VEC_L;
       bf16x8 X[KS];
+      // The weight stream advances in half steps of HS fragments through the
+      // two buffers fr[0] / fr[1]: while one half is multiplied the next half
+      // is loaded.  On entry fr[0] holds half 0 of step 0 of this layer.
       // ---- attention block
       layer_norm<NB>(res, V16, uint32_t(S::VLN1G * 4), uint32_t(S::VLN1B * 4), X);
 #pragma unroll
       for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VBO + q * 32) * 4));
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        // step 4b: Q (fr[0]); 4b+1: K (fr[1]); 4b+2: V (fr[0]); 4b+3: O (fr[1])
-        load_step<D>(fr[1], W, 4 * b + 1);
+        // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O); halves alternate fr[0], fr[1]
         f32x16 Qc = vec16_at(V16, uint32_t((S::VBQ + b * 32) * 4));
+        load_half<D>(fr[1], W, 4 * b, 1);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) Qc = mfma(fr[0][s], X[s], Qc);
-        load_step<D>(fr[0], W, 4 * b + 2);
+        for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
+        load_half<D>(fr[0], W, 4 * b + 1, 0);
+#pragma unroll
+        for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
         f32x16 Kc = vec16_at(V16, uint32_t((S::VBK + b * 32) * 4));
+        load_half<D>(fr[1], W, 4 * b + 1, 1);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) Kc = mfma(fr[1][s], X[s], Kc);
-        load_step<D>(fr[1], W, 4 * b + 3);
+        for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
+        load_half<D>(fr[0], W, 4 * b + 2, 0);
+#pragma unroll
+        for (int i = 0; i < HS; ++i) Kc = mfma(fr[1][i], X[HS + i], Kc);
         f32x16 Vc;
         const float bvv = lv[S::VBV + 32 * b + r];
 #pragma unroll
         for (int j = 0; j < 16; ++j) Vc[j] = bvv;
+        load_half<D>(fr[1], W, 4 * b + 2, 1);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) Vc = mfma(X[s], fr[0][s], Vc);
-        load_step<D>(fr[0], W, 4 * b + 4);   // next Q, or the first FFN step
+        for (int i = 0; i < HS; ++i) Vc = mfma(X[i], fr[0][i], Vc);
+        load_half<D>(fr[0], W, 4 * b + 3, 0);
+#pragma unroll
+        for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
+        load_half<D>(fr[1], W, 4 * b + 3, 1);
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
         f32x16 O;
 #pragma unroll
@@ -361,35 +376,42 @@ fused_kernel(FusedArgs a) {
           for (int j = 0; j < 8; ++j) O[e * 8 + j] = Oe[e * 8 + j];
         }
         const bf16x8 O0 = to_bf16(O, 0), O1 = to_bf16(O, 1);
+        // output projection: fragment i = 2q + e (q = output block)
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          res[q] = mfma(fr[1][2 * q], O0, res[q]);
-          res[q] = mfma(fr[1][2 * q + 1], O1, res[q]);
-        }
+        for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]);
+        load_half<D>(fr[0], W, 4 * b + 4, 0);   // next Q, or the first FFN step
+#pragma unroll
+        for (int i = 0; i < HS; ++i)
+          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]);
       }
-      // ---- feed-forward block: step 4NB + 2fb = W1 (fr[0]), +1 = W2 (fr[1])
+      // ---- feed-forward block: step 4NB + 2fb = W1, +1 = W2
       layer_norm<NB>(res, V16, uint32_t(S::VLN2G * 4), uint32_t(S::VLN2B * 4), X);
 #pragma unroll
       for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VB2 + q * 32) * 4));
 #pragma unroll
       for (int fb = 0; fb < FB; ++fb) {
         const int s = 4 * NB + 2 * fb;
-        load_step<D>(fr[1], W, s + 1);
         f32x16 Hc = vec16_at(V16, uint32_t((S::VB1 + fb * 32) * 4));
+        load_half<D>(fr[1], W, s, 1);
 #pragma unroll
-        for (int k = 0; k < KS; ++k) Hc = mfma(fr[0][k], X[k], Hc);
-        if (s + 2 < STEPS)
-          load_step<D>(fr[0], W, s + 2);
-        else
-          load_step<D>(fr[0], Wn, 0);
+        for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
+        load_half<D>(fr[0], W, s + 1, 0);
+#pragma unroll
+        for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
+        load_half<D>(fr[1], W, s + 1, 1);
 #pragma unroll
         for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
         const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
+        // second FFN layer: fragment i = 2q + e
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          res[q] = mfma(fr[1][2 * q], H0, res[q]);
-          res[q] = mfma(fr[1][2 * q + 1], H1, res[q]);
-        }
+        for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
+        if (s + 2 < STEPS)
+          load_half<D>(fr[0], W, s + 2, 0);
+        else
+          load_half<D>(fr[0], Wn, 0, 0);
+#pragma unroll
+        for (int i = 0; i < HS; ++i)
+          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? H1 : H0, res[(HS + i) / 2]);
       }
     }
 

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnqs.so")
+LIB_PATH = os.environ.get("NQS_LIB", os.path.join(_HERE, "libnqs.so"))
 
 MODEL_MLP, MODEL_TRANSFORMER = 1, 2
 FP64, FP32, BF16 = 1, 2, 3
