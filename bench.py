@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--fp32-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy a MIB-MiB buffer once (a plain copy kernel of "
+                         "known size, to scale HBM byte counters)")
     ap.add_argument("--lr", type=float, default=1e-5,
                     help="Adam step size; small so every timed step sees the calibrated workload")
     args = ap.parse_args()
@@ -146,6 +149,13 @@ def main():
         out = vmc_step(nqs, ham, model, cfg, 1000 + w, state, t)
         t += 1
         log(f"warmup {w}: unique={out[0].numel()} pairs={out[4]}")
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del src, dst
     torch.cuda.synchronize()
     nqs.timing_enable(True)
     nqs.timing_read()
