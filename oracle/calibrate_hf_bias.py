@@ -6,13 +6,18 @@ values were picked from this output (target: about 3e3 unique samples at 20
 spin-orbitals / 1e5 samples, about 2e4 at 30 spin-orbitals / 1e6 samples).
 
     python -m oracle.calibrate_hf_bias fp32 2.5 3.0 3.5
+    python -m oracle.calibrate_hf_bias batching 1.5 2.0 2.5
+
+For ``batching`` the value is the shared model's per-electron bias and the
+output lists the unique counts of the first eight molecules.
 """
 import sys
 import time
 
-from oracle.model import build_model
+from oracle.model import TransformerModel, build_model
 from oracle.sampler import sample_tree
-from synth import make_transformer_params, workload
+from oracle.sector import Sector
+from synth import BATCHING_MODEL, batching_molecules, make_transformer_params, workload
 
 
 def unique_count(name, bias, seed=0):
@@ -25,8 +30,24 @@ def unique_count(name, bias, seed=0):
     return len(configs)
 
 
+def batching_unique_counts(bias, count=8, seed=0):
+    c = BATCHING_MODEL
+    params = make_transformer_params(c["n"], 0, 0, c["d"], c["n_layers"], ffn=c["ffn"],
+                                     phase_hidden=c["phase_hidden"], seed=c["seed"],
+                                     occ_bias=bias, round_to=c["round_to"])
+    out = []
+    for i, m in enumerate(batching_molecules()[:count]):
+        model = TransformerModel(params, Sector(m["n"], m["n_alpha"], m["n_beta"]), c["n_heads"])
+        configs, _, _ = sample_tree(model, m["n_samples"], seed, stream=i)
+        out.append(len(configs))
+    return out
+
+
 if __name__ == "__main__":
     name = sys.argv[1]
     for b in sys.argv[2:]:
+        if name == "batching":
+            print(name, b, batching_unique_counts(float(b)), flush=True)
+            continue
         t = time.time()
         print(name, b, unique_count(name, float(b)), f"{time.time() - t:.1f}s", flush=True)

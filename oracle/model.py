@@ -16,6 +16,10 @@ them all):
 * The phase is carried separately from the masked modulus: the MLP gives one
   phase per (position, token) and phi = sum_p phi_p[x_p]; the transformer
   has a phase MLP over the one-hot code of the whole configuration.
+* One transformer may serve molecules of different sizes (its position
+  tables cover the largest): a molecule of n tokens reads rows 0..n-1 of the
+  position embedding and of the per-position logit bias, and its phase-MLP
+  input is its one-hot code followed by zeros for the absent positions.
 * MLP activations: tanh, then leaky ReLU with slope 0.01 for x < 0 (the
   printed "-0.01 x" is read as the usual leaky ReLU).
 """
@@ -154,11 +158,14 @@ class TransformerModel(AmplitudeModel):
             a = layer_norm(h, t[f"l{l}.ln2_g"], t[f"l{l}.ln2_b"])
             h = h + gelu_tanh(a @ t[f"l{l}.w1"] + t[f"l{l}.b1"]) @ t[f"l{l}.w2"] + t[f"l{l}.b2"]
         hf = layer_norm(h, t["lnf_g"], t["lnf_b"])
-        return hf @ t["whead"] + t["bhead"] + t["logit_bias"][None]
+        return hf @ t["whead"] + t["bhead"] + t["logit_bias"][None, :n]
 
     def phase(self, toks):
         t, B, n = self.t, toks.shape[0], self.n
         oh = F.one_hot(toks, 4).to(torch.float64).reshape(B, 4 * n)
+        rows = t["ph_w1"].shape[0]
+        if rows > 4 * n:     # model shared with larger molecules: absent positions are zero
+            oh = torch.cat([oh, torch.zeros((B, rows - 4 * n), dtype=torch.float64)], 1)
         z = gelu_tanh(oh @ t["ph_w1"] + t["ph_b1"])
         z = gelu_tanh(z @ t["ph_w2"] + t["ph_b2"])
         return (z @ t["ph_w3"] + t["ph_b3"])[:, 0]

@@ -21,6 +21,9 @@ the 64-bit seed, counter (prefix low 32 bits, prefix high 32 bits,
 p + 64 j, block) where j is which of the three conditional binomials of the
 node is drawn and block counts Philox calls.  Each call yields two uniforms.
 Results therefore depend only on (seed, node), not on processing order.
+When several trees are drawn with one seed (one per molecule of a batch),
+tree number ``stream`` puts ``stream << 58`` into the prefix field of the
+counter, so the trees use disjoint counters.
 
 Binomial draws (all float64, no fused multiply-add):
 
@@ -171,10 +174,11 @@ def child_weights(logits, allowed):
     return [math.exp(logits[k] - m) if allowed[k] else 0.0 for k in range(4)]
 
 
-def sample_tree(model, n_samples, seed, strategy="MU", d=0):
+def sample_tree(model, n_samples, seed, strategy="MU", d=0, stream=0):
     """Returns ``(configs, counts, lost)``: unique configurations (ints) in tree
     order (lexicographic in the token sequence), their counts, and the number
     of samples lost to unphysical children (0 under MU)."""
+    tag = stream << 58
     n, sec = model.n, model.sector
     mask_levels = {"MU": n, "DU": 0, "MUd": n - d}[strategy]
     frontier = [(0, n_samples, 0, 0)]     # (prefix bits, count, alpha, beta)
@@ -191,7 +195,7 @@ def sample_tree(model, n_samples, seed, strategy="MU", d=0):
             phys = sec.child_mask(p, a, b)
             allowed = phys if p < mask_levels else [True] * 4
             w = child_weights([float(v) for v in lg[i]], allowed)
-            split = split_counts(cnt, w, seed, x, p)
+            split = split_counts(cnt, w, seed, tag | x, p)
             for k in range(4):
                 if split[k] == 0:
                     continue

@@ -9,10 +9,12 @@ the HIP path can both read the same inputs without sharing any computation.
 from .integrals import make_integrals
 from .params import (mlp_param_spec, transformer_param_spec, make_mlp_params,
                      make_transformer_params, flatten_params, unflatten_params)
-from .workloads import WORKLOADS, workload, batching_molecules
+from .workloads import (WORKLOADS, BATCHING_MODEL, workload, batching_molecules,
+                        batching_params, batching_workload)
 
 __all__ = [
     "make_integrals", "mlp_param_spec", "transformer_param_spec",
     "make_mlp_params", "make_transformer_params", "flatten_params",
-    "unflatten_params", "WORKLOADS", "workload", "batching_molecules",
+    "unflatten_params", "WORKLOADS", "BATCHING_MODEL", "workload", "batching_molecules",
+    "batching_params", "batching_workload",
 ]

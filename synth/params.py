@@ -79,12 +79,18 @@ def make_mlp_params(n, hidden=64, seed=0, std=0.02, round_to=None, bias_std=0.0)
 
 def make_transformer_params(n, n_alpha, n_beta, d, n_layers, ffn=None,
                             phase_hidden=256, seed=0, std=0.02, hf_bias=0.0,
-                            round_to=None, bias_std=0.0):
+                            round_to=None, bias_std=0.0, occ_bias=0.0):
+    """``hf_bias`` favours each position's Hartree-Fock token of the sector
+    (n_alpha, n_beta).  ``occ_bias`` instead adds ``occ_bias`` per electron of
+    the token (0, 1, 1, 2 for tokens 0..3) at every position, which favours
+    the Hartree-Fock state of *any* sector under the symmetry mask; it is the
+    knob of a model shared by molecules of different electron counts."""
     ffn = 4 * d if ffn is None else ffn
     bias = np.zeros((n, 4))
     for p in range(n):
         hf_tok = int(p < n_alpha) + 2 * int(p < n_beta)
         bias[p, hf_tok] = hf_bias
+        bias[p] += occ_bias * np.array([0.0, 1.0, 1.0, 2.0])
     spec = transformer_param_spec(n, d, n_layers, ffn, phase_hidden)
     return _init(spec, seed, std, round_to, {"logit_bias": bias}, bias_std)
 

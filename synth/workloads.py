@@ -11,7 +11,9 @@
 sets how peaked the initial Born distribution is and therefore how many unique
 samples a batch of ``n_samples`` produces; its values were chosen with the CPU
 oracle's sampler (``oracle/calibrate_hf_bias.py``) to give about 3e3 unique
-samples at ``fp32`` and about 2e4 at ``precision``.
+samples at ``fp32`` and about 2e4 at ``precision``.  The batching workload's
+shared model uses the per-electron ``occ_bias`` instead (same script), chosen
+so that the molecules' unique counts spread over roughly 1e2 .. 3e3.
 """
 import numpy as np
 
@@ -45,6 +47,28 @@ def workload(name):
             cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg["d"], cfg["n_layers"],
             seed=cfg["seed"], hf_bias=cfg["hf_bias"], round_to=cfg.get("round_to"))
     return cfg, h, eri, params
+
+
+BATCHING_MODEL = dict(n=14, d=64, n_layers=2, n_heads=4, ffn=256, phase_hidden=256,
+                      seed=4, occ_bias=2.0, round_to="bf16")
+
+
+def batching_params():
+    """Shared transformer of the batching workload: 14 positions (the largest
+    molecule), d_model 64, 2 layers, 4 heads, electron-count logit bias."""
+    c = BATCHING_MODEL
+    return make_transformer_params(c["n"], 0, 0, c["d"], c["n_layers"], ffn=c["ffn"],
+                                   phase_hidden=c["phase_hidden"], seed=c["seed"],
+                                   occ_bias=c["occ_bias"], round_to=c["round_to"])
+
+
+def batching_workload(count=64, base_seed=1000):
+    """``(molecules, params)``: each molecule dict also carries its integrals
+    ``h``, ``eri``; ``params`` is the shared model."""
+    mols = batching_molecules(count, base_seed)
+    for m in mols:
+        m["h"], m["eri"] = make_integrals(m["n"], m["rank"], m["seed"])
+    return mols, batching_params()
 
 
 def batching_molecules(count=64, base_seed=1000):

@@ -156,3 +156,46 @@ def test_du_levels_unmasked():
     with torch.no_grad():
         full = torch.exp(2 * m.log_abs(toks)).sum().item()
     assert abs(full - 1.0) < 1e-12
+
+
+# ------------------------------------------------ model shared by molecules
+
+def shared_params(n_max=14, d=16, L=2, occ_bias=0.0, seed=3):
+    return make_transformer_params(n_max, 0, 0, d, L, phase_hidden=32, seed=seed, std=0.3,
+                                   occ_bias=occ_bias, bias_std=0.1)
+
+
+@pytest.mark.parametrize("n,na,nb", [(6, 3, 4), (10, 4, 5), (14, 7, 7)])
+def test_shared_model_equals_truncated_tables(n, na, nb):
+    """A molecule of n tokens on a model with 14 positions equals a model whose
+    position tables are cut to n rows (the absent positions contribute nothing)."""
+    full = shared_params()
+    cut = dict(full)
+    cut["pos_emb"] = full["pos_emb"][:n]
+    cut["logit_bias"] = full["logit_bias"][:n]
+    cut["ph_w1"] = full["ph_w1"][:4 * n]
+    sec = Sector(n, na, nb)
+    rng = np.random.default_rng(n)
+    xs = [sec.enumerate()[i] for i in rng.choice(len(sec.enumerate()), 50)] if n < 14 else \
+        [sec.x_hf]
+    a = TransformerModel(full, sec, 4).amplitudes(xs)
+    b = TransformerModel(cut, sec, 4).amplitudes(xs)
+    for u, v in zip(a, b):
+        assert torch.max(torch.abs(u - v)).item() < 1e-13
+
+
+def test_shared_model_normalised():
+    m = TransformerModel(shared_params(), Sector(6, 3, 4), 4)
+    p = exact_probabilities(m, m.sector.enumerate())
+    assert abs(p.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("n,na,nb", [(6, 2, 3), (6, 3, 3), (8, 4, 3), (8, 5, 5)])
+def test_occupation_bias_peaks_hf_of_any_sector(n, na, nb):
+    """Under the symmetry mask a per-electron logit bias favours the
+    Hartree-Fock state of whatever sector the molecule has."""
+    p = make_transformer_params(14, 0, 0, 16, 2, phase_hidden=32, seed=5, std=0.02,
+                                occ_bias=4.0)
+    m = TransformerModel(p, Sector(n, na, nb), 4)
+    basis = m.sector.enumerate()
+    assert basis[int(np.argmax(exact_probabilities(m, basis)))] == m.sector.x_hf

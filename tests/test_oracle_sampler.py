@@ -133,3 +133,21 @@ def test_tree_sampler_mud_distribution():
     assert lost + sum(cnt) == 20_000
     pv = _chi2_pvalue(cfg, cnt, basis, probs / probs.sum(), sum(cnt))
     assert pv > 1e-4
+
+
+def test_tree_sampler_streams():
+    """Stream 0 is the single-tree sampler; another stream draws a different,
+    equally valid sample (every config in the sector, counts summing to N_s)."""
+    from oracle.model import TransformerModel
+    from oracle.sector import Sector
+    from synth import make_transformer_params
+    sec = Sector(6, 3, 2)
+    params = make_transformer_params(14, 0, 0, 16, 2, phase_hidden=32, seed=2, std=0.3)
+    m = TransformerModel(params, sec, 4)
+    a = sample_tree(m, 5000, 17)
+    b = sample_tree(m, 5000, 17, stream=0)
+    c = sample_tree(m, 5000, 17, stream=3)
+    assert a == b
+    assert a[0] != c[0] or a[1] != c[1]
+    assert sum(c[1]) == 5000 and c[2] == 0
+    assert all(sec.contains(x) for x in c[0])
