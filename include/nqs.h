@@ -38,6 +38,7 @@ extern "C" {
 
 typedef struct nqs_ham nqs_ham;
 typedef struct nqs_model nqs_model;
+typedef struct nqs_batch nqs_batch;
 typedef void *nqs_stream;     /* a hipStream_t */
 
 /* Message of the calling thread's last failure ("" if none). */
@@ -154,6 +155,22 @@ int amp_model_set_params(nqs_model *m, const double *host_in);
 void amp_model_destroy(nqs_model *m);
 
 /*
+ * amp_model_set_sectors - let one transformer serve n_mol (1..64) molecules
+ * of different sizes (the batching form of the path; the paper's masks per
+ * molecule, Algorithm 1 per sector).  Molecule i has n[i] <= dims[0] orbital
+ * tokens and (n_alpha[i], n_beta[i]) electrons (host arrays).  Afterwards every
+ * configuration word given to the model carries its molecule index in bits
+ * 58..63 (occupation bits below; so dims[0] <= 29): the molecule reads rows
+ * 0..n[i]-1 of pos_emb and logit_bias, its phase-MLP input is its one-hot code
+ * followed by zeros, and its conditionals are masked by its own sector.
+ * n_mol = 0 returns the model to its own single sector (untagged words).
+ * Errors: NQS_EINVAL (counts out of range), NQS_EUNSUPPORTED (MLP model,
+ * dims[0] > 29).
+ */
+int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n, const int32_t *n_alpha,
+                          const int32_t *n_beta);
+
+/*
  * amp_forward - log|psi(x)| and phase phi(x) for n configurations.
  * x (dev, n uint64), logabs / phase (dev, n doubles each, written).  A
  * configuration outside the sector gets logabs = -inf.  n = 0 is a no-op.
@@ -196,6 +213,23 @@ int amp_backward(nqs_model *m, const uint64_t *x, int64_t n, const double *g_log
 int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, uint64_t *configs,
                   uint64_t *counts, int64_t capacity, int64_t *n_unique, uint64_t *lost,
                   nqs_stream stream);
+
+/*
+ * sample_unique_batch - sample_unique for every molecule of a model with
+ * sectors (amp_model_set_sectors): one tree per molecule, all expanded level
+ * by level together; tree i starts from n_samples[i] (host array) samples and
+ * keys Philox with i in bits 58..63 of the prefix word, so the trees draw
+ * disjoint random streams.  A molecule with fewer tokens than the deepest
+ * level keeps its leaves unchanged there.  Outputs (dev) configs / counts as in
+ * sample_unique, tagged with the molecule and grouped by molecule in ascending
+ * order; offsets (host, n_mol + 1) receives the first sample of each molecule
+ * and the total.  Errors as sample_unique; NQS_EINVAL if the model has no
+ * sectors or n_mol differs from them.
+ */
+int sample_unique_batch(nqs_model *m, int n_mol, const uint64_t *n_samples, uint64_t seed,
+                        uint64_t *configs, uint64_t *counts, int64_t capacity,
+                        int64_t *n_unique, int64_t *offsets, uint64_t *lost,
+                        nqs_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* Local energy and the counts-weighted reducer                              */
@@ -257,6 +291,79 @@ int vmc_weights(const double *eloc, const uint64_t *counts, int64_t n, const dou
 int adam_update(void *params, const void *grad, void *m, void *v, int64_t n,
                 int elem_bytes, double lr, double b1, double b2, double eps,
                 int64_t t, nqs_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Many molecules in one pass                                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * batch_create - the local energy of n_mol (1..64) molecules that share one
+ * transformer (paper's local-energy and energy-estimator equations, per
+ * molecule).  hams (host array of n_mol compiled Hamiltonians, each N <= 57
+ * spin-orbitals with every single and double excitation present as a flip
+ * group, so that every configuration of molecule i has the same number K_i of
+ * connected in-sector x') is copied into concatenated device tables; the
+ * model gets the molecules' sectors (amp_model_set_sectors) and stays owned by
+ * the caller, alive while the batch is used.  Errors: NQS_EINVAL,
+ * NQS_EUNSUPPORTED (a missing flip group, N too large, model shape).
+ */
+int batch_create(nqs_ham *const *hams, int n_mol, nqs_model *model, nqs_batch **out);
+void batch_destroy(nqs_batch *b);
+
+/* K_i (connected x' per configuration) and the flip-group count of every
+ * molecule (host arrays of n_mol, either may be NULL). */
+int batch_info(const nqs_batch *b, int64_t *k_per_config, int64_t *n_groups);
+
+/*
+ * batch_local_energy - E_loc of every sample of every molecule and the
+ * per-molecule sums.  x, counts (dev, U tagged words as produced by
+ * sample_unique_batch, grouped by molecule); offsets (host, n_mol + 1, first
+ * sample of each molecule, offsets[0] = 0, U = offsets[n_mol]); logabs_x /
+ * phase_x (dev, U; both NULL = computed here); eloc (dev, 2U doubles, re/im,
+ * written); sums (dev, 4 n_mol doubles: W, sum n Re E, sum n Im E,
+ * sum n |E|^2 of each molecule, written).  *n_pairs (host, may be NULL)
+ * receives sum_i U_i K_i.
+ * With a BF16 model the whole step is one sequence of fixed-grid launches
+ * (bit kernel with hash-table dedupe of x', fused amplitude kernel on the
+ * samples and on the distinct x', accumulation, reduction) whose sizes are
+ * read from device memory; it is captured into a hipGraph once per capacity
+ * and launch shape and replayed (batch_set_mode can switch to direct
+ * launches).  Launch shapes are chosen on the first call by timing candidates
+ * on that call's data.  FP32 / FP64 models run the same kernels with the
+ * layer-by-layer network between them (no graph).  Synchronises the stream.
+ * Errors: NQS_EINVAL (offsets, a configuration with more than K_i connected
+ * x' or an overfull table), NQS_ENOMEM.
+ */
+int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_t *counts,
+                       const int64_t *offsets, const double *logabs_x, const double *phase_x,
+                       double *eloc, double *sums, int64_t *n_pairs, nqs_stream stream);
+
+/* use_graph = 0: launch the step's kernels directly instead of replaying the
+ * captured graph; retune != 0: choose launch shapes again on the next call. */
+int batch_set_mode(nqs_batch *b, int use_graph, int retune);
+
+/* Fix the launch shape instead of tuning it: bit-kernel blocks (of four
+ * waves), configuration pairs per fused-kernel chunk (1..16) and fused-kernel
+ * blocks.  Results do not depend on the shape. */
+int batch_set_tile(nqs_batch *b, int pairs_blocks, int fused_pairs, int fused_blocks);
+
+/* Last call's pairs and distinct x', the number of graph captures so far, the
+ * chosen launch shape tile[3] = {bit-kernel blocks, fused pairs per chunk,
+ * fused blocks} and the tuner's candidate timings in ms (first n_tune).  Any
+ * output may be NULL. */
+int batch_stats(const nqs_batch *b, int64_t *n_pairs, int64_t *n_distinct, int64_t *captures,
+                int32_t *tile, double *tune_ms, int n_tune);
+
+/*
+ * vmc_weights_batch - vmc_weights per molecule for the gradient of the sum of
+ * the molecules' energies: sample l of molecule i (from the tag of x[l]) gets
+ * g_logabs = 2 n_l / W_i Re(E_loc,l - E_i), g_phase = 2 n_l / W_i Im(E_loc,l -
+ * E_i), with W_i, E_i from sums[4 i ..] of batch_local_energy (n_mol
+ * molecules; a word with a larger index gets NaN weights).  All dev.
+ */
+int vmc_weights_batch(const double *eloc, const uint64_t *counts, const uint64_t *x, int64_t n,
+                      const double *sums, int n_mol, double *g_logabs, double *g_phase,
+                      nqs_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */

@@ -1,5 +1,6 @@
 // C-ABI entry points: model handles, amplitudes, local energy, reducer, Adam.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <memory>
 #include <string>
@@ -62,6 +63,32 @@ std::vector<uint8_t> physical_children(int n, int na, int nb) {
         R(p, a, b) = mask != 0;
       }
   return kids;
+}
+
+// Sector tables of a model: one per molecule, physical-children table of each
+// from Algorithm 1, masked levels from the model's pruning strategy.
+void install_sectors(nqs_model &m, const std::vector<std::array<int, 3>> &secs, bool tagged) {
+  std::vector<uint8_t> phys;
+  std::vector<nqs_sector_info> info;
+  for (const auto &sc : secs) {
+    const int n = sc[0];
+    nqs_sector_info si{};
+    si.n = n;
+    si.na = sc[1];
+    si.nb = sc[2];
+    si.mask_levels = m.strategy == NQS_MU ? n : m.strategy == NQS_DU ? 0 : std::max(n - m.dlev, 0);
+    si.phys_off = int64_t(phys.size());
+    const std::vector<uint8_t> t = physical_children(n, si.na, si.nb);
+    phys.insert(phys.end(), t.begin(), t.end());
+    info.push_back(si);
+  }
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(m.phys.reserve(phys.size()), phys.data(), phys.size(), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(m.sec.reserve(info.size() * sizeof(nqs_sector_info)), info.data(),
+                   info.size() * sizeof(nqs_sector_info), hipMemcpyHostToDevice));
+  m.phys_host = std::move(phys);
+  m.sec_host = std::move(info);
+  m.tagged = tagged ? 1 : 0;
 }
 
 }  // namespace
@@ -141,10 +168,8 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
     NQS_REQUIRE(n_params == m->P, NQS_EINVAL,
                 "amp_model_create: n_params does not match the dimensions (expected " +
                     std::to_string(m->P) + ")");
-    m->phys_host = physical_children(n, m->na, m->nb);
     check_device();
-    HIP_OK(hipMemcpy(m->phys.reserve(m->phys_host.size()), m->phys_host.data(),
-                     m->phys_host.size(), hipMemcpyHostToDevice));
+    install_sectors(*m, {{n, m->na, m->nb}}, false);
     if (m->fp64()) {
       HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 8), params, size_t(m->P) * 8,
                        hipMemcpyHostToDevice));
@@ -156,6 +181,33 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
     if (precision == NQS_BF16) fused_pack(*m, nullptr);
     HIP_OK(hipDeviceSynchronize());
     *out = m.release();
+  });
+}
+
+extern "C" int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n,
+                                     const int32_t *n_alpha, const int32_t *n_beta) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_sectors: null handle");
+    NQS_REQUIRE(n_mol >= 0 && n_mol <= 64, NQS_EINVAL,
+                "amp_model_set_sectors: between 0 and 64 molecules");
+    if (n_mol == 0) {
+      install_sectors(*m, {{m->n, m->na, m->nb}}, false);
+      return;
+    }
+    NQS_REQUIRE(n && n_alpha && n_beta, NQS_EINVAL, "amp_model_set_sectors: null array");
+    NQS_REQUIRE(m->kind == NQS_MODEL_TRANSFORMER, NQS_EUNSUPPORTED,
+                "amp_model_set_sectors: only the transformer serves several molecules");
+    NQS_REQUIRE(2 * m->n <= kTagShift, NQS_EUNSUPPORTED,
+                "amp_model_set_sectors: more than 29 tokens leave no room for the molecule index");
+    std::vector<std::array<int, 3>> secs;
+    for (int i = 0; i < n_mol; ++i) {
+      NQS_REQUIRE(n[i] >= 1 && n[i] <= m->n, NQS_EINVAL,
+                  "amp_model_set_sectors: molecule has more tokens than the model's positions");
+      NQS_REQUIRE(n_alpha[i] >= 0 && n_alpha[i] <= n[i] && n_beta[i] >= 0 && n_beta[i] <= n[i],
+                  NQS_EINVAL, "amp_model_set_sectors: electron counts out of range");
+      secs.push_back({n[i], n_alpha[i], n_beta[i]});
+    }
+    install_sectors(*m, secs, true);
   });
 }
 
@@ -266,8 +318,8 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
     NQS_REQUIRE(n == 0 || (x && eloc), NQS_EINVAL, "local_energy: null array");
     NQS_REQUIRE((logabs_x == nullptr) == (phase_x == nullptr), NQS_EINVAL,
                 "local_energy: give both or neither of logabs_x, phase_x");
-    NQS_REQUIRE(H->n == m->n && H->n_alpha == m->na && H->n_beta == m->nb, NQS_EINVAL,
-                "local_energy: Hamiltonian and model describe different systems");
+    NQS_REQUIRE(H->n == m->n && H->n_alpha == m->na && H->n_beta == m->nb && !m->tagged,
+                NQS_EINVAL, "local_energy: Hamiltonian and model describe different systems");
     hipStream_t s = as_stream(stream);
     check_device();
     H->upload();

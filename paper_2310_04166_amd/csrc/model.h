@@ -5,6 +5,42 @@
 
 #include "common.h"
 
+// One molecule (symmetry sector) served by a model: its token count,
+// electrons, number of masked levels and where its physical-children table
+// starts in the model's concatenated tables ([(n+1)^3] 4-bit masks each).
+struct nqs_sector_info {
+  int32_t n, na, nb, mask_levels;
+  int64_t phys_off;
+};
+
+namespace nqs {
+// A model that serves several molecules reads the molecule of a configuration
+// word from bits 58..63 (its occupation bits stay below); a model with one
+// sector uses the words as they are.
+constexpr int kTagShift = 58;
+constexpr uint64_t kOccMask = (uint64_t(1) << kTagShift) - 1;
+
+struct Sectors {                      // device view handed to kernels
+  const nqs_sector_info *info;
+  const uint8_t *phys;
+  int tagged, count;                  // count = number of sectors in info
+};
+
+// A word whose molecule index is out of range reads molecule 0's sector (its
+// results are meaningless, but no access leaves the tables).
+__device__ inline const nqs_sector_info &sector_of(const Sectors &S, uint64_t x) {
+  const int i = S.tagged ? int(x >> kTagShift) : 0;
+  return S.info[i < S.count ? i : 0];
+}
+__device__ inline uint64_t occupation(const Sectors &S, uint64_t x) {
+  return S.tagged ? (x & kOccMask) : x;
+}
+// 4-bit set of physical tokens at level t after a alpha / b beta electrons
+__device__ inline int phys_mask(const Sectors &S, const nqs_sector_info &si, int t, int a, int b) {
+  return S.phys[si.phys_off + (int64_t(t) * (si.n + 1) + a) * (si.n + 1) + b];
+}
+}  // namespace nqs
+
 struct nqs_model {
   int kind = 0, precision = 0, strategy = 0, dlev = 0;
   int n = 0, na = 0, nb = 0;          // tokens, sector
@@ -13,10 +49,13 @@ struct nqs_model {
   int mask_levels = 0;                // positions p < mask_levels use masked conditionals
   int64_t P = 0;                      // parameter count
   std::vector<int64_t> off;           // parameter offsets, see param_index()
-  std::vector<uint8_t> phys_host;     // [(n+1)^3] 4-bit physical-child masks
+  std::vector<uint8_t> phys_host;     // concatenated physical-child tables of the sectors
+  std::vector<nqs_sector_info> sec_host;  // one entry, or one per molecule when tagged
+  int tagged = 0;                     // configuration words carry the molecule index
 
   nqs::DevBuf master;                 // canonical parameters (double in FP64, float otherwise)
   nqs::DevBuf phys;                   // device copy of phys_host
+  nqs::DevBuf sec;                    // device copy of sec_host
   nqs::DevBuf packed;                 // bf16 weight fragments of the fused kernel
   nqs::DevBuf packed_vec;             // permuted fp32 vectors of the fused kernel
   bool packed_valid = false;
@@ -27,6 +66,9 @@ struct nqs_model {
   size_t ones_bytes = 0;
 
   bool fp64() const { return precision == NQS_FP64; }
+  nqs::Sectors sectors() const {
+    return {sec.as<nqs_sector_info>(), phys.as<uint8_t>(), tagged, int(sec_host.size())};
+  }
   size_t elem() const { return fp64() ? 8 : 4; }
 };
 
@@ -58,8 +100,18 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
                     const double *gp, void *grad, hipStream_t s);
 // Fused bf16 forward (tf_fused.hip).
 int64_t model_chunk(const nqs_model &m, bool bwd);
+// Launch shape of the fused kernel: chunks of 2 * pairs configurations per
+// wave step, `blocks` blocks of four waves striding over the chunks (0 = the
+// default: one chunk per wave, chunk size from the batch size).
+struct FusedTile {
+  int pairs = 0, blocks = 0;
+};
+// With `count` (a device pointer) the kernel reads the number of
+// configurations from the device and B is only the capacity of x / outputs;
+// such a launch has a fixed grid and can be captured in a graph.
 void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
-                   double *cond_out, int cond_p, hipStream_t s);
+                   double *cond_out, int cond_p, hipStream_t s, const int64_t *count = nullptr,
+                   FusedTile tile = FusedTile{});
 void fused_pack(nqs_model &m, hipStream_t s);
 bool fused_supported(const nqs_model &m);
 

@@ -75,20 +75,22 @@ __global__ void __launch_bounds__(256) head_kernel(const T *h, int64_t R, int n,
 }
 
 // log|psi| = 1/2 sum_t log softmax over allowed tokens; one thread per configuration.
-// stride/koff select the 4 logits of position t inside a row of `stride` values.
+// Rows hold T positions; the configuration's own molecule has n <= T tokens.
+// stride selects the 4 logits of position t inside a row of `stride` values.
 template <class T>
-__global__ void logabs_kernel(const uint64_t *x, int64_t B, int n, const T *logits, int stride,
-                              const uint8_t *phys, int mask_levels, double *logabs) {
+__global__ void logabs_kernel(const uint64_t *x, int64_t B, int Tn, const T *logits, int stride,
+                              Sectors S, double *logabs) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const uint64_t xb = x[b];
+  const nqs_sector_info si = sector_of(S, xb);
   int a = 0, c = 0;
   double s = 0.0;
-  for (int t = 0; t < n; ++t) {
+  for (int t = 0; t < si.n; ++t) {
     const int tk = tok_of(xb, t);
-    const int allow = t < mask_levels ? phys[(t * (n + 1) + a) * (n + 1) + c] : 0xF;
+    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c) : 0xF;
     if (!((allow >> tk) & 1)) { s = -INFINITY; break; }
-    const T *l = logits + (b * n + t) * stride;
+    const T *l = logits + (b * Tn + t) * stride;
     double mx = -INFINITY;
     for (int k = 0; k < 4; ++k)
       if ((allow >> k) & 1) mx = fmax(mx, double(l[k]));
@@ -102,28 +104,32 @@ __global__ void logabs_kernel(const uint64_t *x, int64_t B, int n, const T *logi
   logabs[b] = 0.5 * s;
 }
 
-// d(sum_b g_b log|psi_b|)/d logits; zero for masked tokens
+// d(sum_b g_b log|psi_b|)/d logits; zero for masked tokens and absent positions
 template <class T>
-__global__ void dlogits_kernel(const uint64_t *x, int64_t B, int n, const T *logits, int stride,
-                               const uint8_t *phys, int mask_levels, const double *gl, T *dlog,
-                               int dstride) {
+__global__ void dlogits_kernel(const uint64_t *x, int64_t B, int Tn, const T *logits, int stride,
+                               Sectors S, const double *gl, T *dlog, int dstride) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const uint64_t xb = x[b];
+  const nqs_sector_info si = sector_of(S, xb);
   int a = 0, c = 0;
   bool ok = true;
-  for (int t = 0; t < n; ++t) {
+  for (int t = 0; t < Tn; ++t) {
+    T *dl = dlog + (b * Tn + t) * dstride;
+    if (t >= si.n) {
+      for (int k = 0; k < 4; ++k) dl[k] = T(0);
+      continue;
+    }
     const int tk = tok_of(xb, t);
-    const int allow = t < mask_levels ? phys[(t * (n + 1) + a) * (n + 1) + c] : 0xF;
+    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c) : 0xF;
     if (!((allow >> tk) & 1)) ok = false;
-    const T *l = logits + (b * n + t) * stride;
+    const T *l = logits + (b * Tn + t) * stride;
     double mx = -INFINITY;
     for (int k = 0; k < 4; ++k)
       if ((allow >> k) & 1) mx = fmax(mx, double(l[k]));
     double z = 0.0;
     for (int k = 0; k < 4; ++k)
       if ((allow >> k) & 1) z += exp(double(l[k]) - mx);
-    T *dl = dlog + (b * n + t) * dstride;
     for (int k = 0; k < 4; ++k) {
       double v = 0.0;
       if (ok && ((allow >> k) & 1))
@@ -143,13 +149,15 @@ __global__ void cond_extract_kernel(const T *logits, int64_t B, int n, int strid
   out[i] = double(logits[((i / 4) * n + p) * stride + (i % 4)]);
 }
 
+// phase-MLP first layer over the one-hot code of the configuration's own tokens
 template <class T>
-__global__ void phase_in_kernel(const uint64_t *x, int64_t B, int n, int PH, const T *W1,
+__global__ void phase_in_kernel(const uint64_t *x, int64_t B, Sectors S, int PH, const T *W1,
                                 const T *b1, T *pre, T *out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= B * PH) return;
   const int j = int(idx % PH);
   const uint64_t xb = x[idx / PH];
+  const int n = sector_of(S, xb).n;
   T a = b1[j];
   for (int t = 0; t < n; ++t) a += W1[(4 * t + tok_of(xb, t)) * PH + j];
   pre[idx] = a;
@@ -179,13 +187,15 @@ __global__ void mlp_phase_kernel(const uint64_t *x, int64_t B, int n, const T *o
   phase[b] = s;
 }
 
-// one-hot code of tokens 0..p-1, [B, 4p]
+// one-hot code of tokens 0..p-1, [B, 4p]; positions beyond the configuration's
+// own molecule are zero
 template <class T>
-__global__ void onehot_kernel(const uint64_t *x, int64_t B, int p, T *X) {
+__global__ void onehot_kernel(const uint64_t *x, int64_t B, int p, Sectors S, T *X) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= B * 4 * p) return;
   const int col = int(idx % (4 * p));
-  X[idx] = tok_of(x[idx / (4 * p)], col / 4) == (col % 4) ? T(1) : T(0);
+  const uint64_t xb = x[idx / (4 * p)];
+  X[idx] = (col / 4 < sector_of(S, xb).n && tok_of(xb, col / 4) == (col % 4)) ? T(1) : T(0);
 }
 
 // scatter rows [B, w] into positions of [B, n, w]
@@ -337,11 +347,11 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
   HIP_LAUNCH_OK();
   if (logabs) {
     hipLaunchKernelGGL(logabs_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.logits, 4,
-                       m.phys.as<uint8_t>(), m.mask_levels, logabs);
+                       m.sectors(), logabs);
     HIP_LAUNCH_OK();
   }
   if (phase || save) {
-    hipLaunchKernelGGL(phase_in_kernel<T>, g1(B * PH), dim3(256), 0, s, x, B, n, PH,
+    hipLaunchKernelGGL(phase_in_kernel<T>, g1(B * PH), dim3(256), 0, s, x, B, m.sectors(), PH,
                        P<T>(m, tf_tail(L, TF_PW1)), P<T>(m, tf_tail(L, TF_PB1)), A.z1pre, A.z1);
     HIP_LAUNCH_OK();
     gemm<T, false, false>(B, PH, PH, A.z1, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, A.z2, PH,
@@ -411,7 +421,7 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
 
   // head and masked log-softmax
   hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.logits, 4,
-                     m.phys.as<uint8_t>(), m.mask_levels, gl, dl, 4);
+                     m.sectors(), gl, dl, 4);
   HIP_LAUNCH_OK();
   wgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), s);
   bgrad<T>(m, dl, R, 4, 4, tf_tail(L, TF_BHEAD), s);
@@ -469,7 +479,7 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
                           nullptr, EPI_STORE, s);
   gelu_bwd<T>(A.z1pre, dz1, B * PH, s);
   bgrad<T>(m, dz1, B, PH, PH, tf_tail(L, TF_PB1), s);
-  hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * n), dim3(256), 0, s, x, B, n, tmp);
+  hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * n), dim3(256), 0, s, x, B, n, m.sectors(), tmp);
   HIP_LAUNCH_OK();
   wgrad<T>(m, 4 * n, PH, B, tmp, 4 * n, dz1, PH, tf_tail(L, TF_PW1), s);
 }
@@ -485,7 +495,7 @@ void mlp_position(nqs_model &m, const uint64_t *x, int64_t B, int p, T *X, T *h1
                   T *o, hipStream_t s) {
   const int hid = m.hid;
   if (p > 0) {
-    hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * p), dim3(256), 0, s, x, B, p, X);
+    hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * p), dim3(256), 0, s, x, B, p, m.sectors(), X);
     HIP_LAUNCH_OK();
   }
   auto W = [&](int k) { return P<T>(m, 6 * p + k); };
@@ -526,7 +536,7 @@ void mlp_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, double *logab
   }
   if (logabs) {
     hipLaunchKernelGGL(logabs_kernel<T>, g1(B), dim3(256), 0, s, x, B, m.n, out8, 8,
-                       m.phys.as<uint8_t>(), m.mask_levels, logabs);
+                       m.sectors(), logabs);
     HIP_LAUNCH_OK();
   }
   if (phase) {
@@ -557,8 +567,8 @@ void mlp_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double
     hipLaunchKernelGGL(scatter_pos_kernel<T>, g1(B * 8), dim3(256), 0, s, o, B, n, 8, p, out8);
     HIP_LAUNCH_OK();
   }
-  hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, out8, 8,
-                     m.phys.as<uint8_t>(), m.mask_levels, gl, d8, 8);
+  hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, out8, 8, m.sectors(),
+                     gl, d8, 8);
   HIP_LAUNCH_OK();
   hipLaunchKernelGGL(mlp_dphase_kernel<T>, g1(B * n * 4), dim3(256), 0, s, x, B, n, gp, d8);
   HIP_LAUNCH_OK();

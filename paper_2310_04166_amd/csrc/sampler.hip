@@ -15,6 +15,7 @@
 // J. Statist. Comput. Simul. 46, 1993).  All of this is double precision
 // without contraction, so a draw depends only on (seed, node, logits).
 #include <cmath>
+#include <vector>
 
 #include "ham.h"
 #include "model.h"
@@ -129,18 +130,28 @@ __device__ int64_t binomial(int64_t n, double p, Uniforms &uni) {
   return flip ? n - k : k;
 }
 
-// One thread per frontier node: split its samples over the four tokens.
+// One thread per frontier node: split its samples over the four tokens.  A
+// node whose molecule has no token at level p (a smaller molecule of a batch)
+// passes all its samples to child 0, which is the same configuration word.
 __global__ void split_kernel(const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ cnt,
-                             const double *__restrict__ logits, int64_t B, int p, int n,
-                             int mask_levels, const uint8_t *__restrict__ phys, uint64_t seed,
-                             uint64_t *__restrict__ child, uint64_t *__restrict__ flag,
-                             unsigned long long *__restrict__ lost) {
+                             const double *__restrict__ logits, int64_t B, int p, Sectors S,
+                             uint64_t seed, uint64_t *__restrict__ child,
+                             uint64_t *__restrict__ flag, unsigned long long *__restrict__ lost) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= B) return;
   const uint64_t x = prefix[i];
-  const int a = __popcll(x & kAlphaBits), b = __popcll(x & kBetaBits);
-  const int ph = phys[(p * (n + 1) + a) * (n + 1) + b];
-  const int allow = p < mask_levels ? ph : 0xF;
+  const nqs_sector_info si = sector_of(S, x);
+  if (p >= si.n) {
+    for (int k = 0; k < 4; ++k) {
+      child[4 * i + k] = k == 0 ? cnt[i] : 0;
+      flag[4 * i + k] = k == 0 ? 1 : 0;
+    }
+    return;
+  }
+  const uint64_t occ = occupation(S, x);
+  const int a = __popcll(occ & kAlphaBits), b = __popcll(occ & kBetaBits);
+  const int ph = phys_mask(S, si, p, a, b);
+  const int allow = p < si.mask_levels ? ph : 0xF;
   const double *l = logits + 4 * i;
   double mx = -INFINITY;
   for (int k = 0; k < 4; ++k)
@@ -188,11 +199,78 @@ __global__ void compact_kernel(const uint64_t *__restrict__ prefix,
   ncnt[o] = c;
 }
 
-__global__ void init_kernel(uint64_t *pre, uint64_t *cnt, uint64_t n_samples,
-                            unsigned long long *lost) {
-  pre[0] = 0;
-  cnt[0] = n_samples;
-  *lost = 0;
+__global__ void init_kernel(unsigned long long *lost) { *lost = 0; }
+
+// offsets[i] = first leaf of molecule i (leaves are grouped by molecule in
+// ascending order); offsets[n_mol] = B.
+__global__ void mol_offsets_kernel(const uint64_t *__restrict__ leaves, int64_t B, int n_mol,
+                                   int64_t *__restrict__ offsets) {
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i > n_mol) return;
+  int64_t lo = 0, hi = B;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (int(leaves[mid] >> kTagShift) < i) lo = mid + 1;
+    else hi = mid;
+  }
+  offsets[i] = lo;
+}
+
+// Expands the trees whose roots (configuration word, samples) are given, all
+// levels together; returns the number of leaves, left in m.s_pre/s_cnt[cur].
+int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
+                   const std::vector<uint64_t> &root_cnt, uint64_t seed, int &cur,
+                   uint64_t &lost_out, hipStream_t s) {
+  int64_t B = int64_t(root_pre.size());
+  auto *lost_d = static_cast<unsigned long long *>(m.s_lost.reserve(8));
+  cur = 0;
+  m.s_pre[0].reserve(size_t(B > 0 ? B : 1) * 8);
+  m.s_cnt[0].reserve(size_t(B > 0 ? B : 1) * 8);
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1), 0, s, lost_d);
+  HIP_LAUNCH_OK();
+  if (B > 0) {
+    HIP_OK(hipMemcpyAsync(m.s_pre[0].ptr, root_pre.data(), size_t(B) * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(m.s_cnt[0].ptr, root_cnt.data(), size_t(B) * 8, hipMemcpyHostToDevice, s));
+  }
+  for (int p = 0; p < m.n && B > 0; ++p) {
+    double *cond = static_cast<double *>(m.s_cond.reserve(size_t(B) * 4 * 8));
+    model_cond_logits(m, m.s_pre[cur].as<uint64_t>(), B, p, cond, s);
+    auto *child = static_cast<uint64_t *>(m.s_child.reserve(size_t(B) * 4 * 8));
+    auto *flag = static_cast<int64_t *>(m.s_flag.reserve(size_t(B) * 4 * 8));
+    auto *off = static_cast<int64_t *>(m.s_off.reserve(size_t(B * 4 + 1) * 8));
+    hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
+                       m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, p,
+                       m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);
+    HIP_LAUNCH_OK();
+    launch_exclusive_scan(flag, off, B * 4, s);
+    int64_t nb = 0;
+    HIP_OK(hipMemcpyAsync(&nb, off + B * 4, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const int nxt = 1 - cur;
+    m.s_pre[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
+    m.s_cnt[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
+    hipLaunchKernelGGL(compact_kernel, dim3(unsigned(ceil_div(B * 4, 256))), dim3(256), 0, s,
+                       m.s_pre[cur].as<uint64_t>(), child, off, B * 4, p,
+                       m.s_pre[nxt].as<uint64_t>(), m.s_cnt[nxt].as<uint64_t>());
+    HIP_LAUNCH_OK();
+    cur = nxt;
+    B = nb;
+  }
+  uint64_t lost_h = 0;
+  HIP_OK(hipMemcpyAsync(&lost_h, lost_d, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  lost_out = lost_h;
+  return B;
+}
+
+void copy_leaves(nqs_model &m, int cur, int64_t B, int64_t capacity, uint64_t *configs,
+                 uint64_t *counts, hipStream_t s) {
+  NQS_REQUIRE(B <= capacity, NQS_ECAPACITY, "sampler: capacity too small");
+  NQS_REQUIRE(B == 0 || (configs && counts), NQS_EINVAL, "sampler: null output");
+  if (B > 0) {
+    HIP_OK(hipMemcpyAsync(configs, m.s_pre[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(counts, m.s_cnt[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
+  }
 }
 
 }  // namespace
@@ -206,51 +284,51 @@ extern "C" int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, ui
   return guarded([&] {
     NQS_REQUIRE(m && n_unique, NQS_EINVAL, "sample_unique: null argument");
     NQS_REQUIRE(capacity >= 0, NQS_EINVAL, "sample_unique: negative capacity");
+    NQS_REQUIRE(!m->tagged, NQS_EINVAL,
+                "sample_unique: the model serves several molecules (use sample_unique_batch)");
     hipStream_t s = as_stream(stream);
-    int64_t B = 1;
-    auto *lost_d = static_cast<unsigned long long *>(m->s_lost.reserve(8));
-    int cur = 0;
-    m->s_pre[0].reserve(8);
-    m->s_cnt[0].reserve(8);
-    hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1), 0, s, m->s_pre[0].as<uint64_t>(),
-                       m->s_cnt[0].as<uint64_t>(), n_samples, lost_d);
-    HIP_LAUNCH_OK();
-    if (n_samples == 0) B = 0;
-    for (int p = 0; p < m->n && B > 0; ++p) {
-      double *cond = static_cast<double *>(m->s_cond.reserve(size_t(B) * 4 * 8));
-      model_cond_logits(*m, m->s_pre[cur].as<uint64_t>(), B, p, cond, s);
-      auto *child = static_cast<uint64_t *>(m->s_child.reserve(size_t(B) * 4 * 8));
-      auto *flag = static_cast<int64_t *>(m->s_flag.reserve(size_t(B) * 4 * 8));
-      auto *off = static_cast<int64_t *>(m->s_off.reserve(size_t(B * 4 + 1) * 8));
-      hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
-                         m->s_pre[cur].as<uint64_t>(), m->s_cnt[cur].as<uint64_t>(), cond, B, p,
-                         m->n, m->mask_levels, m->phys.as<uint8_t>(), seed, child,
-                         reinterpret_cast<uint64_t *>(flag), lost_d);
-      HIP_LAUNCH_OK();
-      launch_exclusive_scan(flag, off, B * 4, s);
-      int64_t nb = 0;
-      HIP_OK(hipMemcpyAsync(&nb, off + B * 4, 8, hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
-      const int nxt = 1 - cur;
-      m->s_pre[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
-      m->s_cnt[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
-      hipLaunchKernelGGL(compact_kernel, dim3(unsigned(ceil_div(B * 4, 256))), dim3(256), 0, s,
-                         m->s_pre[cur].as<uint64_t>(), child, off, B * 4, p,
-                         m->s_pre[nxt].as<uint64_t>(), m->s_cnt[nxt].as<uint64_t>());
-      HIP_LAUNCH_OK();
-      cur = nxt;
-      B = nb;
+    std::vector<uint64_t> pre, cnt;
+    if (n_samples > 0) {
+      pre.push_back(0);
+      cnt.push_back(n_samples);
     }
+    int cur = 0;
     uint64_t lost_h = 0;
-    HIP_OK(hipMemcpyAsync(&lost_h, lost_d, 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    const int64_t B = walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
     if (lost) *lost = lost_h;
     *n_unique = B;
-    NQS_REQUIRE(B <= capacity, NQS_ECAPACITY, "sample_unique: capacity too small");
-    NQS_REQUIRE(B == 0 || (configs && counts), NQS_EINVAL, "sample_unique: null output");
-    if (B > 0) {
-      HIP_OK(hipMemcpyAsync(configs, m->s_pre[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
-      HIP_OK(hipMemcpyAsync(counts, m->s_cnt[cur].ptr, size_t(B) * 8, hipMemcpyDeviceToDevice, s));
-    }
+    copy_leaves(*m, cur, B, capacity, configs, counts, s);
+  });
+}
+
+extern "C" int sample_unique_batch(nqs_model *m, int n_mol, const uint64_t *n_samples,
+                                   uint64_t seed, uint64_t *configs, uint64_t *counts,
+                                   int64_t capacity, int64_t *n_unique, int64_t *offsets,
+                                   uint64_t *lost, nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(m && n_unique && n_samples && offsets, NQS_EINVAL,
+                "sample_unique_batch: null argument");
+    NQS_REQUIRE(capacity >= 0, NQS_EINVAL, "sample_unique_batch: negative capacity");
+    NQS_REQUIRE(m->tagged && n_mol == int(m->sec_host.size()), NQS_EINVAL,
+                "sample_unique_batch: n_mol differs from the model's molecules");
+    hipStream_t s = as_stream(stream);
+    std::vector<uint64_t> pre, cnt;
+    for (int i = 0; i < n_mol; ++i)
+      if (n_samples[i] > 0) {
+        pre.push_back(uint64_t(i) << kTagShift);
+        cnt.push_back(n_samples[i]);
+      }
+    int cur = 0;
+    uint64_t lost_h = 0;
+    const int64_t B = walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
+    if (lost) *lost = lost_h;
+    *n_unique = B;
+    int64_t *off_d = static_cast<int64_t *>(m->s_off.reserve(size_t(n_mol + 1) * 8));
+    hipLaunchKernelGGL(mol_offsets_kernel, dim3(unsigned(ceil_div(n_mol + 1, 64))), dim3(64), 0,
+                       s, m->s_pre[cur].as<uint64_t>(), B, n_mol, off_d);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(offsets, off_d, size_t(n_mol + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    copy_leaves(*m, cur, B, capacity, configs, counts, s);
   });
 }

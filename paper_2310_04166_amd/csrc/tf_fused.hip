@@ -63,11 +63,12 @@ struct FusedArgs {
       bo[kMaxLayers], ln2g[kMaxLayers], ln2b[kMaxLayers], b1[kMaxLayers], b2[kMaxLayers];
   int64_t p2;                       // phase W2 fragments
   int64_t lnfg, lnfb, whead, bhead, lbias, tok, pos, pb1, pb2, pw3, pb3, pw1;  // vec offsets
-  const uint8_t *phys;
+  Sectors sec;                      // molecule(s) of the configurations
   const uint64_t *x;
-  int64_t B;
-  int n, L, mask_levels, cond_p;
-  int pairs;                        // passes per wave (configurations per wave / 2), <= 16
+  int64_t B;                        // configurations (capacity when `count` is given)
+  const int64_t *count;             // optional device-side count (persistent launches)
+  int n, L, cond_p;                 // n = positions of the model
+  int pairs;                        // passes per chunk (configurations per chunk / 2), <= 16
   double *logabs, *phase, *cond;
 };
 
@@ -255,9 +256,12 @@ fused_kernel(FusedArgs a) {
   using S = Shape<D>;
   constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
   const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
-  const int64_t group = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
-  const int64_t c_base = group * 2 * a.pairs;
-  if (c_base >= a.B) return;
+  // wave index, explicitly wave-uniform so the chunk loop stays a scalar loop
+  const int64_t group = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64));
+  // a persistent launch reads the number of configurations from the device
+  const int64_t B = a.count ? (*a.count < a.B ? *a.count : a.B) : a.B;
+  if (group * 2 * a.pairs >= B) return;
+  const int64_t n_groups = int64_t(gridDim.x) * 4;
   const int t = r % kSeq;            // position of this lane's row
   const bool upper = r >= kSeq;      // second configuration of the pair
   const int n = a.n;
@@ -278,10 +282,13 @@ fused_kernel(FusedArgs a) {
   bf16x8 fr[2][HS];
   load_half<D>(fr[0], wview(0), 0, 0);
 
+  // chunks of 2 * pairs configurations, strided over the waves of the grid
+  for (int64_t chunk = group; chunk * 2 * a.pairs < B; chunk += n_groups) {
+  const int64_t c_base = chunk * 2 * a.pairs;
   for (int pair = 0; pair < a.pairs; ++pair) {
     const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
-    if (c_base + 2 * pair >= a.B) break;
-    const bool live = cfg < a.B;
+    if (c_base + 2 * pair >= B) break;
+    const bool live = cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
 
     // embedding: token of the previous position (BOS at position 0)
@@ -452,10 +459,17 @@ fused_kernel(FusedArgs a) {
     if (t < n) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) lg[k] += vec[a.bhead + k] + vec[a.lbias + t * 4 + k];
+      if (a.cond && t == a.cond_p && h == 0 && live) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
+      }
+    }
+    const nqs_sector_info &si = sector_of(a.sec, x);
+    if (t < si.n) {
       const uint64_t below = (t == 0) ? 0ull : (~0ull >> (64 - 2 * t));
       const int na = __popcll(x & below & 0x5555555555555555ull);
       const int nb = __popcll(x & below & 0xAAAAAAAAAAAAAAAAull);
-      const int allow = t < a.mask_levels ? a.phys[(t * (n + 1) + na) * (n + 1) + nb] : 0xF;
+      const int allow = t < si.mask_levels ? phys_mask(a.sec, si, t, na, nb) : 0xF;
       const int tk = int((x >> (2 * t)) & 3ull);
       float mx = -INFINITY;
 #pragma unroll
@@ -466,10 +480,6 @@ fused_kernel(FusedArgs a) {
       for (int k = 0; k < 4; ++k)
         if ((allow >> k) & 1) z += expf(lg[k] - mx);
       logp = ((allow >> tk) & 1) ? lg[tk] - mx - logf(z) : -INFINITY;
-      if (a.cond && t == a.cond_p && h == 0 && live) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
-      }
     }
     if (a.logabs) {
       logp += __shfl_xor(logp, 1);
@@ -480,17 +490,18 @@ fused_kernel(FusedArgs a) {
     }
   }
 
-  // ---- phase MLP for the group's 32 configurations (column = configuration)
+  // ---- phase MLP for the chunk's configurations (column = configuration)
   if (a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
     const int64_t cfg = c_base + r;
-    const bool live = r < 2 * a.pairs && cfg < a.B;
+    const bool live = r < 2 * a.pairs && cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
+    const int nx = live ? sector_of(a.sec, x).n : 0;
     bf16x8 Z[PKS];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       f32x16 z = load16(vec + a.pb1 + (b * 2 + h) * 16);
-      for (int tt = 0; tt < n; ++tt) {
+      for (int tt = 0; tt < nx; ++tt) {
         const int row = 4 * tt + int((x >> (2 * tt)) & 3ull);
         z += load16(vec + a.pw1 + int64_t(row) * PH + (b * 2 + h) * 16);
       }
@@ -512,6 +523,7 @@ fused_kernel(FusedArgs a) {
     ph = pair_sum(ph);
     if (h == 0 && live) a.phase[cfg] = double(ph + vec[a.pb3]);
   }
+  }  // chunk
 }
 
 // ----------------------------------------------------------------- packing
@@ -694,19 +706,20 @@ void fused_pack(nqs_model &m, hipStream_t s) {
 }
 
 void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
-                   double *cond_out, int cond_p, hipStream_t s) {
+                   double *cond_out, int cond_p, hipStream_t s, const int64_t *count,
+                   FusedTile tile) {
   NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
   if (B <= 0) return;
   Layout L = plan(m);
   FusedArgs a = L.a;
   a.pk = m.packed.as<bf16x8>();
   a.vec = m.packed_vec.as<float>();
-  a.phys = m.phys.as<uint8_t>();
+  a.sec = m.sectors();
   a.x = x;
   a.B = B;
+  a.count = nullptr;
   a.n = m.n;
   a.L = m.L;
-  a.mask_levels = m.mask_levels;
   a.cond_p = cond_p;
   a.logabs = logabs;
   a.phase = phase;
@@ -715,10 +728,14 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   // small to give every SIMD of the chip two waves
   const int64_t target_waves = 2048;
   a.pairs = int(std::min<int64_t>(kPairs, std::max<int64_t>(1, ceil_div(B, 2 * target_waves))));
+  if (tile.pairs > 0) a.pairs = std::min(tile.pairs, kPairs);
+  a.count = count;
   const int64_t groups = ceil_div(B, 2 * a.pairs);
-  const dim3 grid(unsigned(ceil_div(groups, 4)));
+  int64_t blocks = ceil_div(groups, 4);
+  if (tile.blocks > 0) blocks = std::min<int64_t>(blocks, tile.blocks);
+  const dim3 grid = dim3(unsigned(blocks));
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_timing) {
+  if (g_timing && !count) {
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, s));
@@ -728,7 +745,7 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   else
     hipLaunchKernelGGL(fused_kernel<64>, grid, dim3(256), 0, s, a);
   HIP_LAUNCH_OK();
-  if (g_timing) {
+  if (g_timing && !count) {
     HIP_OK(hipEventRecord(e1, s));
     g_records.push_back({e0, e1, B});
   }

@@ -57,6 +57,19 @@ _SIGS = {
     "vmc_weights": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "adam_update": ([_vp, _vp, _vp, _vp, _i64, C.c_int, _dbl, _dbl, _dbl, _dbl, _i64, _vp],
                     C.c_int),
+    "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
+    "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
+                             C.POINTER(_u64), _vp], C.c_int),
+    "batch_create": ([_vp, C.c_int, _vp, C.POINTER(_vp)], C.c_int),
+    "batch_destroy": ([_vp], None),
+    "batch_info": ([_vp, _vp, _vp], C.c_int),
+    "batch_local_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64), _vp],
+                           C.c_int),
+    "batch_set_mode": ([_vp, C.c_int, C.c_int], C.c_int),
+    "batch_set_tile": ([_vp, C.c_int, C.c_int, C.c_int], C.c_int),
+    "batch_stats": ([_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), _vp, _vp, C.c_int],
+                    C.c_int),
+    "vmc_weights_batch": ([_vp, _vp, _vp, _i64, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "nqs_timing_enable": ([C.c_int], C.c_int),
     "nqs_timing_read": ([C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
 }
@@ -173,6 +186,13 @@ class Model:
         assert len(p) == self.n_params
         _check(lib().amp_model_set_params(self.handle, _ptr(p)))
 
+    def set_sectors(self, sectors):
+        """Serve several molecules: ``sectors`` = [(n, n_alpha, n_beta), ...]
+        (empty = back to the model's own sector)."""
+        a = np.ascontiguousarray(np.asarray(sectors, dtype=np.int32).reshape(-1, 3).T)
+        _check(lib().amp_model_set_sectors(self.handle, a.shape[1], _ptr(a[0].copy()),
+                                           _ptr(a[1].copy()), _ptr(a[2].copy())))
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.amp_model_destroy(self.handle)
@@ -213,6 +233,97 @@ def sample_unique(model, n_samples, seed, capacity=None, stream=None, device="cu
         return sample_unique(model, n_samples, seed, nu.value, stream, device)
     _check(st)
     return configs[:nu.value], counts[:nu.value], lost.value
+
+
+TAG_SHIFT = 58
+
+
+def tag(x, mol):
+    """Configuration words of molecule ``mol`` (int64 tensor, bits 58..63)."""
+    return x | (int(mol) << TAG_SHIFT)
+
+
+def untag(x):
+    """(occupation bits, molecule index) of tagged words."""
+    return x & ((1 << TAG_SHIFT) - 1), (x >> TAG_SHIFT) & 63
+
+
+def sample_unique_batch(model, n_samples, seed, capacity=None, stream=None, device="cuda"):
+    """One tree per molecule of a model with sectors.  Returns (configs, counts,
+    offsets (numpy, n_mol + 1), lost)."""
+    ns = np.ascontiguousarray(n_samples, dtype=np.uint64)
+    n_mol = len(ns)
+    cap = int(capacity if capacity is not None else min(int(ns.sum()), 1 << 24))
+    configs = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    counts = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    offsets = np.zeros(n_mol + 1, dtype=np.int64)
+    nu, lost = _i64(), _u64()
+    st = lib().sample_unique_batch(model.handle, n_mol, _ptr(ns), int(seed) & ((1 << 64) - 1),
+                                   _ptr(configs), _ptr(counts), cap, C.byref(nu), _ptr(offsets),
+                                   C.byref(lost), _stream(stream))
+    if st == -2 and capacity is None:
+        return sample_unique_batch(model, n_samples, seed, nu.value, stream, device)
+    _check(st)
+    return configs[:nu.value], counts[:nu.value], offsets, lost.value
+
+
+class Batch:
+    """Molecules sharing one transformer (``batch_create``)."""
+
+    def __init__(self, hams, model):
+        arr = (C.c_void_p * len(hams))(*[h.handle for h in hams])
+        h = _vp()
+        _check(lib().batch_create(arr, len(hams), model.handle, C.byref(h)))
+        self.handle, self.hams, self.model, self.n_mol = h, list(hams), model, len(hams)
+
+    def info(self):
+        k = np.zeros(self.n_mol, np.int64)
+        g = np.zeros(self.n_mol, np.int64)
+        _check(lib().batch_info(self.handle, _ptr(k), _ptr(g)))
+        return k, g
+
+    def set_mode(self, use_graph=True, retune=False):
+        _check(lib().batch_set_mode(self.handle, int(bool(use_graph)), int(bool(retune))))
+
+    def set_tile(self, pairs_blocks, fused_pairs, fused_blocks):
+        _check(lib().batch_set_tile(self.handle, pairs_blocks, fused_pairs, fused_blocks))
+
+    def local_energy(self, x, counts, offsets, logabs_x=None, phase_x=None, stream=None):
+        """Returns (eloc complex128 [U], sums float64 [n_mol, 4], n_pairs)."""
+        x = _dev(x, torch.int64)
+        n = x.numel()
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        eloc = torch.empty((max(n, 1), 2), dtype=torch.float64, device=x.device)
+        sums = torch.empty((self.n_mol, 4), dtype=torch.float64, device=x.device)
+        npairs = _i64()
+        _check(lib().batch_local_energy(self.handle, _ptr(x), _ptr(counts), _ptr(off),
+                                        _ptr(logabs_x), _ptr(phase_x), _ptr(eloc), _ptr(sums),
+                                        C.byref(npairs), _stream(stream)))
+        return torch.view_as_complex(eloc[:n]), sums, npairs.value
+
+    def stats(self, n_tune=12):
+        p, d, c = _i64(), _i64(), _i64()
+        tile = np.zeros(3, np.int32)
+        tm = np.zeros(n_tune, np.float64)
+        _check(lib().batch_stats(self.handle, C.byref(p), C.byref(d), C.byref(c), _ptr(tile),
+                                 _ptr(tm), n_tune))
+        return {"pairs": p.value, "distinct": d.value, "captures": c.value,
+                "tile": tile.tolist(), "tune_ms": tm.tolist()}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.batch_destroy(self.handle)
+            self.handle = None
+
+
+def vmc_weights_batch(eloc, counts, x, sums, stream=None):
+    er = torch.view_as_real(eloc).contiguous()
+    n = eloc.numel()
+    gl = torch.empty(n, dtype=torch.float64, device=eloc.device)
+    gp = torch.empty(n, dtype=torch.float64, device=eloc.device)
+    _check(lib().vmc_weights_batch(_ptr(er), _ptr(counts), _ptr(x), n, _ptr(sums),
+                                   sums.shape[0], _ptr(gl), _ptr(gp), _stream(stream)))
+    return gl, gp
 
 
 def connected_pairs(ham, x, capacity=None, stream=None):

@@ -1,0 +1,260 @@
+"""Many molecules sharing one transformer: parity of the batched path (tagged
+configuration words, one sampler tree per molecule, bit kernel with hash-table
+dedupe, graph-captured bf16 step) against the FP64 CPU oracle, molecule by
+molecule."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.hamiltonian import slater_condon_row
+from oracle.model import TransformerModel
+from oracle.sampler import sample_tree
+from oracle.sector import Sector
+from oracle.vmc import energy_stats, gradient, local_energies, surrogate_weights
+from synth import (BATCHING_MODEL, batching_molecules, batching_params, flatten_params,
+                   make_integrals, transformer_param_spec)
+
+pytestmark = pytest.mark.gpu
+
+C4 = BATCHING_MODEL
+SPEC = transformer_param_spec(C4["n"], C4["d"], C4["n_layers"], C4["ffn"], C4["phase_hidden"])
+DIMS = [C4["n"], 0, 0, C4["d"], C4["n_layers"], C4["n_heads"], C4["ffn"], C4["phase_hidden"]]
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    from paper_2310_04166_amd import nqs as mod
+    mod.lib()
+    return mod
+
+
+def small_molecules():
+    """Five molecules of the batching workload with n <= 10, fewer samples."""
+    mols = [m for m in batching_molecules() if m["n"] <= 10][:5]
+    for m in mols:
+        m["h"], m["eri"] = make_integrals(m["n"], m["rank"], m["seed"])
+        m["n_samples"] = 3000
+    return mols
+
+
+def k_closed_form(n, na, nb):
+    c2 = lambda a: a * (a - 1) // 2
+    return (na * (n - na) + nb * (n - nb) + c2(na) * c2(n - na) + c2(nb) * c2(n - nb)
+            + na * (n - na) * nb * (n - nb))
+
+
+def make(nqs, mols, precision, params=None):
+    params = batching_params() if params is None else params
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, DIMS, flatten_params(params, SPEC), precision)
+    hams = [nqs.ham_compile(mm["h"], mm["eri"], mm["n_alpha"], mm["n_beta"]) for mm in mols]
+    b = nqs.Batch(hams, m)
+    return m, b, params
+
+
+def oracle_model(params, mm):
+    return TransformerModel(params, Sector(mm["n"], mm["n_alpha"], mm["n_beta"]), C4["n_heads"])
+
+
+def split(x, offsets):
+    occ = (x & ((1 << 58) - 1)).cpu().numpy().view(np.uint64)
+    return [[int(v) for v in occ[offsets[i]:offsets[i + 1]]] for i in range(len(offsets) - 1)]
+
+
+def test_batch_sampler_replay_fp64(nqs):
+    """FP64 conditionals, one Philox stream per molecule: every molecule's
+    unique samples and counts equal the oracle tree sampler's, bit for bit."""
+    mols = small_molecules()
+    m, b, params = make(nqs, mols, "fp64")
+    x, c, off, lost = nqs.sample_unique_batch(m, [mm["n_samples"] for mm in mols], 21)
+    assert lost == 0
+    mol_of = ((x >> 58) & 63).cpu().numpy()
+    assert np.all(np.diff(mol_of) >= 0)
+    for i, mm in enumerate(mols):
+        cfg_o, cnt_o, _ = sample_tree(oracle_model(params, mm), mm["n_samples"], 21, stream=i)
+        got = split(x, off)[i]
+        log(f"molecule {i} n={mm['n']} ({mm['n_alpha']},{mm['n_beta']}): {len(got)} unique")
+        assert got == cfg_o
+        assert c[off[i]:off[i + 1]].cpu().tolist() == cnt_o
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 3e-2)])
+def test_batch_forward(nqs, precision, tol):
+    """Amplitudes of tagged configurations of molecules of 6..10 tokens."""
+    mols = small_molecules()
+    m, b, params = make(nqs, mols, precision)
+    rng = np.random.default_rng(5)
+    words, refs = [], []
+    for i, mm in enumerate(mols):
+        basis = Sector(mm["n"], mm["n_alpha"], mm["n_beta"]).enumerate()
+        xs = [basis[k] for k in rng.choice(len(basis), 40, replace=False)]
+        la, ph = oracle_model(params, mm).amplitudes(xs)
+        refs.append((la.detach().numpy(), ph.detach().numpy()))
+        words += [x | (i << 58) for x in xs]
+    xw = torch.as_tensor(np.asarray(words, dtype=np.uint64).view(np.int64)).cuda()
+    la, ph = nqs.amp_forward(m, xw)
+    la, ph = la.cpu().numpy(), ph.cpu().numpy()
+    want_la = np.concatenate([r[0] for r in refs])
+    want_ph = np.concatenate([r[1] for r in refs])
+    err = max(np.max(np.abs(la - want_la)), np.max(np.abs(ph - want_ph)))
+    log(f"batch forward {precision}: max err {err:.2e}")
+    assert err < tol
+
+
+def test_batch_local_energy_fp64(nqs):
+    """FP64 model: per-sample E_loc 1e-10 relative, pairs = sum U_i K_i with
+    the closed-form K_i, distinct x' = the union of the oracle's connected
+    sets (integer, exact), per-molecule sums."""
+    mols = small_molecules()[:3]
+    m, b, params = make(nqs, mols, "fp64")
+    k, _ = b.info()
+    assert [int(v) for v in k] == [k_closed_form(mm["n"], mm["n_alpha"], mm["n_beta"]) for mm in mols]
+    x, c, off, _ = nqs.sample_unique_batch(m, [mm["n_samples"] for mm in mols], 3)
+    eloc, sums, npairs = b.local_energy(x, c, off)
+    st = b.stats()
+    assert npairs == sum((off[i + 1] - off[i]) * k[i] for i in range(len(mols)))
+    occ = split(x, off)
+    got = eloc.cpu().numpy()
+    s = sums.cpu().numpy()
+    distinct = 0
+    for i, mm in enumerate(mols):
+        ref = oracle_model(params, mm)
+        xs = occ[i]
+        want = local_energies(ref, mm["h"], mm["eri"], xs)
+        g = got[off[i]:off[i + 1]]
+        err = np.max(np.abs(g - want) / np.abs(want))
+        log(f"molecule {i}: {len(xs)} samples, E_loc max rel err {err:.2e}")
+        assert err < 1e-10
+        cnt = c[off[i]:off[i + 1]].cpu().numpy()
+        W, E, _ = energy_stats(want, cnt)
+        assert s[i, 0] == W
+        assert abs(s[i, 1] / W - E.real) < 1e-10 * abs(E)
+        conn = set()
+        for xx in xs:
+            conn.update(slater_condon_row(mm["h"], mm["eri"], xx)[0][1:])
+        distinct += len(conn)
+    assert st["distinct"] == distinct
+
+
+@pytest.fixture(scope="module")
+def bf16_step(nqs):
+    mols = small_molecules()
+    m, b, params = make(nqs, mols, "bf16")
+    x, c, off, _ = nqs.sample_unique_batch(m, [mm["n_samples"] for mm in mols], 8)
+    return dict(m=m, b=b, params=params, mols=mols, x=x, c=c, off=off)
+
+
+def test_batch_graph_replays_match_direct_launches(nqs, bf16_step):
+    """The captured step, replayed three times with other GPU work in between,
+    gives bit-identical results to launching the same kernels directly."""
+    b, x, c, off = bf16_step["b"], bf16_step["x"], bf16_step["c"], bf16_step["off"]
+    b.set_mode(use_graph=False)
+    e0, s0, _ = b.local_energy(x, c, off)
+    e0, s0 = e0.clone(), s0.clone()
+    b.set_mode(use_graph=True)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        e, s, _ = b.local_energy(x, c, off)
+        assert torch.equal(e, e0) and torch.equal(s, s0), rep
+        assert torch.isfinite(junk)
+    st = b.stats()
+    log(f"graph: captures {st['captures']}, tile {st['tile']}, distinct {st['distinct']}")
+    assert st["captures"] >= 1
+
+
+def test_batch_tile_invariance(nqs, bf16_step):
+    """Launch shapes change only the speed: results are bitwise equal."""
+    b, x, c, off = bf16_step["b"], bf16_step["x"], bf16_step["c"], bf16_step["off"]
+    out = []
+    for tile in [(512, 2, 512), (2048, 16, 1024), (1024, 8, 256)]:
+        b.set_tile(*tile)
+        e, s, _ = b.local_energy(x, c, off)
+        out.append((e.clone(), s.clone()))
+    for e, s in out[1:]:
+        assert torch.equal(e, out[0][0]) and torch.equal(s, out[0][1])
+
+
+def test_batch_bf16_energy_vs_oracle(nqs, bf16_step):
+    """Mixed precision against the FP64 oracle on the same samples: per-sample
+    E_loc within the bf16 bound of the single-molecule path and the molecules'
+    energies within 1e-3 relative."""
+    b, x, c, off = bf16_step["b"], bf16_step["x"], bf16_step["c"], bf16_step["off"]
+    params, mols = bf16_step["params"], bf16_step["mols"]
+    eloc, sums, _ = b.local_energy(x, c, off)
+    occ = split(x, off)
+    got = eloc.cpu().numpy()
+    s = sums.cpu().numpy()
+    for i, mm in enumerate(mols):
+        want = local_energies(oracle_model(params, mm), mm["h"], mm["eri"], occ[i])
+        g = got[off[i]:off[i + 1]]
+        cnt = c[off[i]:off[i + 1]].cpu().numpy()
+        _, E, _ = energy_stats(want, cnt)
+        e_gpu = s[i, 1] / s[i, 0]
+        log(f"molecule {i}: E bf16 {e_gpu:.6f} oracle {E.real:.6f}; "
+            f"max |dE_loc| {np.max(np.abs(g - want)):.2e}")
+        assert np.max(np.abs(g - want)) < 5e-3 * max(1.0, np.max(np.abs(want)))
+        assert abs(e_gpu - E.real) < 1e-3 * abs(E.real)
+
+
+def test_batch_weights_and_backward_fp64(nqs):
+    """Per-molecule upstream weights and the shared model's gradient of the sum
+    of the molecules' energies, against the oracle's autograd."""
+    mols = small_molecules()[:3]
+    params = batching_params()
+    m, b, _ = make(nqs, mols, "fp64", params)
+    x, c, off, _ = nqs.sample_unique_batch(m, [400, 300, 500], 4)
+    eloc, sums, _ = b.local_energy(x, c, off)
+    gl, gp = nqs.vmc_weights_batch(eloc, c, x, sums)
+    g = nqs.amp_backward(m, x, gl, gp).double().cpu().numpy()
+    occ = split(x, off)
+    el = eloc.cpu().numpy()
+    g_ref = np.zeros_like(g)
+    for i, mm in enumerate(mols):
+        cnt = c[off[i]:off[i + 1]].cpu().numpy()
+        e = el[off[i]:off[i + 1]]
+        rl, rp = surrogate_weights(cnt, e)
+        assert np.max(np.abs(gl[off[i]:off[i + 1]].cpu().numpy() - rl)) < 1e-14
+        assert np.max(np.abs(gp[off[i]:off[i + 1]].cpu().numpy() - rp)) < 1e-14
+        ref = TransformerModel(params, Sector(mm["n"], mm["n_alpha"], mm["n_beta"]),
+                               C4["n_heads"], requires_grad=True)
+        g_ref += gradient(ref, occ[i], cnt, e, SPEC)
+    err = np.max(np.abs(g - g_ref))
+    log(f"batch backward: max|g| {np.max(np.abs(g_ref)):.3e} err {err:.3e}")
+    assert err < 1e-10 * np.max(np.abs(g_ref))
+
+
+def test_batch_full_workload(nqs):
+    """All 64 molecules (12..28 spin-orbitals) in one graph-captured bf16 step:
+    sizes exact, every molecule's energy finite and variational-looking, and a
+    few samples of every fifth molecule against the FP64 oracle."""
+    from synth import batching_workload
+    mols, params = batching_workload()
+    m, b, _ = make(nqs, mols, "bf16", params)
+    x, c, off, lost = nqs.sample_unique_batch(m, [mm["n_samples"] for mm in mols], 1)
+    assert lost == 0
+    k, _ = b.info()
+    eloc, sums, npairs = b.local_energy(x, c, off)
+    e2, s2, _ = b.local_energy(x, c, off)           # a replay of the captured step
+    assert torch.equal(eloc, e2) and torch.equal(sums, s2)
+    u = np.diff(off)
+    assert npairs == int(np.sum(u * k))
+    for i, mm in enumerate(mols):
+        assert int(c[off[i]:off[i + 1]].sum()) == mm["n_samples"]
+    st = b.stats()
+    log(f"64 molecules: unique {off[-1]} (min {u.min()}, max {u.max()}), pairs {npairs}, "
+        f"distinct {st['distinct']}, tile {st['tile']}")
+    s = sums.cpu().numpy()
+    assert np.all(np.isfinite(s))
+    occ = split(x, off)
+    got = eloc.cpu().numpy()
+    for i in range(0, len(mols), 5):
+        mm = mols[i]
+        pick = np.argsort(-c[off[i]:off[i + 1]].cpu().numpy())[:2]
+        xs = [occ[i][j] for j in pick]
+        want = local_energies(oracle_model(params, mm), mm["h"], mm["eri"], xs)
+        g = got[off[i]:off[i + 1]][pick]
+        assert np.max(np.abs(g - want)) < 5e-3 * max(1.0, np.max(np.abs(want))), i
