@@ -347,12 +347,13 @@ int batch_set_mode(nqs_batch *b, int use_graph, int retune);
  * blocks.  Results do not depend on the shape. */
 int batch_set_tile(nqs_batch *b, int pairs_blocks, int fused_pairs, int fused_blocks);
 
-/* Last call's pairs and distinct x', the number of graph captures so far, the
- * chosen launch shape tile[3] = {bit-kernel blocks, fused pairs per chunk,
- * fused blocks} and the tuner's candidate timings in ms (first n_tune).  Any
- * output may be NULL. */
-int batch_stats(const nqs_batch *b, int64_t *n_pairs, int64_t *n_distinct, int64_t *captures,
-                int32_t *tile, double *tune_ms, int n_tune);
+/* Last call's pairs, distinct x' (total and per molecule, host array of
+ * n_mol), the number of graph captures so far, the chosen launch shape
+ * tile[3] = {bit-kernel blocks, fused pairs per chunk, fused blocks} and the
+ * tuner's candidate timings in ms (first n_tune).  Any output may be NULL. */
+int batch_stats(const nqs_batch *b, int64_t *n_pairs, int64_t *n_distinct,
+                int64_t *distinct_per_mol, int64_t *captures, int32_t *tile, double *tune_ms,
+                int n_tune);
 
 /*
  * vmc_weights_batch - vmc_weights per molecule for the gradient of the sum of
@@ -372,7 +373,9 @@ int vmc_weights_batch(const double *eloc, const uint64_t *counts, const uint64_t
 /*
  * Kernel timing of the dominant kernel (the fused bf16 amplitude kernel).
  * While enabled, every launch of it is bracketed by two HIP events recorded on
- * the launch's own stream.  nqs_timing_read synchronises those events and
+ * the launch's own stream (in batch_local_energy: by two events inside the
+ * step's launch sequence, read after the call; its launches on the samples
+ * are not recorded).  nqs_timing_read synchronises those events and
  * returns the summed kernel time in milliseconds, the number of launches and
  * the number of configurations they evaluated, then clears the record.
  * Not thread-safe; intended for benchmarks.

@@ -252,6 +252,27 @@ __global__ void __launch_bounds__(256) reduce_kernel(const StepDesc *__restrict_
   if (threadIdx.x < 4) sums[4 * i + threadIdx.x] = part[threadIdx.x][0];
 }
 
+// distinct x' per molecule (from the tags of the distinct list)
+__global__ void count_mol_kernel(const uint64_t *__restrict__ ukeys,
+                                 const Counters *__restrict__ ctr, int n_mol,
+                                 unsigned long long *__restrict__ per_mol) {
+  __shared__ unsigned long long local[kMaxMol];
+  if (threadIdx.x < kMaxMol) local[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = ctr->distinct;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int m = int(ukeys[i] >> kTagShift);
+    if (m < n_mol) atomicAdd(&local[m], 1ull);
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < n_mol && local[threadIdx.x]) atomicAdd(&per_mol[threadIdx.x], local[threadIdx.x]);
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0;
+}
+
 // Upstream weights of the summed energy of the molecules: sample s of molecule
 // i gets 2 n_s / W_i (E_loc,s - E_i), split into real and imaginary parts.
 __global__ void weights_kernel(const double *__restrict__ eloc, const uint64_t *__restrict__ counts,
@@ -302,13 +323,18 @@ struct nqs_batch {
   bool tuned = false, use_graph = true;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the distinct-x' amplitude launch
   bool graph_has_psi_x = false;
   // statistics of the last step
   int64_t last_pairs = 0, last_distinct = 0, captures = 0;
+  std::vector<int64_t> distinct_per_mol;
+  DevBuf per_mol;
   std::vector<double> tune_ms;     // candidate timings of the last tuning
 
   ~nqs_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (desc_host) (void)hipHostFree(desc_host);
   }
@@ -373,8 +399,10 @@ void enqueue(nqs_batch &b, bool psi_x, hipStream_t s) {
   if (psi_x)
     fused_forward(m, b.x.as<uint64_t>(), b.u_cap, b.lax.as<double>(), b.phx.as<double>(), nullptr,
                   -1, s, &desc->U, b.x_tile);
+  HIP_OK(hipEventRecord(b.ev0, s));
   fused_forward(m, b.ukeys.as<uint64_t>(), b.p_cap, b.la.as<double>(), b.ph.as<double>(), nullptr,
                 -1, s, &ctr->distinct, b.xp_tile);
+  HIP_OK(hipEventRecord(b.ev1, s));
   hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(b.acc_blocks)), dim3(256), 0, s, desc,
                      b.tabs.as<MolTab>(), b.x.as<uint64_t>(), b.n_mol, b.slot.as<uint32_t>(),
                      b.ids.as<uint32_t>(), b.hval.as<double>(), b.la.as<double>(),
@@ -553,6 +581,8 @@ extern "C" int batch_create(nqs_ham *const *hams, int n_mol, nqs_model *model, n
     b->ctr.reserve(sizeof(Counters));
     HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&b->desc_host), sizeof(StepDesc),
                          hipHostMallocDefault));
+    HIP_OK(hipEventCreate(&b->ev0));
+    HIP_OK(hipEventCreate(&b->ev1));
     *out = b.release();
   });
 }
@@ -677,6 +707,15 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
                          b->eloc.as<double>(), b->cnt.as<uint64_t>(), b->sums.as<double>());
       HIP_LAUNCH_OK();
     }
+    auto *per_mol = static_cast<unsigned long long *>(b->per_mol.reserve(kMaxMol * 8));
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kMaxMol), 0, s, per_mol, kMaxMol);
+    HIP_LAUNCH_OK();
+    hipLaunchKernelGGL(count_mol_kernel, dim3(256), dim3(256), 0, s, b->ukeys.as<uint64_t>(),
+                       b->ctr.as<Counters>(), b->n_mol, per_mol);
+    HIP_LAUNCH_OK();
+    b->distinct_per_mol.assign(size_t(b->n_mol), 0);
+    HIP_OK(hipMemcpyAsync(b->distinct_per_mol.data(), per_mol, size_t(b->n_mol) * 8,
+                          hipMemcpyDeviceToHost, s));
     Counters c{};
     HIP_OK(hipMemcpyAsync(&c, b->ctr.ptr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     if (U > 0)
@@ -684,6 +723,11 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
     HIP_OK(hipMemcpyAsync(sums, b->sums.ptr, size_t(b->n_mol) * 32, hipMemcpyDeviceToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
     b->last_distinct = c.distinct;
+    if (m.precision == NQS_BF16 && U > 0 && timing_on()) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+      timing_add(ms, c.distinct);
+    }
     NQS_REQUIRE(c.overflow == 0, NQS_EINVAL,
                 "batch_local_energy: a configuration's molecule disagrees with the offsets, or it "
                 "had more connected x' than its molecule's K, or the distinct-x' table overflowed");
@@ -691,9 +735,13 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
 }
 
 extern "C" int batch_stats(const nqs_batch *b, int64_t *n_pairs, int64_t *n_distinct,
-                           int64_t *captures, int32_t *tile, double *tune_ms, int n_tune) {
+                           int64_t *distinct_per_mol, int64_t *captures, int32_t *tile,
+                           double *tune_ms, int n_tune) {
   return guarded([&] {
     NQS_REQUIRE(b, NQS_EINVAL, "batch_stats: null handle");
+    if (distinct_per_mol)
+      for (int i = 0; i < b->n_mol; ++i)
+        distinct_per_mol[i] = size_t(i) < b->distinct_per_mol.size() ? b->distinct_per_mol[size_t(i)] : 0;
     if (n_pairs) *n_pairs = b->last_pairs;
     if (n_distinct) *n_distinct = b->last_distinct;
     if (captures) *captures = b->captures;

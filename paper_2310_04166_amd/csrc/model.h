@@ -113,6 +113,10 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
                    double *cond_out, int cond_p, hipStream_t s, const int64_t *count = nullptr,
                    FusedTile tile = FusedTile{});
 void fused_pack(nqs_model &m, hipStream_t s);
+// Kernel timing of the fused kernel (nqs_timing_*): whether it is on, and a
+// record measured by a caller (events inside a captured graph).
+bool timing_on();
+void timing_add(float ms, int64_t configs);
 bool fused_supported(const nqs_model &m);
 
 }  // namespace nqs

@@ -40,8 +40,9 @@ typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 struct TimingRecord {
-  hipEvent_t start, stop;
+  hipEvent_t start, stop;           // null for a record measured elsewhere (ms set)
   int64_t configs;
+  float ms;
 };
 bool g_timing = false;
 std::vector<TimingRecord> g_records;
@@ -747,9 +748,13 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   HIP_LAUNCH_OK();
   if (g_timing && !count) {
     HIP_OK(hipEventRecord(e1, s));
-    g_records.push_back({e0, e1, B});
+    g_records.push_back({e0, e1, B, 0.f});
   }
 }
+
+bool timing_on() { return g_timing; }
+
+void timing_add(float ms, int64_t configs) { g_records.push_back({nullptr, nullptr, configs, ms}); }
 
 }  // namespace nqs
 
@@ -764,9 +769,11 @@ extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) 
     double total = 0.0;
     int64_t cfgs = 0;
     for (const TimingRecord &r : g_records) {
-      HIP_OK(hipEventSynchronize(r.stop));
-      float t = 0.f;
-      HIP_OK(hipEventElapsedTime(&t, r.start, r.stop));
+      float t = r.ms;
+      if (r.stop) {
+        HIP_OK(hipEventSynchronize(r.stop));
+        HIP_OK(hipEventElapsedTime(&t, r.start, r.stop));
+      }
       total += t;
       cfgs += r.configs;
     }
@@ -774,8 +781,8 @@ extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) 
     if (launches) *launches = int64_t(g_records.size());
     if (configs) *configs = cfgs;
     for (const TimingRecord &r : g_records) {
-      (void)hipEventDestroy(r.start);
-      (void)hipEventDestroy(r.stop);
+      if (r.start) (void)hipEventDestroy(r.start);
+      if (r.stop) (void)hipEventDestroy(r.stop);
     }
     g_records.clear();
   });

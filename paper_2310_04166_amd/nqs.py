@@ -67,8 +67,8 @@ _SIGS = {
                            C.c_int),
     "batch_set_mode": ([_vp, C.c_int, C.c_int], C.c_int),
     "batch_set_tile": ([_vp, C.c_int, C.c_int, C.c_int], C.c_int),
-    "batch_stats": ([_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), _vp, _vp, C.c_int],
-                    C.c_int),
+    "batch_stats": ([_vp, C.POINTER(_i64), C.POINTER(_i64), _vp, C.POINTER(_i64), _vp, _vp,
+                     C.c_int], C.c_int),
     "vmc_weights_batch": ([_vp, _vp, _vp, _i64, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "nqs_timing_enable": ([C.c_int], C.c_int),
     "nqs_timing_read": ([C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
@@ -303,12 +303,13 @@ class Batch:
 
     def stats(self, n_tune=12):
         p, d, c = _i64(), _i64(), _i64()
+        per = np.zeros(self.n_mol, np.int64)
         tile = np.zeros(3, np.int32)
         tm = np.zeros(n_tune, np.float64)
-        _check(lib().batch_stats(self.handle, C.byref(p), C.byref(d), C.byref(c), _ptr(tile),
-                                 _ptr(tm), n_tune))
-        return {"pairs": p.value, "distinct": d.value, "captures": c.value,
-                "tile": tile.tolist(), "tune_ms": tm.tolist()}
+        _check(lib().batch_stats(self.handle, C.byref(p), C.byref(d), _ptr(per), C.byref(c),
+                                 _ptr(tile), _ptr(tm), n_tune))
+        return {"pairs": p.value, "distinct": d.value, "distinct_per_mol": per,
+                "captures": c.value, "tile": tile.tolist(), "tune_ms": tm.tolist()}
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

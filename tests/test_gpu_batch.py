@@ -136,6 +136,7 @@ def test_batch_local_energy_fp64(nqs):
         for xx in xs:
             conn.update(slater_condon_row(mm["h"], mm["eri"], xx)[0][1:])
         distinct += len(conn)
+        assert st["distinct_per_mol"][i] == len(conn)
     assert st["distinct"] == distinct
 
 
