@@ -70,6 +70,7 @@ struct FusedArgs {
   const int64_t *count;             // optional device-side count (persistent launches)
   int n, L, cond_p;                 // n = positions of the model
   int pairs;                        // passes per chunk (configurations per chunk / 2), <= 16
+  int lds_floats;                   // vec[0 .. lds_floats) is staged in LDS (all but pw1)
   double *logabs, *phase, *cond;
 };
 
@@ -134,14 +135,28 @@ __device__ inline bf16x8 pack8(const float (&v)[8]) {
   return r;
 }
 
-struct View;
-__device__ inline f32x16 vec16_at(const View &v, uint32_t byte_off);
+
+// 16 consecutive floats from LDS
+__device__ inline f32x16 lds16(const float *p) {
+  const f32x4 *q = reinterpret_cast<const f32x4 *>(p);
+  const f32x4 a = q[0], b = q[1], c = q[2], d = q[3];
+  f32x16 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = a[i];
+    r[4 + i] = b[i];
+    r[8 + i] = c[i];
+    r[12 + i] = d[i];
+  }
+  return r;
+}
 
 // Layer norm of the feature-major residual into a bf16 operand; gain and shift
-// are permuted vectors read through V (byte offsets g_off, b_off).
+// are permuted vectors in LDS at V + g_off / V + b_off (V includes the lane
+// half's offset), 32 floats per accumulator block.
 template <int NB>
-__device__ inline void layer_norm(const f32x16 (&res)[NB], const View &V, uint32_t g_off,
-                                  uint32_t b_off, bf16x8 (&X)[2 * NB]) {
+__device__ inline void layer_norm(const f32x16 (&res)[NB], const float *V, int g_off, int b_off,
+                                  bf16x8 (&X)[2 * NB]) {
   float s = 0.f, s2 = 0.f;
 #pragma unroll
   for (int q = 0; q < NB; ++q)
@@ -156,7 +171,7 @@ __device__ inline void layer_norm(const f32x16 (&res)[NB], const View &V, uint32
   const float rs = rsqrtf(fmaxf(s2 * (1.0f / (32 * NB)) - mu * mu, 0.f) + 1e-5f);
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const f32x16 gg = vec16_at(V, g_off + q * 128), bb = vec16_at(V, b_off + q * 128);
+    const f32x16 gg = lds16(V + g_off + q * 32), bb = lds16(V + b_off + q * 32);
     f32x16 y;
 #pragma unroll
     for (int j = 0; j < 16; ++j) y[j] = fmaf((res[q][j] - mu) * rs, gg[j], bb[j]);
@@ -201,18 +216,6 @@ __device__ inline bf16x8 frag_at(const View &v, uint32_t byte_off) {
   return __builtin_bit_cast(bf16x8,
                             __builtin_amdgcn_raw_buffer_load_b128(v.rsrc, v.voff, byte_off, 0));
 }
-__device__ inline f32x16 vec16_at(const View &v, uint32_t byte_off) {
-  f32x16 r;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const f32x4 q = __builtin_bit_cast(
-        f32x4, __builtin_amdgcn_raw_buffer_load_b128(v.rsrc, v.voff, byte_off + 16 * c, 0));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r[4 * c + i] = q[i];
-  }
-  return r;
-}
-
 // W = the layer's fragments (voff = 16 * lane); s = step index; fragments
 // half * KS/2 .. half * KS/2 + KS/2 - 1 of the step go to f[0 .. KS/2)
 template <int D>
@@ -257,6 +260,16 @@ fused_kernel(FusedArgs a) {
   using S = Shape<D>;
   constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
   const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
+  // The permuted fp32 vectors (biases, layer-norm parameters, head, embeddings)
+  // are read by every lane at the same few addresses; they are staged in LDS
+  // once per block so that the vector memory path carries only the weights.
+  extern __shared__ f32x4 s_vec4[];
+  {
+    const f32x4 *src = reinterpret_cast<const f32x4 *>(a.vec);
+    for (int i = int(threadIdx.x); i < a.lds_floats / 4; i += int(blockDim.x)) s_vec4[i] = src[i];
+    __syncthreads();
+  }
+  const float *svec = reinterpret_cast<const float *>(s_vec4);
   // wave index, explicitly wave-uniform so the chunk loop stays a scalar loop
   const int64_t group = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64));
   // a persistent launch reads the number of configurations from the device
@@ -275,7 +288,7 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) madd[i] = ((i / 4) * 8 + h * 4 + (i % 4)) <= t ? 0.f : -INFINITY;
 
-  constexpr uint32_t kFragBytes = uint32_t(S::FRAG_L * 16), kVecBytes = uint32_t(S::VEC_L * 4);
+  constexpr uint32_t kFragBytes = uint32_t(S::FRAG_L * 16);
   auto wview = [&](int l) {
     return make_view(a.pk + int64_t(l) * S::FRAG_L, kFragBytes, uint32_t(lane) * 16u);
   };
@@ -299,36 +312,36 @@ fused_kernel(FusedArgs a) {
       const bool pad = t >= n;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const f32x16 te = load16(vec + a.tok + in * D + (q * 2 + h) * 16);
-        const f32x16 pe = pad ? f32x16{} : load16(vec + a.pos + t * D + (q * 2 + h) * 16);
+        const f32x16 te = lds16(svec + a.tok + in * D + (q * 2 + h) * 16);
+        const f32x16 pe = pad ? f32x16{} : lds16(svec + a.pos + t * D + (q * 2 + h) * 16);
         res[q] = te + pe;
       }
     }
 
     for (int l = 0; l < a.L; ++l) {
       const View W = wview(l), Wn = wview(l + 1 < a.L ? l + 1 : 0);
-      // permuted vectors of the layer: lane-half h reads 16 floats at (2q+h)*16
-      const View V16 = make_view(vec + int64_t(l) * S::VEC_L, kVecBytes, uint32_t(h) * 64u);
-      const float *lv = vec + int64_t(l) * S::VEC_L;
+      // permuted vectors of the layer (LDS): lane-half h reads 16 floats at (2q+h)*16
+      const float *lv = svec + l * int(S::VEC_L);
+      const float *V16 = lv + h * 16;
       bf16x8 X[KS];
       // The weight stream advances in half steps of HS fragments through the
       // two buffers fr[0] / fr[1]: while one half is multiplied the next half
       // is loaded.  On entry fr[0] holds half 0 of step 0 of this layer.
       // ---- attention block
-      layer_norm<NB>(res, V16, uint32_t(S::VLN1G * 4), uint32_t(S::VLN1B * 4), X);
+      layer_norm<NB>(res, V16, int(S::VLN1G), int(S::VLN1B), X);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VBO + q * 32) * 4));
+      for (int q = 0; q < NB; ++q) res[q] += lds16(V16 + S::VBO + q * 32);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O); halves alternate fr[0], fr[1]
-        f32x16 Qc = vec16_at(V16, uint32_t((S::VBQ + b * 32) * 4));
+        f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
         load_half<D>(fr[1], W, 4 * b, 1);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
         load_half<D>(fr[0], W, 4 * b + 1, 0);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
-        f32x16 Kc = vec16_at(V16, uint32_t((S::VBK + b * 32) * 4));
+        f32x16 Kc = lds16(V16 + S::VBK + b * 32);
         load_half<D>(fr[1], W, 4 * b + 1, 1);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
@@ -393,13 +406,13 @@ fused_kernel(FusedArgs a) {
           res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]);
       }
       // ---- feed-forward block: step 4NB + 2fb = W1, +1 = W2
-      layer_norm<NB>(res, V16, uint32_t(S::VLN2G * 4), uint32_t(S::VLN2B * 4), X);
+      layer_norm<NB>(res, V16, int(S::VLN2G), int(S::VLN2B), X);
 #pragma unroll
-      for (int q = 0; q < NB; ++q) res[q] += vec16_at(V16, uint32_t((S::VB2 + q * 32) * 4));
+      for (int q = 0; q < NB; ++q) res[q] += lds16(V16 + S::VB2 + q * 32);
 #pragma unroll
       for (int fb = 0; fb < FB; ++fb) {
         const int s = 4 * NB + 2 * fb;
-        f32x16 Hc = vec16_at(V16, uint32_t((S::VB1 + fb * 32) * 4));
+        f32x16 Hc = lds16(V16 + S::VB1 + fb * 32);
         load_half<D>(fr[1], W, s, 1);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
@@ -440,9 +453,9 @@ fused_kernel(FusedArgs a) {
       const float rs = rsqrtf(fmaxf(s2 * (1.0f / D) - mu * mu, 0.f) + 1e-5f);
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const f32x16 gg = load16(vec + a.lnfg + (q * 2 + h) * 16);
-        const f32x16 bb = load16(vec + a.lnfb + (q * 2 + h) * 16);
-        const f32x4 *wh = reinterpret_cast<const f32x4 *>(vec + a.whead) + (q * 2 + h) * 16;
+        const f32x16 gg = lds16(svec + a.lnfg + (q * 2 + h) * 16);
+        const f32x16 bb = lds16(svec + a.lnfb + (q * 2 + h) * 16);
+        const f32x4 *wh = reinterpret_cast<const f32x4 *>(svec + a.whead) + (q * 2 + h) * 16;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const float y = fmaf((res[q][j] - mu) * rs, gg[j], bb[j]);
@@ -459,7 +472,7 @@ fused_kernel(FusedArgs a) {
     float logp = 0.f;
     if (t < n) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) lg[k] += vec[a.bhead + k] + vec[a.lbias + t * 4 + k];
+      for (int k = 0; k < 4; ++k) lg[k] += svec[a.bhead + k] + svec[a.lbias + t * 4 + k];
       if (a.cond && t == a.cond_p && h == 0 && live) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
@@ -501,7 +514,7 @@ fused_kernel(FusedArgs a) {
     bf16x8 Z[PKS];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
-      f32x16 z = load16(vec + a.pb1 + (b * 2 + h) * 16);
+      f32x16 z = lds16(svec + a.pb1 + (b * 2 + h) * 16);
       for (int tt = 0; tt < nx; ++tt) {
         const int row = 4 * tt + int((x >> (2 * tt)) & 3ull);
         z += load16(vec + a.pw1 + int64_t(row) * PH + (b * 2 + h) * 16);
@@ -513,16 +526,16 @@ fused_kernel(FusedArgs a) {
     }
     float ph = 0.f;
     for (int b = 0; b < PB; ++b) {
-      f32x16 z = load16(vec + a.pb2 + (b * 2 + h) * 16);
+      f32x16 z = lds16(svec + a.pb2 + (b * 2 + h) * 16);
       const bf16x8 *w = pk + a.p2 + int64_t(b) * PKS * 64;
 #pragma unroll
       for (int s = 0; s < PKS; ++s) z = mfma(w[s * 64], Z[s], z);
-      const f32x16 w3 = load16(vec + a.pw3 + (b * 2 + h) * 16);
+      const f32x16 w3 = lds16(svec + a.pw3 + (b * 2 + h) * 16);
 #pragma unroll
       for (int j = 0; j < 16; ++j) ph = fmaf(gelu(z[j]), w3[j], ph);
     }
     ph = pair_sum(ph);
-    if (h == 0 && live) a.phase[cfg] = double(ph + vec[a.pb3]);
+    if (h == 0 && live) a.phase[cfg] = double(ph + svec[a.pb3]);
   }
   }  // chunk
 }
@@ -731,6 +744,19 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   a.pairs = int(std::min<int64_t>(kPairs, std::max<int64_t>(1, ceil_div(B, 2 * target_waves))));
   if (tile.pairs > 0) a.pairs = std::min(tile.pairs, kPairs);
   a.count = count;
+  a.lds_floats = int(L.a.pw1);   // every vector before the phase-MLP input table
+  const size_t lds_bytes = size_t(a.lds_floats) * 4;
+  // two blocks per CU must fit the 160 KiB of LDS
+  NQS_REQUIRE(lds_bytes <= 80 * 1024, NQS_EUNSUPPORTED,
+              "fused forward: model vectors exceed the LDS budget");
+  if (lds_bytes > 64 * 1024) {
+    if (m.d == 128)
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<128>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
+    else
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<64>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
+  }
   const int64_t groups = ceil_div(B, 2 * a.pairs);
   int64_t blocks = ceil_div(groups, 4);
   if (tile.blocks > 0) blocks = std::min<int64_t>(blocks, tile.blocks);
@@ -742,9 +768,9 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
     HIP_OK(hipEventRecord(e0, s));
   }
   if (m.d == 128)
-    hipLaunchKernelGGL(fused_kernel<128>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(fused_kernel<128>, grid, dim3(256), lds_bytes, s, a);
   else
-    hipLaunchKernelGGL(fused_kernel<64>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(fused_kernel<64>, grid, dim3(256), lds_bytes, s, a);
   HIP_LAUNCH_OK();
   if (g_timing && !count) {
     HIP_OK(hipEventRecord(e1, s));
