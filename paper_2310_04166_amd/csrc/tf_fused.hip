@@ -199,59 +199,66 @@ struct Shape {
                            VB2 = 8 * D + F, VEC_L = 9 * D + F;
 };
 
-// Per-layer slices are read through buffer resources: the layer's base goes
-// into the resource, the lane's part of the address into a fixed VGPR and the
+// Per-layer weight slices are read through buffer resources: the layer's base
+// goes into the resource, the lane's part of the address into a VGPR and the
 // compile-time offset into the scalar offset, so no 64-bit addresses stay live.
-struct View {
-  __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t voff;
-};
 typedef __attribute__((ext_vector_type(4))) int i32x4;
-
-__device__ inline View make_view(const void *base, uint32_t bytes, uint32_t voff) {
-  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000),
-          voff};
-}
-__device__ inline bf16x8 frag_at(const View &v, uint32_t byte_off) {
-  return __builtin_bit_cast(bf16x8,
-                            __builtin_amdgcn_raw_buffer_load_b128(v.rsrc, v.voff, byte_off, 0));
-}
-// W = the layer's fragments (voff = 16 * lane); s = step index; fragments
-// half * KS/2 .. half * KS/2 + KS/2 - 1 of the step go to f[0 .. KS/2)
+// The four waves of a block stream the same weight fragments.  Each step is
+// loaded once per block into a ring of three LDS slots (one step, KS
+// fragments of 1 KiB, each): wave w loads fragments w, w + 4, ... of the step
+// after next into registers, stores the next step's share into its slot, and
+// a block barrier publishes it.  The MFMAs read their fragments from LDS.
+//
+// The wave-dependent part of a fragment's address depends only on the kind
+// of step, so it sits in three per-lane offsets (voff[kind]); the rest is a
+// compile-time constant of (step, j).
+struct StageOff {
+  uint32_t v[3];   // bytes: lane * 16 + wave part for Q/K/V/W1, output projection, W2
+};
 template <int D>
-__device__ inline void load_half(bf16x8 (&f)[Shape<D>::KS / 2], const View &W, int s, int half) {
+__device__ inline StageOff stage_offsets(int lane, int wv) {
+  using S = Shape<D>;
+  const uint32_t l = uint32_t(lane) * 16u;
+  return {{l + uint32_t(wv) * 1024u, l + uint32_t((wv / 2) * S::KS + wv % 2) * 1024u,
+           l + uint32_t((wv / 2) * S::FKS + wv % 2) * 1024u}};
+}
+template <int D>
+__device__ inline void stage_load(bf16x8 (&st)[Shape<D>::KS / 4], __amdgpu_buffer_rsrc_t W,
+                                  const StageOff &vo, int s) {
   using S = Shape<D>;
   constexpr int KS = S::KS;
-  int64_t base;
-  int kind;
-  if (s < 4 * S::NB) {
-    const int b = s / 4;
-    kind = s % 4;
-    base = kind == 0 ? S::OQ + int64_t(b) * KS * 64
-         : kind == 1 ? S::OK + int64_t(b) * KS * 64
-         : kind == 2 ? S::OV + int64_t(b) * KS * 64
-                     : S::OO + int64_t(2 * b) * 64;
-    kind = kind == 3 ? 1 : 0;
-  } else {
-    const int fb = (s - 4 * S::NB) / 2;
-    if ((s - 4 * S::NB) % 2 == 0) {
-      base = S::OW1 + int64_t(fb) * KS * 64;
-      kind = 0;
-    } else {
-      base = S::OW2 + int64_t(2 * fb) * 64;
-      kind = 2;
-    }
-  }
 #pragma unroll
-  for (int ii = 0; ii < KS / 2; ++ii) {
-    // kind 0: KS consecutive k-steps of one output block; kind 1 (output
-    // projection) / 2 (second FFN layer): output block i/2, k-step 2b + i%2
-    const int i = half * (KS / 2) + ii;
-    const int64_t o = kind == 0 ? int64_t(i) * 64
-                    : kind == 1 ? (int64_t(i / 2) * KS + (i % 2)) * 64
-                                : (int64_t(i / 2) * S::FKS + (i % 2)) * 64;
-    f[ii] = frag_at(W, uint32_t((base + o) * 16));
+  for (int j = 0; j < KS / 4; ++j) {
+    int kind;
+    int64_t off;   // fragment f = wv + 4 j without the wave part
+    if (s < 4 * S::NB) {
+      const int b = s / 4;
+      kind = s % 4 == 3 ? 1 : 0;
+      off = s % 4 == 3 ? S::OO + (int64_t(2 * b) + int64_t(2 * j) * KS) * 64
+          : (s % 4 == 0 ? S::OQ : s % 4 == 1 ? S::OK : S::OV) + int64_t(b) * KS * 64 + int64_t(4 * j) * 64;
+    } else {
+      const int fb = (s - 4 * S::NB) / 2;
+      const bool w1 = (s - 4 * S::NB) % 2 == 0;
+      kind = w1 ? 0 : 2;
+      off = w1 ? S::OW1 + int64_t(fb) * KS * 64 + int64_t(4 * j) * 64
+               : S::OW2 + (int64_t(2 * fb) + int64_t(2 * j) * S::FKS) * 64;
+    }
+    st[j] = __builtin_bit_cast(
+        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, vo.v[kind], uint32_t(off * 16), 0));
   }
+}
+template <int D>
+__device__ inline void stage_store(bf16x8 *slot, const bf16x8 (&st)[Shape<D>::KS / 4], int wv,
+                                   int lane) {
+#pragma unroll
+  for (int j = 0; j < Shape<D>::KS / 4; ++j) slot[(wv + 4 * j) * 64 + lane] = st[j];
+}
+// fragments half * KS/2 .. half * KS/2 + KS/2 - 1 of the step in `slot`
+template <int D>
+__device__ inline void fetch_half(bf16x8 (&f)[Shape<D>::KS / 2], const bf16x8 *slot, int half,
+                                  int lane) {
+#pragma unroll
+  for (int ii = 0; ii < Shape<D>::KS / 2; ++ii) f[ii] = slot[(half * (Shape<D>::KS / 2) + ii) * 64 + lane];
 }
 
 template <int D>
@@ -270,12 +277,18 @@ fused_kernel(FusedArgs a) {
     __syncthreads();
   }
   const float *svec = reinterpret_cast<const float *>(s_vec4);
-  // wave index, explicitly wave-uniform so the chunk loop stays a scalar loop
-  const int64_t group = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64));
+  bf16x8 *ring = reinterpret_cast<bf16x8 *>(s_vec4 + a.lds_floats / 4);
+  constexpr int RS = KS * 64;        // one ring slot, in bf16x8 entries
+  // wave of the block, explicitly wave-uniform so the loops stay scalar
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64));
   // a persistent launch reads the number of configurations from the device
   const int64_t B = a.count ? (*a.count < a.B ? *a.count : a.B) : a.B;
-  if (group * 2 * a.pairs >= B) return;
-  const int64_t n_groups = int64_t(gridDim.x) * 4;
+  // All four waves of a block take part in every barrier of the weight
+  // stream, so the loops are uniform over the block: a block owns chunks of
+  // 4 x 2 x pairs configurations (wave w the w-th quarter) and a wave whose
+  // configurations run out computes on empty rows and writes nothing.
+  const int64_t block_cfgs = int64_t(8) * a.pairs;
+  if (int64_t(blockIdx.x) * block_cfgs >= B) return;
   const int t = r % kSeq;            // position of this lane's row
   const bool upper = r >= kSeq;      // second configuration of the pair
   const int n = a.n;
@@ -289,19 +302,37 @@ fused_kernel(FusedArgs a) {
   for (int i = 0; i < 8; ++i) madd[i] = ((i / 4) * 8 + h * 4 + (i % 4)) <= t ? 0.f : -INFINITY;
 
   constexpr uint32_t kFragBytes = uint32_t(S::FRAG_L * 16);
-  auto wview = [&](int l) {
-    return make_view(a.pk + int64_t(l) * S::FRAG_L, kFragBytes, uint32_t(lane) * 16u);
+  auto wres = [&](int l) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16x8 *>(a.pk + int64_t(l) * S::FRAG_L),
+                                             0, int(kFragBytes), 0x00020000);
   };
+  const StageOff vo = stage_offsets<D>(lane, wv);
   constexpr int HS = KS / 2;
   bf16x8 fr[2][HS];
-  load_half<D>(fr[0], wview(0), 0, 0);
+  bf16x8 staged[KS / 4];
+  int cur = 0;                       // ring slot of the current step
+  // prologue: step 0 of layer 0 into slot 0, step 1 in flight
+  stage_load<D>(staged, wres(0), vo, 0);
+  stage_store<D>(ring, staged, wv, lane);
+  stage_load<D>(staged, wres(0), vo, 1);
+  __syncthreads();
+  fetch_half<D>(fr[0], ring, 0, lane);
+  // end of step s: publish step s + 1, start loading step s + 2 (layer Wsrc,
+  // index s_load), make step s + 1 current
+  auto advance = [&](__amdgpu_buffer_rsrc_t Wsrc, int s_load) {
+    const int nxt = cur == 2 ? 0 : cur + 1;
+    stage_store<D>(ring + nxt * RS, staged, wv, lane);
+    stage_load<D>(staged, Wsrc, vo, s_load);
+    __syncthreads();
+    cur = nxt;
+  };
 
-  // chunks of 2 * pairs configurations, strided over the waves of the grid
-  for (int64_t chunk = group; chunk * 2 * a.pairs < B; chunk += n_groups) {
-  const int64_t c_base = chunk * 2 * a.pairs;
+  // block chunks strided over the grid
+  for (int64_t bc = blockIdx.x; bc * block_cfgs < B; bc += gridDim.x) {
+  const int64_t c_base = bc * block_cfgs + int64_t(wv) * 2 * a.pairs;
   for (int pair = 0; pair < a.pairs; ++pair) {
     const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
-    if (c_base + 2 * pair >= B) break;
+    if (bc * block_cfgs + 2 * pair >= B) break;   // uniform over the block
     const bool live = cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
 
@@ -319,14 +350,15 @@ fused_kernel(FusedArgs a) {
     }
 
     for (int l = 0; l < a.L; ++l) {
-      const View W = wview(l), Wn = wview(l + 1 < a.L ? l + 1 : 0);
+      const __amdgpu_buffer_rsrc_t W = wres(l), Wn = wres(l + 1 < a.L ? l + 1 : 0);
       // permuted vectors of the layer (LDS): lane-half h reads 16 floats at (2q+h)*16
       const float *lv = svec + l * int(S::VEC_L);
       const float *V16 = lv + h * 16;
       bf16x8 X[KS];
       // The weight stream advances in half steps of HS fragments through the
       // two buffers fr[0] / fr[1]: while one half is multiplied the next half
-      // is loaded.  On entry fr[0] holds half 0 of step 0 of this layer.
+      // is read from the LDS ring.  On entry fr[0] holds half 0 of step 0 of
+      // this layer and the ring's current slot holds step 0.
       // ---- attention block
       layer_norm<NB>(res, V16, int(S::VLN1G), int(S::VLN1B), X);
 #pragma unroll
@@ -335,30 +367,33 @@ fused_kernel(FusedArgs a) {
       for (int b = 0; b < NB; ++b) {
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O); halves alternate fr[0], fr[1]
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
-        load_half<D>(fr[1], W, 4 * b, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
-        load_half<D>(fr[0], W, 4 * b + 1, 0);
+        advance(W, 4 * b + 2);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
         f32x16 Kc = lds16(V16 + S::VBK + b * 32);
-        load_half<D>(fr[1], W, 4 * b + 1, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
-        load_half<D>(fr[0], W, 4 * b + 2, 0);
+        advance(W, 4 * b + 3);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Kc = mfma(fr[1][i], X[HS + i], Kc);
         f32x16 Vc;
         const float bvv = lv[S::VBV + 32 * b + r];
 #pragma unroll
         for (int j = 0; j < 16; ++j) Vc[j] = bvv;
-        load_half<D>(fr[1], W, 4 * b + 2, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Vc = mfma(X[i], fr[0][i], Vc);
-        load_half<D>(fr[0], W, 4 * b + 3, 0);
+        advance(W, 4 * b + 4);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
-        load_half<D>(fr[1], W, 4 * b + 3, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
         f32x16 O;
 #pragma unroll
@@ -400,7 +435,8 @@ fused_kernel(FusedArgs a) {
         // output projection: fragment i = 2q + e (q = output block)
 #pragma unroll
         for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]);
-        load_half<D>(fr[0], W, 4 * b + 4, 0);   // next Q, or the first FFN step
+        advance(W, 4 * b + 5);   // next Q, or the first FFN step
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i)
           res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]);
@@ -413,23 +449,28 @@ fused_kernel(FusedArgs a) {
       for (int fb = 0; fb < FB; ++fb) {
         const int s = 4 * NB + 2 * fb;
         f32x16 Hc = lds16(V16 + S::VB1 + fb * 32);
-        load_half<D>(fr[1], W, s, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
-        load_half<D>(fr[0], W, s + 1, 0);
+        if (s + 2 < STEPS)
+          advance(W, s + 2);
+        else
+          advance(Wn, s + 2 - STEPS);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
-        load_half<D>(fr[1], W, s + 1, 1);
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
         const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
         // second FFN layer: fragment i = 2q + e
 #pragma unroll
         for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
-        if (s + 2 < STEPS)
-          load_half<D>(fr[0], W, s + 2, 0);
+        if (s + 3 < STEPS)
+          advance(W, s + 3);
         else
-          load_half<D>(fr[0], Wn, 0, 0);
+          advance(Wn, s + 3 - STEPS);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i)
           res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? H1 : H0, res[(HS + i) / 2]);
@@ -745,7 +786,8 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   if (tile.pairs > 0) a.pairs = std::min(tile.pairs, kPairs);
   a.count = count;
   a.lds_floats = int(L.a.pw1);   // every vector before the phase-MLP input table
-  const size_t lds_bytes = size_t(a.lds_floats) * 4;
+  // vectors, then the weight ring (three slots of d/16 fragments of 1 KiB)
+  const size_t lds_bytes = size_t(a.lds_floats) * 4 + size_t(3) * (m.d / 16) * 1024;
   // two blocks per CU must fit the 160 KiB of LDS
   NQS_REQUIRE(lds_bytes <= 80 * 1024, NQS_EUNSUPPORTED,
               "fused forward: model vectors exceed the LDS budget");
@@ -757,8 +799,7 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<64>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
   }
-  const int64_t groups = ceil_div(B, 2 * a.pairs);
-  int64_t blocks = ceil_div(groups, 4);
+  int64_t blocks = ceil_div(B, int64_t(8) * a.pairs);   // four waves of 2 x pairs configurations
   if (tile.blocks > 0) blocks = std::min<int64_t>(blocks, tile.blocks);
   const dim3 grid = dim3(unsigned(blocks));
   hipEvent_t e0 = nullptr, e1 = nullptr;
