@@ -169,6 +169,10 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
                 "amp_model_create: n_params does not match the dimensions (expected " +
                     std::to_string(m->P) + ")");
     check_device();
+    size_t free_b = 0, total_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &total_b));
+    m->act_budget = std::min<int64_t>(std::max<int64_t>(int64_t(free_b / 8), int64_t(1) << 30),
+                                      int64_t(16) << 30);
     install_sectors(*m, {{n, m->na, m->nb}}, false);
     if (m->fp64()) {
       HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 8), params, size_t(m->P) * 8,

@@ -52,6 +52,7 @@ struct nqs_model {
   std::vector<uint8_t> phys_host;     // concatenated physical-child tables of the sectors
   std::vector<nqs_sector_info> sec_host;  // one entry, or one per molecule when tagged
   int tagged = 0;                     // configuration words carry the molecule index
+  int64_t act_budget = int64_t(1) << 30;  // bytes of activations per layer-by-layer chunk
 
   nqs::DevBuf master;                 // canonical parameters (double in FP64, float otherwise)
   nqs::DevBuf phys;                   // device copy of phys_host

@@ -3,6 +3,7 @@
 // Mask-Unphysical conditionals ("Pruning strategies"); Appendix B for the
 // per-token MLP.  The physicality of a prefix comes from Algorithm 1, filled
 // bottom-up into a (position, n_alpha, n_beta) table when the model is made.
+#include <algorithm>
 #include <cmath>
 
 #include "model.h"
@@ -594,15 +595,19 @@ void mlp_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double
 
 template <class T>
 int64_t chunk_rows(const nqs_model &m, bool bwd) {
-  // configurations per chunk, sized for about 1 GiB of activations
+  // configurations per chunk, sized for the model's activation budget (an
+  // eighth of the device memory free at creation, 1..16 GiB): on a 288 GB
+  // device a whole 2e4-sample, 15-token backward is one chunk of large GEMMs
   const int64_t per = m.kind == NQS_MODEL_MLP
                           ? int64_t(m.n) * 8 * 4 + 4 * m.n + 3 * m.hid + 8
                           : int64_t(m.n) * (bwd ? (m.L * (7 * m.d + 2 * m.F + 8) +
                                                    m.L * m.H * m.n + 14 * m.d + 3 * m.F)
                                                 : (8 * m.d + 2 * m.F + 8)) + 6 * m.PH;
-  int64_t c = (int64_t(1) << 30) / (per * int64_t(sizeof(T)));
-  c = c < 64 ? 64 : c;
-  return c > 65536 ? 65536 : c;
+  int64_t c = m.act_budget / (per * int64_t(sizeof(T)));
+  // at most 128k token rows: measured fastest for the library GEMMs of both transformer
+  // workloads (64k and 320k rows are 5-25 % slower per step)
+  c = std::min<int64_t>(c, 131072 / m.n);
+  return c < 64 ? 64 : c;
 }
 
 template <class T>

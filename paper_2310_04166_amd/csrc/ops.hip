@@ -251,6 +251,130 @@ __global__ void __launch_bounds__(64) attention_bwd_kernel(const T *qkv, const T
   }
 }
 
+// Short sequences (T <= 16 positions, head dim <= 16): sixteen lanes per
+// (sequence, head) item, lane t owns query / key position t, so nearly every
+// lane works; the item's K, V (and for the backward Q, dO, P, dS) rows sit in
+// LDS.  IPB items per block.  Loops run over all 16 slots with masks, so the
+// per-lane arrays stay in registers.
+template <class T, int IPB>
+__global__ void __launch_bounds__(IPB * 16) attention_fwd16_kernel(const T *qkv, int64_t n_items,
+                                                                   int T_, int d, int H, T *o,
+                                                                   T *probs) {
+  __shared__ T kk[IPB][16][17], vv[IPB][16][17];
+  const int g = threadIdx.x / 16, t = threadIdx.x % 16;
+  const int64_t item = int64_t(blockIdx.x) * IPB + g;
+  const bool ok = item < n_items && t < T_;
+  const int dh = d / H;
+  const int64_t b = item / H;
+  const int h = int(item % H);
+  const T *row = qkv + (b * T_ + t) * 3 * d + h * dh;
+  T q[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const bool in = ok && j < dh;
+    q[j] = in ? row[j] : T(0);
+    kk[g][t][j] = in ? row[d + j] : T(0);
+    vv[g][t][j] = in ? row[2 * d + j] : T(0);
+  }
+  __syncthreads();
+  if (!ok) return;
+  const T scale = T(1) / sqrt(T(dh));
+  T sc[16];
+  T mx = T(-1e300);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    T a = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a += q[j] * kk[g][u][j];
+    sc[u] = a * scale;
+    if (u <= t) mx = sc[u] > mx ? sc[u] : mx;
+  }
+  T z = 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    sc[u] = u <= t ? exp(sc[u] - mx) : T(0);
+    z += sc[u];
+  }
+  const T iz = T(1) / z;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) sc[u] *= iz;
+  if (probs) {
+    T *pr = probs + (item * T_ + t) * T_;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (u < T_) pr[u] = sc[u];
+  }
+  T *orow = o + (b * T_ + t) * d + h * dh;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    T a = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a += sc[u] * vv[g][u][j];
+    if (j < dh) orow[j] = a;
+  }
+}
+
+template <class T, int IPB>
+__global__ void __launch_bounds__(IPB * 16) attention_bwd16_kernel(const T *qkv, const T *probs,
+                                                                   const T *dout, int64_t n_items,
+                                                                   int T_, int d, int H, T *dqkv) {
+  __shared__ T qq[IPB][16][17], kk[IPB][16][17], vv[IPB][16][17], dO[IPB][16][17];
+  __shared__ T P[IPB][16][17], dS[IPB][16][17];
+  const int g = threadIdx.x / 16, t = threadIdx.x % 16;
+  const int64_t item = int64_t(blockIdx.x) * IPB + g;
+  const bool ok = item < n_items && t < T_;
+  const int dh = d / H;
+  const int64_t b = item / H;
+  const int h = int(item % H);
+  const T *row = qkv + (b * T_ + t) * 3 * d + h * dh;
+  const T *drow = dout + (b * T_ + t) * d + h * dh;
+  const T *pr = probs + (item * T_ + t) * T_;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const bool in = ok && j < dh;
+    qq[g][t][j] = in ? row[j] : T(0);
+    kk[g][t][j] = in ? row[d + j] : T(0);
+    vv[g][t][j] = in ? row[2 * d + j] : T(0);
+    dO[g][t][j] = in ? drow[j] : T(0);
+    P[g][t][j] = (ok && j < T_) ? pr[j] : T(0);
+  }
+  __syncthreads();
+  {
+    // dS[t][u] = P[t][u] (dO[t] . V[u] - sum_w P[t][w] dO[t] . V[w]); P = 0 above the diagonal
+    T dp[16];
+    T rowdot = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      T a = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a += dO[g][t][j] * vv[g][u][j];
+      dp[u] = a;
+      rowdot += a * P[g][t][u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) dS[g][t][u] = P[g][t][u] * (dp[u] - rowdot);
+  }
+  __syncthreads();
+  if (!ok) return;
+  const T scale = T(1) / sqrt(T(dh));
+  T *out = dqkv + (b * T_ + t) * 3 * d + h * dh;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    T aq = 0, ak = 0, av = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      aq += dS[g][t][u] * kk[g][u][j];   // dQ[t] = sum_u dS[t,u] K[u]
+      ak += dS[g][u][t] * qq[g][u][j];   // dK[t] = sum_u dS[u,t] Q[u]
+      av += P[g][u][t] * dO[g][u][j];    // dV[t] = sum_u P[u,t] dO[u]
+    }
+    if (j < dh) {
+      out[j] = aq * scale;
+      out[d + j] = ak * scale;
+      out[2 * d + j] = av;
+    }
+  }
+}
+
 template <class T>
 __global__ void gelu_bwd_kernel(const T *pre, T *dy, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -349,6 +473,13 @@ void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, c
 template <class T>
 void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s) {
   if (B <= 0) return;
+  if (T_ <= 16 && d / H <= 16) {
+    constexpr int IPB = sizeof(T) == 8 ? 8 : 16;
+    hipLaunchKernelGGL((attention_fwd16_kernel<T, IPB>), dim3(unsigned(ceil_div(B * H, IPB))),
+                       dim3(IPB * 16), 0, s, qkv, B * H, T_, d, H, o, probs);
+    HIP_LAUNCH_OK();
+    return;
+  }
   NQS_REQUIRE(T_ <= 32 && d / H <= 64, NQS_EUNSUPPORTED, "attention: sequence > 32 or head dim > 64");
   hipLaunchKernelGGL(attention_fwd_kernel<T>, dim3(unsigned(B * H)), dim3(64), 0, s, qkv, T_, d, H,
                      o, probs);
@@ -359,6 +490,13 @@ template <class T>
 void attention_bwd(const T *qkv, const T *probs, const T *dout, int64_t B, int T_, int d, int H,
                    T *dqkv, hipStream_t s) {
   if (B <= 0) return;
+  if (T_ <= 16 && d / H <= 16) {
+    constexpr int IPB = sizeof(T) == 8 ? 4 : 8;
+    hipLaunchKernelGGL((attention_bwd16_kernel<T, IPB>), dim3(unsigned(ceil_div(B * H, IPB))),
+                       dim3(IPB * 16), 0, s, qkv, probs, dout, B * H, T_, d, H, dqkv);
+    HIP_LAUNCH_OK();
+    return;
+  }
   NQS_REQUIRE(T_ <= 32 && d / H <= 64, NQS_EUNSUPPORTED, "attention: sequence > 32 or head dim > 64");
   hipLaunchKernelGGL(attention_bwd_kernel<T>, dim3(unsigned(B * H)), dim3(64), 0, s, qkv, probs,
                      dout, T_, d, H, dqkv);
