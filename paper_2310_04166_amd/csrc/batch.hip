@@ -87,12 +87,16 @@ __global__ void clear_kernel(uint64_t *__restrict__ table, int64_t table_size,
   }
 }
 
+// Longest linear probe; a longer run means the table is too full for the
+// step (it is then enlarged and the step run again).
+constexpr int kMaxProbe = 256;
+
 // Inserts key; returns its slot.  The first inserter numbers the key.
 __device__ inline uint32_t insert_key(uint64_t key, uint64_t tagged, uint64_t *table,
                                       uint32_t *ids, uint64_t mask, uint64_t *ukeys,
                                       Counters *ctr) {
   uint64_t h = mix64(key) & mask;
-  for (uint64_t probe = 0; probe <= mask; ++probe) {
+  for (int probe = 0; probe < kMaxProbe; ++probe) {
     const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(table + h),
                                     (unsigned long long)kEmpty, (unsigned long long)key);
     if (prev == kEmpty) {
@@ -327,6 +331,7 @@ struct nqs_batch {
   bool graph_has_psi_x = false;
   // statistics of the last step
   int64_t last_pairs = 0, last_distinct = 0, captures = 0;
+  int64_t est_distinct = 0;        // raised when a step overfills the distinct-x' table
   std::vector<int64_t> distinct_per_mol;
   DevBuf per_mol;
   std::vector<double> tune_ms;     // candidate timings of the last tuning
@@ -364,17 +369,25 @@ void reserve(nqs_batch &b, int64_t U, int64_t P) {
   }
   if (P > b.p_cap) {
     b.p_cap = std::max<int64_t>(P + P / 2, 1 << 16);
-    int64_t t = 1;
-    while (t < 2 * b.p_cap) t <<= 1;   // load factor below one half
-    NQS_REQUIRE(t <= (int64_t(1) << 32), NQS_EUNSUPPORTED, "batch: more than 2^31 pairs");
-    b.t_size = t;
-    b.table.reserve(size_t(t) * 8);
-    b.ids.reserve(size_t(t) * 4);
+    NQS_REQUIRE(b.p_cap < (int64_t(1) << 32), NQS_EUNSUPPORTED, "batch: more than 2^32 pairs");
     b.ukeys.reserve(size_t(b.p_cap) * 8);
     b.la.reserve(size_t(b.p_cap) * 8);
     b.ph.reserve(size_t(b.p_cap) * 8);
     b.slot.reserve(size_t(b.p_cap) * 4);
     b.hval.reserve(size_t(b.p_cap) * 8);
+    grown = true;
+  }
+  // distinct-x' table: at least twice the pairs (or the enlarged estimate
+  // after an overfull step).  A sparse table is measured faster than one
+  // sized for the distinct x' alone: fewer keys share a cache line, so the
+  // concurrent compare-and-swaps of different CUs rarely collide.
+  const int64_t want = std::max<int64_t>(b.est_distinct, b.p_cap);
+  int64_t t = int64_t(1) << 16;
+  while (t < 2 * want) t <<= 1;
+  if (t > b.t_size) {
+    b.t_size = t;
+    b.table.reserve(size_t(t) * 8);
+    b.ids.reserve(size_t(t) * 4);
     grown = true;
   }
   if (grown) drop_graph(b);
@@ -651,6 +664,7 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
     if (n_pairs) *n_pairs = P;
     b->last_pairs = P;
     NQS_REQUIRE(U == 0 || (x && counts && eloc), NQS_EINVAL, "batch_local_energy: null array");
+    for (int attempt = 0;; ++attempt) {
     reserve(*b, std::max<int64_t>(U, 1), std::max<int64_t>(P, 1));
     HIP_OK(hipMemcpyAsync(b->desc.ptr, &d, sizeof(StepDesc), hipMemcpyHostToDevice, s));
     if (U > 0) {
@@ -718,6 +732,12 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
                           hipMemcpyDeviceToHost, s));
     Counters c{};
     HIP_OK(hipMemcpyAsync(&c, b->ctr.ptr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if ((c.overflow & 2) && attempt < 3) {
+      // the table was too small for this step's distinct x': enlarge, run again
+      b->est_distinct = std::max<int64_t>(4 * b->est_distinct, c.distinct * 2 + 1);
+      continue;
+    }
     if (U > 0)
       HIP_OK(hipMemcpyAsync(eloc, b->eloc.ptr, size_t(U) * 16, hipMemcpyDeviceToDevice, s));
     HIP_OK(hipMemcpyAsync(sums, b->sums.ptr, size_t(b->n_mol) * 32, hipMemcpyDeviceToDevice, s));
@@ -731,6 +751,8 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
     NQS_REQUIRE(c.overflow == 0, NQS_EINVAL,
                 "batch_local_energy: a configuration's molecule disagrees with the offsets, or it "
                 "had more connected x' than its molecule's K, or the distinct-x' table overflowed");
+    break;
+    }
   });
 }
 
