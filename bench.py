@@ -30,6 +30,21 @@ sys.path.insert(0, ROOT)
 FLOP_PER_CONFIG = 2 * (15 * 4 * 12 * 128 ** 2 + 4 * 2 * 128 * 120 + 15 * 4 * 128 + 256 * 256 + 256)
 BF16_PEAK_TFLOPS = 2500.0
 
+# HBM bytes per launch of the fused kernel on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid only for the kernel source they were
+# taken on (sha256 prefix), otherwise the roofline reports null.
+FUSED_TRAFFIC = {"source_sha256_prefix": "fb324e1f03c95208", "bytes_per_launch": 30.68e6,
+                 "profile": "profiles/fused_kernel_precision_traffic.md"}
+
+
+def fused_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_04166_amd", "csrc", "tf_fused.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return FUSED_TRAFFIC["bytes_per_launch"] if sha == FUSED_TRAFFIC["source_sha256_prefix"] else None
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -330,7 +345,9 @@ def main():
     value = total_pairs / elapsed
     achieved = (k_cfgs * FLOP_PER_CONFIG) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                "traffic": fused_traffic() if args.workload == "precision" else None,
+                "traffic_unit": "bytes per launch",
                 "kernel": "fused_kernel<128> (bf16 amplitude network)",
                 "avg_launch_ms": round(k_ms / max(k_launches, 1), 3), "launches": k_launches,
                 "configs": k_cfgs, "flop_per_config": FLOP_PER_CONFIG,
