@@ -4,7 +4,12 @@
 // kernel.
 #include "ops.h"
 
+#include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
+
+#include <array>
+#include <functional>
+#include <map>
 
 namespace nqs {
 namespace {
@@ -68,14 +73,156 @@ rocblas_handle blas(hipStream_t s) {
   return handles[dev];
 }
 
+// FP32 GEMMs: rocBLAS or hipBLASLt (FP32 compute), whichever is faster for the
+// call's shape.  On the first call of a shape bucket both are timed (rocBLAS and
+// up to eight hipBLASLt algorithms from its heuristic, each once after a warm-up,
+// into a scratch output) and the fastest is kept for the bucket; hipBLASLt's kernels for the
+// backward's weight-gradient shapes (reductions over ~1e5 token rows) are
+// several times faster than rocBLAS's, its first heuristic choice for narrow
+// outputs is several times slower.
+struct GemmChoice {
+  bool lt = false;
+  hipblasLtMatmulDesc_t desc = nullptr;
+  hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, lc = nullptr;
+  hipblasLtMatmulAlgo_t algo{};
+};
+
+struct LtState {
+  hipblasLtHandle_t handle = nullptr;
+  DevBuf ws, scratch;
+  std::map<std::array<int, 9>, GemmChoice> plans;   // exact shapes
+  // timing decisions per shape bucket (dimensions rounded up to powers of two, so
+  // the ragged last chunk of a step reuses them): -1 = rocBLAS, r = hipBLASLt's
+  // r-th heuristic algorithm
+  std::map<std::array<int, 9>, int> decisions;
+};
+
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+constexpr size_t kLtWorkspace = size_t(64) << 20;
+
+LtState &lt_state() {
+  static LtState states[64];
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  NQS_REQUIRE(dev >= 0 && dev < 64, NQS_EHIP, "device index out of range");
+  LtState &st = states[dev];
+  if (!st.handle) {
+    if (hipblasLtCreate(&st.handle) != HIPBLAS_STATUS_SUCCESS)
+      throw Error(NQS_EHIP, "hipblasLtCreate failed");
+    st.ws.reserve(kLtWorkspace);
+  }
+  return st;
+}
+
+float time_call(hipStream_t s, const std::function<bool()> &f) {
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float ms = -1.f;
+  if (f()) {                       // warm-up; also checks the call is accepted
+    HIP_OK(hipEventRecord(e0, s));
+    const bool ok = f();
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    if (ok) HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+const GemmChoice &choose_gemm(LtState &st, rocblas_handle h, rocblas_operation ta,
+                              rocblas_operation tb, int m, int n, int k, const float *A, int lda,
+                              const float *B, int ldb, float beta, int ldc, hipStream_t s) {
+  const bool tA = ta == rocblas_operation_transpose, tB = tb == rocblas_operation_transpose;
+  const std::array<int, 9> key{int(tA), int(tB), m, n, k, lda, ldb, ldc, int(beta != 0.f)};
+  auto it = st.plans.find(key);
+  if (it != st.plans.end()) return it->second;
+  const std::array<int, 9> bucket{int(tA), int(tB), pow2_ceil(m), pow2_ceil(n), pow2_ceil(k),
+                                  tA ? pow2_ceil(lda) : lda, tB ? pow2_ceil(ldb) : ldb, ldc,
+                                  int(beta != 0.f)};
+  auto dit = st.decisions.find(bucket);
+  const int decided = dit == st.decisions.end() ? -2 : dit->second;
+  GemmChoice c;
+  float *C = static_cast<float *>(st.scratch.reserve(size_t(ldc) * size_t(n) * 4));
+  const float alpha = 1.f;
+  int best_rank = -1;
+  float best = 1e30f;
+  if (decided == -2) {
+    best = time_call(s, [&] {
+      return rocblas_sgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc) ==
+             rocblas_status_success;
+    });
+    if (best < 0.f) best = 1e30f;
+  }
+  const hipblasOperation_t opa = tA ? HIPBLAS_OP_T : HIPBLAS_OP_N, opb = tB ? HIPBLAS_OP_T : HIPBLAS_OP_N;
+  bool good = hipblasLtMatmulDescCreate(&c.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(c.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opa, sizeof(opa)) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatmulDescSetAttribute(c.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opb, sizeof(opb)) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&c.la, HIP_R_32F, tA ? k : m, tA ? m : k, lda) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&c.lb, HIP_R_32F, tB ? n : k, tB ? k : n, ldb) == HIPBLAS_STATUS_SUCCESS &&
+              hipblasLtMatrixLayoutCreate(&c.lc, HIP_R_32F, m, n, ldc) == HIPBLAS_STATUS_SUCCESS;
+  if (good) {
+    hipblasLtMatmulPreference_t pref = nullptr;
+    size_t wsb = kLtWorkspace;
+    hipblasLtMatmulHeuristicResult_t res[8] = {};
+    int got = 0;
+    if (hipblasLtMatmulPreferenceCreate(&pref) == HIPBLAS_STATUS_SUCCESS &&
+        hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsb,
+                                              sizeof(wsb)) == HIPBLAS_STATUS_SUCCESS &&
+        hipblasLtMatmulAlgoGetHeuristic(st.handle, c.desc, c.la, c.lb, c.lc, c.lc, pref, 8, res,
+                                        &got) == HIPBLAS_STATUS_SUCCESS) {
+      if (decided >= 0 && decided < got) {
+        c.lt = true;
+        c.algo = res[decided].algo;
+      } else if (decided == -2) {
+        for (int a = 0; a < got; ++a) {
+          const float ms = time_call(s, [&] {
+            return hipblasLtMatmul(st.handle, c.desc, &alpha, A, c.la, B, c.lb, &beta, C, c.lc,
+                                   C, c.lc, &res[a].algo, st.ws.ptr, kLtWorkspace, s) ==
+                   HIPBLAS_STATUS_SUCCESS;
+          });
+          if (ms >= 0.f && ms < best) {
+            best = ms;
+            best_rank = a;
+            c.lt = true;
+            c.algo = res[a].algo;
+          }
+        }
+      }
+    }
+    if (pref) hipblasLtMatmulPreferenceDestroy(pref);
+  }
+  if (decided == -2) st.decisions.emplace(bucket, best_rank);
+  return st.plans.emplace(key, c).first->second;
+}
+
 void blas_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
                float alpha, const float *A, int lda, const float *B, int ldb, float beta,
-               float *C, int ldc) {
+               float *C, int ldc, hipStream_t s) {
+  // the library's kernels may assume 16-byte aligned operands
+  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+                         reinterpret_cast<uintptr_t>(C)) & 15) == 0;
+  if (aligned && alpha == 1.f) {
+    LtState &st = lt_state();
+    const GemmChoice &c = choose_gemm(st, h, ta, tb, m, n, k, A, lda, B, ldb, beta, ldc, s);
+    if (c.lt) {
+      if (hipblasLtMatmul(st.handle, c.desc, &alpha, A, c.la, B, c.lb, &beta, C, c.lc, C, c.lc,
+                          &c.algo, st.ws.ptr, kLtWorkspace, s) != HIPBLAS_STATUS_SUCCESS)
+        throw Error(NQS_EHIP, "hipblasLtMatmul failed");
+      return;
+    }
+  }
   BLAS_OK(rocblas_sgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc));
 }
 void blas_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
                double alpha, const double *A, int lda, const double *B, int ldb, double beta,
-               double *C, int ldc) {
+               double *C, int ldc, hipStream_t) {
   BLAS_OK(rocblas_dgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc));
 }
 
@@ -413,7 +560,7 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
   // row-major C = op(A) op(B) is column-major C^T = op(B)^T op(A)^T
   blas_gemm(blas(s), TB ? rocblas_operation_transpose : rocblas_operation_none,
             TA ? rocblas_operation_transpose : rocblas_operation_none, int(N), int(M), int(K),
-            T(1), B, int(ldb), A, int(lda), epi == EPI_ADD ? T(1) : T(0), C, int(ldc));
+            T(1), B, int(ldb), A, int(lda), epi == EPI_ADD ? T(1) : T(0), C, int(ldc), s);
   if (bias || (epi != EPI_STORE && epi != EPI_ADD)) {
     hipLaunchKernelGGL(epilogue_kernel<T>, grid1(M * N), dim3(256), 0, s, C, M, N, ldc, bias, aux,
                        epi);
