@@ -97,6 +97,14 @@ __device__ inline uint32_t insert_key(uint64_t key, uint64_t tagged, uint64_t *t
                                       Counters *ctr) {
   uint64_t h = mix64(key) & mask;
   for (int probe = 0; probe < kMaxProbe; ++probe) {
+    // most keys are already present (a distinct x' has ~10 pairs): a plain
+    // read settles those without an atomic, so popular keys see no contention
+    const uint64_t seen = __hip_atomic_load(table + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen == key) return uint32_t(h);
+    if (seen != kEmpty) {
+      h = (h + 1) & mask;
+      continue;
+    }
     const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(table + h),
                                     (unsigned long long)kEmpty, (unsigned long long)key);
     if (prev == kEmpty) {
@@ -112,6 +120,11 @@ __device__ inline uint32_t insert_key(uint64_t key, uint64_t tagged, uint64_t *t
   return kNoSlot;
 }
 
+struct Pend {
+  int g, r;       // flip group, output rank within the sample
+  uint64_t xp;    // the connected configuration
+};
+
 __global__ void __launch_bounds__(256) pairs_kernel(
     const StepDesc *__restrict__ desc, const MolTab *__restrict__ tabs,
     const uint64_t *__restrict__ flip, const int64_t *__restrict__ goff,
@@ -123,6 +136,8 @@ __global__ void __launch_bounds__(256) pairs_kernel(
   const int lane = threadIdx.x % kWave;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const int64_t U = desc->U;
+  __shared__ Pend pend_all[4][2 * kWave];   // per wave: kept pairs waiting to be handled
+  Pend *pend = pend_all[threadIdx.x / kWave];
   // samples strided over the waves (the samples of every molecule are spread
   // over all waves); the wave index is made wave-uniform explicitly
   const int64_t wave = int64_t(blockIdx.x) * (blockDim.x / kWave) +
@@ -140,7 +155,39 @@ __global__ void __launch_bounds__(256) pairs_kernel(
     const MolTab tb = tabs[mol];
     const int64_t base = desc->p_off[mol] + (s - desc->u_off[mol]) * tb.K;
     const uint64_t tag = uint64_t(mol) << kTagShift, ktag = uint64_t(mol) << nbits;
-    int64_t found = 0;
+    // Kept pairs are first listed in LDS (group, output rank, x'), then handled
+    // 64 at a time with every lane busy: most flip groups fail the sector
+    // screen, so handling them where they are found would leave ~70 % of the
+    // lanes idle through the term loop and the table insert.
+    int found = 0, npend = 0;
+    auto handle = [&](int count) {
+      if (lane < count) {
+        const Pend e = pend[lane];
+        if (e.r < tb.K) {
+          // the group's terms, four loads in flight at a time, summed in order
+          const int64_t t0 = goff[tb.o0 + e.g], t1 = goff[tb.o0 + e.g + 1];
+          double hv = 0.0;
+          int64_t t = t0;
+          for (; t + 4 <= t1; t += 4) {
+            double c[4];
+            uint64_t z[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              c[u] = coef[t + u];
+              z[u] = zmask[t + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) hv += (__popcll(xs & z[u]) & 1) ? -c[u] : c[u];
+          }
+          for (; t < t1; ++t) {
+            const double c = coef[t];
+            hv += (__popcll(xs & zmask[t]) & 1) ? -c : c;
+          }
+          hval[base + e.r] = hv;
+          slot[base + e.r] = insert_key(ktag | e.xp, tag | e.xp, table, ids, table_mask, ukeys, ctr);
+        }
+      }
+    };
     for (int64_t g0 = 1; g0 < tb.G; g0 += kWave) {
       const int64_t g = g0 + lane;
       const uint64_t f = (g < tb.G) ? flip[tb.g0 + g] : 0ull;
@@ -148,20 +195,32 @@ __global__ void __launch_bounds__(256) pairs_kernel(
       const bool keep = g < tb.G && __popcll(xp & kAlphaBits) == tb.na &&
                         __popcll(xp & kBetaBits) == tb.nb;
       const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int64_t r = found + __popcll(m & below);
-        if (r < tb.K) {
-          double hv = 0.0;
-          for (int64_t t = goff[tb.o0 + g]; t < goff[tb.o0 + g + 1]; ++t) {
-            const double c = coef[t];
-            hv += (__popcll(xs & zmask[t]) & 1) ? -c : c;
-          }
-          hval[base + r] = hv;
-          slot[base + r] = insert_key(ktag | xp, tag | xp, table, ids, table_mask, ukeys, ctr);
-        }
-      }
+      const int rank = __popcll(m & below);
+      if (keep) pend[npend + rank] = Pend{int(g), found + rank, xp};
+      npend += __popcll(m);
       found += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (npend >= kWave) {
+        handle(kWave);
+        // move the overflow (fewer than 64 entries) to the front of the list
+        Pend tail{};
+        if (lane < npend - kWave) tail = pend[kWave + lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < npend - kWave) pend[lane] = tail;
+        npend -= kWave;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     }
+    handle(npend);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (found > tb.K) {
       atomicOr(reinterpret_cast<unsigned long long *>(&ctr->overflow), 1ull);
       found = tb.K;
