@@ -62,9 +62,6 @@ struct nqs_model {
   bool packed_valid = false;
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
-  nqs::DevBuf ones;                   // vector of ones for column sums
-  int64_t ones_rows = 0;
-  size_t ones_bytes = 0;
 
   bool fp64() const { return precision == NQS_FP64; }
   nqs::Sectors sectors() const {

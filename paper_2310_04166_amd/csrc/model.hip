@@ -365,27 +365,19 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
   }
 }
 
-// dW (+)= op(A)^T dY reduced over rows, accumulated in double at grad offset.
+// dW += X^T dY reduced over the R rows, accumulated in double at the parameter's offset.
 template <class T>
 void wgrad(nqs_model &m, int64_t Mi, int64_t No, int64_t R, const T *X, int64_t ldx, const T *dY,
            int64_t ldy, int pidx, hipStream_t s) {
-  T *part = static_cast<T *>(m.part.reserve(size_t(Mi * No) * sizeof(T)));
-  gemm<T, true, false>(Mi, No, R, X, ldx, dY, ldy, part, No, nullptr, nullptr, EPI_STORE, s);
-  add_into<T>(part, Mi * No, m.grad_acc.as<double>() + m.off[pidx], s);
+  void *part = m.part.reserve(wgrad_scratch_bytes(R, Mi, No, std::max(ldx, ldy), sizeof(T)));
+  wgrad_acc(X, ldx, dY, ldy, R, Mi, No, m.grad_acc.as<double>() + m.off[pidx], part, s);
 }
 
+// db += column sums of dY (fixed-order, double)
 template <class T>
 void bgrad(nqs_model &m, const T *dY, int64_t R, int64_t N, int64_t ld, int pidx, hipStream_t s) {
-  // column sums as a GEMM with a vector of ones: dY^T 1
-  if (m.ones_rows < R || m.ones_bytes != sizeof(T)) {
-    T *o = static_cast<T *>(m.ones.reserve(size_t(R) * sizeof(T)));
-    fill_ones<T>(o, R, s);
-    m.ones_rows = R;
-    m.ones_bytes = sizeof(T);
-  }
-  T *part = static_cast<T *>(m.part.reserve(size_t(N) * sizeof(T)));
-  gemm<T, true, false>(N, 1, R, dY, ld, m.ones.as<T>(), 1, part, 1, nullptr, nullptr, EPI_STORE, s);
-  add_into<T>(part, N, m.grad_acc.as<double>() + m.off[pidx], s);
+  double *part = static_cast<double *>(m.part.reserve(colsum_scratch_bytes(R, N)));
+  colsum_acc<T>(dY, R, N, ld, m.grad_acc.as<double>() + m.off[pidx], part, s);
 }
 
 template <class T>

@@ -27,10 +27,21 @@ void add_into(const T *src, int64_t n, double *dst, hipStream_t s);
 template <class T>
 void fill_ones(T *dst, int64_t n, hipStream_t s);
 
-// Deterministic column sums: acc[j] += sum_r Y[r*ld + j] (double accumulator).
+// Deterministic column sums: acc[j] += sum_r Y[r*ld + j] (double accumulator);
+// scratch holds colsum_scratch_bytes(R, N) bytes.
 template <class T>
 void colsum_acc(const T *Y, int64_t R, int64_t N, int64_t ld, double *acc, double *scratch,
                 hipStream_t s);
+size_t colsum_scratch_bytes(int64_t R, int64_t N);
+// Weight gradient: acc[i*N + j] += sum_r X[r*ldx + i] * dY[r*ldy + j] for i < M,
+// j < N (double accumulator).  FP32: a split-K MFMA reduction over row slices
+// whose partial sums are added in a fixed order; FP64: a library GEMM.  scratch
+// holds at least wgrad_scratch_bytes(R, M, N, max(ldx, ldy), element size) bytes.
+void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R, int64_t M,
+               int64_t N, double *acc, void *scratch, hipStream_t s);
+void wgrad_acc(const double *X, int64_t ldx, const double *dY, int64_t ldy, int64_t R, int64_t M,
+               int64_t N, double *acc, void *scratch, hipStream_t s);
+size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t elem);
 // acc[i] += sum_z part[z*len + i]
 void slices_acc(const double *part, int64_t nslices, int64_t len, double *acc, hipStream_t s);
 

@@ -226,7 +226,8 @@ void blas_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int
   BLAS_OK(rocblas_dgemm(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc));
 }
 
-// partial[y][j] = sum over rows of slice y of Y[r, j]; 64 columns x 4 row lanes per block
+// partial[y][j] = sum over rows of slice y of Y[r, j]; 64 columns x 4 row lanes
+// per block, eight loads in flight per lane, a fixed summation order
 template <class T>
 __global__ void __launch_bounds__(256) colsum_kernel(const T *Y, int64_t R, int64_t N, int64_t ld,
                                                      int64_t rows_per, double *partial) {
@@ -236,20 +237,154 @@ __global__ void __launch_bounds__(256) colsum_kernel(const T *Y, int64_t R, int6
   const int64_t r0 = int64_t(blockIdx.y) * rows_per;
   const int64_t r1 = r0 + rows_per < R ? r0 + rows_per : R;
   double a = 0.0;
-  if (j < N)
-    for (int64_t r = r0 + q; r < r1; r += 4) a += double(Y[r * ld + j]);
+  if (j < N) {
+    int64_t r = r0 + q;
+    for (; r + 28 < r1; r += 32) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Y[(r + 4 * u) * ld + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += double(v[u]);
+    }
+    for (; r < r1; r += 4) a += double(Y[r * ld + j]);
+  }
   red[q][c] = a;
   __syncthreads();
   if (q == 0 && j < N)
     partial[int64_t(blockIdx.y) * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-__global__ void slices_acc_kernel(const double *part, int64_t nslices, int64_t len, double *acc) {
+// First level of a slice reduction: out[g][i] = sum of part[z][i] over the
+// slices z of group g (groups of zs consecutive slices); 64 elements x 4 slice
+// lanes per block, a fixed summation order.
+template <class P>
+__global__ void __launch_bounds__(256) sum_slices_kernel(const P *part, int64_t nslices,
+                                                         int64_t len, int64_t zs, double *out) {
+  __shared__ double red[4][64];
+  const int c = threadIdx.x % 64, q = threadIdx.x / 64;
+  const int64_t i = int64_t(blockIdx.x) * 64 + c;
+  const int64_t z0 = int64_t(blockIdx.y) * zs;
+  const int64_t z1 = z0 + zs < nslices ? z0 + zs : nslices;
+  double a = 0.0;
+  if (i < len) {
+    int64_t z = z0 + q;
+    for (; z + 12 < z1; z += 16) {
+      P v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = part[(z + 4 * u) * len + i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a += double(v[u]);
+    }
+    for (; z < z1; z += 4) a += double(part[z * len + i]);
+  }
+  red[q][c] = a;
+  __syncthreads();
+  if (q == 0 && i < len)
+    out[int64_t(blockIdx.y) * len + i] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// acc[i] += sum over slices z of part[z][i], in slice order
+template <class P>
+__global__ void slices_acc_kernel(const P *part, int64_t nslices, int64_t len, double *acc) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= len) return;
   double a = 0.0;
-  for (int64_t z = 0; z < nslices; ++z) a += part[z * len + i];
+  int64_t z = 0;
+  for (; z + 8 <= nslices; z += 8) {
+    P v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(z + u) * len + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += double(v[u]);
+  }
+  for (; z < nslices; ++z) a += double(part[z * len + i]);
   acc[i] += a;
+}
+
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+// Weight-gradient partial sums on fp32 MFMA (32x32x2):
+//     part[z][i][j] = sum over the rows r of slice z of X[r][i] * dY[r][j].
+// One block per (128 x 128 output tile, row slice); wave w owns the 64 x 64
+// quarter (w / 2, w % 2) as 2 x 2 accumulator blocks.  For a pair of rows the
+// lane l supplies X[r + l/32][i0 + l%32] (A operand, k = l/32) and
+// dY[r + l/32][j0 + l%32] (B operand); accumulator element v of lane l is
+// (i0 + (v/4)*8 + (l/32)*4 + v%4, j0 + l%32).
+// The slice's rows are read through buffer resources that end at the slice's
+// last row, so rows past it read as zeros; columns outside the matrices read a
+// clamped valid column, which only feeds accumulator rows / columns that are
+// never stored.  The host keeps a slice under 2 GiB of either matrix.
+__global__ void __launch_bounds__(256) wgrad_f32_kernel(const float *__restrict__ X, int64_t ldx,
+                                                        const float *__restrict__ dY, int64_t ldy,
+                                                        int64_t R, int M, int N, int64_t rows_per,
+                                                        int tiles_n, float *__restrict__ part) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int tm = int(blockIdx.x) / tiles_n, tn = int(blockIdx.x) % tiles_n;
+  const int i0 = tm * 128 + (w / 2) * 64, j0 = tn * 128 + (w % 2) * 64;
+  const int64_t r0 = int64_t(blockIdx.y) * rows_per;
+  const int64_t r1 = r0 + rows_per < R ? r0 + rows_per : R;
+  const int rows = int(r1 - r0);
+  const int kk = lane / 32, c = lane % 32;
+  const int ia = i0 + c, ib = i0 + 32 + c, ja = j0 + c, jb = j0 + 32 + c;
+  const auto rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(X + r0 * ldx), 0,
+                                                    int(int64_t(rows) * ldx * 4), 0x00020000);
+  const auto ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(dY + r0 * ldy), 0,
+                                                    int(int64_t(rows) * ldy * 4), 0x00020000);
+  const int lx = int(ldx) * 4, ly = int(ldy) * 4;   // bytes per row
+  const int oxa = kk * lx + (ia < M ? ia : M - 1) * 4, oxb = kk * lx + (ib < M ? ib : M - 1) * 4;
+  const int oya = kk * ly + (ja < N ? ja : N - 1) * 4, oyb = kk * ly + (jb < N ? jb : N - 1) * 4;
+  f32x16 acc[2][2] = {};
+  constexpr int U = 8;   // row pairs per batch of loads
+  struct Batch {
+    float a0[U], a1[U], b0[U], b1[U];
+  };
+  auto load = [&](int r, Batch &q) {   // rows r .. r + 2U - 1 of the slice
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // row offsets in unsigned 32-bit arithmetic: a batch may run past the slice
+      const int sx = int(uint32_t(r + 2 * u) * uint32_t(lx));
+      const int sy = int(uint32_t(r + 2 * u) * uint32_t(ly));
+      q.a0[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, oxa, sx, 0));
+      q.a1[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, oxb, sx, 0));
+      q.b0[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, oya, sy, 0));
+      q.b1[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, oyb, sy, 0));
+    }
+  };
+  auto multiply = [&](const Batch &q) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.a0[u], q.b0[u], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.a0[u], q.b1[u], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.a1[u], q.b0[u], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q.a1[u], q.b1[u], acc[1][1], 0, 0, 0);
+    }
+  };
+  // two batches in flight: the next batch loads while the current one
+  // multiplies (a batch past the slice reads zeros and is never multiplied)
+  const int nb = (rows + 2 * U - 1) / (2 * U);
+  Batch p0, p1;
+  load(0, p0);
+  int bt = 0;
+  for (; bt + 2 <= nb; bt += 2) {
+    load((bt + 1) * 2 * U, p1);
+    multiply(p0);
+    load((bt + 2) * 2 * U, p0);
+    multiply(p1);
+  }
+  if (bt < nb) multiply(p0);
+  float *pz = part + int64_t(blockIdx.y) * M * N;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int j = j0 + 32 * bj + c;
+      if (j >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = i0 + 32 * bi + (v / 4) * 8 + kk * 4 + v % 4;
+        if (i < M) pz[int64_t(i) * N + j] = acc[bi][bj][v];
+      }
+    }
 }
 
 // one wave per row
@@ -582,22 +717,119 @@ void fill_ones(T *dst, int64_t n, hipStream_t s) {
   HIP_LAUNCH_OK();
 }
 
+namespace {
+// Second-level scratch of a slice reduction: at most kLevelElems doubles.
+constexpr int64_t kLevelElems = int64_t(1) << 17;
+
+// acc[i] += sum_z part[z*len + i] in a fixed order: slices are summed in
+// groups by sum_slices_kernel (enough blocks to fill the chip), then the group
+// sums in order by slices_acc_kernel.  lvl holds kLevelElems doubles.
+template <class P>
+void reduce_slices(const P *part, int64_t nslices, int64_t len, double *acc, double *lvl,
+                   hipStream_t s) {
+  if (len <= 0 || nslices <= 0) return;
+  const int64_t col_blocks = ceil_div(len, int64_t(64));
+  int64_t groups = std::min(ceil_div(int64_t(2048), col_blocks), ceil_div(nslices, int64_t(8)));
+  groups = std::min(groups, kLevelElems / len);
+  if (groups <= 1) {
+    hipLaunchKernelGGL(slices_acc_kernel<P>, grid1(len), dim3(256), 0, s, part, nslices, len, acc);
+    HIP_LAUNCH_OK();
+    return;
+  }
+  const int64_t zs = ceil_div(nslices, groups);
+  groups = ceil_div(nslices, zs);
+  hipLaunchKernelGGL(sum_slices_kernel<P>, dim3(unsigned(col_blocks), unsigned(groups)), dim3(256),
+                     0, s, part, nslices, len, zs, lvl);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(slices_acc_kernel<double>, grid1(len), dim3(256), 0, s,
+                     static_cast<const double *>(lvl), groups, len, acc);
+  HIP_LAUNCH_OK();
+}
+
+// row slices of a column sum: enough blocks to fill the chip, >= 256 rows each
+int64_t colsum_slices(int64_t R, int64_t N) {
+  const int64_t z = std::min(ceil_div(int64_t(2048), ceil_div(N, int64_t(64))),
+                             ceil_div(R, int64_t(256)));
+  return std::max<int64_t>(z, 1);
+}
+}  // namespace
+
+size_t colsum_scratch_bytes(int64_t R, int64_t N) {
+  return size_t(colsum_slices(R, N) * N + kLevelElems) * sizeof(double);
+}
+
 template <class T>
 void colsum_acc(const T *Y, int64_t R, int64_t N, int64_t ld, double *acc, double *scratch,
                 hipStream_t s) {
   if (R <= 0 || N <= 0) return;
-  const int64_t slices = R < 4096 ? 1 : 64;
+  const int64_t slices = colsum_slices(R, N);
   const int64_t rows_per = ceil_div(R, slices);
-  hipLaunchKernelGGL(colsum_kernel<T>, dim3(unsigned(ceil_div(N, 64)), unsigned(slices)), dim3(256),
+  const int64_t used = ceil_div(R, rows_per);
+  hipLaunchKernelGGL(colsum_kernel<T>, dim3(unsigned(ceil_div(N, 64)), unsigned(used)), dim3(256),
                      0, s, Y, R, N, ld, rows_per, scratch);
   HIP_LAUNCH_OK();
-  slices_acc(scratch, slices, N, acc, s);
+  reduce_slices<double>(scratch, used, N, acc, scratch + slices * N, s);
 }
 
 void slices_acc(const double *part, int64_t nslices, int64_t len, double *acc, hipStream_t s) {
   if (len <= 0) return;
-  hipLaunchKernelGGL(slices_acc_kernel, grid1(len), dim3(256), 0, s, part, nslices, len, acc);
+  hipLaunchKernelGGL(slices_acc_kernel<double>, grid1(len), dim3(256), 0, s, part, nslices, len,
+                     acc);
   HIP_LAUNCH_OK();
+}
+
+namespace {
+// row slices of the weight-gradient reduction: enough blocks to fill the chip,
+// at least 128 rows per slice, partial sums within the scratch budget
+constexpr size_t kWgradScratch = size_t(64) << 20;
+int64_t wgrad_slices(int64_t R, int64_t M, int64_t N) {
+  const int64_t tiles = ceil_div(M, 128) * ceil_div(N, 128);
+  int64_t z = ceil_div(int64_t(1024), tiles);
+  z = std::min<int64_t>(z, ceil_div(R, int64_t(128)));
+  z = std::min<int64_t>(z, int64_t(kWgradScratch / size_t(4 * M * N)));
+  return std::max<int64_t>(z, 1);
+}
+// a slice of either matrix must stay under 2 GiB (32-bit buffer offsets; rows
+// are at most 1 MiB, so a batch reaching 16 rows past the slice cannot wrap)
+int64_t wgrad_slices(int64_t R, int64_t M, int64_t N, int64_t ld) {
+  const int64_t z = wgrad_slices(R, M, N);
+  return std::max<int64_t>(z, ceil_div(R * ld * 4, int64_t(1) << 30) + 1);
+}
+}  // namespace
+
+size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t elem) {
+  if (elem == sizeof(double)) return size_t(M * N) * sizeof(double);
+  // float partials, then the second level of the reduction (8-byte aligned)
+  return size_t(ceil_div(wgrad_slices(R, M, N, ld) * M * N, int64_t(2))) * 8 +
+         size_t(kLevelElems) * sizeof(double);
+}
+
+void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
+                      int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  NQS_REQUIRE(M < (int64_t(1) << 24) && N < (int64_t(1) << 24), NQS_EUNSUPPORTED,
+              "weight gradient: dimension too large");
+  if (R <= 0) return;
+  const int64_t ld = std::max(ldx, ldy);
+  NQS_REQUIRE(ld * 4 <= (int64_t(1) << 20), NQS_EUNSUPPORTED, "weight gradient: row too long");
+  const int64_t z = wgrad_slices(R, M, N, ld), rows_per = ceil_div(R, z);
+  const int tiles_n = int(ceil_div(N, int64_t(128)));
+  const int64_t tiles = ceil_div(M, int64_t(128)) * tiles_n;
+  const dim3 grid = dim3(unsigned(tiles), unsigned(ceil_div(R, rows_per)));
+  float *part = static_cast<float *>(scratch);
+  hipLaunchKernelGGL(wgrad_f32_kernel, grid, dim3(256), 0, s, X, ldx, dY, ldy, R, int(M), int(N),
+                     rows_per, tiles_n, part);
+  HIP_LAUNCH_OK();
+  double *lvl = static_cast<double *>(scratch) + ceil_div(z * M * N, int64_t(2));
+  reduce_slices<float>(part, int64_t(grid.y), M * N, acc, lvl, s);
+}
+
+void wgrad_acc(const double *X, int64_t ldx, const double *dY, int64_t ldy, int64_t R,
+                       int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s) {
+  if (M <= 0 || N <= 0 || R <= 0) return;
+  double *part = static_cast<double *>(scratch);
+  gemm<double, true, false>(M, N, R, X, ldx, dY, ldy, part, N, nullptr, nullptr, EPI_STORE, s);
+  add_into<double>(part, M * N, acc, s);
 }
 
 template <class T>
