@@ -6,8 +6,8 @@
 // forms x' = x ^ f and keeps it when x' has the sector's alpha and beta
 // electron counts (popcounts of the even and odd bits).  A wave ballot and a
 // popcount of the lanes below give each kept pair its output slot, so pairs
-// come out in group order without atomics.  A kept lane then sums its group's
-// Pauli terms, coef * (-1)^popcount(x & zmask), in double.
+// come out in group order without atomics.  Each kept group's Pauli terms,
+// coef * (-1)^popcount(x & zmask), are then summed in double, in term order.
 #include "ham.h"
 
 namespace nqs {
@@ -22,15 +22,40 @@ __device__ inline bool in_sector(uint64_t xp, int na, int nb) {
   return __popcll(xp & kAlphaBits) == na && __popcll(xp & kBetaBits) == nb;
 }
 
+// Sum of one flip group's Pauli terms in term order, four loads in flight.
 __device__ inline double group_value(uint64_t x, int64_t t0, int64_t t1, const uint64_t *zmask,
                                      const double *coef) {
   double h = 0.0;
-  for (int64_t t = t0; t < t1; ++t) {
+  int64_t t = t0;
+  for (; t + 4 <= t1; t += 4) {
+    double c[4];
+    uint64_t z[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = coef[t + u];
+      z[u] = zmask[t + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) h += (__popcll(x & z[u]) & 1) ? -c[u] : c[u];
+  }
+  for (; t < t1; ++t) {
     const double c = coef[t];
     h += (__popcll(x & zmask[t]) & 1) ? -c : c;
   }
   return h;
 }
+
+// Order visible to the other lanes of the wave (LDS list below).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct PendPair {
+  int64_t slot;   // output slot of a kept pair
+  int64_t g;      // its flip group
+};
 
 __global__ void __launch_bounds__(256) count_pairs_kernel(
     const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip, int64_t G,
@@ -48,31 +73,59 @@ __global__ void __launch_bounds__(256) count_pairs_kernel(
   if (lane == 0) cnt[i] = c;
 }
 
+// Kept pairs are written (x', owner) as they are found, and their groups are
+// listed in LDS; the Pauli sums are then taken 64 groups at a time with every
+// lane busy (most groups fail the sector test, so summing where they are found
+// would leave most lanes idle through the term loop).
 __global__ void __launch_bounds__(256) emit_pairs_kernel(
     const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip,
     const int64_t *__restrict__ goff, const uint64_t *__restrict__ zmask,
     const double *__restrict__ coef, int64_t G, int na, int nb, const int64_t *__restrict__ off,
     uint64_t *__restrict__ xp, double *__restrict__ hval, int32_t *__restrict__ owner,
     double *__restrict__ hdiag, int64_t owner_base) {
+  __shared__ PendPair pend_all[kWavesPerBlock][2 * kWave];
   const int lane = threadIdx.x % kWave;
+  PendPair *pend = pend_all[threadIdx.x / kWave];
   const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-  if (i >= n) return;
+  if (i >= n) return;   // uniform over the wave; no block barrier follows
   const uint64_t xi = x[i];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   int64_t base = off[i] - off[0];
+  int npend = 0;
+  auto handle = [&](int count) {
+    if (lane < count) {
+      const PendPair e = pend[lane];
+      hval[e.slot] = group_value(xi, goff[e.g], goff[e.g + 1], zmask, coef);
+    }
+  };
   for (int64_t g0 = 1; g0 < G; g0 += kWave) {
     const int64_t g = g0 + lane;
     const uint64_t f = (g < G) ? flip[g] : 0ull;
     const bool keep = g < G && in_sector(xi ^ f, na, nb);
     const uint64_t mask = __ballot(keep);
+    const int rank = __popcll(mask & below);
     if (keep) {
-      const int64_t slot = base + __popcll(mask & below);
+      const int64_t slot = base + rank;
       if (xp) xp[slot] = xi ^ f;
-      if (hval) hval[slot] = group_value(xi, goff[g], goff[g + 1], zmask, coef);
       if (owner) owner[slot] = int32_t(owner_base + i);
+      if (hval) pend[npend + rank] = PendPair{slot, g};
     }
     base += __popcll(mask);
+    if (!hval) continue;
+    npend += __popcll(mask);
+    wave_sync();
+    if (npend >= kWave) {
+      handle(kWave);
+      // move the overflow (fewer than 64 entries) to the front of the list
+      PendPair tail{};
+      if (lane < npend - kWave) tail = pend[kWave + lane];
+      wave_sync();
+      if (lane < npend - kWave) pend[lane] = tail;
+      npend -= kWave;
+      wave_sync();
+    }
   }
+  if (hval) handle(npend);
   if (hdiag) {
     // diagonal group: lanes split its terms, then a fixed-order wave reduction
     double h = 0.0;
