@@ -276,7 +276,10 @@ int local_energy_stats(const nqs_ham *ham, int64_t *n_pairs, int64_t *n_distinct
  * vmc_weights - upstream weights of the VMC gradient (paper: gradient
  * equation in "Variational Monte Carlo"): with W = sums[0] and E =
  * (sums[1] + i sums[2]) / W, g_logabs[l] = 2 n_l / W Re(E_loc,l - E) and
- * g_phase[l] = 2 n_l / W Im(E_loc,l - E).  All dev arrays.
+ * g_phase[l] = 2 n_l / W Im(E_loc,l - E).  All dev arrays.  local_energy
+ * leaves W = sum of the counts in sums[0]; when samples were lost (DU, MU-d)
+ * a caller may set sums[0] = N_s for the paper's estimator, which divides by
+ * the number of samples drawn.
  */
 int vmc_weights(const double *eloc, const uint64_t *counts, int64_t n, const double *sums,
                 double *g_logabs, double *g_phase, nqs_stream stream);
