@@ -149,3 +149,88 @@ def hf_energy(h, eri, n_alpha, n_beta):
             if s == t:
                 e -= 0.5 * eri[p, q, q, p]
     return e
+
+
+# ------------------------------------------------------------------ Z2 symmetries
+# (paper: "Molecular symmetries").  A Z2 symmetry is a tensor product of
+# identities and Pauli Z on a set m of qubits that commutes with H.  Under the
+# Jordan-Wigner map a term a+_P a+_R a_S a_Q (or a+_P a_Q) carries X / Y on the
+# qubits where its operators do not cancel, f = e_P ^ e_R ^ e_S ^ e_Q, and Z
+# (or identity) elsewhere; Z^m commutes with it iff m and f share an even
+# number of qubits.  The symmetries of H are therefore the m orthogonal over
+# GF(2) to the flip masks f of every term with a nonzero coefficient.
+
+def term_flip_masks(h, eri):
+    """The set of flip masks f of the terms of H with nonzero coefficients."""
+    n = h.shape[0]
+    masks = set()
+    for p in range(n):
+        for q in range(n):
+            if h[p, q] != 0.0:
+                for s in (0, 1):
+                    masks.add((1 << (2 * p + s)) ^ (1 << (2 * q + s)))
+    for p in range(n):
+        for q in range(n):
+            for r in range(n):
+                for t in range(n):
+                    if eri[p, q, r, t] == 0.0:
+                        continue
+                    for s in (0, 1):
+                        for u in (0, 1):
+                            # a+_{p s} a+_{r u} a_{t u} a_{q s}
+                            masks.add((1 << (2 * p + s)) ^ (1 << (2 * r + u)) ^
+                                      (1 << (2 * t + u)) ^ (1 << (2 * q + s)))
+    masks.discard(0)
+    return masks
+
+
+def gf2_null_space(rows, nbits):
+    """Basis of {m : popcount(m & f) even for every f in rows} over GF(2):
+    reduced row echelon form of the rows, one basis vector per free column."""
+    pivots = {}                                  # pivot column -> reduced row
+    for f in rows:
+        for c, r in pivots.items():
+            if (f >> c) & 1:
+                f ^= r
+        if f == 0:
+            continue
+        c = f.bit_length() - 1                   # highest set bit as the pivot
+        for c2 in list(pivots):                  # keep the other rows reduced
+            if (pivots[c2] >> c) & 1:
+                pivots[c2] ^= f
+        pivots[c] = f
+    basis = []
+    for free in range(nbits):
+        if free in pivots:
+            continue
+        m = 1 << free
+        for c, r in pivots.items():              # solve each pivot bit from the free one
+            if (r >> free) & 1:
+                m |= 1 << c
+        basis.append(m)
+    return basis
+
+
+def z2_symmetries(h, eri):
+    """A basis (qubit masks) of the Z2 symmetries of H: the null space of the
+    flip masks of its terms.  It includes the parities of the alpha and beta
+    electron numbers (all even / all odd qubits)."""
+    return gf2_null_space(term_flip_masks(h, eri), 2 * h.shape[0])
+
+
+def gf2_span_key(vectors):
+    """A canonical description of the span of ``vectors`` (its reduced row
+    echelon basis, sorted), to compare two bases of the same space."""
+    pivots = {}
+    for f in vectors:
+        for c, r in pivots.items():
+            if (f >> c) & 1:
+                f ^= r
+        if f == 0:
+            continue
+        c = f.bit_length() - 1
+        for c2 in list(pivots):
+            if (pivots[c2] >> c) & 1:
+                pivots[c2] ^= f
+        pivots[c] = f
+    return tuple(sorted(pivots.values()))

@@ -48,13 +48,26 @@ class AmplitudeModel:
         self.names = list(params.keys())
         self.t = {k: torch.tensor(np.asarray(v), dtype=torch.float64,
                                   requires_grad=requires_grad) for k, v in params.items()}
-        n = self.n
-        tab = torch.zeros((n + 1, n + 1, n + 1, 4), dtype=torch.bool)
+        n, K = self.n, len(sector.z2)
+        # child masks by (position, alpha, beta, Z2 partial eigenvalues of the
+        # prefix as a K-bit index: bit j set when eigenvalue j is -1)
+        tab = torch.zeros((n + 1, n + 1, n + 1, 1 << K, 4), dtype=torch.bool)
         for p in range(n):
             for a in range(n + 1):
                 for b in range(n + 1):
-                    tab[p, a, b] = torch.tensor(sector.child_mask(p, a, b))
+                    for zi in range(1 << K):
+                        z = tuple(-1 if (zi >> j) & 1 else 1 for j in range(K))
+                        tab[p, a, b, zi] = torch.tensor(sector.child_mask(p, a, b, z))
         self.phys = tab
+        # K-bit Z2 index contribution of token t at position p
+        self.z2_flip = torch.zeros((max(n, 1), 4), dtype=torch.long)
+        for p in range(n):
+            for t in range(4):
+                v = 0
+                for j, m in enumerate(sector.z2):
+                    v |= ((((m >> (2 * p)) & 1) & (t & 1)) ^
+                          (((m >> (2 * p + 1)) & 1) & (t >> 1))) << j
+                self.z2_flip[p, t] = v
 
     # -- to be provided by subclasses
     def logits(self, toks):
@@ -71,15 +84,23 @@ class AmplitudeModel:
         a = torch.cat([torch.zeros((B, 1), dtype=torch.long), alpha.cumsum(1)[:, :-1]], 1)
         b = torch.cat([torch.zeros((B, 1), dtype=torch.long), beta.cumsum(1)[:, :-1]], 1)
         p = torch.arange(n).expand(B, n)
-        m = self.phys[p, a, b]
+        flips = self.z2_flip[p, toks]                      # [B, n]
+        zi = torch.zeros((B, n), dtype=torch.long)
+        for q in range(1, n):
+            zi[:, q] = zi[:, q - 1] ^ flips[:, q - 1]
+        m = self.phys[p, a, b, zi]
         m[:, self.mask_levels:, :] = True
         return m
 
     def log_cond(self, toks):
-        """Masked log conditional probabilities, [B, n, 4] (-inf where masked)."""
+        """Masked log conditional probabilities, [B, n, 4] (-inf where masked).
+        After an unphysical prefix no token is physical: the whole row is -inf
+        (probability zero), so a configuration outside the sector has
+        log|psi| = -inf."""
         lg = self.logits(toks)
-        lg = lg.masked_fill(~self.masks(toks), float("-inf"))
-        return torch.log_softmax(lg, dim=-1)
+        m = self.masks(toks)
+        lp = torch.log_softmax(lg.masked_fill(~m, float("-inf")), dim=-1)
+        return lp.masked_fill(~m.any(-1, keepdim=True), float("-inf"))
 
     def log_abs(self, toks):
         lp = self.log_cond(toks)

@@ -192,7 +192,7 @@ def sample_tree(model, n_samples, seed, strategy="MU", d=0, stream=0):
             lg = model.logits(toks)[:, p, :].numpy()
         nxt = []
         for i, (x, cnt, a, b) in enumerate(frontier):
-            phys = sec.child_mask(p, a, b)
+            phys = sec.child_mask(p, a, b, sec.prefix_z2(x, p))
             allowed = phys if p < mask_levels else [True] * 4
             w = child_weights([float(v) for v in lg[i]], allowed)
             split = split_counts(cnt, w, seed, tag | x, p)

@@ -5,7 +5,10 @@ The quantum-number symmetries are the particle number, s(x) = sum_i x_i, and
 the spin projection, s(x) = 1/2 sum_i (-1)^(i-1) x_i with i counted from 1
 (Appendix A).  Both are additive, so the composition operation of Algorithm 1
 is addition.  The spin projection is carried as the integer 2 S_z to keep the
-arithmetic exact.  The target sector is that of the Hartree-Fock determinant.
+arithmetic exact.  Optional Z2 symmetries ("Molecular symmetries"): Z on the
+qubits of a mask m, eigenvalue s(x) = prod over qubits i in m of (-1)^x_i,
+composed by multiplication.  The target sector is that of the Hartree-Fock
+determinant.
 
 Tokens: the sampler moves one spatial orbital (two qubits) per level, token
 t_p = x_{2p} + 2 x_{2p+1} in {0: empty, 1: alpha, 2: beta, 3: both}.  Token
@@ -25,24 +28,31 @@ def hf_config(n, n_alpha, n_beta):
     return x
 
 
-def local_eigs(i, bit):
-    """(particle number, 2 S_z) of qubit i (counted from 1) holding ``bit``."""
-    return (bit, bit if (i - 1) % 2 == 0 else -bit)
+def local_eigs(i, bit, z2=()):
+    """(particle number, 2 S_z, Z2 eigenvalues ...) of qubit i (counted from 1)
+    holding ``bit``."""
+    zs = tuple(-1 if bit and (m >> (i - 1)) & 1 else 1 for m in z2)
+    return (bit, bit if (i - 1) % 2 == 0 else -bit) + zs
 
 
-def eigs(x, N):
-    s = (0, 0)
+def compose(s, e):
+    """The composition of Algorithm 1: addition for the particle number and
+    2 S_z, multiplication for the Z2 eigenvalues."""
+    return (s[0] + e[0], s[1] + e[1]) + tuple(u * v for u, v in zip(s[2:], e[2:]))
+
+
+def eigs(x, N, z2=()):
+    s = (0, 0) + (1,) * len(z2)
     for i in range(1, N + 1):
-        e = local_eigs(i, (x >> (i - 1)) & 1)
-        s = (s[0] + e[0], s[1] + e[1])
+        s = compose(s, local_eigs(i, (x >> (i - 1)) & 1, z2))
     return s
 
 
 class IsPhys:
     """Algorithm 1 with its lookup table, over the N-qubit binary tree."""
 
-    def __init__(self, N, s_ref):
-        self.N, self.s_ref, self.lookup = N, s_ref, {}
+    def __init__(self, N, s_ref, z2=()):
+        self.N, self.s_ref, self.z2, self.lookup = N, s_ref, tuple(z2), {}
 
     def __call__(self, i, s):
         key = (i, s)
@@ -52,39 +62,55 @@ class IsPhys:
             else:
                 children = []
                 for bit in (0, 1):
-                    e = local_eigs(i, bit)
-                    children.append(self(i + 1, (s[0] + e[0], s[1] + e[1])))
+                    children.append(self(i + 1, compose(s, local_eigs(i, bit, self.z2))))
                 self.lookup[key] = children[0] or children[1]
         return self.lookup[key]
 
 
 class Sector:
-    """The (N_alpha, N_beta) sector of an n-spatial-orbital system."""
+    """The (N_alpha, N_beta) sector of an n-spatial-orbital system, optionally
+    restricted by Z2 symmetries (qubit masks ``z2``) to the eigenvalues of the
+    HF determinant."""
 
-    def __init__(self, n, n_alpha, n_beta):
+    def __init__(self, n, n_alpha, n_beta, z2=()):
         self.n, self.n_alpha, self.n_beta = n, n_alpha, n_beta
         self.N = 2 * n
+        self.z2 = tuple(int(m) for m in z2)
         self.x_hf = hf_config(n, n_alpha, n_beta)
-        self.s_ref = eigs(self.x_hf, self.N)
-        self.isphys = IsPhys(self.N, self.s_ref)
+        self.s_ref = eigs(self.x_hf, self.N, self.z2)
+        self.isphys = IsPhys(self.N, self.s_ref, self.z2)
 
-    def token_phys(self, p, a, b):
+    def prefix_z2(self, x, p):
+        """Z2 partial eigenvalues of the first p tokens of x."""
+        return eigs(x & ((1 << (2 * p)) - 1), self.N, self.z2)[2:]
+
+    def token_phys(self, p, a, b, z=()):
         """Physicality of a token prefix of length p holding a alpha and b beta
-        electrons: Algorithm 1 at qubit level 2p + 1."""
-        return self.isphys(2 * p + 1, (a + b, a - b))
+        electrons (and Z2 partial eigenvalues z): Algorithm 1 at qubit level
+        2p + 1."""
+        return self.isphys(2 * p + 1, (a + b, a - b) + (tuple(z) or (1,) * len(self.z2)))
 
-    def child_mask(self, p, a, b):
+    def child_mask(self, p, a, b, z=()):
         """Which of the 4 tokens at position p keep the prefix physical."""
-        return [self.token_phys(p + 1, a + (k & 1), b + (k >> 1)) for k in range(4)]
+        z = tuple(z) or (1,) * len(self.z2)
+        out = []
+        for k in range(4):
+            e = compose(compose((0, 0) + z, local_eigs(2 * p + 1, k & 1, self.z2)),
+                        local_eigs(2 * p + 2, k >> 1, self.z2))
+            out.append(self.token_phys(p + 1, a + (k & 1), b + (k >> 1), e[2:]))
+        return out
 
     def contains(self, x):
-        return eigs(x, self.N) == self.s_ref and x >> self.N == 0
+        return eigs(x, self.N, self.z2) == self.s_ref and x >> self.N == 0
 
     def enumerate(self):
         """Every basis vector of the sector, ascending as integers."""
         alpha = [sum(1 << (2 * p) for p in c) for c in combinations(range(self.n), self.n_alpha)]
         beta = [sum(1 << (2 * p + 1) for p in c) for c in combinations(range(self.n), self.n_beta)]
-        return sorted(a | b for a in alpha for b in beta)
+        out = sorted(a | b for a in alpha for b in beta)
+        if self.z2:
+            out = [x for x in out if eigs(x, self.N, self.z2)[2:] == self.s_ref[2:]]
+        return out
 
 
 def tokens_of(x, n):
