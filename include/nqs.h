@@ -82,6 +82,19 @@ int ham_info(const nqs_ham *ham, int64_t *n_groups, int64_t *n_terms);
  * the term arrays), zmask[T], coef[T].  Any pointer may be NULL. */
 int ham_tables(const nqs_ham *ham, uint64_t *flip, int64_t *off, uint64_t *zmask, double *coef);
 
+/*
+ * ham_z2_symmetries - Z2 symmetries of the Hamiltonian (paper: "Molecular
+ * symmetries"): qubit masks m such that Z on the qubits of m commutes with H,
+ * i.e. m shares an even number of qubits with every flip mask (the null space
+ * over GF(2) of the flip masks).  Returned: a basis of that space modulo the
+ * parities of the alpha and beta electron numbers (which the electron counts
+ * fix); for integrals with point-group selection rules, one mask per
+ * generator of the abelian point group.  masks (host, max_gen entries)
+ * receives min(count, max_gen) masks, n_gen (host) the count.
+ * Errors: NQS_EINVAL (null), NQS_ECAPACITY (count > max_gen; n_gen set).
+ */
+int ham_z2_symmetries(const nqs_ham *ham, int max_gen, uint64_t *masks, int *n_gen);
+
 void ham_destroy(nqs_ham *ham);
 
 /* ------------------------------------------------------------------------ */
@@ -165,10 +178,26 @@ void amp_model_destroy(nqs_model *m);
  * followed by zeros, and its conditionals are masked by its own sector.
  * n_mol = 0 returns the model to its own single sector (untagged words).
  * Errors: NQS_EINVAL (counts out of range), NQS_EUNSUPPORTED (MLP model,
- * dims[0] > 29).
+ * dims[0] > 29, Z2 symmetries set).
  */
 int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n, const int32_t *n_alpha,
                           const int32_t *n_beta);
+
+/*
+ * amp_model_set_z2 - restrict the model's sector by Z2 symmetries (paper:
+ * "Molecular symmetries"; Algorithm 1 with the Z2 eigenvalues composed by
+ * multiplication): n_gen (0..4) qubit masks (host), e.g. from
+ * ham_z2_symmetries, and their target parities targets[j] in {0, 1} (host;
+ * NULL = those of the Hartree-Fock determinant, the paper's choice).  The
+ * masked conditionals, the sampler and amp_forward then keep only
+ * configurations with popcount(x & masks[j]) % 2 == targets[j] for every j;
+ * n_gen = 0 removes the restriction.  The Hamiltonian's connected x' of a
+ * sample stay in its Z2 sector by construction.
+ * Errors: NQS_EINVAL (n_gen out of range, empty masks or masks beyond the
+ * model's qubits, targets not 0/1), NQS_EUNSUPPORTED (the model serves
+ * several molecules).
+ */
+int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks, const int32_t *targets);
 
 /*
  * amp_forward - log|psi(x)| and phase phi(x) for n configurations.

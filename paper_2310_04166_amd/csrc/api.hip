@@ -41,27 +41,43 @@ void check_device() {
     throw Error(NQS_EHIP, "no HIP device available");
 }
 
-// Algorithm 1 evaluated bottom-up over token levels: phys[p][a][b] holds the
-// 4-bit set of tokens k whose child prefix (a + k&1, b + k>>1) at level p+1
-// can still reach (n_alpha, n_beta) at level n.
-std::vector<uint8_t> physical_children(int n, int na, int nb) {
-  const int S = n + 1;
-  std::vector<uint8_t> reach(size_t(S + 1) * S * S, 0);  // reach[p][a][b]
-  auto R = [&](int p, int a, int b) -> uint8_t & { return reach[(size_t(p) * S + a) * S + b]; };
+// Algorithm 1 evaluated bottom-up over token levels: phys[p][a][b][z] holds
+// the 4-bit set of tokens k whose child prefix at level p+1 - a + k&1 alpha,
+// b + k>>1 beta electrons, Z2 parities z ^ dz(p, k) - can still reach
+// (n_alpha, n_beta) and the target parities at level n.  The partial Z2
+// eigenvalues (+-1, composed by multiplication) are carried as parity bits
+// (composed by XOR); without Z2 symmetries z has the single value 0.
+std::vector<uint8_t> physical_children(int n, int na, int nb, const std::vector<uint64_t> &z2,
+                                       uint32_t target) {
+  const int S = n + 1, Z = 1 << int(z2.size());
+  std::vector<uint8_t> reach(size_t(S + 1) * S * S * Z, 0);  // reach[p][a][b][z]
+  auto at = [&](int p, int a, int b, int z) { return ((size_t(p) * S + a) * S + b) * Z + z; };
   for (int a = 0; a <= n; ++a)
-    for (int b = 0; b <= n; ++b) R(n, a, b) = (a == na && b == nb);
-  std::vector<uint8_t> kids(size_t(S) * S * S, 0);
-  for (int p = n - 1; p >= 0; --p)
-    for (int a = 0; a <= n; ++a)
-      for (int b = 0; b <= n; ++b) {
-        uint8_t mask = 0;
-        for (int k = 0; k < 4; ++k) {
-          const int a2 = a + (k & 1), b2 = b + (k >> 1);
-          if (a2 <= n && b2 <= n && R(p + 1, a2, b2)) mask |= uint8_t(1u << k);
-        }
-        kids[(size_t(p) * S + a) * S + b] = mask;
-        R(p, a, b) = mask != 0;
+    for (int b = 0; b <= n; ++b)
+      for (int z = 0; z < Z; ++z) reach[at(n, a, b, z)] = (a == na && b == nb && uint32_t(z) == target);
+  std::vector<uint8_t> kids(size_t(S) * S * S * Z, 0);
+  for (int p = n - 1; p >= 0; --p) {
+    int dz[4];                                       // parity change of token k at level p
+    for (int k = 0; k < 4; ++k) {
+      dz[k] = 0;
+      for (size_t j = 0; j < z2.size(); ++j) {
+        const int bit = int(((z2[j] >> (2 * p)) & 1ull) & uint64_t(k & 1)) ^
+                        int(((z2[j] >> (2 * p + 1)) & 1ull) & uint64_t(k >> 1));
+        dz[k] |= bit << j;
       }
+    }
+    for (int a = 0; a <= n; ++a)
+      for (int b = 0; b <= n; ++b)
+        for (int z = 0; z < Z; ++z) {
+          uint8_t mask = 0;
+          for (int k = 0; k < 4; ++k) {
+            const int a2 = a + (k & 1), b2 = b + (k >> 1);
+            if (a2 <= n && b2 <= n && reach[at(p + 1, a2, b2, z ^ dz[k])]) mask |= uint8_t(1u << k);
+          }
+          kids[at(p, a, b, z)] = mask;
+          reach[at(p, a, b, z)] = mask != 0;
+        }
+  }
   return kids;
 }
 
@@ -78,7 +94,12 @@ void install_sectors(nqs_model &m, const std::vector<std::array<int, 3>> &secs, 
     si.nb = sc[2];
     si.mask_levels = m.strategy == NQS_MU ? n : m.strategy == NQS_DU ? 0 : std::max(n - m.dlev, 0);
     si.phys_off = int64_t(phys.size());
-    const std::vector<uint8_t> t = physical_children(n, si.na, si.nb);
+    // Z2 symmetries only for the model's own sector (untagged words)
+    const std::vector<uint64_t> none;
+    const std::vector<uint64_t> &z2 = tagged ? none : m.z2;
+    si.nz2 = int32_t(z2.size());
+    for (size_t j = 0; j < z2.size(); ++j) si.z2[j] = z2[j];
+    const std::vector<uint8_t> t = physical_children(n, si.na, si.nb, z2, tagged ? 0u : m.z2_target);
     phys.insert(phys.end(), t.begin(), t.end());
     info.push_back(si);
   }
@@ -201,6 +222,8 @@ extern "C" int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n,
     NQS_REQUIRE(n && n_alpha && n_beta, NQS_EINVAL, "amp_model_set_sectors: null array");
     NQS_REQUIRE(m->kind == NQS_MODEL_TRANSFORMER, NQS_EUNSUPPORTED,
                 "amp_model_set_sectors: only the transformer serves several molecules");
+    NQS_REQUIRE(m->z2.empty(), NQS_EUNSUPPORTED,
+                "amp_model_set_sectors: a model with Z2 symmetries serves one molecule");
     NQS_REQUIRE(2 * m->n <= kTagShift, NQS_EUNSUPPORTED,
                 "amp_model_set_sectors: more than 29 tokens leave no room for the molecule index");
     std::vector<std::array<int, 3>> secs;
@@ -212,6 +235,36 @@ extern "C" int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n,
       secs.push_back({n[i], n_alpha[i], n_beta[i]});
     }
     install_sectors(*m, secs, true);
+  });
+}
+
+extern "C" int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks,
+                                const int32_t *targets) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_z2: null handle");
+    NQS_REQUIRE(!m->tagged, NQS_EUNSUPPORTED,
+                "amp_model_set_z2: the model serves several molecules");
+    NQS_REQUIRE(n_gen >= 0 && n_gen <= 4, NQS_EINVAL, "amp_model_set_z2: between 0 and 4 masks");
+    NQS_REQUIRE(n_gen == 0 || masks, NQS_EINVAL, "amp_model_set_z2: null mask array");
+    const uint64_t qubits = 2 * m->n >= 64 ? ~0ull : ((1ull << (2 * m->n)) - 1);
+    // the Hartree-Fock determinant fixes the target eigenvalues unless given
+    uint64_t hf = 0;
+    for (int p = 0; p < m->na; ++p) hf |= 1ull << (2 * p);
+    for (int p = 0; p < m->nb; ++p) hf |= 1ull << (2 * p + 1);
+    std::vector<uint64_t> z2;
+    uint32_t target = 0;
+    for (int j = 0; j < n_gen; ++j) {
+      NQS_REQUIRE(masks[j] != 0 && (masks[j] & ~qubits) == 0, NQS_EINVAL,
+                  "amp_model_set_z2: a mask is empty or names qubits beyond the model's");
+      NQS_REQUIRE(!targets || targets[j] == 0 || targets[j] == 1, NQS_EINVAL,
+                  "amp_model_set_z2: target parities are 0 or 1");
+      const uint32_t t = targets ? uint32_t(targets[j]) : uint32_t(__builtin_popcountll(hf & masks[j]) & 1);
+      target |= t << j;
+      z2.push_back(masks[j]);
+    }
+    m->z2 = std::move(z2);
+    m->z2_target = target;
+    install_sectors(*m, {{m->n, m->na, m->nb}}, false);
   });
 }
 

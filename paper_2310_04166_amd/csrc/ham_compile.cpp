@@ -185,6 +185,73 @@ extern "C" int ham_tables(const nqs_ham *H, uint64_t *flip, int64_t *off, uint64
   });
 }
 
+// Z2 symmetries (paper: "Molecular symmetries"): Z on the qubits of m commutes
+// with a Pauli string iff m and the string's X/Y support f share an even number
+// of qubits, so the symmetries of H are the null space over GF(2) of its flip
+// masks.  Elimination column by column: each pivot row owns its lowest set
+// bit, which the other rows do not contain; every free column c then gives the
+// null vector e_c + sum of the pivot columns whose row contains c.  Returned:
+// the null vectors that are independent modulo the parities of the alpha and
+// beta electron numbers (which the electron counts already fix).
+extern "C" int ham_z2_symmetries(const nqs_ham *H, int max_gen, uint64_t *masks, int *n_gen) {
+  return nqs::guarded([&] {
+    NQS_REQUIRE(H && n_gen, NQS_EINVAL, "ham_z2_symmetries: null argument");
+    NQS_REQUIRE(max_gen >= 0 && (max_gen == 0 || masks), NQS_EINVAL,
+                "ham_z2_symmetries: null mask array");
+    const int N = H->N;
+    std::vector<uint64_t> rows;             // reduced rows, pivot = lowest set bit
+    std::vector<int> pivot_of(N, -1);       // column -> row index
+    for (uint64_t f : H->flip) {
+      for (size_t r = 0; r < rows.size(); ++r) {
+        const int c = __builtin_ctzll(rows[r]);
+        if ((f >> c) & 1ull) f ^= rows[r];
+      }
+      if (f == 0) continue;
+      const int c = __builtin_ctzll(f);
+      for (auto &r : rows)
+        if ((r >> c) & 1ull) r ^= f;
+      pivot_of[c] = int(rows.size());
+      rows.push_back(f);
+    }
+    // null vectors, kept when independent of the alpha / beta parity masks
+    // and of the vectors kept before (the electron counts fix those parities)
+    uint64_t alpha = 0;
+    for (int p = 0; p < H->n; ++p) alpha |= 1ull << (2 * p);
+    std::vector<uint64_t> span = {alpha, alpha << 1};   // reduced, pivot = highest bit
+    auto reduce = [&](uint64_t v) {
+      for (uint64_t b : span)
+        if ((v >> (63 - __builtin_clzll(b))) & 1ull) v ^= b;
+      return v;
+    };
+    {
+      std::vector<uint64_t> echelon;
+      for (uint64_t b : span) {
+        for (uint64_t e : echelon)
+          if ((b >> (63 - __builtin_clzll(e))) & 1ull) b ^= e;
+        if (b) echelon.push_back(b);
+      }
+      span = echelon;
+    }
+    int count = 0;
+    for (int c = 0; c < N; ++c) {
+      if (pivot_of[c] >= 0) continue;
+      uint64_t m = 1ull << c;
+      for (int p = 0; p < N; ++p)
+        if (pivot_of[p] >= 0 && ((rows[size_t(pivot_of[p])] >> c) & 1ull)) m |= 1ull << p;
+      const uint64_t r = reduce(m);
+      if (r == 0) continue;
+      for (auto &b : span)                 // keep the span reduced on the new pivot
+        if ((b >> (63 - __builtin_clzll(r))) & 1ull) b ^= r;
+      span.push_back(r);
+      if (count < max_gen) masks[count] = m;
+      ++count;
+    }
+    *n_gen = count;
+    NQS_REQUIRE(count <= max_gen, NQS_ECAPACITY,
+                "ham_z2_symmetries: more symmetries than max_gen (n_gen holds the count)");
+  });
+}
+
 extern "C" void ham_destroy(nqs_ham *H) { delete H; }
 
 void nqs_ham::upload() {

@@ -6,11 +6,14 @@
 #include "common.h"
 
 // One molecule (symmetry sector) served by a model: its token count,
-// electrons, number of masked levels and where its physical-children table
-// starts in the model's concatenated tables ([(n+1)^3] 4-bit masks each).
+// electrons, number of masked levels, optional Z2 symmetries (qubit masks) and
+// where its physical-children table starts in the model's concatenated tables
+// ([(n+1)^3 2^nz2] 4-bit masks each, the last index the prefix's Z2 parities).
 struct nqs_sector_info {
   int32_t n, na, nb, mask_levels;
   int64_t phys_off;
+  int32_t nz2, pad;
+  uint64_t z2[4];
 };
 
 namespace nqs {
@@ -35,9 +38,15 @@ __device__ inline const nqs_sector_info &sector_of(const Sectors &S, uint64_t x)
 __device__ inline uint64_t occupation(const Sectors &S, uint64_t x) {
   return S.tagged ? (x & kOccMask) : x;
 }
-// 4-bit set of physical tokens at level t after a alpha / b beta electrons
-__device__ inline int phys_mask(const Sectors &S, const nqs_sector_info &si, int t, int a, int b) {
-  return S.phys[si.phys_off + (int64_t(t) * (si.n + 1) + a) * (si.n + 1) + b];
+// 4-bit set of physical tokens at level t after a alpha / b beta electrons;
+// occ holds the occupation bits of the prefix (bits of later tokens ignored),
+// whose Z2 parities select the table entry
+__device__ inline int phys_mask(const Sectors &S, const nqs_sector_info &si, int t, int a, int b,
+                                uint64_t occ) {
+  const uint64_t below = t >= 32 ? ~0ull : ((1ull << (2 * t)) - 1);
+  int par = 0;
+  for (int j = 0; j < si.nz2; ++j) par |= (__popcll(occ & below & si.z2[j]) & 1) << j;
+  return S.phys[si.phys_off + ((int64_t(t) * (si.n + 1) + a) * (si.n + 1) + b) * (1 << si.nz2) + par];
 }
 }  // namespace nqs
 
@@ -52,6 +61,8 @@ struct nqs_model {
   std::vector<uint8_t> phys_host;     // concatenated physical-child tables of the sectors
   std::vector<nqs_sector_info> sec_host;  // one entry, or one per molecule when tagged
   int tagged = 0;                     // configuration words carry the molecule index
+  std::vector<uint64_t> z2;           // Z2 symmetries of the model's own sector (qubit masks)
+  uint32_t z2_target = 0;             // their parities in the target sector (bit j)
   int64_t act_budget = int64_t(1) << 30;  // bytes of activations per layer-by-layer chunk
 
   nqs::DevBuf master;                 // canonical parameters (double in FP64, float otherwise)

@@ -89,7 +89,7 @@ __global__ void logabs_kernel(const uint64_t *x, int64_t B, int Tn, const T *log
   double s = 0.0;
   for (int t = 0; t < si.n; ++t) {
     const int tk = tok_of(xb, t);
-    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c) : 0xF;
+    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c, occupation(S, xb)) : 0xF;
     if (!((allow >> tk) & 1)) { s = -INFINITY; break; }
     const T *l = logits + (b * Tn + t) * stride;
     double mx = -INFINITY;
@@ -122,7 +122,7 @@ __global__ void dlogits_kernel(const uint64_t *x, int64_t B, int Tn, const T *lo
       continue;
     }
     const int tk = tok_of(xb, t);
-    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c) : 0xF;
+    const int allow = t < si.mask_levels ? phys_mask(S, si, t, a, c, occupation(S, xb)) : 0xF;
     if (!((allow >> tk) & 1)) ok = false;
     const T *l = logits + (b * Tn + t) * stride;
     double mx = -INFINITY;

@@ -150,7 +150,7 @@ __global__ void split_kernel(const uint64_t *__restrict__ prefix, const uint64_t
   }
   const uint64_t occ = occupation(S, x);
   const int a = __popcll(occ & kAlphaBits), b = __popcll(occ & kBetaBits);
-  const int ph = phys_mask(S, si, p, a, b);
+  const int ph = phys_mask(S, si, p, a, b, occ);
   const int allow = p < si.mask_levels ? ph : 0xF;
   const double *l = logits + 4 * i;
   double mx = -INFINITY;

@@ -524,7 +524,7 @@ fused_kernel(FusedArgs a) {
       const uint64_t below = (t == 0) ? 0ull : (~0ull >> (64 - 2 * t));
       const int na = __popcll(x & below & 0x5555555555555555ull);
       const int nb = __popcll(x & below & 0xAAAAAAAAAAAAAAAAull);
-      const int allow = t < si.mask_levels ? phys_mask(a.sec, si, t, na, nb) : 0xF;
+      const int allow = t < si.mask_levels ? phys_mask(a.sec, si, t, na, nb, x) : 0xF;
       const int tk = int((x >> (2 * t)) & 3ull);
       float mx = -INFINITY;
 #pragma unroll

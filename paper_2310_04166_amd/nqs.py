@@ -38,6 +38,7 @@ _SIGS = {
     "ham_info": ([_vp, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "ham_tables": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "ham_destroy": ([_vp], None),
+    "ham_z2_symmetries": ([_vp, C.c_int, _vp, C.POINTER(_i32)], C.c_int),
     "amp_model_create": ([C.c_int, _vp, C.c_int, _vp, _i64, C.c_int, C.c_int, C.c_int,
                           C.POINTER(_vp)], C.c_int),
     "amp_model_info": ([_vp, C.POINTER(_i64), C.POINTER(_i32)], C.c_int),
@@ -58,6 +59,7 @@ _SIGS = {
     "adam_update": ([_vp, _vp, _vp, _vp, _i64, C.c_int, _dbl, _dbl, _dbl, _dbl, _i64, _vp],
                     C.c_int),
     "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
+    "amp_model_set_z2": ([_vp, C.c_int, _vp, _vp], C.c_int),
     "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
                              C.POINTER(_u64), _vp], C.c_int),
     "batch_create": ([_vp, C.c_int, _vp, C.POINTER(_vp)], C.c_int),
@@ -133,6 +135,14 @@ class Hamiltonian:
         _check(lib().ham_info(self.handle, C.byref(G), C.byref(T)))
         return G.value, T.value
 
+    def z2_symmetries(self, max_gen=16):
+        """Qubit masks of the Hamiltonian's Z2 symmetries beyond the electron
+        parities (``ham_z2_symmetries``)."""
+        masks = np.zeros(max_gen, np.uint64)
+        n = _i32()
+        _check(lib().ham_z2_symmetries(self.handle, max_gen, _ptr(masks), C.byref(n)))
+        return [int(v) for v in masks[:n.value]]
+
     def tables(self):
         G, T = self.info()
         flip = np.zeros(G, np.uint64)
@@ -192,6 +202,13 @@ class Model:
         a = np.ascontiguousarray(np.asarray(sectors, dtype=np.int32).reshape(-1, 3).T)
         _check(lib().amp_model_set_sectors(self.handle, a.shape[1], _ptr(a[0].copy()),
                                            _ptr(a[1].copy()), _ptr(a[2].copy())))
+
+    def set_z2(self, masks, targets=None):
+        """Restrict the sector by Z2 symmetries (``amp_model_set_z2``); targets
+        default to the Hartree-Fock determinant's parities."""
+        m = np.ascontiguousarray([int(v) for v in masks], dtype=np.uint64)
+        t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib().amp_model_set_z2(self.handle, len(m), _ptr(m) if len(m) else None, _ptr(t)))
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

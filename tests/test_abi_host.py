@@ -141,3 +141,21 @@ def test_error_codes(nqs):
     with pytest.raises(nqs.NQSError) as e:
         nqs.Model(nqs.MODEL_MLP, [40, 2, 2, 64], np.zeros(10), "fp64")
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("n,irreps,count", [
+    (6, None, 0),                                   # generic integrals: no point group
+    (6, [0, 0, 1, 2, 1, 3], 2),                     # Z2 x Z2 (C2v-like)
+    (8, [0, 1, 2, 4, 3, 5, 6, 7], 3),               # Z2^3 (D2h-like)
+])
+def test_z2_symmetries_span_the_oracle_null_space(nqs, n, irreps, count):
+    """ham_z2_symmetries (host C++, from the compiled flip groups) together with
+    the alpha / beta parity masks spans the oracle's null space of the terms'
+    flip masks (built from the integrals)."""
+    from oracle.hamiltonian import gf2_span_key, z2_symmetries
+    h, eri = make_integrals(n, 2 * n, 7, irreps=irreps)
+    H = nqs.ham_compile(h, eri, n // 2, n // 2)
+    got = H.z2_symmetries()
+    alpha = sum(1 << (2 * p) for p in range(n))
+    assert len(got) == count
+    assert gf2_span_key(got + [alpha, alpha << 1]) == gf2_span_key(z2_symmetries(h, eri))
