@@ -184,12 +184,15 @@ def sample_tree(model, n_samples, seed, strategy="MU", d=0, stream=0):
     frontier = [(0, n_samples, 0, 0)]     # (prefix bits, count, alpha, beta)
     lost = 0
     for p in range(n):
-        toks = torch.zeros((len(frontier), n), dtype=torch.long)
-        for i, (x, _, _, _) in enumerate(frontier):
-            for q in range(p):
-                toks[i, q] = ((x >> (2 * q)) & 1) + 2 * ((x >> (2 * q + 1)) & 1)
         with torch.no_grad():
-            lg = model.logits(toks)[:, p, :].numpy()
+            if hasattr(model, "token_logits"):      # per-qubit ansatz: token log-probabilities
+                lg = model.token_logits([f[0] for f in frontier], p).numpy()
+            else:
+                toks = torch.zeros((len(frontier), n), dtype=torch.long)
+                for i, (x, _, _, _) in enumerate(frontier):
+                    for q in range(p):
+                        toks[i, q] = ((x >> (2 * q)) & 1) + 2 * ((x >> (2 * q + 1)) & 1)
+                lg = model.logits(toks)[:, p, :].numpy()
         nxt = []
         for i, (x, cnt, a, b) in enumerate(frontier):
             phys = sec.child_mask(p, a, b, sec.prefix_z2(x, p))

@@ -8,13 +8,14 @@ the HIP path can both read the same inputs without sharing any computation.
 """
 from .integrals import make_integrals
 from .params import (mlp_param_spec, transformer_param_spec, make_mlp_params,
-                     make_transformer_params, flatten_params, unflatten_params)
+                     make_transformer_params, flatten_params, unflatten_params,
+                     nade_param_spec, make_nade_params)
 from .workloads import (WORKLOADS, BATCHING_MODEL, workload, batching_molecules,
                         batching_params, batching_workload)
 
 __all__ = [
     "make_integrals", "mlp_param_spec", "transformer_param_spec",
     "make_mlp_params", "make_transformer_params", "flatten_params",
-    "unflatten_params", "WORKLOADS", "BATCHING_MODEL", "workload", "batching_molecules",
-    "batching_params", "batching_workload",
+    "unflatten_params", "nade_param_spec", "make_nade_params", "WORKLOADS",
+    "BATCHING_MODEL", "workload", "batching_molecules", "batching_params", "batching_workload",
 ]

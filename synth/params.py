@@ -108,3 +108,31 @@ def unflatten_params(flat, spec):
         o += size
     assert o == len(flat), (o, len(flat))
     return out
+
+
+def nade_param_spec(n, hidden=64):
+    """The paper's per-qubit ansatz: one complex-weight MLP per qubit i of the
+    2n, reading the i previous bits, two hidden layers of width ``hidden`` and
+    two complex outputs.  Real and imaginary parts are separate real tensors,
+    matrices (in, out)."""
+    spec = []
+    for i in range(2 * n):
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.w1_{part}", (i, hidden)))
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.b1_{part}", (hidden,)))
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.w2_{part}", (hidden, hidden)))
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.b2_{part}", (hidden,)))
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.w3_{part}", (hidden, 2)))
+        for part in ("re", "im"):
+            spec.append((f"nade{i}.b3_{part}", (2,)))
+    return spec
+
+
+def make_nade_params(n, hidden=64, seed=0, std=0.1, bias_std=0.0, round_to=None):
+    """Weights N(0, std) (real and imaginary parts drawn independently, in spec
+    order), biases N(0, bias_std)."""
+    return _init(nade_param_spec(n, hidden), seed, std, round_to, {}, bias_std)
