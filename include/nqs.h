@@ -103,6 +103,7 @@ void ham_destroy(nqs_ham *ham);
 
 #define NQS_MODEL_MLP         1   /* per-token NADE-like MLPs (Appendix B)      */
 #define NQS_MODEL_TRANSFORMER 2   /* decoder-only transformer + phase MLP       */
+#define NQS_MODEL_NADE        3   /* the paper's per-qubit complex-weight MLPs  */
 
 #define NQS_FP64 1   /* every operation in double                            */
 #define NQS_FP32 2   /* every operation in float                             */
@@ -122,6 +123,7 @@ void ham_destroy(nqs_ham *ham);
  * dims (host):
  *   MLP:         {n, n_alpha, n_beta, hidden}
  *   TRANSFORMER: {n, n_alpha, n_beta, d_model, n_layers, n_heads, ffn, phase_hidden}
+ *   NADE:        {n, n_alpha, n_beta, hidden}
  * params (host, n_params doubles) is the canonical parameter vector: the
  * concatenation of the tensors below, each row-major, matrices (in, out) so
  * that a layer computes y = x W + b.
@@ -138,6 +140,14 @@ void ham_destroy(nqs_ham *ham);
  *      Pre-LN blocks (eps 1e-5), causal attention with scale 1/sqrt(d/heads),
  *      tanh-form GELU, input [BOS, x_0 .. x_{n-2}], output p = logits of
  *      token p; phase = MLP(one-hot of all n tokens) with GELU.
+ *   NADE (paper: Appendix "ANQS architecture"), for qubit i = 0..2n-1: w1_re,
+ *      w1_im (i, hidden), b1_re, b1_im (hidden), w2_re, w2_im (hidden,
+ *      hidden), b2_re, b2_im (hidden), w3_re, w3_im (hidden, 2), b3_re,
+ *      b3_im (2): complex weights W = W_re + i W_im; on the previous bits x,
+ *      h1 = tanh(x W1 + b1) (complex tanh), h2 = LeReLU(Re(h1 W2 + b2)) +
+ *      i LeReLU(Im(h1 W2 + b2)), z = h2 W3 + b3, log psi_i(v | x_<i) = z_v -
+ *      1/2 log(e^{2 Re z_0} + e^{2 Re z_1}).  Mask-Unphysical per qubit: with
+ *      one physical value v, psi_i(v) = 1 and psi_i(1 - v) = 0.  FP64 / FP32.
  * log|psi(x)| = 1/2 sum_p log softmax over allowed tokens; phase separate.
  * Errors: NQS_EINVAL (sizes, n_params mismatch), NQS_EUNSUPPORTED (n > 32,
  * d_model not a multiple of n_heads, unknown kind / precision / strategy),

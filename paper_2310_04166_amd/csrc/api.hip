@@ -125,13 +125,13 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
   return guarded([&] {
     NQS_REQUIRE(out && dims && params, NQS_EINVAL, "amp_model_create: null argument");
     *out = nullptr;
-    NQS_REQUIRE(kind == NQS_MODEL_MLP || kind == NQS_MODEL_TRANSFORMER, NQS_EUNSUPPORTED,
-                "amp_model_create: unknown model kind");
+    NQS_REQUIRE(kind == NQS_MODEL_MLP || kind == NQS_MODEL_TRANSFORMER || kind == NQS_MODEL_NADE,
+                NQS_EUNSUPPORTED, "amp_model_create: unknown model kind");
     NQS_REQUIRE(precision == NQS_FP64 || precision == NQS_FP32 || precision == NQS_BF16,
                 NQS_EUNSUPPORTED, "amp_model_create: unknown precision");
     NQS_REQUIRE(strategy == NQS_MU || strategy == NQS_DU || strategy == NQS_MUD, NQS_EUNSUPPORTED,
                 "amp_model_create: unknown strategy");
-    NQS_REQUIRE(n_dims == (kind == NQS_MODEL_MLP ? 4 : 8), NQS_EINVAL,
+    NQS_REQUIRE(n_dims == (kind == NQS_MODEL_TRANSFORMER ? 8 : 4), NQS_EINVAL,
                 "amp_model_create: wrong number of dims");
     auto m = std::make_unique<nqs_model>();
     m->kind = kind;
@@ -154,7 +154,18 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
       m->off.push_back(o);
       o += size;
     };
-    if (kind == NQS_MODEL_MLP) {
+    if (kind == NQS_MODEL_NADE) {
+      m->hid = dims[3];
+      NQS_REQUIRE(m->hid >= 1, NQS_EINVAL, "amp_model_create: hidden < 1");
+      NQS_REQUIRE(precision != NQS_BF16, NQS_EUNSUPPORTED,
+                  "amp_model_create: the per-qubit ansatz has no bf16 mode");
+      const int h = m->hid;
+      for (int i = 0; i < 2 * n; ++i) {
+        add(int64_t(i) * h); add(int64_t(i) * h); add(h); add(h);
+        add(int64_t(h) * h); add(int64_t(h) * h); add(h); add(h);
+        add(int64_t(h) * 2); add(int64_t(h) * 2); add(2); add(2);
+      }
+    } else if (kind == NQS_MODEL_MLP) {
       m->hid = dims[3];
       NQS_REQUIRE(m->hid >= 1, NQS_EINVAL, "amp_model_create: hidden < 1");
       NQS_REQUIRE(precision != NQS_BF16, NQS_EUNSUPPORTED, "amp_model_create: MLP has no bf16 mode");
@@ -204,6 +215,7 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
                        hipMemcpyHostToDevice));
     }
     if (precision == NQS_BF16) fused_pack(*m, nullptr);
+    if (kind == NQS_MODEL_NADE) nade_pack(*m, nullptr);
     HIP_OK(hipDeviceSynchronize());
     *out = m.release();
   });
@@ -287,6 +299,7 @@ extern "C" int amp_model_sync(nqs_model *m, nqs_stream stream) {
   return guarded([&] {
     NQS_REQUIRE(m, NQS_EINVAL, "amp_model_sync: null handle");
     if (m->precision == NQS_BF16) fused_pack(*m, as_stream(stream));
+    if (m->kind == NQS_MODEL_NADE) nade_pack(*m, as_stream(stream));
   });
 }
 
@@ -315,6 +328,7 @@ extern "C" int amp_model_set_params(nqs_model *m, const double *host_in) {
       HIP_OK(hipMemcpy(m->master.ptr, f.data(), size_t(m->P) * 4, hipMemcpyHostToDevice));
     }
     if (m->precision == NQS_BF16) fused_pack(*m, nullptr);
+    if (m->kind == NQS_MODEL_NADE) nade_pack(*m, nullptr);
     HIP_OK(hipDeviceSynchronize());
   });
 }

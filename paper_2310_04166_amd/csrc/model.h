@@ -62,6 +62,7 @@ struct nqs_model {
   std::vector<nqs_sector_info> sec_host;  // one entry, or one per molecule when tagged
   int tagged = 0;                     // configuration words carry the molecule index
   std::vector<uint64_t> z2;           // Z2 symmetries of the model's own sector (qubit masks)
+  std::vector<int64_t> nade_off;      // per-qubit ansatz: offsets of its derived blocks in packed
   uint32_t z2_target = 0;             // their parities in the target sector (bit j)
   int64_t act_budget = int64_t(1) << 30;  // bytes of activations per layer-by-layer chunk
 
@@ -122,6 +123,8 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
                    double *cond_out, int cond_p, hipStream_t s, const int64_t *count = nullptr,
                    FusedTile tile = FusedTile{});
 void fused_pack(nqs_model &m, hipStream_t s);
+// per-qubit ansatz: block matrices of the complex layers from the canonical parameters
+void nade_pack(nqs_model &m, hipStream_t s);
 // Kernel timing of the fused kernel (nqs_timing_*): whether it is on, and a
 // record measured by a caller (events inside a captured graph).
 bool timing_on();

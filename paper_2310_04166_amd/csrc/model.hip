@@ -4,6 +4,7 @@
 // per-token MLP.  The physicality of a prefix comes from Algorithm 1, filled
 // bottom-up into a (position, n_alpha, n_beta) table when the model is made.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "model.h"
@@ -585,12 +586,426 @@ void mlp_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double
   }
 }
 
+// ------------------------------------------------------------------ NADE ---
+// The paper's per-qubit ansatz with complex weights (Appendix "ANQS
+// architecture"): qubit i has an MLP reading the i previous bits, h1 =
+// tanh(x W1 + b1) (complex tanh), h2 = LeReLU(Re) + i LeReLU(Im) of h1 W2 + b2,
+// z = h2 W3 + b3 (two complex outputs), log psi_i(v) = z_v - 1/2 LSE(2 Re z).
+// A complex layer is one real GEMM: [Re h, Im h] times the block matrix
+// [[Re W, Im W], [-Im W, Re W]] gives [Re(hW), Im(hW)]; the blocks are built
+// from the canonical parameters (nade_pack).  Token p of the four-way sampler
+// is qubits 2p (alpha) and 2p + 1 (beta): its outputs are the token
+// log-probabilities 2 Re log psi_2p(a) + 2 Re log psi_2p+1(b | a) and phases
+// Im log psi_2p(a) + Im log psi_2p+1(b | a), so the MLP model's log-softmax,
+// phase and gradient kernels apply to them unchanged.  Mask-Unphysical per
+// qubit: with one physical value v, psi_i(v) = 1 and psi_i(1 - v) = 0.
+
+// derived blocks of qubit i, in order: W1cat (i x 2H), b1cat (2H), W2blk
+// (2H x 2H), b2cat (2H), W3blk (2H x 4, columns Re z0, Re z1, Im z0, Im z1), b3cat (4)
+constexpr int kNadeBlocks = 6;
+
+template <class T>
+__global__ void nade_pack_kernel(const T *w1r, const T *w1i, const T *b1r, const T *b1i,
+                                 const T *w2r, const T *w2i, const T *b2r, const T *b2i,
+                                 const T *w3r, const T *w3i, const T *b3r, const T *b3i, int in,
+                                 int H, T *W1, T *B1, T *W2, T *B2, T *W3, T *B3) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t H2 = 2 * H;
+  const int64_t n1 = int64_t(in) * H2, n2 = H2 * H2, n3 = H2 * 4;
+  if (idx < n1) {
+    const int64_t j = idx / H2, c = idx % H2;
+    W1[idx] = c < H ? w1r[j * H + c] : w1i[j * H + c - H];
+  } else if (idx < n1 + H2) {
+    const int64_t c = idx - n1;
+    B1[c] = c < H ? b1r[c] : b1i[c - H];
+  } else if (idx < n1 + H2 + n2) {
+    const int64_t e = idx - n1 - H2, r = e / H2, c = e % H2;
+    const int64_t rr = r % H, cc = c % H;
+    W2[e] = (r < H) == (c < H) ? w2r[rr * H + cc] : (r < H ? w2i[rr * H + cc] : -w2i[rr * H + cc]);
+  } else if (idx < n1 + 2 * H2 + n2) {
+    const int64_t c = idx - n1 - H2 - n2;
+    B2[c] = c < H ? b2r[c] : b2i[c - H];
+  } else if (idx < n1 + 2 * H2 + n2 + n3) {
+    const int64_t e = idx - n1 - 2 * H2 - n2, r = e / 4, c = e % 4;
+    const int64_t rr = r % H, v = c % 2;
+    W3[e] = (r < H) == (c < 2) ? w3r[rr * 2 + v] : (r < H ? w3i[rr * 2 + v] : -w3i[rr * 2 + v]);
+  } else if (idx < n1 + 2 * H2 + n2 + n3 + 4) {
+    const int64_t c = idx - n1 - 2 * H2 - n2 - n3;
+    B3[c] = c < 2 ? b3r[c] : b3i[c - 2];
+  }
+}
+
+// gradient of the derived blocks folded back onto the canonical parameters
+template <class T>
+__global__ void nade_fold_kernel(const double *G, int in, int H, double *acc, int64_t o_w1r,
+                                 int64_t o_w1i, int64_t o_b1r, int64_t o_b1i, int64_t o_w2r,
+                                 int64_t o_w2i, int64_t o_b2r, int64_t o_b2i, int64_t o_w3r,
+                                 int64_t o_w3i, int64_t o_b3r, int64_t o_b3i) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t H2 = 2 * H;
+  const double *G1 = G, *gb1 = G1 + int64_t(in) * H2, *G2 = gb1 + H2, *gb2 = G2 + H2 * H2,
+               *G3 = gb2 + H2, *gb3 = G3 + H2 * 4;
+  const int64_t n1 = int64_t(in) * H, n2 = int64_t(H) * H, n3 = int64_t(H) * 2;
+  int64_t e = idx;
+  if (e < n1) {                                       // w1: rows j, columns c
+    const int64_t j = e / H, c = e % H;
+    acc[o_w1r + e] += G1[j * H2 + c];
+    acc[o_w1i + e] += G1[j * H2 + H + c];
+    return;
+  }
+  e -= n1;
+  if (e < H) {
+    acc[o_b1r + e] += gb1[e];
+    acc[o_b1i + e] += gb1[H + e];
+    return;
+  }
+  e -= H;
+  if (e < n2) {                                       // w2 from the four blocks
+    const int64_t r = e / H, c = e % H;
+    acc[o_w2r + e] += G2[r * H2 + c] + G2[(H + r) * H2 + H + c];
+    acc[o_w2i + e] += G2[r * H2 + H + c] - G2[(H + r) * H2 + c];
+    return;
+  }
+  e -= n2;
+  if (e < H) {
+    acc[o_b2r + e] += gb2[e];
+    acc[o_b2i + e] += gb2[H + e];
+    return;
+  }
+  e -= H;
+  if (e < n3) {
+    const int64_t r = e / 2, v = e % 2;
+    acc[o_w3r + e] += G3[r * 4 + v] + G3[(H + r) * 4 + 2 + v];
+    acc[o_w3i + e] += G3[r * 4 + 2 + v] - G3[(H + r) * 4 + v];
+    return;
+  }
+  e -= n3;
+  if (e < 2) {
+    acc[o_b3r + e] += gb3[e];
+    acc[o_b3i + e] += gb3[2 + e];
+  }
+}
+
+// X[b][c] = bit c of x for c < 2p, X[b][2p] = a (row stride 2p + 1)
+template <class T>
+__global__ void nade_bits_kernel(const uint64_t *x, int64_t B, int p, int a, T *X) {
+  const int w = 2 * p + 1;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= B * w) return;
+  const int c = int(idx % w);
+  X[idx] = c < 2 * p ? T((x[idx / w] >> c) & 1ull) : T(a);
+}
+
+// complex tanh in place on rows [Re(H) | Im(H)]: with r = e^{-2|a|},
+// tanh(a + ib) = (sgn(a)(1 - r^2) + 2i r sin 2b) / (1 + 2r cos 2b + r^2)
+template <class T>
+__global__ void nade_ctanh_kernel(T *h, int64_t B, int H) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= B * H) return;
+  T *row = h + (idx / H) * 2 * H;
+  const int64_t j = idx % H;
+  const T a = row[j], b = row[H + j];
+  const T r = exp(T(-2) * fabs(a));
+  const T den = T(1) + T(2) * r * cos(T(2) * b) + r * r;
+  row[j] = (a >= T(0) ? T(1) : T(-1)) * (T(1) - r * r) / den;
+  row[H + j] = T(2) * r * sin(T(2) * b) / den;
+}
+
+// d(tanh z): with s = 1 - h^2 (complex), dz = (Re s gr + Im s gi) + i (-Im s gr + Re s gi)
+template <class T>
+__global__ void nade_ctanh_bwd_kernel(const T *h, T *g, int64_t B, int H) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= B * H) return;
+  const int64_t base = (idx / H) * 2 * H, j = idx % H;
+  const T hr = h[base + j], hi = h[base + H + j];
+  const T sr = T(1) - hr * hr + hi * hi, si = T(-2) * hr * hi;
+  const T gr = g[base + j], gi = g[base + H + j];
+  g[base + j] = sr * gr + si * gi;
+  g[base + H + j] = -si * gr + sr * gi;
+}
+
+// masked log-modulus and phase of one qubit's two values from its outputs
+// z = (Re z0, Re z1, Im z0, Im z1)
+template <class T>
+__device__ inline void nade_qubit(const T *z, bool masked, bool ok0, bool ok1, double (&la)[2],
+                                  double (&ph)[2]) {
+  if (!masked || (ok0 && ok1)) {
+    const double r0 = 2.0 * double(z[0]), r1 = 2.0 * double(z[1]);
+    const double mx = fmax(r0, r1);
+    const double lse = mx + log(exp(r0 - mx) + exp(r1 - mx));
+    la[0] = double(z[0]) - 0.5 * lse;
+    la[1] = double(z[1]) - 0.5 * lse;
+    ph[0] = double(z[2]);
+    ph[1] = double(z[3]);
+  } else {
+    la[0] = ok0 ? 0.0 : -INFINITY;
+    la[1] = ok1 ? 0.0 : -INFINITY;
+    ph[0] = ph[1] = 0.0;
+  }
+}
+
+// the physical tokens of token p and whether the level is masked
+__device__ inline int nade_phys(uint64_t xb, int p, Sectors S, bool &masked) {
+  const nqs_sector_info &si = sector_of(S, xb);
+  const uint64_t occ = occupation(S, xb);
+  const uint64_t below = (p == 0) ? 0ull : (~0ull >> (64 - 2 * p));
+  const int na = __popcll(occ & below & 0x5555555555555555ull);
+  const int nb = __popcll(occ & below & 0xAAAAAAAAAAAAAAAAull);
+  masked = p < si.mask_levels;
+  return masked ? phys_mask(S, si, p, na, nb, occ) : 0xF;
+}
+
+// token outputs of position p: out8[b, p, k] = 2 (la_a(a) + la_b(b | a)),
+// out8[b, p, 4 + k] = ph_a(a) + ph_b(b | a), k = a + 2b
+template <class T>
+__global__ void nade_combine_kernel(const uint64_t *x, int64_t B, int n, int p, const T *za,
+                                    const T *zb0, const T *zb1, Sectors S, T *out8) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  bool masked;
+  const int phys = nade_phys(x[b], p, S, masked);
+  double laA[2], phA[2], laB[2][2], phB[2][2];
+  nade_qubit(za + 4 * b, masked, (phys & 5) != 0, (phys & 10) != 0, laA, phA);
+  for (int a = 0; a < 2; ++a)
+    nade_qubit((a ? zb1 : zb0) + 4 * b, masked, ((phys >> a) & 1) != 0,
+               ((phys >> (a + 2)) & 1) != 0, laB[a], phB[a]);
+  T *o = out8 + (b * n + p) * 8;
+  for (int k = 0; k < 4; ++k) {
+    const int a = k & 1, c = k >> 1;
+    o[k] = T(2.0 * (laA[a] + laB[a][c]));
+    o[4 + k] = T(phA[a] + phB[a][c]);
+  }
+}
+
+// d(outputs of position p) -> d z of the three evaluations
+template <class T>
+__device__ inline void nade_qubit_bwd(const T *z, bool masked, bool ok0, bool ok1,
+                                      const double (&dla)[2], const double (&dph)[2], T *dz) {
+  if (!masked || (ok0 && ok1)) {
+    const double r0 = 2.0 * double(z[0]), r1 = 2.0 * double(z[1]);
+    const double mx = fmax(r0, r1);
+    const double e0 = exp(r0 - mx), e1 = exp(r1 - mx);
+    const double q0 = e0 / (e0 + e1), q1 = e1 / (e0 + e1);
+    const double s = dla[0] + dla[1];
+    dz[0] = T(dla[0] - q0 * s);
+    dz[1] = T(dla[1] - q1 * s);
+    dz[2] = T(dph[0]);
+    dz[3] = T(dph[1]);
+  } else {
+    for (int k = 0; k < 4; ++k) dz[k] = T(0);
+  }
+}
+
+template <class T>
+__global__ void nade_combine_bwd_kernel(const uint64_t *x, int64_t B, int n, int p, const T *za,
+                                        const T *zb0, const T *zb1, Sectors S, const T *d8,
+                                        T *dza, T *dzb0, T *dzb1) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  bool masked;
+  const int phys = nade_phys(x[b], p, S, masked);
+  const T *d = d8 + (b * n + p) * 8;
+  // masked token outputs are -inf and get a zero upstream gradient
+  double dlaA[2] = {0, 0}, dphA[2] = {0, 0};
+  for (int a = 0; a < 2; ++a) {
+    double dlaB[2], dphB[2];
+    for (int c = 0; c < 2; ++c) {
+      const int k = a + 2 * c;
+      const double g = 2.0 * double(d[k]);
+      dlaB[c] = g;
+      dlaA[a] += g;
+      dphB[c] = double(d[4 + k]);
+      dphA[a] += double(d[4 + k]);
+    }
+    nade_qubit_bwd((a ? zb1 : zb0) + 4 * b, masked, ((phys >> a) & 1) != 0,
+                   ((phys >> (a + 2)) & 1) != 0, dlaB, dphB, (a ? dzb1 : dzb0) + 4 * b);
+  }
+  nade_qubit_bwd(za + 4 * b, masked, (phys & 5) != 0, (phys & 10) != 0, dlaA, dphA, dza + 4 * b);
+}
+
+template <class T>
+const T *nade_blk(const nqs_model &m, int i, int k) {
+  return m.packed.as<T>() + m.nade_off[size_t(i) * kNadeBlocks + k];
+}
+
+template <class T>
+struct NadeEval {
+  T *h1, *pre2, *h2, *z;
+};
+
+// qubit i's network on B rows of X (row stride ldx, i inputs)
+template <class T>
+void nade_subnet(nqs_model &m, int i, int64_t B, const T *X, int ldx, const NadeEval<T> &E,
+                 hipStream_t s) {
+  const int H2 = 2 * m.hid;
+  gemm<T, false, false>(B, H2, i, X, ldx > 0 ? ldx : 1, nade_blk<T>(m, i, 0), H2, E.h1, H2,
+                        nade_blk<T>(m, i, 1), nullptr, EPI_STORE, s);
+  hipLaunchKernelGGL(nade_ctanh_kernel<T>, g1(B * m.hid), dim3(256), 0, s, E.h1, B, m.hid);
+  HIP_LAUNCH_OK();
+  gemm<T, false, false>(B, H2, H2, E.h1, H2, nade_blk<T>(m, i, 2), H2, E.h2, H2,
+                        nade_blk<T>(m, i, 3), E.pre2, EPI_LRELU, s);
+  gemm<T, false, false>(B, 4, H2, E.h2, H2, nade_blk<T>(m, i, 4), 4, E.z, 4,
+                        nade_blk<T>(m, i, 5), nullptr, EPI_STORE, s);
+}
+
+// d of the derived blocks of qubit i accumulated into G (double, block order)
+template <class T>
+void nade_subnet_bwd(nqs_model &m, int i, int64_t B, const T *X, int ldx, const NadeEval<T> &E,
+                     const T *dz, T *dh2, T *dh1, double *G, hipStream_t s) {
+  const int H = m.hid, H2 = 2 * H;
+  double *G1 = G, *gb1 = G1 + int64_t(i) * H2, *G2 = gb1 + H2, *gb2 = G2 + int64_t(H2) * H2,
+         *G3 = gb2 + H2, *gb3 = G3 + int64_t(H2) * 4;
+  auto wg = [&](const T *A, int lda, const T *D, int ldd, int M, int N, double *acc) {
+    void *scr = m.part.reserve(wgrad_scratch_bytes(B, M, N, std::max(lda, ldd), sizeof(T)));
+    wgrad_acc(A, lda, D, ldd, B, M, N, acc, scr, s);
+  };
+  auto cs = [&](const T *D, int N, double *acc) {
+    double *scr = static_cast<double *>(m.part.reserve(colsum_scratch_bytes(B, N)));
+    colsum_acc<T>(D, B, N, N, acc, scr, s);
+  };
+  wg(E.h2, H2, dz, 4, H2, 4, G3);
+  cs(dz, 4, gb3);
+  gemm<T, false, true>(B, H2, 4, dz, 4, nade_blk<T>(m, i, 4), 4, dh2, H2, nullptr, nullptr,
+                       EPI_STORE, s);
+  lrelu_bwd<T>(E.pre2, dh2, B * H2, s);
+  wg(E.h1, H2, dh2, H2, H2, H2, G2);
+  cs(dh2, H2, gb2);
+  gemm<T, false, true>(B, H2, H2, dh2, H2, nade_blk<T>(m, i, 2), H2, dh1, H2, nullptr, nullptr,
+                       EPI_STORE, s);
+  hipLaunchKernelGGL(nade_ctanh_bwd_kernel<T>, g1(B * H), dim3(256), 0, s, E.h1, dh1, B, H);
+  HIP_LAUNCH_OK();
+  if (i > 0) wg(X, ldx, dh1, H2, i, H2, G1);
+  cs(dh1, H2, gb1);
+}
+
+template <class T>
+void nade_fold(nqs_model &m, int i, const double *G, hipStream_t s) {
+  const int H = m.hid;
+  const int64_t total = int64_t(i) * H + H + int64_t(H) * H + H + int64_t(H) * 2 + 2;
+  auto o = [&](int k) { return m.off[size_t(12 * i + k)]; };
+  hipLaunchKernelGGL(nade_fold_kernel<T>, g1(total), dim3(256), 0, s, G, i, H,
+                     m.grad_acc.as<double>(), o(0), o(1), o(2), o(3), o(4), o(5), o(6), o(7),
+                     o(8), o(9), o(10), o(11));
+  HIP_LAUNCH_OK();
+}
+
+template <class T>
+struct NadeAct {
+  T *X0, *X1, *out8;
+  NadeEval<T> e[3];     // alpha, beta | a = 0, beta | a = 1
+};
+
+template <class T>
+size_t nade_carve(const nqs_model &m, int64_t B, Carver &c, NadeAct<T> &A) {
+  const int64_t w = 2 * m.n + 1, H2 = 2 * m.hid;
+  A.X0 = c.take<T>(B * w);
+  A.X1 = c.take<T>(B * w);
+  A.out8 = c.take<T>(B * m.n * 8);
+  for (auto &e : A.e) {
+    e.h1 = c.take<T>(B * H2);
+    e.pre2 = c.take<T>(B * H2);
+    e.h2 = c.take<T>(B * H2);
+    e.z = c.take<T>(B * 4);
+  }
+  return c.used;
+}
+
+// the three evaluations of token p (alpha qubit; beta qubit after a = 0 and a = 1)
+template <class T>
+void nade_token(nqs_model &m, const uint64_t *x, int64_t B, int p, NadeAct<T> &A, hipStream_t s) {
+  const int w = 2 * p + 1;
+  hipLaunchKernelGGL(nade_bits_kernel<T>, g1(B * w), dim3(256), 0, s, x, B, p, 0, A.X0);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(nade_bits_kernel<T>, g1(B * w), dim3(256), 0, s, x, B, p, 1, A.X1);
+  HIP_LAUNCH_OK();
+  nade_subnet<T>(m, 2 * p, B, A.X0, w, A.e[0], s);
+  nade_subnet<T>(m, 2 * p + 1, B, A.X0, w, A.e[1], s);
+  nade_subnet<T>(m, 2 * p + 1, B, A.X1, w, A.e[2], s);
+}
+
+template <class T>
+void nade_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
+                        T *out8_keep, hipStream_t s) {
+  NadeAct<T> A;
+  Carver c0{nullptr};
+  nade_carve<T>(m, B, c0, A);
+  Carver c{static_cast<char *>(m.ws.reserve(c0.used))};
+  nade_carve<T>(m, B, c, A);
+  if (out8_keep) A.out8 = out8_keep;
+  for (int p = 0; p < m.n; ++p) {
+    nade_token<T>(m, x, B, p, A, s);
+    hipLaunchKernelGGL(nade_combine_kernel<T>, g1(B), dim3(256), 0, s, x, B, m.n, p, A.e[0].z,
+                       A.e[1].z, A.e[2].z, m.sectors(), A.out8);
+    HIP_LAUNCH_OK();
+  }
+  if (logabs) {
+    hipLaunchKernelGGL(logabs_kernel<T>, g1(B), dim3(256), 0, s, x, B, m.n, A.out8, 8,
+                       m.sectors(), logabs);
+    HIP_LAUNCH_OK();
+  }
+  if (phase) {
+    hipLaunchKernelGGL(mlp_phase_kernel<T>, g1(B), dim3(256), 0, s, x, B, m.n, A.out8, phase);
+    HIP_LAUNCH_OK();
+  }
+}
+
+template <class T>
+void nade_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
+                         const double *gp, hipStream_t s) {
+  const int n = m.n, H2 = 2 * m.hid;
+  NadeAct<T> A;
+  Carver c0{nullptr};
+  nade_carve<T>(m, B, c0, A);
+  T *d8 = c0.take<T>(B * n * 8);
+  T *dz = c0.take<T>(B * 12);
+  T *dh2 = c0.take<T>(B * H2);
+  T *dh1 = c0.take<T>(B * H2);
+  Carver c{static_cast<char *>(m.ws.reserve(c0.used))};
+  nade_carve<T>(m, B, c, A);
+  d8 = c.take<T>(B * n * 8);
+  dz = c.take<T>(B * 12);
+  dh2 = c.take<T>(B * H2);
+  dh1 = c.take<T>(B * H2);
+  for (int p = 0; p < n; ++p) {
+    nade_token<T>(m, x, B, p, A, s);
+    hipLaunchKernelGGL(nade_combine_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, p, A.e[0].z,
+                       A.e[1].z, A.e[2].z, m.sectors(), A.out8);
+    HIP_LAUNCH_OK();
+  }
+  hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.out8, 8, m.sectors(),
+                     gl, d8, 8);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(mlp_dphase_kernel<T>, g1(B * n * 4), dim3(256), 0, s, x, B, n, gp, d8);
+  HIP_LAUNCH_OK();
+  // gradient of the derived blocks of one qubit (the largest qubit's size)
+  const int64_t gsize = int64_t(2 * n) * H2 + 2 * H2 + int64_t(H2) * H2 + int64_t(H2) * 4 + 4;
+  double *G = static_cast<double *>(m.ws2.reserve(size_t(gsize) * 8));
+  for (int p = 0; p < n; ++p) {
+    nade_token<T>(m, x, B, p, A, s);
+    const int w = 2 * p + 1;
+    hipLaunchKernelGGL(nade_combine_bwd_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, p,
+                       A.e[0].z, A.e[1].z, A.e[2].z, m.sectors(), d8, dz, dz + 4 * B,
+                       dz + 8 * B);
+    HIP_LAUNCH_OK();
+    zero_async(G, size_t(gsize) * 8, s);
+    nade_subnet_bwd<T>(m, 2 * p, B, A.X0, w, A.e[0], dz, dh2, dh1, G, s);
+    nade_fold<T>(m, 2 * p, G, s);
+    zero_async(G, size_t(gsize) * 8, s);
+    nade_subnet_bwd<T>(m, 2 * p + 1, B, A.X0, w, A.e[1], dz + 4 * B, dh2, dh1, G, s);
+    nade_subnet_bwd<T>(m, 2 * p + 1, B, A.X1, w, A.e[2], dz + 8 * B, dh2, dh1, G, s);
+    nade_fold<T>(m, 2 * p + 1, G, s);
+  }
+}
+
 template <class T>
 int64_t chunk_rows(const nqs_model &m, bool bwd) {
   // configurations per chunk, sized for the model's activation budget (an
   // eighth of the device memory free at creation, 1..16 GiB): on a 288 GB
   // device a whole 2e4-sample, 15-token backward is one chunk of large GEMMs
-  const int64_t per = m.kind == NQS_MODEL_MLP
+  const int64_t per = m.kind == NQS_MODEL_NADE
+                          ? int64_t(m.n) * 8 * 2 + 2 * (2 * m.n + 1) + 3 * (6 * m.hid + 4) + 12 +
+                                4 * m.hid
+                      : m.kind == NQS_MODEL_MLP
                           ? int64_t(m.n) * 8 * 4 + 4 * m.n + 3 * m.hid + 8
                           : int64_t(m.n) * (bwd ? (m.L * (7 * m.d + 2 * m.F + 8) +
                                                    m.L * m.H * m.n + 14 * m.d + 3 * m.F)
@@ -607,6 +1022,10 @@ void forward_T(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, doubl
                T *logits_keep, hipStream_t s) {
   if (m.kind == NQS_MODEL_MLP) {
     mlp_forward_chunk<T>(m, x, B, logabs, phase, logits_keep, s);
+    return;
+  }
+  if (m.kind == NQS_MODEL_NADE) {
+    nade_forward_chunk<T>(m, x, B, logabs, phase, logits_keep, s);
     return;
   }
   Carver c0{nullptr};
@@ -627,7 +1046,7 @@ int64_t model_chunk(const nqs_model &m, bool bwd) {
 void model_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
                    void *logits, hipStream_t s) {
   const int64_t ch = model_chunk(m, false);
-  const int w = m.kind == NQS_MODEL_MLP ? 8 : 4;
+  const int w = m.kind == NQS_MODEL_TRANSFORMER ? 4 : 8;
   for (int64_t b0 = 0; b0 < B; b0 += ch) {
     const int64_t nb = B - b0 < ch ? B - b0 : ch;
     const size_t lo = size_t(b0) * m.n * w;
@@ -646,7 +1065,7 @@ void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, d
     fused_forward(m, prefix, B, nullptr, nullptr, out4, p, s);
     return;
   }
-  const int w = m.kind == NQS_MODEL_MLP ? 8 : 4;
+  const int w = m.kind == NQS_MODEL_TRANSFORMER ? 4 : 8;
   const int64_t ch = model_chunk(m, false);
   void *buf = m.logit_buf.reserve(size_t(ch) * m.n * w * m.elem());
   for (int64_t b0 = 0; b0 < B; b0 += ch) {
@@ -664,6 +1083,38 @@ void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, d
   }
 }
 
+// derived NADE blocks of every qubit from the canonical parameters
+void nade_pack(nqs_model &m, hipStream_t s) {
+  const int H = m.hid, H2 = 2 * H;
+  m.nade_off.clear();
+  int64_t total = 0;
+  for (int i = 0; i < 2 * m.n; ++i) {
+    const int64_t sizes[kNadeBlocks] = {int64_t(i) * H2, H2, int64_t(H2) * H2, H2,
+                                        int64_t(H2) * 4, 4};
+    for (int k = 0; k < kNadeBlocks; ++k) {
+      m.nade_off.push_back(total);
+      total += sizes[k];
+    }
+  }
+  m.packed.reserve(size_t(total) * m.elem());
+  for (int i = 0; i < 2 * m.n; ++i) {
+    const int64_t count = int64_t(i) * H2 + 2 * H2 + int64_t(H2) * H2 + int64_t(H2) * 4 + 4;
+    auto launch = [&](auto *base) {
+      using T = std::remove_pointer_t<decltype(base)>;
+      auto prm = [&](int k) { return base + m.off[size_t(12 * i + k)]; };
+      auto blk = [&](int k) { return m.packed.as<T>() + m.nade_off[size_t(i) * kNadeBlocks + k]; };
+      hipLaunchKernelGGL(nade_pack_kernel<T>, g1(count), dim3(256), 0, s, prm(0), prm(1), prm(2),
+                         prm(3), prm(4), prm(5), prm(6), prm(7), prm(8), prm(9), prm(10), prm(11),
+                         i, H, blk(0), blk(1), blk(2), blk(3), blk(4), blk(5));
+    };
+    if (m.fp64())
+      launch(m.master.as<double>());
+    else
+      launch(m.master.as<float>());
+    HIP_LAUNCH_OK();
+  }
+}
+
 void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
                     const double *gp, void *grad, hipStream_t s) {
   double *acc = static_cast<double *>(m.grad_acc.reserve(size_t(m.P) * 8));
@@ -674,6 +1125,9 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
     if (m.kind == NQS_MODEL_MLP) {
       if (m.fp64()) mlp_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
       else mlp_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
+    } else if (m.kind == NQS_MODEL_NADE) {
+      if (m.fp64()) nade_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
+      else nade_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
     } else {
       if (m.fp64()) tf_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
       else tf_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);

@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("NQS_LIB", os.path.join(_HERE, "libnqs.so"))
 
-MODEL_MLP, MODEL_TRANSFORMER = 1, 2
+MODEL_MLP, MODEL_TRANSFORMER, MODEL_NADE = 1, 2, 3
 FP64, FP32, BF16 = 1, 2, 3
 MU, DU, MUD = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
@@ -415,7 +415,7 @@ def timing_read():
 
 def model_dims(cfg):
     """dims vector of amp_model_create for a workload description."""
-    if cfg["model"] == "mlp":
+    if cfg["model"] in ("mlp", "nade"):
         return [cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg.get("hidden", 64)]
     d = cfg["d"]
     return [cfg["n"], cfg["n_alpha"], cfg["n_beta"], d, cfg["n_layers"], cfg["n_heads"],
@@ -423,4 +423,4 @@ def model_dims(cfg):
 
 
 def model_kind(cfg):
-    return MODEL_MLP if cfg["model"] == "mlp" else MODEL_TRANSFORMER
+    return {"mlp": MODEL_MLP, "nade": MODEL_NADE}.get(cfg["model"], MODEL_TRANSFORMER)
