@@ -12,6 +12,11 @@ Inputs are seeded synthetic integrals and a random-initialised transformer
 
 Prints one JSON line.  `value` = connected (x, x') pairs per second of the
 whole step (the E_loc evals/s metric measured over complete steps).
+
+--workload nade: the same system and step with the paper's per-qubit
+complex-weight ansatz (hidden width 64) and its fused bf16 kernel; the roofline
+is then the VALU bound of that kernel.  --workload batching: 64 molecules in
+one graph-captured step (run_batching).
 """
 import argparse
 import json
@@ -29,6 +34,27 @@ sys.path.insert(0, ROOT)
 # + head 15 x 4 d + phase MLP 256^2 + 256
 FLOP_PER_CONFIG = 2 * (15 * 4 * 12 * 128 ** 2 + 4 * 2 * 128 * 120 + 15 * 4 * 128 + 256 * 256 + 256)
 BF16_PEAK_TFLOPS = 2500.0
+
+# The per-qubit ansatz (workload "nade") is bound by its elementwise VALU work.
+# Peak VALU issue of MI355X without packed fp32 (disabled in this build):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second, a
+# transcendental (exp2, log2, sin, cos, reciprocal) taking 4 issue slots.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic slots per evaluation: complex tanh = 4 transcendentals + 11 plain
+# operations; split leaky ReLU = 2 per real value; normaliser of one qubit =
+# 3 transcendentals + 6 plain.
+NADE_SLOTS = {"ctanh": 4 * 4 + 11, "lerelu": 2, "normaliser": 3 * 4 + 6}
+
+
+def nade_work(n_qubits, hidden):
+    """Per configuration: (multiply-adds x 2 of the three complex layers as real
+    block GEMMs, qubit i: i x 2H, 2H x 2H, 2H x 4; VALU slots of the
+    elementwise work: H complex tanh, 2H leaky ReLU values, one normaliser)."""
+    h2 = 2 * hidden
+    flop = sum(2 * (i * h2 + h2 * h2 + h2 * 4) for i in range(n_qubits))
+    slots = n_qubits * (hidden * NADE_SLOTS["ctanh"] + h2 * NADE_SLOTS["lerelu"]
+                        + NADE_SLOTS["normaliser"])
+    return flop, slots
 
 # HBM bytes per launch of the fused kernel on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
@@ -52,9 +78,12 @@ def log(msg):
 
 def setup(workload_name, precision):
     from paper_2310_04166_amd import nqs
-    from synth import flatten_params, transformer_param_spec, workload
+    from synth import flatten_params, nade_param_spec, transformer_param_spec, workload
     cfg, h, eri, params = workload(workload_name)
-    spec = transformer_param_spec(cfg["n"], cfg["d"], cfg["n_layers"], 4 * cfg["d"], 256)
+    if cfg["model"] == "nade":
+        spec = nade_param_spec(cfg["n"], cfg["hidden"])
+    else:
+        spec = transformer_param_spec(cfg["n"], cfg["d"], cfg["n_layers"], 4 * cfg["d"], 256)
     ham = nqs.ham_compile(h, eri, cfg["n_alpha"], cfg["n_beta"])
     model = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg), flatten_params(params, spec),
                       precision)
@@ -343,15 +372,28 @@ def main():
     nqs.timing_enable(False)
 
     value = total_pairs / elapsed
-    achieved = (k_cfgs * FLOP_PER_CONFIG) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
-                "traffic": fused_traffic() if args.workload == "precision" else None,
-                "traffic_unit": "bytes per launch",
-                "kernel": "fused_kernel<128> (bf16 amplitude network)",
-                "avg_launch_ms": round(k_ms / max(k_launches, 1), 3), "launches": k_launches,
-                "configs": k_cfgs, "flop_per_config": FLOP_PER_CONFIG,
-                "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
+    nade = cfg["model"] == "nade"
+    if nade:
+        flop, slots = nade_work(2 * cfg["n"], cfg["hidden"])
+        achieved = (k_cfgs * slots) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
+                    "unit": "T VALU lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                    "traffic": None, "kernel": "nade_fused_kernel (bf16 per-qubit ansatz)",
+                    "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
+                    "launches": k_launches, "configs": k_cfgs, "valu_slots_per_config": slots,
+                    "flop_per_config": flop,
+                    "mfma_tflops": round(k_cfgs * flop / (k_ms * 1e-3) / 1e12, 2) if k_ms else 0,
+                    "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
+    else:
+        achieved = (k_cfgs * FLOP_PER_CONFIG) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                    "traffic": fused_traffic() if args.workload == "precision" else None,
+                    "traffic_unit": "bytes per launch",
+                    "kernel": "fused_kernel<128> (bf16 amplitude network)",
+                    "avg_launch_ms": round(k_ms / max(k_launches, 1), 3), "launches": k_launches,
+                    "configs": k_cfgs, "flop_per_config": FLOP_PER_CONFIG,
+                    "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
 
     cpu = None
     if not args.no_cpu:
@@ -366,7 +408,10 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic",
            "config": {"workload": f"{args.workload}: 30 spin-orbitals 7a+7b, sector 41,409,225, "
-                                  "1e6 samples/step, transformer d128 L4 h8 + phase MLP 256",
+                                  "1e6 samples/step, " +
+                                  ("the paper's per-qubit ansatz (complex weights, hidden 64, "
+                                   "30 qubits)" if nade else
+                                   "transformer d128 L4 h8 + phase MLP 256"),
                       "unique_per_step": total_unique / args.steps,
                       "pairs_per_step": total_pairs / args.steps,
                       "distinct_xprime_per_step": total_distinct / args.steps,

@@ -147,11 +147,17 @@ void ham_destroy(nqs_ham *ham);
  *      h1 = tanh(x W1 + b1) (complex tanh), h2 = LeReLU(Re(h1 W2 + b2)) +
  *      i LeReLU(Im(h1 W2 + b2)), z = h2 W3 + b3, log psi_i(v | x_<i) = z_v -
  *      1/2 log(e^{2 Re z_0} + e^{2 Re z_1}).  Mask-Unphysical per qubit: with
- *      one physical value v, psi_i(v) = 1 and psi_i(1 - v) = 0.  FP64 / FP32.
+ *      one physical value v, psi_i(v) = 1 and psi_i(1 - v) = 0.  FP64, FP32,
+ *      and BF16 with hidden = 64: amp_forward and local_energy then run one
+ *      fused kernel per batch (all three layers on MFMA, bf16 operands, fp32
+ *      accumulation, complex tanh / leaky ReLU / normaliser in fp32, log|psi|
+ *      and phase summed in double); the sampler and amp_backward use the
+ *      fp32 master parameters layer by layer.
  * log|psi(x)| = 1/2 sum_p log softmax over allowed tokens; phase separate.
  * Errors: NQS_EINVAL (sizes, n_params mismatch), NQS_EUNSUPPORTED (n > 32,
- * d_model not a multiple of n_heads, unknown kind / precision / strategy),
- * NQS_EHIP / NQS_ENOMEM (device).
+ * d_model not a multiple of n_heads, unknown kind / precision / strategy,
+ * BF16 with an MLP, a transformer outside the fused kernel's shapes or a
+ * per-qubit ansatz with hidden != 64), NQS_EHIP / NQS_ENOMEM (device).
  */
 int amp_model_create(int kind, const int32_t *dims, int n_dims, const double *params,
                      int64_t n_params, int precision, int strategy, int d,
@@ -413,7 +419,8 @@ int vmc_weights_batch(const double *eloc, const uint64_t *counts, const uint64_t
 /* ------------------------------------------------------------------------ */
 
 /*
- * Kernel timing of the dominant kernel (the fused bf16 amplitude kernel).
+ * Kernel timing of the dominant kernel (the fused bf16 amplitude kernel of
+ * the transformer, or of the per-qubit ansatz).
  * While enabled, every launch of it is bracketed by two HIP events recorded on
  * the launch's own stream (in batch_local_energy: by two events inside the
  * step's launch sequence, read after the call; its launches on the samples

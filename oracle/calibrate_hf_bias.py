@@ -3,10 +3,12 @@
 Runs the oracle's tree sampler on the workload's model for a few bias values
 and prints the number of unique samples each gives.  The workloads' ``hf_bias``
 values were picked from this output (target: about 3e3 unique samples at 20
-spin-orbitals / 1e5 samples, about 2e4 at 30 spin-orbitals / 1e6 samples).
+spin-orbitals / 1e5 samples, about 2e4 at 30 spin-orbitals / 1e6 samples, for
+the transformer and for the paper's per-qubit ansatz alike).
 
     python -m oracle.calibrate_hf_bias fp32 2.5 3.0 3.5
     python -m oracle.calibrate_hf_bias batching 1.5 2.0 2.5
+    python -m oracle.calibrate_hf_bias nade 1.0 1.5 2.0
 
 For ``batching`` the value is the shared model's per-electron bias and the
 output lists the unique counts of the first eight molecules.
@@ -17,11 +19,18 @@ import time
 from oracle.model import TransformerModel, build_model
 from oracle.sampler import sample_tree
 from oracle.sector import Sector
-from synth import BATCHING_MODEL, batching_molecules, make_transformer_params, workload
+from synth import (BATCHING_MODEL, batching_molecules, make_nade_params,
+                   make_transformer_params, workload)
 
 
 def unique_count(name, bias, seed=0):
     cfg, _, _, _ = workload(name)
+    if cfg["model"] == "nade":
+        params = make_nade_params(cfg["n"], cfg["hidden"], seed=cfg["seed"], std=cfg["std"],
+                                  n_alpha=cfg["n_alpha"], n_beta=cfg["n_beta"], hf_bias=bias,
+                                  round_to=cfg.get("round_to"))
+        configs, _, _ = sample_tree(build_model(cfg, params), cfg["n_samples"], seed)
+        return len(configs)
     params = make_transformer_params(cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg["d"],
                                      cfg["n_layers"], seed=cfg["seed"], hf_bias=bias,
                                      round_to=cfg.get("round_to"))

@@ -196,6 +196,9 @@ def build_model(cfg, params, sector=None, requires_grad=False, mask_levels=None)
     sector = sector or Sector(cfg["n"], cfg["n_alpha"], cfg["n_beta"])
     if cfg["model"] == "mlp":
         return MLPModel(params, sector, mask_levels=mask_levels, requires_grad=requires_grad)
+    if cfg["model"] == "nade":
+        from .nade import NADEModel
+        return NADEModel(params, sector, mask_levels=mask_levels, requires_grad=requires_grad)
     return TransformerModel(params, sector, cfg["n_heads"], mask_levels=mask_levels,
                             requires_grad=requires_grad)
 

@@ -119,6 +119,17 @@ using namespace nqs;
 
 extern "C" const char *nqs_last_error(void) { return g_last_error.c_str(); }
 
+// derived weights from the canonical parameters: fp32 / fp64 block matrices of
+// the per-qubit ansatz, then the bf16 fragments of the fused forward
+static void repack(nqs_model &m, hipStream_t s) {
+  if (m.kind == NQS_MODEL_NADE) {
+    nade_pack(m, s);
+    if (m.precision == NQS_BF16) nade_fused_pack(m, s);
+  } else if (m.precision == NQS_BF16) {
+    fused_pack(m, s);
+  }
+}
+
 extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const double *params,
                                 int64_t n_params, int precision, int strategy, int dlev,
                                 nqs_model **out) {
@@ -157,8 +168,8 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
     if (kind == NQS_MODEL_NADE) {
       m->hid = dims[3];
       NQS_REQUIRE(m->hid >= 1, NQS_EINVAL, "amp_model_create: hidden < 1");
-      NQS_REQUIRE(precision != NQS_BF16, NQS_EUNSUPPORTED,
-                  "amp_model_create: the per-qubit ansatz has no bf16 mode");
+      NQS_REQUIRE(precision != NQS_BF16 || nade_fused_supported(*m), NQS_EUNSUPPORTED,
+                  "amp_model_create: bf16 mode of the per-qubit ansatz needs hidden width 64");
       const int h = m->hid;
       for (int i = 0; i < 2 * n; ++i) {
         add(int64_t(i) * h); add(int64_t(i) * h); add(h); add(h);
@@ -214,8 +225,7 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
       HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 4), f.data(), size_t(m->P) * 4,
                        hipMemcpyHostToDevice));
     }
-    if (precision == NQS_BF16) fused_pack(*m, nullptr);
-    if (kind == NQS_MODEL_NADE) nade_pack(*m, nullptr);
+    repack(*m, nullptr);
     HIP_OK(hipDeviceSynchronize());
     *out = m.release();
   });
@@ -298,8 +308,7 @@ extern "C" int amp_model_params(nqs_model *m, void **dev_params) {
 extern "C" int amp_model_sync(nqs_model *m, nqs_stream stream) {
   return guarded([&] {
     NQS_REQUIRE(m, NQS_EINVAL, "amp_model_sync: null handle");
-    if (m->precision == NQS_BF16) fused_pack(*m, as_stream(stream));
-    if (m->kind == NQS_MODEL_NADE) nade_pack(*m, as_stream(stream));
+    repack(*m, as_stream(stream));
   });
 }
 
@@ -327,8 +336,7 @@ extern "C" int amp_model_set_params(nqs_model *m, const double *host_in) {
       std::vector<float> f(host_in, host_in + m->P);
       HIP_OK(hipMemcpy(m->master.ptr, f.data(), size_t(m->P) * 4, hipMemcpyHostToDevice));
     }
-    if (m->precision == NQS_BF16) fused_pack(*m, nullptr);
-    if (m->kind == NQS_MODEL_NADE) nade_pack(*m, nullptr);
+    repack(*m, nullptr);
     HIP_OK(hipDeviceSynchronize());
   });
 }

@@ -71,6 +71,8 @@ struct nqs_model {
   nqs::DevBuf sec;                    // device copy of sec_host
   nqs::DevBuf packed;                 // bf16 weight fragments of the fused kernel
   nqs::DevBuf packed_vec;             // permuted fp32 vectors of the fused kernel
+  nqs::DevBuf nade_frag, nade_vec;    // per-qubit ansatz, bf16: weight fragments, fp32 vectors
+  std::vector<int32_t> nade_fo;       // first fragment set of each qubit in nade_frag
   bool packed_valid = false;
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
@@ -125,10 +127,20 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
 void fused_pack(nqs_model &m, hipStream_t s);
 // per-qubit ansatz: block matrices of the complex layers from the canonical parameters
 void nade_pack(nqs_model &m, hipStream_t s);
-// Kernel timing of the fused kernel (nqs_timing_*): whether it is on, and a
+// per-qubit ansatz in bf16 (nade_fused.hip): fragments from the fp32 block
+// matrices of nade_pack, and the fused forward (log|psi|, phase)
+bool nade_fused_supported(const nqs_model &m);
+void nade_fused_pack(nqs_model &m, hipStream_t s);
+void nade_fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                        double *phase, hipStream_t s, const int64_t *count = nullptr);
+// Kernel timing of the fused kernels (nqs_timing_*): whether it is on, and a
 // record measured by a caller (events inside a captured graph).
 bool timing_on();
 void timing_add(float ms, int64_t configs);
+// an event recorded on s when timing is on and the launch has a host-side size
+// (count == nullptr), else null; timing_end records the launch between the two
+hipEvent_t timing_begin(hipStream_t s, const int64_t *count);
+void timing_end(hipEvent_t start, hipStream_t s, int64_t configs);
 bool fused_supported(const nqs_model &m);
 
 }  // namespace nqs

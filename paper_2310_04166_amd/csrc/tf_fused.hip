@@ -763,6 +763,12 @@ void fused_pack(nqs_model &m, hipStream_t s) {
 void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
                    double *cond_out, int cond_p, hipStream_t s, const int64_t *count,
                    FusedTile tile) {
+  if (m.kind == NQS_MODEL_NADE) {
+    NQS_REQUIRE(cond_out == nullptr, NQS_EUNSUPPORTED,
+                "fused forward: the per-qubit ansatz has no conditional-logit mode");
+    nade_fused_forward(m, x, B, logabs, phase, s, count);
+    return;
+  }
   NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
   if (B <= 0) return;
   Layout L = plan(m);
@@ -820,6 +826,22 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
 }
 
 bool timing_on() { return g_timing; }
+
+hipEvent_t timing_begin(hipStream_t s, const int64_t *count) {
+  if (!g_timing || count) return nullptr;
+  hipEvent_t e0 = nullptr;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventRecord(e0, s));
+  return e0;
+}
+
+void timing_end(hipEvent_t start, hipStream_t s, int64_t configs) {
+  if (!start) return;
+  hipEvent_t e1 = nullptr;
+  HIP_OK(hipEventCreate(&e1));
+  HIP_OK(hipEventRecord(e1, s));
+  g_records.push_back({start, e1, configs, 0.f});
+}
 
 void timing_add(float ms, int64_t configs) { g_records.push_back({nullptr, nullptr, configs, ms}); }
 

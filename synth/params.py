@@ -132,7 +132,16 @@ def nade_param_spec(n, hidden=64):
     return spec
 
 
-def make_nade_params(n, hidden=64, seed=0, std=0.1, bias_std=0.0, round_to=None):
+def make_nade_params(n, hidden=64, seed=0, std=0.1, bias_std=0.0, round_to=None,
+                     n_alpha=0, n_beta=0, hf_bias=0.0):
     """Weights N(0, std) (real and imaginary parts drawn independently, in spec
-    order), biases N(0, bias_std)."""
-    return _init(nade_param_spec(n, hidden), seed, std, round_to, {}, bias_std)
+    order), biases N(0, bias_std).  ``hf_bias`` is added to the real output bias
+    of each qubit's Hartree-Fock value in the sector (n_alpha, n_beta): qubit
+    2p + s is occupied when p < n_alpha (s = 0) or p < n_beta (s = 1)."""
+    params = _init(nade_param_spec(n, hidden), seed, std, round_to, {}, bias_std)
+    if hf_bias:
+        for i in range(2 * n):
+            p, s = divmod(i, 2)
+            occupied = int(p < (n_alpha if s == 0 else n_beta))
+            params[f"nade{i}.b3_re"][occupied] += hf_bias
+    return params

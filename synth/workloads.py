@@ -1,4 +1,4 @@
-"""The five synthetic workloads, shaped like the paper's molecules.
+"""The six synthetic workloads, shaped like the paper's molecules.
 
 * ``tiny``      - 12 spin-orbitals, 2+2 electrons (LiH-sized sector of 225), MLP.
 * ``fp32``      - 20 spin-orbitals, 5+5 electrons (sector 63,504), small transformer.
@@ -6,6 +6,8 @@
                   d_model 128 / 4 layers / 8 heads transformer, bf16 GEMMs.
 * ``batching``  - 64 molecules of 12..28 spin-orbitals sharing one d_model 64 model.
 * ``grad``      - the ``precision`` system, full step plus gradient check.
+* ``nade``      - the ``precision`` system with the paper's per-qubit ansatz
+                  (complex weights, hidden width 64, 30 qubits), bf16 fused forward.
 
 ``hf_bias`` is the initial logit bias on each position's Hartree-Fock token.  It
 sets how peaked the initial Born distribution is and therefore how many unique
@@ -18,7 +20,7 @@ so that the molecules' unique counts spread over roughly 1e2 .. 3e3.
 import numpy as np
 
 from .integrals import make_integrals
-from .params import make_mlp_params, make_transformer_params
+from .params import make_mlp_params, make_nade_params, make_transformer_params
 
 WORKLOADS = {
     "tiny": dict(n=6, n_alpha=2, n_beta=2, rank=12, seed=1, model="mlp",
@@ -29,6 +31,9 @@ WORKLOADS = {
     "precision": dict(n=15, n_alpha=7, n_beta=7, rank=30, seed=3, model="transformer",
                       d=128, n_layers=4, n_heads=8, n_samples=1_000_000,
                       precision="bf16", hf_bias=3.3, round_to="bf16"),
+    "nade": dict(n=15, n_alpha=7, n_beta=7, rank=30, seed=3, model="nade", hidden=64,
+                 std=0.1, n_samples=1_000_000, precision="bf16", hf_bias=1.5,
+                 round_to="bf16"),
     "grad": dict(n=15, n_alpha=7, n_beta=7, rank=30, seed=3, model="transformer",
                  d=128, n_layers=4, n_heads=8, n_samples=1_000_000,
                  precision="bf16", hf_bias=3.3, round_to="bf16", fd_params=100,
@@ -42,6 +47,10 @@ def workload(name):
     h, eri = make_integrals(cfg["n"], cfg["rank"], cfg["seed"])
     if cfg["model"] == "mlp":
         params = make_mlp_params(cfg["n"], cfg["hidden"], seed=cfg["seed"])
+    elif cfg["model"] == "nade":
+        params = make_nade_params(cfg["n"], cfg["hidden"], seed=cfg["seed"], std=cfg["std"],
+                                  n_alpha=cfg["n_alpha"], n_beta=cfg["n_beta"],
+                                  hf_bias=cfg["hf_bias"], round_to=cfg.get("round_to"))
     else:
         params = make_transformer_params(
             cfg["n"], cfg["n_alpha"], cfg["n_beta"], cfg["d"], cfg["n_layers"],
