@@ -128,11 +128,13 @@ void fused_pack(nqs_model &m, hipStream_t s);
 // per-qubit ansatz: block matrices of the complex layers from the canonical parameters
 void nade_pack(nqs_model &m, hipStream_t s);
 // per-qubit ansatz in bf16 (nade_fused.hip): fragments from the fp32 block
-// matrices of nade_pack, and the fused forward (log|psi|, phase)
+// matrices of nade_pack, and the fused forward (log|psi|, phase, or the
+// sampler's token log-probabilities of token cond_p)
 bool nade_fused_supported(const nqs_model &m);
 void nade_fused_pack(nqs_model &m, hipStream_t s);
 void nade_fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
-                        double *phase, hipStream_t s, const int64_t *count = nullptr);
+                        double *phase, double *cond_out, int cond_p, hipStream_t s,
+                        const int64_t *count = nullptr);
 // Kernel timing of the fused kernels (nqs_timing_*): whether it is on, and a
 // record measured by a caller (events inside a captured graph).
 bool timing_on();

@@ -1061,7 +1061,7 @@ void model_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
 
 void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, double *out4,
                        hipStream_t s) {
-  if (m.precision == NQS_BF16 && fused_supported(m)) {
+  if (m.precision == NQS_BF16 && (fused_supported(m) || nade_fused_supported(m))) {
     fused_forward(m, prefix, B, nullptr, nullptr, out4, p, s);
     return;
   }

@@ -58,7 +58,9 @@ struct NadeArgs {
   int64_t B;                             // configurations (capacity when `count` is given)
   const int64_t *count;                  // optional device-side count
   int N;                                 // qubits (2n)
-  double *logabs, *phase;
+  int cond_p;                            // token of the conditional mode
+  double *logabs, *phase;                // forward mode (either may be null)
+  double *cond;                          // conditional mode: [B x 4] token log-probabilities
 };
 
 __device__ __host__ inline int feat_of(int h, int j) { return (j / 4) * 8 + h * 4 + (j % 4); }
@@ -118,7 +120,83 @@ __device__ inline void ctanh(float a, float b, float &re, float &im) {
   im = tr * sn * inv;
 }
 
-__global__ void __launch_bounds__(256) nade_fused_kernel(NadeArgs a) {
+// (Re z0, Re z1, Im z0, Im z1) of qubit i for the wave's 32 configurations,
+// whose bits below i are those of occ; valid in lanes 0..31 (lane = column)
+__device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane) {
+  const int h = lane >> 5, col = lane & 31;
+  const bf16x8 *W = a.frag + int64_t(a.fo[i]) * 64 + lane;
+  const float *V = a.vec + int64_t(i) * kVec;
+  const int ks = (i + 15) >> 4;
+  // layer 1 and the complex tanh, one pair of blocks (Re features 32b.., Im
+  // features 64 + 32b..) at a time, so that at most 32 accumulators are live
+  bf16x8 hf[8];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    f32x16 ar = load16(V + (2 * b + h) * 16), ai = load16(V + (2 * (b + 2) + h) * 16);
+    for (int k = 0; k < ks; ++k) {
+      const bf16x8 xb = bits_frag(occ, 16 * k + 8 * h);
+      ar = mfma(W[(b * ks + k) * 64], xb, ar);
+      ai = mfma(W[((b + 2) * ks + k) * 64], xb, ai);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float re[8], im[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ctanh(ar[8 * u + e], ai[8 * u + e], re[e], im[e]);
+      hf[2 * b + u] = pack8(re);
+      hf[4 + 2 * b + u] = pack8(im);
+    }
+  }
+  W += 4 * ks * 64;
+  // layer 2 one output block at a time, leaky ReLU applied at once
+  bf16x8 g[8];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x16 c = load16(V + kFeat + (2 * t + h) * 16);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c = mfma(W[(t * 8 + k) * 64], hf[k], c);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float y = c[8 * u + e];
+        v[e] = fmaxf(y, 0.01f * y);
+      }
+      g[2 * t + u] = pack8(v);
+    }
+  }
+  W += 32 * 64;
+  f32x16 z = {};
+  const bf16x8 zero = {};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) z = mfma(col < 4 ? W[k * 64] : zero, g[k], z);
+  const float *b3 = V + 2 * kFeat;
+  return f32x4{z[0] + b3[0], z[1] + b3[1], z[2] + b3[2], z[3] + b3[3]};
+}
+
+// log psi_i(0), log psi_i(1) (real parts) under Mask-Unphysical: the network's
+// normalised conditionals when unmasked or both values are physical, else 0
+// for the physical value and -inf for the other
+__device__ inline void qubit_logp(const f32x4 &z, bool masked, bool ok0, bool ok1, float &l0,
+                                  float &l1) {
+  if (!masked || (ok0 && ok1)) {
+    constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
+    const float r0 = 2.0f * z[0], r1 = 2.0f * z[1], mx = fmaxf(r0, r1);
+    const float lse = mx + kLn2 * __builtin_amdgcn_logf(__builtin_amdgcn_exp2f((r0 - mx) * kLog2e) +
+                                                        __builtin_amdgcn_exp2f((r1 - mx) * kLog2e));
+    l0 = z[0] - 0.5f * lse;
+    l1 = z[1] - 0.5f * lse;
+  } else {
+    l0 = ok0 ? 0.0f : -INFINITY;
+    l1 = ok1 ? 0.0f : -INFINITY;
+  }
+}
+
+// kCond: the sampler's conditional mode (its own kernel, so that the three
+// evaluations it keeps do not raise the forward's register allocation)
+template <bool kCond>
+__device__ inline void nade_body(const NadeArgs &a) {
   const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
   const int64_t B = a.count ? (*a.count < a.B ? *a.count : a.B) : a.B;
   const int64_t c0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 32;
@@ -129,59 +207,36 @@ __global__ void __launch_bounds__(256) nade_fused_kernel(NadeArgs a) {
   const nqs_sector_info &si = sector_of(a.sec, xw);
   const uint64_t occ = occupation(a.sec, xw);
   const int mask_levels = si.mask_levels;
+  if (kCond) {
+    // token p of the four-way sampler: qubit 2p on the prefix, qubit 2p + 1
+    // on the prefix extended by a = 0 and a = 1; outputs the token
+    // log-probabilities 2 (log|psi_2p(a)| + log|psi_2p+1(b | a)|), k = a + 2b
+    const int p = a.cond_p;
+    const uint64_t below = p == 0 ? 0ull : (~0ull >> (64 - 2 * p));
+    const uint64_t pre = occ & below;
+    const f32x4 zA = qubit_z(a, 2 * p, pre, lane);
+    const f32x4 zB0 = qubit_z(a, 2 * p + 1, pre, lane);
+    const f32x4 zB1 = qubit_z(a, 2 * p + 1, pre | (1ull << (2 * p)), lane);
+    const bool masked = p < mask_levels;
+    const int phys = masked ? phys_mask(a.sec, si, p, __popcll(pre & 0x5555555555555555ull),
+                                        __popcll(pre & 0xAAAAAAAAAAAAAAAAull), pre)
+                            : 0xF;
+    float lA[2], lB[2][2];
+    qubit_logp(zA, masked, (phys & 5) != 0, (phys & 10) != 0, lA[0], lA[1]);
+    qubit_logp(zB0, masked, (phys & 1) != 0, (phys & 4) != 0, lB[0][0], lB[0][1]);
+    qubit_logp(zB1, masked, (phys & 2) != 0, (phys & 8) != 0, lB[1][0], lB[1][1]);
+    if (h == 0 && valid) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        a.cond[cfg * 4 + k] = 2.0 * (double(lA[k & 1]) + double(lB[k & 1][k >> 1]));
+    }
+    return;
+  }
   double la = 0.0, ph = 0.0;
   int na = 0, nb = 0, phys = 0xF;
   for (int i = 0; i < a.N; ++i) {
-    const bf16x8 *W = a.frag + int64_t(a.fo[i]) * 64 + lane;
-    const float *V = a.vec + int64_t(i) * kVec;
-    const int ks = (i + 15) >> 4;
-    f32x16 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = load16(V + (2 * t + h) * 16);
-    for (int k = 0; k < ks; ++k) {
-      const bf16x8 xb = bits_frag(occ, 16 * k + 8 * h);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma(W[(t * ks + k) * 64], xb, acc[t]);
-    }
-    W += 4 * ks * 64;
-    bf16x8 hf[8];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        float re[8], im[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) ctanh(acc[b][8 * u + e], acc[b + 2][8 * u + e], re[e], im[e]);
-        hf[2 * b + u] = pack8(re);
-        hf[4 + 2 * b + u] = pack8(im);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = load16(V + kFeat + (2 * t + h) * 16);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma(W[(t * 8 + k) * 64], hf[k], acc[t]);
-    }
-    W += 32 * 64;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        float v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float y = acc[t][8 * u + e];
-          v[e] = fmaxf(y, 0.01f * y);
-        }
-        hf[2 * t + u] = pack8(v);
-      }
-    }
-    f32x16 z = {};
-    const bf16x8 zero = {};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z = mfma(col < 4 ? W[k * 64] : zero, hf[k], z);
-    // Mask-Unphysical and the normaliser; lanes 0..31 hold this qubit's z
+    const f32x4 z = qubit_z(a, i, occ, lane);
+    // Mask-Unphysical on the qubit's two values; lanes 0..31 hold its z
     const int p = i >> 1, v = int((occ >> i) & 1);
     const bool masked = p < mask_levels;
     if ((i & 1) == 0 && masked) phys = phys_mask(a.sec, si, p, na, nb, occ);
@@ -194,17 +249,10 @@ __global__ void __launch_bounds__(256) nade_fused_kernel(NadeArgs a) {
       ok0 = ((phys >> al) & 1) != 0;
       ok1 = ((phys >> (al + 2)) & 1) != 0;
     }
-    if (!masked || (ok0 && ok1)) {
-      constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
-      const float z0 = z[0] + V[2 * kFeat], z1 = z[1] + V[2 * kFeat + 1];
-      const float r0 = 2.0f * z0, r1 = 2.0f * z1, mx = fmaxf(r0, r1);
-      const float lse = mx + kLn2 * __builtin_amdgcn_logf(__builtin_amdgcn_exp2f((r0 - mx) * kLog2e) +
-                                                          __builtin_amdgcn_exp2f((r1 - mx) * kLog2e));
-      la += double((v ? z1 : z0) - 0.5f * lse);
-      ph += double(v ? z[3] + V[2 * kFeat + 3] : z[2] + V[2 * kFeat + 2]);
-    } else if (!(v ? ok1 : ok0)) {
-      la = -INFINITY;
-    }
+    float l0, l1;
+    qubit_logp(z, masked, ok0, ok1, l0, l1);
+    la += double(v ? l1 : l0);
+    if (!masked || (ok0 && ok1)) ph += double(v ? z[3] : z[2]);
     if (i & 1) {
       na += int((occ >> (i - 1)) & 1);
       nb += v;
@@ -215,6 +263,15 @@ __global__ void __launch_bounds__(256) nade_fused_kernel(NadeArgs a) {
     if (a.phase) a.phase[cfg] = ph;
   }
 }
+
+// four waves per SIMD (at most 128 registers, a 16-byte spill): the kernel is
+// latency-bound, and 4 waves beat 3 (the compiler's default) by 10 % and 2 by 40 %
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+nade_fused_kernel(NadeArgs a) {
+  nade_body<false>(a);
+}
+
+__global__ void __launch_bounds__(256) nade_cond_kernel(NadeArgs a) { nade_body<true>(a); }
 
 // Fragment order: (block ob, k-step s, lane l, slot e) <- W[krow][32 ob + l%32]
 // with krow = 16 s + 8 (l/32) + e (natural, for the bit input) or
@@ -290,7 +347,8 @@ void nade_fused_pack(nqs_model &m, hipStream_t s) {
 }
 
 void nade_fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
-                        double *phase, hipStream_t s, const int64_t *count) {
+                        double *phase, double *cond_out, int cond_p, hipStream_t s,
+                        const int64_t *count) {
   NQS_REQUIRE(m.nade_fo.size() == size_t(2 * m.n), NQS_EINVAL,
               "fused forward: weights not packed");
   if (B <= 0) return;
@@ -305,10 +363,17 @@ void nade_fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   a.N = 2 * m.n;
   a.logabs = logabs;
   a.phase = phase;
+  a.cond = cond_out;
+  a.cond_p = cond_p;
+  NQS_REQUIRE(!cond_out || (cond_p >= 0 && cond_p < m.n), NQS_EINVAL,
+              "fused forward: conditional token out of range");
   const int64_t blocks = ceil_div(B, int64_t(32) * kWaves);
   NQS_REQUIRE(blocks <= int64_t(0x7FFFFFFF), NQS_EUNSUPPORTED, "fused forward: batch too large");
-  hipEvent_t e0 = timing_begin(s, count);
-  hipLaunchKernelGGL(nade_fused_kernel, dim3(unsigned(blocks)), dim3(64 * kWaves), 0, s, a);
+  hipEvent_t e0 = cond_out ? nullptr : timing_begin(s, count);
+  if (cond_out)
+    hipLaunchKernelGGL(nade_cond_kernel, dim3(unsigned(blocks)), dim3(64 * kWaves), 0, s, a);
+  else
+    hipLaunchKernelGGL(nade_fused_kernel, dim3(unsigned(blocks)), dim3(64 * kWaves), 0, s, a);
   HIP_LAUNCH_OK();
   timing_end(e0, s, B);
 }

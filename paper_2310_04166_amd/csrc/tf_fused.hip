@@ -764,9 +764,7 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
                    double *cond_out, int cond_p, hipStream_t s, const int64_t *count,
                    FusedTile tile) {
   if (m.kind == NQS_MODEL_NADE) {
-    NQS_REQUIRE(cond_out == nullptr, NQS_EUNSUPPORTED,
-                "fused forward: the per-qubit ansatz has no conditional-logit mode");
-    nade_fused_forward(m, x, B, logabs, phase, s, count);
+    nade_fused_forward(m, x, B, logabs, phase, cond_out, cond_p, s, count);
     return;
   }
   NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
