@@ -64,12 +64,19 @@ FUSED_TRAFFIC = {"source_sha256_prefix": "97ef1fa0957e4308", "bytes_per_launch":
                  "profile": "profiles/fused_kernel_precision_traffic.md"}
 
 
-def fused_traffic():
+# The same for the per-qubit ansatz's fused kernel on workload "nade" (mean of a
+# step's two launches, the samples and the distinct x').
+NADE_TRAFFIC = {"source_sha256_prefix": "1b9a601f1cc877d4", "bytes_per_launch": 114.05e6,
+                "profile": "profiles/nade_fused_kernel_traffic.md"}
+
+
+def fused_traffic(entry=None, source="tf_fused.hip"):
     import hashlib
-    src = os.path.join(ROOT, "paper_2310_04166_amd", "csrc", "tf_fused.hip")
+    entry = entry or FUSED_TRAFFIC
+    src = os.path.join(ROOT, "paper_2310_04166_amd", "csrc", source)
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return FUSED_TRAFFIC["bytes_per_launch"] if sha == FUSED_TRAFFIC["source_sha256_prefix"] else None
+    return entry["bytes_per_launch"] if sha == entry["source_sha256_prefix"] else None
 
 
 def log(msg):
@@ -378,7 +385,9 @@ def main():
         achieved = (k_cfgs * slots) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                     "unit": "T VALU lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                    "traffic": None, "kernel": "nade_fused_kernel (bf16 per-qubit ansatz)",
+                    "traffic": fused_traffic(NADE_TRAFFIC, "nade_fused.hip"),
+                    "traffic_unit": "bytes per launch",
+                    "kernel": "nade_fused_kernel (bf16 per-qubit ansatz)",
                     "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
                     "launches": k_launches, "configs": k_cfgs, "valu_slots_per_config": slots,
                     "flop_per_config": flop,
