@@ -604,17 +604,20 @@ void mlp_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double
 // (2H x 2H), b2cat (2H), W3blk (2H x 4, columns Re z0, Re z1, Im z0, Im z1), b3cat (4)
 constexpr int kNadeBlocks = 6;
 
+// W1 has Q rows (the qubit count): rows in .. Q-1 are zero, so that every
+// qubit's block has the same shape (the batched products read all Q rows, the
+// per-qubit ones the first `in`)
 template <class T>
 __global__ void nade_pack_kernel(const T *w1r, const T *w1i, const T *b1r, const T *b1i,
                                  const T *w2r, const T *w2i, const T *b2r, const T *b2i,
                                  const T *w3r, const T *w3i, const T *b3r, const T *b3i, int in,
-                                 int H, T *W1, T *B1, T *W2, T *B2, T *W3, T *B3) {
+                                 int Q, int H, T *W1, T *B1, T *W2, T *B2, T *W3, T *B3) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t H2 = 2 * H;
-  const int64_t n1 = int64_t(in) * H2, n2 = H2 * H2, n3 = H2 * 4;
+  const int64_t n1 = int64_t(Q) * H2, n2 = H2 * H2, n3 = H2 * 4;
   if (idx < n1) {
     const int64_t j = idx / H2, c = idx % H2;
-    W1[idx] = c < H ? w1r[j * H + c] : w1i[j * H + c - H];
+    W1[idx] = j >= in ? T(0) : c < H ? w1r[j * H + c] : w1i[j * H + c - H];
   } else if (idx < n1 + H2) {
     const int64_t c = idx - n1;
     B1[c] = c < H ? b1r[c] : b1i[c - H];
@@ -632,57 +635,6 @@ __global__ void nade_pack_kernel(const T *w1r, const T *w1i, const T *b1r, const
   } else if (idx < n1 + 2 * H2 + n2 + n3 + 4) {
     const int64_t c = idx - n1 - 2 * H2 - n2 - n3;
     B3[c] = c < 2 ? b3r[c] : b3i[c - 2];
-  }
-}
-
-// gradient of the derived blocks folded back onto the canonical parameters
-template <class T>
-__global__ void nade_fold_kernel(const double *G, int in, int H, double *acc, int64_t o_w1r,
-                                 int64_t o_w1i, int64_t o_b1r, int64_t o_b1i, int64_t o_w2r,
-                                 int64_t o_w2i, int64_t o_b2r, int64_t o_b2i, int64_t o_w3r,
-                                 int64_t o_w3i, int64_t o_b3r, int64_t o_b3i) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t H2 = 2 * H;
-  const double *G1 = G, *gb1 = G1 + int64_t(in) * H2, *G2 = gb1 + H2, *gb2 = G2 + H2 * H2,
-               *G3 = gb2 + H2, *gb3 = G3 + H2 * 4;
-  const int64_t n1 = int64_t(in) * H, n2 = int64_t(H) * H, n3 = int64_t(H) * 2;
-  int64_t e = idx;
-  if (e < n1) {                                       // w1: rows j, columns c
-    const int64_t j = e / H, c = e % H;
-    acc[o_w1r + e] += G1[j * H2 + c];
-    acc[o_w1i + e] += G1[j * H2 + H + c];
-    return;
-  }
-  e -= n1;
-  if (e < H) {
-    acc[o_b1r + e] += gb1[e];
-    acc[o_b1i + e] += gb1[H + e];
-    return;
-  }
-  e -= H;
-  if (e < n2) {                                       // w2 from the four blocks
-    const int64_t r = e / H, c = e % H;
-    acc[o_w2r + e] += G2[r * H2 + c] + G2[(H + r) * H2 + H + c];
-    acc[o_w2i + e] += G2[r * H2 + H + c] - G2[(H + r) * H2 + c];
-    return;
-  }
-  e -= n2;
-  if (e < H) {
-    acc[o_b2r + e] += gb2[e];
-    acc[o_b2i + e] += gb2[H + e];
-    return;
-  }
-  e -= H;
-  if (e < n3) {
-    const int64_t r = e / 2, v = e % 2;
-    acc[o_w3r + e] += G3[r * 4 + v] + G3[(H + r) * 4 + 2 + v];
-    acc[o_w3i + e] += G3[r * 4 + 2 + v] - G3[(H + r) * 4 + v];
-    return;
-  }
-  e -= n3;
-  if (e < 2) {
-    acc[o_b3r + e] += gb3[e];
-    acc[o_b3i + e] += gb3[2 + e];
   }
 }
 
@@ -777,52 +729,6 @@ __global__ void nade_combine_kernel(const uint64_t *x, int64_t B, int n, int p, 
   }
 }
 
-// d(outputs of position p) -> d z of the three evaluations
-template <class T>
-__device__ inline void nade_qubit_bwd(const T *z, bool masked, bool ok0, bool ok1,
-                                      const double (&dla)[2], const double (&dph)[2], T *dz) {
-  if (!masked || (ok0 && ok1)) {
-    const double r0 = 2.0 * double(z[0]), r1 = 2.0 * double(z[1]);
-    const double mx = fmax(r0, r1);
-    const double e0 = exp(r0 - mx), e1 = exp(r1 - mx);
-    const double q0 = e0 / (e0 + e1), q1 = e1 / (e0 + e1);
-    const double s = dla[0] + dla[1];
-    dz[0] = T(dla[0] - q0 * s);
-    dz[1] = T(dla[1] - q1 * s);
-    dz[2] = T(dph[0]);
-    dz[3] = T(dph[1]);
-  } else {
-    for (int k = 0; k < 4; ++k) dz[k] = T(0);
-  }
-}
-
-template <class T>
-__global__ void nade_combine_bwd_kernel(const uint64_t *x, int64_t B, int n, int p, const T *za,
-                                        const T *zb0, const T *zb1, Sectors S, const T *d8,
-                                        T *dza, T *dzb0, T *dzb1) {
-  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  bool masked;
-  const int phys = nade_phys(x[b], p, S, masked);
-  const T *d = d8 + (b * n + p) * 8;
-  // masked token outputs are -inf and get a zero upstream gradient
-  double dlaA[2] = {0, 0}, dphA[2] = {0, 0};
-  for (int a = 0; a < 2; ++a) {
-    double dlaB[2], dphB[2];
-    for (int c = 0; c < 2; ++c) {
-      const int k = a + 2 * c;
-      const double g = 2.0 * double(d[k]);
-      dlaB[c] = g;
-      dlaA[a] += g;
-      dphB[c] = double(d[4 + k]);
-      dphA[a] += double(d[4 + k]);
-    }
-    nade_qubit_bwd((a ? zb1 : zb0) + 4 * b, masked, ((phys >> a) & 1) != 0,
-                   ((phys >> (a + 2)) & 1) != 0, dlaB, dphB, (a ? dzb1 : dzb0) + 4 * b);
-  }
-  nade_qubit_bwd(za + 4 * b, masked, (phys & 5) != 0, (phys & 10) != 0, dlaA, dphA, dza + 4 * b);
-}
-
 template <class T>
 const T *nade_blk(const nqs_model &m, int i, int k) {
   return m.packed.as<T>() + m.nade_off[size_t(i) * kNadeBlocks + k];
@@ -846,47 +752,6 @@ void nade_subnet(nqs_model &m, int i, int64_t B, const T *X, int ldx, const Nade
                         nade_blk<T>(m, i, 3), E.pre2, EPI_LRELU, s);
   gemm<T, false, false>(B, 4, H2, E.h2, H2, nade_blk<T>(m, i, 4), 4, E.z, 4,
                         nade_blk<T>(m, i, 5), nullptr, EPI_STORE, s);
-}
-
-// d of the derived blocks of qubit i accumulated into G (double, block order)
-template <class T>
-void nade_subnet_bwd(nqs_model &m, int i, int64_t B, const T *X, int ldx, const NadeEval<T> &E,
-                     const T *dz, T *dh2, T *dh1, double *G, hipStream_t s) {
-  const int H = m.hid, H2 = 2 * H;
-  double *G1 = G, *gb1 = G1 + int64_t(i) * H2, *G2 = gb1 + H2, *gb2 = G2 + int64_t(H2) * H2,
-         *G3 = gb2 + H2, *gb3 = G3 + int64_t(H2) * 4;
-  auto wg = [&](const T *A, int lda, const T *D, int ldd, int M, int N, double *acc) {
-    void *scr = m.part.reserve(wgrad_scratch_bytes(B, M, N, std::max(lda, ldd), sizeof(T)));
-    wgrad_acc(A, lda, D, ldd, B, M, N, acc, scr, s);
-  };
-  auto cs = [&](const T *D, int N, double *acc) {
-    double *scr = static_cast<double *>(m.part.reserve(colsum_scratch_bytes(B, N)));
-    colsum_acc<T>(D, B, N, N, acc, scr, s);
-  };
-  wg(E.h2, H2, dz, 4, H2, 4, G3);
-  cs(dz, 4, gb3);
-  gemm<T, false, true>(B, H2, 4, dz, 4, nade_blk<T>(m, i, 4), 4, dh2, H2, nullptr, nullptr,
-                       EPI_STORE, s);
-  lrelu_bwd<T>(E.pre2, dh2, B * H2, s);
-  wg(E.h1, H2, dh2, H2, H2, H2, G2);
-  cs(dh2, H2, gb2);
-  gemm<T, false, true>(B, H2, H2, dh2, H2, nade_blk<T>(m, i, 2), H2, dh1, H2, nullptr, nullptr,
-                       EPI_STORE, s);
-  hipLaunchKernelGGL(nade_ctanh_bwd_kernel<T>, g1(B * H), dim3(256), 0, s, E.h1, dh1, B, H);
-  HIP_LAUNCH_OK();
-  if (i > 0) wg(X, ldx, dh1, H2, i, H2, G1);
-  cs(dh1, H2, gb1);
-}
-
-template <class T>
-void nade_fold(nqs_model &m, int i, const double *G, hipStream_t s) {
-  const int H = m.hid;
-  const int64_t total = int64_t(i) * H + H + int64_t(H) * H + H + int64_t(H) * 2 + 2;
-  auto o = [&](int k) { return m.off[size_t(12 * i + k)]; };
-  hipLaunchKernelGGL(nade_fold_kernel<T>, g1(total), dim3(256), 0, s, G, i, H,
-                     m.grad_acc.as<double>(), o(0), o(1), o(2), o(3), o(4), o(5), o(6), o(7),
-                     o(8), o(9), o(10), o(11));
-  HIP_LAUNCH_OK();
 }
 
 template <class T>
@@ -949,52 +814,277 @@ void nade_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   }
 }
 
+// ---- the per-qubit ansatz with all qubits batched (amp_forward, local energy
+// and the backward in FP64 / FP32).  Given x every qubit's network reads known
+// bits, so the Q = 2n networks are independent: each layer is one strided batch
+// of Q products (W1 padded to Q rows), activations are qubit-major [Q][B][.].
+
+// X[b][c] = bit c of the configuration (c < Q)
 template <class T>
-void nade_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
-                         const double *gp, hipStream_t s) {
-  const int n = m.n, H2 = 2 * m.hid;
-  NadeAct<T> A;
+__global__ void nade_qb_bits_kernel(const uint64_t *x, int64_t B, int Q, Sectors S, T *X) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= B * Q) return;
+  X[idx] = T((occupation(S, x[idx / Q]) >> (idx % Q)) & 1ull);
+}
+
+// rows [Re(H) | Im(H)] of qubit q (rows of B per qubit): add b1[q], complex tanh
+template <class T>
+__global__ void nade_qb_bias_ctanh_kernel(T *h, const T *b1, int64_t B, int Q, int H) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(Q) * B * H) return;
+  const int64_t row = idx / H, j = idx % H, q = row / B;
+  T *r = h + row * 2 * H;
+  const T *bq = b1 + q * 2 * H;
+  const T a = r[j] + bq[j], b = r[H + j] + bq[H + j];
+  const T e = exp(T(-2) * fabs(a));
+  const T den = T(1) + T(2) * e * cos(T(2) * b) + e * e;
+  r[j] = (a >= T(0) ? T(1) : T(-1)) * (T(1) - e * e) / den;
+  r[H + j] = T(2) * e * sin(T(2) * b) / den;
+}
+
+// pre = P + b2[q] (kept in P), Y = leaky ReLU(pre), slope 0.01
+template <class T>
+__global__ void nade_qb_bias_lrelu_kernel(T *P, const T *b2, int64_t B, int Q, int H2, T *Y) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(Q) * B * H2) return;
+  const int64_t q = idx / (B * H2), c = idx % H2;
+  const T v = P[idx] + b2[q * H2 + c];
+  P[idx] = v;
+  Y[idx] = v >= T(0) ? v : T(0.01) * v;
+}
+
+// Walk the qubits of configuration b with their outputs z = Z[q][b] + b3[q]:
+// Mask-Unphysical per qubit, log|psi| and phase; with gl / gp, the gradient of
+// gl log|psi| + gp phase with respect to every qubit's z instead (DZ[q][b]).
+template <class T>
+__global__ void nade_qb_combine_kernel(const uint64_t *x, int64_t B, int Q, Sectors S, const T *Z,
+                                       const T *b3, double *logabs, double *phase,
+                                       const double *gl, const double *gp, T *DZ) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const nqs_sector_info &si = sector_of(S, x[b]);
+  const uint64_t occ = occupation(S, x[b]);
+  double la = 0.0, ph = 0.0;
+  int na = 0, nb = 0, phys = 0xF;
+  for (int q = 0; q < Q; ++q) {
+    const int p = q >> 1, v = int((occ >> q) & 1);
+    const bool masked = p < si.mask_levels;
+    if ((q & 1) == 0 && masked) phys = phys_mask(S, si, p, na, nb, occ);
+    bool ok0, ok1;
+    if ((q & 1) == 0) {
+      ok0 = (phys & 5) != 0;
+      ok1 = (phys & 10) != 0;
+    } else {
+      const int al = int((occ >> (q - 1)) & 1);
+      ok0 = ((phys >> al) & 1) != 0;
+      ok1 = ((phys >> (al + 2)) & 1) != 0;
+    }
+    const T *zq = Z + (int64_t(q) * B + b) * 4;
+    double z[4];
+    for (int k = 0; k < 4; ++k) z[k] = double(zq[k]) + double(b3[q * 4 + k]);
+    const bool free = !masked || (ok0 && ok1);
+    double dz[4] = {0.0, 0.0, 0.0, 0.0};
+    if (free) {
+      const double r0 = 2.0 * z[0], r1 = 2.0 * z[1], mx = fmax(r0, r1);
+      const double e0 = exp(r0 - mx), e1 = exp(r1 - mx);
+      la += z[v] - 0.5 * (mx + log(e0 + e1));
+      ph += z[2 + v];
+      if (DZ) {
+        // d(z_v - LSE(2 Re z) / 2) / d Re z_w = [w == v] - softmax(2 Re z)_w
+        const double w0 = e0 / (e0 + e1), w1 = e1 / (e0 + e1);
+        dz[0] = gl[b] * ((v == 0 ? 1.0 : 0.0) - w0);
+        dz[1] = gl[b] * ((v == 1 ? 1.0 : 0.0) - w1);
+        dz[2 + v] = gp[b];
+      }
+    } else if (!(v ? ok1 : ok0)) {
+      la = -INFINITY;
+    }
+    if (DZ) {
+      T *d = DZ + (int64_t(q) * B + b) * 4;
+      for (int k = 0; k < 4; ++k) d[k] = T(dz[k]);
+    }
+    if (q & 1) {
+      na += int((occ >> (q - 1)) & 1);
+      nb += v;
+    }
+  }
+  if (logabs) logabs[b] = la;
+  if (phase) phase[b] = ph;
+}
+
+// Canonical parameters of every qubit from the block-matrix gradients
+// (G1 [Q][Q][2H], g1 [Q][2H], G2 [Q][2H][2H], g2 [Q][2H], G3 [Q][2H][4],
+// g3 [Q][4]); blockIdx.y is the qubit, whose parameters start at
+// H i (i - 1) + i (2H^2 + 8H + 4) in the canonical order
+template <class T>
+__global__ void nade_qb_fold_kernel(const T *G1, const T *g1, const T *G2, const T *g2,
+                                    const T *G3, const T *g3, int Q, int H, double *acc) {
+  const int i = blockIdx.y;
+  const int64_t H2 = 2 * H;
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double *o = acc + int64_t(H) * i * (i - 1) + int64_t(i) * (2 * H * H + 8 * H + 4);
+  const T *W1 = G1 + int64_t(i) * Q * H2, *b1 = g1 + i * H2, *W2 = G2 + int64_t(i) * H2 * H2,
+          *b2 = g2 + i * H2, *W3 = G3 + int64_t(i) * H2 * 4, *b3 = g3 + i * 4;
+  const int64_t n1 = int64_t(i) * H, n2 = int64_t(H) * H;
+  if (e < n1) {
+    const int64_t j = e / H, c = e % H;
+    o[e] += double(W1[j * H2 + c]);
+    o[n1 + e] += double(W1[j * H2 + H + c]);
+    return;
+  }
+  e -= n1;
+  o += 2 * n1;
+  if (e < H) {
+    o[e] += double(b1[e]);
+    o[H + e] += double(b1[H + e]);
+    return;
+  }
+  e -= H;
+  o += 2 * H;
+  if (e < n2) {
+    const int64_t r = e / H, c = e % H;
+    o[e] += double(W2[r * H2 + c]) + double(W2[(H + r) * H2 + H + c]);
+    o[n2 + e] += double(W2[r * H2 + H + c]) - double(W2[(H + r) * H2 + c]);
+    return;
+  }
+  e -= n2;
+  o += 2 * n2;
+  if (e < H) {
+    o[e] += double(b2[e]);
+    o[H + e] += double(b2[H + e]);
+    return;
+  }
+  e -= H;
+  o += 2 * H;
+  if (e < 2 * H) {
+    const int64_t r = e / 2, v = e % 2;
+    o[e] += double(W3[r * 4 + v]) + double(W3[(H + r) * 4 + 2 + v]);
+    o[2 * H + e] += double(W3[r * 4 + 2 + v]) - double(W3[(H + r) * 4 + v]);
+    return;
+  }
+  e -= 2 * H;
+  o += 4 * H;
+  if (e < 2) {
+    o[e] += double(b3[e]);
+    o[2 + e] += double(b3[2 + e]);
+  }
+}
+
+template <class T>
+struct NadeQB {
+  T *X, *H1, *P2, *Y2, *Z;       // bits [B][Q]; per qubit: tanh, pre-ReLU, ReLU, outputs
+  T *DZ, *D2, *ones;             // backward only (D1 reuses Y2)
+};
+
+template <class T>
+size_t nade_qb_carve(const nqs_model &m, int64_t B, bool bwd, Carver &c, NadeQB<T> &A) {
+  const int64_t Q = 2 * m.n, H2 = 2 * m.hid;
+  A.X = c.take<T>(B * Q);
+  A.H1 = c.take<T>(Q * B * H2);
+  A.P2 = c.take<T>(Q * B * H2);
+  A.Y2 = c.take<T>(Q * B * H2);
+  A.Z = c.take<T>(Q * B * 4);
+  A.DZ = A.D2 = A.ones = nullptr;
+  if (bwd) {
+    A.DZ = c.take<T>(Q * B * 4);
+    A.D2 = c.take<T>(Q * B * H2);
+    A.ones = c.take<T>(B);
+  }
+  return c.used;
+}
+
+// the Q networks on B configurations: H1, P2, Y2 and Z (b3 not added)
+template <class T>
+void nade_qb_layers(nqs_model &m, const uint64_t *x, int64_t B, NadeQB<T> &A, hipStream_t s) {
+  const int Q = 2 * m.n, H = m.hid, H2 = 2 * H;
+  hipLaunchKernelGGL(nade_qb_bits_kernel<T>, g1(B * Q), dim3(256), 0, s, x, B, Q, m.sectors(), A.X);
+  HIP_LAUNCH_OK();
+  gemm_batched<T, false, false>(B, H2, Q, A.X, Q, 0, nade_blk<T>(m, 0, 0), H2, int64_t(Q) * H2,
+                                A.H1, H2, B * H2, Q, false, s);
+  hipLaunchKernelGGL(nade_qb_bias_ctanh_kernel<T>, g1(int64_t(Q) * B * H), dim3(256), 0, s, A.H1,
+                     nade_blk<T>(m, 0, 1), B, Q, H);
+  HIP_LAUNCH_OK();
+  gemm_batched<T, false, false>(B, H2, H2, A.H1, H2, B * H2, nade_blk<T>(m, 0, 2), H2,
+                                int64_t(H2) * H2, A.P2, H2, B * H2, Q, false, s);
+  hipLaunchKernelGGL(nade_qb_bias_lrelu_kernel<T>, g1(int64_t(Q) * B * H2), dim3(256), 0, s, A.P2,
+                     nade_blk<T>(m, 0, 3), B, Q, H2, A.Y2);
+  HIP_LAUNCH_OK();
+  gemm_batched<T, false, false>(B, 4, H2, A.Y2, H2, B * H2, nade_blk<T>(m, 0, 4), 4,
+                                int64_t(H2) * 4, A.Z, 4, B * 4, Q, false, s);
+}
+
+template <class T>
+void nade_qb_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                           double *phase, hipStream_t s) {
+  NadeQB<T> A;
   Carver c0{nullptr};
-  nade_carve<T>(m, B, c0, A);
-  T *d8 = c0.take<T>(B * n * 8);
-  T *dz = c0.take<T>(B * 12);
-  T *dh2 = c0.take<T>(B * H2);
-  T *dh1 = c0.take<T>(B * H2);
+  nade_qb_carve<T>(m, B, false, c0, A);
   Carver c{static_cast<char *>(m.ws.reserve(c0.used))};
-  nade_carve<T>(m, B, c, A);
-  d8 = c.take<T>(B * n * 8);
-  dz = c.take<T>(B * 12);
-  dh2 = c.take<T>(B * H2);
-  dh1 = c.take<T>(B * H2);
-  for (int p = 0; p < n; ++p) {
-    nade_token<T>(m, x, B, p, A, s);
-    hipLaunchKernelGGL(nade_combine_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, p, A.e[0].z,
-                       A.e[1].z, A.e[2].z, m.sectors(), A.out8);
-    HIP_LAUNCH_OK();
-  }
-  hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.out8, 8, m.sectors(),
-                     gl, d8, 8);
+  nade_qb_carve<T>(m, B, false, c, A);
+  nade_qb_layers<T>(m, x, B, A, s);
+  hipLaunchKernelGGL(nade_qb_combine_kernel<T>, g1(B), dim3(256), 0, s, x, B, 2 * m.n,
+                     m.sectors(), A.Z, nade_blk<T>(m, 0, 5), logabs, phase, nullptr, nullptr,
+                     static_cast<T *>(nullptr));
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(mlp_dphase_kernel<T>, g1(B * n * 4), dim3(256), 0, s, x, B, n, gp, d8);
-  HIP_LAUNCH_OK();
-  // gradient of the derived blocks of one qubit (the largest qubit's size)
-  const int64_t gsize = int64_t(2 * n) * H2 + 2 * H2 + int64_t(H2) * H2 + int64_t(H2) * 4 + 4;
-  double *G = static_cast<double *>(m.ws2.reserve(size_t(gsize) * 8));
-  for (int p = 0; p < n; ++p) {
-    nade_token<T>(m, x, B, p, A, s);
-    const int w = 2 * p + 1;
-    hipLaunchKernelGGL(nade_combine_bwd_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, p,
-                       A.e[0].z, A.e[1].z, A.e[2].z, m.sectors(), d8, dz, dz + 4 * B,
-                       dz + 8 * B);
+}
+
+// Gradients of the block matrices of every qubit, accumulated over the chunks
+// of the batch in T (G: the six arrays of nade_qb_fold_kernel, contiguous),
+// then folded onto the canonical parameters in m.grad_acc.
+template <class T>
+void nade_qb_backward(nqs_model &m, const uint64_t *x, int64_t Btot, const double *gl,
+                      const double *gp, int64_t ch, hipStream_t s) {
+  const int Q = 2 * m.n, H = m.hid, H2 = 2 * H;
+  for (int i = 0; i < Q; ++i)
+    NQS_REQUIRE(m.off[size_t(12 * i)] ==
+                    int64_t(H) * i * (i - 1) + int64_t(i) * (2 * H * H + 8 * H + 4),
+                NQS_EINVAL, "per-qubit ansatz: unexpected parameter layout");
+  const int64_t s1 = int64_t(Q) * H2, s2 = int64_t(H2) * H2, s3 = int64_t(H2) * 4;
+  const int64_t gsize = Q * (s1 + H2 + s2 + H2 + s3 + 4);
+  T *G1 = static_cast<T *>(m.ws2.reserve(size_t(gsize) * sizeof(T)));
+  T *gb1 = G1 + Q * s1, *G2 = gb1 + Q * H2, *gb2 = G2 + Q * s2, *G3 = gb2 + Q * H2,
+    *gb3 = G3 + Q * s3;
+  zero_async(G1, size_t(gsize) * sizeof(T), s);
+  NadeQB<T> A;
+  Carver c0{nullptr};
+  nade_qb_carve<T>(m, std::min(ch, Btot), true, c0, A);
+  Carver c{static_cast<char *>(m.ws.reserve(c0.used))};
+  for (int64_t b0 = 0; b0 < Btot; b0 += ch) {
+    const int64_t B = std::min(ch, Btot - b0);
+    Carver cc{c.base};
+    nade_qb_carve<T>(m, B, true, cc, A);
+    const uint64_t *xb = x + b0;
+    nade_qb_layers<T>(m, xb, B, A, s);
+    hipLaunchKernelGGL(nade_qb_combine_kernel<T>, g1(B), dim3(256), 0, s, xb, B, Q, m.sectors(),
+                       A.Z, nade_blk<T>(m, 0, 5), nullptr, nullptr, gl + b0, gp + b0, A.DZ);
     HIP_LAUNCH_OK();
-    zero_async(G, size_t(gsize) * 8, s);
-    nade_subnet_bwd<T>(m, 2 * p, B, A.X0, w, A.e[0], dz, dh2, dh1, G, s);
-    nade_fold<T>(m, 2 * p, G, s);
-    zero_async(G, size_t(gsize) * 8, s);
-    nade_subnet_bwd<T>(m, 2 * p + 1, B, A.X0, w, A.e[1], dz + 4 * B, dh2, dh1, G, s);
-    nade_subnet_bwd<T>(m, 2 * p + 1, B, A.X1, w, A.e[2], dz + 8 * B, dh2, dh1, G, s);
-    nade_fold<T>(m, 2 * p + 1, G, s);
+    fill_ones<T>(A.ones, B, s);
+    // layer 3: dW3 = Y2^T DZ, db3 = 1^T DZ, dY2 = DZ W3^T
+    gemm_batched<T, true, false>(H2, 4, B, A.Y2, H2, B * H2, A.DZ, 4, B * 4, G3, 4, s3, Q, true, s);
+    gemm_batched<T, true, false>(1, 4, B, A.ones, 1, 0, A.DZ, 4, B * 4, gb3, 4, 4, Q, true, s);
+    gemm_batched<T, false, true>(B, H2, 4, A.DZ, 4, B * 4, nade_blk<T>(m, 0, 4), 4, s3, A.D2, H2,
+                                 B * H2, Q, false, s);
+    // layer 2 through the leaky ReLU
+    lrelu_bwd<T>(A.P2, A.D2, int64_t(Q) * B * H2, s);
+    gemm_batched<T, true, false>(H2, H2, B, A.H1, H2, B * H2, A.D2, H2, B * H2, G2, H2, s2, Q,
+                                 true, s);
+    gemm_batched<T, true, false>(1, H2, B, A.ones, 1, 0, A.D2, H2, B * H2, gb2, H2, H2, Q, true,
+                                 s);
+    T *D1 = A.Y2;
+    gemm_batched<T, false, true>(B, H2, H2, A.D2, H2, B * H2, nade_blk<T>(m, 0, 2), H2, s2, D1,
+                                 H2, B * H2, Q, false, s);
+    // layer 1 through the complex tanh; rows of W1 beyond a qubit's inputs get
+    // gradients of padding, which the fold does not read
+    hipLaunchKernelGGL(nade_ctanh_bwd_kernel<T>, g1(int64_t(Q) * B * H), dim3(256), 0, s, A.H1,
+                       D1, int64_t(Q) * B, H);
+    HIP_LAUNCH_OK();
+    gemm_batched<T, true, false>(Q, H2, B, A.X, Q, 0, D1, H2, B * H2, G1, H2, s1, Q, true, s);
+    gemm_batched<T, true, false>(1, H2, B, A.ones, 1, 0, D1, H2, B * H2, gb1, H2, H2, Q, true, s);
   }
+  const int64_t per_max = int64_t(Q - 1) * H + 2 * H + int64_t(H) * H + 2 * H + 2;
+  hipLaunchKernelGGL(nade_qb_fold_kernel<T>, dim3(unsigned(ceil_div(per_max, 256)), unsigned(Q)),
+                     dim3(256), 0, s, G1, gb1, G2, gb2, G3, gb3, Q, H, m.grad_acc.as<double>());
+  HIP_LAUNCH_OK();
 }
 
 template <class T>
@@ -1002,9 +1092,10 @@ int64_t chunk_rows(const nqs_model &m, bool bwd) {
   // configurations per chunk, sized for the model's activation budget (an
   // eighth of the device memory free at creation, 1..16 GiB): on a 288 GB
   // device a whole 2e4-sample, 15-token backward is one chunk of large GEMMs
+  // (per-qubit ansatz: the qubit-batched activations, which also bound the
+  // sampler's token evaluations)
   const int64_t per = m.kind == NQS_MODEL_NADE
-                          ? int64_t(m.n) * 8 * 2 + 2 * (2 * m.n + 1) + 3 * (6 * m.hid + 4) + 12 +
-                                4 * m.hid
+                          ? int64_t(2 * m.n) * (4 * 2 * m.hid + 9) + 1
                       : m.kind == NQS_MODEL_MLP
                           ? int64_t(m.n) * 8 * 4 + 4 * m.n + 3 * m.hid + 8
                           : int64_t(m.n) * (bwd ? (m.L * (7 * m.d + 2 * m.F + 8) +
@@ -1013,7 +1104,7 @@ int64_t chunk_rows(const nqs_model &m, bool bwd) {
   int64_t c = m.act_budget / (per * int64_t(sizeof(T)));
   // at most 128k token rows: measured fastest for the library GEMMs of both transformer
   // workloads (64k and 320k rows are 5-25 % slower per step)
-  c = std::min<int64_t>(c, 131072 / m.n);
+  c = std::min<int64_t>(c, m.kind == NQS_MODEL_NADE ? 65536 : 131072 / m.n);
   return c < 64 ? 64 : c;
 }
 
@@ -1025,7 +1116,9 @@ void forward_T(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, doubl
     return;
   }
   if (m.kind == NQS_MODEL_NADE) {
-    nade_forward_chunk<T>(m, x, B, logabs, phase, logits_keep, s);
+    // the sampler's token outputs from the token path, amplitudes batched over qubits
+    if (logits_keep) nade_forward_chunk<T>(m, x, B, logabs, phase, logits_keep, s);
+    else nade_qb_forward_chunk<T>(m, x, B, logabs, phase, s);
     return;
   }
   Carver c0{nullptr};
@@ -1085,27 +1178,28 @@ void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, d
 
 // derived NADE blocks of every qubit from the canonical parameters
 void nade_pack(nqs_model &m, hipStream_t s) {
-  const int H = m.hid, H2 = 2 * H;
-  m.nade_off.clear();
-  int64_t total = 0;
-  for (int i = 0; i < 2 * m.n; ++i) {
-    const int64_t sizes[kNadeBlocks] = {int64_t(i) * H2, H2, int64_t(H2) * H2, H2,
-                                        int64_t(H2) * 4, 4};
-    for (int k = 0; k < kNadeBlocks; ++k) {
-      m.nade_off.push_back(total);
-      total += sizes[k];
-    }
+  const int H = m.hid, H2 = 2 * H, Q = 2 * m.n;
+  // one array per block kind, qubit-major with a uniform stride (W1 padded to
+  // Q rows), so that the batched products can stride over the qubits
+  const int64_t sizes[kNadeBlocks] = {int64_t(Q) * H2, H2, int64_t(H2) * H2, H2, int64_t(H2) * 4, 4};
+  int64_t first[kNadeBlocks], total = 0;
+  for (int k = 0; k < kNadeBlocks; ++k) {
+    first[k] = total;
+    total += Q * sizes[k];
   }
+  m.nade_off.clear();
+  for (int i = 0; i < Q; ++i)
+    for (int k = 0; k < kNadeBlocks; ++k) m.nade_off.push_back(first[k] + i * sizes[k]);
   m.packed.reserve(size_t(total) * m.elem());
-  for (int i = 0; i < 2 * m.n; ++i) {
-    const int64_t count = int64_t(i) * H2 + 2 * H2 + int64_t(H2) * H2 + int64_t(H2) * 4 + 4;
+  for (int i = 0; i < Q; ++i) {
+    const int64_t count = int64_t(Q) * H2 + 2 * H2 + int64_t(H2) * H2 + int64_t(H2) * 4 + 4;
     auto launch = [&](auto *base) {
       using T = std::remove_pointer_t<decltype(base)>;
       auto prm = [&](int k) { return base + m.off[size_t(12 * i + k)]; };
       auto blk = [&](int k) { return m.packed.as<T>() + m.nade_off[size_t(i) * kNadeBlocks + k]; };
       hipLaunchKernelGGL(nade_pack_kernel<T>, g1(count), dim3(256), 0, s, prm(0), prm(1), prm(2),
                          prm(3), prm(4), prm(5), prm(6), prm(7), prm(8), prm(9), prm(10), prm(11),
-                         i, H, blk(0), blk(1), blk(2), blk(3), blk(4), blk(5));
+                         i, Q, H, blk(0), blk(1), blk(2), blk(3), blk(4), blk(5));
     };
     if (m.fp64())
       launch(m.master.as<double>());
@@ -1120,14 +1214,15 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
   double *acc = static_cast<double *>(m.grad_acc.reserve(size_t(m.P) * 8));
   zero_async(acc, size_t(m.P) * 8, s);
   const int64_t ch = model_chunk(m, true);
-  for (int64_t b0 = 0; b0 < B; b0 += ch) {
+  if (m.kind == NQS_MODEL_NADE && B > 0) {
+    if (m.fp64()) nade_qb_backward<double>(m, x, B, gl, gp, ch, s);
+    else nade_qb_backward<float>(m, x, B, gl, gp, ch, s);
+  }
+  for (int64_t b0 = 0; b0 < B && m.kind != NQS_MODEL_NADE; b0 += ch) {
     const int64_t nb = B - b0 < ch ? B - b0 : ch;
     if (m.kind == NQS_MODEL_MLP) {
       if (m.fp64()) mlp_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
       else mlp_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
-    } else if (m.kind == NQS_MODEL_NADE) {
-      if (m.fp64()) nade_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
-      else nade_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
     } else {
       if (m.fp64()) tf_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
       else tf_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);

@@ -21,6 +21,13 @@ enum Epi : int {
 template <class T, bool TA, bool TB>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb, T *C,
           int64_t ldc, const T *bias, T *aux, int epi, hipStream_t s);
+// Strided batch of row-major products, no epilogue: for q < batch,
+// C_q (+)= op(A_q) op(B_q) with A_q = A + q sa, B_q = B + q sb, C_q = C + q sc
+// (a stride may be 0 to share an operand); accumulate adds into C.
+template <class T, bool TA, bool TB>
+void gemm_batched(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, int64_t sa,
+                  const T *B, int64_t ldb, int64_t sb, T *C, int64_t ldc, int64_t sc,
+                  int64_t batch, bool accumulate, hipStream_t s);
 // dst[i] += src[i] (into a double accumulator)
 template <class T>
 void add_into(const T *src, int64_t n, double *dst, hipStream_t s);

@@ -703,6 +703,35 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
   }
 }
 
+void blas_gemm_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
+                       int k, float alpha, const float *A, int lda, int64_t sa, const float *B,
+                       int ldb, int64_t sb, float beta, float *C, int ldc, int64_t sc, int batch) {
+  BLAS_OK(rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, &alpha, A, lda, sa, B, ldb, sb, &beta,
+                                        C, ldc, sc, batch));
+}
+void blas_gemm_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
+                       int k, double alpha, const double *A, int lda, int64_t sa, const double *B,
+                       int ldb, int64_t sb, double beta, double *C, int ldc, int64_t sc,
+                       int batch) {
+  BLAS_OK(rocblas_dgemm_strided_batched(h, ta, tb, m, n, k, &alpha, A, lda, sa, B, ldb, sb, &beta,
+                                        C, ldc, sc, batch));
+}
+
+template <class T, bool TA, bool TB>
+void gemm_batched(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, int64_t sa,
+                  const T *B, int64_t ldb, int64_t sb, T *C, int64_t ldc, int64_t sc,
+                  int64_t batch, bool accumulate, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  NQS_REQUIRE(M < (int64_t(1) << 31) && N < (int64_t(1) << 31) && K < (int64_t(1) << 31) &&
+                  batch < (int64_t(1) << 31),
+              NQS_EUNSUPPORTED, "gemm_batched: dimension too large");
+  // row-major C = op(A) op(B) is column-major C^T = op(B)^T op(A)^T
+  blas_gemm_batched(blas(s), TB ? rocblas_operation_transpose : rocblas_operation_none,
+                    TA ? rocblas_operation_transpose : rocblas_operation_none, int(N), int(M),
+                    int(K), T(1), B, int(ldb), sb, A, int(lda), sa, accumulate ? T(1) : T(0), C,
+                    int(ldc), sc, int(batch));
+}
+
 template <class T>
 void add_into(const T *src, int64_t n, double *dst, hipStream_t s) {
   if (n <= 0) return;
@@ -933,6 +962,15 @@ void zero_async(void *p, size_t bytes, hipStream_t s) {
                                      int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
   template void gemm<T, true, false>(int64_t, int64_t, int64_t, const T *, int64_t, const T *,  \
                                      int64_t, T *, int64_t, const T *, T *, int, hipStream_t);   \
+  template void gemm_batched<T, false, false>(int64_t, int64_t, int64_t, const T *, int64_t,     \
+                                              int64_t, const T *, int64_t, int64_t, T *, int64_t, \
+                                              int64_t, int64_t, bool, hipStream_t);               \
+  template void gemm_batched<T, false, true>(int64_t, int64_t, int64_t, const T *, int64_t,      \
+                                             int64_t, const T *, int64_t, int64_t, T *, int64_t,  \
+                                             int64_t, int64_t, bool, hipStream_t);                \
+  template void gemm_batched<T, true, false>(int64_t, int64_t, int64_t, const T *, int64_t,      \
+                                             int64_t, const T *, int64_t, int64_t, T *, int64_t,  \
+                                             int64_t, int64_t, bool, hipStream_t);                \
   template void add_into<T>(const T *, int64_t, double *, hipStream_t);                         \
   template void fill_ones<T>(T *, int64_t, hipStream_t);
 
