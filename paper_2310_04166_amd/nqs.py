@@ -186,6 +186,18 @@ class Model:
     def sync(self, stream=None):
         _check(lib().amp_model_sync(self.handle, _stream(stream)))
 
+    def params_tensor(self):
+        """The master parameter vector as a torch tensor aliasing the library's
+        device buffer (no copy; valid while the model lives).  After writing
+        it, call sync() so that the derived (packed) weights follow."""
+        class _Buffer:
+            pass
+        buf = _Buffer()
+        buf.__cuda_array_interface__ = {
+            "shape": (self.n_params,), "typestr": "<f8" if self.param_bytes == 8 else "<f4",
+            "data": (self.params_ptr(), False), "version": 2}
+        return torch.as_tensor(buf, device="cuda")
+
     def get_params(self):
         out = np.zeros(self.n_params, np.float64)
         _check(lib().amp_model_get_params(self.handle, _ptr(out)))
@@ -235,6 +247,35 @@ def amp_backward(model, x, g_logabs, g_phase, grad=None, stream=None):
     _check(lib().amp_backward(model.handle, _ptr(x), x.numel(), _ptr(_dev(g_logabs, torch.float64)),
                               _ptr(_dev(g_phase, torch.float64)), _ptr(grad), _stream(stream)))
     return grad
+
+
+class AmpFn(torch.autograd.Function):
+    """(log|psi(x)|, phase(x)) as a differentiable function of a parameter
+    vector theta in the canonical layout: forward = amp_forward with theta
+    written into the model (unless theta is model.params_tensor() itself) and
+    the derived weights repacked; backward = amp_backward, the hand-written
+    backward with activations recomputed.  Usage:
+        la, ph = AmpFn.apply(theta, model, x)"""
+
+    @staticmethod
+    def forward(ctx, theta, model, x):
+        view = model.params_tensor()
+        if theta.data_ptr() != view.data_ptr():
+            view.copy_(theta.detach().reshape(-1).to(view.dtype))
+        model.sync()
+        x = _dev(x, torch.int64)
+        la, ph = amp_forward(model, x)
+        ctx.model, ctx.theta_dtype = model, theta.dtype
+        ctx.save_for_backward(x)
+        return la, ph
+
+    @staticmethod
+    def backward(ctx, g_la, g_ph):
+        (x,) = ctx.saved_tensors
+        zeros = lambda g: torch.zeros(x.numel(), dtype=torch.float64, device=x.device) if g is None \
+            else g.contiguous().to(torch.float64)
+        grad = amp_backward(ctx.model, x, zeros(g_la), zeros(g_ph))
+        return grad.to(ctx.theta_dtype), None, None
 
 
 def sample_unique(model, n_samples, seed, capacity=None, stream=None, device="cuda"):
