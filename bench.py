@@ -114,10 +114,14 @@ def setup(workload_name, precision):
     return cfg, ham, model, params
 
 
-def vmc_step(nqs, ham, model, cfg, seed, state, t):
+def vmc_step(nqs, ham, model, cfg, seed, state, t, events=None):
     x, cnt, lost = nqs.sample_unique(model, cfg["n_samples"], seed)
     la, ph = nqs.amp_forward(model, x)
+    if events:
+        events[0].record()
     eloc, sums, npairs = nqs.local_energy(ham, model, x, cnt, la, ph)
+    if events:
+        events[1].record()
     gl, gp = nqs.vmc_weights(eloc, cnt, sums)
     grad = nqs.amp_backward(model, x, gl, gp, grad=state["grad"])
     nqs.adam_update(model.params_ptr(), grad, state["m"], state["v"], lr=state["lr"], t=t)
@@ -149,6 +153,11 @@ def precision_check(nqs, torch, args, cfg, ham, model):
     e16, s16, np16, t16 = out["bf16"]
     d = (e16 - e32).abs().cpu().numpy()
     w = cs.cpu().numpy().astype(np.float64)
+    # the highest-count samples, for the oracle's energy on the same samples
+    top = np.argsort(-w, kind="stable")[:args.cpu_sample]
+    cplx = lambda e: e[..., 0] + 1j * e[..., 1] if e.ndim == 2 else e
+    args._top = ([int(v) for v in xs.cpu().numpy().view(np.uint64)[top]], w[top],
+                 cplx(e16.cpu().numpy())[top], cplx(e32.cpu().numpy())[top])
     return {"samples": len(pick), "counts_covered": int(w.sum()), "pairs": int(np32),
             "E_bf16": float(s16[1] / s16[0]), "E_fp32": float(s32[1] / s32[0]),
             "abs_diff_ha": float(abs(s16[1] / s16[0] - s32[1] / s32[0])),
@@ -157,7 +166,7 @@ def precision_check(nqs, torch, args, cfg, ham, model):
             "speedup_bf16_over_fp32": (np16 / t16) / (np32 / t32)}
 
 
-def cpu_baseline(cfg, params, x_sample):
+def cpu_baseline(cfg, params, x_sample, where):
     """The FP64 oracle's local energy on a bounded sample of unique configurations."""
     import torch
     from oracle.model import build_model
@@ -165,17 +174,19 @@ def cpu_baseline(cfg, params, x_sample):
     from synth import make_integrals
     h, eri = make_integrals(cfg["n"], cfg["rank"], cfg["seed"])
     model = build_model(cfg, params)
-    pairs = 0
+    pairs, elocs = 0, []
     t0 = time.perf_counter()
-    for x in x_sample:
-        _, xs, _ = local_energy(model, h, eri, int(x))
-        pairs += len(xs) - 1
+    with torch.no_grad():
+        for x in x_sample:
+            e, xs, _ = local_energy(model, h, eri, int(x))
+            pairs += len(xs) - 1
+            elocs.append(complex(e))
     dt = time.perf_counter() - t0
     return {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{len(x_sample)} unique configurations of step 0 (largest counts) with all "
+            "sample": f"{len(x_sample)} unique configurations ({where}, largest counts) with all "
                       f"their {pairs} connected x' (FP64 torch CPU forward + Slater-Condon "
-                      f"matrix elements), {dt:.1f} s"}
+                      f"matrix elements), {dt:.1f} s"}, np.array(elocs)
 
 
 def tf_roofline(flop, slots, k_ms):
@@ -391,6 +402,7 @@ def main():
     nqs.timing_enable(True)
     nqs.timing_read()
     total_pairs, total_unique, total_distinct, step_ms, energies = 0, 0, 0, [], []
+    eloc_ms, eloc_pairs = [], []
     first = None
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -398,9 +410,12 @@ def main():
     t_start = time.perf_counter()
     for k in range(args.steps):
         s0 = time.perf_counter()
-        x, cnt, eloc, sums, npairs = vmc_step(nqs, ham, model, cfg, k, state, t)
+        evs = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        x, cnt, eloc, sums, npairs = vmc_step(nqs, ham, model, cfg, k, state, t, evs)
         t += 1
         torch.cuda.synchronize()
+        eloc_ms.append(evs[0].elapsed_time(evs[1]))
+        eloc_pairs.append(npairs)
         step_ms.append((time.perf_counter() - s0) * 1e3)
         s = sums.cpu().numpy()
         energies.append(float(s[1] / s[0]))
@@ -448,11 +463,21 @@ def main():
         del roofline["valu_slots"]
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and precision:
+        # the oracle at the initial parameters on the precision check's
+        # highest-count samples: its energy there against both GPU paths
+        xs_cpu, w, e16, e32 = args._top
+        cpu, e_or = cpu_baseline(cfg, params, xs_cpu, "the precision check's samples")
+        E = lambda e: float(np.real(np.sum(w * e) / np.sum(w)))
+        precision.update({"oracle_samples": len(xs_cpu), "oracle_counts": int(w.sum()),
+                          "E_oracle_top": E(e_or), "E_bf16_top": E(e16), "E_fp32_top": E(e32),
+                          "abs_diff_bf16_oracle_top_ha": abs(E(e16) - E(e_or)),
+                          "abs_diff_fp32_oracle_top_ha": abs(E(e32) - E(e_or))})
+    elif not args.no_cpu:
         x0, c0 = first
         top = torch.argsort(c0, descending=True)[:args.cpu_sample]
         xs_cpu = [int(v) for v in x0[top].cpu().numpy().view(np.uint64)]
-        cpu = cpu_baseline(cfg, params, xs_cpu)
+        cpu, _ = cpu_baseline(cfg, params, xs_cpu, "step 0")
 
     out = {"metric": "connected-config E_loc evals/s over full VMC steps (30 qubits)",
            "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -469,6 +494,9 @@ def main():
                       "distinct_xprime_per_step": total_distinct / args.steps,
                       "gpu_ms_per_step": round(gpu_ms / args.steps, 2),
                       "step_ms": [round(v, 1) for v in step_ms],
+                      "step_ms_median": round(float(np.median(step_ms)), 2),
+                      "local_energy_pairs_per_s": round(sum(eloc_pairs) / (sum(eloc_ms) * 1e-3), 1),
+                      "local_energy_ms": [round(v, 2) for v in eloc_ms],
                       "energy_per_step": energies},
            "roofline": roofline, "cpu_baseline": cpu, "precision": precision}
     print(json.dumps(out), flush=True)
