@@ -354,7 +354,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="precision")
+    ap.add_argument("--workload", default="precision", choices=["precision", "nade", "batching"],
+                    help="precision: the 30-spin-orbital transformer step (default); nade: the "
+                         "same system with the paper's per-qubit ansatz; batching: 64 molecules")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--fp32-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
