@@ -42,19 +42,21 @@ def pair(nqs, n, na, nb, hidden, seed, precision="fp64", strategy="MU", d=0, std
 
 @pytest.mark.parametrize("n,na,nb,hidden,precision,std,tol", [
     (4, 2, 1, 16, "fp64", 0.3, 1e-12), (6, 2, 2, 64, "fp64", 0.3, 1e-12),
-    (6, 2, 2, 64, "fp32", 0.1, 1e-4)])
+    (6, 2, 2, 64, "fp32", 0.1, 1e-4), (16, 4, 3, 32, "fp64", 0.2, 1e-11)])
 def test_forward(nqs, n, na, nb, hidden, precision, std, tol):
     """FP32 tolerance: the complex tanh has poles at i pi / 2, near which float32
-    rounding of its argument is amplified; smaller weights keep away from them."""
+    rounding of its argument is amplified; smaller weights keep away from them.
+    The 32-qubit case runs on 500 sampled configurations of its sector."""
     _, sec, ref, m = pair(nqs, n, na, nb, hidden, 3, precision, std=std)
-    xs = sec.enumerate()
+    xs = sec.enumerate() if n <= 8 else sector_sample(n, na, nb, 500, 1)
     la, ph = nqs.amp_forward(m, dev(xs))
     rla, rph = ref.amplitudes(xs)
     e_la = np.max(np.abs(la.cpu().numpy() - rla.detach().numpy()))
     e_ph = np.max(np.abs(ph.cpu().numpy() - rph.detach().numpy()))
     log(f"nade forward n={n} H={hidden} {precision}: |dla| {e_la:.2e} |dph| {e_ph:.2e}")
     assert e_la < tol and e_ph < tol
-    assert abs(np.exp(2 * la.cpu().numpy()).sum() - 1.0) < max(tol, 1e-10)
+    if n <= 8:
+        assert abs(np.exp(2 * la.cpu().numpy()).sum() - 1.0) < max(tol, 1e-10)
 
 
 def test_forward_discard_unphysical(nqs):
@@ -88,11 +90,14 @@ def test_sampler_replay_fp64(nqs, strategy, d):
     assert k.cpu().tolist() == cnt_o
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
-def test_backward(nqs, precision, tol):
-    params, sec, _, m = pair(nqs, 4, 2, 2, 16, 8, precision)
-    spec = nade_param_spec(4, 16)
-    xs = sec.enumerate()
+@pytest.mark.parametrize("n,precision,tol", [(4, "fp64", 1e-10), (4, "fp32", 2e-4),
+                                              (8, "fp64", 1e-10)])
+def test_backward(nqs, n, precision, tol):
+    """All qubits' networks in one batched backward; the 16-qubit case on 400
+    sampled configurations."""
+    params, sec, _, m = pair(nqs, n, 2, 2, 16, 8, precision)
+    spec = nade_param_spec(n, 16)
+    xs = sec.enumerate() if n <= 4 else sector_sample(n, 2, 2, 400, 2)
     rng = np.random.default_rng(2)
     g = rng.normal(size=(2, len(xs)))
     grad = nqs.amp_backward(m, dev(xs), torch.tensor(g[0]).cuda(), torch.tensor(g[1]).cuda())
