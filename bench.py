@@ -77,7 +77,7 @@ def nade_work(n_qubits, hidden):
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid only for the kernel source they were
 # taken on (sha256 prefix), otherwise the roofline reports null.
-FUSED_TRAFFIC = {"source_sha256_prefix": "1c833bad5f4d6cb5", "bytes_per_launch": 29.53e6,
+FUSED_TRAFFIC = {"source_sha256_prefix": "0de792b0d2361359", "bytes_per_launch": 29.73e6,
                  "profile": "profiles/fused_kernel_precision_traffic.md"}
 
 

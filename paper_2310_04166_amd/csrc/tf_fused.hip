@@ -20,8 +20,14 @@
 //     S^T = K Q^T,  P^T = softmax over keys,  O^T = V^T P^T,
 // where V comes out key-major and O^T feature-major again.
 //
-// Per 32 rows and layer: Q, K (2 x 8 x 8), V (8 x 4), S (8), O (16),
-// out-projection (32), FFN (128 + 128) MFMAs.  After 16 passes (32
+// The attention probabilities P and the attention output O enter their
+// products as bf16 pairs hi + lo (lo = the rounding error of hi, two MFMAs per
+// product): their bf16 rounding dominated the error of the local energy of the
+// highest-count samples (1.6e-4 Ha against the FP64 oracle on the 30-qubit
+// system; 1.7e-6 Ha with the pairs, for 7 % more kernel time).
+//
+// Per 32 rows and layer: Q, K (2 x 8 x 8), V (8 x 4), S (8), O (2 x 16),
+// out-projection (2 x 32), FFN (128 + 128) MFMAs.  After 16 passes (32
 // configurations) the phase MLP of those 32 configurations runs as one
 // 256 x 256 GEMM with the configurations as the 32 columns.
 #include <cmath>
@@ -135,6 +141,22 @@ __device__ inline bf16x8 pack8(const float (&v)[8]) {
   return r;
 }
 
+
+// v = hi + lo, both bf16 (lo is the rounding error of hi)
+__device__ inline void pack8_hilo(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
+  hi = pack8(v);
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = v[i] - float(hi[i]);
+  lo = pack8(r);
+}
+// the bf16 rounding error of to_bf16(c, half) == hi, as bf16
+__device__ inline bf16x8 lo_bf16(const f32x16 &c, int half, const bf16x8 &hi) {
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = c[half * 8 + i] - float(hi[i]);
+  return pack8(r);
+}
 
 // 16 consecutive floats from LDS
 __device__ inline f32x16 lds16(const float *p) {
@@ -422,24 +444,34 @@ fused_kernel(FusedArgs a) {
           const float inv = __builtin_amdgcn_rcpf(pair_sum(sum));
 #pragma unroll
           for (int i = 0; i < 8; ++i) p[i] *= inv;
-          const i32x4 pp = __builtin_bit_cast(i32x4, pack8(p));
+          // P as hi + lo; each split into the lower / upper configuration's keys
+          bf16x8 ph8, pl8;
+          pack8_hilo(p, ph8, pl8);
+          const i32x4 pp = __builtin_bit_cast(i32x4, ph8), ql = __builtin_bit_cast(i32x4, pl8);
           const int m = int(upmask);
           const i32x4 plo = {pp[0] & ~m, pp[1] & ~m, pp[2] & ~m, pp[3] & ~m};
           const i32x4 phi = {pp[0] & m, pp[1] & m, pp[2] & m, pp[3] & m};
+          const i32x4 qlo = {ql[0] & ~m, ql[1] & ~m, ql[2] & ~m, ql[3] & ~m};
+          const i32x4 qhi = {ql[0] & m, ql[1] & m, ql[2] & m, ql[3] & m};
           f32x16 Oe = mfma(V0, __builtin_bit_cast(bf16x8, plo), f32x16{});
           Oe = mfma(V1, __builtin_bit_cast(bf16x8, phi), Oe);
+          Oe = mfma(V0, __builtin_bit_cast(bf16x8, qlo), Oe);
+          Oe = mfma(V1, __builtin_bit_cast(bf16x8, qhi), Oe);
 #pragma unroll
           for (int j = 0; j < 8; ++j) O[e * 8 + j] = Oe[e * 8 + j];
         }
         const bf16x8 O0 = to_bf16(O, 0), O1 = to_bf16(O, 1);
-        // output projection: fragment i = 2q + e (q = output block)
+        const bf16x8 L0 = lo_bf16(O, 0, O0), L1 = lo_bf16(O, 1, O1);
+        // output projection of O = hi + lo: fragment i = 2q + e (q = output block)
 #pragma unroll
-        for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]);
+        for (int i = 0; i < HS; ++i)
+          res[i / 2] = mfma(fr[0][i], (i % 2) ? L1 : L0, mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]));
         advance(W, 4 * b + 5);   // next Q, or the first FFN step
         fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
         for (int i = 0; i < HS; ++i)
-          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]);
+          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? L1 : L0,
+                                   mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]));
       }
       // ---- feed-forward block: step 4NB + 2fb = W1, +1 = W2
       layer_norm<NB>(res, V16, int(S::VLN2G), int(S::VLN2B), X);
