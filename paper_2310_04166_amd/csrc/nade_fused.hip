@@ -25,7 +25,12 @@
 //   combine: lanes 0..31 hold z of their configuration: Mask-Unphysical on
 //            the qubit's two values, log psi_i(v) = z_v - LSE(2 Re z)/2,
 //            log|psi| and phase accumulated in double.
-// Per qubit and wave: 4 ceil(i/16) + 32 + 8 MFMAs and 2048 complex tanh; the
+// The inputs of layers 2 and 3 (tanh and leaky-ReLU outputs) enter as bf16
+// pairs hi + lo (lo = the rounding error of hi, two MFMAs per product): with
+// single bf16 operands the local energy of the dominant samples of the
+// 30-qubit system was 6.7e-4 Ha off the FP64 oracle (7e-7 Ha with the pairs),
+// the per-sample local energies 8e-3 Ha on average (1e-5 Ha).
+// Per qubit and wave: 4 ceil(i/16) + 64 + 16 MFMAs and 2048 complex tanh; the
 // tanh (four transcendentals each) bounds the kernel, not HBM (8 bytes in and
 // 16 bytes out per configuration).
 #include <cmath>
@@ -95,6 +100,15 @@ __device__ inline bf16x8 pack8(const float (&v)[8]) {
   return r;
 }
 
+// v = hi + lo, both bf16 (lo is the rounding error of hi)
+__device__ inline void pack8_hilo(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
+  hi = pack8(v);
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = v[i] - float(hi[i]);
+  lo = pack8(r);
+}
+
 // bits first .. first+7 of occ as bf16 0.0 / 1.0 (0x3F80), in natural order
 __device__ inline bf16x8 bits_frag(uint64_t occ, int first) {
   const uint32_t byte = uint32_t(occ >> first) & 0xFFu;
@@ -128,8 +142,9 @@ __device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane
   const float *V = a.vec + int64_t(i) * kVec;
   const int ks = (i + 15) >> 4;
   // layer 1 and the complex tanh, one pair of blocks (Re features 32b.., Im
-  // features 64 + 32b..) at a time, so that at most 32 accumulators are live
-  bf16x8 hf[8];
+  // features 64 + 32b..) at a time, so that at most 32 accumulators are live;
+  // the tanh outputs as hi (hf) + lo (hl)
+  bf16x8 hf[8], hl[8];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     f32x16 ar = load16(V + (2 * b + h) * 16), ai = load16(V + (2 * (b + 2) + h) * 16);
@@ -143,18 +158,22 @@ __device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane
       float re[8], im[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) ctanh(ar[8 * u + e], ai[8 * u + e], re[e], im[e]);
-      hf[2 * b + u] = pack8(re);
-      hf[4 + 2 * b + u] = pack8(im);
+      pack8_hilo(re, hf[2 * b + u], hl[2 * b + u]);
+      pack8_hilo(im, hf[4 + 2 * b + u], hl[4 + 2 * b + u]);
     }
   }
   W += 4 * ks * 64;
-  // layer 2 one output block at a time, leaky ReLU applied at once
-  bf16x8 g[8];
+  // layer 2 one output block at a time, leaky ReLU applied at once (its
+  // outputs as hi (g) + lo (gl))
+  bf16x8 g[8], gl[8];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x16 c = load16(V + kFeat + (2 * t + h) * 16);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c = mfma(W[(t * 8 + k) * 64], hf[k], c);
+    for (int k = 0; k < 8; ++k) {
+      const bf16x8 w = W[(t * 8 + k) * 64];
+      c = mfma(w, hl[k], mfma(w, hf[k], c));
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       float v[8];
@@ -163,14 +182,17 @@ __device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane
         const float y = c[8 * u + e];
         v[e] = fmaxf(y, 0.01f * y);
       }
-      g[2 * t + u] = pack8(v);
+      pack8_hilo(v, g[2 * t + u], gl[2 * t + u]);
     }
   }
   W += 32 * 64;
   f32x16 z = {};
   const bf16x8 zero = {};
 #pragma unroll
-  for (int k = 0; k < 8; ++k) z = mfma(col < 4 ? W[k * 64] : zero, g[k], z);
+  for (int k = 0; k < 8; ++k) {
+    const bf16x8 w3 = col < 4 ? W[k * 64] : zero;
+    z = mfma(w3, gl[k], mfma(w3, g[k], z));
+  }
   const float *b3 = V + 2 * kFeat;
   return f32x4{z[0] + b3[0], z[1] + b3[1], z[2] + b3[2], z[3] + b3[3]};
 }
@@ -264,9 +286,10 @@ __device__ inline void nade_body(const NadeArgs &a) {
   }
 }
 
-// four waves per SIMD (at most 128 registers, a 16-byte spill): the kernel is
-// latency-bound, and 4 waves beat 3 (the compiler's default) by 10 % and 2 by 40 %
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+// three waves per SIMD (164 registers): the kernel is latency-bound and more
+// waves help, but at four the hi / lo operands spill 140 bytes per lane (40 %
+// slower than three)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 nade_fused_kernel(NadeArgs a) {
   nade_body<false>(a);
 }

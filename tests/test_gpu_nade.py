@@ -188,8 +188,9 @@ def sector_sample(n, na, nb, count, seed):
     (32, 3, 3, 200),          # 64 qubits: W1 over four k-steps
 ])
 def test_bf16_fused_forward_vs_oracle(nqs, n, na, nb, count):
-    """The fused bf16 kernel (bf16 operands, fp32 accumulation) against the FP64
-    oracle and the FP32 GPU path at the same (bf16-representable) weights."""
+    """The fused bf16 kernel (bf16 weights, activations as bf16 hi + lo pairs,
+    fp32 accumulation) against the FP64 oracle and the FP32 GPU path at the same
+    (bf16-representable) weights."""
     params = make_nade_params(n, 64, seed=20 + n, std=0.1, bias_std=0.05, round_to="bf16",
                               n_alpha=na, n_beta=nb, hf_bias=1.0)
     flat = flatten_params(params, nade_param_spec(n, 64))
@@ -209,10 +210,10 @@ def test_bf16_fused_forward_vs_oracle(nqs, n, na, nb, count):
         f"(fp32 {e32:.1e}); logabs {rla.min():.2f}..{rla.max():.2f}")
     assert np.all(np.isfinite(la)) and np.all(np.isfinite(ph))
     assert e32 < 1e-4
-    assert e_la < 2e-2 and e_ph < 2e-2
-    assert abs(np.mean(la - rla)) < 5e-3
+    assert e_la < 2e-4 and e_ph < 2e-4
+    assert abs(np.mean(la - rla)) < 2e-5
     if count is None:
-        assert abs(np.exp(2 * la).sum() - 1.0) < 1e-2
+        assert abs(np.exp(2 * la).sum() - 1.0) < 1e-4
 
 
 def test_bf16_masks_du_and_empty(nqs):
@@ -232,9 +233,9 @@ def test_bf16_masks_du_and_empty(nqs):
     la_du, ph_du = nqs.amp_forward(du, dev(xs))
     with torch.no_grad():
         rla, rph = (v.numpy() for v in NADEModel(params, sec, mask_levels=0).amplitudes(xs))
-    assert np.max(np.abs(la_du.cpu().numpy() - rla)) < 2e-2
-    assert np.max(np.abs(ph_du.cpu().numpy() - rph)) < 2e-2
-    assert abs(np.exp(2 * la_du.cpu().numpy()).sum() - 1.0) < 1e-2
+    assert np.max(np.abs(la_du.cpu().numpy() - rla)) < 2e-4
+    assert np.max(np.abs(ph_du.cpu().numpy() - rph)) < 2e-4
+    assert abs(np.exp(2 * la_du.cpu().numpy()).sum() - 1.0) < 1e-4
     la0, _ = nqs.amp_forward(mu, torch.zeros(0, dtype=torch.int64, device="cuda"))
     assert la0.numel() == 0
 
@@ -256,9 +257,9 @@ def test_bf16_z2_restricted(nqs):
     la, ph = nqs.amp_forward(m, dev(xs))
     with torch.no_grad():
         rla, rph = (v.numpy() for v in ref.amplitudes(xs))
-    assert np.max(np.abs(la.cpu().numpy() - rla)) < 2e-2
-    assert np.max(np.abs(ph.cpu().numpy() - rph)) < 2e-2
-    assert abs(np.exp(2 * la.cpu().numpy()).sum() - 1.0) < 1e-2
+    assert np.max(np.abs(la.cpu().numpy() - rla)) < 2e-4
+    assert np.max(np.abs(ph.cpu().numpy() - rph)) < 2e-4
+    assert abs(np.exp(2 * la.cpu().numpy()).sum() - 1.0) < 1e-4
     outside = [x for x in Sector(6, 2, 2).enumerate() if not sec.contains(x)]
     la_out, _ = nqs.amp_forward(m, dev(outside))
     assert torch.all(torch.isneginf(la_out))
@@ -285,7 +286,7 @@ def test_bf16_full_size_step_sampled_parity(nqs):
     s, s32 = sums.cpu().numpy(), s32.cpu().numpy()
     de = abs(s[1] / s[0] - s32[1] / s32[0])
     log(f"  E bf16 {s[1] / s[0]:.6f} fp32 {s32[1] / s32[0]:.6f} |diff| {de:.2e} Ha")
-    assert de < 1e-3
+    assert de < 1e-5
     ref = NADEModel(params, Sector(cfg["n"], cfg["n_alpha"], cfg["n_beta"]))
     xv, cv, e = x.cpu().numpy().view(np.uint64), c.cpu().numpy(), eloc.cpu().numpy()
     rng = np.random.default_rng(0)
@@ -294,7 +295,7 @@ def test_bf16_full_size_step_sampled_parity(nqs):
             want, _, _ = oracle_eloc(ref, h, eri, int(xv[i]))
         err = abs(e[i] - want)
         log(f"  x={int(xv[i]):#x} count={cv[i]} eloc gpu={e[i]:.6f} oracle={want:.6f} err={err:.2e}")
-        assert err < 5e-3 * max(1.0, abs(want))
+        assert err < 1e-5 * max(1.0, abs(want))
 
 
 @pytest.mark.parametrize("strategy,d", [("MU", 0), ("MUd", 1)])
