@@ -1,0 +1,49 @@
+"""The algorithmic work counts behind bench.py's roofline (host arithmetic, no
+GPU): the constants agree with the per-configuration formulas, the formulas
+with sums written out by hand, and the roofline reports the lower ceiling."""
+import bench
+
+
+def test_transformer_flops_constant_matches_the_formula():
+    # 15 tokens, d 128, 4 layers, ffn 512, phase MLP 256
+    assert bench.FLOP_PER_CONFIG == bench.flop_per_config(15, 128, 4, 512, 256)
+
+
+def test_transformer_flops_by_hand():
+    # per token and layer: q, k, v, o (4 d^2) + ffn (2 d f) multiply-adds;
+    # attention: per layer 2 d (scores and P V) per causal (query, key) pair
+    n, d, L, f, ph = 3, 8, 2, 16, 4
+    macs = n * L * (4 * d * d + 2 * d * f) + L * 2 * d * (1 + 2 + 3) + n * 4 * d + ph * ph + ph
+    assert bench.flop_per_config(n, d, L, f, ph) == 2 * macs
+
+
+def test_transformer_valu_slots_by_hand():
+    n, d, L, H, f, ph = 2, 4, 1, 2, 8, 4
+    ln = 5 * d + 4                                    # one layer norm of one token
+    per_layer = n * (2 * ln + 2 * d + 13 * f) + H * 3 * 8 + H * n * 4
+    total = per_layer + n * d + n * ln + n * 28 + n * ph + 2 * 13 * ph + ph
+    assert bench.tf_valu_slots(n, d, L, H, f, ph) == total
+    # the 30-qubit model of the precision workload
+    assert bench.tf_valu_slots(15, 128, 4, 8, 512, 256) == 547392
+
+
+def test_nade_work_by_hand():
+    flop, slots = bench.nade_work(3, 2)               # 3 qubits, hidden 2 (4 real features)
+    assert flop == 2 * sum(i * 4 + 16 + 16 for i in range(3))
+    assert slots == 3 * (2 * 27 + 4 * 2 + 18)
+    assert bench.nade_work(30, 64) == (1125120, 60060)
+
+
+def test_roofline_reports_the_lower_ceiling():
+    # VALU-bound: the same time is a larger fraction of the VALU peak
+    # (fractions are reported to four decimals)
+    r = bench.tf_roofline(flop=1e14, slots=1e13, k_ms=1000.0)
+    assert r["bound"] == "alu" and abs(r["frac"] - 10.0 / bench.VALU_PEAK_TOPS) < 5e-5
+    assert abs(r["mfma_frac"] - 100.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
+    r = bench.tf_roofline(flop=1e15, slots=1e9, k_ms=1000.0)
+    assert r["bound"] == "mfma" and abs(r["frac"] - 1000.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
+
+
+def test_valu_peak_from_unit_counts():
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
