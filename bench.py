@@ -131,7 +131,9 @@ def vmc_step(nqs, ham, model, cfg, seed, state, t, events=None):
 
 def precision_check(nqs, torch, args, cfg, ham, model):
     """bf16 vs fp32 GPU paths on the same samples at the same (initial) parameters:
-    the 1024 unique samples with the largest counts plus 1024 drawn uniformly."""
+    the 1024 unique samples with the largest counts plus 1024 drawn uniformly.
+    Returns the comparison and, for the oracle, the args.cpu_sample samples with
+    the largest counts: (configurations, counts, bf16 E_loc, fp32 E_loc)."""
     x, c, _ = nqs.sample_unique(model, cfg["n_samples"], 7)
     order = torch.argsort(c, descending=True)
     rng = np.random.default_rng(0)
@@ -156,9 +158,9 @@ def precision_check(nqs, torch, args, cfg, ham, model):
     # the highest-count samples, for the oracle's energy on the same samples
     top = np.argsort(-w, kind="stable")[:args.cpu_sample]
     cplx = lambda e: e[..., 0] + 1j * e[..., 1] if e.ndim == 2 else e
-    args._top = ([int(v) for v in xs.cpu().numpy().view(np.uint64)[top]], w[top],
-                 cplx(e16.cpu().numpy())[top], cplx(e32.cpu().numpy())[top])
-    return {"samples": len(pick), "counts_covered": int(w.sum()), "pairs": int(np32),
+    top_samples = ([int(v) for v in xs.cpu().numpy().view(np.uint64)[top]], w[top],
+                   cplx(e16.cpu().numpy())[top], cplx(e32.cpu().numpy())[top])
+    return top_samples, {"samples": len(pick), "counts_covered": int(w.sum()), "pairs": int(np32),
             "E_bf16": float(s16[1] / s16[0]), "E_fp32": float(s32[1] / s32[0]),
             "abs_diff_ha": float(abs(s16[1] / s16[0] - s32[1] / s32[0])),
             "count_weighted_mean_abs_eloc_diff": float((w * d).sum() / w.sum()),
@@ -381,7 +383,8 @@ def main():
     cfg, ham, model, params = setup(args.workload, "bf16")
     dev = torch.device("cuda:0")
     log(f"workload {args.workload}: n={cfg['n']} N_s={cfg['n_samples']} params={model.n_params}")
-    precision = None if args.no_fp32 else precision_check(nqs, torch, args, cfg, ham, model)
+    top_samples, precision = (None, None) if args.no_fp32 else \
+        precision_check(nqs, torch, args, cfg, ham, model)
     if precision:
         log(f"precision: {precision}")
 
@@ -468,7 +471,7 @@ def main():
     if not args.no_cpu and precision:
         # the oracle at the initial parameters on the precision check's
         # highest-count samples: its energy there against both GPU paths
-        xs_cpu, w, e16, e32 = args._top
+        xs_cpu, w, e16, e32 = top_samples
         cpu, e_or = cpu_baseline(cfg, params, xs_cpu, "the precision check's samples")
         E = lambda e: float(np.real(np.sum(w * e) / np.sum(w)))
         precision.update({"oracle_samples": len(xs_cpu), "oracle_counts": int(w.sum()),
