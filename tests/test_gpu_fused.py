@@ -121,3 +121,33 @@ def test_precision_workload_full_step_sampled_parity(nqs):
         err = abs(e[i] - want)
         log(f"  x={int(xv[i]):#x} count={cv[i]} eloc gpu={e[i]:.6f} oracle={want:.6f} err={err:.2e}")
         assert err < 5e-3 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("strategy,d", [("MU", 0), ("MUd", 1)])
+def test_fused_sampler_matches_its_forward(nqs, strategy, d):
+    """The bf16 sampler's conditionals come from the fused kernel's conditional
+    mode; its samples follow exp(2 log|psi|) of the fused forward (chi-square
+    over the 225-determinant sector, 1e6 samples)."""
+    from scipy.stats import chi2
+    n, na, nb, dm = 6, 2, 2, 64
+    params = make_transformer_params(n, na, nb, dm, 1, seed=12, std=0.05, hf_bias=0.5,
+                                     round_to="bf16", bias_std=0.02)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, dm, 1, 4, 4 * dm, 256],
+                  flatten_params(params, transformer_param_spec(n, dm, 1, 4 * dm, 256)), "bf16",
+                  strategy, d)
+    sec = Sector(n, na, nb)
+    xs = sec.enumerate()
+    la, _ = nqs.amp_forward(m, dev(xs))
+    prob = np.exp(2 * la.cpu().numpy())
+    x, c, lost = nqs.sample_unique(m, 1_000_000, 21)
+    got = dict(zip(x.cpu().numpy().view(np.uint64).tolist(), c.cpu().tolist()))
+    assert all(sec.contains(int(v)) for v in got)
+    if strategy == "MU":
+        assert lost == 0 and abs(prob.sum() - 1.0) < 1e-3
+    expect = prob / prob.sum() * (1_000_000 - lost)
+    obs = np.array([got.get(int(v), 0) for v in xs], dtype=np.float64)
+    keep = expect > 5
+    stat = np.sum((obs[keep] - expect[keep]) ** 2 / expect[keep])
+    pval = chi2.sf(stat, keep.sum() - 1)
+    log(f"fused sampler {strategy}: lost {lost}, chi2 {stat:.1f} on {keep.sum() - 1} dof, p = {pval:.3f}")
+    assert pval > 1e-4
