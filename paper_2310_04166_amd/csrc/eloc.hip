@@ -166,6 +166,39 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ 
   if (threadIdx.x == 0) out[n] = carry;
 }
 
+// First pass of the multi-block scan: tile t (1024 entries) scanned exclusively
+// in place of out, its total in tile_sum[t].
+__global__ void __launch_bounds__(1024) tile_scan_kernel(const int64_t *__restrict__ in,
+                                                         int64_t *__restrict__ out, int64_t n,
+                                                         int64_t *__restrict__ tile_sum) {
+  __shared__ int64_t warp_sums[16];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const int64_t v = (i < n) ? in[i] : 0;
+  int64_t s = v;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t o = __shfl_up(s, d);
+    if (lane >= d) s += o;
+  }
+  if (lane == kWave - 1) warp_sums[w] = s;
+  __syncthreads();
+  int64_t prefix = 0;
+  for (int k = 0; k < w; ++k) prefix += warp_sums[k];
+  if (i < n) out[i] = prefix + s - v;
+  if (threadIdx.x == 1023) tile_sum[blockIdx.x] = prefix + s;
+}
+
+__global__ void copy_one_kernel(const int64_t *__restrict__ src, int64_t *__restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+// Third pass: the exclusive offset of each tile added to its entries.
+__global__ void __launch_bounds__(1024) tile_add_kernel(int64_t *__restrict__ out, int64_t n,
+                                                        const int64_t *__restrict__ tile_off) {
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < n) out[i] += tile_off[blockIdx.x];
+}
+
 // E_loc(x_i) = hdiag_i + sum_j H_ij exp((la'_j - la_i) + i (ph'_j - ph_i)), one
 // wave per x over its contiguous pairs, fixed-order reduction, double.  With
 // uid, the amplitudes of pair j are those of distinct configuration uid[j].
@@ -272,8 +305,33 @@ void launch_emit_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, const int
   HIP_LAUNCH_OK();
 }
 
+// Up to 8 tiles one block scans alone; beyond, three passes (tiles, the tile
+// totals with the one-block scan, offsets added back) over a per-device
+// scratch array of tile totals, which grows outside any graph capture (no
+// captured sequence of this library contains a scan).
 void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, in, out, n);
+  const int64_t tiles = ceil_div(n, 1024);
+  if (tiles <= 8) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, in, out, n);
+    HIP_LAUNCH_OK();
+    return;
+  }
+  static DevBuf scratch[64];
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  NQS_REQUIRE(dev >= 0 && dev < 64, NQS_EHIP, "device index out of range");
+  NQS_REQUIRE(tiles < (int64_t(1) << 31), NQS_EUNSUPPORTED, "scan: too many entries");
+  auto *tile_sum = static_cast<int64_t *>(scratch[dev].reserve(size_t(2 * tiles + 1) * 8));
+  int64_t *tile_off = tile_sum + tiles;
+  hipLaunchKernelGGL(tile_scan_kernel, dim3(unsigned(tiles)), dim3(1024), 0, s, in, out, n,
+                     tile_sum);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, tile_sum, tile_off, tiles);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(tile_add_kernel, dim3(unsigned(tiles)), dim3(1024), 0, s, out, n, tile_off);
+  HIP_LAUNCH_OK();
+  // out[n] = the total, the last entry of the tile-offset scan
+  hipLaunchKernelGGL(copy_one_kernel, dim3(1), dim3(64), 0, s, tile_off + tiles, out + n);
   HIP_LAUNCH_OK();
 }
 

@@ -70,6 +70,23 @@ def test_connected_pairs_bit_exact(nqs, n, na, nb, count):
         assert abs(hd[i] - ref_v[0]) <= 1e-12 * abs(ref_v[0])
 
 
+def test_connected_pairs_offsets_of_many_samples(nqs):
+    """10,001 samples (the offsets' scan runs in tiles of 1024 plus a scan of the
+    tile totals): offsets equal the cumulative connected counts, the per-sample
+    count (92 at 12 spin-orbitals, 2+2) being exact combinatorics."""
+    n, na, nb = 6, 2, 2
+    h, eri = make_integrals(n, 2 * n, 106)
+    H = nqs.ham_compile(h, eri, na, nb)
+    xs = (Sector(n, na, nb).enumerate() * 45)[:10001]
+    off, xp, _, _ = nqs.connected_pairs(H, dev(xs))
+    off = off.cpu().numpy()
+    assert np.array_equal(off, 92 * np.arange(len(xs) + 1))
+    xp = xp.cpu().numpy().view(np.uint64)
+    for i in (0, 1023, 1024, 5000, 10000):          # tiles' edges and the tail
+        ref_x, _ = slater_condon_row(h, eri, xs[i])
+        assert sorted(int(v) for v in xp[off[i]:off[i + 1]]) == sorted(ref_x[1:])
+
+
 def test_connected_pairs_edge_cases(nqs):
     h, eri = make_integrals(6, 12, 1)
     H = nqs.ham_compile(h, eri, 2, 2)
