@@ -5,6 +5,21 @@ Argument marshalling only: every step of the hot path runs in the HIP library
 configurations travel as ``torch.int64`` tensors holding the uint64 bit
 strings.  The library must be built (``python -m paper_2310_04166_amd.build``);
 loading fails loudly if it is missing.
+
+One VMC step (the paper's loop: sample, local energy, gradient, Adam)::
+
+    ham = ham_compile(h, eri, n_alpha, n_beta)            # FP64 integrals, host
+    model = Model(MODEL_TRANSFORMER, dims, params, "bf16")  # or MODEL_NADE, "fp32", ...
+    x, counts, lost = sample_unique(model, n_samples, seed)
+    la, ph = amp_forward(model, x)
+    eloc, sums, n_pairs = local_energy(ham, model, x, counts, la, ph)
+    g_la, g_ph = vmc_weights(eloc, counts, sums)
+    grad = amp_backward(model, x, g_la, g_ph)
+    adam_update(model.params_ptr(), grad, m, v, lr=1e-3, t=step)
+    model.sync()
+
+``AmpFn`` puts the same forward and hand-written backward behind
+torch.autograd; ``Batch`` runs many molecules through one captured step.
 """
 import ctypes as C
 import os
