@@ -182,6 +182,8 @@ def sector_sample(n, na, nb, count, seed):
 
 
 @pytest.mark.parametrize("n,na,nb,count", [
+    (1, 1, 0, None),          # two qubits: qubit 0 has no input, qubit 1 one bit
+    (2, 1, 1, None),
     (6, 2, 2, None),          # the whole sector (225 configurations, a ragged last wave)
     (15, 7, 7, 3001),         # 30 qubits, W1 over two k-steps, many blocks and a ragged tail
     (7, 3, 2, 77),
