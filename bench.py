@@ -83,7 +83,7 @@ FUSED_TRAFFIC = {"source_sha256_prefix": "0de792b0d2361359", "bytes_per_launch":
 
 # The same for the per-qubit ansatz's fused kernel on workload "nade" (mean of a
 # step's two launches, the samples and the distinct x').
-NADE_TRAFFIC = {"source_sha256_prefix": "526a7c9d53e8e838", "bytes_per_launch": 84.03e6,
+NADE_TRAFFIC = {"source_sha256_prefix": "8824cc1e65180fb8", "bytes_per_launch": 84.03e6,
                 "profile": "profiles/nade_fused_kernel_traffic.md"}
 
 

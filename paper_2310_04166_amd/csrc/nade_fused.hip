@@ -163,9 +163,12 @@ __device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane
     }
   }
   W += 4 * ks * 64;
-  // layer 2 one output block at a time, leaky ReLU applied at once (its
-  // outputs as hi (g) + lo (gl))
-  bf16x8 g[8], gl[8];
+  // layer 2 one output block at a time, leaky ReLU applied at once; its
+  // outputs (as hi + lo) enter layer 3 right away, whose input k-step 2t + u is
+  // half u of layer 2's output block t, so no layer-3 operand is kept
+  const bf16x8 *W3 = W + 32 * 64;
+  f32x16 z = {};
+  const bf16x8 zero = {};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x16 c = load16(V + kFeat + (2 * t + h) * 16);
@@ -182,16 +185,11 @@ __device__ inline f32x4 qubit_z(const NadeArgs &a, int i, uint64_t occ, int lane
         const float y = c[8 * u + e];
         v[e] = fmaxf(y, 0.01f * y);
       }
-      pack8_hilo(v, g[2 * t + u], gl[2 * t + u]);
+      bf16x8 g, gl;
+      pack8_hilo(v, g, gl);
+      const bf16x8 w3 = col < 4 ? W3[(2 * t + u) * 64] : zero;
+      z = mfma(w3, gl, mfma(w3, g, z));
     }
-  }
-  W += 32 * 64;
-  f32x16 z = {};
-  const bf16x8 zero = {};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const bf16x8 w3 = col < 4 ? W[k * 64] : zero;
-    z = mfma(w3, gl[k], mfma(w3, g[k], z));
   }
   const float *b3 = V + 2 * kFeat;
   return f32x4{z[0] + b3[0], z[1] + b3[1], z[2] + b3[2], z[3] + b3[3]};
@@ -286,8 +284,8 @@ __device__ inline void nade_body(const NadeArgs &a) {
   }
 }
 
-// three waves per SIMD (164 registers): the kernel is latency-bound and more
-// waves help, but at four the hi / lo operands spill 140 bytes per lane (40 %
+// three waves per SIMD (163 registers): the kernel is latency-bound and more
+// waves help, but at four the hi / lo operands spill (36 bytes per lane, 5 %
 // slower than three)
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 nade_fused_kernel(NadeArgs a) {
