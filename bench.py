@@ -370,8 +370,8 @@ def main():
                     help="Adam step size; small so every timed step sees the calibrated workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
+              "run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

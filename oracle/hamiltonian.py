@@ -1,6 +1,6 @@
 """Matrix elements of the molecular Hamiltonian (paper: "System description", H_SQ).
 
-Conventions (readings of the paper, listed in the design doc):
+Conventions (readings of the paper):
 
 * Spin-orbital j = 2p + s, p the spatial orbital, s = 0 for alpha (spin up,
   the odd orbitals of Appendix A when counted from 1) and s = 1 for beta.

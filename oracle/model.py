@@ -2,8 +2,7 @@
 "Pruning strategies" for Mask-Unphysical; Appendix B for the network).
 
 log psi(x) = sum_p log psi_p(x_p | x_<p) over the n orbital tokens, with
-|psi_p|^2 the conditional probability.  Readings of the paper (the design doc lists
-them all):
+|psi_p|^2 the conditional probability.  Readings of the paper:
 
 * One token per spatial orbital (4 states), not one per qubit.  A prefix of p
   tokens is the qubit prefix of length 2p, so Algorithm 1 applies unchanged.
