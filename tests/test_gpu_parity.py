@@ -368,3 +368,20 @@ def test_vmc_weights_and_adam(nqs):
     opt.step()
     nqs.adam_update(p.data_ptr(), g, mo, ve, lr=1e-2, t=1)
     assert torch.max(torch.abs(p - ref_p.detach())).item() < 1e-12
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+def test_adam_several_steps(nqs, dtype, tol):
+    """Five steps with changing gradients (the bias corrections of step t) against
+    torch.optim.Adam in its default configuration."""
+    rng = np.random.default_rng(4)
+    p = torch.tensor(rng.normal(size=1000), dtype=dtype).cuda()
+    ref_p = p.clone().requires_grad_()
+    opt = torch.optim.Adam([ref_p], lr=1e-3)
+    mo, ve = torch.zeros_like(p), torch.zeros_like(p)
+    for t in range(1, 6):
+        g = torch.tensor(rng.normal(size=1000) * 10 ** rng.uniform(-3, 1), dtype=dtype).cuda()
+        ref_p.grad = g.clone()
+        opt.step()
+        nqs.adam_update(p.data_ptr(), g, mo, ve, lr=1e-3, t=t)
+        assert torch.max(torch.abs(p - ref_p.detach())).item() < tol, t
