@@ -303,7 +303,7 @@ def run_batching(args, torch, nqs):
     del roofline["valu_slots"]
     cpu = None
     if not args.no_cpu:
-        cpu = batching_cpu_baseline(mols, params, first, args.cpu_sample)
+        cpu = batching_cpu_baseline(mols, params, first, args.cpu_sample_batching)
     out = {"metric": "connected-config E_loc evals/s over full VMC steps "
                      "(64 molecules, 12..28 spin-orbitals, one graph-captured step)",
            "value": round(total_pairs / elapsed, 1), "unit": "pairs/s", "n_gpus": 1,
@@ -359,7 +359,10 @@ def main():
     ap.add_argument("--workload", default="precision", choices=["precision", "nade", "batching"],
                     help="precision: the 30-spin-orbital transformer step (default); nade: the "
                          "same system with the paper's per-qubit ansatz; batching: 64 molecules")
-    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=8,
+                    help="samples (largest counts) whose local energies the oracle computes")
+    ap.add_argument("--cpu-sample-batching", type=int, default=100,
+                    help="batching workload: samples per sampled molecule for the oracle")
     ap.add_argument("--fp32-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
