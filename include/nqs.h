@@ -107,8 +107,11 @@ void ham_destroy(nqs_ham *ham);
 
 #define NQS_FP64 1   /* every operation in double                            */
 #define NQS_FP32 2   /* every operation in float                             */
-#define NQS_BF16 3   /* forward GEMMs bf16 x bf16 -> fp32 on MFMA; LN, softmax,
-                        residual, log-softmax in fp32; backward in fp32       */
+#define NQS_BF16 3   /* forward GEMMs bf16 x bf16 -> fp32 on MFMA (the attention
+                        probabilities and output, and the per-qubit ansatz's
+                        hidden activations, as bf16 hi + lo pairs); LN,
+                        softmax, residual, log-softmax in fp32; backward in
+                        fp32                                                  */
 
 #define NQS_MU  0    /* Mask-Unphysical on every level ("Pruning strategies") */
 #define NQS_DU  1    /* Discard-Unphysical on every level                     */
