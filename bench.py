@@ -319,6 +319,7 @@ def run_batching(args, torch, nqs):
                       "tile": st["tile"], "graph_captures": st["captures"],
                       "gpu_ms_per_step": round(gpu_ms / args.steps, 2),
                       "step_ms": [round(v, 1) for v in step_ms],
+                      "step_ms_median": round(float(np.median(step_ms)), 2),
                       "sum_energy_per_step": energies},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
