@@ -179,6 +179,44 @@ def test_batch_tile_invariance(nqs, bf16_step):
         assert torch.equal(e, out[0][0]) and torch.equal(s, out[0][1])
 
 
+def test_batch_empty_molecule_and_empty_step(nqs, bf16_step):
+    """A molecule with no samples between molecules that have some, then a step
+    with no samples at all, through the captured step: the other molecules'
+    E_loc, sums and weights are bitwise those of the full step (a sample's E_loc
+    and a molecule's sums depend only on its own samples), the empty molecule's
+    sums are zero, and the full step run again is unchanged."""
+    b, x, c, off = bf16_step["b"], bf16_step["x"], bf16_step["c"], bf16_step["off"]
+    b.set_mode(use_graph=True)
+    e_full, s_full, p_full = b.local_energy(x, c, off)
+    e_full, s_full = e_full.clone(), s_full.clone()
+    gl, gp = nqs.vmc_weights_batch(e_full, c, x, s_full)
+    n_mol = len(off) - 1
+    k, _ = b.info()
+    drop = 1
+    keep = torch.cat([torch.arange(int(off[i]), int(off[i + 1])) for i in range(n_mol)
+                      if i != drop]).to(x.device)
+    sizes = [0 if i == drop else int(off[i + 1] - off[i]) for i in range(n_mol)]
+    off2 = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x2, c2 = x[keep].contiguous(), c[keep].contiguous()
+    e2, s2, p2 = b.local_energy(x2, c2, off2)
+    assert p2 == p_full - int(off[drop + 1] - off[drop]) * int(k[drop])
+    assert torch.equal(e2, e_full[keep])
+    for i in range(n_mol):
+        if i == drop:
+            assert torch.all(s2[i] == 0)
+        else:
+            assert torch.equal(s2[i], s_full[i]), i
+    gl2, gp2 = nqs.vmc_weights_batch(e2, c2, x2, s2)
+    assert torch.equal(gl2, gl[keep]) and torch.equal(gp2, gp[keep])
+    # no samples in any molecule
+    e0, s0, p0 = b.local_energy(x[:0], c[:0], np.zeros(n_mol + 1, np.int64))
+    assert e0.numel() == 0 and p0 == 0 and bool(torch.all(s0 == 0))
+    gl0, gp0 = nqs.vmc_weights_batch(e0, c[:0], x[:0], s0)
+    assert gl0.numel() == 0 and gp0.numel() == 0
+    e3, s3, _ = b.local_energy(x, c, off)
+    assert torch.equal(e3, e_full) and torch.equal(s3, s_full)
+
+
 def test_batch_bf16_energy_vs_oracle(nqs, bf16_step):
     """Mixed precision against the FP64 oracle on the same samples: per-sample
     E_loc within the bf16 bound of the single-molecule path and the molecules'
