@@ -41,6 +41,10 @@ def sector_sample(n, na, nb, count, seed):
     (10, 5, 5, 64, 2, 0.05, 3001),      # many groups of 32 and a ragged tail
     (15, 7, 7, 128, 4, 0.05, 1000),
     (7, 3, 2, 64, 1, 0.1, 77),
+    (16, 8, 8, 64, 8, 0.05, 300),       # the longest sequence (no padded row) and the most layers
+    (16, 8, 7, 128, 2, 0.05, 300),
+    (1, 1, 0, 64, 1, 0.1, 4),           # one token: a single physical configuration
+    (1, 1, 1, 64, 1, 0.1, 4),
 ])
 def test_fused_forward_vs_oracle(nqs, n, na, nb, d, L, std, count):
     log(f"fused forward n={n} d={d} L={L}")
