@@ -45,13 +45,19 @@ def sector_sample(n, na, nb, count, seed):
 
 # ------------------------------------------------------------------ bit work
 
-@pytest.mark.parametrize("n,na,nb,count", [(6, 2, 2, 225), (10, 5, 5, 37), (15, 7, 7, 5), (8, 3, 4, 61)])
+@pytest.mark.parametrize("n,na,nb,count", [(6, 2, 2, 225), (10, 5, 5, 37), (15, 7, 7, 5), (8, 3, 4, 61),
+                                           (32, 2, 2, 4)])
 def test_connected_pairs_bit_exact(nqs, n, na, nb, count):
+    """Connected sets, order and matrix elements against the oracle's
+    Slater-Condon rows; n = 32 fills the 64-bit word (the last case occupies
+    spin-orbitals 62 and 63)."""
     log(f"connected_pairs n={n} ({na},{nb}) count={count}")
     h, eri = make_integrals(n, 2 * n, 100 + n)
     H = nqs.ham_compile(h, eri, na, nb)
     sec = Sector(n, na, nb)
     xs = sec.enumerate() if count == 225 else [hf_config(n, na, nb)] + sector_sample(n, na, nb, count - 1, n)
+    if n == 32:
+        xs.append((1 << 0) | (1 << 62) | (1 << 11) | (1 << 63))
     off, xp, hv, hd = nqs.connected_pairs(H, dev(xs))
     off, xp, hv, hd = (t.cpu().numpy() for t in (off, xp, hv, hd))
     xp = xp.view(np.uint64)
