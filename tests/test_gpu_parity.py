@@ -355,6 +355,42 @@ def test_backward_transformer(nqs, precision, tol):
     assert np.max(np.abs(g - g_ref)) < tol * np.max(np.abs(g_ref))
 
 
+def test_transformer_32_tokens_fp64(nqs):
+    """32 tokens (64 spin-orbitals, the whole configuration word) on the FP64
+    layer path, whose attention then takes its general kernel: the sampler's
+    unique configurations and counts replayed bit-exactly, amplitudes and the
+    VMC gradient (synthetic complex local energies) against the oracle.  A
+    negative occupation bias pushes the electrons towards the last orbitals, so
+    most samples use bits 60..63."""
+    n, na, nb, d, L, H, PH = 32, 2, 2, 32, 1, 4, 32
+    sec = Sector(n, na, nb)
+    params = make_transformer_params(n, na, nb, d, L, phase_hidden=PH, seed=48, std=0.3,
+                                     occ_bias=-4.0)
+    spec = transformer_param_spec(n, d, L, 4 * d, PH)
+    ref = TransformerModel(params, sec, H)
+    m = gpu_model(nqs, nqs.MODEL_TRANSFORMER, [n, na, nb, d, L, H, 4 * d, PH], params, spec, "fp64")
+    cfg_o, cnt_o, lost_o = sample_tree(ref, 20_000, 9)
+    c, k, lost = nqs.sample_unique(m, 20_000, 9)
+    got = [int(v) for v in c.cpu().numpy().view(np.uint64)]
+    assert lost == 0 == lost_o
+    assert got == cfg_o and k.cpu().tolist() == cnt_o
+    assert sum(1 for v in got if v >> 60) > len(got) // 2
+    la, ph = nqs.amp_forward(m, c)
+    rla, rph = (v.detach().numpy() for v in ref.amplitudes(cfg_o))
+    assert np.max(np.abs(la.cpu().numpy() - rla)) < 1e-10
+    assert np.max(np.abs(ph.cpu().numpy() - rph)) < 1e-10
+    rng = np.random.default_rng(2)
+    eloc = rng.normal(size=len(got)) + 1j * rng.normal(size=len(got))
+    counts = np.asarray(cnt_o)
+    g_ref = gradient(TransformerModel(params, sec, H, requires_grad=True), cfg_o, counts, eloc, spec)
+    gl, gp = surrogate_weights(counts, eloc)
+    g = nqs.amp_backward(m, c, torch.as_tensor(gl).cuda(), torch.as_tensor(gp).cuda())
+    g = g.double().cpu().numpy()
+    err = np.max(np.abs(g - g_ref))
+    log(f"32 tokens: {len(got)} unique, gradient err {err:.2e} of {np.max(np.abs(g_ref)):.2e}")
+    assert err < 1e-10 * np.max(np.abs(g_ref))
+
+
 def test_vmc_weights_and_adam(nqs):
     rng = np.random.default_rng(3)
     eloc = rng.normal(size=50) + 1j * rng.normal(size=50)
