@@ -127,15 +127,18 @@ def test_precision_workload_full_step_sampled_parity(nqs):
         assert err < 5e-3 * max(1.0, abs(want))
 
 
-@pytest.mark.parametrize("strategy,d", [("MU", 0), ("MUd", 1)])
-def test_fused_sampler_matches_its_forward(nqs, strategy, d):
+@pytest.mark.parametrize("n,na,nb,strategy,d", [(6, 2, 2, "MU", 0), (6, 2, 2, "MUd", 1),
+                                                (16, 1, 1, "MU", 0)])
+def test_fused_sampler_matches_its_forward(nqs, n, na, nb, strategy, d):
     """The bf16 sampler's conditionals come from the fused kernel's conditional
     mode; its samples follow exp(2 log|psi|) of the fused forward (chi-square
-    over the 225-determinant sector, 1e6 samples)."""
+    over the whole sector, 1e6 samples: 225 determinants at 12 spin-orbitals,
+    256 at 32, where all 16 positions of the kernel are tokens)."""
     from scipy.stats import chi2
-    n, na, nb, dm = 6, 2, 2, 64
-    params = make_transformer_params(n, na, nb, dm, 1, seed=12, std=0.05, hf_bias=0.5,
-                                     round_to="bf16", bias_std=0.02)
+    dm = 64
+    hf, occ = (0.5, 0.0) if n == 6 else (0.0, -1.0)
+    params = make_transformer_params(n, na, nb, dm, 1, seed=12, std=0.05, hf_bias=hf,
+                                     occ_bias=occ, round_to="bf16", bias_std=0.02)
     m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, dm, 1, 4, 4 * dm, 256],
                   flatten_params(params, transformer_param_spec(n, dm, 1, 4 * dm, 256)), "bf16",
                   strategy, d)
