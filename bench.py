@@ -73,6 +73,10 @@ def nade_work(n_qubits, hidden):
                         + NADE_SLOTS["normaliser"])
     return flop, slots
 
+# The precision check at trained weights: this many VMC steps at this Adam step
+# size on a copy of the model before comparing with the oracle.
+TRAIN_STEPS, TRAIN_LR = 5, 1e-3
+
 # HBM bytes per launch of the fused kernel on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid only for the kernel source they were
@@ -100,18 +104,47 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def param_spec(cfg):
+    from synth import nade_param_spec, transformer_param_spec
+    if cfg["model"] == "nade":
+        return nade_param_spec(cfg["n"], cfg["hidden"])
+    return transformer_param_spec(cfg["n"], cfg["d"], cfg["n_layers"], 4 * cfg["d"], 256)
+
+
 def setup(workload_name, precision):
     from paper_2310_04166_amd import nqs
-    from synth import flatten_params, nade_param_spec, transformer_param_spec, workload
+    from synth import flatten_params, workload
     cfg, h, eri, params = workload(workload_name)
-    if cfg["model"] == "nade":
-        spec = nade_param_spec(cfg["n"], cfg["hidden"])
-    else:
-        spec = transformer_param_spec(cfg["n"], cfg["d"], cfg["n_layers"], 4 * cfg["d"], 256)
     ham = nqs.ham_compile(h, eri, cfg["n_alpha"], cfg["n_beta"])
-    model = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg), flatten_params(params, spec),
-                      precision)
+    model = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg),
+                      flatten_params(params, param_spec(cfg)), precision)
     return cfg, ham, model, params
+
+
+def trained_check(nqs, torch, args, cfg):
+    """A separate copy of the model after TRAIN_STEPS full VMC steps at Adam lr
+    TRAIN_LR, so that the fp32 master weights have left the bf16 grid; the
+    local energies of its cpu_sample highest-count samples on the bf16 and the
+    fp32 GPU paths.  Returns (configurations, counts, bf16 E_loc, fp32 E_loc,
+    the trained parameters as a dict, unique samples per training step)."""
+    from synth import unflatten_params
+    _, ham, m, _ = setup(args.workload, "bf16")
+    dev = torch.device("cuda:0")
+    st = {"grad": torch.empty(m.n_params, dtype=torch.float32, device=dev),
+          "m": torch.zeros(m.n_params, dtype=torch.float32, device=dev),
+          "v": torch.zeros(m.n_params, dtype=torch.float32, device=dev), "lr": TRAIN_LR}
+    unique = []
+    for t in range(1, TRAIN_STEPS + 1):
+        unique.append(vmc_step(nqs, ham, m, cfg, 100 + t, st, t)[0].numel())
+    x, c, _ = nqs.sample_unique(m, cfg["n_samples"], 11)
+    top = torch.argsort(c, descending=True)[:args.cpu_sample]
+    xs, cs = x[top].contiguous(), c[top].contiguous()
+    e16, _, _ = nqs.local_energy(ham, m, xs, cs)
+    params = m.get_params()
+    m32 = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg), params, "fp32")
+    e32, _, _ = nqs.local_energy(ham, m32, xs, cs)
+    return ([int(v) for v in xs.cpu().numpy().view(np.uint64)], cs.cpu().numpy().astype(np.float64),
+            e16.cpu().numpy(), e32.cpu().numpy(), unflatten_params(params, param_spec(cfg)), unique)
 
 
 def vmc_step(nqs, ham, model, cfg, seed, state, t, events=None):
@@ -184,30 +217,56 @@ def cpu_baseline(cfg, params, x_sample, where):
             pairs += len(xs) - 1
             elocs.append(complex(e))
     dt = time.perf_counter() - t0
+    cpu_model, nproc = cpu_info()
     return {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model, "nproc": nproc, "kind": "oracle",
             "sample": f"{len(x_sample)} unique configurations ({where}, largest counts) with all "
                       f"their {pairs} connected x' (FP64 torch CPU forward + Slater-Condon "
                       f"matrix elements), {dt:.1f} s"}, np.array(elocs)
 
 
-def tf_roofline(flop, slots, k_ms):
-    """Both ceilings of the transformer kernel: MFMA (bf16 dense peak) and VALU
-    issue (VALU_PEAK_TOPS); the binding one (the larger fraction of its peak
-    at the measured time, i.e. the lower ceiling) is reported as the bound."""
+def tf_roofline(flop, slots, k_ms, executed_flop=None):
+    """Roofline of the transformer kernel against the bf16 dense MFMA peak (the
+    amplitude network is a dense contraction): achieved = algorithmic FLOP /
+    kernel time.  Beside it, the MFMA rate counting the executed products (the
+    hi/lo operand pairs, padded rows and causal halves included) and the
+    model-based VALU-issue fraction (algorithmic elementwise slots at
+    VALU_PEAK_TOPS)."""
     sec = k_ms * 1e-3 if k_ms > 0 else float("inf")
     mfma = flop / sec / 1e12
-    valu = slots / sec / 1e12
-    out = {"mfma_achieved": round(mfma, 2), "mfma_peak": BF16_PEAK_TFLOPS,
-           "mfma_frac": round(mfma / BF16_PEAK_TFLOPS, 4), "valu_slots": slots}
-    if valu / VALU_PEAK_TOPS >= mfma / BF16_PEAK_TFLOPS:
-        out.update({"bound": "alu", "achieved": round(valu, 3), "peak": VALU_PEAK_TOPS,
-                    "unit": "T VALU lane-op/s", "frac": round(valu / VALU_PEAK_TOPS, 4)})
-    else:
-        out.update({"bound": "mfma", "achieved": round(mfma, 2), "peak": BF16_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(mfma / BF16_PEAK_TFLOPS, 4)})
-    return {k: out[k] for k in ("bound", "achieved", "peak", "unit", "frac", "mfma_achieved",
-                                "mfma_peak", "mfma_frac", "valu_slots")}
+    out = {"bound": "mfma", "achieved": round(mfma, 2), "peak": BF16_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(mfma / BF16_PEAK_TFLOPS, 4),
+           "valu_frac_model": round(slots / sec / 1e12 / VALU_PEAK_TOPS, 4)}
+    if executed_flop is not None:
+        out["executed_mfma_frac"] = round(executed_flop / sec / 1e12 / BF16_PEAK_TFLOPS, 4)
+    return out
+
+
+def executed_flop_per_config(n_layers, d, ph, pad_seq=16):
+    """MFMA FLOP the fused kernel issues per configuration: per 32-row tile
+    (two configurations of 16 padded positions) and layer, with every weight
+    product taken on the hi and lo weight sets and the attention probabilities
+    and output as hi + lo pairs, in 32x32x16 MFMAs of 32768 FLOP; the phase MLP's
+    256 x 256 layer as hi + lo per 32 configurations."""
+    nb, ks, fb = d // 32, d // 16, 4 * d // 32
+    per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks          # QKV hi+lo, S, PV, O-proj
+    per_layer = nb * per_head_pair + 2 * 2 * fb * ks            # + FFN W1, W2 hi+lo
+    tile = n_layers * per_layer * 32768
+    phase = 2 * (ph // 32) * (ph // 16) * 32768 / 32
+    return tile / 2 + phase
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
 
 def flop_per_config(n, d, n_layers, ffn, ph):
@@ -253,6 +312,7 @@ def run_batching(args, torch, nqs):
     torch.cuda.synchronize()
     nqs.timing_read()
     total_pairs, total_unique, flops, slots, step_ms, energies = 0, 0, 0, 0, [], []
+    executed = 0
     first = None
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -278,6 +338,8 @@ def run_batching(args, torch, nqs):
         slots += sum(int(st["distinct_per_mol"][i]) *
                      tf_valu_slots(m["n"], C["d"], C["n_layers"], C["n_heads"], C["ffn"],
                                    C["phase_hidden"]) for i, m in enumerate(mols))
+        executed += st["distinct"] * executed_flop_per_config(C["n_layers"], C["d"],
+                                                              C["phase_hidden"])
         s = sums.cpu().numpy()
         energies.append(float(np.sum(s[:, 1] / s[:, 0])))
         total_pairs += npairs
@@ -293,14 +355,13 @@ def run_batching(args, torch, nqs):
     k_ms, k_launches, k_cfgs = nqs.timing_read()
     nqs.timing_enable(False)
     st = batch.stats()
-    roofline = tf_roofline(flops, slots, k_ms)
+    roofline = tf_roofline(flops, slots, k_ms, executed)
     roofline.update({"traffic": None,
                      "kernel": "fused_kernel<64> on the distinct x' (inside the captured step)",
                      "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
                      "launches": k_launches, "configs": k_cfgs, "algorithmic_flop": flops,
-                     "algorithmic_valu_slots": slots,
+                     "algorithmic_valu_slots": slots, "executed_flop": executed,
                      "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)})
-    del roofline["valu_slots"]
     cpu = None
     if not args.no_cpu:
         cpu = batching_cpu_baseline(mols, params, first, args.cpu_sample_batching)
@@ -345,8 +406,9 @@ def batching_cpu_baseline(mols, params, first, per_mol):
             pairs += len(xp) - 1
             picked.append(i)
     dt = time.perf_counter() - t0
+    cpu_model, nproc = cpu_info()
     return {"value": round(pairs / dt, 1), "unit": "pairs/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model, "nproc": nproc, "kind": "oracle",
             "sample": f"{len(picked)} samples (the {per_mol} most frequent of molecules "
                       f"{sorted(set(picked))}) with all their {pairs} connected x' (FP64 torch "
                       f"CPU forward + Slater-Condon matrix elements), {dt:.1f} s"}
@@ -391,6 +453,7 @@ def main():
         precision_check(nqs, torch, args, cfg, ham, model)
     if precision:
         log(f"precision: {precision}")
+    trained = None if (args.no_fp32 or args.no_cpu) else trained_check(nqs, torch, args, cfg)
 
     state = {"grad": torch.empty(model.n_params, dtype=torch.float32, device=dev),
              "m": torch.zeros(model.n_params, dtype=torch.float32, device=dev),
@@ -458,30 +521,44 @@ def main():
                     "mfma_tflops": round(k_cfgs * flop / (k_ms * 1e-3) / 1e12, 2) if k_ms else 0,
                     "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
     else:
-        roofline = tf_roofline(k_cfgs * FLOP_PER_CONFIG,
-                               k_cfgs * tf_valu_slots(cfg["n"], cfg["d"], cfg["n_layers"],
-                                                      cfg["n_heads"], 4 * cfg["d"], 256), k_ms)
+        slots_cfg = tf_valu_slots(cfg["n"], cfg["d"], cfg["n_layers"], cfg["n_heads"],
+                                  4 * cfg["d"], 256)
+        exe_cfg = executed_flop_per_config(cfg["n_layers"], cfg["d"], 256)
+        roofline = tf_roofline(k_cfgs * FLOP_PER_CONFIG, k_cfgs * slots_cfg, k_ms,
+                               k_cfgs * exe_cfg)
         roofline.update({"traffic": fused_traffic() if args.workload == "precision" else None,
                          "traffic_unit": "bytes per launch",
                          "kernel": "fused_kernel<128> (bf16 amplitude network)",
                          "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
                          "launches": k_launches, "configs": k_cfgs,
                          "flop_per_config": FLOP_PER_CONFIG,
-                         "valu_slots_per_config": k_cfgs and roofline["valu_slots"] // k_cfgs,
+                         "executed_flop_per_config": int(exe_cfg),
+                         "valu_slots_per_config": slots_cfg,
                          "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)})
-        del roofline["valu_slots"]
 
     cpu = None
     if not args.no_cpu and precision:
         # the oracle at the initial parameters on the precision check's
         # highest-count samples: its energy there against both GPU paths
         xs_cpu, w, e16, e32 = top_samples
-        cpu, e_or = cpu_baseline(cfg, params, xs_cpu, "the precision check's samples")
-        E = lambda e: float(np.real(np.sum(w * e) / np.sum(w)))
+        _, e_or = cpu_baseline(cfg, params, xs_cpu, "the precision check's samples")
+        E = lambda e, w=w: float(np.real(np.sum(w * e) / np.sum(w)))
         precision.update({"oracle_samples": len(xs_cpu), "oracle_counts": int(w.sum()),
                           "E_oracle_top": E(e_or), "E_bf16_top": E(e16), "E_fp32_top": E(e32),
                           "abs_diff_bf16_oracle_top_ha": abs(E(e16) - E(e_or)),
                           "abs_diff_fp32_oracle_top_ha": abs(E(e32) - E(e_or))})
+        # and after TRAIN_STEPS steps at lr TRAIN_LR (master weights off the bf16
+        # grid), where the CPU baseline is timed
+        xs_t, w_t, e16_t, e32_t, p_t, unique_t = trained
+        cpu, e_or_t = cpu_baseline(cfg, p_t, xs_t, "the trained model's samples")
+        Et = lambda e: float(np.real(np.sum(w_t * e) / np.sum(w_t)))
+        precision["trained"] = {
+            "steps": TRAIN_STEPS, "lr": TRAIN_LR, "unique_per_step": unique_t,
+            "oracle_samples": len(xs_t), "oracle_counts": int(w_t.sum()),
+            "E_oracle_top": Et(e_or_t), "E_bf16_top": Et(e16_t), "E_fp32_top": Et(e32_t),
+            "abs_diff_bf16_oracle_top_ha": abs(Et(e16_t) - Et(e_or_t)),
+            "abs_diff_fp32_oracle_top_ha": abs(Et(e32_t) - Et(e_or_t)),
+            "max_abs_eloc_diff_bf16_oracle_ha": float(np.max(np.abs(e16_t - e_or_t)))}
     elif not args.no_cpu:
         x0, c0 = first
         top = torch.argsort(c0, descending=True)[:args.cpu_sample]

@@ -26,6 +26,17 @@
 // highest-count samples (1.6e-4 Ha against the FP64 oracle on the 30-qubit
 // system; 1.7e-6 Ha with the pairs, for 7 % more kernel time).
 //
+// Every weight matrix is packed as two bf16 fragment sets, hi = bf16(W) and
+// lo = bf16(W - hi), and every weight product takes both (W x = hi x + lo x),
+// so the weights carry about 16 significant bits.  Optimiser steps move the
+// fp32 master weights off the bf16 grid; rounding them to bf16 alone changes
+// the network itself, the same way for every configuration, and moved the
+// energy of the 30-qubit system's dominant samples by ~1e-4 Ha (local energies
+// of single samples by up to 2e-3 Ha) after steps of the size of five Adam
+// steps at 1e-3.  The lo set is a second step of the same kind in the weight
+// stream (NP sub-steps per step), so the LDS ring and the registers are
+// unchanged; only the MFMA count and the stream length grow.
+//
 // Per 32 rows and layer: Q, K (2 x 8 x 8), V (8 x 4), S (8), O (2 x 16),
 // out-projection (2 x 32), FFN (128 + 128) MFMAs.  After 16 passes (32
 // configurations) the phase MLP of those 32 configurations runs as one
@@ -56,6 +67,7 @@ std::vector<TimingRecord> g_records;
 constexpr int kMaxLayers = 8;
 constexpr int kSeq = 16;          // padded sequence length
 constexpr int kPairs = 16;        // passes per group of 32 configurations
+constexpr int NP = 2;             // weight fragment sets per matrix (hi, lo)
 
 __device__ __host__ inline int perm_feature(int b, int h, int j) {
   return 32 * b + (j / 4) * 8 + h * 4 + (j % 4);
@@ -68,7 +80,7 @@ struct FusedArgs {
       w2[kMaxLayers];               // fragment offsets (units of bf16x8)
   int64_t ln1g[kMaxLayers], ln1b[kMaxLayers], bq[kMaxLayers], bk[kMaxLayers], bv[kMaxLayers],
       bo[kMaxLayers], ln2g[kMaxLayers], ln2b[kMaxLayers], b1[kMaxLayers], b2[kMaxLayers];
-  int64_t p2;                       // phase W2 fragments
+  int64_t p2, p2lo;                 // phase W2 fragments (hi, lo)
   int64_t lnfg, lnfb, whead, bhead, lbias, tok, pos, pb1, pb2, pw3, pb3, pw1;  // vec offsets
   Sectors sec;                      // molecule(s) of the configurations
   const uint64_t *x;
@@ -215,7 +227,9 @@ struct Shape {
   static constexpr int STEPS = 4 * NB + 2 * FB;
   static constexpr int64_t OQ = 0, OK = int64_t(NB) * KS * 64, OV = 2 * OK, OO = 3 * OK,
                            OW1 = 4 * OK, OW2 = OW1 + int64_t(FB) * KS * 64,
-                           FRAG_L = OW2 + int64_t(NB) * FKS * 64;
+                           FRAG_L = OW2 + int64_t(NB) * FKS * 64,
+                           LAYER = NP * FRAG_L;   // hi set, then lo set (FRAG_L further)
+  static constexpr int USTEPS = NP * STEPS;       // sub-steps of the weight stream per layer
   static constexpr int64_t VLN1G = 0, VLN1B = D, VBQ = 2 * D, VBK = 3 * D, VBV = 4 * D,
                            VBO = 5 * D, VLN2G = 6 * D, VLN2B = 7 * D, VB1 = 8 * D,
                            VB2 = 8 * D + F, VEC_L = 9 * D + F;
@@ -244,11 +258,14 @@ __device__ inline StageOff stage_offsets(int lane, int wv) {
   return {{l + uint32_t(wv) * 1024u, l + uint32_t((wv / 2) * S::KS + wv % 2) * 1024u,
            l + uint32_t((wv / 2) * S::FKS + wv % 2) * 1024u}};
 }
+// Sub-step u of a layer's stream is step u / NP of the fragment set u % NP.
 template <int D>
 __device__ inline void stage_load(bf16x8 (&st)[Shape<D>::KS / 4], __amdgpu_buffer_rsrc_t W,
-                                  const StageOff &vo, int s) {
+                                  const StageOff &vo, int u) {
   using S = Shape<D>;
   constexpr int KS = S::KS;
+  const int s = u / NP;
+  const int64_t set_off = int64_t(u % NP) * S::FRAG_L;
 #pragma unroll
   for (int j = 0; j < KS / 4; ++j) {
     int kind;
@@ -266,7 +283,7 @@ __device__ inline void stage_load(bf16x8 (&st)[Shape<D>::KS / 4], __amdgpu_buffe
                : S::OW2 + (int64_t(2 * fb) + int64_t(2 * j) * S::FKS) * 64;
     }
     st[j] = __builtin_bit_cast(
-        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, vo.v[kind], uint32_t(off * 16), 0));
+        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, vo.v[kind], uint32_t((off + set_off) * 16), 0));
   }
 }
 template <int D>
@@ -323,28 +340,29 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) madd[i] = ((i / 4) * 8 + h * 4 + (i % 4)) <= t ? 0.f : -INFINITY;
 
-  constexpr uint32_t kFragBytes = uint32_t(S::FRAG_L * 16);
+  constexpr uint32_t kFragBytes = uint32_t(S::LAYER * 16);
   auto wres = [&](int l) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16x8 *>(a.pk + int64_t(l) * S::FRAG_L),
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16x8 *>(a.pk + int64_t(l) * S::LAYER),
                                              0, int(kFragBytes), 0x00020000);
   };
   const StageOff vo = stage_offsets<D>(lane, wv);
   constexpr int HS = KS / 2;
+  constexpr int US = S::USTEPS;
   bf16x8 fr[2][HS];
   bf16x8 staged[KS / 4];
-  int cur = 0;                       // ring slot of the current step
-  // prologue: step 0 of layer 0 into slot 0, step 1 in flight
+  int cur = 0;                       // ring slot of the current sub-step
+  // prologue: sub-step 0 of layer 0 into slot 0, sub-step 1 in flight
   stage_load<D>(staged, wres(0), vo, 0);
   stage_store<D>(ring, staged, wv, lane);
   stage_load<D>(staged, wres(0), vo, 1);
   __syncthreads();
   fetch_half<D>(fr[0], ring, 0, lane);
-  // end of step s: publish step s + 1, start loading step s + 2 (layer Wsrc,
-  // index s_load), make step s + 1 current
-  auto advance = [&](__amdgpu_buffer_rsrc_t Wsrc, int s_load) {
+  // end of sub-step u: publish sub-step u + 1, start loading sub-step u + 2
+  // (layer Wsrc, index u_load), make sub-step u + 1 current
+  auto advance = [&](__amdgpu_buffer_rsrc_t Wsrc, int u_load) {
     const int nxt = cur == 2 ? 0 : cur + 1;
     stage_store<D>(ring + nxt * RS, staged, wv, lane);
-    stage_load<D>(staged, Wsrc, vo, s_load);
+    stage_load<D>(staged, Wsrc, vo, u_load);
     __syncthreads();
     cur = nxt;
   };
@@ -373,48 +391,66 @@ fused_kernel(FusedArgs a) {
 
     for (int l = 0; l < a.L; ++l) {
       const __amdgpu_buffer_rsrc_t W = wres(l), Wn = wres(l + 1 < a.L ? l + 1 : 0);
+      // start loading sub-step u_load of this layer, or of the next one
+      auto adv = [&](int u_load) {
+        if (u_load < US)
+          advance(W, u_load);
+        else
+          advance(Wn, u_load - US);
+      };
       // permuted vectors of the layer (LDS): lane-half h reads 16 floats at (2q+h)*16
       const float *lv = svec + l * int(S::VEC_L);
       const float *V16 = lv + h * 16;
       bf16x8 X[KS];
-      // The weight stream advances in half steps of HS fragments through the
-      // two buffers fr[0] / fr[1]: while one half is multiplied the next half
-      // is read from the LDS ring.  On entry fr[0] holds half 0 of step 0 of
-      // this layer and the ring's current slot holds step 0.
+      // The weight stream advances in half sub-steps of HS fragments through
+      // the two buffers fr[0] / fr[1]: while one half is multiplied the next
+      // half is read from the LDS ring.  On entry fr[0] holds half 0 of
+      // sub-step 0 of this layer and the ring's current slot holds it.
+      // Sub-step NP s + p of step s multiplies the fragment set p (hi, lo) of
+      // that step's weights.
       // ---- attention block
       layer_norm<NB>(res, V16, int(S::VLN1G), int(S::VLN1B), X);
 #pragma unroll
       for (int q = 0; q < NB; ++q) res[q] += lds16(V16 + S::VBO + q * 32);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O); halves alternate fr[0], fr[1]
+        // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O)
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
-        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
-        advance(W, 4 * b + 2);
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
+          for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
+          adv(NP * (4 * b) + pt + 2);
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
+        }
         f32x16 Kc = lds16(V16 + S::VBK + b * 32);
-        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
-        advance(W, 4 * b + 3);
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Kc = mfma(fr[1][i], X[HS + i], Kc);
+          for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
+          adv(NP * (4 * b + 1) + pt + 2);
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i) Kc = mfma(fr[1][i], X[HS + i], Kc);
+        }
         f32x16 Vc;
         const float bvv = lv[S::VBV + 32 * b + r];
 #pragma unroll
         for (int j = 0; j < 16; ++j) Vc[j] = bvv;
-        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Vc = mfma(X[i], fr[0][i], Vc);
-        advance(W, 4 * b + 4);
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
+          for (int i = 0; i < HS; ++i) Vc = mfma(X[i], fr[0][i], Vc);
+          adv(NP * (4 * b + 2) + pt + 2);
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
+        }
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
         f32x16 O;
@@ -462,16 +498,24 @@ fused_kernel(FusedArgs a) {
         }
         const bf16x8 O0 = to_bf16(O, 0), O1 = to_bf16(O, 1);
         const bf16x8 L0 = lo_bf16(O, 0, O0), L1 = lo_bf16(O, 1, O1);
-        // output projection of O = hi + lo: fragment i = 2q + e (q = output block)
+        // output projection of O = hi + lo: fragment i = 2q + e (q = output
+        // block); the weights' lo set multiplies O's hi part only
 #pragma unroll
-        for (int i = 0; i < HS; ++i)
-          res[i / 2] = mfma(fr[0][i], (i % 2) ? L1 : L0, mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]));
-        advance(W, 4 * b + 5);   // next Q, or the first FFN step
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          if (pt > 0) fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i)
-          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? L1 : L0,
-                                   mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]));
+          for (int i = 0; i < HS; ++i) {
+            f32x16 acc = mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]);
+            res[i / 2] = pt == 0 ? mfma(fr[0][i], (i % 2) ? L1 : L0, acc) : acc;
+          }
+          adv(NP * (4 * b + 3) + pt + 2);   // next Q, or the first FFN sub-step
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i) {
+            f32x16 acc = mfma(fr[1][i], (i % 2) ? O1 : O0, res[(HS + i) / 2]);
+            res[(HS + i) / 2] = pt == 0 ? mfma(fr[1][i], (i % 2) ? L1 : L0, acc) : acc;
+          }
+        }
       }
       // ---- feed-forward block: step 4NB + 2fb = W1, +1 = W2
       layer_norm<NB>(res, V16, int(S::VLN2G), int(S::VLN2B), X);
@@ -481,31 +525,32 @@ fused_kernel(FusedArgs a) {
       for (int fb = 0; fb < FB; ++fb) {
         const int s = 4 * NB + 2 * fb;
         f32x16 Hc = lds16(V16 + S::VB1 + fb * 32);
-        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
-        if (s + 2 < STEPS)
-          advance(W, s + 2);
-        else
-          advance(Wn, s + 2 - STEPS);
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
+          for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
+          adv(NP * s + pt + 2);
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
+        }
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
         for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
         const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
         // second FFN layer: fragment i = 2q + e
 #pragma unroll
-        for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
-        if (s + 3 < STEPS)
-          advance(W, s + 3);
-        else
-          advance(Wn, s + 3 - STEPS);
-        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+        for (int pt = 0; pt < NP; ++pt) {
+          if (pt > 0) fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int i = 0; i < HS; ++i)
-          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? H1 : H0, res[(HS + i) / 2]);
+          for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
+          adv(NP * (s + 1) + pt + 2);
+          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+          for (int i = 0; i < HS; ++i)
+            res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? H1 : H0, res[(HS + i) / 2]);
+        }
       }
     }
 
@@ -601,8 +646,12 @@ fused_kernel(FusedArgs a) {
     for (int b = 0; b < PB; ++b) {
       f32x16 z = lds16(svec + a.pb2 + (b * 2 + h) * 16);
       const bf16x8 *w = pk + a.p2 + int64_t(b) * PKS * 64;
+      const bf16x8 *wl = pk + a.p2lo + int64_t(b) * PKS * 64;
 #pragma unroll
-      for (int s = 0; s < PKS; ++s) z = mfma(w[s * 64], Z[s], z);
+      for (int s = 0; s < PKS; ++s) {
+        z = mfma(w[s * 64], Z[s], z);
+        if (NP > 1) z = mfma(wl[s * 64], Z[s], z);
+      }
       const f32x16 w3 = lds16(svec + a.pw3 + (b * 2 + h) * 16);
 #pragma unroll
       for (int j = 0; j < 16; ++j) ph = fmaf(gelu(z[j]), w3[j], ph);
@@ -617,7 +666,8 @@ fused_kernel(FusedArgs a) {
 
 // Fragment order: (block ob, k-step s, lane l, slot i) <- W[16 s + pi_h(i)][32 ob + l%32],
 // W row-major with leading dimension ld, starting at column col0.
-__global__ void pack_frag_kernel(const float *W, int64_t ld, int col0, int n_ob, int n_ks,
+// lo = 0 writes hi = bf16(w), lo = 1 writes bf16(w - hi) (w - hi is exact in fp32).
+__global__ void pack_frag_kernel(const float *W, int64_t ld, int col0, int n_ob, int n_ks, int lo,
                                  __bf16 *out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(n_ob) * n_ks * 64 * 8) return;
@@ -625,7 +675,9 @@ __global__ void pack_frag_kernel(const float *W, int64_t ld, int col0, int n_ob,
   const int64_t s = (idx / 512) % n_ks, ob = idx / (512 * int64_t(n_ks));
   const int hh = l / 32;
   const int krow = int(16 * s) + (i / 4) * 8 + hh * 4 + (i % 4);
-  out[idx] = __bf16(W[int64_t(krow) * ld + col0 + 32 * ob + (l % 32)]);
+  const float w = W[int64_t(krow) * ld + col0 + 32 * ob + (l % 32)];
+  const __bf16 hi = __bf16(w);
+  out[idx] = lo ? __bf16(w - float(hi)) : hi;
 }
 
 // Permuted vector: out[(b*2+h)*16 + j] = v[perm_feature(b, h, j)], for `rows`
@@ -678,6 +730,15 @@ Layout plan(const nqs_model &m) {
     L.a.o[l] = frag(NB, KS);
     L.a.w1[l] = frag(F / 32, KS);
     L.a.w2[l] = frag(NB, F / 16);
+    // the lo sets (NP = 2) follow the layer's hi sets in the same order
+    for (int p = 1; p < NP; ++p) {
+      frag(NB, KS);
+      frag(NB, KS);
+      frag(NB, KS);
+      frag(NB, KS);
+      frag(F / 32, KS);
+      frag(NB, F / 16);
+    }
     L.a.ln1g[l] = vec(D);
     L.a.ln1b[l] = vec(D);
     L.a.bq[l] = vec(D);
@@ -690,6 +751,7 @@ Layout plan(const nqs_model &m) {
     L.a.b2[l] = vec(D);
   }
   L.a.p2 = frag(PH / 32, PH / 16);
+  L.a.p2lo = frag(PH / 32, PH / 16);
   L.a.lnfg = vec(D);
   L.a.lnfb = vec(D);
   L.a.whead = vec(4 * D);
@@ -722,7 +784,7 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   auto check = [&](auto shape) {
     using S = decltype(shape);
     for (int l = 0; l < m.L; ++l) {
-      const int64_t f = l * S::FRAG_L, v = l * S::VEC_L;
+      const int64_t f = l * S::LAYER, v = l * S::VEC_L;
       NQS_REQUIRE(L.a.q[l] == f + S::OQ && L.a.k[l] == f + S::OK && L.a.v[l] == f + S::OV &&
                       L.a.o[l] == f + S::OO && L.a.w1[l] == f + S::OW1 &&
                       L.a.w2[l] == f + S::OW2 && L.a.ln1g[l] == v + S::VLN1G &&
@@ -741,11 +803,16 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   const int D = m.d, F = m.F, NB = D / 32, KS = D / 16, PH = m.PH, n = m.n;
   auto P = [&](int idx) { return W + m.off[idx]; };
   float *vb = static_cast<float *>(m.packed_vec.reserve(size_t(L.vec_total) * 4));
-  auto pack = [&](const float *src, int64_t ld, int col0, int n_ob, int n_ks, int64_t o) {
-    hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(n_ob) * n_ks * 512), dim3(256), 0, s, src, ld,
-                       col0, n_ob, n_ks, pk + o * 8);
-    HIP_LAUNCH_OK();
+  // hi set at o, lo set (when NP = 2) lo_off fragments entries further
+  auto pack = [&](const float *src, int64_t ld, int col0, int n_ob, int n_ks, int64_t o,
+                  int64_t lo_off) {
+    for (int p = 0; p < NP; ++p) {
+      hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(n_ob) * n_ks * 512), dim3(256), 0, s, src,
+                         ld, col0, n_ob, n_ks, p, pk + (o + p * lo_off) * 8);
+      HIP_LAUNCH_OK();
+    }
   };
+  const int64_t lo_layer = m.d == 128 ? Shape<128>::FRAG_L : Shape<64>::FRAG_L;
   auto perm = [&](const float *src, int N, int rows, int64_t o) {
     hipLaunchKernelGGL(perm_vec_kernel, g1(int64_t(N) * rows), dim3(256), 0, s, src, N, rows, vb + o);
     HIP_LAUNCH_OK();
@@ -756,12 +823,12 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   };
   for (int l = 0; l < m.L; ++l) {
     const float *wqkv = P(tf_layer(l, TF_WQKV)), *bqkv = P(tf_layer(l, TF_BQKV));
-    pack(wqkv, 3 * D, 0, NB, KS, L.a.q[l]);
-    pack(wqkv, 3 * D, D, NB, KS, L.a.k[l]);
-    pack(wqkv, 3 * D, 2 * D, NB, KS, L.a.v[l]);
-    pack(P(tf_layer(l, TF_WO)), D, 0, NB, KS, L.a.o[l]);
-    pack(P(tf_layer(l, TF_W1)), F, 0, F / 32, KS, L.a.w1[l]);
-    pack(P(tf_layer(l, TF_W2)), D, 0, NB, F / 16, L.a.w2[l]);
+    pack(wqkv, 3 * D, 0, NB, KS, L.a.q[l], lo_layer);
+    pack(wqkv, 3 * D, D, NB, KS, L.a.k[l], lo_layer);
+    pack(wqkv, 3 * D, 2 * D, NB, KS, L.a.v[l], lo_layer);
+    pack(P(tf_layer(l, TF_WO)), D, 0, NB, KS, L.a.o[l], lo_layer);
+    pack(P(tf_layer(l, TF_W1)), F, 0, F / 32, KS, L.a.w1[l], lo_layer);
+    pack(P(tf_layer(l, TF_W2)), D, 0, NB, F / 16, L.a.w2[l], lo_layer);
     perm(P(tf_layer(l, TF_LN1G)), D, 1, L.a.ln1g[l]);
     perm(P(tf_layer(l, TF_LN1B)), D, 1, L.a.ln1b[l]);
     perm(bqkv, D, 1, L.a.bq[l]);
@@ -774,7 +841,7 @@ void fused_pack(nqs_model &m, hipStream_t s) {
     perm(P(tf_layer(l, TF_B2)), D, 1, L.a.b2[l]);
   }
   const int Lm = m.L;
-  pack(P(tf_tail(Lm, TF_PW2)), PH, 0, PH / 32, PH / 16, L.a.p2);
+  pack(P(tf_tail(Lm, TF_PW2)), PH, 0, PH / 32, PH / 16, L.a.p2, L.a.p2lo - L.a.p2);
   perm(P(tf_tail(Lm, TF_LNFG)), D, 1, L.a.lnfg);
   perm(P(tf_tail(Lm, TF_LNFB)), D, 1, L.a.lnfb);
   hipLaunchKernelGGL(perm_head_kernel, g1(4 * D), dim3(256), 0, s, P(tf_tail(Lm, TF_WHEAD)), D,

@@ -1,6 +1,6 @@
 """The algorithmic work counts behind bench.py's roofline (host arithmetic, no
 GPU): the constants agree with the per-configuration formulas, the formulas
-with sums written out by hand, and the roofline reports the lower ceiling."""
+with sums written out by hand, and the roofline is the MFMA one."""
 import bench
 
 
@@ -34,14 +34,23 @@ def test_nade_work_by_hand():
     assert bench.nade_work(30, 64) == (1125120, 60060)
 
 
-def test_roofline_reports_the_lower_ceiling():
-    # VALU-bound: the same time is a larger fraction of the VALU peak
-    # (fractions are reported to four decimals)
-    r = bench.tf_roofline(flop=1e14, slots=1e13, k_ms=1000.0)
-    assert r["bound"] == "alu" and abs(r["frac"] - 10.0 / bench.VALU_PEAK_TOPS) < 5e-5
-    assert abs(r["mfma_frac"] - 100.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
-    r = bench.tf_roofline(flop=1e15, slots=1e9, k_ms=1000.0)
-    assert r["bound"] == "mfma" and abs(r["frac"] - 1000.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
+def test_roofline_is_the_mfma_bound():
+    # the amplitude network is a dense contraction: frac = algorithmic FLOP / time
+    # / bf16 peak; the VALU fraction and the executed-MFMA fraction ride along
+    r = bench.tf_roofline(flop=1e14, slots=1e13, k_ms=1000.0, executed_flop=2.5e14)
+    assert r["bound"] == "mfma" and abs(r["frac"] - 100.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
+    assert abs(r["valu_frac_model"] - 10.0 / bench.VALU_PEAK_TOPS) < 5e-5
+    assert abs(r["executed_mfma_frac"] - 250.0 / bench.BF16_PEAK_TFLOPS) < 5e-5
+
+
+def test_executed_mfma_count_by_hand():
+    # per 32-row tile and layer at d 128: per head pair Q, K, V (8 k-steps each,
+    # hi + lo weights) 48, scores 2, P V (hi + lo P) 8, output projection (hi
+    # weights x O hi + lo, lo weights x O hi) 24; per hidden block of 32 (16 of
+    # them) W1 and W2 with hi + lo weights 32 -> 4 * 82 + 16 * 32 = 840 MFMAs
+    per_tile = 4 * 840 * 32768
+    phase = 2 * 8 * 16 * 32768 / 32
+    assert bench.executed_flop_per_config(4, 128, 256) == per_tile / 2 + phase
 
 
 def test_valu_peak_from_unit_counts():
