@@ -306,23 +306,24 @@ void launch_emit_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, const int
 }
 
 // Up to 8 tiles one block scans alone; beyond, three passes (tiles, the tile
-// totals with the one-block scan, offsets added back) over a per-device
-// scratch array of tile totals, which grows outside any graph capture (no
-// captured sequence of this library contains a scan).
-void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+// totals with the one-block scan, offsets added back) over tile_ws, which
+// holds 2 * tiles + 1 int64 (scan_workspace_entries).
+int64_t scan_workspace_entries(int64_t n) {
+  const int64_t tiles = ceil_div(n, 1024);
+  return tiles <= 8 ? 0 : 2 * tiles + 1;
+}
+
+void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s,
+                           int64_t *tile_ws) {
   const int64_t tiles = ceil_div(n, 1024);
   if (tiles <= 8) {
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, in, out, n);
     HIP_LAUNCH_OK();
     return;
   }
-  static DevBuf scratch[64];
-  int dev = 0;
-  HIP_OK(hipGetDevice(&dev));
-  NQS_REQUIRE(dev >= 0 && dev < 64, NQS_EHIP, "device index out of range");
   NQS_REQUIRE(tiles < (int64_t(1) << 31), NQS_EUNSUPPORTED, "scan: too many entries");
-  auto *tile_sum = static_cast<int64_t *>(scratch[dev].reserve(size_t(2 * tiles + 1) * 8));
-  int64_t *tile_off = tile_sum + tiles;
+  NQS_REQUIRE(tile_ws != nullptr, NQS_EINVAL, "scan: no workspace");
+  int64_t *tile_sum = tile_ws, *tile_off = tile_ws + tiles;
   hipLaunchKernelGGL(tile_scan_kernel, dim3(unsigned(tiles)), dim3(1024), 0, s, in, out, n,
                      tile_sum);
   HIP_LAUNCH_OK();
@@ -333,6 +334,17 @@ void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream
   // out[n] = the total, the last entry of the tile-offset scan
   hipLaunchKernelGGL(copy_one_kernel, dim3(1), dim3(64), 0, s, tile_off + tiles, out + n);
   HIP_LAUNCH_OK();
+}
+
+// The same with the workspace in a buffer of the calling handle (grown
+// outside any graph capture: no captured sequence of this library contains a
+// scan), so calls through different handles on different streams do not share
+// it.
+void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s,
+                           DevBuf &ws) {
+  const int64_t e = scan_workspace_entries(n);
+  launch_exclusive_scan(in, out, n, s, e ? static_cast<int64_t *>(ws.reserve(size_t(e) * 8))
+                                         : nullptr);
 }
 
 void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,

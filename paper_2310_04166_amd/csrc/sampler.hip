@@ -242,7 +242,7 @@ int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
                        m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, p,
                        m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);
     HIP_LAUNCH_OK();
-    launch_exclusive_scan(flag, off, B * 4, s);
+    launch_exclusive_scan(flag, off, B * 4, s, m.s_scan);
     int64_t nb = 0;
     HIP_OK(hipMemcpyAsync(&nb, off + B * 4, 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
