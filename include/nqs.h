@@ -104,6 +104,7 @@ void ham_destroy(nqs_ham *ham);
 #define NQS_MODEL_MLP         1   /* per-token NADE-like MLPs (Appendix B)      */
 #define NQS_MODEL_TRANSFORMER 2   /* decoder-only transformer + phase MLP       */
 #define NQS_MODEL_NADE        3   /* the paper's per-qubit complex-weight MLPs  */
+#define NQS_MODEL_TABLE       4   /* psi given explicitly on a basis (no network) */
 
 #define NQS_FP64 1   /* every operation in double                            */
 #define NQS_FP32 2   /* every operation in float                             */
@@ -127,6 +128,9 @@ void ham_destroy(nqs_ham *ham);
  *   MLP:         {n, n_alpha, n_beta, hidden}
  *   TRANSFORMER: {n, n_alpha, n_beta, d_model, n_layers, n_heads, ffn, phase_hidden}
  *   NADE:        {n, n_alpha, n_beta, hidden}
+ *   TABLE:       {n, n_alpha, n_beta, lo_0, hi_0, ..., lo_{M-1}, hi_{M-1}}: the
+ *                M basis configurations as (low, high) 32-bit halves, in
+ *                strictly ascending uint64 order (n_dims = 3 + 2 M)
  * params (host, n_params doubles) is the canonical parameter vector: the
  * concatenation of the tensors below, each row-major, matrices (in, out) so
  * that a layer computes y = x W + b.
@@ -156,6 +160,14 @@ void ham_destroy(nqs_ham *ham);
  *      accumulation, complex tanh / leaky ReLU / normaliser in fp32, log|psi|
  *      and phase summed in double); the sampler and amp_backward use the
  *      fp32 master parameters layer by layer.
+ *   TABLE (local-energy equation; with psi the exact ground vector E_loc = E_0
+ *      everywhere): params = log|psi| of the M basis configurations, then
+ *      their phases (2 M doubles); psi = 0 outside the basis.  FP64 only.
+ *      amp_forward looks x up by binary search; the sampler's conditional of
+ *      token p is the Born mass of the basis configurations continuing the
+ *      prefix with that token over the prefix's mass; amp_backward adds each
+ *      sample's upstream weights to its basis entry.  No sectors of several
+ *      molecules, no Z2 restriction (the basis is the support).
  * log|psi(x)| = 1/2 sum_p log softmax over allowed tokens; phase separate.
  * Errors: NQS_EINVAL (sizes, n_params mismatch), NQS_EUNSUPPORTED (n > 32,
  * d_model not a multiple of n_heads, unknown kind / precision / strategy,

@@ -122,7 +122,9 @@ extern "C" const char *nqs_last_error(void) { return g_last_error.c_str(); }
 // derived weights from the canonical parameters: fp32 / fp64 block matrices of
 // the per-qubit ansatz, then the bf16 fragments of the fused forward
 static void repack(nqs_model &m, hipStream_t s) {
-  if (m.kind == NQS_MODEL_NADE) {
+  if (m.kind == NQS_MODEL_TABLE) {
+    table_pack(m, s);
+  } else if (m.kind == NQS_MODEL_NADE) {
     nade_pack(m, s);
     if (m.precision == NQS_BF16) nade_fused_pack(m, s);
   } else if (m.precision == NQS_BF16) {
@@ -136,14 +138,20 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
   return guarded([&] {
     NQS_REQUIRE(out && dims && params, NQS_EINVAL, "amp_model_create: null argument");
     *out = nullptr;
-    NQS_REQUIRE(kind == NQS_MODEL_MLP || kind == NQS_MODEL_TRANSFORMER || kind == NQS_MODEL_NADE,
+    NQS_REQUIRE(kind == NQS_MODEL_MLP || kind == NQS_MODEL_TRANSFORMER ||
+                    kind == NQS_MODEL_NADE || kind == NQS_MODEL_TABLE,
                 NQS_EUNSUPPORTED, "amp_model_create: unknown model kind");
     NQS_REQUIRE(precision == NQS_FP64 || precision == NQS_FP32 || precision == NQS_BF16,
                 NQS_EUNSUPPORTED, "amp_model_create: unknown precision");
     NQS_REQUIRE(strategy == NQS_MU || strategy == NQS_DU || strategy == NQS_MUD, NQS_EUNSUPPORTED,
                 "amp_model_create: unknown strategy");
-    NQS_REQUIRE(n_dims == (kind == NQS_MODEL_TRANSFORMER ? 8 : 4), NQS_EINVAL,
-                "amp_model_create: wrong number of dims");
+    if (kind == NQS_MODEL_TABLE)
+      NQS_REQUIRE(n_dims >= 5 && (n_dims - 3) % 2 == 0, NQS_EINVAL,
+                  "amp_model_create: a table needs dims {n, n_alpha, n_beta} and two words "
+                  "per basis configuration");
+    else
+      NQS_REQUIRE(n_dims == (kind == NQS_MODEL_TRANSFORMER ? 8 : 4), NQS_EINVAL,
+                  "amp_model_create: wrong number of dims");
     auto m = std::make_unique<nqs_model>();
     m->kind = kind;
     m->precision = precision;
@@ -165,7 +173,17 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
       m->off.push_back(o);
       o += size;
     };
-    if (kind == NQS_MODEL_NADE) {
+    std::vector<uint64_t> basis;
+    if (kind == NQS_MODEL_TABLE) {
+      NQS_REQUIRE(precision == NQS_FP64, NQS_EUNSUPPORTED, "amp_model_create: a table is FP64");
+      const int64_t M = (n_dims - 3) / 2;
+      basis.resize(size_t(M));
+      for (int64_t j = 0; j < M; ++j)
+        basis[size_t(j)] = uint64_t(uint32_t(dims[3 + 2 * j])) |
+                           (uint64_t(uint32_t(dims[4 + 2 * j])) << 32);
+      add(M);    // log|psi|
+      add(M);    // phase
+    } else if (kind == NQS_MODEL_NADE) {
       m->hid = dims[3];
       NQS_REQUIRE(m->hid >= 1, NQS_EINVAL, "amp_model_create: hidden < 1");
       NQS_REQUIRE(precision != NQS_BF16 || nade_fused_supported(*m), NQS_EUNSUPPORTED,
@@ -217,6 +235,7 @@ extern "C" int amp_model_create(int kind, const int32_t *dims, int n_dims, const
     m->act_budget = std::min<int64_t>(std::max<int64_t>(int64_t(free_b / 8), int64_t(1) << 30),
                                       int64_t(16) << 30);
     install_sectors(*m, {{n, m->na, m->nb}}, false);
+    if (kind == NQS_MODEL_TABLE) table_install(*m, basis.data(), int64_t(basis.size()));
     if (m->fp64()) {
       HIP_OK(hipMemcpy(m->master.reserve(size_t(m->P) * 8), params, size_t(m->P) * 8,
                        hipMemcpyHostToDevice));
@@ -264,6 +283,8 @@ extern "C" int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks,
                                 const int32_t *targets) {
   return guarded([&] {
     NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_z2: null handle");
+    NQS_REQUIRE(m->kind != NQS_MODEL_TABLE, NQS_EUNSUPPORTED,
+                "amp_model_set_z2: a table's support is its basis");
     NQS_REQUIRE(!m->tagged, NQS_EUNSUPPORTED,
                 "amp_model_set_z2: the model serves several molecules");
     NQS_REQUIRE(n_gen >= 0 && n_gen <= 4, NQS_EINVAL, "amp_model_set_z2: between 0 and 4 masks");
@@ -378,7 +399,7 @@ extern "C" int connected_pairs(nqs_ham *H, const uint64_t *x, int64_t n, int64_t
     H->upload();
     int64_t *cnt = static_cast<int64_t *>(H->w_cnt.reserve(size_t(n > 0 ? n : 1) * 8));
     if (n > 0) launch_count_pairs(*H, x, n, cnt, s);
-    launch_exclusive_scan(cnt, offsets, n, s);
+    launch_exclusive_scan(cnt, offsets, n, s, H->w_scan);
     int64_t total = 0;
     HIP_OK(hipMemcpyAsync(&total, offsets + n, 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -410,7 +431,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
     int64_t *cnt = static_cast<int64_t *>(H->w_cnt.reserve(size_t(n) * 8));
     int64_t *off = static_cast<int64_t *>(H->w_off.reserve(size_t(n + 1) * 8));
     launch_count_pairs(*H, x, n, cnt, s);
-    launch_exclusive_scan(cnt, off, n, s);
+    launch_exclusive_scan(cnt, off, n, s, H->w_scan);
     std::vector<int64_t> off_h(size_t(n) + 1);
     HIP_OK(hipMemcpyAsync(off_h.data(), off, size_t(n + 1) * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));

@@ -74,8 +74,11 @@ struct nqs_model {
   nqs::DevBuf nade_frag, nade_vec;    // per-qubit ansatz, bf16: weight fragments, fp32 vectors
   std::vector<int32_t> nade_fo;       // first fragment set of each qubit in nade_frag
   bool packed_valid = false;
+  int64_t tab_M = 0;                  // TABLE: basis size
+  nqs::DevBuf tab_basis, tab_tkeys, tab_order, tab_cum;  // TABLE: see table.hip
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
+  nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
 
   bool fp64() const { return precision == NQS_FP64; }
   nqs::Sectors sectors() const {
@@ -144,5 +147,16 @@ void timing_add(float ms, int64_t configs);
 hipEvent_t timing_begin(hipStream_t s, const int64_t *count);
 void timing_end(hipEvent_t start, hipStream_t s, int64_t configs);
 bool fused_supported(const nqs_model &m);
+// explicit psi over a basis (table.hip): install the basis (host, ascending),
+// rebuild the prefix sums of |psi|^2 from the master parameters, forward,
+// conditional logits of token p for the sampler, backward into double acc[2M]
+void table_install(nqs_model &m, const uint64_t *basis, int64_t M);
+void table_pack(nqs_model &m, hipStream_t s);
+void table_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
+                   hipStream_t s);
+void table_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, double *out4,
+                       hipStream_t s);
+void table_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
+                    const double *gp, double *acc, hipStream_t s);
 
 }  // namespace nqs

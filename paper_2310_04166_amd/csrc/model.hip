@@ -1138,6 +1138,11 @@ int64_t model_chunk(const nqs_model &m, bool bwd) {
 
 void model_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
                    void *logits, hipStream_t s) {
+  if (m.kind == NQS_MODEL_TABLE) {
+    NQS_REQUIRE(!logits, NQS_EINVAL, "table model: no per-position logits");
+    table_forward(m, x, B, logabs, phase, s);
+    return;
+  }
   const int64_t ch = model_chunk(m, false);
   const int w = m.kind == NQS_MODEL_TRANSFORMER ? 4 : 8;
   for (int64_t b0 = 0; b0 < B; b0 += ch) {
@@ -1154,6 +1159,10 @@ void model_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
 
 void model_cond_logits(nqs_model &m, const uint64_t *prefix, int64_t B, int p, double *out4,
                        hipStream_t s) {
+  if (m.kind == NQS_MODEL_TABLE) {
+    table_cond_logits(m, prefix, B, p, out4, s);
+    return;
+  }
   if (m.precision == NQS_BF16 && (fused_supported(m) || nade_fused_supported(m))) {
     fused_forward(m, prefix, B, nullptr, nullptr, out4, p, s);
     return;
@@ -1213,6 +1222,11 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
                     const double *gp, void *grad, hipStream_t s) {
   double *acc = static_cast<double *>(m.grad_acc.reserve(size_t(m.P) * 8));
   zero_async(acc, size_t(m.P) * 8, s);
+  if (m.kind == NQS_MODEL_TABLE) {
+    table_backward(m, x, B, gl, gp, acc, s);
+    convert<double, double>(acc, static_cast<double *>(grad), m.P, s);
+    return;
+  }
   const int64_t ch = model_chunk(m, true);
   if (m.kind == NQS_MODEL_NADE && B > 0) {
     if (m.fp64()) nade_qb_backward<double>(m, x, B, gl, gp, ch, s);

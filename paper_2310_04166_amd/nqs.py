@@ -30,7 +30,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("NQS_LIB", os.path.join(_HERE, "libnqs.so"))
 
-MODEL_MLP, MODEL_TRANSFORMER, MODEL_NADE = 1, 2, 3
+MODEL_MLP, MODEL_TRANSFORMER, MODEL_NADE, MODEL_TABLE = 1, 2, 3, 4
 FP64, FP32, BF16 = 1, 2, 3
 MU, DU, MUD = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
@@ -245,6 +245,16 @@ class Model:
 
 def amp_model_create(kind, dims, params, precision="fp32", strategy="MU", d=0):
     return Model(kind, dims, params, precision, strategy, d)
+
+
+def table_model(n, n_alpha, n_beta, basis, logabs, phase, strategy="MU", d=0):
+    """NQS_MODEL_TABLE: psi given on an ascending basis of configurations
+    (ints); dims carry the basis as (low, high) 32-bit halves."""
+    b = np.ascontiguousarray([int(v) for v in basis], dtype=np.uint64)
+    halves = b.view(np.uint32).view(np.int32)            # little-endian: low, high
+    dims = np.concatenate([np.asarray([n, n_alpha, n_beta], np.int32), halves])
+    params = np.concatenate([np.asarray(logabs, np.float64), np.asarray(phase, np.float64)])
+    return Model(MODEL_TABLE, dims, params, "fp64", strategy, d)
 
 
 def amp_forward(model, x, logabs=None, phase=None, stream=None):
