@@ -308,6 +308,26 @@ int connected_pairs(nqs_ham *ham, const uint64_t *x, int64_t n, int64_t *offsets
                     int64_t *n_pairs, nqs_stream stream);
 
 /*
+ * connected_pairs_noalloc - connected_pairs for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, outputs and errors as
+ * connected_pairs; it calls no allocating routine.  Its scratch (the pair
+ * count of every configuration and the multi-block scan's tile totals) is a
+ * fixed device array of the library, NQS_NOALLOC_MAX_CONFIGS + 513 int64
+ * (2 MiB) on every device it runs on, held until the process ends:
+ *   - n > NQS_NOALLOC_MAX_CONFIGS: NQS_EUNSUPPORTED;
+ *   - the Hamiltonian's tables must already be on the current device (the
+ *     first call of any other entry point with it uploads them): NQS_EINVAL;
+ *   - every call on one device shares that array, so calls that overlap on a
+ *     device (other streams or host threads) race and must not be issued.
+ * Synchronises the stream (the pair total is read back).
+ */
+#define NQS_NOALLOC_MAX_CONFIGS 262144
+int connected_pairs_noalloc(const nqs_ham *ham, const uint64_t *x, int64_t n, int64_t *offsets,
+                            uint64_t *xp, double *hval, double *hdiag, int64_t capacity,
+                            int64_t *n_pairs, nqs_stream stream);
+
+/*
  * local_energy - E_loc(x) = sum_{x'} H_{x x'} psi(x') / psi(x) (paper:
  * "Variational Monte Carlo", local-energy equation) over x itself and its
  * structurally connected x' = x ^ f inside the sector.  psi(x') comes from

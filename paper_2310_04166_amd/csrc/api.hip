@@ -3,6 +3,7 @@
 #include <array>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -405,6 +406,70 @@ extern "C" int connected_pairs(nqs_ham *H, const uint64_t *x, int64_t n, int64_t
     HIP_OK(hipStreamSynchronize(s));
     *n_pairs = total;
     NQS_REQUIRE(total <= capacity, NQS_ECAPACITY, "connected_pairs: capacity too small");
+    if (n > 0) launch_emit_pairs(*H, x, n, offsets, xp, hval, nullptr, hdiag, 0, s);
+  });
+}
+
+// ---- connected_pairs_noalloc: the scratch of connected_pairs (the pair count
+// of every configuration and the multi-block scan's tile totals) in a fixed
+// device array.  Every device the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address returned by
+// hipGetSymbolAddress on that device (the array's name is a host-side stand-in).
+namespace nqs {
+namespace {
+constexpr int64_t kNoallocScanWs = 2 * (NQS_NOALLOC_MAX_CONFIGS / 1024) + 1;
+constexpr int64_t kNoallocEntries = NQS_NOALLOC_MAX_CONFIGS + kNoallocScanWs;
+static __device__ __align__(256) int64_t scratch[kNoallocEntries];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call there.
+int64_t *device_scratch() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  NQS_REQUIRE(dev >= 0 && dev < kMaxDevices, NQS_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    NQS_REQUIRE(p != nullptr, NQS_EHIP, "scratch: no device address");
+    g_scratch[dev] = static_cast<int64_t *>(p);
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+}  // namespace nqs
+
+extern "C" int connected_pairs_noalloc(const nqs_ham *H, const uint64_t *x, int64_t n,
+                                       int64_t *offsets, uint64_t *xp, double *hval,
+                                       double *hdiag, int64_t capacity, int64_t *n_pairs,
+                                       nqs_stream stream) {
+  return guarded([&] {
+    NQS_REQUIRE(H && offsets && n_pairs, NQS_EINVAL, "connected_pairs_noalloc: null argument");
+    NQS_REQUIRE(n >= 0, NQS_EINVAL, "connected_pairs_noalloc: negative n");
+    NQS_REQUIRE(n <= NQS_NOALLOC_MAX_CONFIGS, NQS_EUNSUPPORTED,
+                "connected_pairs_noalloc: more than NQS_NOALLOC_MAX_CONFIGS configurations");
+    NQS_REQUIRE(n == 0 || x, NQS_EINVAL, "connected_pairs_noalloc: null x");
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    NQS_REQUIRE(H->device == dev && H->d_flip.ptr, NQS_EINVAL,
+                "connected_pairs_noalloc: the Hamiltonian's tables are not on this device "
+                "(any other call with it uploads them)");
+    hipStream_t s = as_stream(stream);
+    int64_t *cnt = device_scratch();
+    int64_t *ws = cnt + NQS_NOALLOC_MAX_CONFIGS;
+    static_assert(kNoallocScanWs >= 2 * ((NQS_NOALLOC_MAX_CONFIGS + 1023) / 1024) + 1,
+                  "scan workspace of the largest call");
+    if (n > 0) launch_count_pairs(*H, x, n, cnt, s);
+    launch_exclusive_scan(cnt, offsets, n, s, ws);
+    int64_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, offsets + n, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *n_pairs = total;
+    NQS_REQUIRE(total <= capacity, NQS_ECAPACITY, "connected_pairs_noalloc: capacity too small");
     if (n > 0) launch_emit_pairs(*H, x, n, offsets, xp, hval, nullptr, hdiag, 0, s);
   });
 }

@@ -67,6 +67,8 @@ _SIGS = {
     "sample_unique": ([_vp, _u64, _u64, _vp, _vp, _i64, C.POINTER(_i64), C.POINTER(_u64), _vp],
                       C.c_int),
     "connected_pairs": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(_i64), _vp], C.c_int),
+    "connected_pairs_noalloc": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(_i64), _vp],
+                                C.c_int),
     "local_energy": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.POINTER(_i64), _vp],
                      C.c_int),
     "local_energy_stats": ([_vp, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
@@ -428,6 +430,21 @@ def connected_pairs(ham, x, capacity=None, stream=None):
     _check(lib().connected_pairs(ham.handle, _ptr(x), n, _ptr(off), _ptr(xp), _ptr(hv), _ptr(hd),
                                  capacity, C.byref(total), _stream(stream)))
     return off, xp[:total.value], hv[:total.value], hd[:n]
+
+
+NOALLOC_MAX_CONFIGS = 262144
+
+
+def connected_pairs_noalloc(ham, x, offsets, xp, hval, hdiag, stream=None):
+    """connected_pairs into caller-allocated tensors (offsets n+1 int64, xp /
+    hval of equal capacity, hdiag n); the library allocates nothing.  Returns
+    the number of pairs."""
+    x = _dev(x, torch.int64)
+    total = _i64()
+    _check(lib().connected_pairs_noalloc(ham.handle, _ptr(x), x.numel(), _ptr(offsets), _ptr(xp),
+                                         _ptr(hval), _ptr(hdiag), xp.numel(), C.byref(total),
+                                         _stream(stream)))
+    return total.value
 
 
 def local_energy(ham, model, x, counts=None, logabs_x=None, phase_x=None, stream=None):
