@@ -215,6 +215,30 @@ int amp_model_set_sectors(nqs_model *m, int n_mol, const int32_t *n, const int32
                           const int32_t *n_beta);
 
 /*
+ * amp_model_set_symmetries - define the model's sector by general quantum
+ * numbers (paper: "Physicality evaluation algorithm", Algorithm 1 for any
+ * number of symmetries; Appendix A): n_add (0..8) additive symmetries, where
+ * qubit q holding bit b contributes eig[s * 4n + 2 q + b] (host int32) to
+ * symmetry s and a configuration's eigenvalue is the sum over its 2n qubits
+ * (particle number: eig = b; 2 S_z: (-1)^q b; any integer combination is
+ * another instance), with target sums targets[s] (host); and n_z2 (0..4) Z2
+ * symmetries z2_masks (host; Z on those qubits, eigenvalues composed by
+ * multiplication) with target parities z2_targets (host, 0/1 meaning +1/-1;
+ * NULL = all 0).  The masked conditionals, the sampler and amp_forward then
+ * keep exactly the configurations with those sums and parities (the table of
+ * physical prefix states is built on the host by Algorithm 1; the kernels walk
+ * a configuration's tokens through it).  The Hamiltonian's connected x' of a
+ * sample are those of its own (N_alpha, N_beta) block, so local_energy applies
+ * to any such sector of a number-conserving Hamiltonian.  n_add = n_z2 = 0
+ * returns the model to its (n_alpha, n_beta) sector.
+ * Errors: NQS_EINVAL (counts, empty sector, masks beyond the qubits),
+ * NQS_EUNSUPPORTED (the model serves several molecules, more than 2^22 prefix
+ * states in a level).
+ */
+int amp_model_set_symmetries(nqs_model *m, int n_add, const int32_t *eig, const int32_t *targets,
+                             int n_z2, const uint64_t *z2_masks, const int32_t *z2_targets);
+
+/*
  * amp_model_set_z2 - restrict the model's sector by Z2 symmetries (paper:
  * "Molecular symmetries"; Algorithm 1 with the Z2 eigenvalues composed by
  * multiplication): n_gen (0..4) qubit masks (host), e.g. from
@@ -297,7 +321,9 @@ int sample_unique_batch(nqs_model *m, int n_mol, const uint64_t *n_samples, uint
 
 /*
  * connected_pairs - the bit kernel alone: for each x (dev, n), every flip
- * group f != 0 with x ^ f inside the sector, in group order, and its matrix
+ * group f != 0 with x ^ f in x's own (N_alpha, N_beta) block (H conserves
+ * both counts, so these are the structurally connected x'; for x in the
+ * Hamiltonian's sector, that sector), in group order, and its matrix
  * element <x^f|H|x>.  Writes offsets (dev, n+1 int64), xp / hval (dev,
  * capacity each) and hdiag (dev, n doubles, <x|H|x>).  *n_pairs (host)
  * receives the total.  NQS_ECAPACITY if capacity < total (nothing written but
@@ -429,6 +455,14 @@ int batch_set_mode(nqs_batch *b, int use_graph, int retune);
  * waves), configuration pairs per fused-kernel chunk (1..16) and fused-kernel
  * blocks.  Results do not depend on the shape. */
 int batch_set_tile(nqs_batch *b, int pairs_blocks, int fused_pairs, int fused_blocks);
+
+/* Size of the distinct-x' hash table of the next batch_local_energy call:
+ * slots (a power of two, 1024 .. 2^31) instead of the automatic size (at least
+ * twice the pairs); 0 = automatic.  A step whose distinct x' overfill the table
+ * (a probe run longer than 256 slots) is run again with an enlarged,
+ * automatically sized table, so results do not depend on it; the knob is for
+ * memory-constrained callers and for tests of that path. */
+int batch_set_table(nqs_batch *b, int64_t slots);
 
 /* Last call's pairs, distinct x' (total and per molecule, host array of
  * n_mol), the number of graph captures so far, the chosen launch shape

@@ -82,6 +82,78 @@ std::vector<uint8_t> physical_children(int n, int na, int nb, const std::vector<
   return kids;
 }
 
+// Algorithm 1 for general quantum numbers: n_add additive symmetries (qubit q
+// holding bit b contributes eig[s][2 q + b] to symmetry s; composition by
+// addition) and Z2 parities (composition by XOR), as a table of prefix states.
+// Level p holds the states (partial sums, parities) of the physical prefixes of
+// p tokens: those reachable from the empty prefix from which some completion
+// reaches the targets.  Layout (int32): n + 1 level offsets, then four children
+// per state (the child's index within level p + 1, or -1).
+std::vector<int32_t> general_children(int n, int n_add, const std::vector<int32_t> &eig,
+                                      const std::vector<int32_t> &target,
+                                      const std::vector<uint64_t> &z2, uint32_t z2_target) {
+  using State = std::vector<int64_t>;     // n_add partial sums, then the parity bits
+  const int W = 4 * n;                     // eig entries per symmetry (2 per qubit)
+  auto child = [&](const State &s, int p, int k) {
+    State c = s;
+    for (int a = 0; a < n_add; ++a)
+      c[size_t(a)] += eig[size_t(a) * W + 2 * (2 * p) + (k & 1)] +
+                      eig[size_t(a) * W + 2 * (2 * p + 1) + (k >> 1)];
+    int64_t dz = 0;
+    for (size_t j = 0; j < z2.size(); ++j)
+      dz |= int64_t((((z2[j] >> (2 * p)) & 1ull) & uint64_t(k & 1)) ^
+                    (((z2[j] >> (2 * p + 1)) & 1ull) & uint64_t(k >> 1))) << j;
+    c[size_t(n_add)] ^= dz;
+    return c;
+  };
+  // forward: every state reachable at each level
+  std::vector<std::vector<State>> level(size_t(n) + 1);
+  level[0].push_back(State(size_t(n_add) + 1, 0));
+  for (int p = 0; p < n; ++p) {
+    std::vector<State> next;
+    for (const State &st : level[size_t(p)])
+      for (int k = 0; k < 4; ++k) next.push_back(child(st, p, k));
+    std::sort(next.begin(), next.end());
+    next.erase(std::unique(next.begin(), next.end()), next.end());
+    NQS_REQUIRE(next.size() <= (size_t(1) << 22), NQS_EUNSUPPORTED,
+                "amp_model_set_symmetries: more than 2^22 prefix states in a level");
+    level[size_t(p) + 1] = std::move(next);
+  }
+  // backward (Algorithm 1): a state is physical when a child is
+  State goal(target.begin(), target.end());
+  goal.push_back(int64_t(z2_target));
+  std::vector<std::vector<State>> phys(size_t(n) + 1);
+  for (const State &st : level[size_t(n)])
+    if (st == goal) phys[size_t(n)].push_back(st);
+  for (int p = n - 1; p >= 0; --p)
+    for (const State &st : level[size_t(p)]) {
+      bool ok = false;
+      for (int k = 0; k < 4 && !ok; ++k)
+        ok = std::binary_search(phys[size_t(p) + 1].begin(), phys[size_t(p) + 1].end(),
+                                child(st, p, k));
+      if (ok) phys[size_t(p)].push_back(st);   // level states are sorted, so phys is too
+    }
+  NQS_REQUIRE(!phys[0].empty(), NQS_EINVAL, "amp_model_set_symmetries: the sector is empty");
+  std::vector<int32_t> out(size_t(n) + 1, 0);
+  int64_t total = 0;
+  for (int p = 0; p <= n; ++p) {
+    out[size_t(p)] = int32_t(total);
+    total += int64_t(phys[size_t(p)].size());
+  }
+  out.resize(size_t(n) + 1 + 4 * size_t(total), -1);
+  for (int p = 0; p < n; ++p) {
+    const auto &cur = phys[size_t(p)], &nxt = phys[size_t(p) + 1];
+    for (size_t i = 0; i < cur.size(); ++i)
+      for (int k = 0; k < 4; ++k) {
+        const auto it = std::lower_bound(nxt.begin(), nxt.end(), child(cur[i], p, k));
+        if (it != nxt.end() && *it == child(cur[i], p, k))
+          out[size_t(n) + 1 + 4 * (size_t(out[size_t(p)]) + i) + size_t(k)] =
+              int32_t(it - nxt.begin());
+      }
+  }
+  return out;
+}
+
 // Sector tables of a model: one per molecule, physical-children table of each
 // from Algorithm 1, masked levels from the model's pruning strategy.
 void install_sectors(nqs_model &m, const std::vector<std::array<int, 3>> &secs, bool tagged) {
@@ -111,6 +183,38 @@ void install_sectors(nqs_model &m, const std::vector<std::array<int, 3>> &secs, 
   m.phys_host = std::move(phys);
   m.sec_host = std::move(info);
   m.tagged = tagged ? 1 : 0;
+  m.gen_nadd = 0;
+  m.gen_eig.clear();
+  m.gen_target.clear();
+  ++m.sec_gen;   // device tables may have moved: captured launch sequences are stale
+}
+
+// The model's own sector from general symmetries (one sector, untagged words).
+void install_general(nqs_model &m, int n_add, const std::vector<int32_t> &eig,
+                     const std::vector<int32_t> &target, const std::vector<uint64_t> &z2,
+                     uint32_t z2_target) {
+  const std::vector<int32_t> table = general_children(m.n, n_add, eig, target, z2, z2_target);
+  nqs_sector_info si{};
+  si.n = m.n;
+  si.na = m.na;
+  si.nb = m.nb;
+  si.mask_levels = m.mask_levels;
+  si.phys_off = 0;
+  si.general = 1;
+  const size_t bytes = table.size() * 4;
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(m.phys.reserve(bytes), table.data(), bytes, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(m.sec.reserve(sizeof(nqs_sector_info)), &si, sizeof(nqs_sector_info),
+                   hipMemcpyHostToDevice));
+  m.phys_host.assign(reinterpret_cast<const uint8_t *>(table.data()),
+                     reinterpret_cast<const uint8_t *>(table.data()) + bytes);
+  m.sec_host.assign(1, si);
+  m.tagged = 0;
+  m.z2.clear();
+  m.gen_nadd = n_add;
+  m.gen_eig = eig;
+  m.gen_target = target;
+  ++m.sec_gen;
 }
 
 }  // namespace
@@ -309,6 +413,43 @@ extern "C" int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks,
     m->z2 = std::move(z2);
     m->z2_target = target;
     install_sectors(*m, {{m->n, m->na, m->nb}}, false);
+  });
+}
+
+extern "C" int amp_model_set_symmetries(nqs_model *m, int n_add, const int32_t *eig,
+                                        const int32_t *targets, int n_z2, const uint64_t *z2_masks,
+                                        const int32_t *z2_targets) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_symmetries: null handle");
+    NQS_REQUIRE(!m->tagged, NQS_EUNSUPPORTED,
+                "amp_model_set_symmetries: the model serves several molecules");
+    NQS_REQUIRE(n_add >= 0 && n_add <= 8 && n_z2 >= 0 && n_z2 <= 4, NQS_EINVAL,
+                "amp_model_set_symmetries: 0..8 additive and 0..4 Z2 symmetries");
+    if (n_add == 0 && n_z2 == 0) {                 // back to the (n_alpha, n_beta) sector
+      m->z2.clear();
+      m->z2_target = 0;
+      install_sectors(*m, {{m->n, m->na, m->nb}}, false);
+      return;
+    }
+    NQS_REQUIRE(n_add == 0 || (eig && targets), NQS_EINVAL,
+                "amp_model_set_symmetries: null eigenvalues or targets");
+    NQS_REQUIRE(n_z2 == 0 || z2_masks, NQS_EINVAL, "amp_model_set_symmetries: null Z2 masks");
+    const int N = 2 * m->n;
+    const uint64_t qubits = N >= 64 ? ~0ull : ((1ull << N) - 1);
+    std::vector<int32_t> e(eig, eig + size_t(n_add) * 2 * N), t(targets, targets + n_add);
+    for (int32_t v : e)
+      NQS_REQUIRE(v >= -(1 << 20) && v <= (1 << 20), NQS_EINVAL,
+                  "amp_model_set_symmetries: eigenvalue out of range");
+    std::vector<uint64_t> z(z2_masks, z2_masks + n_z2);
+    uint32_t zt = 0;
+    for (int j = 0; j < n_z2; ++j) {
+      NQS_REQUIRE(z[size_t(j)] != 0 && (z[size_t(j)] & ~qubits) == 0, NQS_EINVAL,
+                  "amp_model_set_symmetries: Z2 mask empty or beyond the qubits");
+      const int32_t tj = z2_targets ? z2_targets[j] : 0;
+      NQS_REQUIRE(tj == 0 || tj == 1, NQS_EINVAL, "amp_model_set_symmetries: Z2 target not 0/1");
+      zt |= uint32_t(tj) << j;
+    }
+    install_general(*m, n_add, e, t, z, zt);
   });
 }
 

@@ -373,6 +373,7 @@ using namespace nqs;
 struct nqs_batch {
   int n_mol = 0, nbits = 0;
   nqs_model *model = nullptr;
+  uint64_t sec_gen = 0;            // the model's sector-table generation the graph was made for
   std::vector<MolTab> tabs_host;
   DevBuf tabs, flip, goff, zmask, coef;
   // capacities and step buffers (fixed addresses inside a captured graph)
@@ -391,6 +392,7 @@ struct nqs_batch {
   // statistics of the last step
   int64_t last_pairs = 0, last_distinct = 0, captures = 0;
   int64_t est_distinct = 0;        // raised when a step overfills the distinct-x' table
+  int64_t t_override = 0;          // table size of the next step (batch_set_table), 0 = automatic
   std::vector<int64_t> distinct_per_mol;
   DevBuf per_mol;
   std::vector<double> tune_ms;     // candidate timings of the last tuning
@@ -443,7 +445,8 @@ void reserve(nqs_batch &b, int64_t U, int64_t P) {
   const int64_t want = std::max<int64_t>(b.est_distinct, b.p_cap);
   int64_t t = int64_t(1) << 16;
   while (t < 2 * want) t <<= 1;
-  if (t > b.t_size) {
+  if (b.t_override > 0) t = b.t_override;
+  if (t > b.t_size || (b.t_override > 0 && t != b.t_size)) {
     b.t_size = t;
     b.table.reserve(size_t(t) * 8);
     b.ids.reserve(size_t(t) * 4);
@@ -638,6 +641,7 @@ extern "C" int batch_create(nqs_ham *const *hams, int n_mol, nqs_model *model, n
     NQS_REQUIRE(b->nbits + 7 <= 64, NQS_EUNSUPPORTED, "batch_create: keys need N + 7 bits");
     const int st = amp_model_set_sectors(model, n_mol, ns.data(), nas.data(), nbs.data());
     if (st != NQS_OK) throw Error(st, std::string("batch_create: ") + nqs_last_error());
+    b->sec_gen = model->sec_gen;
     NQS_REQUIRE(model->precision != NQS_BF16 || fused_supported(*model), NQS_EUNSUPPORTED,
                 "batch_create: model shape not supported by the fused kernel");
     auto up = [](DevBuf &d, const void *src, size_t bytes) {
@@ -692,6 +696,17 @@ extern "C" int batch_set_tile(nqs_batch *b, int pairs_blocks, int fused_pairs, i
   });
 }
 
+extern "C" int batch_set_table(nqs_batch *b, int64_t slots) {
+  return guarded([&] {
+    NQS_REQUIRE(b, NQS_EINVAL, "batch_set_table: null handle");
+    NQS_REQUIRE(slots == 0 || (slots >= 1024 && slots <= (int64_t(1) << 31) &&
+                               (slots & (slots - 1)) == 0),
+                NQS_EINVAL, "batch_set_table: 0 or a power of two in 1024 .. 2^31");
+    b->t_override = slots;
+    if (slots == 0) b->t_size = 0;   // automatic size again at the next call
+  });
+}
+
 extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_t *counts,
                                   const int64_t *offsets, const double *logabs_x,
                                   const double *phase_x, double *eloc, double *sums,
@@ -703,6 +718,19 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
     nqs_model &m = *b->model;
     NQS_REQUIRE(m.tagged && int(m.sec_host.size()) == b->n_mol, NQS_EINVAL,
                 "batch_local_energy: the model no longer serves this batch's molecules");
+    if (m.sec_gen != b->sec_gen) {
+      // the model's sector tables were reinstalled (another batch_create or
+      // amp_model_set_sectors): they must still be this batch's molecules, and
+      // the captured sequence, which holds the old tables' addresses, is dropped
+      for (int i = 0; i < b->n_mol; ++i) {
+        const nqs_sector_info &si = m.sec_host[size_t(i)];
+        const MolTab &t = b->tabs_host[size_t(i)];
+        NQS_REQUIRE(si.n == t.n && si.na == t.na && si.nb == t.nb, NQS_EINVAL,
+                    "batch_local_energy: the model's sectors are now another batch's molecules");
+      }
+      drop_graph(*b);
+      b->sec_gen = m.sec_gen;
+    }
     hipStream_t s = as_stream(stream);
     StepDesc &d = *b->desc_host;
     HIP_OK(hipStreamSynchronize(s));   // the pinned descriptor of the previous call is free
@@ -795,6 +823,7 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
     if ((c.overflow & 2) && attempt < 3) {
       // the table was too small for this step's distinct x': enlarge, run again
       b->est_distinct = std::max<int64_t>(4 * b->est_distinct, c.distinct * 2 + 1);
+      b->t_override = 0;
       continue;
     }
     if (U > 0)

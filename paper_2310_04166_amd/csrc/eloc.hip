@@ -3,8 +3,11 @@
 //
 // One 64-lane wavefront owns one sampled configuration x and sweeps the flip
 // groups of the compiled Hamiltonian 64 at a time.  For each group f the lane
-// forms x' = x ^ f and keeps it when x' has the sector's alpha and beta
-// electron counts (popcounts of the even and odd bits).  A wave ballot and a
+// forms x' = x ^ f and keeps it when x' has the alpha and beta electron counts
+// of x itself (popcounts of the even and odd bits): H conserves both, so these
+// are exactly the structurally connected x' (for x in the Hamiltonian's own
+// sector, that sector; for a model whose sector is defined by other additive
+// quantum numbers, x's own (N_alpha, N_beta) block).  A wave ballot and a
 // popcount of the lanes below give each kept pair its output slot, so pairs
 // come out in group order without atomics.  Each kept group's Pauli terms,
 // coef * (-1)^popcount(x & zmask), are then summed in double, in term order.
@@ -59,11 +62,12 @@ struct PendPair {
 
 __global__ void __launch_bounds__(256) count_pairs_kernel(
     const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip, int64_t G,
-    int na, int nb, int64_t *__restrict__ cnt) {
+    int64_t *__restrict__ cnt) {
   const int lane = threadIdx.x % kWave;
   const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   if (i >= n) return;
   const uint64_t xi = x[i];
+  const int na = __popcll(xi & kAlphaBits), nb = __popcll(xi & kBetaBits);
   int64_t c = 0;
   for (int64_t g0 = 1; g0 < G; g0 += kWave) {
     const int64_t g = g0 + lane;
@@ -80,7 +84,7 @@ __global__ void __launch_bounds__(256) count_pairs_kernel(
 __global__ void __launch_bounds__(256) emit_pairs_kernel(
     const uint64_t *__restrict__ x, int64_t n, const uint64_t *__restrict__ flip,
     const int64_t *__restrict__ goff, const uint64_t *__restrict__ zmask,
-    const double *__restrict__ coef, int64_t G, int na, int nb, const int64_t *__restrict__ off,
+    const double *__restrict__ coef, int64_t G, const int64_t *__restrict__ off,
     uint64_t *__restrict__ xp, double *__restrict__ hval, int32_t *__restrict__ owner,
     double *__restrict__ hdiag, int64_t owner_base) {
   __shared__ PendPair pend_all[kWavesPerBlock][2 * kWave];
@@ -89,6 +93,7 @@ __global__ void __launch_bounds__(256) emit_pairs_kernel(
   const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   if (i >= n) return;   // uniform over the wave; no block barrier follows
   const uint64_t xi = x[i];
+  const int na = __popcll(xi & kAlphaBits), nb = __popcll(xi & kBetaBits);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   int64_t base = off[i] - off[0];
   int npend = 0;
@@ -289,7 +294,7 @@ void launch_count_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, int64_t 
   if (n <= 0) return;
   const int64_t blocks = ceil_div(n, kWavesPerBlock);
   hipLaunchKernelGGL(count_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, n,
-                     H.d_flip.as<uint64_t>(), int64_t(H.flip.size()), H.n_alpha, H.n_beta, cnt);
+                     H.d_flip.as<uint64_t>(), int64_t(H.flip.size()), cnt);
   HIP_LAUNCH_OK();
 }
 
@@ -300,8 +305,8 @@ void launch_emit_pairs(const nqs_ham &H, const uint64_t *x, int64_t n, const int
   const int64_t blocks = ceil_div(n, kWavesPerBlock);
   hipLaunchKernelGGL(emit_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, n,
                      H.d_flip.as<uint64_t>(), H.d_off.as<int64_t>(), H.d_zmask.as<uint64_t>(),
-                     H.d_coef.as<double>(), int64_t(H.flip.size()), H.n_alpha, H.n_beta, off, xp,
-                     hval, owner, hdiag, owner_base);
+                     H.d_coef.as<double>(), int64_t(H.flip.size()), off, xp, hval, owner, hdiag,
+                     owner_base);
   HIP_LAUNCH_OK();
 }
 

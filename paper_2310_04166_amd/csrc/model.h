@@ -9,10 +9,14 @@
 // electrons, number of masked levels, optional Z2 symmetries (qubit masks) and
 // where its physical-children table starts in the model's concatenated tables
 // ([(n+1)^3 2^nz2] 4-bit masks each, the last index the prefix's Z2 parities).
+// A sector given by general additive symmetries (general = 1) instead keeps at
+// phys_off an int32 table: n + 1 level offsets, then the four children of every
+// physical prefix state (the child's state index in the next level, -1 when
+// the child is unphysical).
 struct nqs_sector_info {
   int32_t n, na, nb, mask_levels;
   int64_t phys_off;
-  int32_t nz2, pad;
+  int32_t nz2, general;
   uint64_t z2[4];
 };
 
@@ -43,6 +47,16 @@ __device__ inline uint64_t occupation(const Sectors &S, uint64_t x) {
 // whose Z2 parities select the table entry
 __device__ inline int phys_mask(const Sectors &S, const nqs_sector_info &si, int t, int a, int b,
                                 uint64_t occ) {
+  if (si.general) {
+    // the prefix's state: walk its tokens through the children table
+    const int32_t *g = reinterpret_cast<const int32_t *>(S.phys + si.phys_off);
+    const int32_t *kids = g + si.n + 1;
+    int id = 0;
+    for (int p = 0; p < t && id >= 0; ++p) id = kids[4 * (g[p] + id) + int((occ >> (2 * p)) & 3ull)];
+    if (id < 0) return 0;
+    const int32_t *c = kids + 4 * (g[t] + id);
+    return int(c[0] >= 0) | (int(c[1] >= 0) << 1) | (int(c[2] >= 0) << 2) | (int(c[3] >= 0) << 3);
+  }
   const uint64_t below = t >= 32 ? ~0ull : ((1ull << (2 * t)) - 1);
   int par = 0;
   for (int j = 0; j < si.nz2; ++j) par |= (__popcll(occ & below & si.z2[j]) & 1) << j;
@@ -61,7 +75,10 @@ struct nqs_model {
   std::vector<uint8_t> phys_host;     // concatenated physical-child tables of the sectors
   std::vector<nqs_sector_info> sec_host;  // one entry, or one per molecule when tagged
   int tagged = 0;                     // configuration words carry the molecule index
+  uint64_t sec_gen = 0;               // bumped whenever the sector tables are reinstalled
   std::vector<uint64_t> z2;           // Z2 symmetries of the model's own sector (qubit masks)
+  std::vector<int32_t> gen_eig, gen_target;  // general additive symmetries (amp_model_set_symmetries)
+  int gen_nadd = 0;
   std::vector<int64_t> nade_off;      // per-qubit ansatz: offsets of its derived blocks in packed
   uint32_t z2_target = 0;             // their parities in the target sector (bit j)
   int64_t act_budget = int64_t(1) << 30;  // bytes of activations per layer-by-layer chunk

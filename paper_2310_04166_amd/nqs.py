@@ -77,9 +77,11 @@ _SIGS = {
                     C.c_int),
     "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "amp_model_set_z2": ([_vp, C.c_int, _vp, _vp], C.c_int),
+    "amp_model_set_symmetries": ([_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp], C.c_int),
     "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
                              C.POINTER(_u64), _vp], C.c_int),
     "batch_create": ([_vp, C.c_int, _vp, C.POINTER(_vp)], C.c_int),
+    "batch_set_table": ([_vp, _i64], C.c_int),
     "batch_destroy": ([_vp], None),
     "batch_info": ([_vp, _vp, _vp], C.c_int),
     "batch_local_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64), _vp],
@@ -239,6 +241,20 @@ class Model:
         t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int32)
         _check(lib().amp_model_set_z2(self.handle, len(m), _ptr(m) if len(m) else None, _ptr(t)))
 
+    def set_symmetries(self, eig=(), targets=(), z2=(), z2_targets=None):
+        """Sector by general quantum numbers (amp_model_set_symmetries): ``eig``
+        a list of additive symmetries, each 4n integers (qubit q holding bit b
+        -> entry 2q + b), ``targets`` their sums; ``z2`` qubit masks with target
+        parities ``z2_targets`` (default 0).  No arguments: back to the
+        (n_alpha, n_beta) sector."""
+        e = np.ascontiguousarray(np.asarray(eig, dtype=np.int32).reshape(-1))
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        z = np.ascontiguousarray([int(v) for v in z2], dtype=np.uint64)
+        zt = None if z2_targets is None else np.ascontiguousarray(z2_targets, dtype=np.int32)
+        _check(lib().amp_model_set_symmetries(self.handle, len(t), _ptr(e) if len(t) else None,
+                                              _ptr(t) if len(t) else None, len(z),
+                                              _ptr(z) if len(z) else None, _ptr(zt)))
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.amp_model_destroy(self.handle)
@@ -369,6 +385,10 @@ class Batch:
 
     def set_mode(self, use_graph=True, retune=False):
         _check(lib().batch_set_mode(self.handle, int(bool(use_graph)), int(bool(retune))))
+
+    def set_table(self, slots):
+        """Distinct-x' table size of the next call (0 = automatic)."""
+        _check(lib().batch_set_table(self.handle, int(slots)))
 
     def set_tile(self, pairs_blocks, fused_pairs, fused_blocks):
         _check(lib().batch_set_tile(self.handle, pairs_blocks, fused_pairs, fused_blocks))

@@ -309,3 +309,53 @@ def test_batch_full_workload(nqs):
         g = got[off[i]:off[i + 1]][pick]
         for gj, (want, A, eps) in zip(g, res):
             assert abs(gj - want) <= 1.5 * 2 * eps * A + 1e-9, i
+
+
+def test_batch_table_enlarge_and_rerun(nqs, bf16_step):
+    """A distinct-x' table of 1024 slots (batch_set_table) overflows on this
+    step's ~1e4 distinct x': the step is run again with an enlarged table (two
+    more graph captures) and gives bit-identical local energies and sums."""
+    b, x, c, off = bf16_step["b"], bf16_step["x"], bf16_step["c"], bf16_step["off"]
+    b.set_mode(use_graph=True)
+    e0, s0, _ = b.local_energy(x, c, off)
+    e0, s0 = e0.clone(), s0.clone()
+    st0 = b.stats()
+    assert st0["distinct"] > 4096
+    b.set_table(1024)
+    e1, s1, _ = b.local_energy(x, c, off)
+    st1 = b.stats()
+    log(f"table 1024: distinct {st1['distinct']} (auto {st0['distinct']}), captures "
+        f"{st0['captures']} -> {st1['captures']}")
+    assert st1["captures"] >= st0["captures"] + 2
+    assert st1["distinct"] == st0["distinct"]
+    assert torch.equal(e1, e0) and torch.equal(s1, s0)
+    e2, s2, _ = b.local_energy(x, c, off)          # automatic size from here on
+    assert b.stats()["captures"] == st1["captures"]
+    assert torch.equal(e2, e0) and torch.equal(s2, s0)
+
+
+def test_batch_model_shared_by_batches(nqs):
+    """A second batch_create on the same model reinstalls its sector tables: a
+    batch whose molecules the model no longer serves is refused, and once the
+    model serves them again (a batch of the same molecules) the first batch
+    runs again with its captured step rebuilt, with unchanged results."""
+    mols = small_molecules()
+    m, bA, params = make(nqs, mols, "bf16")
+    x, c, off, _ = nqs.sample_unique_batch(m, [mm["n_samples"] for mm in mols], 8)
+    eA, sA, _ = bA.local_energy(x, c, off)
+    eA, sA = eA.clone(), sA.clone()
+    other = mols[::-1]
+    assert [(mm["n"], mm["n_alpha"], mm["n_beta"]) for mm in other] != \
+        [(mm["n"], mm["n_alpha"], mm["n_beta"]) for mm in mols]
+    hams = [nqs.ham_compile(mm["h"], mm["eri"], mm["n_alpha"], mm["n_beta"]) for mm in other]
+    bB = nqs.Batch(hams, m)
+    with pytest.raises(nqs.NQSError) as e:
+        bA.local_energy(x, c, off)
+    assert e.value.status == -1
+    hams2 = [nqs.ham_compile(mm["h"], mm["eri"], mm["n_alpha"], mm["n_beta"]) for mm in mols]
+    bC = nqs.Batch(hams2, m)
+    cap0 = bA.stats()["captures"]
+    e2, s2, _ = bA.local_energy(x, c, off)
+    assert bA.stats()["captures"] == cap0 + 1
+    assert torch.equal(e2, eA) and torch.equal(s2, sA)
+    del bB, bC
