@@ -47,6 +47,9 @@ class AmplitudeModel:
         self.names = list(params.keys())
         self.t = {k: torch.tensor(np.asarray(v), dtype=torch.float64,
                                   requires_grad=requires_grad) for k, v in params.items()}
+        self.phys = None
+        if getattr(sector, "general", False):     # masks walked per configuration
+            return
         n, K = self.n, len(sector.z2)
         # child masks by (position, alpha, beta, Z2 partial eigenvalues of the
         # prefix as a K-bit index: bit j set when eigenvalue j is -1)
@@ -78,6 +81,18 @@ class AmplitudeModel:
     def masks(self, toks):
         """[B, n, 4] bool: which tokens keep each prefix physical."""
         B, n = toks.shape
+        if self.phys is None:                     # general sector: Algorithm 1 per prefix
+            sec = self.sector
+            m = torch.zeros((B, n, 4), dtype=torch.bool)
+            for r in range(B):
+                s = sec.root()
+                for p in range(n):
+                    m[r, p] = torch.tensor(sec.child_mask_state(p, s))
+                    t = int(toks[r, p])
+                    s = sec.compose(sec.compose(s, sec.local_eigs(2 * p, t & 1)),
+                                    sec.local_eigs(2 * p + 1, t >> 1))
+            m[:, self.mask_levels:, :] = True
+            return m
         alpha = (toks & 1)
         beta = (toks >> 1)
         a = torch.cat([torch.zeros((B, 1), dtype=torch.long), alpha.cumsum(1)[:, :-1]], 1)

@@ -195,7 +195,10 @@ def sample_tree(model, n_samples, seed, strategy="MU", d=0, stream=0):
                 lg = model.logits(toks)[:, p, :].numpy()
         nxt = []
         for i, (x, cnt, a, b) in enumerate(frontier):
-            phys = sec.child_mask(p, a, b, sec.prefix_z2(x, p))
+            if getattr(sec, "general", False):         # any additive symmetries
+                phys = sec.child_mask_state(p, sec.prefix_state(x, p))
+            else:
+                phys = sec.child_mask(p, a, b, sec.prefix_z2(x, p))
             allowed = phys if p < mask_levels else [True] * 4
             w = child_weights([float(v) for v in lg[i]], allowed)
             split = split_counts(cnt, w, seed, tag | x, p)

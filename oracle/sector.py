@@ -123,3 +123,101 @@ def config_of(tokens):
         x |= (int(t) & 1) << (2 * p)
         x |= ((int(t) >> 1) & 1) << (2 * p + 1)
     return x
+
+
+class GeneralSector:
+    """A sector fixed by any additive quantum numbers plus optional Z2 parities
+    (paper: "Physicality evaluation algorithm", Algorithm 1 for N_sym
+    symmetries, Appendix A): additive symmetry s gives qubit i (0-based here)
+    holding bit b the integer eigenvalue ``eig[s][2 i + b]``, and the
+    eigenvalue of a configuration is the sum over qubits (composition by
+    addition); Z2 symmetry j gives (-1)^(x_i) on the qubits of ``z2[j]``
+    (composition by multiplication, carried as a parity bit).  The sector is
+    every configuration whose sums equal ``targets`` and whose parities equal
+    ``z2_targets`` (0 = eigenvalue +1).
+
+    The particle number is eig[2i + b] = b, 2 S_z is (-1)^i b, and any
+    combination of them is another instance.  Tokens as in Sector."""
+
+    general = True
+
+    def __init__(self, n, eig, targets, z2=(), z2_targets=None):
+        self.n, self.N = n, 2 * n
+        self.eig = [tuple(int(v) for v in e) for e in eig]
+        assert all(len(e) == 2 * self.N for e in self.eig)
+        self.targets = tuple(int(t) for t in targets)
+        self.z2 = tuple(int(m) for m in z2)
+        zt = [0] * len(self.z2) if z2_targets is None else [int(v) for v in z2_targets]
+        self.s_ref = self.targets + tuple(-1 if t else 1 for t in zt)
+        self.lookup = {}
+
+    def local_eigs(self, i, bit):
+        """Eigenvalues of qubit i (0-based) holding ``bit``."""
+        return tuple(e[2 * i + bit] for e in self.eig) + \
+            tuple(-1 if bit and (m >> i) & 1 else 1 for m in self.z2)
+
+    def compose(self, s, e):
+        k = len(self.eig)
+        return tuple(a + b for a, b in zip(s[:k], e[:k])) + \
+            tuple(a * b for a, b in zip(s[k:], e[k:]))
+
+    def root(self):
+        return (0,) * len(self.eig) + (1,) * len(self.z2)
+
+    def isphys(self, i, s):
+        """Algorithm 1 over the binary tree: can the prefix of qubits 0..i-1 with
+        eigenvalues s be completed into the sector?"""
+        key = (i, s)
+        if key not in self.lookup:
+            if i == self.N:
+                self.lookup[key] = s == self.s_ref
+            else:
+                self.lookup[key] = any(self.isphys(i + 1, self.compose(s, self.local_eigs(i, b)))
+                                       for b in (0, 1))
+        return self.lookup[key]
+
+    def prefix_state(self, x, p):
+        s = self.root()
+        for i in range(2 * p):
+            s = self.compose(s, self.local_eigs(i, (x >> i) & 1))
+        return s
+
+    def child_mask_state(self, p, s):
+        """Which of the 4 tokens at position p keep a prefix with eigenvalues s
+        physical."""
+        out = []
+        for k in range(4):
+            e = self.compose(self.compose(s, self.local_eigs(2 * p, k & 1)),
+                             self.local_eigs(2 * p + 1, k >> 1))
+            out.append(self.isphys(2 * p + 2, e))
+        return out
+
+    def contains(self, x):
+        return x >> self.N == 0 and self.prefix_state(x, self.n) == self.s_ref
+
+    def enumerate(self):
+        """Every configuration of the sector, ascending, by walking the token
+        tree through physical prefixes."""
+        out = []
+
+        def walk(p, x, s):
+            if p == self.n:
+                out.append(x)
+                return
+            for k, ok in enumerate(self.child_mask_state(p, s)):
+                if ok:
+                    e = self.compose(self.compose(s, self.local_eigs(2 * p, k & 1)),
+                                     self.local_eigs(2 * p + 1, k >> 1))
+                    walk(p + 1, x | (k << (2 * p)), e)
+
+        if self.isphys(0, self.root()):
+            walk(0, 0, self.root())
+        return sorted(out)
+
+
+def particle_number_eigs(n):
+    return [b for i in range(2 * n) for b in (0, 1)]
+
+
+def two_sz_eigs(n):
+    return [b if i % 2 == 0 else -b for i in range(2 * n) for b in (0, 1)]
