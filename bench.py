@@ -244,13 +244,14 @@ def tf_roofline(flop, slots, k_ms, executed_flop=None):
 
 def executed_flop_per_config(n_layers, d, ph, pad_seq=16):
     """MFMA FLOP the fused kernel issues per configuration: per 32-row tile
-    (two configurations of 16 padded positions) and layer, with every weight
-    product taken on the hi and lo weight sets and the attention probabilities
-    and output as hi + lo pairs, in 32x32x16 MFMAs of 32768 FLOP; the phase MLP's
-    256 x 256 layer as hi + lo per 32 configurations."""
+    (two configurations of 16 padded positions) and layer, with the attention
+    weight products taken on the hi and lo weight sets, the feed-forward ones on
+    one set, and the attention probabilities and output as hi + lo pairs, in
+    32x32x16 MFMAs of 32768 FLOP; the phase MLP's 256 x 256 layer as hi + lo per
+    32 configurations."""
     nb, ks, fb = d // 32, d // 16, 4 * d // 32
     per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks          # QKV hi+lo, S, PV, O-proj
-    per_layer = nb * per_head_pair + 2 * 2 * fb * ks            # + FFN W1, W2 hi+lo
+    per_layer = nb * per_head_pair + 2 * fb * ks                # + FFN W1, W2
     tile = n_layers * per_layer * 32768
     phase = 2 * (ph // 32) * (ph // 16) * 32768 / 32
     return tile / 2 + phase

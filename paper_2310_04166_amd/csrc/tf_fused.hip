@@ -26,16 +26,17 @@
 // highest-count samples (1.6e-4 Ha against the FP64 oracle on the 30-qubit
 // system; 1.7e-6 Ha with the pairs, for 7 % more kernel time).
 //
-// Every weight matrix is packed as two bf16 fragment sets, hi = bf16(W) and
-// lo = bf16(W - hi), and every weight product takes both (W x = hi x + lo x),
-// so the weights carry about 16 significant bits.  Optimiser steps move the
-// fp32 master weights off the bf16 grid; rounding them to bf16 alone changes
-// the network itself, the same way for every configuration, and moved the
-// energy of the 30-qubit system's dominant samples by ~1e-4 Ha (local energies
-// of single samples by up to 2e-3 Ha) after steps of the size of five Adam
-// steps at 1e-3.  The lo set is a second step of the same kind in the weight
-// stream (NP sub-steps per step), so the LDS ring and the registers are
-// unchanged; only the MFMA count and the stream length grow.
+// The attention weight matrices are packed as two bf16 fragment sets, hi =
+// bf16(W) and lo = bf16(W - hi), and their products take both (W x = hi x +
+// lo x), so those weights carry about 16 significant bits.  Optimiser steps
+// move the fp32 master weights off the bf16 grid; rounding them to bf16 alone
+// changes the network itself, the same way for every configuration, and moved
+// the energy of the 30-qubit system's dominant samples by ~1e-4 Ha (local
+// energies of single samples by up to 2e-3 Ha) after steps of the size of five
+// Adam steps at 1e-3, most of it from the attention matrices (NP_* below).  The
+// lo set is a second step of the same kind in the weight stream (a sub-step),
+// so the LDS ring and the registers are unchanged; only the MFMA count and the
+// stream length grow.
 //
 // Per 32 rows and layer: Q, K (2 x 8 x 8), V (8 x 4), S (8), O (2 x 16),
 // out-projection (2 x 32), FFN (128 + 128) MFMAs.  After 16 passes (32
@@ -67,7 +68,18 @@ std::vector<TimingRecord> g_records;
 constexpr int kMaxLayers = 8;
 constexpr int kSeq = 16;          // padded sequence length
 constexpr int kPairs = 16;        // passes per group of 32 configurations
-constexpr int NP = 2;             // weight fragment sets per matrix (hi, lo)
+// Fragment sets (1 = hi, 2 = hi and lo) of the attention matrices (Q, K, V,
+// output projection), of the first and of the second feed-forward matrix.
+// Measured on the 30-qubit model after five Adam steps at 1e-3 (energy of the
+// eight highest-count samples against the FP64 oracle; kernel time per launch
+// on the local-energy step): every matrix split 3.8e-5 Ha / 22.4 ms, attention
+// and W2 6.5e-5 / 20.0 ms, attention only 2.4e-5 / 17.4 ms, none (weights
+// rounded to bf16) ~1.8e-4 Ha in an FP64 simulation of the same rounding.  With
+// the attention matrices split the remaining difference is the activations'
+// rounding (the FFN weights' share simulated at 6e-6 .. 4e-5 Ha on three
+// trained models), so the FFN matrices keep one set.
+constexpr int NP_ATT = 2, NP_W1 = 1, NP_W2 = 1;
+constexpr int NP = 2;             // layout: every layer keeps room for both sets
 
 __device__ __host__ inline int perm_feature(int b, int h, int j) {
   return 32 * b + (j / 4) * 8 + h * 4 + (j % 4);
@@ -229,7 +241,22 @@ struct Shape {
                            OW1 = 4 * OK, OW2 = OW1 + int64_t(FB) * KS * 64,
                            FRAG_L = OW2 + int64_t(NB) * FKS * 64,
                            LAYER = NP * FRAG_L;   // hi set, then lo set (FRAG_L further)
-  static constexpr int USTEPS = NP * STEPS;       // sub-steps of the weight stream per layer
+  // sub-steps: step s of the stream contributes one per fragment set it uses
+  static constexpr int np_of(int s) {
+    return s < 4 * NB ? NP_ATT : ((s - 4 * NB) % 2 == 0 ? NP_W1 : NP_W2);
+  }
+  static constexpr int first_sub(int s) {      // index of step s's first sub-step
+    return s <= 4 * NB ? s * NP_ATT
+                       : 4 * NB * NP_ATT + ((s - 4 * NB) / 2) * (NP_W1 + NP_W2) +
+                             ((s - 4 * NB) % 2 ? NP_W1 : 0);
+  }
+  static constexpr int USTEPS = first_sub(STEPS);  // sub-steps of the weight stream per layer
+  static constexpr int step_of(int u) {        // the step of sub-step u, and its set
+    return u < 4 * NB * NP_ATT ? u / NP_ATT
+         : 4 * NB + 2 * ((u - 4 * NB * NP_ATT) / (NP_W1 + NP_W2)) +
+               ((u - 4 * NB * NP_ATT) % (NP_W1 + NP_W2) < NP_W1 ? 0 : 1);
+  }
+  static constexpr int set_of(int u) { return u - first_sub(step_of(u)); }
   static constexpr int64_t VLN1G = 0, VLN1B = D, VBQ = 2 * D, VBK = 3 * D, VBV = 4 * D,
                            VBO = 5 * D, VLN2G = 6 * D, VLN2B = 7 * D, VB1 = 8 * D,
                            VB2 = 8 * D + F, VEC_L = 9 * D + F;
@@ -258,14 +285,15 @@ __device__ inline StageOff stage_offsets(int lane, int wv) {
   return {{l + uint32_t(wv) * 1024u, l + uint32_t((wv / 2) * S::KS + wv % 2) * 1024u,
            l + uint32_t((wv / 2) * S::FKS + wv % 2) * 1024u}};
 }
-// Sub-step u of a layer's stream is step u / NP of the fragment set u % NP.
+// Sub-step u of a layer's stream is step S::step_of(u) of the fragment set
+// S::set_of(u).
 template <int D>
 __device__ inline void stage_load(bf16x8 (&st)[Shape<D>::KS / 4], __amdgpu_buffer_rsrc_t W,
                                   const StageOff &vo, int u) {
   using S = Shape<D>;
   constexpr int KS = S::KS;
-  const int s = u / NP;
-  const int64_t set_off = int64_t(u % NP) * S::FRAG_L;
+  const int s = S::step_of(u);
+  const int64_t set_off = int64_t(S::set_of(u)) * S::FRAG_L;
 #pragma unroll
   for (int j = 0; j < KS / 4; ++j) {
     int kind;
@@ -417,22 +445,22 @@ fused_kernel(FusedArgs a) {
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O)
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_ATT; ++pt) {
           fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Qc = mfma(fr[0][i], X[i], Qc);
-          adv(NP * (4 * b) + pt + 2);
+          adv(S::first_sub(4 * b) + pt + 2);
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Qc = mfma(fr[1][i], X[HS + i], Qc);
         }
         f32x16 Kc = lds16(V16 + S::VBK + b * 32);
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_ATT; ++pt) {
           fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Kc = mfma(fr[0][i], X[i], Kc);
-          adv(NP * (4 * b + 1) + pt + 2);
+          adv(S::first_sub(4 * b + 1) + pt + 2);
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Kc = mfma(fr[1][i], X[HS + i], Kc);
@@ -442,11 +470,11 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) Vc[j] = bvv;
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_ATT; ++pt) {
           fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Vc = mfma(X[i], fr[0][i], Vc);
-          adv(NP * (4 * b + 2) + pt + 2);
+          adv(S::first_sub(4 * b + 2) + pt + 2);
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
@@ -501,14 +529,14 @@ fused_kernel(FusedArgs a) {
         // output projection of O = hi + lo: fragment i = 2q + e (q = output
         // block); the weights' lo set multiplies O's hi part only
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_ATT; ++pt) {
           if (pt > 0) fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) {
             f32x16 acc = mfma(fr[0][i], (i % 2) ? O1 : O0, res[i / 2]);
             res[i / 2] = pt == 0 ? mfma(fr[0][i], (i % 2) ? L1 : L0, acc) : acc;
           }
-          adv(NP * (4 * b + 3) + pt + 2);   // next Q, or the first FFN sub-step
+          adv(S::first_sub(4 * b + 3) + pt + 2);   // next Q, or the first FFN sub-step
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) {
@@ -526,11 +554,11 @@ fused_kernel(FusedArgs a) {
         const int s = 4 * NB + 2 * fb;
         f32x16 Hc = lds16(V16 + S::VB1 + fb * 32);
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_W1; ++pt) {
           fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
-          adv(NP * s + pt + 2);
+          adv(S::first_sub(s) + pt + 2);
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
@@ -541,11 +569,11 @@ fused_kernel(FusedArgs a) {
         const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
         // second FFN layer: fragment i = 2q + e
 #pragma unroll
-        for (int pt = 0; pt < NP; ++pt) {
+        for (int pt = 0; pt < NP_W2; ++pt) {
           if (pt > 0) fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
-          adv(NP * (s + 1) + pt + 2);
+          adv(S::first_sub(s + 1) + pt + 2);
           fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
           for (int i = 0; i < HS; ++i)
@@ -805,8 +833,8 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   float *vb = static_cast<float *>(m.packed_vec.reserve(size_t(L.vec_total) * 4));
   // hi set at o, lo set (when NP = 2) lo_off fragments entries further
   auto pack = [&](const float *src, int64_t ld, int col0, int n_ob, int n_ks, int64_t o,
-                  int64_t lo_off) {
-    for (int p = 0; p < NP; ++p) {
+                  int64_t lo_off, int sets) {
+    for (int p = 0; p < sets; ++p) {
       hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(n_ob) * n_ks * 512), dim3(256), 0, s, src,
                          ld, col0, n_ob, n_ks, p, pk + (o + p * lo_off) * 8);
       HIP_LAUNCH_OK();
@@ -823,12 +851,12 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   };
   for (int l = 0; l < m.L; ++l) {
     const float *wqkv = P(tf_layer(l, TF_WQKV)), *bqkv = P(tf_layer(l, TF_BQKV));
-    pack(wqkv, 3 * D, 0, NB, KS, L.a.q[l], lo_layer);
-    pack(wqkv, 3 * D, D, NB, KS, L.a.k[l], lo_layer);
-    pack(wqkv, 3 * D, 2 * D, NB, KS, L.a.v[l], lo_layer);
-    pack(P(tf_layer(l, TF_WO)), D, 0, NB, KS, L.a.o[l], lo_layer);
-    pack(P(tf_layer(l, TF_W1)), F, 0, F / 32, KS, L.a.w1[l], lo_layer);
-    pack(P(tf_layer(l, TF_W2)), D, 0, NB, F / 16, L.a.w2[l], lo_layer);
+    pack(wqkv, 3 * D, 0, NB, KS, L.a.q[l], lo_layer, NP_ATT);
+    pack(wqkv, 3 * D, D, NB, KS, L.a.k[l], lo_layer, NP_ATT);
+    pack(wqkv, 3 * D, 2 * D, NB, KS, L.a.v[l], lo_layer, NP_ATT);
+    pack(P(tf_layer(l, TF_WO)), D, 0, NB, KS, L.a.o[l], lo_layer, NP_ATT);
+    pack(P(tf_layer(l, TF_W1)), F, 0, F / 32, KS, L.a.w1[l], lo_layer, NP_W1);
+    pack(P(tf_layer(l, TF_W2)), D, 0, NB, F / 16, L.a.w2[l], lo_layer, NP_W2);
     perm(P(tf_layer(l, TF_LN1G)), D, 1, L.a.ln1g[l]);
     perm(P(tf_layer(l, TF_LN1B)), D, 1, L.a.ln1b[l]);
     perm(bqkv, D, 1, L.a.bq[l]);
@@ -841,7 +869,7 @@ void fused_pack(nqs_model &m, hipStream_t s) {
     perm(P(tf_layer(l, TF_B2)), D, 1, L.a.b2[l]);
   }
   const int Lm = m.L;
-  pack(P(tf_tail(Lm, TF_PW2)), PH, 0, PH / 32, PH / 16, L.a.p2, L.a.p2lo - L.a.p2);
+  pack(P(tf_tail(Lm, TF_PW2)), PH, 0, PH / 32, PH / 16, L.a.p2, L.a.p2lo - L.a.p2, NP);
   perm(P(tf_tail(Lm, TF_LNFG)), D, 1, L.a.lnfg);
   perm(P(tf_tail(Lm, TF_LNFB)), D, 1, L.a.lnfb);
   hipLaunchKernelGGL(perm_head_kernel, g1(4 * D), dim3(256), 0, s, P(tf_tail(Lm, TF_WHEAD)), D,

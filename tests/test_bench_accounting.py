@@ -47,8 +47,8 @@ def test_executed_mfma_count_by_hand():
     # per 32-row tile and layer at d 128: per head pair Q, K, V (8 k-steps each,
     # hi + lo weights) 48, scores 2, P V (hi + lo P) 8, output projection (hi
     # weights x O hi + lo, lo weights x O hi) 24; per hidden block of 32 (16 of
-    # them) W1 and W2 with hi + lo weights 32 -> 4 * 82 + 16 * 32 = 840 MFMAs
-    per_tile = 4 * 840 * 32768
+    # them) W1 and W2 on one weight set 16 -> 4 * 82 + 16 * 16 = 584 MFMAs
+    per_tile = 4 * 584 * 32768
     phase = 2 * 8 * 16 * 32768 / 32
     assert bench.executed_flop_per_config(4, 128, 256) == per_tile / 2 + phase
 
