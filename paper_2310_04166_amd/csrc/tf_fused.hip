@@ -257,6 +257,13 @@ struct Shape {
                ((u - 4 * NB * NP_ATT) % (NP_W1 + NP_W2) < NP_W1 ? 0 : 1);
   }
   static constexpr int set_of(int u) { return u - first_sub(step_of(u)); }
+  // Feed-forward steps in stream order j = step - 4 NB: W1(0), W1(1), then
+  // W1(fb + 1), W2(fb - 1) for fb = 1 .. FB - 2, then W2(FB - 2), W2(FB - 1)
+  // (the kernel evaluates the GELU of block fb between those two products).
+  static constexpr bool ffn_is_w1(int j) { return j < 2 || (j < 2 * FB - 2 && j % 2 == 0); }
+  static constexpr int ffn_block(int j) {
+    return j < 2 ? j : j >= 2 * FB - 2 ? j - FB : (j % 2 == 0 ? j / 2 + 1 : j / 2 - 1);
+  }
   static constexpr int64_t VLN1G = 0, VLN1B = D, VBQ = 2 * D, VBK = 3 * D, VBV = 4 * D,
                            VBO = 5 * D, VLN2G = 6 * D, VLN2B = 7 * D, VB1 = 8 * D,
                            VB2 = 8 * D + F, VEC_L = 9 * D + F;
@@ -304,14 +311,15 @@ __device__ inline void stage_load(bf16x8 (&st)[Shape<D>::KS / 4], __amdgpu_buffe
       off = s % 4 == 3 ? S::OO + (int64_t(2 * b) + int64_t(2 * j) * KS) * 64
           : (s % 4 == 0 ? S::OQ : s % 4 == 1 ? S::OK : S::OV) + int64_t(b) * KS * 64 + int64_t(4 * j) * 64;
     } else {
-      const int fb = (s - 4 * S::NB) / 2;
-      const bool w1 = (s - 4 * S::NB) % 2 == 0;
+      const int fb = S::ffn_block(s - 4 * S::NB);
+      const bool w1 = S::ffn_is_w1(s - 4 * S::NB);
       kind = w1 ? 0 : 2;
       off = w1 ? S::OW1 + int64_t(fb) * KS * 64 + int64_t(4 * j) * 64
                : S::OW2 + (int64_t(2 * fb) + int64_t(2 * j) * S::FKS) * 64;
     }
+    const uint32_t voff = kind == 0 ? vo.v[0] : kind == 1 ? vo.v[1] : vo.v[2];
     st[j] = __builtin_bit_cast(
-        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, vo.v[kind], uint32_t((off + set_off) * 16), 0));
+        bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, voff, uint32_t((off + set_off) * 16), 0));
   }
 }
 template <int D>
@@ -326,6 +334,29 @@ __device__ inline void fetch_half(bf16x8 (&f)[Shape<D>::KS / 2], const bf16x8 *s
                                   int lane) {
 #pragma unroll
   for (int ii = 0; ii < Shape<D>::KS / 2; ++ii) f[ii] = slot[(half * (Shape<D>::KS / 2) + ii) * 64 + lane];
+}
+
+// One half step of the pipelined feed-forward block: the HS MFMAs of fragment
+// half h of a W1 step (into Hn) or of a W2 step (into res, operand Hp0 / Hp1),
+// each followed by PER / HS of the GELU values G0 .. G0 + PER - 1 of Hc.
+template <int D, bool W1, int PER, int G0>
+__device__ inline void ffn_half(const bf16x8 (&f)[Shape<D>::KS / 2], int h,
+                                const bf16x8 (&X)[Shape<D>::KS], f32x16 &Hn,
+                                f32x16 (&res)[Shape<D>::NB], const bf16x8 &Hp0,
+                                const bf16x8 &Hp1, f32x16 &Hc) {
+  constexpr int HS = Shape<D>::KS / 2, PM = PER / HS;
+  static_assert(PER % HS == 0, "GELU values per MFMA");
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    if (W1) {
+      Hn = mfma(f[i], X[h * HS + i], Hn);
+    } else {
+      const int fi = h * HS + i;               // W2 fragment 2q + e
+      res[fi / 2] = mfma(f[i], (fi % 2) ? Hp1 : Hp0, res[fi / 2]);
+    }
+#pragma unroll
+    for (int k = 0; k < PM; ++k) Hc[G0 + i * PM + k] = gelu(Hc[G0 + i * PM + k]);
+  }
 }
 
 template <int D>
@@ -545,40 +576,69 @@ fused_kernel(FusedArgs a) {
           }
         }
       }
-      // ---- feed-forward block: step 4NB + 2fb = W1, +1 = W2
+      // ---- feed-forward block, software-pipelined: the GELU of hidden block
+      // fb is evaluated between the MFMAs of W1(fb + 1) and W2(fb - 1), which
+      // do not depend on it, so that one wave keeps the matrix pipe busy while
+      // it issues the elementwise work (waves sharing a SIMD were measured not
+      // to fill each other's MFMA time).  The weight stream follows the same
+      // order (Shape::ffn_is_w1 / ffn_block).
+      static_assert(NP_W1 == 1 && NP_W2 == 1, "pipelined feed-forward block: one weight set");
       layer_norm<NB>(res, V16, int(S::VLN2G), int(S::VLN2B), X);
 #pragma unroll
       for (int q = 0; q < NB; ++q) res[q] += lds16(V16 + S::VB2 + q * 32);
-#pragma unroll
-      for (int fb = 0; fb < FB; ++fb) {
-        const int s = 4 * NB + 2 * fb;
-        f32x16 Hc = lds16(V16 + S::VB1 + fb * 32);
-#pragma unroll
-        for (int pt = 0; pt < NP_W1; ++pt) {
-          fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
-#pragma unroll
-          for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
-          adv(S::first_sub(s) + pt + 2);
-          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
-#pragma unroll
-          for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
-        }
+      {
+        constexpr int J0 = 4 * NB;                  // first feed-forward step
+        f32x16 Hc = lds16(V16 + S::VB1);
+        // W1(0), stream position 0
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) Hc[j] = gelu(Hc[j]);
-        const bf16x8 H0 = to_bf16(Hc, 0), H1 = to_bf16(Hc, 1);
-        // second FFN layer: fragment i = 2q + e
+        for (int i = 0; i < HS; ++i) Hc = mfma(fr[0][i], X[i], Hc);
+        adv(S::first_sub(J0) + 2);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
 #pragma unroll
-        for (int pt = 0; pt < NP_W2; ++pt) {
-          if (pt > 0) fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
-#pragma unroll
-          for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? H1 : H0, res[i / 2]);
-          adv(S::first_sub(s + 1) + pt + 2);
-          fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
-#pragma unroll
-          for (int i = 0; i < HS; ++i)
-            res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? H1 : H0, res[(HS + i) / 2]);
+        for (int i = 0; i < HS; ++i) Hc = mfma(fr[1][i], X[HS + i], Hc);
+        bf16x8 Hp0 = {}, Hp1 = {};                  // GELU output of the previous block
+        // a W1 or W2 sub-step at stream position j, GELU values interleaved
+        // (PER per half step, starting at G0 for half 0 and G0 + PER for half 1)
+#define NQS_FFN_SUB(W1_, PER_, G0_, j_)                                                   \
+  {                                                                                       \
+    fetch_half<D>(fr[1], ring + cur * RS, 1, lane);                                       \
+    ffn_half<D, W1_, PER_, G0_>(fr[0], 0, X, Hn, res, Hp0, Hp1, Hc);                      \
+    adv(S::first_sub(J0 + (j_)) + 2);                                                     \
+    fetch_half<D>(fr[0], ring + cur * RS, 0, lane);                                       \
+    ffn_half<D, W1_, PER_, G0_ + PER_>(fr[1], 1, X, Hn, res, Hp0, Hp1, Hc);               \
+  }
+        {   // fb = 0: W1(1) at position 1 with all 16 GELU values of block 0
+          f32x16 Hn = lds16(V16 + S::VB1 + 32);
+          NQS_FFN_SUB(true, 8, 0, 1)
+          Hp0 = to_bf16(Hc, 0);
+          Hp1 = to_bf16(Hc, 1);
+          Hc = Hn;
         }
+        for (int fb = 1; fb < FB - 1; ++fb) {     // W1(fb + 1) at 2 fb, W2(fb - 1) at 2 fb + 1
+          f32x16 Hn = lds16(V16 + S::VB1 + (fb + 1) * 32);
+          NQS_FFN_SUB(true, 4, 0, 2 * fb)
+          NQS_FFN_SUB(false, 4, 8, 2 * fb + 1)
+          Hp0 = to_bf16(Hc, 0);
+          Hp1 = to_bf16(Hc, 1);
+          Hc = Hn;
+        }
+        {   // fb = FB - 1: W2(FB - 2) at position 2 FB - 2
+          f32x16 Hn{};
+          NQS_FFN_SUB(false, 8, 0, 2 * FB - 2)
+          Hp0 = to_bf16(Hc, 0);
+          Hp1 = to_bf16(Hc, 1);
+        }
+#undef NQS_FFN_SUB
+        // W2(FB - 1), stream position 2 FB - 1
+        fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
+#pragma unroll
+        for (int i = 0; i < HS; ++i) res[i / 2] = mfma(fr[0][i], (i % 2) ? Hp1 : Hp0, res[i / 2]);
+        adv(S::first_sub(J0 + 2 * FB - 1) + 2);
+        fetch_half<D>(fr[0], ring + cur * RS, 0, lane);
+#pragma unroll
+        for (int i = 0; i < HS; ++i)
+          res[(HS + i) / 2] = mfma(fr[1][i], (i % 2) ? Hp1 : Hp0, res[(HS + i) / 2]);
       }
     }
 
