@@ -34,6 +34,20 @@ sys.path.insert(0, ROOT)
 # + head 15 x 4 d + phase MLP 256^2 + 256
 FLOP_PER_CONFIG = 2 * (15 * 4 * 12 * 128 ** 2 + 4 * 2 * 128 * 120 + 15 * 4 * 128 + 256 * 256 + 256)
 BF16_PEAK_TFLOPS = 2500.0
+# positions of a shared prefix (the library evaluates positions 0..7 once per
+# distinct 8-token prefix, positions 8.. per configuration)
+TRUNK = 8
+
+
+def rows_flop(t0, t1, d, n_layers, ffn, ph, phase):
+    """Multiply-adds x 2 of positions t0 .. t1 - 1 of one configuration: per
+    position and layer 4 d^2 + 2 d ffn, causal attention 2 d (t + 1) per query t
+    and layer, the head 4 d per position; the phase MLP ph^2 + ph if asked for.
+    rows_flop(0, n, ...) with the phase MLP is one whole evaluation."""
+    pos = t1 - t0
+    keys = sum(t + 1 for t in range(t0, t1))
+    return 2 * (pos * n_layers * (4 * d * d + 2 * d * ffn) + n_layers * 2 * d * keys
+                + pos * 4 * d + ((ph * ph + ph) if phase else 0))
 
 # The per-qubit ansatz (workload "nade") is bound by its elementwise VALU work.
 # Peak VALU issue of MI355X without packed fp32 (disabled in this build):
@@ -46,7 +60,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 NADE_SLOTS = {"ctanh": 4 * 4 + 11, "lerelu": 2, "normaliser": 3 * 4 + 6}
 
 
-def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph):
+def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph, t0=0):
     """Algorithmic VALU slots of one transformer evaluation of an n-token
     configuration (same accounting as NADE_SLOTS): per layer and token two layer
     norms (5 per feature + a reciprocal square root), two residual additions
@@ -56,10 +70,13 @@ def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph):
     reciprocal per row); the embedding sum, the final layer norm, the masked
     log-softmax of 4 logits per token (28); the phase MLP (its first layer a sum
     of n rows, two GELU layers, the final dot product).  Bias additions ride in
-    the MFMA accumulators and are not counted; neither are bf16 conversions."""
+    the MFMA accumulators and are not counted; neither are bf16 conversions.
+    With t0 > 0: positions t0 .. n - 1 only (a suffix over a shared prefix)."""
     ln = 5 * d + 4
-    per_layer = n * (2 * ln + 2 * d + 13 * ffn) + n_heads * (n * (n + 1) // 2) * 8 + n_heads * n * 4
-    return (n_layers * per_layer + n * d + n * ln + n * 28
+    pos = n - t0
+    keys = sum(t + 1 for t in range(t0, n))
+    per_layer = pos * (2 * ln + 2 * d + 13 * ffn) + n_heads * keys * 8 + n_heads * pos * 4
+    return (n_layers * per_layer + pos * d + pos * ln + pos * 28
             + n * ph + 2 * 13 * ph + ph)
 
 
@@ -242,19 +259,23 @@ def tf_roofline(flop, slots, k_ms, executed_flop=None):
     return out
 
 
-def executed_flop_per_config(n_layers, d, ph, pad_seq=16):
-    """MFMA FLOP the fused kernel issues per configuration: per 32-row tile
-    (two configurations of 16 padded positions) and layer, with the attention
-    weight products taken on the hi and lo weight sets, the feed-forward ones on
-    one set, and the attention probabilities and output as hi + lo pairs, in
-    32x32x16 MFMAs of 32768 FLOP; the phase MLP's 256 x 256 layer as hi + lo per
-    32 configurations."""
+def executed_flop_per_config(n_layers, d, ph, mode="plain"):
+    """MFMA FLOP the fused kernel issues per configuration: per 32-row tile and
+    layer, with the attention weight products taken on the hi and lo weight
+    sets, the feed-forward ones on one set, and the attention probabilities and
+    output as hi + lo pairs, in 32x32x16 MFMAs of 32768 FLOP; the phase MLP's
+    256 x 256 layer as hi + lo per 32 configurations.  A tile holds 2
+    configurations of 16 padded positions ("plain"), 4 prefixes of 8 positions
+    ("trunk", no phase MLP) or 4 configurations of 8 positions that also attend
+    to their prefix's 8 keys ("suffix": two more score and four more
+    probability-value products per head)."""
     nb, ks, fb = d // 32, d // 16, 4 * d // 32
-    per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks          # QKV hi+lo, S, PV, O-proj
+    extra = 2 + 8 if mode == "suffix" else 0
+    per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks + extra   # QKV hi+lo, S, PV, O-proj
     per_layer = nb * per_head_pair + 2 * fb * ks                # + FFN W1, W2
     tile = n_layers * per_layer * 32768
-    phase = 2 * (ph // 32) * (ph // 16) * 32768 / 32
-    return tile / 2 + phase
+    phase = 0 if mode == "trunk" else 2 * (ph // 32) * (ph // 16) * 32768 / 32
+    return tile / (2 if mode == "plain" else 4) + phase
 
 
 def cpu_info():
@@ -503,7 +524,13 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     gpu_ms = ev0.elapsed_time(ev1)
-    k_ms, k_launches, k_cfgs = nqs.timing_read()
+    # the dominant kernel: positions 8.. of every configuration (prefix-shared
+    # evaluation), then the prefixes, then every other launch (the sampler's)
+    sfx = nqs.timing_read(nqs.TIMING_SUFFIX)
+    trk = nqs.timing_read(nqs.TIMING_TRUNK)
+    rest = nqs.timing_read()
+    shared = sfx[1] > 0
+    k_ms, k_launches, k_cfgs = sfx if shared else rest
     nqs.timing_enable(False)
 
     value = total_pairs / elapsed
@@ -522,20 +549,35 @@ def main():
                     "mfma_tflops": round(k_cfgs * flop / (k_ms * 1e-3) / 1e12, 2) if k_ms else 0,
                     "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
     else:
-        slots_cfg = tf_valu_slots(cfg["n"], cfg["d"], cfg["n_layers"], cfg["n_heads"],
-                                  4 * cfg["d"], 256)
-        exe_cfg = executed_flop_per_config(cfg["n_layers"], cfg["d"], 256)
-        roofline = tf_roofline(k_cfgs * FLOP_PER_CONFIG, k_cfgs * slots_cfg, k_ms,
-                               k_cfgs * exe_cfg)
+        n, d, nl = cfg["n"], cfg["d"], cfg["n_layers"]
+        t0 = TRUNK if shared else 0
+        slots_cfg = tf_valu_slots(n, d, nl, cfg["n_heads"], 4 * d, 256, t0)
+        flop_cfg = rows_flop(t0, n, d, nl, 4 * d, 256, True)
+        exe_cfg = executed_flop_per_config(nl, d, 256, "suffix" if shared else "plain")
+        roofline = tf_roofline(k_cfgs * flop_cfg, k_cfgs * slots_cfg, k_ms, k_cfgs * exe_cfg)
         roofline.update({"traffic": fused_traffic() if args.workload == "precision" else None,
                          "traffic_unit": "bytes per launch",
-                         "kernel": "fused_kernel<128> (bf16 amplitude network)",
+                         "kernel": ("fused_kernel<128, SUFFIX> (bf16 amplitude network, "
+                                    "positions 8..15 of each configuration)") if shared else
+                                   "fused_kernel<128, PLAIN> (bf16 amplitude network)",
                          "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
                          "launches": k_launches, "configs": k_cfgs,
-                         "flop_per_config": FLOP_PER_CONFIG,
+                         "flop_per_config": flop_cfg,
+                         "network_flop_per_config": FLOP_PER_CONFIG,
                          "executed_flop_per_config": int(exe_cfg),
                          "valu_slots_per_config": slots_cfg,
                          "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)})
+        if shared:
+            tflop = rows_flop(0, TRUNK, d, nl, 4 * d, 256, False)
+            roofline["prefixes"] = {
+                "kernel": "fused_kernel<128, TRUNK> (positions 0..7 once per distinct "
+                          "8-token prefix)",
+                "launches": trk[1], "prefixes": trk[2], "ms": round(trk[0], 3),
+                "flop_per_prefix": tflop,
+                "mfma_frac": round(trk[2] * tflop / max(trk[0], 1e-9) / 1e9 / BF16_PEAK_TFLOPS, 4),
+                "share_of_steps": round(trk[0] / max(gpu_ms, 1e-9), 4)}
+            roofline["other_fused"] = {"launches": rest[1], "configs": rest[2],
+                                       "ms": round(rest[0], 3)}
 
     cpu = None
     if not args.no_cpu and precision:

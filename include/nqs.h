@@ -255,6 +255,21 @@ int amp_model_set_symmetries(nqs_model *m, int n_add, const int32_t *eig, const 
 int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks, const int32_t *targets);
 
 /*
+ * amp_model_set_prefix_sharing - evaluate batches of a bf16 transformer with
+ * 9..16 tokens (one molecule) by shared prefixes (on = 1, the default) or
+ * configuration by configuration (on = 0).  Paper: ANQS product rule (the
+ * network is causal: the hidden states of positions 0..7 depend only on tokens
+ * 0..6).  Shared: the distinct 8-token prefixes of a batch are evaluated once
+ * (positions 0..7; keys and values of every layer kept in a model-owned
+ * buffer of up to 65,536 entries of L * d * 32 bytes), then positions 8..15 of
+ * every configuration attend to its prefix's keys and values.  Used by
+ * amp_forward and local_energy (the sampler's conditionals are unaffected).
+ * Results agree with the unshared evaluation up to the order of fp32 sums.
+ * Errors: NQS_EINVAL (null handle).
+ */
+int amp_model_set_prefix_sharing(nqs_model *m, int on);
+
+/*
  * amp_forward - log|psi(x)| and phase phi(x) for n configurations.
  * x (dev, n uint64), logabs / phase (dev, n doubles each, written).  A
  * configuration outside the sector gets logabs = -inf.  n = 0 is a no-op.
@@ -500,6 +515,15 @@ int vmc_weights_batch(const double *eloc, const uint64_t *counts, const uint64_t
  */
 int nqs_timing_enable(int on);
 int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs);
+/*
+ * The same for the launches of one row layout only (those records are
+ * removed, the others kept): mode 0 = transformer, up to 16 tokens (2
+ * configurations x 16 positions per 32 rows); 1 = 17..32 tokens; 2 = shared
+ * prefixes (positions 0..7 once per distinct 8-token prefix); 3 = their
+ * suffixes (positions 8..15 per configuration); -1 = the per-qubit ansatz;
+ * -2 = every record (nqs_timing_read).
+ */
+int nqs_timing_read_mode(int mode, double *ms, int64_t *launches, int64_t *configs);
 
 #ifdef __cplusplus
 }

@@ -506,6 +506,22 @@ extern "C" int amp_model_set_params(nqs_model *m, const double *host_in) {
 
 extern "C" void amp_model_destroy(nqs_model *m) { delete m; }
 
+extern "C" int amp_model_set_prefix_sharing(nqs_model *m, int on) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_prefix_sharing: null handle");
+    m->prefix_share = on != 0;
+  });
+}
+
+namespace {
+// bf16 forward of a batch: prefix-shared where the model allows it
+void bf16_forward(nqs_model &m, const uint64_t *x, int64_t n, double *logabs, double *phase,
+                  hipStream_t s) {
+  if (fused_shared_supported(m)) fused_forward_shared(m, x, n, logabs, phase, s);
+  else fused_forward(m, x, n, logabs, phase, nullptr, -1, s);
+}
+}  // namespace
+
 extern "C" int amp_forward(nqs_model *m, const uint64_t *x, int64_t n, double *logabs,
                            double *phase, nqs_stream stream) {
   return guarded([&] {
@@ -514,7 +530,7 @@ extern "C" int amp_forward(nqs_model *m, const uint64_t *x, int64_t n, double *l
     if (n == 0) return;
     NQS_REQUIRE(x && (logabs || phase), NQS_EINVAL, "amp_forward: null pointer");
     if (m->precision == NQS_BF16)
-      fused_forward(*m, x, n, logabs, phase, nullptr, -1, as_stream(stream));
+      bf16_forward(*m, x, n, logabs, phase, as_stream(stream));
     else
       model_forward(*m, x, n, logabs, phase, nullptr, as_stream(stream));
   });
@@ -648,7 +664,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
     if (!lax) {
       double *a = static_cast<double *>(H->w_lax.reserve(size_t(n) * 8));
       double *b = static_cast<double *>(H->w_phx.reserve(size_t(n) * 8));
-      if (m->precision == NQS_BF16) fused_forward(*m, x, n, a, b, nullptr, -1, s);
+      if (m->precision == NQS_BF16) bf16_forward(*m, x, n, a, b, s);
       else model_forward(*m, x, n, a, b, nullptr, s);
       lax = a;
       phx = b;
@@ -679,7 +695,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
                                       H->w_tmp, s);
       H->last_distinct += nu;
       if (nu > 0) {
-        if (m->precision == NQS_BF16) fused_forward(*m, ukeys, nu, la, ph, nullptr, -1, s);
+        if (m->precision == NQS_BF16) bf16_forward(*m, ukeys, nu, la, ph, s);
         else model_forward(*m, ukeys, nu, la, ph, nullptr, s);
       }
       launch_accumulate(i1 - i0, off + i0, hv, np > 0 ? uid : nullptr, la, ph, lax + i0,

@@ -96,6 +96,8 @@ struct nqs_model {
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
   nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
+  int prefix_share = 1;               // bf16 transformer: prefix-shared evaluation of batches
+  nqs::DevBuf pf_tab, pf_list, pf_logp, pf_kv, pf_scan;  // its prefix table, keys and values
 
   bool fp64() const { return precision == NQS_FP64; }
   nqs::Sectors sectors() const {
@@ -158,12 +160,18 @@ void nade_fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *loga
 // Kernel timing of the fused kernels (nqs_timing_*): whether it is on, and a
 // record measured by a caller (events inside a captured graph).
 bool timing_on();
-void timing_add(float ms, int64_t configs);
+void timing_add(float ms, int64_t configs, int mode = 0);
 // an event recorded on s when timing is on and the launch has a host-side size
 // (count == nullptr), else null; timing_end records the launch between the two
 hipEvent_t timing_begin(hipStream_t s, const int64_t *count);
-void timing_end(hipEvent_t start, hipStream_t s, int64_t configs);
+void timing_end(hipEvent_t start, hipStream_t s, int64_t configs, int mode = -1);
 bool fused_supported(const nqs_model &m);
+// Prefix-shared bf16 forward (log|psi| and phase) for 8 < n <= 16 tokens of an
+// untagged model with prefix sharing on: positions 0..7 once per distinct
+// 8-token prefix of x, positions 8..15 per configuration (tf_fused.hip).
+bool fused_shared_supported(const nqs_model &m);
+void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                          double *phase, hipStream_t s);
 // explicit psi over a basis (table.hip): install the basis (host, ascending),
 // rebuild the prefix sums of |psi|^2 from the master parameters, forward,
 // conditional logits of token p for the sampler, backward into double acc[2M]

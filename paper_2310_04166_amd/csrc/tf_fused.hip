@@ -45,6 +45,7 @@
 #include <cmath>
 #include <vector>
 
+#include "ham.h"
 #include "model.h"
 #include "ops.h"
 
@@ -56,18 +57,42 @@ typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(2))) int i32x2;
 
 struct TimingRecord {
   hipEvent_t start, stop;           // null for a record measured elsewhere (ms set)
   int64_t configs;
   float ms;
+  int mode;                         // row layout of the transformer kernel, -1 for the others
 };
 bool g_timing = false;
 std::vector<TimingRecord> g_records;
 
 constexpr int kMaxLayers = 8;
-constexpr int kSeq = 16;          // padded sequence length
-constexpr int kPairs = 16;        // passes per group of 32 configurations
+constexpr int kSeqMax = 32;       // longest sequence (tokens)
+constexpr int kTrunk = 8;         // positions of a shared prefix (TRUNK / SUFFIX)
+
+// Row layouts of a wave's 32 rows (R rows per configuration, 32 / R
+// configurations per pass):
+//   PLAIN   R = 16: positions 0..15 of 2 configurations (up to 16 tokens);
+//   WIDE    R = 32: positions 0..31 of 1 configuration (17..32 tokens);
+//   TRUNK   R = 8:  positions 0..7 of 4 distinct 8-token prefixes; the keys and
+//                   values of every layer and the log-probability of the 8
+//                   tokens are stored per prefix;
+//   SUFFIX  R = 8:  positions 8..15 of 4 configurations, attending to the
+//                   stored keys and values of their prefix.
+// Positions 0..7 of a causal network see only tokens 0..6, so their hidden
+// states, keys and values are the same for every configuration with the same
+// first 8 tokens; distinct x' of one step share few such prefixes (at most
+// 4^8), so TRUNK + SUFFIX do about half the work of PLAIN per configuration.
+enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3 };
+template <int MODE>
+struct Rows {
+  static constexpr int R = MODE == PLAIN ? 16 : MODE == WIDE ? 32 : 8;
+  static constexpr int CPT = 32 / R;            // configurations per pass
+  static constexpr int P0 = MODE == SUFFIX ? kTrunk : 0;   // first position
+  static constexpr int MAXP = 32 / CPT;         // passes per chunk of 32 configurations
+};
 // Fragment sets (1 = hi, 2 = hi and lo) of the attention matrices (Q, K, V,
 // output projection), of the first and of the second feed-forward matrix.
 // Measured on the 30-qubit model after five Adam steps at 1e-3 (energy of the
@@ -99,10 +124,33 @@ struct FusedArgs {
   int64_t B;                        // configurations (capacity when `count` is given)
   const int64_t *count;             // optional device-side count (persistent launches)
   int n, L, cond_p;                 // n = positions of the model
-  int pairs;                        // passes per chunk (configurations per chunk / 2), <= 16
+  int passes;                       // passes per chunk (32 / R configurations each)
   int lds_floats;                   // vec[0 .. lds_floats) is staged in LDS (all but pw1)
   double *logabs, *phase, *cond;
+  // TRUNK / SUFFIX: per prefix entry (kv_bytes each) the keys and values of
+  // positions 0..7 in every layer, and the log-probability of tokens 0..7;
+  // SUFFIX finds a configuration's entry at slot[x & 0xFFFF]
+  uint8_t *kv;
+  int64_t kv_bytes, kv_total;       // bytes per entry, of the buffer (<= 2^31)
+  float *plogp;
+  const int64_t *slot;
 };
+
+// Byte offsets inside a prefix entry, layer l (NB blocks of 32 features):
+//   key   (block b, head e, position t, lane half h) at kv_key_off + 32 t + 16 h:
+//         16 B, the lane's 8 feature slots of head e;
+//   value (block b, feature f, lane half h) at kv_val_off + 16 f + 8 h: 8 B,
+//         positions 4 h .. 4 h + 3.
+// The layer / block / head part is wave-uniform (a scalar offset), the lane
+// part a per-lane constant.
+template <int NB>
+__device__ inline uint32_t kv_key_off(int l, int b, int e) {
+  return uint32_t(l * NB * 1024 + b * 512 + e * 256);
+}
+template <int NB>
+__device__ inline uint32_t kv_val_off(int l, int b) {
+  return uint32_t(l * NB * 1024 + NB * 512 + b * 512);
+}
 
 __device__ inline bf16x8 to_bf16(const f32x16 &c, int half) {
   bf16x8 r;
@@ -173,6 +221,22 @@ __device__ inline void pack8_hilo(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) r[i] = v[i] - float(hi[i]);
   lo = pack8(r);
+}
+// four values as hi (words h[0], h[1]) and lo (l[0], l[1]) bf16 pairs
+__device__ inline void pack4_hilo(const float *v, uint32_t (&hw)[2], uint32_t (&lw)[2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const f32x2 p = {v[2 * i], v[2 * i + 1]};
+    const bf16x2 q = __builtin_convertvector(p, bf16x2);
+    const f32x2 d = {v[2 * i] - float(q[0]), v[2 * i + 1] - float(q[1])};
+    hw[i] = __builtin_bit_cast(uint32_t, q);
+    lw[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector(d, bf16x2));
+  }
+}
+// m ? b : a, bitwise (one v_bfi_b32; keeps a lane-dependent choice between
+// vector elements from becoming a dynamically indexed vector)
+__device__ inline float bsel(float a, float b, uint32_t m) {
+  return __uint_as_float((__float_as_uint(b) & m) | (__float_as_uint(a) & ~m));
 }
 // the bf16 rounding error of to_bf16(c, half) == hi, as bf16
 __device__ inline bf16x8 lo_bf16(const f32x16 &c, int half, const bf16x8 &hi) {
@@ -359,11 +423,12 @@ __device__ inline void ffn_half(const bf16x8 (&f)[Shape<D>::KS / 2], int h,
   }
 }
 
-template <int D>
+template <int D, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 fused_kernel(FusedArgs a) {
   using S = Shape<D>;
   constexpr int NB = S::NB, KS = S::KS, FB = S::FB, STEPS = S::STEPS;
+  constexpr int R = Rows<MODE>::R, CPT = Rows<MODE>::CPT, P0 = Rows<MODE>::P0;
   const int lane = threadIdx.x % 64, h = lane / 32, r = lane % 32;
   // The permuted fp32 vectors (biases, layer-norm parameters, head, embeddings)
   // are read by every lane at the same few addresses; they are staged in LDS
@@ -383,21 +448,37 @@ fused_kernel(FusedArgs a) {
   const int64_t B = a.count ? (*a.count < a.B ? *a.count : a.B) : a.B;
   // All four waves of a block take part in every barrier of the weight
   // stream, so the loops are uniform over the block: a block owns chunks of
-  // 4 x 2 x pairs configurations (wave w the w-th quarter) and a wave whose
+  // 4 x CPT x passes configurations (wave w the w-th quarter) and a wave whose
   // configurations run out computes on empty rows and writes nothing.
-  const int64_t block_cfgs = int64_t(8) * a.pairs;
+  const int64_t block_cfgs = int64_t(4 * CPT) * a.passes;
   if (int64_t(blockIdx.x) * block_cfgs >= B) return;
-  const int t = r % kSeq;            // position of this lane's row
-  const bool upper = r >= kSeq;      // second configuration of the pair
+  const int c = r / R;               // configuration of this lane's row within the pass
+  const int t = P0 + r % R;          // position of this lane's row
   const int n = a.n;
   const bf16x8 *pk = a.pk + lane;
   const float *vec = a.vec;
 
-  const uint32_t upmask = upper ? 0xFFFFFFFFu : 0u;
-  // causal mask of this lane's 8 key slots (the same in every head and layer)
-  float madd[8];
+  // Score slot j (0..15) of a lane holds key row (j/4)*8 + h*4 + j%4 of the
+  // 32-row tile.  The lane's own configuration owns slots 8c..8c+7 (PLAIN),
+  // 4c..4c+3 (TRUNK / SUFFIX) or all 16 (WIDE); the masks select them.
+  const uint32_t upmask = c & 1 ? 0xFFFFFFFFu : 0u;    // PLAIN: second configuration
+  const uint32_t m_c1 = c & 2 ? 0xFFFFFFFFu : 0u;      // R = 8: configurations 2, 3
+  // R = 8: word w of the probability operand of k-step s holds this lane's
+  // configuration's keys iff s = c / 2 and w / 2 = c % 2
+  const uint32_t m_s0 = ~m_c1, m_w0 = ~upmask;
+  // causal mask of the lane's own key slots (the same in every head and layer)
+  constexpr int NM = R == 16 ? 8 : R == 8 ? 4 : 16;
+  float madd[NM];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) madd[i] = ((i / 4) * 8 + h * 4 + (i % 4)) <= t ? 0.f : -INFINITY;
+  for (int i = 0; i < NM; ++i) {
+    const int kp = R == 8 ? h * 4 + i : (i / 4) * 8 + h * 4 + (i % 4);   // key position - P0
+    madd[i] = kp <= t - P0 ? 0.f : -INFINITY;
+  }
+  // prefix entries (TRUNK / SUFFIX), read and written through one buffer resource
+  const __amdgpu_buffer_rsrc_t kvr =
+      __builtin_amdgcn_make_buffer_rsrc(a.kv, 0, int(uint32_t(a.kv_total)), 0x00020000);
+  const uint32_t kv_key_lane = uint32_t((r % 8) * 32 + h * 16);
+  const uint32_t kv_val_lane = uint32_t(r * 16 + h * 8);
 
   constexpr uint32_t kFragBytes = uint32_t(S::LAYER * 16);
   auto wres = [&](int l) {
@@ -428,12 +509,32 @@ fused_kernel(FusedArgs a) {
 
   // block chunks strided over the grid
   for (int64_t bc = blockIdx.x; bc * block_cfgs < B; bc += gridDim.x) {
-  const int64_t c_base = bc * block_cfgs + int64_t(wv) * 2 * a.pairs;
-  for (int pair = 0; pair < a.pairs; ++pair) {
-    const int64_t cfg = c_base + 2 * pair + (upper ? 1 : 0);
-    if (bc * block_cfgs + 2 * pair >= B) break;   // uniform over the block
+  const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * a.passes;
+  for (int pass = 0; pass < a.passes; ++pass) {
+    const int64_t cfg0 = c_base + CPT * pass;
+    const int64_t cfg = cfg0 + c;
+    if (bc * block_cfgs + CPT * pass >= B) break;   // uniform over the block
     const bool live = cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
+    // prefix entries: of this lane's configuration (keys, log-probability) and
+    // of the pass's four configurations (values)
+    // (byte offsets in a.kv, below 2^31)
+    uint32_t kv_cfg[4] = {0u, 0u, 0u, 0u};
+    int64_t ent_own = 0;
+    uint32_t kv_own = 0;
+    if constexpr (MODE == TRUNK || MODE == SUFFIX) {
+      int64_t ent[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        int64_t e = cfg0 + cc;                  // TRUNK: entry = index in the prefix list
+        if (MODE == SUFFIX) e = a.slot[(e < B ? a.x[e] : 0ull) & 0xFFFFull];
+        else if (e >= B) e = 0;                 // never written (see the stores)
+        ent[cc] = e;
+        kv_cfg[cc] = uint32_t(e * a.kv_bytes);
+      }
+      ent_own = c == 0 ? ent[0] : c == 1 ? ent[1] : c == 2 ? ent[2] : ent[3];
+      kv_own = uint32_t(ent_own * a.kv_bytes);
+    }
 
     // embedding: token of the previous position (BOS at position 0)
     f32x16 res[NB];
@@ -473,6 +574,30 @@ fused_kernel(FusedArgs a) {
       for (int q = 0; q < NB; ++q) res[q] += lds16(V16 + S::VBO + q * 32);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
+        // SUFFIX: the prefix's keys and values of block b, read while Q, K and
+        // V are computed.  As MFMA operands: key row r = (configuration r / 8,
+        // position r % 8) with this lane half's 8 feature slots of head e; value
+        // feature r with key slots 16 s + (i/4)*8 + 4h + i%4, i.e. positions
+        // 4h .. 4h+3 of configurations 2s (slots 0..3) and 2s + 1 (slots 4..7).
+        bf16x8 Kk[2], Vk[2];
+        if constexpr (MODE == SUFFIX) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            Kk[e] = __builtin_bit_cast(
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv_own + kv_key_lane,
+                                                              kv_key_off<NB>(l, b, e), 0));
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const i32x2 v0 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv_val_lane,
+                                                            kv_cfg[2 * s] + kv_val_off<NB>(l, b), 0));
+            const i32x2 v1 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv_val_lane,
+                                                            kv_cfg[2 * s + 1] + kv_val_off<NB>(l, b), 0));
+            const i32x4 w = {v0[0], v0[1], v1[0], v1[1]};
+            Vk[s] = __builtin_bit_cast(bf16x8, w);
+          }
+        }
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O)
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
 #pragma unroll
@@ -512,46 +637,119 @@ fused_kernel(FusedArgs a) {
         }
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
+        if constexpr (MODE == TRUNK) {
+          // keep this block's values for the suffixes: slots 0..3 / 4..7 of
+          // k-step s are configurations 2s / 2s + 1
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const i32x4 w = __builtin_bit_cast(i32x4, s == 0 ? V0 : V1);
+            if (cfg0 + 2 * s < B)
+              __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[0], w[1]}, kvr, kv_val_lane,
+                                                    kv_cfg[2 * s] + kv_val_off<NB>(l, b), 0);
+            if (cfg0 + 2 * s + 1 < B)
+              __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2], w[3]}, kvr, kv_val_lane,
+                                                    kv_cfg[2 * s + 1] + kv_val_off<NB>(l, b), 0);
+          }
+        }
         f32x16 O;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          // S[j] = score(key (j/4)*8 + h*4 + j%4, query r); the lane's own
-          // configuration holds slots j = 0..7 (lower) or 8..15 (upper)
-          const f32x16 Sc = mfma(to_bf16(Kc, e), to_bf16(Qc, e), f32x16{});
-          float p[8];
+          // S[j] = score(key (j/4)*8 + h*4 + j%4, query r)
+          const bf16x8 Qe = to_bf16(Qc, e), Ke = to_bf16(Kc, e);
+          if constexpr (MODE == TRUNK) {
+            if (live)
+              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kvr,
+                                                     kv_own + kv_key_lane, kv_key_off<NB>(l, b, e), 0);
+          }
+          const f32x16 Sc = mfma(Ke, Qe, f32x16{});
+          constexpr int NO = R / 2;                    // own keys per lane
+          constexpr int NK = MODE == SUFFIX ? 4 : 0;   // prefix keys per lane
+          float p[NO + NK];
           float mx = -INFINITY;
+          constexpr float kScale = 0.25f * 1.4426950408889634f;   // 1/sqrt(16), base 2
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            // bitwise select of the lane's half (keeps the compiler from
-            // turning it into a dynamically indexed vector)
-            const float s = __uint_as_float((__float_as_uint(Sc[8 + i]) & upmask) |
-                                            (__float_as_uint(Sc[i]) & ~upmask));
-            p[i] = fmaf(s, 0.25f * 1.4426950408889634f, madd[i]);
+          for (int i = 0; i < NO; ++i) {
+            float s;
+            if constexpr (R == 32) s = Sc[i];
+            else if constexpr (R == 16) s = bsel(Sc[i], Sc[8 + i], upmask);
+            else s = bsel(bsel(Sc[i], Sc[4 + i], upmask), bsel(Sc[8 + i], Sc[12 + i], upmask), m_c1);
+            p[i] = fmaf(s, kScale, madd[i]);
             mx = fmaxf(mx, p[i]);
+          }
+          if constexpr (MODE == SUFFIX) {
+            const f32x16 Sk = mfma(Kk[e], Qe, f32x16{});
+#pragma unroll
+            for (int i = 0; i < NK; ++i) {
+              const float s = bsel(bsel(Sk[i], Sk[4 + i], upmask), bsel(Sk[8 + i], Sk[12 + i], upmask), m_c1);
+              p[NO + i] = s * kScale;
+              mx = fmaxf(mx, p[NO + i]);
+            }
           }
           mx = pair_max(mx);
           float sum = 0.f;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
+          for (int i = 0; i < NO + NK; ++i) {
             p[i] = __builtin_amdgcn_exp2f(p[i] - mx);
             sum += p[i];
           }
           const float inv = __builtin_amdgcn_rcpf(pair_sum(sum));
 #pragma unroll
-          for (int i = 0; i < 8; ++i) p[i] *= inv;
-          // P as hi + lo; each split into the lower / upper configuration's keys
-          bf16x8 ph8, pl8;
-          pack8_hilo(p, ph8, pl8);
-          const i32x4 pp = __builtin_bit_cast(i32x4, ph8), ql = __builtin_bit_cast(i32x4, pl8);
-          const int m = int(upmask);
-          const i32x4 plo = {pp[0] & ~m, pp[1] & ~m, pp[2] & ~m, pp[3] & ~m};
-          const i32x4 phi = {pp[0] & m, pp[1] & m, pp[2] & m, pp[3] & m};
-          const i32x4 qlo = {ql[0] & ~m, ql[1] & ~m, ql[2] & ~m, ql[3] & ~m};
-          const i32x4 qhi = {ql[0] & m, ql[1] & m, ql[2] & m, ql[3] & m};
-          f32x16 Oe = mfma(V0, __builtin_bit_cast(bf16x8, plo), f32x16{});
-          Oe = mfma(V1, __builtin_bit_cast(bf16x8, phi), Oe);
-          Oe = mfma(V0, __builtin_bit_cast(bf16x8, qlo), Oe);
-          Oe = mfma(V1, __builtin_bit_cast(bf16x8, qhi), Oe);
+          for (int i = 0; i < NO + NK; ++i) p[i] *= inv;
+          // O^T = V^T P^T with P as hi + lo
+          f32x16 Oe;
+          if constexpr (R == 32) {
+            float q0[8], q1[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              q0[i] = p[i];
+              q1[i] = p[8 + i];
+            }
+            bf16x8 h0, l0, h1, l1;
+            pack8_hilo(q0, h0, l0);
+            pack8_hilo(q1, h1, l1);
+            Oe = mfma(V0, h0, f32x16{});
+            Oe = mfma(V1, h1, Oe);
+            Oe = mfma(V0, l0, Oe);
+            Oe = mfma(V1, l1, Oe);
+          } else if constexpr (R == 16) {
+            // each split into the lower / upper configuration's keys
+            float q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = p[i];
+            bf16x8 ph8, pl8;
+            pack8_hilo(q, ph8, pl8);
+            const i32x4 pp = __builtin_bit_cast(i32x4, ph8), ql = __builtin_bit_cast(i32x4, pl8);
+            const int m = int(upmask);
+            const i32x4 plo = {pp[0] & ~m, pp[1] & ~m, pp[2] & ~m, pp[3] & ~m};
+            const i32x4 phi = {pp[0] & m, pp[1] & m, pp[2] & m, pp[3] & m};
+            const i32x4 qlo = {ql[0] & ~m, ql[1] & ~m, ql[2] & ~m, ql[3] & ~m};
+            const i32x4 qhi = {ql[0] & m, ql[1] & m, ql[2] & m, ql[3] & m};
+            Oe = mfma(V0, __builtin_bit_cast(bf16x8, plo), f32x16{});
+            Oe = mfma(V1, __builtin_bit_cast(bf16x8, phi), Oe);
+            Oe = mfma(V0, __builtin_bit_cast(bf16x8, qlo), Oe);
+            Oe = mfma(V1, __builtin_bit_cast(bf16x8, qhi), Oe);
+          } else {
+            // 4 probabilities per lane, placed at slots 4 (c % 2) .. +3 of k-step c / 2
+            auto place = [&](const uint32_t (&w)[2], int s) {
+              const uint32_t ms = s == 0 ? m_s0 : m_c1;
+              const i32x4 v = {int(w[0] & ms & m_w0), int(w[1] & ms & m_w0), int(w[0] & ms & upmask),
+                               int(w[1] & ms & upmask)};
+              return __builtin_bit_cast(bf16x8, v);
+            };
+            uint32_t hw[2], lw[2];
+            pack4_hilo(p, hw, lw);
+            Oe = mfma(V0, place(hw, 0), f32x16{});
+            Oe = mfma(V1, place(hw, 1), Oe);
+            Oe = mfma(V0, place(lw, 0), Oe);
+            Oe = mfma(V1, place(lw, 1), Oe);
+            if constexpr (MODE == SUFFIX) {
+              pack4_hilo(p + NO, hw, lw);
+              Oe = mfma(Vk[0], place(hw, 0), Oe);
+              Oe = mfma(Vk[1], place(hw, 1), Oe);
+              Oe = mfma(Vk[0], place(lw, 0), Oe);
+              Oe = mfma(Vk[1], place(lw, 1), Oe);
+            }
+          }
 #pragma unroll
           for (int j = 0; j < 8; ++j) O[e * 8 + j] = Oe[e * 8 + j];
         }
@@ -679,7 +877,7 @@ fused_kernel(FusedArgs a) {
     if (t < n) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) lg[k] += svec[a.bhead + k] + svec[a.lbias + t * 4 + k];
-      if (a.cond && t == a.cond_p && h == 0 && live) {
+      if (MODE <= WIDE && a.cond && t == a.cond_p && h == 0 && live) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
       }
@@ -701,20 +899,27 @@ fused_kernel(FusedArgs a) {
         if ((allow >> k) & 1) z += expf(lg[k] - mx);
       logp = ((allow >> tk) & 1) ? lg[tk] - mx - logf(z) : -INFINITY;
     }
-    if (a.logabs) {
-      logp += __shfl_xor(logp, 1);
-      logp += __shfl_xor(logp, 2);
-      logp += __shfl_xor(logp, 4);
-      logp += __shfl_xor(logp, 8);
-      if (t == 0 && h == 0 && live) a.logabs[cfg] = 0.5 * double(logp);
+    if (MODE == TRUNK || a.logabs) {
+      // sum over the configuration's R rows
+#pragma unroll
+      for (int w = 1; w < R; w *= 2) logp += __shfl_xor(logp, w);
+      if (r % R == 0 && h == 0 && live) {
+        if constexpr (MODE == TRUNK) {
+          a.plogp[cfg] = logp;
+        } else if constexpr (MODE == SUFFIX) {
+          a.logabs[cfg] = 0.5 * double(logp + a.plogp[ent_own]);
+        } else {
+          a.logabs[cfg] = 0.5 * double(logp);
+        }
+      }
     }
   }
 
   // ---- phase MLP for the chunk's configurations (column = configuration)
-  if (a.phase) {
+  if (MODE != TRUNK && a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
     const int64_t cfg = c_base + r;
-    const bool live = r < 2 * a.pairs && cfg < B;
+    const bool live = r < CPT * a.passes && cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
     const int nx = live ? sector_of(a.sec, x).n : 0;
     bf16x8 Z[PKS];
@@ -857,11 +1062,49 @@ Layout plan(const nqs_model &m) {
 
 inline dim3 g1(int64_t n) { return dim3(unsigned(ceil_div(n, 256))); }
 
+template <int D, int MODE>
+void launch_mode(const FusedArgs &a, dim3 grid, size_t lds_bytes, hipStream_t s) {
+  if (lds_bytes > 64 * 1024)
+    HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<D, MODE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
+  hipLaunchKernelGGL((fused_kernel<D, MODE>), grid, dim3(256), lds_bytes, s, a);
+  HIP_LAUNCH_OK();
+}
+
+template <int D>
+void launch_d(int mode, const FusedArgs &a, dim3 grid, size_t lds_bytes, hipStream_t s) {
+  switch (mode) {
+    case PLAIN: launch_mode<D, PLAIN>(a, grid, lds_bytes, s); break;
+    case WIDE: launch_mode<D, WIDE>(a, grid, lds_bytes, s); break;
+    case TRUNK: launch_mode<D, TRUNK>(a, grid, lds_bytes, s); break;
+    default: launch_mode<D, SUFFIX>(a, grid, lds_bytes, s); break;
+  }
+}
+
+// prefix table of the shared evaluation: flag[k] = 1 for every 8-token prefix
+// k = x & 0xFFFF present in x
+__global__ void prefix_mark_kernel(const uint64_t *__restrict__ x, int64_t B,
+                                   int64_t *__restrict__ flag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < B) flag[x[i] & 0xFFFFull] = 1;
+}
+// list[slot[k]] = k for every flagged prefix (slot = exclusive scan of flag)
+__global__ void prefix_list_kernel(const int64_t *__restrict__ flag,
+                                   const int64_t *__restrict__ slot, uint64_t *__restrict__ list) {
+  const int k = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < (1 << 16) && flag[k]) list[slot[k]] = uint64_t(k);
+}
+
 }  // namespace
 
 bool fused_supported(const nqs_model &m) {
   return m.kind == NQS_MODEL_TRANSFORMER && (m.d == 64 || m.d == 128) && m.F == 4 * m.d &&
-         m.H * 16 == m.d && m.PH == 256 && m.n <= kSeq && m.L <= kMaxLayers;
+         m.H * 16 == m.d && m.PH == 256 && m.n <= kSeqMax && m.L <= kMaxLayers;
+}
+
+bool fused_shared_supported(const nqs_model &m) {
+  return m.precision == NQS_BF16 && fused_supported(m) && m.n > kTrunk && m.n <= 16 && !m.tagged &&
+         m.prefix_share;
 }
 
 void fused_pack(nqs_model &m, hipStream_t s) {
@@ -947,6 +1190,44 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   m.packed_valid = true;
 }
 
+namespace {
+// Passes per chunk (at most 32 configurations per wave and chunk; fewer when
+// the batch is too small to give every SIMD of the chip two waves), the grid,
+// the LDS size, the launch and its timing record.
+void launch_fused(nqs_model &m, int mode, FusedArgs &a, int64_t B, hipStream_t s,
+                  const int64_t *count, int passes, int max_blocks) {
+  const int cpt = mode == PLAIN ? 2 : mode == WIDE ? 1 : 4;
+  const int maxp = 32 / cpt;
+  const int64_t target_waves = 2048;
+  a.passes = int(std::min<int64_t>(maxp, std::max<int64_t>(1, ceil_div(B, cpt * target_waves))));
+  if (passes > 0) a.passes = std::min(passes, maxp);
+  a.count = count;
+  Layout L = plan(m);
+  a.lds_floats = int(L.a.pw1);   // every vector before the phase-MLP input table
+  // vectors, then the weight ring (three slots of d/16 fragments of 1 KiB)
+  const size_t lds_bytes = size_t(a.lds_floats) * 4 + size_t(3) * (m.d / 16) * 1024;
+  // two blocks per CU must fit the 160 KiB of LDS
+  NQS_REQUIRE(lds_bytes <= 80 * 1024, NQS_EUNSUPPORTED,
+              "fused forward: model vectors exceed the LDS budget");
+  int64_t blocks = ceil_div(B, int64_t(4 * cpt) * a.passes);   // four waves per block
+  if (max_blocks > 0) blocks = std::min<int64_t>(blocks, max_blocks);
+  NQS_REQUIRE(blocks <= int64_t(0x7FFFFFFF), NQS_EUNSUPPORTED, "fused forward: batch too large");
+  const dim3 grid = dim3(unsigned(blocks));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_timing && !count) {
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+  }
+  if (m.d == 128) launch_d<128>(mode, a, grid, lds_bytes, s);
+  else launch_d<64>(mode, a, grid, lds_bytes, s);
+  if (g_timing && !count) {
+    HIP_OK(hipEventRecord(e1, s));
+    g_records.push_back({e0, e1, B, 0.f, mode});
+  }
+}
+}  // namespace
+
 void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, double *phase,
                    double *cond_out, int cond_p, hipStream_t s, const int64_t *count,
                    FusedTile tile) {
@@ -970,44 +1251,61 @@ void fused_forward(nqs_model &m, const uint64_t *x, int64_t B, double *logabs, d
   a.logabs = logabs;
   a.phase = phase;
   a.cond = cond_out;
-  // up to 16 passes (32 configurations) per wave; fewer when the batch is too
-  // small to give every SIMD of the chip two waves
-  const int64_t target_waves = 2048;
-  a.pairs = int(std::min<int64_t>(kPairs, std::max<int64_t>(1, ceil_div(B, 2 * target_waves))));
-  if (tile.pairs > 0) a.pairs = std::min(tile.pairs, kPairs);
-  a.count = count;
-  a.lds_floats = int(L.a.pw1);   // every vector before the phase-MLP input table
-  // vectors, then the weight ring (three slots of d/16 fragments of 1 KiB)
-  const size_t lds_bytes = size_t(a.lds_floats) * 4 + size_t(3) * (m.d / 16) * 1024;
-  // two blocks per CU must fit the 160 KiB of LDS
-  NQS_REQUIRE(lds_bytes <= 80 * 1024, NQS_EUNSUPPORTED,
-              "fused forward: model vectors exceed the LDS budget");
-  if (lds_bytes > 64 * 1024) {
-    if (m.d == 128)
-      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<128>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
-    else
-      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_kernel<64>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes)));
-  }
-  int64_t blocks = ceil_div(B, int64_t(8) * a.pairs);   // four waves of 2 x pairs configurations
-  if (tile.blocks > 0) blocks = std::min<int64_t>(blocks, tile.blocks);
-  const dim3 grid = dim3(unsigned(blocks));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_timing && !count) {
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    HIP_OK(hipEventRecord(e0, s));
-  }
-  if (m.d == 128)
-    hipLaunchKernelGGL(fused_kernel<128>, grid, dim3(256), lds_bytes, s, a);
-  else
-    hipLaunchKernelGGL(fused_kernel<64>, grid, dim3(256), lds_bytes, s, a);
+  launch_fused(m, m.n > 16 ? WIDE : PLAIN, a, B, s, count, tile.pairs, tile.blocks);
+}
+
+
+void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                          double *phase, hipStream_t s) {
+  NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
+  NQS_REQUIRE(fused_shared_supported(m), NQS_EUNSUPPORTED, "shared forward: unsupported model");
+  if (B <= 0) return;
+  constexpr int64_t K = int64_t(1) << 16;      // 8-token prefixes
+  const int64_t cap = std::min(K, B);          // entries: at most one per configuration
+  const int64_t kv_bytes = int64_t(m.L) * (m.d / 32) * 1024;
+  static_assert((int64_t(1) << 16) * kMaxLayers * 4 * 1024 <= (int64_t(1) << 31),
+                "prefix entries are addressed by 32-bit offsets");
+  auto *flag = static_cast<int64_t *>(m.pf_tab.reserve(size_t(2 * K + 1) * 8));
+  int64_t *slot = flag + K;
+  auto *list = static_cast<uint64_t *>(m.pf_list.reserve(size_t(cap) * 8));
+  auto *plogp = static_cast<float *>(m.pf_logp.reserve(size_t(cap) * 4));
+  auto *kv = static_cast<uint8_t *>(m.pf_kv.reserve(size_t(cap) * size_t(kv_bytes)));
+  zero_async(flag, size_t(K) * 8, s);
+  hipLaunchKernelGGL(prefix_mark_kernel, g1(B), dim3(256), 0, s, x, B, flag);
   HIP_LAUNCH_OK();
-  if (g_timing && !count) {
-    HIP_OK(hipEventRecord(e1, s));
-    g_records.push_back({e0, e1, B, 0.f});
-  }
+  launch_exclusive_scan(flag, slot, K, s, m.pf_scan);
+  hipLaunchKernelGGL(prefix_list_kernel, g1(K), dim3(256), 0, s, flag, slot, list);
+  HIP_LAUNCH_OK();
+  int64_t n_prefix = 0;
+  HIP_OK(hipMemcpyAsync(&n_prefix, slot + K, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  NQS_REQUIRE(n_prefix >= 1 && n_prefix <= cap, NQS_EINVAL, "shared forward: prefix count");
+  Layout L = plan(m);
+  FusedArgs a = L.a;
+  a.pk = m.packed.as<bf16x8>();
+  a.vec = m.packed_vec.as<float>();
+  a.sec = m.sectors();
+  a.n = m.n;
+  a.L = m.L;
+  a.cond_p = -1;
+  a.cond = nullptr;
+  a.kv = kv;
+  a.kv_bytes = kv_bytes;
+  a.kv_total = cap * kv_bytes;
+  a.plogp = plogp;
+  a.slot = slot;
+  // positions 0..7 of every prefix (their number is on the device: slot[K])
+  a.x = list;
+  a.B = n_prefix;
+  a.logabs = nullptr;
+  a.phase = nullptr;
+  launch_fused(m, TRUNK, a, n_prefix, s, nullptr, 0, 0);
+  // positions 8..15 of every configuration
+  a.x = x;
+  a.B = B;
+  a.logabs = logabs;
+  a.phase = phase;
+  launch_fused(m, SUFFIX, a, B, s, nullptr, 0, 0);
 }
 
 bool timing_on() { return g_timing; }
@@ -1020,15 +1318,17 @@ hipEvent_t timing_begin(hipStream_t s, const int64_t *count) {
   return e0;
 }
 
-void timing_end(hipEvent_t start, hipStream_t s, int64_t configs) {
+void timing_end(hipEvent_t start, hipStream_t s, int64_t configs, int mode) {
   if (!start) return;
   hipEvent_t e1 = nullptr;
   HIP_OK(hipEventCreate(&e1));
   HIP_OK(hipEventRecord(e1, s));
-  g_records.push_back({start, e1, configs, 0.f});
+  g_records.push_back({start, e1, configs, 0.f, mode});
 }
 
-void timing_add(float ms, int64_t configs) { g_records.push_back({nullptr, nullptr, configs, ms}); }
+void timing_add(float ms, int64_t configs, int mode) {
+  g_records.push_back({nullptr, nullptr, configs, ms, mode});
+}
 
 }  // namespace nqs
 
@@ -1038,11 +1338,16 @@ extern "C" int nqs_timing_enable(int on) {
   return guarded([&] { g_timing = on != 0; });
 }
 
-extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) {
+extern "C" int nqs_timing_read_mode(int mode, double *ms, int64_t *launches, int64_t *configs) {
   return guarded([&] {
     double total = 0.0;
-    int64_t cfgs = 0;
+    int64_t cfgs = 0, nl = 0;
+    std::vector<TimingRecord> keep;
     for (const TimingRecord &r : g_records) {
+      if (mode != -2 && r.mode != mode) {
+        keep.push_back(r);
+        continue;
+      }
       float t = r.ms;
       if (r.stop) {
         HIP_OK(hipEventSynchronize(r.stop));
@@ -1050,14 +1355,17 @@ extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) 
       }
       total += t;
       cfgs += r.configs;
-    }
-    if (ms) *ms = total;
-    if (launches) *launches = int64_t(g_records.size());
-    if (configs) *configs = cfgs;
-    for (const TimingRecord &r : g_records) {
+      ++nl;
       if (r.start) (void)hipEventDestroy(r.start);
       if (r.stop) (void)hipEventDestroy(r.stop);
     }
-    g_records.clear();
+    if (ms) *ms = total;
+    if (launches) *launches = nl;
+    if (configs) *configs = cfgs;
+    g_records.swap(keep);
   });
+}
+
+extern "C" int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs) {
+  return nqs_timing_read_mode(-2, ms, launches, configs);
 }

@@ -77,6 +77,7 @@ _SIGS = {
                     C.c_int),
     "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "amp_model_set_z2": ([_vp, C.c_int, _vp, _vp], C.c_int),
+    "amp_model_set_prefix_sharing": ([_vp, C.c_int], C.c_int),
     "amp_model_set_symmetries": ([_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp], C.c_int),
     "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
                              C.POINTER(_u64), _vp], C.c_int),
@@ -93,6 +94,7 @@ _SIGS = {
     "vmc_weights_batch": ([_vp, _vp, _vp, _i64, _vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "nqs_timing_enable": ([C.c_int], C.c_int),
     "nqs_timing_read": ([C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
+    "nqs_timing_read_mode": ([C.c_int, C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -233,6 +235,11 @@ class Model:
         a = np.ascontiguousarray(np.asarray(sectors, dtype=np.int32).reshape(-1, 3).T)
         _check(lib().amp_model_set_sectors(self.handle, a.shape[1], _ptr(a[0].copy()),
                                            _ptr(a[1].copy()), _ptr(a[2].copy())))
+
+    def set_prefix_sharing(self, on):
+        """bf16 transformer batches by shared 8-token prefixes (default) or
+        configuration by configuration (``amp_model_set_prefix_sharing``)."""
+        _check(lib().amp_model_set_prefix_sharing(self.handle, 1 if on else 0))
 
     def set_z2(self, masks, targets=None):
         """Restrict the sector by Z2 symmetries (``amp_model_set_z2``); targets
@@ -507,11 +514,18 @@ def timing_enable(on=True):
     _check(lib().nqs_timing_enable(1 if on else 0))
 
 
-def timing_read():
-    """(milliseconds, launches, configurations) of the fused amplitude kernel."""
+def timing_read(mode=None):
+    """(milliseconds, launches, configurations) of the fused amplitude kernel:
+    every launch, or those of one row layout (TIMING_* below)."""
     ms, nl, nc = _dbl(), _i64(), _i64()
-    _check(lib().nqs_timing_read(C.byref(ms), C.byref(nl), C.byref(nc)))
+    if mode is None:
+        _check(lib().nqs_timing_read(C.byref(ms), C.byref(nl), C.byref(nc)))
+    else:
+        _check(lib().nqs_timing_read_mode(mode, C.byref(ms), C.byref(nl), C.byref(nc)))
     return ms.value, nl.value, nc.value
+
+
+TIMING_PLAIN, TIMING_WIDE, TIMING_TRUNK, TIMING_SUFFIX, TIMING_NADE = 0, 1, 2, 3, -1
 
 
 # ---------------------------------------------------------------- models ---

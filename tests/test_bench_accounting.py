@@ -56,3 +56,33 @@ def test_executed_mfma_count_by_hand():
 def test_valu_peak_from_unit_counts():
     # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_prefix_split_work_adds_up():
+    # positions 0..7 (once per prefix) and 8..n-1 (per configuration, with the
+    # phase MLP) make one whole evaluation
+    for n in (9, 15, 16):
+        whole = bench.flop_per_config(n, 128, 4, 512, 256)
+        assert bench.rows_flop(0, n, 128, 4, 512, 256, True) == whole
+        assert (bench.rows_flop(0, 8, 128, 4, 512, 256, False)
+                + bench.rows_flop(8, n, 128, 4, 512, 256, True)) == whole
+    # suffix of the 30-qubit model by hand: 7 positions, queries 8..14 see 9..15 keys
+    macs = 7 * 4 * (4 * 128 ** 2 + 2 * 128 * 512) + 4 * 2 * 128 * sum(range(9, 16)) \
+        + 7 * 4 * 128 + 256 * 256 + 256
+    assert bench.rows_flop(8, 15, 128, 4, 512, 256, True) == 2 * macs
+    # the VALU model of the suffix: the same per-position terms over 7 positions
+    n, d, L, H, f, ph = 15, 128, 4, 8, 512, 256
+    ln = 5 * d + 4
+    per_layer = 7 * (2 * ln + 2 * d + 13 * f) + H * sum(range(9, 16)) * 8 + H * 7 * 4
+    total = L * per_layer + 7 * d + 7 * ln + 7 * 28 + n * ph + 2 * 13 * ph + ph
+    assert bench.tf_valu_slots(n, d, L, H, f, ph, 8) == total
+
+
+def test_executed_mfma_count_shared_prefix_by_hand():
+    # suffix tile: 4 configurations x 8 positions; per head pair also the
+    # scores against the prefix's 8 keys (2) and their P V products (hi + lo
+    # P, 2 k-steps, 2 heads: 8) -> 4 * 92 + 256 = 624 MFMAs per layer
+    phase = 2 * 8 * 16 * 32768 / 32
+    assert bench.executed_flop_per_config(4, 128, 256, "suffix") == 4 * 624 * 32768 / 4 + phase
+    # trunk tile: 4 prefixes x 8 positions, the plain count, no phase MLP
+    assert bench.executed_flop_per_config(4, 128, 256, "trunk") == 4 * 584 * 32768 / 4

@@ -45,8 +45,14 @@ def sector_sample(n, na, nb, count, seed):
     (16, 8, 7, 128, 2, 0.05, 300),
     (1, 1, 0, 64, 1, 0.1, 4),           # one token: a single physical configuration
     (1, 1, 1, 64, 1, 0.1, 4),
+    (9, 4, 5, 64, 2, 0.05, 1001),       # the shortest sequence of the prefix-shared path
+    (17, 8, 8, 64, 1, 0.1, 101),        # 17..32 tokens: one configuration per 32 rows
+    (18, 9, 9, 128, 4, 0.05, 300),      # 36 spin-orbitals (NaCl's size)
+    (32, 16, 16, 64, 2, 0.05, 200),     # 64 spin-orbitals: every bit of the word
 ])
 def test_fused_forward_vs_oracle(nqs, n, na, nb, d, L, std, count):
+    """bf16 forward against the FP64 oracle; for 9..16 tokens both the
+    prefix-shared evaluation (the default) and the per-configuration one."""
     log(f"fused forward n={n} d={d} L={L}")
     params = make_transformer_params(n, na, nb, d, L, seed=7 + n, std=std, hf_bias=1.0,
                                      round_to="bf16", bias_std=0.02)
@@ -71,6 +77,66 @@ def test_fused_forward_vs_oracle(nqs, n, na, nb, d, L, std, count):
     assert e_la < 2e-2 and e_ph < 2e-2
     # the bf16 error is noise around the exact value, not a bias
     assert abs(np.mean(la.cpu().numpy() - rla)) < 5e-3
+    if 8 < n <= 16:
+        m16.set_prefix_sharing(False)
+        lu, pu = nqs.amp_forward(m16, dev(xs))
+        lu, pu = lu.cpu().numpy(), pu.cpu().numpy()
+        e_lu, e_pu = np.max(np.abs(lu - rla)), np.max(np.abs(pu - rph))
+        d_la = np.abs(lu - la.cpu().numpy())
+        log(f"  unshared: max |dlogabs| {e_lu:.2e} max |dphase| {e_pu:.2e}; shared - unshared "
+            f"logabs max {d_la.max():.2e} median {np.median(d_la):.2e}, phase max "
+            f"{np.max(np.abs(pu - ph.cpu().numpy())):.2e}")
+        assert e_lu < 2e-2 and e_pu < 2e-2
+        assert abs(np.mean(lu - rla)) < 5e-3
+        # the same bf16 operands in both; only the order of fp32 sums differs
+        # (softmax sums over the prefix's and the own keys, the log-probability
+        # sum), which moves an activation across a bf16 rounding boundary now
+        # and then: most configurations agree to fp32 rounding
+        assert np.median(d_la) < 1e-5
+        assert np.array_equal(pu, ph.cpu().numpy())   # the phase MLP is the same code
+
+
+def test_shared_prefix_edge_cases(nqs):
+    """The prefix-shared evaluation against the per-configuration one (same
+    bf16 model) on the shapes its bookkeeping has to get right: one
+    configuration; several sharing one prefix (one entry); a ragged batch whose
+    distinct prefixes span several scan tiles (more than 8192); configurations
+    outside the sector (-inf from the prefix or from the suffix); an empty
+    batch."""
+    n, na, nb, d = 12, 6, 6, 64
+    params = make_transformer_params(n, na, nb, d, 2, seed=5, std=0.05, hf_bias=0.5,
+                                     round_to="bf16", bias_std=0.02)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, 2, 4, 4 * d, 256],
+                  flatten_params(params, transformer_param_spec(n, d, 2, 4 * d, 256)), "bf16")
+    sec = Sector(n, na, nb)
+    allx = sec.enumerate()
+    rng = np.random.default_rng(3)
+    big = [int(v) for v in rng.choice(np.array(allx, dtype=np.uint64), 60_001, replace=False)]
+    hf = hf_config(n, na, nb)
+    same = [v for v in allx if v & 0xFFFF == hf & 0xFFFF][:7]
+    bad = [hf ^ (1 << 20), (hf & 0xFFFF) | (0b11 << 16), 0]   # wrong count in the suffix / prefix
+    cases = {"one": [hf], "same prefix": same, "ragged": big, "outside": bad + same[:2]}
+    for name, xs in cases.items():
+        x = dev(xs)
+        m.set_prefix_sharing(True)
+        ls, ps = nqs.amp_forward(m, x)
+        m.set_prefix_sharing(False)
+        lu, pu = nqs.amp_forward(m, x)
+        ls, ps, lu, pu = (v.cpu().numpy() for v in (ls, ps, lu, pu))
+        fin = np.isfinite(lu)
+        npre = len({v & 0xFFFF for v in xs})
+        log(f"  {name}: {len(xs)} configurations, {npre} prefixes, max |shared - unshared| "
+            f"{np.max(np.abs(ls[fin] - lu[fin])) if fin.any() else 0:.2e}")
+        assert np.array_equal(np.isfinite(ls), fin)
+        assert np.all(ls[~fin] == -np.inf)
+        assert np.all(np.abs(ls[fin] - lu[fin]) < 2e-2)
+        assert np.median(np.abs(ls[fin] - lu[fin])) < 1e-5 if fin.any() else True
+        assert np.array_equal(ps, pu)
+    assert len({v & 0xFFFF for v in big}) > 8192
+    assert not np.isfinite(nqs.amp_forward(m, dev(bad))[0].cpu().numpy()).any()
+    m.set_prefix_sharing(True)
+    la, _ = nqs.amp_forward(m, torch.zeros(0, dtype=torch.int64, device="cuda"))
+    assert la.numel() == 0
 
 
 def test_fused_outside_sector_and_empty(nqs):
@@ -143,12 +209,17 @@ def test_precision_workload_full_step_sampled_parity(nqs):
 
 
 @pytest.mark.parametrize("n,na,nb,strategy,d", [(6, 2, 2, "MU", 0), (6, 2, 2, "MUd", 1),
-                                                (16, 1, 1, "MU", 0)])
+                                                (16, 1, 1, "MU", 0), (18, 1, 1, "MU", 0)])
 def test_fused_sampler_matches_its_forward(nqs, n, na, nb, strategy, d):
     """The bf16 sampler's conditionals come from the fused kernel's conditional
     mode; its samples follow exp(2 log|psi|) of the fused forward (chi-square
     over the whole sector, 1e6 samples: 225 determinants at 12 spin-orbitals,
-    256 at 32, where all 16 positions of the kernel are tokens)."""
+    256 at 32, where all 16 positions of the kernel are tokens, 324 at 36, one
+    configuration per 32 rows).  Against the FP64 oracle's distribution: the
+    total-variation distance of the sample frequencies is at most that of the
+    bf16 distribution (normalised |psi|^2 ratios within e^(+-4 eps), eps the
+    largest log-amplitude error: at most (e^(4 eps) - 1) / 2) plus the sampling
+    noise (at most sqrt(K / (2 pi N)) in expectation; 1.5 sqrt(K / N) allowed)."""
     from scipy.stats import chi2
     dm = 64
     hf, occ = (0.5, 0.0) if n == 6 else (0.0, -1.0)
@@ -173,3 +244,14 @@ def test_fused_sampler_matches_its_forward(nqs, n, na, nb, strategy, d):
     pval = chi2.sf(stat, keep.sum() - 1)
     log(f"fused sampler {strategy}: lost {lost}, chi2 {stat:.1f} on {keep.sum() - 1} dof, p = {pval:.3f}")
     assert pval > 1e-4
+    if strategy == "MU":
+        ref = TransformerModel(params, sec, dm // 16)
+        rla = ref.amplitudes(xs)[0].detach().numpy()
+        p_or = np.exp(2 * rla)
+        eps = np.max(np.abs(la.cpu().numpy() - rla))
+        tv = 0.5 * np.sum(np.abs(obs / obs.sum() - p_or / p_or.sum()))
+        bound = 0.5 * (np.exp(4 * eps) - 1) + 1.5 * np.sqrt(len(xs) / 1_000_000)
+        log(f"  vs oracle: total variation {tv:.4f} (bound {bound:.4f}, eps {eps:.1e}, "
+            f"oracle norm {p_or.sum():.6f})")
+        assert abs(p_or.sum() - 1.0) < 1e-9
+        assert tv <= bound
