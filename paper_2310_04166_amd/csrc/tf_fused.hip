@@ -451,7 +451,19 @@ fused_kernel(FusedArgs a) {
   // 4 x CPT x passes configurations (wave w the w-th quarter) and a wave whose
   // configurations run out computes on empty rows and writes nothing.
   const int64_t block_cfgs = int64_t(4 * CPT) * a.passes;
-  if (int64_t(blockIdx.x) * block_cfgs >= B) return;
+  // Blocks are dispatched to the chip's 8 XCDs in turn (block i on XCD i % 8),
+  // each with its own L2.  When the grid has one chunk per block, the chunks
+  // of one XCD are made contiguous (neighbouring configurations share a
+  // prefix's keys and values), a bijection of the block indices.
+  int64_t bc0 = blockIdx.x;
+  {
+    const int64_t G = gridDim.x;
+    if (G * block_cfgs >= B && G >= 8) {
+      const int64_t xcd = bc0 % 8, k = bc0 / 8, q = G / 8, rem = G % 8;
+      bc0 = xcd * q + (xcd < rem ? xcd : rem) + k;
+    }
+  }
+  if (bc0 * block_cfgs >= B) return;
   const int c = r / R;               // configuration of this lane's row within the pass
   const int t = P0 + r % R;          // position of this lane's row
   const int n = a.n;
@@ -508,7 +520,7 @@ fused_kernel(FusedArgs a) {
   };
 
   // block chunks strided over the grid
-  for (int64_t bc = blockIdx.x; bc * block_cfgs < B; bc += gridDim.x) {
+  for (int64_t bc = bc0; bc * block_cfgs < B; bc += gridDim.x) {
   const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * a.passes;
   for (int pass = 0; pass < a.passes; ++pass) {
     const int64_t cfg0 = c_base + CPT * pass;

@@ -1,0 +1,54 @@
+"""The premise of the prefix-shared forward, measured on the 30-spin-orbital
+workload (ANQS product rule: the transformer is causal, so positions 0..7 of
+a configuration depend on its first 8 tokens only).  One step's distinct
+connected x' share few 8-token prefixes; the table of distinct k-token
+prefixes shows where sharing stops paying (a 14-token prefix fixes the
+configuration: the last token is forced by the electron counts).  And the
+energies of both evaluations agree with each other."""
+import numpy as np
+import pytest
+import torch
+
+from synth import flatten_params, transformer_param_spec, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_distinct_prefixes_of_one_step():
+    from paper_2310_04166_amd import nqs
+    nqs.lib()
+    cfg, h, eri, params = workload("precision")
+    spec = transformer_param_spec(15, 128, 4, 512, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, nqs.model_dims(cfg), flatten_params(params, spec), "bf16")
+    H = nqs.ham_compile(h, eri, 7, 7)
+    x, c, _ = nqs.sample_unique(m, cfg["n_samples"], 11)
+    _, xp, _, _ = nqs.connected_pairs(H, x)
+    u = torch.unique(xp)
+    print(f"unique samples {x.numel()}, pairs {xp.numel()}, distinct x' {u.numel()}", flush=True)
+    counts = {}
+    for k in range(4, 16):
+        counts[k] = torch.unique(u & ((1 << (2 * k)) - 1)).numel()
+        print(f"  {k:2d}-token prefixes: {counts[k]:9d} ({counts[k] / u.numel():.4f} of the x')",
+              flush=True)
+    assert counts[8] <= 4 ** 8 and counts[8] < 0.02 * u.numel()
+    assert counts[14] == counts[15] == u.numel()
+    # both evaluations of the step's local energies (bf16 amplitudes)
+    e_sh, s_sh, _ = nqs.local_energy(H, m, x, c)
+    m.set_prefix_sharing(False)
+    e_un, s_un, _ = nqs.local_energy(H, m, x, c)
+    s_sh, s_un = s_sh.cpu().numpy(), s_un.cpu().numpy()
+    d = np.abs(e_sh.cpu().numpy() - e_un.cpu().numpy())
+    print(f"  energy shared {s_sh[1] / s_sh[0]:.8f} unshared {s_un[1] / s_un[0]:.8f}; per-sample "
+          f"|difference| median {np.median(d):.1e} max {d.max():.1e} Ha", flush=True)
+    # The two use the same bf16 operands and differ in the order of fp32 sums
+    # only, but a configuration has ~1e5 activations rounded to bf16, so a few
+    # of them land on the other side of a rounding boundary (one bf16 ulp,
+    # 2^-9 relative): per sample the two evaluations are two draws of the
+    # bf16 error itself (against the oracle 3e-5 .. 4e-4 Ha on the
+    # highest-count samples of this model, the first-order bound 2 eps A(x)
+    # larger where A(x) is large), which average out in the energy.
+    w = c.cpu().numpy().astype(np.float64)
+    wmean = float(np.sum(w * d) / w.sum())
+    print(f"  count-weighted mean |difference| {wmean:.1e} Ha", flush=True)
+    assert abs(s_sh[1] / s_sh[0] - s_un[1] / s_un[0]) < 1e-5
+    assert np.median(d) < 1e-3 and wmean < 1e-3
