@@ -261,22 +261,27 @@ def tf_roofline(flop, slots, k_ms, executed_flop=None):
 
 
 def executed_flop_per_config(n_layers, d, ph, mode="plain"):
-    """MFMA FLOP the fused kernel issues per configuration: per 32-row tile and
-    layer, with the attention weight products taken on the hi and lo weight
-    sets, the feed-forward ones on one set, and the attention probabilities and
-    output as hi + lo pairs, in 32x32x16 MFMAs of 32768 FLOP; the phase MLP's
-    256 x 256 layer as hi + lo per 32 configurations.  A tile holds 2
-    configurations of 16 padded positions ("plain"), 4 prefixes of 8 positions
-    ("trunk", no phase MLP) or 4 configurations of 8 positions that also attend
-    to their prefix's 8 keys ("suffix": two more score and four more
-    probability-value products per head)."""
+    """MFMA FLOP the fused kernel issues per configuration (or prefix): per
+    32-row tile and layer, with the attention weight products taken on the hi
+    and lo weight sets, the feed-forward ones on one set, and the attention
+    probabilities and output as hi + lo pairs, in 32x32x16 MFMAs of 32768 FLOP;
+    the phase MLP's 256 x 256 layer as hi + lo per 32 configurations.  A tile
+    holds 2 configurations of 16 padded positions ("plain"), 4 prefixes of 8
+    positions ("trunk", no phase MLP), 4 configurations of 8 positions that also
+    attend to their prefix's 8 keys ("suffix": per head pair two more score and
+    eight more probability-value products), 8 prefixes of 4 positions that also
+    attend to the 8-token prefix ("mid": two more scores and four more
+    probability-value products, no phase MLP) or 8 configurations of 4 positions
+    that attend to both levels ("tail": four more scores, twelve more
+    probability-value products)."""
     nb, ks, fb = d // 32, d // 16, 4 * d // 32
-    extra = 2 + 8 if mode == "suffix" else 0
+    extra = {"plain": 0, "trunk": 0, "suffix": 2 + 8, "mid": 2 + 4, "tail": 4 + 12}[mode]
     per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks + extra   # QKV hi+lo, S, PV, O-proj
     per_layer = nb * per_head_pair + 2 * fb * ks                # + FFN W1, W2
     tile = n_layers * per_layer * 32768
-    phase = 0 if mode == "trunk" else 2 * (ph // 32) * (ph // 16) * 32768 / 32
-    return tile / (2 if mode == "plain" else 4) + phase
+    phase = 0 if mode in ("trunk", "mid") else 2 * (ph // 32) * (ph // 16) * 32768 / 32
+    per_tile = {"plain": 2, "trunk": 4, "suffix": 4, "mid": 8, "tail": 8}[mode]
+    return tile / per_tile + phase
 
 
 def cpu_info():
@@ -525,18 +530,18 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     gpu_ms = ev0.elapsed_time(ev1)
-    # the dominant kernel: positions 8.. of every configuration (prefix-shared
-    # evaluation), then the prefixes, then every other launch (the sampler's)
-    sfx = nqs.timing_read(nqs.TIMING_SUFFIX)
-    trk = nqs.timing_read(nqs.TIMING_TRUNK)
-    rest = nqs.timing_read()
-    shared = sfx[1] > 0
-    k_ms, k_launches, k_cfgs = sfx if shared else rest
+    # launches by row layout: the last positions of every configuration (TAIL
+    # with three levels, SUFFIX with two), the shared levels, every other
+    # launch (the sampler's, and the samples' own forward without sharing)
+    rec = {k: nqs.timing_read(getattr(nqs, "TIMING_" + k.upper()))
+           for k in ("tail", "mid", "suffix", "trunk")}
+    rec["rest"] = nqs.timing_read()
     nqs.timing_enable(False)
 
     value = total_pairs / elapsed
     nade = cfg["model"] == "nade"
     if nade:
+        k_ms, k_launches, k_cfgs = rec["rest"]
         flop, slots = nade_work(2 * cfg["n"], cfg["hidden"])
         achieved = (k_cfgs * slots) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
@@ -550,17 +555,30 @@ def main():
                     "mfma_tflops": round(k_cfgs * flop / (k_ms * 1e-3) / 1e12, 2) if k_ms else 0,
                     "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
     else:
-        n, d, nl = cfg["n"], cfg["d"], cfg["n_layers"]
-        t0 = TRUNK if shared else 0
-        slots_cfg = tf_valu_slots(n, d, nl, cfg["n_heads"], 4 * d, 256, t0)
-        flop_cfg = rows_flop(t0, n, d, nl, 4 * d, 256, True)
-        exe_cfg = executed_flop_per_config(nl, d, 256, "suffix" if shared else "plain")
+        n, d, nl, nh = cfg["n"], cfg["d"], cfg["n_layers"], cfg["n_heads"]
+        pm = n - 4
+        # rows each layout evaluates: (first position, last + 1, phase MLP, executed kind)
+        rows = {"tail": (pm, n, True, "tail"), "mid": (TRUNK, pm, False, "mid"),
+                "suffix": (TRUNK, n, True, "suffix"), "trunk": (0, TRUNK, False, "trunk"),
+                "rest": (0, n, True, "plain")}
+        names = {"tail": "fused_kernel<128, TAIL> (bf16 amplitude network, the last four "
+                         "positions of each configuration)",
+                 "mid": f"fused_kernel<128, MID> (positions 8..{pm - 1} once per distinct "
+                        f"{pm}-token prefix)",
+                 "suffix": "fused_kernel<128, SUFFIX> (positions 8..15 of each configuration)",
+                 "trunk": "fused_kernel<128, TRUNK> (positions 0..7 once per distinct "
+                          "8-token prefix)",
+                 "rest": "fused_kernel<128, PLAIN> (bf16 amplitude network)"}
+        dom = max(("tail", "suffix", "rest"), key=lambda k: rec[k][0])
+        k_ms, k_launches, k_cfgs = rec[dom]
+        t0, t1, ph, kind = rows[dom]
+        slots_cfg = tf_valu_slots(t1, d, nl, nh, 4 * d, 256, t0)
+        flop_cfg = rows_flop(t0, t1, d, nl, 4 * d, 256, ph)
+        exe_cfg = executed_flop_per_config(nl, d, 256, kind)
         roofline = tf_roofline(k_cfgs * flop_cfg, k_cfgs * slots_cfg, k_ms, k_cfgs * exe_cfg)
         roofline.update({"traffic": fused_traffic() if args.workload == "precision" else None,
                          "traffic_unit": "bytes per launch",
-                         "kernel": ("fused_kernel<128, SUFFIX> (bf16 amplitude network, "
-                                    "positions 8..15 of each configuration)") if shared else
-                                   "fused_kernel<128, PLAIN> (bf16 amplitude network)",
+                         "kernel": names[dom],
                          "avg_launch_ms": round(k_ms / max(k_launches, 1), 3),
                          "launches": k_launches, "configs": k_cfgs,
                          "flop_per_config": flop_cfg,
@@ -568,17 +586,20 @@ def main():
                          "executed_flop_per_config": int(exe_cfg),
                          "valu_slots_per_config": slots_cfg,
                          "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)})
-        if shared:
-            tflop = rows_flop(0, TRUNK, d, nl, 4 * d, 256, False)
-            roofline["prefixes"] = {
-                "kernel": "fused_kernel<128, TRUNK> (positions 0..7 once per distinct "
-                          "8-token prefix)",
-                "launches": trk[1], "prefixes": trk[2], "ms": round(trk[0], 3),
-                "flop_per_prefix": tflop,
-                "mfma_frac": round(trk[2] * tflop / max(trk[0], 1e-9) / 1e9 / BF16_PEAK_TFLOPS, 4),
-                "share_of_steps": round(trk[0] / max(gpu_ms, 1e-9), 4)}
-            roofline["other_fused"] = {"launches": rest[1], "configs": rest[2],
-                                       "ms": round(rest[0], 3)}
+        others = {}
+        for k in ("mid", "trunk", "suffix", "tail", "rest"):
+            ms, nlaunch, cfgs = rec[k]
+            if k == dom or nlaunch == 0:
+                continue
+            t0, t1, ph, kind = rows[k]
+            f = rows_flop(t0, t1, d, nl, 4 * d, 256, ph)
+            others[k] = {"kernel": names[k], "launches": nlaunch, "items": cfgs,
+                         "ms": round(ms, 3), "flop_per_item": f,
+                         "mfma_frac": round(cfgs * f / max(ms, 1e-9) / 1e9 / BF16_PEAK_TFLOPS, 4),
+                         "executed_mfma_frac": round(cfgs * executed_flop_per_config(
+                             nl, d, 256, kind) / max(ms, 1e-9) / 1e9 / BF16_PEAK_TFLOPS, 4),
+                         "share_of_steps": round(ms / max(gpu_ms, 1e-9), 4)}
+        roofline["other_launches"] = others
 
     cpu = None
     if not args.no_cpu and precision:

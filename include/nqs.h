@@ -262,8 +262,11 @@ int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks, const int32
  * 0..6).  Shared: the distinct 8-token prefixes of a batch are evaluated once
  * (positions 0..7; keys and values of every layer kept in a model-owned
  * buffer of up to 65,536 entries of L * d * 32 bytes), then positions 8..15 of
- * every configuration attend to its prefix's keys and values.  Used by
- * amp_forward and local_energy (the sampler's conditionals are unaffected).
+ * every configuration attend to its prefix's keys and values (amp_forward).
+ * local_energy, whose distinct x' it sorts by prefix, shares a second level
+ * for 13..16 tokens: positions 8 .. n-5 once per distinct (n-4)-token prefix
+ * (entries of L * d * 16 bytes, in slices of at most 2 GiB), the last four
+ * positions per configuration.  The sampler's conditionals are unaffected.
  * Results agree with the unshared evaluation up to the order of fp32 sums.
  * Errors: NQS_EINVAL (null handle).
  */
@@ -520,8 +523,10 @@ int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs);
  * removed, the others kept): mode 0 = transformer, up to 16 tokens (2
  * configurations x 16 positions per 32 rows); 1 = 17..32 tokens; 2 = shared
  * prefixes (positions 0..7 once per distinct 8-token prefix); 3 = their
- * suffixes (positions 8..15 per configuration); -1 = the per-qubit ansatz;
- * -2 = every record (nqs_timing_read).
+ * suffixes (positions 8..15 per configuration); 4 = the second shared level
+ * (positions 8 .. n-5 once per distinct (n-4)-token prefix); 5 = the last four
+ * positions per configuration; -1 = the per-qubit ansatz; -2 = every record
+ * (nqs_timing_read).
  */
 int nqs_timing_read_mode(int mode, double *ms, int64_t *launches, int64_t *configs);
 

@@ -24,7 +24,7 @@ void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const 
                        const double *la_p, const double *ph_p, const double *la_x,
                        const double *ph_x, const double *hdiag, double *eloc, hipStream_t s);
 // defined in dedupe.hip
-int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int rot, uint64_t *keys_sorted,
+int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *keys_sorted,
                      uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
                      uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s);
 void launch_reduce(const double *eloc, const uint64_t *counts, int64_t n, double *sums,
@@ -691,13 +691,15 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
       while (i1 < n && off_h[i1 + 1] - off_h[i0] <= slice) ++i1;
       const int64_t np = off_h[i1] - off_h[i0];
       launch_emit_pairs(*H, x + i0, i1 - i0, off + i0, xp, hv, nullptr, hdiag + i0, 0, s);
-      // grouped by 8-token prefix for the prefix-shared forward
-      const int rot = m->precision == NQS_BF16 && fused_shared_supported(*m) ? 16 : 0;
-      const int64_t nu = dedupe_pairs(xp, np, H->N, rot, keys, vin, vsort, head, run, ukeys, uid,
+      // grouped by the prefixes of the prefix-shared forward
+      const int levels = fused_shared_levels(*m);
+      const int pm = levels == 3 ? 2 * (m->n - 4) : levels == 2 ? 16 : 0;
+      const int64_t nu = dedupe_pairs(xp, np, H->N, pm, keys, vin, vsort, head, run, ukeys, uid,
                                       H->w_tmp, s);
       H->last_distinct += nu;
       if (nu > 0) {
-        if (m->precision == NQS_BF16) bf16_forward(*m, ukeys, nu, la, ph, s);
+        if (levels == 3) fused_forward_shared3(*m, ukeys, nu, la, ph, s);
+        else if (m->precision == NQS_BF16) bf16_forward(*m, ukeys, nu, la, ph, s);
         else model_forward(*m, ukeys, nu, la, ph, nullptr, s);
       }
       launch_accumulate(i1 - i0, off + i0, hv, np > 0 ? uid : nullptr, la, ph, lax + i0,

@@ -7,10 +7,11 @@
 // a head flag marks the first of each run of equal keys; an inclusive scan of
 // the flags numbers the runs; run heads write the distinct keys in ascending
 // order and every pair learns its run number through the sorted pair index.
-// Optionally the low `rot` bits are made the most significant before sorting
-// (and restored in the output), so that the distinct x' come out grouped by
-// their first rot / 2 tokens (the prefix-shared forward reads one prefix's
-// keys and values for consecutive configurations).
+// Optionally (pm >= 16) the bits are reordered before sorting - bits 0..15
+// most significant, then bits 16 .. pm-1, then the rest - and restored in the
+// output, so that the distinct x' come out grouped by their first 8 tokens and
+// within those by their first pm / 2 tokens (the prefix-shared forward reads
+// one prefix's keys and values for consecutive configurations).
 #include <algorithm>
 
 #include <hipcub/hipcub.hpp>
@@ -25,13 +26,18 @@ __global__ void iota_kernel(uint32_t *v, int64_t n) {
   if (i < n) v[i] = uint32_t(i);
 }
 
-// x' -> x' rotated right by rot bits within key_bits bits (in place)
-__global__ void rotate_kernel(uint64_t *__restrict__ k, int64_t n, int key_bits, int rot) {
+__host__ __device__ inline uint64_t low_bits(int b) { return b >= 64 ? ~0ull : (1ull << b) - 1; }
+// x' -> sort key (fields [0,16), [16,pm), [pm,N) to [N-16,N), [N-pm,N-16), [0,N-pm))
+__device__ inline uint64_t prefix_key(uint64_t v, int N, int pm) {
+  return ((v & 0xFFFFull) << (N - 16)) | (((v >> 16) & low_bits(pm - 16)) << (N - pm)) | (v >> pm);
+}
+__device__ inline uint64_t prefix_key_inverse(uint64_t k, int N, int pm) {
+  return (k >> (N - 16)) | (((k >> (N - pm)) & low_bits(pm - 16)) << 16) |
+         ((k & low_bits(N - pm)) << pm);
+}
+__global__ void prefix_key_kernel(uint64_t *__restrict__ k, int64_t n, int key_bits, int pm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const uint64_t v = k[i];
-    k[i] = (v >> rot) | ((v & ((1ull << rot) - 1)) << (key_bits - rot));
-  }
+  if (i < n) k[i] = prefix_key(k[i], key_bits, pm);
 }
 
 __global__ void head_kernel(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ head) {
@@ -41,16 +47,12 @@ __global__ void head_kernel(const uint64_t *__restrict__ keys, int64_t n, uint32
 
 __global__ void scatter_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
                                const uint32_t *__restrict__ head, const uint32_t *__restrict__ run,
-                               int64_t n, int key_bits, int rot, uint64_t *__restrict__ ukeys,
+                               int64_t n, int key_bits, int pm, uint64_t *__restrict__ ukeys,
                                uint32_t *__restrict__ pair_uid) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t id = run[i] - 1u;
-  if (head[i]) {
-    const uint64_t k = keys[i];
-    ukeys[id] = rot == 0 ? k
-                         : ((k >> (key_bits - rot)) | ((k & ((1ull << (key_bits - rot)) - 1)) << rot));
-  }
+  if (head[i]) ukeys[id] = pm == 0 ? keys[i] : prefix_key_inverse(keys[i], key_bits, pm);
   pair_uid[vals[i]] = id;
 }
 
@@ -59,18 +61,18 @@ inline dim3 g1(int64_t n) { return dim3(unsigned(ceil_div(n, 256))); }
 }  // namespace
 
 // Returns the number of distinct keys U; ukeys[0..U) ascending (in the
-// rotated order when rot > 0: then xp is rotated in place), pair_uid[p] =
+// reordered key when pm > 0: then xp is reordered in place), pair_uid[p] =
 // index of xp[p] in ukeys.  All buffers are caller-provided workspaces sized
 // for n pairs; tmp is grown as needed.
-int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int rot, uint64_t *keys_sorted,
+int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *keys_sorted,
                      uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
                      uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s) {
   if (n <= 0) return 0;
   NQS_REQUIRE(n < (int64_t(1) << 31), NQS_EUNSUPPORTED, "dedupe: slice too large");
-  NQS_REQUIRE(rot == 0 || (rot > 0 && rot < key_bits), NQS_EINVAL, "dedupe: rotation");
+  NQS_REQUIRE(pm == 0 || (pm >= 16 && pm < key_bits), NQS_EINVAL, "dedupe: prefix fields");
   const int ni = int(n);
-  if (rot > 0) {
-    hipLaunchKernelGGL(rotate_kernel, g1(n), dim3(256), 0, s, xp, n, key_bits, rot);
+  if (pm > 0) {
+    hipLaunchKernelGGL(prefix_key_kernel, g1(n), dim3(256), 0, s, xp, n, key_bits, pm);
     HIP_LAUNCH_OK();
   }
   hipLaunchKernelGGL(iota_kernel, g1(n), dim3(256), 0, s, vals_in, n);
@@ -86,7 +88,7 @@ int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int rot, uint64_t *k
   HIP_LAUNCH_OK();
   HIP_OK(hipcub::DeviceScan::InclusiveSum(t, scan_bytes, head, run, ni, s));
   hipLaunchKernelGGL(scatter_kernel, g1(n), dim3(256), 0, s, keys_sorted, vals_sorted, head, run,
-                     n, key_bits, rot, ukeys, pair_uid);
+                     n, key_bits, pm, ukeys, pair_uid);
   HIP_LAUNCH_OK();
   uint32_t u = 0;
   HIP_OK(hipMemcpyAsync(&u, run + (n - 1), 4, hipMemcpyDeviceToHost, s));

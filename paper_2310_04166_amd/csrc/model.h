@@ -98,6 +98,7 @@ struct nqs_model {
   nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
   int prefix_share = 1;               // bf16 transformer: prefix-shared evaluation of batches
   nqs::DevBuf pf_tab, pf_list, pf_logp, pf_kv, pf_scan;  // its prefix table, keys and values
+  nqs::DevBuf pf3_ws, pf3_logp, pf3_kv;  // three levels: bookkeeping, middle-level entries
 
   bool fp64() const { return precision == NQS_FP64; }
   nqs::Sectors sectors() const {
@@ -172,6 +173,13 @@ bool fused_supported(const nqs_model &m);
 bool fused_shared_supported(const nqs_model &m);
 void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
                           double *phase, hipStream_t s);
+// 2 or 3 (13..16 tokens) levels of the shared forward, 0 if it does not apply.
+// Three levels: positions 0..7 per 8-token prefix, 8 .. n-5 per (n-4)-token
+// prefix, the last four per configuration; x must be sorted by those prefixes
+// (dedupe_pairs with pm = 2 (n - 4) bits).
+int fused_shared_levels(const nqs_model &m);
+void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                           double *phase, hipStream_t s);
 // explicit psi over a basis (table.hip): install the basis (host, ascending),
 // rebuild the prefix sums of |psi|^2 from the master parameters, forward,
 // conditional logits of token p for the sampler, backward into double acc[2M]

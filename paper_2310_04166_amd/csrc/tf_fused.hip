@@ -71,6 +71,8 @@ std::vector<TimingRecord> g_records;
 constexpr int kMaxLayers = 8;
 constexpr int kSeqMax = 32;       // longest sequence (tokens)
 constexpr int kTrunk = 8;         // positions of a shared prefix (TRUNK / SUFFIX)
+// bytes of middle-level entries held at once (a slice; addressed by 32-bit offsets)
+constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 
 // Row layouts of a wave's 32 rows (R rows per configuration, 32 / R
 // configurations per pass):
@@ -85,12 +87,20 @@ constexpr int kTrunk = 8;         // positions of a shared prefix (TRUNK / SUFFI
 // states, keys and values are the same for every configuration with the same
 // first 8 tokens; distinct x' of one step share few such prefixes (at most
 // 4^8), so TRUNK + SUFFIX do about half the work of PLAIN per configuration.
-enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3 };
+//   MID     R = 4:  positions 8..11 of 8 distinct 12-token prefixes (all with
+//                   one 8-token prefix), attending to the 8-token prefix's keys
+//                   and values; stores its own keys and values and the
+//                   log-probability of tokens 8..11 per 12-token prefix;
+//   TAIL    R = 4:  positions 12..15 of 8 configurations (one 8-token prefix),
+//                   attending to both stored levels.
+// MID / TAIL take their items through an index list (a.src; -1 = padding)
+// in which every 8-token prefix starts a new pass.
+enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5 };
 template <int MODE>
 struct Rows {
-  static constexpr int R = MODE == PLAIN ? 16 : MODE == WIDE ? 32 : 8;
+  static constexpr int R = MODE == PLAIN ? 16 : MODE == WIDE ? 32 : MODE <= SUFFIX ? 8 : 4;
   static constexpr int CPT = 32 / R;            // configurations per pass
-  static constexpr int P0 = MODE == SUFFIX ? kTrunk : 0;   // first position
+  static constexpr int P0 = MODE == SUFFIX || MODE == MID ? kTrunk : MODE == TAIL ? 12 : 0;
   static constexpr int MAXP = 32 / CPT;         // passes per chunk of 32 configurations
 };
 // Fragment sets (1 = hi, 2 = hi and lo) of the attention matrices (Q, K, V,
@@ -134,6 +144,16 @@ struct FusedArgs {
   int64_t kv_bytes, kv_total;       // bytes per entry, of the buffer (<= 2^31)
   float *plogp;
   const int64_t *slot;
+  // MID / TAIL: item -> configuration (-1 = padding); the 8- and 12-token
+  // prefix entries of configuration i are pre8[i + 1] - 1 and pre12[i + 1] - 1
+  // (inclusive counts of the prefixes' first occurrences in x); the 12-token
+  // prefix entries (kv2_bytes each) hold keys and values of positions 8..11
+  const int64_t *src, *pre8, *pre12;
+  uint8_t *kv2;
+  int64_t kv2_bytes, kv2_total;
+  int64_t j0;                       // first 12-token prefix entry held in kv2 (a slice)
+  float *plogp2;
+  int pm;                           // MID covers positions 8 .. pm - 1, TAIL pm .. pm + 3
 };
 
 // Byte offsets inside a prefix entry, layer l (NB blocks of 32 features):
@@ -150,6 +170,17 @@ __device__ inline uint32_t kv_key_off(int l, int b, int e) {
 template <int NB>
 __device__ inline uint32_t kv_val_off(int l, int b) {
   return uint32_t(l * NB * 1024 + NB * 512 + b * 512);
+}
+// 12-token prefix entries (positions 8..11), layer l: key (block b, head e,
+// position t < 4, lane half h) at mk_off + 32 t + 16 h, 16 B; value (block b,
+// feature f) at mv_off + 8 f, 8 B = positions 0..3.
+template <int NB>
+__device__ inline uint32_t mk_off(int l, int b, int e) {
+  return uint32_t(l * NB * 512 + b * 256 + e * 128);
+}
+template <int NB>
+__device__ inline uint32_t mv_off(int l, int b) {
+  return uint32_t(l * NB * 512 + NB * 256 + b * 256);
 }
 
 __device__ inline bf16x8 to_bf16(const f32x16 &c, int half) {
@@ -465,32 +496,45 @@ fused_kernel(FusedArgs a) {
   }
   if (bc0 * block_cfgs >= B) return;
   const int c = r / R;               // configuration of this lane's row within the pass
-  const int t = P0 + r % R;          // position of this lane's row
+  const int t = (MODE == TAIL ? a.pm : P0) + r % R;   // position of this lane's row
   const int n = a.n;
   const bf16x8 *pk = a.pk + lane;
   const float *vec = a.vec;
 
   // Score slot j (0..15) of a lane holds key row (j/4)*8 + h*4 + j%4 of the
   // 32-row tile.  The lane's own configuration owns slots 8c..8c+7 (PLAIN),
-  // 4c..4c+3 (TRUNK / SUFFIX) or all 16 (WIDE); the masks select them.
+  // 4c..4c+3 (TRUNK / SUFFIX), all 16 (WIDE), or, with R = 4, slots
+  // 4(c/2)..4(c/2)+3 of the lane half h = c % 2 only; the masks select them.
   const uint32_t upmask = c & 1 ? 0xFFFFFFFFu : 0u;    // PLAIN: second configuration
   const uint32_t m_c1 = c & 2 ? 0xFFFFFFFFu : 0u;      // R = 8: configurations 2, 3
+  const uint32_t m_c2 = c & 4 ? 0xFFFFFFFFu : 0u;      // R = 4: configurations 4..7
   // R = 8: word w of the probability operand of k-step s holds this lane's
   // configuration's keys iff s = c / 2 and w / 2 = c % 2
   const uint32_t m_s0 = ~m_c1, m_w0 = ~upmask;
+  // R = 4: this lane half holds the configuration's own keys (key rows 4c..4c+3)
+  const bool own_half = R == 4 && h == (c & 1);
+  const uint32_t m_half = own_half ? 0xFFFFFFFFu : 0u;
   // causal mask of the lane's own key slots (the same in every head and layer)
-  constexpr int NM = R == 16 ? 8 : R == 8 ? 4 : 16;
+  constexpr int NM = R == 16 ? 8 : R == 8 || R == 4 ? 4 : 16;
   float madd[NM];
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
-    const int kp = R == 8 ? h * 4 + i : (i / 4) * 8 + h * 4 + (i % 4);   // key position - P0
-    madd[i] = kp <= t - P0 ? 0.f : -INFINITY;
+    const int kp = R == 4 ? i : R == 8 ? h * 4 + i : (i / 4) * 8 + h * 4 + (i % 4);   // key position - P0
+    madd[i] = kp <= r % R && (R != 4 || own_half) ? 0.f : -INFINITY;
   }
-  // prefix entries (TRUNK / SUFFIX), read and written through one buffer resource
+  // TAIL: the middle level's keys (positions 8 + i, those below pm)
+  float madd_mid[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) madd_mid[i] = own_half && 8 + i < a.pm ? 0.f : -INFINITY;
+  // prefix entries (TRUNK .. TAIL), read and written through buffer resources
   const __amdgpu_buffer_rsrc_t kvr =
       __builtin_amdgcn_make_buffer_rsrc(a.kv, 0, int(uint32_t(a.kv_total)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t kv2r =
+      __builtin_amdgcn_make_buffer_rsrc(a.kv2, 0, int(uint32_t(a.kv2_total)), 0x00020000);
   const uint32_t kv_key_lane = uint32_t((r % 8) * 32 + h * 16);
   const uint32_t kv_val_lane = uint32_t(r * 16 + h * 8);
+  const uint32_t mk_lane = uint32_t((r % 4) * 32 + h * 16);
+  const uint32_t mv_lane = uint32_t(r * 8);
 
   constexpr uint32_t kFragBytes = uint32_t(S::LAYER * 16);
   auto wres = [&](int l) {
@@ -524,9 +568,11 @@ fused_kernel(FusedArgs a) {
   const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * a.passes;
   for (int pass = 0; pass < a.passes; ++pass) {
     const int64_t cfg0 = c_base + CPT * pass;
-    const int64_t cfg = cfg0 + c;
     if (bc * block_cfgs + CPT * pass >= B) break;   // uniform over the block
-    const bool live = cfg < B;
+    // MID / TAIL: item cfg0 + c stands for configuration src (-1: padding)
+    const int64_t src = MODE >= MID ? (cfg0 + c < B ? a.src[cfg0 + c] : -1) : cfg0 + c;
+    const int64_t cfg = MODE >= MID ? src : cfg0 + c;
+    const bool live = MODE >= MID ? src >= 0 : cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
     // prefix entries: of this lane's configuration (keys, log-probability) and
     // of the pass's four configurations (values)
@@ -547,6 +593,30 @@ fused_kernel(FusedArgs a) {
       ent_own = c == 0 ? ent[0] : c == 1 ? ent[1] : c == 2 ? ent[2] : ent[3];
       kv_own = uint32_t(ent_own * a.kv_bytes);
     }
+    // MID / TAIL: the pass's one 8-token prefix entry (its first item is never
+    // padding), the lane's 12-token prefix entry, and TAIL's value sources:
+    // the entries of configurations 4s + h (slots 0..3) and 4s + 2 + h (4..7)
+    // (the pass's eight entries are wave-uniform: scalar registers; a lane picks
+    // its two with h)
+    int64_t ent8 = 0, ent12 = 0;
+    uint32_t kv8_off = 0, mid_own = 0, mid_e[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t mid_live = 0;             // bit k: item k of the pass is not padding
+    if constexpr (MODE >= MID) {
+      ent8 = a.pre8[a.src[cfg0] + 1] - 1;
+      kv8_off = uint32_t(ent8 * a.kv_bytes);
+      ent12 = live ? a.pre12[src + 1] - 1 : a.j0;
+      mid_own = uint32_t((ent12 - a.j0) * a.kv2_bytes);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int64_t it = cfg0 + k;
+        const int64_t sc = it < B ? a.src[it] : -1;
+        mid_live |= sc >= 0 ? (1u << k) : 0u;
+        mid_e[k] = uint32_t((sc >= 0 ? a.pre12[sc + 1] - 1 - a.j0 : 0) * a.kv2_bytes);
+      }
+    }
+    // entry of item 4s + 2k + h (the values of slots 4k .. 4k+3 of k-step s)
+    auto mid_v = [&](int s2, int k2) { return h ? mid_e[4 * s2 + 2 * k2 + 1] : mid_e[4 * s2 + 2 * k2]; };
+    auto mid_ok = [&](int s2, int k2) { return ((mid_live >> (4 * s2 + 2 * k2 + h)) & 1u) != 0u; };
 
     // embedding: token of the previous position (BOS at position 0)
     f32x16 res[NB];
@@ -610,6 +680,14 @@ fused_kernel(FusedArgs a) {
             Vk[s] = __builtin_bit_cast(bf16x8, w);
           }
         }
+        // MID / TAIL: the 8-token prefix's keys (key row r = position r % 8;
+        // rows 8..31 repeat them and are never selected) and values (slots 0..3
+        // of k-step 0 = positions 4h .. 4h+3, the rest zero); TAIL also the
+        // 12-token prefixes' keys (key row r = configuration r / 4, position
+        // r % 4) and values (as the own values: slots 0..3 of k-step s from
+        // configuration 4s + h, slots 4..7 from 4s + 2 + h)
+        // (keys here, values after the V projection, to keep registers free)
+        bf16x8 Vt, Vm[2];
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O)
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
 #pragma unroll
@@ -648,6 +726,24 @@ fused_kernel(FusedArgs a) {
           for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
         }
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
+        if constexpr (MODE >= MID) {
+          const i32x2 v = __builtin_bit_cast(
+              i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8_off + kv_val_lane,
+                                                          kv_val_off<NB>(l, b), 0));
+          Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], 0, 0});
+        }
+        if constexpr (MODE == TAIL) {
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const i32x2 v0 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 0) + mv_lane,
+                                                            mv_off<NB>(l, b), 0));
+            const i32x2 v1 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 1) + mv_lane,
+                                                            mv_off<NB>(l, b), 0));
+            Vm[s] = __builtin_bit_cast(bf16x8, i32x4{v0[0], v0[1], v1[0], v1[1]});
+          }
+        }
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
         if constexpr (MODE == TRUNK) {
           // keep this block's values for the suffixes: slots 0..3 / 4..7 of
@@ -663,6 +759,19 @@ fused_kernel(FusedArgs a) {
                                                     kv_cfg[2 * s + 1] + kv_val_off<NB>(l, b), 0);
           }
         }
+        if constexpr (MODE == MID) {
+          // keep this block's values for the configurations: slots 0..3 / 4..7
+          // of k-step s are positions 0..3 of items 4s + h / 4s + 2 + h
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const i32x4 w = __builtin_bit_cast(i32x4, s == 0 ? V0 : V1);
+#pragma unroll
+            for (int k2 = 0; k2 < 2; ++k2)
+              if (mid_ok(s, k2))
+                __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2 * k2], w[2 * k2 + 1]}, kv2r,
+                                                      mid_v(s, k2) + mv_lane, mv_off<NB>(l, b), 0);
+          }
+        }
         f32x16 O;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -673,9 +782,16 @@ fused_kernel(FusedArgs a) {
               __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kvr,
                                                      kv_own + kv_key_lane, kv_key_off<NB>(l, b, e), 0);
           }
+          if constexpr (MODE == MID) {
+            if (live)
+              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kv2r,
+                                                     mid_own + mk_lane, mk_off<NB>(l, b, e), 0);
+          }
           const f32x16 Sc = mfma(Ke, Qe, f32x16{});
-          constexpr int NO = R / 2;                    // own keys per lane
-          constexpr int NK = MODE == SUFFIX ? 4 : 0;   // prefix keys per lane
+          constexpr int NO = R == 4 ? 4 : R / 2;       // own keys per lane
+          // prefix keys per lane: SUFFIX 4 of the 8-token prefix; MID those 4;
+          // TAIL also 4 of the 12-token prefix
+          constexpr int NK = MODE == SUFFIX || MODE == MID ? 4 : MODE == TAIL ? 8 : 0;
           float p[NO + NK];
           float mx = -INFINITY;
           constexpr float kScale = 0.25f * 1.4426950408889634f;   // 1/sqrt(16), base 2
@@ -684,7 +800,10 @@ fused_kernel(FusedArgs a) {
             float s;
             if constexpr (R == 32) s = Sc[i];
             else if constexpr (R == 16) s = bsel(Sc[i], Sc[8 + i], upmask);
-            else s = bsel(bsel(Sc[i], Sc[4 + i], upmask), bsel(Sc[8 + i], Sc[12 + i], upmask), m_c1);
+            else if constexpr (R == 8)
+              s = bsel(bsel(Sc[i], Sc[4 + i], upmask), bsel(Sc[8 + i], Sc[12 + i], upmask), m_c1);
+            else   // R = 4: slot group c / 2
+              s = bsel(bsel(Sc[i], Sc[4 + i], m_c1), bsel(Sc[8 + i], Sc[12 + i], m_c1), m_c2);
             p[i] = fmaf(s, kScale, madd[i]);
             mx = fmaxf(mx, p[i]);
           }
@@ -695,6 +814,32 @@ fused_kernel(FusedArgs a) {
               const float s = bsel(bsel(Sk[i], Sk[4 + i], upmask), bsel(Sk[8 + i], Sk[12 + i], upmask), m_c1);
               p[NO + i] = s * kScale;
               mx = fmaxf(mx, p[NO + i]);
+            }
+          }
+          if constexpr (MODE >= MID) {
+            __builtin_amdgcn_sched_barrier(0);
+            // the 8-token prefix's keys of this lane half: positions 4h + i in slots 0..3
+            const bf16x8 Kte = __builtin_bit_cast(
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv8_off + kv_key_lane,
+                                                              kv_key_off<NB>(l, b, e), 0));
+            const f32x16 St = mfma(Kte, Qe, f32x16{});
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              p[NO + i] = St[i] * kScale;
+              mx = fmaxf(mx, p[NO + i]);
+            }
+          }
+          if constexpr (MODE == TAIL) {
+            __builtin_amdgcn_sched_barrier(0);
+            const bf16x8 Kme = __builtin_bit_cast(
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kv2r, mid_own + mk_lane,
+                                                              mk_off<NB>(l, b, e), 0));
+            const f32x16 Sm = mfma(Kme, Qe, f32x16{});
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float s = bsel(bsel(Sm[i], Sm[4 + i], m_c1), bsel(Sm[8 + i], Sm[12 + i], m_c1), m_c2);
+              p[NO + 4 + i] = fmaf(s, kScale, madd_mid[i]);
+              mx = fmaxf(mx, p[NO + 4 + i]);
             }
           }
           mx = pair_max(mx);
@@ -740,6 +885,32 @@ fused_kernel(FusedArgs a) {
             Oe = mfma(V1, __builtin_bit_cast(bf16x8, phi), Oe);
             Oe = mfma(V0, __builtin_bit_cast(bf16x8, qlo), Oe);
             Oe = mfma(V1, __builtin_bit_cast(bf16x8, qhi), Oe);
+          } else if constexpr (R == 4) {
+            // own (and 12-token prefix) keys: 4 probabilities in the lane half
+            // h = c % 2 at slots 4 ((c / 2) % 2) .. +3 of k-step c / 4; the
+            // 8-token prefix's keys: slots 0..3 of k-step 0 in both halves
+            auto place = [&](const uint32_t (&w)[2], int s) {
+              const uint32_t ms = (s == 0 ? ~m_c2 : m_c2) & m_half;
+              const i32x4 v = {int(w[0] & ms & ~m_c1), int(w[1] & ms & ~m_c1), int(w[0] & ms & m_c1),
+                               int(w[1] & ms & m_c1)};
+              return __builtin_bit_cast(bf16x8, v);
+            };
+            uint32_t hw[2], lw[2];
+            pack4_hilo(p, hw, lw);
+            Oe = mfma(V0, place(hw, 0), f32x16{});
+            Oe = mfma(V1, place(hw, 1), Oe);
+            Oe = mfma(V0, place(lw, 0), Oe);
+            Oe = mfma(V1, place(lw, 1), Oe);
+            pack4_hilo(p + NO, hw, lw);
+            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(hw[0]), int(hw[1]), 0, 0}), Oe);
+            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(lw[0]), int(lw[1]), 0, 0}), Oe);
+            if constexpr (MODE == TAIL) {
+              pack4_hilo(p + NO + 4, hw, lw);
+              Oe = mfma(Vm[0], place(hw, 0), Oe);
+              Oe = mfma(Vm[1], place(hw, 1), Oe);
+              Oe = mfma(Vm[0], place(lw, 0), Oe);
+              Oe = mfma(Vm[1], place(lw, 1), Oe);
+            }
           } else {
             // 4 probabilities per lane, placed at slots 4 (c % 2) .. +3 of k-step c / 2
             auto place = [&](const uint32_t (&w)[2], int s) {
@@ -895,7 +1066,8 @@ fused_kernel(FusedArgs a) {
       }
     }
     const nqs_sector_info &si = sector_of(a.sec, x);
-    if (t < si.n) {
+    // (MID: its rows from pm on belong to TAIL)
+    if (t < si.n && (MODE != MID || t < a.pm)) {
       const uint64_t below = (t == 0) ? 0ull : (~0ull >> (64 - 2 * t));
       const int na = __popcll(x & below & 0x5555555555555555ull);
       const int nb = __popcll(x & below & 0xAAAAAAAAAAAAAAAAull);
@@ -911,7 +1083,7 @@ fused_kernel(FusedArgs a) {
         if ((allow >> k) & 1) z += expf(lg[k] - mx);
       logp = ((allow >> tk) & 1) ? lg[tk] - mx - logf(z) : -INFINITY;
     }
-    if (MODE == TRUNK || a.logabs) {
+    if (MODE == TRUNK || MODE == MID || a.logabs) {
       // sum over the configuration's R rows
 #pragma unroll
       for (int w = 1; w < R; w *= 2) logp += __shfl_xor(logp, w);
@@ -920,6 +1092,10 @@ fused_kernel(FusedArgs a) {
           a.plogp[cfg] = logp;
         } else if constexpr (MODE == SUFFIX) {
           a.logabs[cfg] = 0.5 * double(logp + a.plogp[ent_own]);
+        } else if constexpr (MODE == MID) {
+          a.plogp2[ent12] = logp;
+        } else if constexpr (MODE == TAIL) {
+          a.logabs[cfg] = 0.5 * double(logp + a.plogp[ent8] + a.plogp2[ent12]);
         } else {
           a.logabs[cfg] = 0.5 * double(logp);
         }
@@ -928,10 +1104,12 @@ fused_kernel(FusedArgs a) {
   }
 
   // ---- phase MLP for the chunk's configurations (column = configuration)
-  if (MODE != TRUNK && a.phase) {
+  if (MODE != TRUNK && MODE != MID && a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
-    const int64_t cfg = c_base + r;
-    const bool live = r < CPT * a.passes && cfg < B;
+    const int64_t item = c_base + r;
+    const bool in = r < CPT * a.passes && item < B;
+    const int64_t cfg = MODE == TAIL ? (in ? a.src[item] : -1) : item;
+    const bool live = MODE == TAIL ? cfg >= 0 : in;
     const uint64_t x = live ? a.x[cfg] : 0ull;
     const int nx = live ? sector_of(a.sec, x).n : 0;
     bf16x8 Z[PKS];
@@ -1089,7 +1267,9 @@ void launch_d(int mode, const FusedArgs &a, dim3 grid, size_t lds_bytes, hipStre
     case PLAIN: launch_mode<D, PLAIN>(a, grid, lds_bytes, s); break;
     case WIDE: launch_mode<D, WIDE>(a, grid, lds_bytes, s); break;
     case TRUNK: launch_mode<D, TRUNK>(a, grid, lds_bytes, s); break;
-    default: launch_mode<D, SUFFIX>(a, grid, lds_bytes, s); break;
+    case SUFFIX: launch_mode<D, SUFFIX>(a, grid, lds_bytes, s); break;
+    case MID: launch_mode<D, MID>(a, grid, lds_bytes, s); break;
+    default: launch_mode<D, TAIL>(a, grid, lds_bytes, s); break;
   }
 }
 
@@ -1107,6 +1287,70 @@ __global__ void prefix_list_kernel(const int64_t *__restrict__ flag,
   if (k < (1 << 16) && flag[k]) list[slot[k]] = uint64_t(k);
 }
 
+// Three-level bookkeeping over x sorted by (first 8 tokens, tokens 8 .. pm-1,
+// the rest): h8[i] / hm[i] = 1 where configuration i starts a new 8-token /
+// pm-token prefix.
+__global__ void prefix_heads_kernel(const uint64_t *__restrict__ x, int64_t B, uint64_t mmask,
+                                    int64_t *__restrict__ h8, int64_t *__restrict__ hm) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t d = i == 0 ? ~0ull : x[i] ^ x[i - 1];
+  h8[i] = (d & 0xFFFFull) != 0;
+  hm[i] = (d & mmask) != 0;
+}
+// per 8-token group g (pre8 / prem: exclusive scans of h8 / hm): its first
+// configuration and first pm-token prefix, and the trunk list entry; the
+// sentinels first8[G] = B, firstm[G] = number of pm-token prefixes
+__global__ void prefix_groups_kernel(const uint64_t *__restrict__ x, int64_t B,
+                                     const int64_t *__restrict__ h8, const int64_t *__restrict__ pre8,
+                                     const int64_t *__restrict__ prem, int64_t *__restrict__ first8,
+                                     int64_t *__restrict__ firstm, uint64_t *__restrict__ list8) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  if (h8[i]) {
+    const int64_t g = pre8[i];
+    first8[g] = i;
+    firstm[g] = prem[i];
+    list8[g] = x[i] & 0xFFFFull;
+  }
+  if (i == 0) {
+    first8[pre8[B]] = B;
+    firstm[pre8[B]] = prem[B];
+  }
+}
+// padded sizes of the groups' item lists (multiples of 8: a pass never mixes
+// 8-token prefixes), zero beyond the last group
+__global__ void prefix_pads_kernel(const int64_t *__restrict__ pre8, int64_t B,
+                                   const int64_t *__restrict__ first8,
+                                   const int64_t *__restrict__ firstm, int64_t K,
+                                   int64_t *__restrict__ pad_t, int64_t *__restrict__ pad_m) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= K) return;
+  const int64_t G = pre8[B];
+  pad_t[g] = g < G ? (first8[g + 1] - first8[g] + 7) / 8 * 8 : 0;
+  pad_m[g] = g < G ? (firstm[g + 1] - firstm[g] + 7) / 8 * 8 : 0;
+}
+__global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+// item lists: tail[start_t[g] + i - first8[g]] = i for every configuration i;
+// mid[start_m[g] + j - firstm[g]] = i for the first configuration i of every
+// pm-token prefix j
+__global__ void prefix_maps_kernel(int64_t B, const int64_t *__restrict__ hm,
+                                   const int64_t *__restrict__ pre8, const int64_t *__restrict__ prem,
+                                   const int64_t *__restrict__ first8,
+                                   const int64_t *__restrict__ firstm,
+                                   const int64_t *__restrict__ start_t,
+                                   const int64_t *__restrict__ start_m, int64_t *__restrict__ tail,
+                                   int64_t *__restrict__ mid) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const int64_t g = pre8[i + 1] - 1;
+  tail[start_t[g] + i - first8[g]] = i;
+  if (hm[i]) mid[start_m[g] + prem[i] - firstm[g]] = i;
+}
+
 }  // namespace
 
 bool fused_supported(const nqs_model &m) {
@@ -1117,6 +1361,10 @@ bool fused_supported(const nqs_model &m) {
 bool fused_shared_supported(const nqs_model &m) {
   return m.precision == NQS_BF16 && fused_supported(m) && m.n > kTrunk && m.n <= 16 && !m.tagged &&
          m.prefix_share;
+}
+
+int fused_shared_levels(const nqs_model &m) {
+  return !fused_shared_supported(m) ? 0 : m.n >= 13 ? 3 : 2;
 }
 
 void fused_pack(nqs_model &m, hipStream_t s) {
@@ -1208,7 +1456,7 @@ namespace {
 // the LDS size, the launch and its timing record.
 void launch_fused(nqs_model &m, int mode, FusedArgs &a, int64_t B, hipStream_t s,
                   const int64_t *count, int passes, int max_blocks) {
-  const int cpt = mode == PLAIN ? 2 : mode == WIDE ? 1 : 4;
+  const int cpt = mode == PLAIN ? 2 : mode == WIDE ? 1 : mode <= SUFFIX ? 4 : 8;
   const int maxp = 32 / cpt;
   const int64_t target_waves = 2048;
   a.passes = int(std::min<int64_t>(maxp, std::max<int64_t>(1, ceil_div(B, cpt * target_waves))));
@@ -1318,6 +1566,105 @@ void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *lo
   a.logabs = logabs;
   a.phase = phase;
   launch_fused(m, SUFFIX, a, B, s, nullptr, 0, 0);
+}
+
+void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                           double *phase, hipStream_t s) {
+  NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
+  NQS_REQUIRE(fused_shared_levels(m) == 3, NQS_EUNSUPPORTED, "shared forward: unsupported model");
+  if (B <= 0) return;
+  constexpr int64_t K = int64_t(1) << 16;      // 8-token prefixes
+  const int pm = m.n - 4;                      // TAIL: the last four positions
+  const uint64_t mmask = (1ull << (2 * pm)) - 1;
+  const int64_t kv_bytes = int64_t(m.L) * (m.d / 32) * 1024;
+  const int64_t kv2_bytes = int64_t(m.L) * (m.d / 32) * 512;
+  const int64_t cap8 = std::min(K, B), items = B + 7 * cap8;
+  // workspaces: flags and their scans, groups, pads and their scans, item lists
+  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(4 * (B + 1) + 6 * (K + 1) + 2 * items) * 8));
+  int64_t *h8 = w, *hm = h8 + (B + 1), *pre8 = hm + (B + 1), *prem = pre8 + (B + 1);
+  int64_t *first8 = prem + (B + 1), *firstm = first8 + (K + 1), *pad_t = firstm + (K + 1);
+  int64_t *pad_m = pad_t + (K + 1), *start_t = pad_m + (K + 1), *start_m = start_t + (K + 1);
+  int64_t *tail = start_m + (K + 1), *mid = tail + items;
+  auto *list8 = static_cast<uint64_t *>(m.pf_list.reserve(size_t(cap8) * 8));
+  auto *plogp = static_cast<float *>(m.pf_logp.reserve(size_t(cap8) * 4));
+  auto *kv = static_cast<uint8_t *>(m.pf_kv.reserve(size_t(cap8) * size_t(kv_bytes)));
+  auto *plogp2 = static_cast<float *>(m.pf3_logp.reserve(size_t(B) * 4));
+  hipLaunchKernelGGL(prefix_heads_kernel, g1(B), dim3(256), 0, s, x, B, mmask, h8, hm);
+  HIP_LAUNCH_OK();
+  launch_exclusive_scan(h8, pre8, B, s, m.pf_scan);
+  launch_exclusive_scan(hm, prem, B, s, m.pf_scan);
+  hipLaunchKernelGGL(prefix_groups_kernel, g1(B), dim3(256), 0, s, x, B, h8, pre8, prem, first8,
+                     firstm, list8);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(prefix_pads_kernel, g1(K), dim3(256), 0, s, pre8, B, first8, firstm, K,
+                     pad_t, pad_m);
+  HIP_LAUNCH_OK();
+  launch_exclusive_scan(pad_t, start_t, K, s, m.pf_scan);
+  launch_exclusive_scan(pad_m, start_m, K, s, m.pf_scan);
+  hipLaunchKernelGGL(fill_i64_kernel, g1(2 * items), dim3(256), 0, s, tail, 2 * items, int64_t(-1));
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(prefix_maps_kernel, g1(B), dim3(256), 0, s, B, hm, pre8, prem, first8,
+                     firstm, start_t, start_m, tail, mid);
+  HIP_LAUNCH_OK();
+  int64_t cnt[2] = {0, 0};
+  HIP_OK(hipMemcpyAsync(&cnt[0], pre8 + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&cnt[1], prem + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int64_t G = cnt[0], PM = cnt[1];
+  NQS_REQUIRE(G >= 1 && G <= cap8 && PM >= G && PM <= B, NQS_EINVAL, "shared forward: prefix count");
+  std::vector<int64_t> st_t(size_t(G) + 1), st_m(size_t(G) + 1), fm(size_t(G) + 1);
+  HIP_OK(hipMemcpyAsync(st_t.data(), start_t, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(st_m.data(), start_m, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(fm.data(), firstm, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+
+  Layout L = plan(m);
+  FusedArgs a = L.a;
+  a.pk = m.packed.as<bf16x8>();
+  a.vec = m.packed_vec.as<float>();
+  a.sec = m.sectors();
+  a.n = m.n;
+  a.L = m.L;
+  a.cond_p = -1;
+  a.cond = nullptr;
+  a.kv = kv;
+  a.kv_bytes = kv_bytes;
+  a.kv_total = cap8 * kv_bytes;
+  a.plogp = plogp;
+  a.pre8 = pre8;
+  a.pre12 = prem;
+  a.kv2_bytes = kv2_bytes;
+  a.plogp2 = plogp2;
+  a.pm = pm;
+  // positions 0..7 once per 8-token prefix (entry g = group g)
+  a.x = list8;
+  a.B = G;
+  launch_fused(m, TRUNK, a, G, s, nullptr, 0, 0);
+  // positions 8 .. pm-1 once per pm-token prefix, then the last four of every
+  // configuration, in slices of whole groups whose middle entries fit in
+  // 32-bit offsets (at most kMidSlice entries)
+  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  auto *kv2 = static_cast<uint8_t *>(m.pf3_kv.reserve(size_t(slice) * size_t(kv2_bytes)));
+  a.kv2 = kv2;
+  a.kv2_total = slice * kv2_bytes;
+  a.x = x;
+  for (int64_t g0 = 0; g0 < G;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
+    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "shared forward: slice");
+    a.j0 = fm[size_t(g0)];
+    a.src = mid + st_m[size_t(g0)];
+    a.B = st_m[size_t(g1)] - st_m[size_t(g0)];
+    a.logabs = nullptr;
+    a.phase = nullptr;
+    launch_fused(m, MID, a, a.B, s, nullptr, 0, 0);
+    a.src = tail + st_t[size_t(g0)];
+    a.B = st_t[size_t(g1)] - st_t[size_t(g0)];
+    a.logabs = logabs;
+    a.phase = phase;
+    launch_fused(m, TAIL, a, a.B, s, nullptr, 0, 0);
+    g0 = g1;
+  }
 }
 
 bool timing_on() { return g_timing; }

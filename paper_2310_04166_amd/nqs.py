@@ -525,7 +525,8 @@ def timing_read(mode=None):
     return ms.value, nl.value, nc.value
 
 
-TIMING_PLAIN, TIMING_WIDE, TIMING_TRUNK, TIMING_SUFFIX, TIMING_NADE = 0, 1, 2, 3, -1
+TIMING_PLAIN, TIMING_WIDE, TIMING_TRUNK, TIMING_SUFFIX, TIMING_MID, TIMING_TAIL = 0, 1, 2, 3, 4, 5
+TIMING_NADE = -1
 
 
 # ---------------------------------------------------------------- models ---

@@ -86,3 +86,15 @@ def test_executed_mfma_count_shared_prefix_by_hand():
     assert bench.executed_flop_per_config(4, 128, 256, "suffix") == 4 * 624 * 32768 / 4 + phase
     # trunk tile: 4 prefixes x 8 positions, the plain count, no phase MLP
     assert bench.executed_flop_per_config(4, 128, 256, "trunk") == 4 * 584 * 32768 / 4
+
+
+def test_executed_mfma_count_three_levels_by_hand():
+    # mid tile: 8 prefixes x 4 positions; per head pair scores against the own and
+    # the 8-token prefix's keys (4), probability-value products own (2 k-steps x
+    # hi + lo x 2 heads = 8) and prefix (1 k-step: 4) -> 48 + 4 + 12 + 24 = 88
+    assert bench.executed_flop_per_config(4, 128, 256, "mid") == 4 * (4 * 88 + 256) * 32768 / 8
+    # tail tile: 8 configurations x 4 positions, also the middle level's keys:
+    # scores 6, probability-value products 8 + 4 + 8 = 20 -> 98 per head pair
+    phase = 2 * 8 * 16 * 32768 / 32
+    assert bench.executed_flop_per_config(4, 128, 256, "tail") == \
+        4 * (4 * 98 + 256) * 32768 / 8 + phase

@@ -52,3 +52,53 @@ def test_distinct_prefixes_of_one_step():
     print(f"  count-weighted mean |difference| {wmean:.1e} Ha", flush=True)
     assert abs(s_sh[1] / s_sh[0] - s_un[1] / s_un[0]) < 1e-5
     assert np.median(d) < 1e-3 and wmean < 1e-3
+
+
+@pytest.mark.parametrize("n,na,nb,d,L,samples", [
+    (13, 3, 3, 64, 2, 20_000),     # the shortest sequence of three levels (middle: position 8)
+    (14, 2, 3, 128, 2, 50_000),
+    (16, 3, 2, 64, 1, 20_000),     # every position a token (middle: positions 8..11)
+])
+def test_three_levels_vs_unshared_and_oracle(n, na, nb, d, L, samples):
+    """13..16 tokens: the local energy evaluates positions 0..7 once per 8-token
+    prefix, 8 .. n-5 once per (n-4)-token prefix and the last four per
+    configuration (slices, padding to whole passes per 8-token prefix).  Its
+    energy against the per-configuration evaluation (same bf16 operands) and,
+    on the four highest-count samples, every local energy against the FP64
+    oracle within 1.5 x its first-order bound (tests/eloc_bound.py)."""
+    import eloc_bound
+    from oracle.model import TransformerModel
+    from oracle.sector import Sector
+    from paper_2310_04166_amd import nqs
+    from synth import make_integrals, make_transformer_params
+    nqs.lib()
+    h, eri = make_integrals(n, n, 40 + n)
+    params = make_transformer_params(n, na, nb, d, L, seed=n, std=0.05, hf_bias=1.0,
+                                     round_to="bf16", bias_std=0.02)
+    spec = transformer_param_spec(n, d, L, 4 * d, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, L, d // 16, 4 * d, 256],
+                  flatten_params(params, spec), "bf16")
+    H = nqs.ham_compile(h, eri, na, nb)
+    x, c, _ = nqs.sample_unique(m, samples, 3)
+    e3, s3, npairs = nqs.local_energy(H, m, x, c)
+    distinct = nqs.local_energy_stats(H)[1]
+    m.set_prefix_sharing(False)
+    eu, su, _ = nqs.local_energy(H, m, x, c)
+    m.set_prefix_sharing(True)
+    s3, su = s3.cpu().numpy(), su.cpu().numpy()
+    E3, Eu = s3[1] / s3[0], su[1] / su[0]
+    d_e = np.abs(e3.cpu().numpy() - eu.cpu().numpy())
+    print(f"n={n}: unique {x.numel()}, pairs {npairs}, distinct {distinct}; energy three levels "
+          f"{E3:.8f} unshared {Eu:.8f}; per-sample |difference| median {np.median(d_e):.1e}",
+          flush=True)
+    assert abs(E3 - Eu) < 1e-5
+    ref = TransformerModel(params, Sector(n, na, nb), d // 16)
+    cv = c.cpu().numpy()
+    top = list(np.argsort(-cv, kind="stable")[:4])
+    xv = x.cpu().numpy().view(np.uint64)
+    e = e3.cpu().numpy()
+    res = eloc_bound.check(ref, h, eri, [int(xv[i]) for i in top], eloc_bound.gpu_amplitudes(nqs, m))
+    for i, (want, A, eps) in zip(top, res):
+        err = abs(e[i] - want)
+        print(f"  x={int(xv[i]):#x} count={cv[i]} err {err:.2e} bound {2 * eps * A:.2e}", flush=True)
+        assert err <= 1.5 * 2 * eps * A + 1e-9
