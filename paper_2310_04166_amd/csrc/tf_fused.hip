@@ -156,6 +156,11 @@ struct FusedArgs {
   int pm;                           // MID covers positions 8 .. pm - 1, TAIL pm .. pm + 3
 };
 
+// A buffer store whose per-lane offset is at least the resource's size is
+// discarded by the hardware's range check; lanes without an entry store there
+// instead of branching around the store (buffers here are at most 2^31 bytes).
+constexpr uint32_t kDropOff = 0xC0000000u;
+
 // Byte offsets inside a prefix entry, layer l (NB blocks of 32 features):
 //   key   (block b, head e, position t, lane half h) at kv_key_off + 32 t + 16 h:
 //         16 B, the lane's 8 feature slots of head e;
@@ -751,12 +756,12 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const i32x4 w = __builtin_bit_cast(i32x4, s == 0 ? V0 : V1);
-            if (cfg0 + 2 * s < B)
-              __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[0], w[1]}, kvr, kv_val_lane,
-                                                    kv_cfg[2 * s] + kv_val_off<NB>(l, b), 0);
-            if (cfg0 + 2 * s + 1 < B)
-              __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2], w[3]}, kvr, kv_val_lane,
-                                                    kv_cfg[2 * s + 1] + kv_val_off<NB>(l, b), 0);
+            __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[0], w[1]}, kvr,
+                                                  cfg0 + 2 * s < B ? kv_val_lane : kDropOff,
+                                                  kv_cfg[2 * s] + kv_val_off<NB>(l, b), 0);
+            __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2], w[3]}, kvr,
+                                                  cfg0 + 2 * s + 1 < B ? kv_val_lane : kDropOff,
+                                                  kv_cfg[2 * s + 1] + kv_val_off<NB>(l, b), 0);
           }
         }
         if constexpr (MODE == MID) {
@@ -767,9 +772,9 @@ fused_kernel(FusedArgs a) {
             const i32x4 w = __builtin_bit_cast(i32x4, s == 0 ? V0 : V1);
 #pragma unroll
             for (int k2 = 0; k2 < 2; ++k2)
-              if (mid_ok(s, k2))
-                __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2 * k2], w[2 * k2 + 1]}, kv2r,
-                                                      mid_v(s, k2) + mv_lane, mv_off<NB>(l, b), 0);
+              __builtin_amdgcn_raw_buffer_store_b64(i32x2{w[2 * k2], w[2 * k2 + 1]}, kv2r,
+                                                    mid_ok(s, k2) ? mid_v(s, k2) + mv_lane : kDropOff,
+                                                    mv_off<NB>(l, b), 0);
           }
         }
         f32x16 O;
@@ -777,16 +782,14 @@ fused_kernel(FusedArgs a) {
         for (int e = 0; e < 2; ++e) {
           // S[j] = score(key (j/4)*8 + h*4 + j%4, query r)
           const bf16x8 Qe = to_bf16(Qc, e), Ke = to_bf16(Kc, e);
-          if constexpr (MODE == TRUNK) {
-            if (live)
-              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kvr,
-                                                     kv_own + kv_key_lane, kv_key_off<NB>(l, b, e), 0);
-          }
-          if constexpr (MODE == MID) {
-            if (live)
-              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kv2r,
-                                                     mid_own + mk_lane, mk_off<NB>(l, b, e), 0);
-          }
+          if constexpr (MODE == TRUNK)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kvr,
+                                                   live ? kv_own + kv_key_lane : kDropOff,
+                                                   kv_key_off<NB>(l, b, e), 0);
+          if constexpr (MODE == MID)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, Ke), kv2r,
+                                                   live ? mid_own + mk_lane : kDropOff,
+                                                   mk_off<NB>(l, b, e), 0);
           const f32x16 Sc = mfma(Ke, Qe, f32x16{});
           constexpr int NO = R == 4 ? 4 : R / 2;       // own keys per lane
           // prefix keys per lane: SUFFIX 4 of the 8-token prefix; MID those 4;
