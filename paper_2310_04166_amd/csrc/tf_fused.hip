@@ -87,12 +87,13 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // states, keys and values are the same for every configuration with the same
 // first 8 tokens; distinct x' of one step share few such prefixes (at most
 // 4^8), so TRUNK + SUFFIX do about half the work of PLAIN per configuration.
-//   MID     R = 4:  positions 8..11 of 8 distinct 12-token prefixes (all with
-//                   one 8-token prefix), attending to the 8-token prefix's keys
-//                   and values; stores its own keys and values and the
-//                   log-probability of tokens 8..11 per 12-token prefix;
-//   TAIL    R = 4:  positions 12..15 of 8 configurations (one 8-token prefix),
-//                   attending to both stored levels.
+//   MID     R = 4:  positions 8..pm-1 (pm = n - 4 <= 12; rows up to 11) of 8
+//                   distinct pm-token prefixes (all with one 8-token prefix),
+//                   attending to the 8-token prefix's keys and values; stores
+//                   its own keys and values and the log-probability of tokens
+//                   8..pm-1 per pm-token prefix;
+//   TAIL    R = 4:  the last four positions pm..pm+3 of 8 configurations (one
+//                   8-token prefix), attending to both stored levels.
 // MID / TAIL take their items through an index list (a.src; -1 = padding)
 // in which every 8-token prefix starts a new pass.
 enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5 };
@@ -144,14 +145,14 @@ struct FusedArgs {
   int64_t kv_bytes, kv_total;       // bytes per entry, of the buffer (<= 2^31)
   float *plogp;
   const int64_t *slot;
-  // MID / TAIL: item -> configuration (-1 = padding); the 8- and 12-token
+  // MID / TAIL: item -> configuration (-1 = padding); the 8- and pm-token
   // prefix entries of configuration i are pre8[i + 1] - 1 and pre12[i + 1] - 1
-  // (inclusive counts of the prefixes' first occurrences in x); the 12-token
-  // prefix entries (kv2_bytes each) hold keys and values of positions 8..11
+  // (inclusive counts of the prefixes' first occurrences in x); the pm-token
+  // prefix entries (kv2_bytes each) hold keys and values of rows 8..11
   const int64_t *src, *pre8, *pre12;
   uint8_t *kv2;
   int64_t kv2_bytes, kv2_total;
-  int64_t j0;                       // first 12-token prefix entry held in kv2 (a slice)
+  int64_t j0;                       // first pm-token prefix entry held in kv2 (a slice)
   float *plogp2;
   int pm;                           // MID covers positions 8 .. pm - 1, TAIL pm .. pm + 3
 };
@@ -176,7 +177,7 @@ template <int NB>
 __device__ inline uint32_t kv_val_off(int l, int b) {
   return uint32_t(l * NB * 1024 + NB * 512 + b * 512);
 }
-// 12-token prefix entries (positions 8..11), layer l: key (block b, head e,
+// pm-token prefix entries (rows 8..11), layer l: key (block b, head e,
 // position t < 4, lane half h) at mk_off + 32 t + 16 h, 16 B; value (block b,
 // feature f) at mv_off + 8 f, 8 B = positions 0..3.
 template <int NB>
@@ -599,7 +600,7 @@ fused_kernel(FusedArgs a) {
       kv_own = uint32_t(ent_own * a.kv_bytes);
     }
     // MID / TAIL: the pass's one 8-token prefix entry (its first item is never
-    // padding), the lane's 12-token prefix entry, and TAIL's value sources:
+    // padding), the lane's pm-token prefix entry, and TAIL's value sources:
     // the entries of configurations 4s + h (slots 0..3) and 4s + 2 + h (4..7)
     // (the pass's eight entries are wave-uniform: scalar registers; a lane picks
     // its two with h)
@@ -688,11 +689,43 @@ fused_kernel(FusedArgs a) {
         // MID / TAIL: the 8-token prefix's keys (key row r = position r % 8;
         // rows 8..31 repeat them and are never selected) and values (slots 0..3
         // of k-step 0 = positions 4h .. 4h+3, the rest zero); TAIL also the
-        // 12-token prefixes' keys (key row r = configuration r / 4, position
-        // r % 4) and values (as the own values: slots 0..3 of k-step s from
-        // configuration 4s + h, slots 4..7 from 4s + 2 + h)
-        // (keys here, values after the V projection, to keep registers free)
-        bf16x8 Vt, Vm[2];
+        // middle level's keys (key row r = configuration r / 4, position r % 4)
+        // and values (as the own values: slots 0..3 of k-step s from
+        // configuration 4s + h, slots 4..7 from 4s + 2 + h), all read while Q,
+        // K and V are computed
+        bf16x8 Vt, Vm[2], Kt[2], Km[2];
+        if constexpr (MODE >= MID) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            Kt[e] = __builtin_bit_cast(
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv8_off + kv_key_lane,
+                                                              kv_key_off<NB>(l, b, e), 0));
+        }
+        if constexpr (MODE == TAIL) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            Km[e] = __builtin_bit_cast(
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kv2r, mid_own + mk_lane,
+                                                              mk_off<NB>(l, b, e), 0));
+        }
+        if constexpr (MODE >= MID) {
+          const i32x2 v = __builtin_bit_cast(
+              i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8_off + kv_val_lane,
+                                                          kv_val_off<NB>(l, b), 0));
+          Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], 0, 0});
+        }
+        if constexpr (MODE == TAIL) {
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const i32x2 v0 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 0) + mv_lane,
+                                                            mv_off<NB>(l, b), 0));
+            const i32x2 v1 = __builtin_bit_cast(
+                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 1) + mv_lane,
+                                                            mv_off<NB>(l, b), 0));
+            Vm[s] = __builtin_bit_cast(bf16x8, i32x4{v0[0], v0[1], v1[0], v1[1]});
+          }
+        }
         // steps 4b (Q), 4b+1 (K), 4b+2 (V), 4b+3 (O)
         f32x16 Qc = lds16(V16 + S::VBQ + b * 32);
 #pragma unroll
@@ -731,24 +764,6 @@ fused_kernel(FusedArgs a) {
           for (int i = 0; i < HS; ++i) Vc = mfma(X[HS + i], fr[1][i], Vc);
         }
         fetch_half<D>(fr[1], ring + cur * RS, 1, lane);
-        if constexpr (MODE >= MID) {
-          const i32x2 v = __builtin_bit_cast(
-              i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8_off + kv_val_lane,
-                                                          kv_val_off<NB>(l, b), 0));
-          Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], 0, 0});
-        }
-        if constexpr (MODE == TAIL) {
-#pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const i32x2 v0 = __builtin_bit_cast(
-                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 0) + mv_lane,
-                                                            mv_off<NB>(l, b), 0));
-            const i32x2 v1 = __builtin_bit_cast(
-                i32x2, __builtin_amdgcn_raw_buffer_load_b64(kv2r, mid_v(s, 1) + mv_lane,
-                                                            mv_off<NB>(l, b), 0));
-            Vm[s] = __builtin_bit_cast(bf16x8, i32x4{v0[0], v0[1], v1[0], v1[1]});
-          }
-        }
         const bf16x8 V0 = to_bf16(Vc, 0), V1 = to_bf16(Vc, 1);
         if constexpr (MODE == TRUNK) {
           // keep this block's values for the suffixes: slots 0..3 / 4..7 of
@@ -793,7 +808,7 @@ fused_kernel(FusedArgs a) {
           const f32x16 Sc = mfma(Ke, Qe, f32x16{});
           constexpr int NO = R == 4 ? 4 : R / 2;       // own keys per lane
           // prefix keys per lane: SUFFIX 4 of the 8-token prefix; MID those 4;
-          // TAIL also 4 of the 12-token prefix
+          // TAIL also 4 of the middle level
           constexpr int NK = MODE == SUFFIX || MODE == MID ? 4 : MODE == TAIL ? 8 : 0;
           float p[NO + NK];
           float mx = -INFINITY;
@@ -822,10 +837,7 @@ fused_kernel(FusedArgs a) {
           if constexpr (MODE >= MID) {
             __builtin_amdgcn_sched_barrier(0);
             // the 8-token prefix's keys of this lane half: positions 4h + i in slots 0..3
-            const bf16x8 Kte = __builtin_bit_cast(
-                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv8_off + kv_key_lane,
-                                                              kv_key_off<NB>(l, b, e), 0));
-            const f32x16 St = mfma(Kte, Qe, f32x16{});
+            const f32x16 St = mfma(Kt[e], Qe, f32x16{});
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               p[NO + i] = St[i] * kScale;
@@ -834,10 +846,7 @@ fused_kernel(FusedArgs a) {
           }
           if constexpr (MODE == TAIL) {
             __builtin_amdgcn_sched_barrier(0);
-            const bf16x8 Kme = __builtin_bit_cast(
-                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kv2r, mid_own + mk_lane,
-                                                              mk_off<NB>(l, b, e), 0));
-            const f32x16 Sm = mfma(Kme, Qe, f32x16{});
+            const f32x16 Sm = mfma(Km[e], Qe, f32x16{});
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float s = bsel(bsel(Sm[i], Sm[4 + i], m_c1), bsel(Sm[8 + i], Sm[12 + i], m_c1), m_c2);
@@ -889,7 +898,7 @@ fused_kernel(FusedArgs a) {
             Oe = mfma(V0, __builtin_bit_cast(bf16x8, qlo), Oe);
             Oe = mfma(V1, __builtin_bit_cast(bf16x8, qhi), Oe);
           } else if constexpr (R == 4) {
-            // own (and 12-token prefix) keys: 4 probabilities in the lane half
+            // own (and middle-level) keys: 4 probabilities in the lane half
             // h = c % 2 at slots 4 ((c / 2) % 2) .. +3 of k-step c / 4; the
             // 8-token prefix's keys: slots 0..3 of k-step 0 in both halves
             auto place = [&](const uint32_t (&w)[2], int s) {
