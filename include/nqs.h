@@ -530,6 +530,15 @@ int nqs_timing_read(double *ms, int64_t *launches, int64_t *configs);
  */
 int nqs_timing_read_mode(int mode, double *ms, int64_t *launches, int64_t *configs);
 
+/*
+ * The samplers of a bf16 model with at most 2^24 samples keep the frontier
+ * sizes on the device and wait for the host once per call instead of once per
+ * tree level (on = 1, the default); on = 0 takes the per-level walk for every
+ * model.  Both give the same samples (the random numbers are keyed by node).
+ * Process-wide; for comparisons.
+ */
+int nqs_sampler_device_walk(int on);
+
 #ifdef __cplusplus
 }
 #endif

@@ -133,12 +133,23 @@ __device__ int64_t binomial(int64_t n, double p, Uniforms &uni) {
 // One thread per frontier node: split its samples over the four tokens.  A
 // node whose molecule has no token at level p (a smaller molecule of a batch)
 // passes all its samples to child 0, which is the same configuration word.
+// With `count` (device) the frontier holds *count nodes of capacity B, and
+// the threads past them clear their children so that the scan over the
+// capacity sees zeros.
 __global__ void split_kernel(const uint64_t *__restrict__ prefix, const uint64_t *__restrict__ cnt,
-                             const double *__restrict__ logits, int64_t B, int p, Sectors S,
+                             const double *__restrict__ logits, int64_t B,
+                             const int64_t *__restrict__ count, int p, Sectors S,
                              uint64_t seed, uint64_t *__restrict__ child,
                              uint64_t *__restrict__ flag, unsigned long long *__restrict__ lost) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= B) return;
+  if (count && i >= *count) {
+    for (int k = 0; k < 4; ++k) {
+      child[4 * i + k] = 0;
+      flag[4 * i + k] = 0;
+    }
+    return;
+  }
   const uint64_t x = prefix[i];
   const nqs_sector_info si = sector_of(S, x);
   if (p >= si.n) {
@@ -185,11 +196,13 @@ __global__ void split_kernel(const uint64_t *__restrict__ prefix, const uint64_t
   if (dropped) atomicAdd(lost, dropped);
 }
 
+// (next_count, optional: the number of children, off[B4], for the next level)
 __global__ void compact_kernel(const uint64_t *__restrict__ prefix,
                                const uint64_t *__restrict__ child, const int64_t *__restrict__ off,
                                int64_t B4, int p, uint64_t *__restrict__ npre,
-                               uint64_t *__restrict__ ncnt) {
+                               uint64_t *__restrict__ ncnt, int64_t *__restrict__ next_count) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (next_count && j == 0) *next_count = off[B4];
   if (j >= B4) return;
   const uint64_t c = child[j];
   if (c == 0) return;
@@ -239,8 +252,9 @@ int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
     auto *flag = static_cast<int64_t *>(m.s_flag.reserve(size_t(B) * 4 * 8));
     auto *off = static_cast<int64_t *>(m.s_off.reserve(size_t(B * 4 + 1) * 8));
     hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
-                       m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, p,
-                       m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);
+                       m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B,
+                       nullptr, p, m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag),
+                       lost_d);
     HIP_LAUNCH_OK();
     launch_exclusive_scan(flag, off, B * 4, s, m.s_scan);
     int64_t nb = 0;
@@ -251,7 +265,7 @@ int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
     m.s_cnt[nxt].reserve(size_t(nb > 0 ? nb : 1) * 8);
     hipLaunchKernelGGL(compact_kernel, dim3(unsigned(ceil_div(B * 4, 256))), dim3(256), 0, s,
                        m.s_pre[cur].as<uint64_t>(), child, off, B * 4, p,
-                       m.s_pre[nxt].as<uint64_t>(), m.s_cnt[nxt].as<uint64_t>());
+                       m.s_pre[nxt].as<uint64_t>(), m.s_cnt[nxt].as<uint64_t>(), nullptr);
     HIP_LAUNCH_OK();
     cur = nxt;
     B = nb;
@@ -261,6 +275,77 @@ int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
   HIP_OK(hipStreamSynchronize(s));
   lost_out = lost_h;
   return B;
+}
+
+// The same walk with the frontier sizes kept on the device: every level's
+// arrays are sized by a bound (four children per node, at most one node per
+// sample) and its kernels read the node count from the device, so the host
+// waits once, after the last level, instead of once per level.  For models
+// whose conditionals take a device count (the fused bf16 kernels); results are
+// those of walk_trees (the random numbers are keyed by node, not by position).
+constexpr int64_t kDeviceWalkMax = int64_t(1) << 24;   // frontier bound (nodes)
+bool g_device_walk = true;                             // nqs_sampler_device_walk
+
+bool device_walk_ok(const nqs_model &m, uint64_t total) {
+  return g_device_walk && m.precision == NQS_BF16 &&
+         (fused_supported(m) || nade_fused_supported(m)) && total <= uint64_t(kDeviceWalkMax);
+}
+
+int64_t walk_trees_device(nqs_model &m, const std::vector<uint64_t> &root_pre,
+                          const std::vector<uint64_t> &root_cnt, uint64_t seed, int &cur,
+                          uint64_t &lost_out, hipStream_t s) {
+  const int64_t B0 = int64_t(root_pre.size());
+  uint64_t total = 0;
+  for (uint64_t c : root_cnt) total += c;
+  // frontier bounds per level
+  std::vector<int64_t> cap(size_t(m.n) + 1);
+  cap[0] = B0;
+  int64_t cmax = std::max<int64_t>(B0, 1);
+  for (int p = 0; p < m.n; ++p) {
+    cap[size_t(p + 1)] = std::min<int64_t>(4 * cap[size_t(p)], int64_t(total));
+    cmax = std::max(cmax, cap[size_t(p + 1)]);
+  }
+  auto *lost_d = static_cast<unsigned long long *>(m.s_lost.reserve(8 + 8 * size_t(m.n + 1)));
+  int64_t *nb_d = reinterpret_cast<int64_t *>(lost_d + 1);   // node count of each level
+  cur = 0;
+  for (int k = 0; k < 2; ++k) {
+    m.s_pre[k].reserve(size_t(cmax) * 8);
+    m.s_cnt[k].reserve(size_t(cmax) * 8);
+  }
+  auto *cond = static_cast<double *>(m.s_cond.reserve(size_t(cmax) * 4 * 8));
+  auto *child = static_cast<uint64_t *>(m.s_child.reserve(size_t(cmax) * 4 * 8));
+  auto *flag = static_cast<int64_t *>(m.s_flag.reserve(size_t(cmax) * 4 * 8));
+  auto *off = static_cast<int64_t *>(m.s_off.reserve(size_t(cmax * 4 + 1) * 8));
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(1), 0, s, lost_d);
+  HIP_LAUNCH_OK();
+  if (B0 > 0) {
+    HIP_OK(hipMemcpyAsync(m.s_pre[0].ptr, root_pre.data(), size_t(B0) * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(m.s_cnt[0].ptr, root_cnt.data(), size_t(B0) * 8, hipMemcpyHostToDevice, s));
+  }
+  int64_t last = 0;   // level whose count is the result
+  for (int p = 0; p < m.n && cap[size_t(p)] > 0; ++p) {
+    const int64_t B = cap[size_t(p)];
+    const int64_t *count = p == 0 ? nullptr : nb_d + p;   // level 0: B0 nodes (host)
+    fused_forward(m, m.s_pre[cur].as<uint64_t>(), B, nullptr, nullptr, cond, p, s, count);
+    hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
+                       m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, count,
+                       p, m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);
+    HIP_LAUNCH_OK();
+    launch_exclusive_scan(flag, off, B * 4, s, m.s_scan);
+    const int nxt = 1 - cur;
+    hipLaunchKernelGGL(compact_kernel, dim3(unsigned(ceil_div(B * 4, 256))), dim3(256), 0, s,
+                       m.s_pre[cur].as<uint64_t>(), child, off, B * 4, p,
+                       m.s_pre[nxt].as<uint64_t>(), m.s_cnt[nxt].as<uint64_t>(), nb_d + p + 1);
+    HIP_LAUNCH_OK();
+    cur = nxt;
+    last = p + 1;
+  }
+  uint64_t host[2] = {0, 0};
+  HIP_OK(hipMemcpyAsync(&host[0], lost_d, 8, hipMemcpyDeviceToHost, s));
+  if (last > 0) HIP_OK(hipMemcpyAsync(&host[1], nb_d + last, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  lost_out = host[0];
+  return last > 0 ? int64_t(host[1]) : B0;
 }
 
 void copy_leaves(nqs_model &m, int cur, int64_t B, int64_t capacity, uint64_t *configs,
@@ -278,6 +363,10 @@ void copy_leaves(nqs_model &m, int cur, int64_t B, int64_t capacity, uint64_t *c
 
 using namespace nqs;
 
+extern "C" int nqs_sampler_device_walk(int on) {
+  return guarded([&] { g_device_walk = on != 0; });
+}
+
 extern "C" int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, uint64_t *configs,
                              uint64_t *counts, int64_t capacity, int64_t *n_unique, uint64_t *lost,
                              nqs_stream stream) {
@@ -294,7 +383,9 @@ extern "C" int sample_unique(nqs_model *m, uint64_t n_samples, uint64_t seed, ui
     }
     int cur = 0;
     uint64_t lost_h = 0;
-    const int64_t B = walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
+    const int64_t B = device_walk_ok(*m, n_samples)
+                          ? walk_trees_device(*m, pre, cnt, seed, cur, lost_h, s)
+                          : walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
     if (lost) *lost = lost_h;
     *n_unique = B;
     copy_leaves(*m, cur, B, capacity, configs, counts, s);
@@ -320,7 +411,11 @@ extern "C" int sample_unique_batch(nqs_model *m, int n_mol, const uint64_t *n_sa
       }
     int cur = 0;
     uint64_t lost_h = 0;
-    const int64_t B = walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
+    uint64_t total = 0;
+    for (uint64_t c : cnt) total += c;
+    const int64_t B = device_walk_ok(*m, total)
+                          ? walk_trees_device(*m, pre, cnt, seed, cur, lost_h, s)
+                          : walk_trees(*m, pre, cnt, seed, cur, lost_h, s);
     if (lost) *lost = lost_h;
     *n_unique = B;
     int64_t *off_d = static_cast<int64_t *>(m->s_off.reserve(size_t(n_mol + 1) * 8));

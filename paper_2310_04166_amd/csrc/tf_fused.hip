@@ -135,7 +135,7 @@ struct FusedArgs {
   int64_t B;                        // configurations (capacity when `count` is given)
   const int64_t *count;             // optional device-side count (persistent launches)
   int n, L, cond_p;                 // n = positions of the model
-  int passes;                       // passes per chunk (32 / R configurations each)
+  int passes;                       // passes per chunk (32 / R configurations each; 0: from *count)
   int lds_floats;                   // vec[0 .. lds_floats) is staged in LDS (all but pw1)
   double *logabs, *phase, *cond;
   // TRUNK / SUFFIX: per prefix entry (kv_bytes each) the keys and values of
@@ -481,13 +481,21 @@ fused_kernel(FusedArgs a) {
   constexpr int RS = KS * 64;        // one ring slot, in bf16x8 entries
   // wave of the block, explicitly wave-uniform so the loops stay scalar
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64));
-  // a persistent launch reads the number of configurations from the device
+  // a persistent launch reads the number of configurations from the device;
+  // with passes = 0 it also sizes its chunks from it: the fewest passes that
+  // spread the count over the grid's blocks
   const int64_t B = a.count ? (*a.count < a.B ? *a.count : a.B) : a.B;
+  int passes = a.passes;
+  if (passes == 0) {
+    const int64_t per = int64_t(4 * CPT) * gridDim.x;
+    const int64_t want = (B + per - 1) / per;
+    passes = want < 1 ? 1 : want > Rows<MODE>::MAXP ? Rows<MODE>::MAXP : int(want);
+  }
   // All four waves of a block take part in every barrier of the weight
   // stream, so the loops are uniform over the block: a block owns chunks of
   // 4 x CPT x passes configurations (wave w the w-th quarter) and a wave whose
   // configurations run out computes on empty rows and writes nothing.
-  const int64_t block_cfgs = int64_t(4 * CPT) * a.passes;
+  const int64_t block_cfgs = int64_t(4 * CPT) * passes;
   // Blocks are dispatched to the chip's 8 XCDs in turn (block i on XCD i % 8),
   // each with its own L2.  When the grid has one chunk per block, the chunks
   // of one XCD are made contiguous (neighbouring configurations share a
@@ -571,8 +579,8 @@ fused_kernel(FusedArgs a) {
 
   // block chunks strided over the grid
   for (int64_t bc = bc0; bc * block_cfgs < B; bc += gridDim.x) {
-  const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * a.passes;
-  for (int pass = 0; pass < a.passes; ++pass) {
+  const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * passes;
+  for (int pass = 0; pass < passes; ++pass) {
     const int64_t cfg0 = c_base + CPT * pass;
     if (bc * block_cfgs + CPT * pass >= B) break;   // uniform over the block
     // MID / TAIL: item cfg0 + c stands for configuration src (-1: padding)
@@ -1119,7 +1127,7 @@ fused_kernel(FusedArgs a) {
   if (MODE != TRUNK && MODE != MID && a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
     const int64_t item = c_base + r;
-    const bool in = r < CPT * a.passes && item < B;
+    const bool in = r < CPT * passes && item < B;
     const int64_t cfg = MODE == TAIL ? (in ? a.src[item] : -1) : item;
     const bool live = MODE == TAIL ? cfg >= 0 : in;
     const uint64_t x = live ? a.x[cfg] : 0ull;
@@ -1473,6 +1481,10 @@ void launch_fused(nqs_model &m, int mode, FusedArgs &a, int64_t B, hipStream_t s
   const int64_t target_waves = 2048;
   a.passes = int(std::min<int64_t>(maxp, std::max<int64_t>(1, ceil_div(B, cpt * target_waves))));
   if (passes > 0) a.passes = std::min(passes, maxp);
+  // a device count without a tile: the 2048 waves that fill the chip (fewer
+  // for a small capacity), passes chosen by the kernel from the count
+  const bool auto_passes = count && passes <= 0;
+  if (auto_passes) a.passes = 0;
   a.count = count;
   Layout L = plan(m);
   a.lds_floats = int(L.a.pw1);   // every vector before the phase-MLP input table
@@ -1481,7 +1493,8 @@ void launch_fused(nqs_model &m, int mode, FusedArgs &a, int64_t B, hipStream_t s
   // two blocks per CU must fit the 160 KiB of LDS
   NQS_REQUIRE(lds_bytes <= 80 * 1024, NQS_EUNSUPPORTED,
               "fused forward: model vectors exceed the LDS budget");
-  int64_t blocks = ceil_div(B, int64_t(4 * cpt) * a.passes);   // four waves per block
+  int64_t blocks = auto_passes ? std::min<int64_t>(ceil_div(B, int64_t(4 * cpt)), target_waves / 4)
+                               : ceil_div(B, int64_t(4 * cpt) * a.passes);   // four waves per block
   if (max_blocks > 0) blocks = std::min<int64_t>(blocks, max_blocks);
   NQS_REQUIRE(blocks <= int64_t(0x7FFFFFFF), NQS_EUNSUPPORTED, "fused forward: batch too large");
   const dim3 grid = dim3(unsigned(blocks));

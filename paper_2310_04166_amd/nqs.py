@@ -95,6 +95,7 @@ _SIGS = {
     "nqs_timing_enable": ([C.c_int], C.c_int),
     "nqs_timing_read": ([C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "nqs_timing_read_mode": ([C.c_int, C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
+    "nqs_sampler_device_walk": ([C.c_int], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -523,6 +524,12 @@ def timing_read(mode=None):
     else:
         _check(lib().nqs_timing_read_mode(mode, C.byref(ms), C.byref(nl), C.byref(nc)))
     return ms.value, nl.value, nc.value
+
+
+def sampler_device_walk(on=True):
+    """Frontier sizes of bf16 samplers kept on the device (default) or the
+    per-level walk (``nqs_sampler_device_walk``)."""
+    _check(lib().nqs_sampler_device_walk(1 if on else 0))
 
 
 TIMING_PLAIN, TIMING_WIDE, TIMING_TRUNK, TIMING_SUFFIX, TIMING_MID, TIMING_TAIL = 0, 1, 2, 3, 4, 5

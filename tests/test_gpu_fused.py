@@ -255,3 +255,38 @@ def test_fused_sampler_matches_its_forward(nqs, n, na, nb, strategy, d):
             f"oracle norm {p_or.sum():.6f})")
         assert abs(p_or.sum() - 1.0) < 1e-9
         assert tv <= bound
+
+
+@pytest.mark.parametrize("kind", ["transformer", "batch"])
+def test_sampler_device_walk_equals_per_level_walk(nqs, kind):
+    """The bf16 sampler with frontier sizes on the device (one host wait per
+    call) returns the same samples, counts and lost count as the per-level
+    walk: single molecule (30 spin-orbitals, 1e6 samples, MU-2) and a batch of
+    molecules of different sizes."""
+    if kind == "transformer":
+        cfg, h, eri, params = workload("precision")
+        spec = transformer_param_spec(15, 128, 4, 512, 256)
+        m = nqs.Model(nqs.MODEL_TRANSFORMER, nqs.model_dims(cfg), flatten_params(params, spec),
+                      "bf16", "MUd", 2)
+        run = lambda: nqs.sample_unique(m, cfg["n_samples"], 5)
+    else:
+        from synth import BATCHING_MODEL as C, batching_workload
+        mols, params = batching_workload(8)
+        spec = transformer_param_spec(C["n"], C["d"], C["n_layers"], C["ffn"], C["phase_hidden"])
+        dims = [C["n"], 0, 0, C["d"], C["n_layers"], C["n_heads"], C["ffn"], C["phase_hidden"]]
+        m = nqs.Model(nqs.MODEL_TRANSFORMER, dims, flatten_params(params, spec), "bf16")
+        hams = [nqs.ham_compile(x["h"], x["eri"], x["n_alpha"], x["n_beta"]) for x in mols]
+        batch = nqs.Batch(hams, m)
+        ns = [x["n_samples"] for x in mols]
+        run = lambda: nqs.sample_unique_batch(m, ns, 9)
+    try:
+        nqs.sampler_device_walk(True)
+        a = run()
+        nqs.sampler_device_walk(False)
+        b = run()
+    finally:
+        nqs.sampler_device_walk(True)
+    log(f"  {kind}: unique {a[0].numel()} lost {a[-1]}")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[-1] == b[-1]
+    if kind == "batch":
+        assert np.array_equal(a[2], b[2])
