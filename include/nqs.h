@@ -273,6 +273,21 @@ int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks, const int32
 int amp_model_set_prefix_sharing(nqs_model *m, int on);
 
 /*
+ * amp_model_set_mixed_backward - products of a bf16 transformer's backward
+ * (amp_backward; its forward recomputation included) on the bf16 matrix cores
+ * with split operands (on = 1, the default) or as fp32 library products
+ * (on = 0).  Paper: Variational Monte Carlo (the energy gradient through the
+ * amplitude network).  Split: every fp32 operand x becomes hi = bf16(x) and
+ * lo = bf16(x - hi), a product is hi hi + hi lo + lo hi with fp32
+ * accumulation (about 2^-16 relative error per product), bias, residual, GELU
+ * and its derivative applied in the products' epilogues; the weight gradients
+ * take the same split.  Layer norms, attention and the reductions stay fp32 /
+ * fp64.  Models whose widths are not multiples of 32 keep the fp32 products.
+ * Errors: NQS_EINVAL (null handle).
+ */
+int amp_model_set_mixed_backward(nqs_model *m, int on);
+
+/*
  * amp_forward - log|psi(x)| and phase phi(x) for n configurations.
  * x (dev, n uint64), logabs / phase (dev, n doubles each, written).  A
  * configuration outside the sector gets logabs = -inf.  n = 0 is a no-op.

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnqs.so")
 SOURCES = ["ham_compile.cpp", "eloc.hip", "ops.hip", "model.hip", "sampler.hip", "api.hip", "dedupe.hip",
-           "tf_fused.hip", "nade_fused.hip", "batch.hip", "table.hip"]
+           "tf_fused.hip", "nade_fused.hip", "batch.hip", "table.hip", "mx_gemm.hip"]
 ARCH = os.environ.get("NQS_OFFLOAD_ARCH", "gfx950")
 
 

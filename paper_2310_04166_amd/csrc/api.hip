@@ -513,6 +513,13 @@ extern "C" int amp_model_set_prefix_sharing(nqs_model *m, int on) {
   });
 }
 
+extern "C" int amp_model_set_mixed_backward(nqs_model *m, int on) {
+  return guarded([&] {
+    NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_mixed_backward: null handle");
+    m->mixed_backward = on != 0;
+  });
+}
+
 namespace {
 // bf16 forward of a batch: prefix-shared where the model allows it
 void bf16_forward(nqs_model &m, const uint64_t *x, int64_t n, double *logabs, double *phase,

@@ -97,6 +97,8 @@ struct nqs_model {
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
   nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
   int prefix_share = 1;               // bf16 transformer: prefix-shared evaluation of batches
+  int mixed_backward = 1;             // bf16 transformer: backward on split-bf16 MFMA products
+  nqs::DevBuf mx_w;                   // their weight images
   nqs::DevBuf pf_tab, pf_list, pf_logp, pf_kv, pf_scan;  // its prefix table, keys and values
   nqs::DevBuf pf3_ws, pf3_logp, pf3_kv;  // three levels: bookkeeping, middle-level entries
 

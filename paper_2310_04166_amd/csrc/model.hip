@@ -315,9 +315,78 @@ const T *P(const nqs_model &m, int idx) {
 
 // ----------------------------------------------------------- transformer ---
 
+// Split bf16 images of the transformer's weights for the backward of bf16
+// models (mixed-precision products, mx_gemm): per layer the right operands of
+// the forward products (QKV, O, W1, W2) and of the input gradients (their
+// transposes), and the phase MLP's W2 both ways.
+struct MxPack {
+  struct Layer {
+    const void *qkv, *o, *w1, *w2, *qkvT, *oT, *w1T, *w2T;
+  };
+  std::vector<Layer> layer;
+  const void *pw2 = nullptr, *pw2T = nullptr;
+};
+
+bool mx_backward_ok(const nqs_model &m) {
+  const int64_t d = m.d, F = m.F, PH = m.PH;
+  return m.precision == NQS_BF16 && m.kind == NQS_MODEL_TRANSFORMER && mx_supported(3 * d, d) &&
+         mx_supported(d, 3 * d) && mx_supported(d, d) && mx_supported(F, d) &&
+         mx_supported(d, F) && mx_supported(PH, PH);
+}
+
+MxPack mx_pack_model(nqs_model &m, hipStream_t s) {
+  const int64_t d = m.d, F = m.F, PH = m.PH;
+  struct Item {
+    const float *W;
+    int64_t ldw;
+    bool trans;
+    int64_t N, K;
+    const void **dst;
+  };
+  MxPack pk;
+  pk.layer.resize(size_t(m.L));
+  std::vector<Item> items;
+  for (int l = 0; l < m.L; ++l) {
+    auto W = [&](int k) { return P<float>(m, tf_layer(l, k)); };
+    MxPack::Layer &y = pk.layer[size_t(l)];
+    items.push_back({W(TF_WQKV), 3 * d, false, 3 * d, d, &y.qkv});
+    items.push_back({W(TF_WO), d, false, d, d, &y.o});
+    items.push_back({W(TF_W1), F, false, F, d, &y.w1});
+    items.push_back({W(TF_W2), d, false, d, F, &y.w2});
+    items.push_back({W(TF_WQKV), 3 * d, true, d, 3 * d, &y.qkvT});
+    items.push_back({W(TF_WO), d, true, d, d, &y.oT});
+    items.push_back({W(TF_W1), F, true, d, F, &y.w1T});
+    items.push_back({W(TF_W2), d, true, F, d, &y.w2T});
+  }
+  const float *pw2 = P<float>(m, tf_tail(m.L, TF_PW2));
+  items.push_back({pw2, PH, false, PH, PH, &pk.pw2});
+  items.push_back({pw2, PH, true, PH, PH, &pk.pw2T});
+  size_t total = 0;
+  for (const Item &it : items) total += (mx_pack_bytes(it.N, it.K) + 255) & ~size_t(255);
+  char *base = static_cast<char *>(m.mx_w.reserve(total));
+  size_t off = 0;
+  for (const Item &it : items) {
+    mx_pack(it.W, it.ldw, it.trans, it.N, it.K, base + off, s);
+    *it.dst = base + off;
+    off += (mx_pack_bytes(it.N, it.K) + 255) & ~size_t(255);
+  }
+  return pk;
+}
+
+// mx_gemm for fp32 activations (the mixed path exists for them only)
+template <class T>
+void mxg(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const void *Wp, T *C,
+         int64_t ldc, const T *res, int64_t ldr, const T *bias, T *aux, int epi, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value)
+    mx_gemm(M, N, K, A, lda, Wp, C, ldc, res, ldr, bias, aux, epi, s);
+  else
+    NQS_REQUIRE(false, NQS_EINVAL, "mixed products take fp32 activations");
+}
+
+// mx: the weights' split images (bf16 models' backward), else library products
 template <class T>
 void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfAct<T> &A,
-                      double *logabs, double *phase, hipStream_t s) {
+                      double *logabs, double *phase, hipStream_t s, const MxPack *mx = nullptr) {
   const int n = m.n, d = m.d, F = m.F, H = m.H, L = m.L, PH = m.PH;
   const int64_t R = B * n;
   hipLaunchKernelGGL(embed_kernel<T>, g1(R * d), dim3(256), 0, s, x, B, n, d, P<T>(m, TF_TOK),
@@ -327,6 +396,19 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
     Layer<T> &y = A.layer[l];
     auto W = [&](int k) { return P<T>(m, tf_layer(l, k)); };
     layernorm<T>(y.h_in, R, d, W(TF_LN1G), W(TF_LN1B), y.a1, y.m1, y.r1, s);
+    T *h_next = (l + 1 < L) ? A.layer[l + 1].h_in : A.h_out;
+    if (mx) {
+      // residuals read from the previous stream position, no copies
+      const MxPack::Layer &p = mx->layer[size_t(l)];
+      mxg<T>(R, 3 * d, d, y.a1, d, p.qkv, y.qkv, 3 * d, nullptr, 0, W(TF_BQKV), nullptr, MX_STORE,
+             s);
+      attention_fwd<T>(y.qkv, B, n, d, H, y.o, y.probs, s);
+      mxg<T>(R, d, d, y.o, d, p.o, y.h_mid, d, y.h_in, d, W(TF_BO), nullptr, MX_ADD, s);
+      layernorm<T>(y.h_mid, R, d, W(TF_LN2G), W(TF_LN2B), y.a2, y.m2, y.r2, s);
+      mxg<T>(R, F, d, y.a2, d, p.w1, y.f, F, nullptr, 0, W(TF_B1), y.fpre, MX_GELU, s);
+      mxg<T>(R, d, F, y.f, F, p.w2, h_next, d, y.h_mid, d, W(TF_B2), nullptr, MX_ADD, s);
+      continue;
+    }
     gemm<T, false, false>(R, 3 * d, d, y.a1, d, W(TF_WQKV), 3 * d, y.qkv, 3 * d, W(TF_BQKV),
                              nullptr, EPI_STORE, s);
     attention_fwd<T>(y.qkv, B, n, d, H, y.o, y.probs, s);
@@ -336,7 +418,6 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
                              s);
     layernorm<T>(y.h_mid, R, d, W(TF_LN2G), W(TF_LN2B), y.a2, y.m2, y.r2, s);
     gemm<T, false, false>(R, F, d, y.a2, d, W(TF_W1), F, y.f, F, W(TF_B1), y.fpre, EPI_GELU, s);
-    T *h_next = (l + 1 < L) ? A.layer[l + 1].h_in : A.h_out;
     if (h_next != y.h_mid)
       HIP_OK(hipMemcpyAsync(h_next, y.h_mid, R * d * sizeof(T), hipMemcpyDeviceToDevice, s));
     gemm<T, false, false>(R, d, F, y.f, F, W(TF_W2), d, h_next, d, W(TF_B2), nullptr, EPI_ADD,
@@ -356,8 +437,12 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
     hipLaunchKernelGGL(phase_in_kernel<T>, g1(B * PH), dim3(256), 0, s, x, B, m.sectors(), PH,
                        P<T>(m, tf_tail(L, TF_PW1)), P<T>(m, tf_tail(L, TF_PB1)), A.z1pre, A.z1);
     HIP_LAUNCH_OK();
-    gemm<T, false, false>(B, PH, PH, A.z1, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, A.z2, PH,
-                             P<T>(m, tf_tail(L, TF_PB2)), A.z2pre, EPI_GELU, s);
+    if (mx)
+      mxg<T>(B, PH, PH, A.z1, PH, mx->pw2, A.z2, PH, nullptr, 0, P<T>(m, tf_tail(L, TF_PB2)),
+             A.z2pre, MX_GELU, s);
+    else
+      gemm<T, false, false>(B, PH, PH, A.z1, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, A.z2, PH,
+                               P<T>(m, tf_tail(L, TF_PB2)), A.z2pre, EPI_GELU, s);
     if (phase) {
       hipLaunchKernelGGL(phase_out_kernel<T>, g1(B, 4), dim3(256), 0, s, A.z2, B, PH,
                          P<T>(m, tf_tail(L, TF_PW3)), P<T>(m, tf_tail(L, TF_PB3)), phase);
@@ -366,12 +451,16 @@ void tf_forward_chunk(nqs_model &m, const uint64_t *x, int64_t B, bool save, TfA
   }
 }
 
-// dW += X^T dY reduced over the R rows, accumulated in double at the parameter's offset.
+// dW += X^T dY reduced over the R rows, accumulated in double at the parameter's offset
+// (mixed: split bf16 operands).
 template <class T>
 void wgrad(nqs_model &m, int64_t Mi, int64_t No, int64_t R, const T *X, int64_t ldx, const T *dY,
-           int64_t ldy, int pidx, hipStream_t s) {
+           int64_t ldy, int pidx, hipStream_t s, bool mixed = false) {
   void *part = m.part.reserve(wgrad_scratch_bytes(R, Mi, No, std::max(ldx, ldy), sizeof(T)));
-  wgrad_acc(X, ldx, dY, ldy, R, Mi, No, m.grad_acc.as<double>() + m.off[pidx], part, s);
+  if constexpr (std::is_same<T, float>::value)
+    wgrad_acc(X, ldx, dY, ldy, R, Mi, No, m.grad_acc.as<double>() + m.off[pidx], part, s, mixed);
+  else
+    wgrad_acc(X, ldx, dY, ldy, R, Mi, No, m.grad_acc.as<double>() + m.off[pidx], part, s);
 }
 
 // db += column sums of dY (fixed-order, double)
@@ -381,9 +470,10 @@ void bgrad(nqs_model &m, const T *dY, int64_t R, int64_t N, int64_t ld, int pidx
   colsum_acc<T>(dY, R, N, ld, m.grad_acc.as<double>() + m.off[pidx], part, s);
 }
 
+// mx: the weights' split images (bf16 models), else library products
 template <class T>
 void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
-                       const double *gp, hipStream_t s) {
+                       const double *gp, hipStream_t s, const MxPack *mx = nullptr) {
   const int n = m.n, d = m.d, F = m.F, H = m.H, L = m.L, PH = m.PH;
   const int64_t R = B * n;
   Carver c0{nullptr};
@@ -411,13 +501,14 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   carve_tf<T>(m, B, true, c2, A);
   carve_bwd(c2, dh, dl, da, df, dq, tmp, dz, gpt);
 
-  tf_forward_chunk<T>(m, x, B, true, A, nullptr, nullptr, s);
+  tf_forward_chunk<T>(m, x, B, true, A, nullptr, nullptr, s, mx);
+  const bool mixed = mx != nullptr;
 
   // head and masked log-softmax
   hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.logits, 4,
                      m.sectors(), gl, dl, 4);
   HIP_LAUNCH_OK();
-  wgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), s);
+  wgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), s, mixed);
   bgrad<T>(m, dl, R, 4, 4, tf_tail(L, TF_BHEAD), s);
   bgrad<T>(m, dl, B, int64_t(n) * 4, int64_t(n) * 4, tf_tail(L, TF_LBIAS), s);
   gemm<T, false, true>(R, d, 4, dl, 4, P<T>(m, tf_tail(L, TF_WHEAD)), 4, da, d, nullptr,
@@ -429,26 +520,36 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   for (int l = L - 1; l >= 0; --l) {
     Layer<T> &y = A.layer[l];
     auto W = [&](int k) { return P<T>(m, tf_layer(l, k)); };
+    const MxPack::Layer *p = mixed ? &mx->layer[size_t(l)] : nullptr;
     // h_out = h_mid + gelu(a2 W1 + b1) W2 + b2
-    wgrad<T>(m, F, d, R, y.f, F, dh, d, tf_layer(l, TF_W2), s);
+    wgrad<T>(m, F, d, R, y.f, F, dh, d, tf_layer(l, TF_W2), s, mixed);
     bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_B2), s);
-    gemm<T, false, true>(R, F, d, dh, d, W(TF_W2), d, df, F, nullptr, nullptr, EPI_STORE, s);
-    gelu_bwd<T>(y.fpre, df, R * F, s);
-    wgrad<T>(m, d, F, R, y.a2, d, df, F, tf_layer(l, TF_W1), s);
+    if (p) {
+      mxg<T>(R, F, d, dh, d, p->w2T, df, F, nullptr, 0, nullptr, y.fpre, MX_DGELU, s);
+    } else {
+      gemm<T, false, true>(R, F, d, dh, d, W(TF_W2), d, df, F, nullptr, nullptr, EPI_STORE, s);
+      gelu_bwd<T>(y.fpre, df, R * F, s);
+    }
+    wgrad<T>(m, d, F, R, y.a2, d, df, F, tf_layer(l, TF_W1), s, mixed);
     bgrad<T>(m, df, R, F, F, tf_layer(l, TF_B1), s);
-    gemm<T, false, true>(R, d, F, df, F, W(TF_W1), F, da, d, nullptr, nullptr, EPI_STORE, s);
+    if (p) mxg<T>(R, d, F, df, F, p->w1T, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
+    else gemm<T, false, true>(R, d, F, df, F, W(TF_W1), F, da, d, nullptr, nullptr, EPI_STORE, s);
     layernorm_bwd<T>(y.h_mid, y.m2, y.r2, R, d, W(TF_LN2G), da, dh, true, tmp, s);
     bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN2G), s);
     bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN2B), s);
     // h_mid = h_in + attn(a1) Wo + bo
-    wgrad<T>(m, d, d, R, y.o, d, dh, d, tf_layer(l, TF_WO), s);
+    wgrad<T>(m, d, d, R, y.o, d, dh, d, tf_layer(l, TF_WO), s, mixed);
     bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_BO), s);
-    gemm<T, false, true>(R, d, d, dh, d, W(TF_WO), d, da, d, nullptr, nullptr, EPI_STORE, s);
+    if (p) mxg<T>(R, d, d, dh, d, p->oT, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
+    else gemm<T, false, true>(R, d, d, dh, d, W(TF_WO), d, da, d, nullptr, nullptr, EPI_STORE, s);
     attention_bwd<T>(y.qkv, y.probs, da, B, n, d, H, dq, s);
-    wgrad<T>(m, d, 3 * d, R, y.a1, d, dq, 3 * d, tf_layer(l, TF_WQKV), s);
+    wgrad<T>(m, d, 3 * d, R, y.a1, d, dq, 3 * d, tf_layer(l, TF_WQKV), s, mixed);
     bgrad<T>(m, dq, R, 3 * d, 3 * d, tf_layer(l, TF_BQKV), s);
-    gemm<T, false, true>(R, d, 3 * d, dq, 3 * d, W(TF_WQKV), 3 * d, da, d, nullptr, nullptr,
-                            EPI_STORE, s);
+    if (p)
+      mxg<T>(R, d, 3 * d, dq, 3 * d, p->qkvT, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
+    else
+      gemm<T, false, true>(R, d, 3 * d, dq, 3 * d, W(TF_WQKV), 3 * d, da, d, nullptr, nullptr,
+                              EPI_STORE, s);
     layernorm_bwd<T>(y.h_in, y.m1, y.r1, R, d, W(TF_LN1G), da, dh, true, tmp, s);
     bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN1G), s);
     bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN1B), s);
@@ -456,7 +557,7 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   // embeddings: token table through the one-hot input classes, positions by column sums
   hipLaunchKernelGGL(in_class_kernel<T>, g1(R * 5), dim3(256), 0, s, x, B, n, tmp);
   HIP_LAUNCH_OK();
-  wgrad<T>(m, 5, d, R, tmp, 5, dh, d, TF_TOK, s);
+  wgrad<T>(m, 5, d, R, tmp, 5, dh, d, TF_TOK, s, mixed);
   bgrad<T>(m, dh, B, int64_t(n) * d, int64_t(n) * d, TF_POS, s);
 
   // phase MLP: phi = gelu(gelu(onehot W1 + b1) W2 + b2) w3 + b3
@@ -464,18 +565,22 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   hipLaunchKernelGGL(phase_dz_kernel<T>, g1(B * PH), dim3(256), 0, s, gp, B, PH,
                      P<T>(m, tf_tail(L, TF_PW3)), dz2, gpt);
   HIP_LAUNCH_OK();
-  wgrad<T>(m, PH, 1, B, A.z2, PH, gpt, 1, tf_tail(L, TF_PW3), s);
+  wgrad<T>(m, PH, 1, B, A.z2, PH, gpt, 1, tf_tail(L, TF_PW3), s, mixed);
   bgrad<T>(m, gpt, B, 1, 1, tf_tail(L, TF_PB3), s);
   gelu_bwd<T>(A.z2pre, dz2, B * PH, s);
-  wgrad<T>(m, PH, PH, B, A.z1, PH, dz2, PH, tf_tail(L, TF_PW2), s);
+  wgrad<T>(m, PH, PH, B, A.z1, PH, dz2, PH, tf_tail(L, TF_PW2), s, mixed);
   bgrad<T>(m, dz2, B, PH, PH, tf_tail(L, TF_PB2), s);
-  gemm<T, false, true>(B, PH, PH, dz2, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, dz1, PH, nullptr,
-                          nullptr, EPI_STORE, s);
-  gelu_bwd<T>(A.z1pre, dz1, B * PH, s);
+  if (mixed) {
+    mxg<T>(B, PH, PH, dz2, PH, mx->pw2T, dz1, PH, nullptr, 0, nullptr, A.z1pre, MX_DGELU, s);
+  } else {
+    gemm<T, false, true>(B, PH, PH, dz2, PH, P<T>(m, tf_tail(L, TF_PW2)), PH, dz1, PH, nullptr,
+                            nullptr, EPI_STORE, s);
+    gelu_bwd<T>(A.z1pre, dz1, B * PH, s);
+  }
   bgrad<T>(m, dz1, B, PH, PH, tf_tail(L, TF_PB1), s);
   hipLaunchKernelGGL(onehot_kernel<T>, g1(B * 4 * n), dim3(256), 0, s, x, B, n, m.sectors(), tmp);
   HIP_LAUNCH_OK();
-  wgrad<T>(m, 4 * n, PH, B, tmp, 4 * n, dz1, PH, tf_tail(L, TF_PW1), s);
+  wgrad<T>(m, 4 * n, PH, B, tmp, 4 * n, dz1, PH, tf_tail(L, TF_PW1), s, mixed);
 }
 
 // ------------------------------------------------------------------- MLP ---
@@ -1232,6 +1337,10 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
     if (m.fp64()) nade_qb_backward<double>(m, x, B, gl, gp, ch, s);
     else nade_qb_backward<float>(m, x, B, gl, gp, ch, s);
   }
+  // bf16 transformers: split images of the weights, made once per call
+  MxPack mx;
+  const bool mixed = B > 0 && m.mixed_backward && mx_backward_ok(m);
+  if (mixed) mx = mx_pack_model(m, s);
   for (int64_t b0 = 0; b0 < B && m.kind != NQS_MODEL_NADE; b0 += ch) {
     const int64_t nb = B - b0 < ch ? B - b0 : ch;
     if (m.kind == NQS_MODEL_MLP) {
@@ -1239,7 +1348,7 @@ void model_backward(nqs_model &m, const uint64_t *x, int64_t B, const double *gl
       else mlp_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
     } else {
       if (m.fp64()) tf_backward_chunk<double>(m, x + b0, nb, gl + b0, gp + b0, s);
-      else tf_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s);
+      else tf_backward_chunk<float>(m, x + b0, nb, gl + b0, gp + b0, s, mixed ? &mx : nullptr);
     }
   }
   if (m.fp64()) convert<double, double>(acc, static_cast<double *>(grad), m.P, s);

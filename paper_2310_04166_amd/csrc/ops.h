@@ -44,13 +44,42 @@ size_t colsum_scratch_bytes(int64_t R, int64_t N);
 // j < N (double accumulator).  FP32: a split-K MFMA reduction over row slices
 // whose partial sums are added in a fixed order; FP64: a library GEMM.  scratch
 // holds at least wgrad_scratch_bytes(R, M, N, max(ldx, ldy), element size) bytes.
+// mixed: the partial sums take split bf16 operands (mx_wgrad_partials) instead
+// of fp32 MFMA.
 void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R, int64_t M,
-               int64_t N, double *acc, void *scratch, hipStream_t s);
+               int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed = false);
 void wgrad_acc(const double *X, int64_t ldx, const double *dY, int64_t ldy, int64_t R, int64_t M,
                int64_t N, double *acc, void *scratch, hipStream_t s);
 size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t elem);
 // acc[i] += sum_z part[z*len + i]
 void slices_acc(const double *part, int64_t nslices, int64_t len, double *acc, hipStream_t s);
+
+// ---- Mixed-precision products (mx_gemm.hip), used by the backward of bf16
+// models: fp32 operands split into bf16 hi + lo parts, three MFMA products
+// (hi hi, hi lo, lo hi) with fp32 accumulation, about 2^-16 relative error per
+// product.
+enum MxEpi : int {
+  MX_STORE = 0,   // C = A op(W) + bias
+  MX_ADD = 1,     // C = res + A op(W) + bias (res another array)
+  MX_GELU = 2,    // aux = A op(W) + bias, C = gelu_tanh(aux)
+  MX_DGELU = 3,   // C = (A op(W)) * gelu_tanh'(aux), no bias
+};
+// Shapes the products take: N and K multiples of 32.
+bool mx_supported(int64_t N, int64_t K);
+// Image of a right operand, op(W)(k, n) = trans ? W[n*ldw + k] : W[k*ldw + n]
+// (k < K, n < N), in mx_pack_bytes(N, K) bytes of device memory.
+size_t mx_pack_bytes(int64_t N, int64_t K);
+void mx_pack(const float *W, int64_t ldw, bool trans, int64_t N, int64_t K, void *out,
+             hipStream_t s);
+// C[M,N] (ldc) from A[M,K] (row-major, lda % 4 == 0, 16-byte aligned) and the
+// image Wp of op(W), with the epilogue epi; aux has the leading dimension ldc.
+void mx_gemm(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const void *Wp, float *C,
+             int64_t ldc, const float *res, int64_t ldr, const float *bias, float *aux, int epi,
+             hipStream_t s);
+// part[z][i][j] = sum over rows r of slice z (rows z*rows_per ..) of
+// X[r][i] dY[r][j], i < M, j < N; a slice under 1 GiB of either matrix.
+void mx_wgrad_partials(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
+                       int64_t M, int64_t N, int64_t rows_per, float *part, hipStream_t s);
 
 // Row-wise layer norm over d columns; mean/rstd may be null.
 template <class T>

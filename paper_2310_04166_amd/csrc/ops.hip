@@ -4,6 +4,8 @@
 // kernel.
 #include "ops.h"
 
+#include "act.h"
+
 #include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
 
@@ -13,19 +15,6 @@
 
 namespace nqs {
 namespace {
-
-template <class T>
-__device__ inline T gelu_tanh(T x) {
-  const T c = T(0.7978845608028654);  // sqrt(2/pi)
-  return T(0.5) * x * (T(1) + tanh(c * (x + T(0.044715) * x * x * x)));
-}
-template <class T>
-__device__ inline T gelu_tanh_grad(T x) {
-  const T c = T(0.7978845608028654);
-  const T u = c * (x + T(0.044715) * x * x * x);
-  const T t = tanh(u);
-  return T(0.5) * (T(1) + t) + T(0.5) * x * (T(1) - t * t) * c * (T(1) + T(3 * 0.044715) * x * x);
-}
 
 // Epilogue of the library GEMM: bias and activation, in place on C (M x N, ldc).
 template <class T>
@@ -834,7 +823,7 @@ size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t e
 }
 
 void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
-                      int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s) {
+                      int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed) {
   if (M <= 0 || N <= 0) return;
   NQS_REQUIRE(M < (int64_t(1) << 24) && N < (int64_t(1) << 24), NQS_EUNSUPPORTED,
               "weight gradient: dimension too large");
@@ -846,9 +835,13 @@ void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_
   const int64_t tiles = ceil_div(M, int64_t(128)) * tiles_n;
   const dim3 grid = dim3(unsigned(tiles), unsigned(ceil_div(R, rows_per)));
   float *part = static_cast<float *>(scratch);
-  hipLaunchKernelGGL(wgrad_f32_kernel, grid, dim3(256), 0, s, X, ldx, dY, ldy, R, int(M), int(N),
-                     rows_per, tiles_n, part);
-  HIP_LAUNCH_OK();
+  if (mixed) {
+    mx_wgrad_partials(X, ldx, dY, ldy, R, M, N, rows_per, part, s);
+  } else {
+    hipLaunchKernelGGL(wgrad_f32_kernel, grid, dim3(256), 0, s, X, ldx, dY, ldy, R, int(M), int(N),
+                       rows_per, tiles_n, part);
+    HIP_LAUNCH_OK();
+  }
   double *lvl = static_cast<double *>(scratch) + ceil_div(z * M * N, int64_t(2));
   reduce_slices<float>(part, int64_t(grid.y), M * N, acc, lvl, s);
 }

@@ -78,6 +78,7 @@ _SIGS = {
     "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "amp_model_set_z2": ([_vp, C.c_int, _vp, _vp], C.c_int),
     "amp_model_set_prefix_sharing": ([_vp, C.c_int], C.c_int),
+    "amp_model_set_mixed_backward": ([_vp, C.c_int], C.c_int),
     "amp_model_set_symmetries": ([_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp], C.c_int),
     "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
                              C.POINTER(_u64), _vp], C.c_int),
@@ -241,6 +242,11 @@ class Model:
         """bf16 transformer batches by shared 8-token prefixes (default) or
         configuration by configuration (``amp_model_set_prefix_sharing``)."""
         _check(lib().amp_model_set_prefix_sharing(self.handle, 1 if on else 0))
+
+    def set_mixed_backward(self, on):
+        """bf16 transformer backward on split-bf16 MFMA products (default) or
+        fp32 library products (``amp_model_set_mixed_backward``)."""
+        _check(lib().amp_model_set_mixed_backward(self.handle, 1 if on else 0))
 
     def set_z2(self, masks, targets=None):
         """Restrict the sector by Z2 symmetries (``amp_model_set_z2``); targets
