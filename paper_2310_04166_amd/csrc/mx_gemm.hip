@@ -14,8 +14,6 @@
 // than in passes of their own over C.
 #include "ops.h"
 
-#include "act.h"
-
 namespace nqs {
 namespace {
 
@@ -43,6 +41,27 @@ __device__ inline void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo) {
     lo[i] = l[0];
     lo[i + 1] = l[1];
   }
+}
+
+// The tanh form of GELU, 0.5 x (1 + tanh u) with u = sqrt(2/pi) (x + 0.044715 x^3),
+// written as x s with s = 1 / (1 + e^{-2u}) (hardware exp2 and reciprocal,
+// about 1 ulp each), and its derivative s + 2 x s (1 - s) du/dx
+// (tanh u = 2 s - 1, 1 - tanh^2 u = 4 s (1 - s)).
+constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
+__device__ inline float gelu_sig(float x, float &s) {
+  const float e = __builtin_amdgcn_exp2f(-2.0f * 1.4426950408889634f * kGeluC * x *
+                                         fmaf(0.044715f, x * x, 1.0f));
+  s = __builtin_amdgcn_rcpf(1.0f + e);
+  return x * s;
+}
+__device__ inline float gelu_fast(float x) {
+  float s;
+  return gelu_sig(x, s);
+}
+__device__ inline float gelu_grad_fast(float x) {
+  float s;
+  gelu_sig(x, s);
+  return fmaf(2.0f * x * s * (1.0f - s), kGeluC * fmaf(3.0f * 0.044715f, x * x, 1.0f), s);
 }
 
 __device__ inline f32x16 mfma(const bf16x8 &a, const bf16x8 &b, const f32x16 &c) {
@@ -189,9 +208,9 @@ mx_gemm_kernel(MxArgs a) {
           cb[rv * a.ldc] = in[v] + x;
         } else if (EPI == MX_GELU) {
           xb[rv * a.ldc] = x;
-          cb[rv * a.ldc] = gelu_tanh(x);
+          cb[rv * a.ldc] = gelu_fast(x);
         } else {
-          cb[rv * a.ldc] = x * gelu_tanh_grad(in[v]);
+          cb[rv * a.ldc] = x * gelu_grad_fast(in[v]);
         }
       }
       acc[t] = f32x16{};

@@ -646,6 +646,219 @@ __global__ void __launch_bounds__(IPB * 16) attention_bwd16_kernel(const T *qkv,
   }
 }
 
+// Short sequences with head dimension 16 (T <= 16 positions): one block per
+// S whole sequences and all H heads.  A sequence's rows are contiguous, so the
+// block's q, k, v rows (and, for the backward, dO rows) are one contiguous
+// range, loaded into LDS with 16-byte loads; lane (sequence s, head h,
+// position t) then works from LDS (the 16 lanes of a head read the same key
+// row at a time), and the outputs go back through LDS to 16-byte stores.
+// The backward recomputes the probabilities from q and k with the forward's
+// arithmetic, so no probability array is kept.
+constexpr int kSeqPad = 4;   // LDS row padding (elements), rows stay 16-byte aligned
+
+template <class T>
+struct Vec16 {
+  typedef __attribute__((ext_vector_type(16 / sizeof(T)))) T type;
+};
+
+// n elements (a multiple of the vector width) between global and LDS rows of
+// w elements (LDS row stride ld)
+template <class T, bool TO_LDS>
+__device__ inline void seq_copy(T *sm, int ld, T *g, int64_t n, int w) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VW = 16 / sizeof(T);
+  for (int64_t i = threadIdx.x; i * VW < n; i += blockDim.x) {
+    const int64_t e = i * VW;
+    const int row = int(e / w), col = int(e % w);
+    V *l = reinterpret_cast<V *>(sm + row * ld + col);
+    V *q = reinterpret_cast<V *>(g + e);
+    if (TO_LDS) *l = *q;
+    else *q = *l;
+  }
+}
+
+// scores of query row t against key rows u <= t, softmax; p[u] = 0 above t
+template <class T>
+__device__ inline void seq_probs(const T (&q)[16], const T *krow0, int ld, int t, T scale,
+                                 T (&p)[16]) {
+  T mx = T(-1e300);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    T a = 0;
+    if (u <= t) {
+      const T *k = krow0 + u * ld;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a += q[j] * k[j];
+    }
+    p[u] = a * scale;
+    if (u <= t) mx = p[u] > mx ? p[u] : mx;
+  }
+  T z = 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    p[u] = u <= t ? exp(p[u] - mx) : T(0);
+    z += p[u];
+  }
+  const T iz = T(1) / z;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) p[u] *= iz;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) attention_fwd_seq_kernel(const T *__restrict__ qkv,
+                                                                int64_t B, int T_, int d, int H,
+                                                                int S, T *__restrict__ o) {
+  extern __shared__ __attribute__((aligned(16))) char seq_smem[];
+  T *sm = reinterpret_cast<T *>(seq_smem);
+  const int ld = 3 * d + kSeqPad;
+  const int64_t b0 = int64_t(blockIdx.x) * S;
+  const int nseq = B - b0 < S ? int(B - b0) : S;
+  seq_copy<T, true>(sm, ld, const_cast<T *>(qkv) + b0 * T_ * 3 * d, int64_t(nseq) * T_ * 3 * d,
+                    3 * d);
+  __syncthreads();
+  const int sq = int(threadIdx.x) / (H * 16), h = (int(threadIdx.x) / 16) % H,
+            t = int(threadIdx.x) % 16;
+  const bool ok = sq < nseq && t < T_;
+  T acc[16];
+  if (ok) {
+    const T *base = sm + (sq * T_) * ld + h * 16;
+    T q[16], p[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) q[j] = base[t * ld + j];
+    seq_probs<T>(q, base + d, ld, t, T(0.25), p);   // 1 / sqrt(16)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (u > t) continue;
+      const T *v = base + u * ld + 2 * d;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] += p[u] * v[j];
+    }
+  }
+  __syncthreads();   // every lane has read the q rows
+  if (ok) {
+    T *dst = sm + (sq * T_ + t) * ld + h * 16;   // the lane's own q slot
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dst[j] = acc[j];
+  }
+  __syncthreads();
+  seq_copy<T, false>(sm, ld, o + b0 * T_ * d, int64_t(nseq) * T_ * d, d);
+}
+
+// LDS: rows of q, k, v (3d) and dO (d), then per (sequence, head) the 16 x 17
+// probabilities and score gradients
+template <class T>
+__global__ void __launch_bounds__(256) attention_bwd_seq_kernel(const T *__restrict__ qkv,
+                                                                const T *__restrict__ dout,
+                                                                int64_t B, int T_, int d, int H,
+                                                                int S, T *__restrict__ dqkv) {
+  extern __shared__ __attribute__((aligned(16))) char seq_smem[];
+  T *sm = reinterpret_cast<T *>(seq_smem);
+  const int ld = 3 * d + kSeqPad, ldo = d + kSeqPad;
+  T *so = sm + S * 16 * ld;                    // dO rows
+  T *sp = so + S * 16 * ldo;                   // [S][H][16][17] probabilities
+  T *sd = sp + S * H * 16 * 17;                // [S][H][16][17] score gradients
+  const int64_t b0 = int64_t(blockIdx.x) * S;
+  const int nseq = B - b0 < S ? int(B - b0) : S;
+  seq_copy<T, true>(sm, ld, const_cast<T *>(qkv) + b0 * T_ * 3 * d, int64_t(nseq) * T_ * 3 * d,
+                    3 * d);
+  seq_copy<T, true>(so, ldo, const_cast<T *>(dout) + b0 * T_ * d, int64_t(nseq) * T_ * d, d);
+  __syncthreads();
+  const int sq = int(threadIdx.x) / (H * 16), h = (int(threadIdx.x) / 16) % H,
+            t = int(threadIdx.x) % 16;
+  const bool ok = sq < nseq && t < T_;
+  const T *base = sm + (sq * T_) * ld + h * 16;    // q of position 0, head h
+  const T *obase = so + (sq * T_) * ldo + h * 16;  // dO of position 0, head h
+  T *P = sp + (sq * H + h) * 16 * 17, *dS = sd + (sq * H + h) * 16 * 17;
+  const T scale = T(0.25);
+  T gq[16];
+  if (ok) {
+    T q[16], p[16], dO[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      q[j] = base[t * ld + j];
+      dO[j] = obase[t * ldo + j];
+    }
+    seq_probs<T>(q, base + d, ld, t, scale, p);
+    // dS[t][u] = P[t][u] (dO[t] . V[u] - sum_w P[t][w] dO[t] . V[w])
+    T dp[16], rowdot = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      T a = 0;
+      if (u <= t) {
+        const T *v = base + u * ld + 2 * d;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a += dO[j] * v[j];
+      }
+      dp[u] = a;
+      rowdot += a * p[u];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gq[j] = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const T ds = p[u] * (dp[u] - rowdot);
+      P[t * 17 + u] = p[u];
+      dS[t * 17 + u] = ds;
+      if (u > t) continue;
+      const T *k = base + u * ld + d;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) gq[j] += ds * k[j];   // dQ[t] = sum_u dS[t,u] K[u]
+    }
+  }
+  __syncthreads();
+  T gk[16], gv[16];
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gk[j] = gv[j] = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (u < t || u >= T_) continue;
+      const T ds = dS[u * 17 + t], pu = P[u * 17 + t];
+      const T *q = base + u * ld, *dO = obase + u * ldo;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        gk[j] += ds * q[j];    // dK[t] = sum_u dS[u,t] Q[u]
+        gv[j] += pu * dO[j];   // dV[t] = sum_u P[u,t] dO[u]
+      }
+    }
+  }
+  __syncthreads();   // every lane has read the q, k, v rows
+  if (ok) {
+    T *dst = sm + (sq * T_ + t) * ld + h * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      dst[j] = gq[j] * scale;
+      dst[d + j] = gk[j] * scale;
+      dst[2 * d + j] = gv[j];
+    }
+  }
+  __syncthreads();
+  seq_copy<T, false>(sm, ld, dqkv + b0 * T_ * 3 * d, int64_t(nseq) * T_ * 3 * d, 3 * d);
+}
+
+// sequences per block of the seq kernels: all heads of S sequences in at most
+// 256 lanes and 64 KiB of LDS (0: the shape does not fit them)
+template <class T>
+int seq_per_block(int T_, int d, int H, bool bwd) {
+  if (T_ > 16 || d != 16 * H || (3 * d * int(sizeof(T))) % 16 != 0) return 0;
+  const size_t per = size_t(16) * (3 * d + kSeqPad) * sizeof(T) +
+                     (bwd ? size_t(16) * (d + kSeqPad) * sizeof(T) + size_t(2) * H * 16 * 17 * sizeof(T)
+                          : 0);
+  int S = 256 / (16 * H);
+  while (S > 1 && per * S > 64 * 1024) --S;
+  return per * S <= 64 * 1024 && S >= 1 ? S : 0;
+}
+template <class T>
+size_t seq_lds_bytes(int T_, int d, int H, bool bwd, int S) {
+  (void)T_;
+  return size_t(S) * (size_t(16) * (3 * d + kSeqPad) * sizeof(T) +
+                      (bwd ? size_t(16) * (d + kSeqPad) * sizeof(T) +
+                                 size_t(2) * H * 16 * 17 * sizeof(T)
+                           : 0));
+}
+
 template <class T>
 __global__ void gelu_bwd_kernel(const T *pre, T *dy, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -874,6 +1087,16 @@ void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, c
 template <class T>
 void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s) {
   if (B <= 0) return;
+  // the seq kernels only where the backward fits them too: it recomputes the
+  // probabilities the seq forward does not write
+  if (seq_per_block<T>(T_, d, H, true) > 0) {
+    const int S = seq_per_block<T>(T_, d, H, false);
+    hipLaunchKernelGGL(attention_fwd_seq_kernel<T>, dim3(unsigned(ceil_div(B, S))),
+                       dim3(unsigned(S * H * 16)), seq_lds_bytes<T>(T_, d, H, false, S), s, qkv, B,
+                       T_, d, H, S, o);
+    HIP_LAUNCH_OK();
+    return;
+  }
   if (T_ <= 16 && d / H <= 16) {
     constexpr int IPB = sizeof(T) == 8 ? 8 : 16;
     hipLaunchKernelGGL((attention_fwd16_kernel<T, IPB>), dim3(unsigned(ceil_div(B * H, IPB))),
@@ -891,6 +1114,13 @@ template <class T>
 void attention_bwd(const T *qkv, const T *probs, const T *dout, int64_t B, int T_, int d, int H,
                    T *dqkv, hipStream_t s) {
   if (B <= 0) return;
+  if (const int S = seq_per_block<T>(T_, d, H, true)) {
+    hipLaunchKernelGGL(attention_bwd_seq_kernel<T>, dim3(unsigned(ceil_div(B, S))),
+                       dim3(unsigned(S * H * 16)), seq_lds_bytes<T>(T_, d, H, true, S), s, qkv,
+                       dout, B, T_, d, H, S, dqkv);
+    HIP_LAUNCH_OK();
+    return;
+  }
   if (T_ <= 16 && d / H <= 16) {
     constexpr int IPB = sizeof(T) == 8 ? 4 : 8;
     hipLaunchKernelGGL((attention_bwd16_kernel<T, IPB>), dim3(unsigned(ceil_div(B * H, IPB))),
