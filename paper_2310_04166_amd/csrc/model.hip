@@ -470,6 +470,40 @@ void bgrad(nqs_model &m, const T *dY, int64_t R, int64_t N, int64_t ld, int pidx
   colsum_acc<T>(dY, R, N, ld, m.grad_acc.as<double>() + m.off[pidx], part, s);
 }
 
+// layer-norm backward into dx with its gain and bias gradients (one kernel
+// where the width allows; else the row kernel, dy * xhat into tmp and two
+// column sums)
+template <class T>
+void lnbgrad(nqs_model &m, const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
+             const T *dy, T *dx, bool accumulate, T *tmp, int gidx, int bidx, hipStream_t s) {
+  if (layernorm_bwd_acc_supported(d)) {
+    double *scratch = static_cast<double *>(m.part.reserve(layernorm_bwd_acc_scratch_bytes(d)));
+    double *acc = m.grad_acc.as<double>();
+    layernorm_bwd_acc<T>(x, mean, rstd, R, d, g, dy, dx, accumulate, acc + m.off[gidx],
+                         acc + m.off[bidx], scratch, s);
+    return;
+  }
+  layernorm_bwd<T>(x, mean, rstd, R, d, g, dy, dx, accumulate, tmp, s);
+  bgrad<T>(m, tmp, R, d, d, gidx, s);
+  bgrad<T>(m, dy, R, d, d, bidx, s);
+}
+
+// a linear layer's dW += X^T dY and db += column sums of dY (mixed: in one kernel)
+template <class T>
+void wbgrad(nqs_model &m, int64_t Mi, int64_t No, int64_t R, const T *X, int64_t ldx, const T *dY,
+            int64_t ldy, int widx, int bidx, hipStream_t s, bool mixed) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (mixed) {
+      void *part = m.part.reserve(wgrad_scratch_bytes(R, Mi, No, std::max(ldx, ldy), sizeof(T)));
+      double *acc = m.grad_acc.as<double>();
+      wgrad_acc(X, ldx, dY, ldy, R, Mi, No, acc + m.off[widx], part, s, true, acc + m.off[bidx]);
+      return;
+    }
+  }
+  wgrad<T>(m, Mi, No, R, X, ldx, dY, ldy, widx, s, mixed);
+  bgrad<T>(m, dY, R, No, ldy, bidx, s);
+}
+
 // mx: the weights' split images (bf16 models), else library products
 template <class T>
 void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double *gl,
@@ -508,51 +542,44 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   hipLaunchKernelGGL(dlogits_kernel<T>, g1(B), dim3(256), 0, s, x, B, n, A.logits, 4,
                      m.sectors(), gl, dl, 4);
   HIP_LAUNCH_OK();
-  wgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), s, mixed);
-  bgrad<T>(m, dl, R, 4, 4, tf_tail(L, TF_BHEAD), s);
+  wbgrad<T>(m, d, 4, R, A.hf, d, dl, 4, tf_tail(L, TF_WHEAD), tf_tail(L, TF_BHEAD), s, mixed);
   bgrad<T>(m, dl, B, int64_t(n) * 4, int64_t(n) * 4, tf_tail(L, TF_LBIAS), s);
   gemm<T, false, true>(R, d, 4, dl, 4, P<T>(m, tf_tail(L, TF_WHEAD)), 4, da, d, nullptr,
                           nullptr, EPI_STORE, s);
-  layernorm_bwd<T>(A.h_out, A.mf, A.rf, R, d, P<T>(m, tf_tail(L, TF_LNFG)), da, dh, false, tmp, s);
-  bgrad<T>(m, tmp, R, d, d, tf_tail(L, TF_LNFG), s);
-  bgrad<T>(m, da, R, d, d, tf_tail(L, TF_LNFB), s);
+  lnbgrad<T>(m, A.h_out, A.mf, A.rf, R, d, P<T>(m, tf_tail(L, TF_LNFG)), da, dh, false, tmp,
+             tf_tail(L, TF_LNFG), tf_tail(L, TF_LNFB), s);
 
   for (int l = L - 1; l >= 0; --l) {
     Layer<T> &y = A.layer[l];
     auto W = [&](int k) { return P<T>(m, tf_layer(l, k)); };
     const MxPack::Layer *p = mixed ? &mx->layer[size_t(l)] : nullptr;
     // h_out = h_mid + gelu(a2 W1 + b1) W2 + b2
-    wgrad<T>(m, F, d, R, y.f, F, dh, d, tf_layer(l, TF_W2), s, mixed);
-    bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_B2), s);
+    wbgrad<T>(m, F, d, R, y.f, F, dh, d, tf_layer(l, TF_W2), tf_layer(l, TF_B2), s, mixed);
     if (p) {
       mxg<T>(R, F, d, dh, d, p->w2T, df, F, nullptr, 0, nullptr, y.fpre, MX_DGELU, s);
     } else {
       gemm<T, false, true>(R, F, d, dh, d, W(TF_W2), d, df, F, nullptr, nullptr, EPI_STORE, s);
       gelu_bwd<T>(y.fpre, df, R * F, s);
     }
-    wgrad<T>(m, d, F, R, y.a2, d, df, F, tf_layer(l, TF_W1), s, mixed);
-    bgrad<T>(m, df, R, F, F, tf_layer(l, TF_B1), s);
+    wbgrad<T>(m, d, F, R, y.a2, d, df, F, tf_layer(l, TF_W1), tf_layer(l, TF_B1), s, mixed);
     if (p) mxg<T>(R, d, F, df, F, p->w1T, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
     else gemm<T, false, true>(R, d, F, df, F, W(TF_W1), F, da, d, nullptr, nullptr, EPI_STORE, s);
-    layernorm_bwd<T>(y.h_mid, y.m2, y.r2, R, d, W(TF_LN2G), da, dh, true, tmp, s);
-    bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN2G), s);
-    bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN2B), s);
+    lnbgrad<T>(m, y.h_mid, y.m2, y.r2, R, d, W(TF_LN2G), da, dh, true, tmp, tf_layer(l, TF_LN2G),
+               tf_layer(l, TF_LN2B), s);
     // h_mid = h_in + attn(a1) Wo + bo
-    wgrad<T>(m, d, d, R, y.o, d, dh, d, tf_layer(l, TF_WO), s, mixed);
-    bgrad<T>(m, dh, R, d, d, tf_layer(l, TF_BO), s);
+    wbgrad<T>(m, d, d, R, y.o, d, dh, d, tf_layer(l, TF_WO), tf_layer(l, TF_BO), s, mixed);
     if (p) mxg<T>(R, d, d, dh, d, p->oT, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
     else gemm<T, false, true>(R, d, d, dh, d, W(TF_WO), d, da, d, nullptr, nullptr, EPI_STORE, s);
     attention_bwd<T>(y.qkv, y.probs, da, B, n, d, H, dq, s);
-    wgrad<T>(m, d, 3 * d, R, y.a1, d, dq, 3 * d, tf_layer(l, TF_WQKV), s, mixed);
-    bgrad<T>(m, dq, R, 3 * d, 3 * d, tf_layer(l, TF_BQKV), s);
+    wbgrad<T>(m, d, 3 * d, R, y.a1, d, dq, 3 * d, tf_layer(l, TF_WQKV), tf_layer(l, TF_BQKV), s,
+              mixed);
     if (p)
       mxg<T>(R, d, 3 * d, dq, 3 * d, p->qkvT, da, d, nullptr, 0, nullptr, nullptr, MX_STORE, s);
     else
       gemm<T, false, true>(R, d, 3 * d, dq, 3 * d, W(TF_WQKV), 3 * d, da, d, nullptr, nullptr,
                               EPI_STORE, s);
-    layernorm_bwd<T>(y.h_in, y.m1, y.r1, R, d, W(TF_LN1G), da, dh, true, tmp, s);
-    bgrad<T>(m, tmp, R, d, d, tf_layer(l, TF_LN1G), s);
-    bgrad<T>(m, da, R, d, d, tf_layer(l, TF_LN1B), s);
+    lnbgrad<T>(m, y.h_in, y.m1, y.r1, R, d, W(TF_LN1G), da, dh, true, tmp, tf_layer(l, TF_LN1G),
+               tf_layer(l, TF_LN1B), s);
   }
   // embeddings: token table through the one-hot input classes, positions by column sums
   hipLaunchKernelGGL(in_class_kernel<T>, g1(R * 5), dim3(256), 0, s, x, B, n, tmp);
@@ -568,8 +595,7 @@ void tf_backward_chunk(nqs_model &m, const uint64_t *x, int64_t B, const double 
   wgrad<T>(m, PH, 1, B, A.z2, PH, gpt, 1, tf_tail(L, TF_PW3), s, mixed);
   bgrad<T>(m, gpt, B, 1, 1, tf_tail(L, TF_PB3), s);
   gelu_bwd<T>(A.z2pre, dz2, B * PH, s);
-  wgrad<T>(m, PH, PH, B, A.z1, PH, dz2, PH, tf_tail(L, TF_PW2), s, mixed);
-  bgrad<T>(m, dz2, B, PH, PH, tf_tail(L, TF_PB2), s);
+  wbgrad<T>(m, PH, PH, B, A.z1, PH, dz2, PH, tf_tail(L, TF_PW2), tf_tail(L, TF_PB2), s, mixed);
   if (mixed) {
     mxg<T>(B, PH, PH, dz2, PH, mx->pw2T, dz1, PH, nullptr, 0, nullptr, A.z1pre, MX_DGELU, s);
   } else {
@@ -1208,8 +1234,10 @@ int64_t chunk_rows(const nqs_model &m, bool bwd) {
                                                 : (8 * m.d + 2 * m.F + 8)) + 6 * m.PH;
   int64_t c = m.act_budget / (per * int64_t(sizeof(T)));
   // at most 128k token rows: measured fastest for the library GEMMs of both transformer
-  // workloads (64k and 320k rows are 5-25 % slower per step)
-  c = std::min<int64_t>(c, m.kind == NQS_MODEL_NADE ? 65536 : 131072 / m.n);
+  // workloads (64k and 320k rows are 5-25 % slower per step); the split-bf16
+  // backward takes up to 512k rows (fewer launches)
+  const bool mx = bwd && m.mixed_backward && mx_backward_ok(m);
+  c = std::min<int64_t>(c, m.kind == NQS_MODEL_NADE ? 65536 : (mx ? 524288 : 131072) / m.n);
   return c < 64 ? 64 : c;
 }
 

@@ -236,12 +236,15 @@ constexpr int kWLds = kWRows + 8;     // bf16 per LDS column of a slab (padded)
 // offset), so rows past it read as zeros; a column past M (N) reads whatever
 // lies there in the slice (the next row's entries, or zero past its end),
 // which only feeds accumulator rows (columns) that are never stored.  The
-// host keeps a slice under 1 GiB of either matrix.
+// host keeps a slice under 1 GiB of either matrix.  With bpart, the blocks of
+// the first row of output tiles also sum dY's columns over the slice from the
+// fp32 values they load (double sums in a fixed order): bpart[z][j].
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 mx_wgrad_kernel(const float *__restrict__ X, int64_t ldx, const float *__restrict__ dY,
                 int64_t ldy, int64_t R, int M, int N, int64_t rows_per, int tiles_n,
-                float *__restrict__ part) {
+                float *__restrict__ part, double *__restrict__ bpart) {
   __shared__ __attribute__((aligned(16))) __bf16 sW[4][128 * kWLds];   // X hi, X lo, dY hi, dY lo
+  __shared__ double sbias[128];
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64, c = lane % 32, kg = lane / 32;
   const int tm = int(blockIdx.x) / tiles_n, tn = int(blockIdx.x) % tiles_n;
   const int i0 = tm * 128, j0 = tn * 128;
@@ -283,9 +286,15 @@ mx_wgrad_kernel(const float *__restrict__ X, int64_t ldx, const float *__restric
     }
   };
   f32x16 acc[2][2] = {};
+  const bool bias = bpart && tm == 0;
+  double bsum = 0.0;
   const int nslab = (rows + kWRows - 1) / kWRows;
   load(0);
   for (int g = 0; g < nslab; ++g) {
+    if (bias) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) bsum += double(vy[u]);
+    }
     store();
     __syncthreads();
     if (g + 1 < nslab) load((g + 1) * kWRows);
@@ -311,6 +320,11 @@ mx_wgrad_kernel(const float *__restrict__ X, int64_t ldx, const float *__restric
         }
     }
     __syncthreads();
+  }
+  if (bias) {   // the two row groups of each column: sr = 16 into LDS, sr = 0 adds
+    if (sr != 0) sbias[sc] = bsum;
+    __syncthreads();
+    if (sr == 0 && j0 + sc < N) bpart[int64_t(blockIdx.y) * N + j0 + sc] = bsum + sbias[sc];
   }
   float *pz = part + int64_t(blockIdx.y) * M * N;
 #pragma unroll
@@ -371,12 +385,13 @@ void mx_gemm(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const
 }
 
 void mx_wgrad_partials(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
-                       int64_t M, int64_t N, int64_t rows_per, float *part, hipStream_t s) {
+                       int64_t M, int64_t N, int64_t rows_per, float *part, double *bpart,
+                       hipStream_t s) {
   const int tiles_n = int(ceil_div(N, int64_t(128)));
   const int64_t tiles = ceil_div(M, int64_t(128)) * tiles_n;
   const dim3 grid = dim3(unsigned(tiles), unsigned(ceil_div(R, rows_per)));
   hipLaunchKernelGGL(mx_wgrad_kernel, grid, dim3(256), 0, s, X, ldx, dY, ldy, R, int(M), int(N),
-                     rows_per, tiles_n, part);
+                     rows_per, tiles_n, part, bpart);
   HIP_LAUNCH_OK();
 }
 

@@ -45,9 +45,10 @@ size_t colsum_scratch_bytes(int64_t R, int64_t N);
 // whose partial sums are added in a fixed order; FP64: a library GEMM.  scratch
 // holds at least wgrad_scratch_bytes(R, M, N, max(ldx, ldy), element size) bytes.
 // mixed: the partial sums take split bf16 operands (mx_wgrad_partials) instead
-// of fp32 MFMA.
+// of fp32 MFMA, and with bias_acc also bias_acc[j] += sum_r dY[r*ldy + j].
 void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R, int64_t M,
-               int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed = false);
+               int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed = false,
+               double *bias_acc = nullptr);
 void wgrad_acc(const double *X, int64_t ldx, const double *dY, int64_t ldy, int64_t R, int64_t M,
                int64_t N, double *acc, void *scratch, hipStream_t s);
 size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t elem);
@@ -77,9 +78,11 @@ void mx_gemm(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const
              int64_t ldc, const float *res, int64_t ldr, const float *bias, float *aux, int epi,
              hipStream_t s);
 // part[z][i][j] = sum over rows r of slice z (rows z*rows_per ..) of
-// X[r][i] dY[r][j], i < M, j < N; a slice under 1 GiB of either matrix.
+// X[r][i] dY[r][j], i < M, j < N; a slice under 1 GiB of either matrix; with
+// bpart (optional) also bpart[z][j] = sum over those rows of dY[r][j] (double).
 void mx_wgrad_partials(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
-                       int64_t M, int64_t N, int64_t rows_per, float *part, hipStream_t s);
+                       int64_t M, int64_t N, int64_t rows_per, float *part, double *bpart,
+                       hipStream_t s);
 
 // Row-wise layer norm over d columns; mean/rstd may be null.
 template <class T>
@@ -89,6 +92,16 @@ void layernorm(const T *x, int64_t R, int d, const T *g, const T *b, T *y, T *me
 template <class T>
 void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
                    const T *dy, T *dx, bool accumulate, T *dyxh, hipStream_t s);
+
+// The same with the layer norm's parameter gradients: gacc[j] += sum_r dy *
+// xhat, bacc[j] += sum_r dy (double, fixed order), for d = 64 or 128;
+// scratch holds layernorm_bwd_acc_scratch_bytes(d) bytes.
+bool layernorm_bwd_acc_supported(int d);
+size_t layernorm_bwd_acc_scratch_bytes(int d);
+template <class T>
+void layernorm_bwd_acc(const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
+                       const T *dy, T *dx, bool accumulate, double *gacc, double *bacc,
+                       double *scratch, hipStream_t s);
 
 // Causal attention for B sequences of T tokens: qkv [B*T, 3d] -> o [B*T, d],
 // probs [B, H, T, T] (if non-null; not written for head dimension 16,

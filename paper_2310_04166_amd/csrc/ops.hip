@@ -429,6 +429,67 @@ __global__ void __launch_bounds__(256) layernorm_bwd_kernel(const T *x, const T 
   }
 }
 
+// The layer-norm backward with its parameters' gradients: rows of a block's
+// contiguous range taken by its four waves in turn (wave w: rows w, w + 4, ..),
+// each lane owning columns lane + 64 k (k < CPL); per-lane double sums of
+// dy * xhat (gain) and dy (bias) over the rows, combined over the waves in
+// order into gpart[block][j], bpart[block][j].
+template <class T, int CPL>
+__global__ void __launch_bounds__(256) layernorm_bwd_acc_kernel(
+    const T *__restrict__ x, const T *__restrict__ mean, const T *__restrict__ rstd, int64_t R,
+    int64_t rows_per, const T *__restrict__ g, const T *__restrict__ dy, T *__restrict__ dx,
+    bool accumulate, double *__restrict__ gpart, double *__restrict__ bpart) {
+  constexpr int d = 64 * CPL;
+  __shared__ double red[2][4][d];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int64_t r0 = int64_t(blockIdx.x) * rows_per;
+  const int64_t r1 = r0 + rows_per < R ? r0 + rows_per : R;
+  double ga[CPL], ba[CPL];
+  T gj[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    ga[k] = ba[k] = 0.0;
+    gj[k] = g[lane + 64 * k];
+  }
+  for (int64_t r = r0 + w; r < r1; r += 4) {
+    const T mu = mean[r], rs = rstd[r];
+    T xh[CPL], dyv[CPL], s1 = 0, s2 = 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int64_t e = r * d + lane + 64 * k;
+      xh[k] = (x[e] - mu) * rs;
+      dyv[k] = dy[e];
+      const T gy = dyv[k] * gj[k];
+      s1 += gy;
+      s2 += gy * xh[k];
+      ga[k] += double(dyv[k] * xh[k]);
+      ba[k] += double(dyv[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s1 += __shfl_xor(s1, o);
+      s2 += __shfl_xor(s2, o);
+    }
+    s1 /= T(d);
+    s2 /= T(d);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int64_t e = r * d + lane + 64 * k;
+      const T v = rs * (dyv[k] * gj[k] - s1 - xh[k] * s2);
+      dx[e] = accumulate ? dx[e] + v : v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    red[0][w][lane + 64 * k] = ga[k];
+    red[1][w][lane + 64 * k] = ba[k];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < d; j += 256) {
+    gpart[int64_t(blockIdx.x) * d + j] = ((red[0][0][j] + red[0][1][j]) + red[0][2][j]) + red[0][3][j];
+    bpart[int64_t(blockIdx.x) * d + j] = ((red[1][0][j] + red[1][1][j]) + red[1][2][j]) + red[1][3][j];
+  }
+}
+
 // One 64-lane block per (sequence, head); T_ <= 32, dh <= 64.
 template <class T>
 __global__ void __launch_bounds__(64) attention_fwd_kernel(const T *qkv, int T_, int d, int H,
@@ -1030,13 +1091,16 @@ int64_t wgrad_slices(int64_t R, int64_t M, int64_t N, int64_t ld) {
 
 size_t wgrad_scratch_bytes(int64_t R, int64_t M, int64_t N, int64_t ld, size_t elem) {
   if (elem == sizeof(double)) return size_t(M * N) * sizeof(double);
-  // float partials, then the second level of the reduction (8-byte aligned)
-  return size_t(ceil_div(wgrad_slices(R, M, N, ld) * M * N, int64_t(2))) * 8 +
-         size_t(kLevelElems) * sizeof(double);
+  // float partials, the second level of the reduction (8-byte aligned), then
+  // the mixed kernel's column sums (double)
+  const int64_t z = wgrad_slices(R, M, N, ld);
+  return size_t(ceil_div(z * M * N, int64_t(2))) * 8 + size_t(kLevelElems) * sizeof(double) +
+         size_t(z * N) * sizeof(double);
 }
 
 void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_t R,
-                      int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed) {
+                      int64_t M, int64_t N, double *acc, void *scratch, hipStream_t s, bool mixed,
+                      double *bias_acc) {
   if (M <= 0 || N <= 0) return;
   NQS_REQUIRE(M < (int64_t(1) << 24) && N < (int64_t(1) << 24), NQS_EUNSUPPORTED,
               "weight gradient: dimension too large");
@@ -1048,15 +1112,18 @@ void wgrad_acc(const float *X, int64_t ldx, const float *dY, int64_t ldy, int64_
   const int64_t tiles = ceil_div(M, int64_t(128)) * tiles_n;
   const dim3 grid = dim3(unsigned(tiles), unsigned(ceil_div(R, rows_per)));
   float *part = static_cast<float *>(scratch);
+  double *lvl = static_cast<double *>(scratch) + ceil_div(z * M * N, int64_t(2));
+  double *bpart = lvl + kLevelElems;
+  NQS_REQUIRE(!bias_acc || mixed, NQS_EINVAL, "weight gradient: bias sums need the mixed kernel");
   if (mixed) {
-    mx_wgrad_partials(X, ldx, dY, ldy, R, M, N, rows_per, part, s);
+    mx_wgrad_partials(X, ldx, dY, ldy, R, M, N, rows_per, part, bias_acc ? bpart : nullptr, s);
   } else {
     hipLaunchKernelGGL(wgrad_f32_kernel, grid, dim3(256), 0, s, X, ldx, dY, ldy, R, int(M), int(N),
                        rows_per, tiles_n, part);
     HIP_LAUNCH_OK();
   }
-  double *lvl = static_cast<double *>(scratch) + ceil_div(z * M * N, int64_t(2));
   reduce_slices<float>(part, int64_t(grid.y), M * N, acc, lvl, s);
+  if (bias_acc) reduce_slices<double>(bpart, int64_t(grid.y), N, bias_acc, lvl, s);
 }
 
 void wgrad_acc(const double *X, int64_t ldx, const double *dY, int64_t ldy, int64_t R,
@@ -1082,6 +1149,35 @@ void layernorm_bwd(const T *x, const T *mean, const T *rstd, int64_t R, int d, c
   hipLaunchKernelGGL(layernorm_bwd_kernel<T>, grid1(R, 4), dim3(256), 0, s, x, mean, rstd, R, d, g,
                      dy, dx, accumulate, dyxh);
   HIP_LAUNCH_OK();
+}
+
+namespace {
+constexpr int64_t kLnBlocks = 1024;   // row ranges of the layer-norm backward's sums
+}
+
+bool layernorm_bwd_acc_supported(int d) { return d == 64 || d == 128; }
+
+size_t layernorm_bwd_acc_scratch_bytes(int d) {
+  return size_t(2 * kLnBlocks * d + kLevelElems) * sizeof(double);
+}
+
+template <class T>
+void layernorm_bwd_acc(const T *x, const T *mean, const T *rstd, int64_t R, int d, const T *g,
+                       const T *dy, T *dx, bool accumulate, double *gacc, double *bacc,
+                       double *scratch, hipStream_t s) {
+  if (R <= 0) return;
+  NQS_REQUIRE(layernorm_bwd_acc_supported(d), NQS_EUNSUPPORTED, "layer norm backward: d");
+  const int64_t rows_per = ceil_div(R, kLnBlocks), blocks = ceil_div(R, rows_per);
+  double *gpart = scratch, *bpart = scratch + kLnBlocks * d, *lvl = scratch + 2 * kLnBlocks * d;
+  if (d == 64)
+    hipLaunchKernelGGL((layernorm_bwd_acc_kernel<T, 1>), dim3(unsigned(blocks)), dim3(256), 0, s, x,
+                       mean, rstd, R, rows_per, g, dy, dx, accumulate, gpart, bpart);
+  else
+    hipLaunchKernelGGL((layernorm_bwd_acc_kernel<T, 2>), dim3(unsigned(blocks)), dim3(256), 0, s, x,
+                       mean, rstd, R, rows_per, g, dy, dx, accumulate, gpart, bpart);
+  HIP_LAUNCH_OK();
+  reduce_slices<double>(gpart, blocks, d, gacc, lvl, s);
+  reduce_slices<double>(bpart, blocks, d, bacc, lvl, s);
 }
 
 template <class T>
@@ -1173,6 +1269,9 @@ void zero_async(void *p, size_t bytes, hipStream_t s) {
                              hipStream_t);                                                       \
   template void layernorm_bwd<T>(const T *, const T *, const T *, int64_t, int, const T *,      \
                                  const T *, T *, bool, T *, hipStream_t);                        \
+  template void layernorm_bwd_acc<T>(const T *, const T *, const T *, int64_t, int, const T *,  \
+                                     const T *, T *, bool, double *, double *, double *,          \
+                                     hipStream_t);                                                \
   template void attention_fwd<T>(const T *, int64_t, int, int, int, T *, T *, hipStream_t);     \
   template void attention_bwd<T>(const T *, const T *, const T *, int64_t, int, int, int, T *,  \
                                  hipStream_t);                                                   \
