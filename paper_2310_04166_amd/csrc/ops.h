@@ -104,9 +104,9 @@ void layernorm_bwd_acc(const T *x, const T *mean, const T *rstd, int64_t R, int 
                        double *scratch, hipStream_t s);
 
 // Causal attention for B sequences of T tokens: qkv [B*T, 3d] -> o [B*T, d],
-// probs [B, H, T, T] (if non-null; not written for head dimension 16,
-// T <= 16 and a backward that fits 64 KiB of LDS per block: there the
-// backward recomputes them and ignores probs).
+// probs [B, H, T, T] (if non-null; not written for head dimension 16 and
+// T <= 16 in fp32, nor in fp64 where the backward fits 64 KiB of LDS per
+// block: there the backward recomputes them and ignores probs).
 template <class T>
 void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s);
 template <class T>

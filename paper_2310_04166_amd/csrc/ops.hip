@@ -10,6 +10,7 @@
 #include <rocblas/rocblas.h>
 
 #include <array>
+#include <type_traits>
 #include <functional>
 #include <map>
 
@@ -399,6 +400,49 @@ __global__ void __launch_bounds__(256) layernorm_kernel(const T *x, int64_t R, i
   }
 }
 
+// d = 64 CPL: a wave normalises RPW consecutive rows, all their loads issued
+// before the first reduction (lane: columns lane + 64 k); the same arithmetic
+// as layernorm_kernel per row.
+template <class T, int CPL, int RPW>
+__global__ void __launch_bounds__(256) layernorm_rows_kernel(const T *__restrict__ x, int64_t R,
+                                                             const T *__restrict__ g,
+                                                             const T *__restrict__ b,
+                                                             T *__restrict__ y, T *__restrict__ mean,
+                                                             T *__restrict__ rstd) {
+  constexpr int d = 64 * CPL;
+  const int lane = threadIdx.x % 64;
+  const int64_t r0 = (int64_t(blockIdx.x) * 4 + threadIdx.x / 64) * RPW;
+  if (r0 >= R) return;
+  T v[RPW][CPL];
+#pragma unroll
+  for (int q = 0; q < RPW; ++q)
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) v[q][k] = r0 + q < R ? x[(r0 + q) * d + lane + 64 * k] : T(0);
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    if (r0 + q >= R) break;
+    T sum = 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) sum += v[q][k];
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    const T mu = sum / T(d);
+    T var = 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) var += (v[q][k] - mu) * (v[q][k] - mu);
+    for (int o = 32; o > 0; o >>= 1) var += __shfl_xor(var, o);
+    const T rs = T(1) / sqrt(var / T(d) + T(1e-5));
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int j = lane + 64 * k;
+      y[(r0 + q) * d + j] = (v[q][k] - mu) * rs * g[j] + b[j];
+    }
+    if (lane == 0) {
+      if (mean) mean[r0 + q] = mu;
+      if (rstd) rstd[r0 + q] = rs;
+    }
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) layernorm_bwd_kernel(const T *x, const T *mean,
                                                             const T *rstd, int64_t R, int d,
@@ -715,6 +759,7 @@ __global__ void __launch_bounds__(IPB * 16) attention_bwd16_kernel(const T *qkv,
 // row at a time), and the outputs go back through LDS to 16-byte stores.
 // The backward recomputes the probabilities from q and k with the forward's
 // arithmetic, so no probability array is kept.
+typedef __attribute__((ext_vector_type(4))) float f4;
 constexpr int kSeqPad = 4;   // LDS row padding (elements), rows stay 16-byte aligned
 
 template <class T>
@@ -897,6 +942,171 @@ __global__ void __launch_bounds__(256) attention_bwd_seq_kernel(const T *__restr
   }
   __syncthreads();
   seq_copy<T, false>(sm, ld, dqkv + b0 * T_ * 3 * d, int64_t(nseq) * T_ * 3 * d, 3 * d);
+}
+
+// fp32, head dimension 16, T <= 16: one 16-lane row of the wave per
+// (sequence, head), lane t holding position t's q, k, v (and dO) in registers;
+// position u's values reach the row's other lanes by the row broadcast of DPP
+// (row_newbcast:u), so no LDS is used.  The backward rebuilds the
+// probabilities and score gradients of column t (P[u][t], dS[u][t], u >= t)
+// from broadcasts of row u's q, dO and its softmax statistics.
+// row_newbcast writes every lane from a lane of its own row, so the DPP's
+// "old" operand never reaches the result; passing the running sum there ties
+// each broadcast to the sum it feeds, which keeps the compiler from hoisting
+// all 256 broadcasts of a loop (and spilling them)
+template <int U>
+__device__ inline float row_bcast(float v, float dep = 0.f) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dep),
+                                                               __builtin_bit_cast(int, v),
+                                                               0x150 + U, 0xF, 0xF, false));
+}
+
+// f(u) for u = 0..15 as constants, one u at a time (a scheduling barrier
+// between them keeps the broadcasts of one u live, not all 256)
+template <int U, class F>
+__device__ inline void for_u(F &&f) {
+  f(std::integral_constant<int, U>{});
+  if constexpr (U + 1 < 16) for_u<U + 1>(f);
+}
+
+__device__ inline void load16(const float *p, bool ok, float (&v)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f4 w = ok ? *reinterpret_cast<const f4 *>(p + 4 * q) : f4{0.f, 0.f, 0.f, 0.f};
+    v[4 * q] = w[0];
+    v[4 * q + 1] = w[1];
+    v[4 * q + 2] = w[2];
+    v[4 * q + 3] = w[3];
+  }
+}
+__device__ inline void store16(float *p, const float (&v)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    *reinterpret_cast<f4 *>(p + 4 * q) = f4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+}
+
+// row t's probabilities over u <= t, and the softmax statistics (max, sum)
+__device__ inline void row_probs(const float (&q)[16], const float (&k)[16], int t,
+                                 float (&p)[16], float &mx, float &z) {
+  for_u<0>([&](auto U) {
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a += q[j] * row_bcast<U>(k[j], a);
+    p[U] = a * 0.25f;   // 1 / sqrt(16)
+  });
+  mx = -INFINITY;
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    if (u <= t) mx = p[u] > mx ? p[u] : mx;
+  z = 0.f;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    p[u] = u <= t ? expf(p[u] - mx) : 0.f;
+    z += p[u];
+  }
+  const float iz = 1.f / z;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) p[u] *= iz;
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+attention_fwd_dpp_kernel(const float *__restrict__ qkv,
+                                                                int64_t n_items, int T_, int d,
+                                                                int H, float *__restrict__ o) {
+  const int t = int(threadIdx.x) % 16;
+  const int64_t item = int64_t(blockIdx.x) * 16 + threadIdx.x / 16;
+  const bool ok = item < n_items && t < T_;
+  const int64_t b = item / H;
+  const int h = int(item % H);
+  const float *row = qkv + (b * T_ + t) * 3 * d + h * 16;
+  float q[16], k[16], v[16], p[16], mx, z;
+  load16(row, ok, q);
+  load16(row + d, ok, k);
+  load16(row + 2 * d, ok, v);
+  row_probs(q, k, t, p, mx, z);
+  float acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  for_u<0>([&](auto U) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] += p[U] * row_bcast<U>(v[j], acc[j]);
+  });
+  if (ok) store16(o + (b * T_ + t) * d + h * 16, acc);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+attention_bwd_dpp_kernel(const float *__restrict__ qkv,
+                                                                const float *__restrict__ dout,
+                                                                int64_t n_items, int T_, int d,
+                                                                int H, float *__restrict__ dqkv) {
+  const int t = int(threadIdx.x) % 16;
+  const int64_t item = int64_t(blockIdx.x) * 16 + threadIdx.x / 16;
+  const bool ok = item < n_items && t < T_;
+  const int64_t b = item / H;
+  const int h = int(item % H);
+  const float *row = qkv + (b * T_ + t) * 3 * d + h * 16;
+  float q[16], k[16], v[16], dO[16], p[16], mx, z;
+  load16(row, ok, q);
+  load16(row + d, ok, k);
+  load16(row + 2 * d, ok, v);
+  load16(dout + (b * T_ + t) * d + h * 16, ok, dO);
+  row_probs(q, k, t, p, mx, z);
+  // row t: dS[t][u] = P[t][u] (dO[t] . V[u] - sum_w P[t][w] dO[t] . V[w]), dQ[t] = sum_u dS[t,u] K[u]
+  float ds[16], rowdot = 0.f;
+  for_u<0>([&](auto U) {
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a += dO[j] * row_bcast<U>(v[j], a);
+    ds[U] = a;
+    rowdot += a * p[U];
+  });
+#pragma unroll
+  for (int u = 0; u < 16; ++u) ds[u] = p[u] * (ds[u] - rowdot);
+  float *out = dqkv + (b * T_ + t) * 3 * d + h * 16;
+  {
+    float gq[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gq[j] = 0.f;
+    for_u<0>([&](auto U) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) gq[j] += ds[U] * row_bcast<U>(k[j], gq[j]);
+    });
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gq[j] *= 0.25f;
+    if (ok) store16(out, gq);
+  }
+  float gk[16], gv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) gk[j] = gv[j] = 0.f;
+  // column t: P[u][t] and dS[u][t] for t <= u < T from row u's broadcasts;
+  // dK[t] = sum_u dS[u,t] Q[u], dV[t] = sum_u P[u,t] dO[u]
+  for_u<0>([&](auto U) {
+    float qb[16], ob[16], sc = 0.f, dp = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      // each broadcast waits for the previous u's accumulation into the same
+      // feature (one u's broadcasts live at a time)
+      qb[j] = row_bcast<U>(q[j], gk[j]);
+      ob[j] = row_bcast<U>(dO[j], gv[j]);
+      sc += qb[j] * k[j];
+      dp += ob[j] * v[j];
+    }
+    const float mu = row_bcast<U>(mx, sc), zu = row_bcast<U>(z, sc), ru = row_bcast<U>(rowdot, dp);
+    const bool in = t <= U && U < T_;
+    const float put = in ? expf(sc * 0.25f - mu) / zu : 0.f;
+    const float dsut = in ? put * (dp - ru) : 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      gk[j] += dsut * qb[j];
+      gv[j] += put * ob[j];
+    }
+  });
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) gk[j] *= 0.25f;
+    store16(out + d, gk);
+    store16(out + 2 * d, gv);
+  }
 }
 
 // sequences per block of the seq kernels: all heads of S sequences in at most
@@ -1138,6 +1348,18 @@ template <class T>
 void layernorm(const T *x, int64_t R, int d, const T *g, const T *b, T *y, T *mean, T *rstd,
                hipStream_t s) {
   if (R <= 0) return;
+  constexpr int RPW = 4;
+  if (d == 64 || d == 128) {
+    const dim3 grid = grid1(ceil_div(R, RPW), 4);
+    if (d == 64)
+      hipLaunchKernelGGL((layernorm_rows_kernel<T, 1, RPW>), grid, dim3(256), 0, s, x, R, g, b, y,
+                         mean, rstd);
+    else
+      hipLaunchKernelGGL((layernorm_rows_kernel<T, 2, RPW>), grid, dim3(256), 0, s, x, R, g, b, y,
+                         mean, rstd);
+    HIP_LAUNCH_OK();
+    return;
+  }
   hipLaunchKernelGGL(layernorm_kernel<T>, grid1(R, 4), dim3(256), 0, s, x, R, d, g, b, y, mean, rstd);
   HIP_LAUNCH_OK();
 }
@@ -1183,6 +1405,14 @@ void layernorm_bwd_acc(const T *x, const T *mean, const T *rstd, int64_t R, int 
 template <class T>
 void attention_fwd(const T *qkv, int64_t B, int T_, int d, int H, T *o, T *probs, hipStream_t s) {
   if (B <= 0) return;
+  if (std::is_same<T, float>::value && T_ <= 16 && d == 16 * H) {
+    // fp32: the DPP kernels (the backward recomputes the probabilities)
+    hipLaunchKernelGGL(attention_fwd_dpp_kernel, dim3(unsigned(ceil_div(B * H, 16))), dim3(256), 0,
+                       s, reinterpret_cast<const float *>(qkv), B * H, T_, d, H,
+                       reinterpret_cast<float *>(o));
+    HIP_LAUNCH_OK();
+    return;
+  }
   // the seq kernels only where the backward fits them too: it recomputes the
   // probabilities the seq forward does not write
   if (seq_per_block<T>(T_, d, H, true) > 0) {
@@ -1210,6 +1440,13 @@ template <class T>
 void attention_bwd(const T *qkv, const T *probs, const T *dout, int64_t B, int T_, int d, int H,
                    T *dqkv, hipStream_t s) {
   if (B <= 0) return;
+  if (std::is_same<T, float>::value && T_ <= 16 && d == 16 * H) {
+    hipLaunchKernelGGL(attention_bwd_dpp_kernel, dim3(unsigned(ceil_div(B * H, 16))), dim3(256), 0,
+                       s, reinterpret_cast<const float *>(qkv), reinterpret_cast<const float *>(dout),
+                       B * H, T_, d, H, reinterpret_cast<float *>(dqkv));
+    HIP_LAUNCH_OK();
+    return;
+  }
   if (const int S = seq_per_block<T>(T_, d, H, true)) {
     hipLaunchKernelGGL(attention_bwd_seq_kernel<T>, dim3(unsigned(ceil_div(B, S))),
                        dim3(unsigned(S * H * 16)), seq_lds_bytes<T>(T_, d, H, true, S), s, qkv,
