@@ -143,8 +143,10 @@ def trained_check(nqs, torch, args, cfg):
     """A separate copy of the model after TRAIN_STEPS full VMC steps at Adam lr
     TRAIN_LR, so that the fp32 master weights have left the bf16 grid; the
     local energies of its cpu_sample highest-count samples on the bf16 and the
-    fp32 GPU paths.  Returns (configurations, counts, bf16 E_loc, fp32 E_loc,
-    the trained parameters as a dict, unique samples per training step)."""
+    fp32 GPU paths, and the energy estimator of both paths over its fp32_sample
+    highest-count samples plus as many drawn uniformly.  Returns
+    (configurations, counts, bf16 E_loc, fp32 E_loc, the trained parameters as
+    a dict, unique samples per training step, the estimator comparison)."""
     from synth import unflatten_params
     _, ham, m, _ = setup(args.workload, "bf16")
     dev = torch.device("cuda:0")
@@ -161,8 +163,24 @@ def trained_check(nqs, torch, args, cfg):
     params = m.get_params()
     m32 = nqs.Model(nqs.model_kind(cfg), nqs.model_dims(cfg), params, "fp32")
     e32, _, _ = nqs.local_energy(ham, m32, xs, cs)
+    order = torch.argsort(c, descending=True)
+    rng = np.random.default_rng(0)
+    pick = np.unique(np.concatenate([order[:args.fp32_sample].cpu().numpy(),
+                                     rng.choice(x.numel(), min(args.fp32_sample, x.numel()),
+                                                replace=False)]))
+    idx = torch.as_tensor(pick, device=x.device)
+    xe, ce = x[idx].contiguous(), c[idx].contiguous()
+    w = ce.cpu().numpy().astype(np.float64)
+    E = {}
+    for name, mm in (("bf16", m), ("fp32", m32)):
+        e, _, _ = nqs.local_energy(ham, mm, xe, ce)
+        E[name] = float(np.real(np.sum(w * e.cpu().numpy()) / np.sum(w)))
+    est = {"estimator_samples": int(xe.numel()), "estimator_counts": int(w.sum()),
+           "E_bf16_estimator": E["bf16"], "E_fp32_estimator": E["fp32"],
+           "abs_diff_bf16_fp32_estimator_ha": abs(E["bf16"] - E["fp32"])}
     return ([int(v) for v in xs.cpu().numpy().view(np.uint64)], cs.cpu().numpy().astype(np.float64),
-            e16.cpu().numpy(), e32.cpu().numpy(), unflatten_params(params, param_spec(cfg)), unique)
+            e16.cpu().numpy(), e32.cpu().numpy(), unflatten_params(params, param_spec(cfg)), unique,
+            est)
 
 
 def vmc_step(nqs, ham, model, cfg, seed, state, t, events=None):
@@ -614,7 +632,7 @@ def main():
                           "abs_diff_fp32_oracle_top_ha": abs(E(e32) - E(e_or))})
         # and after TRAIN_STEPS steps at lr TRAIN_LR (master weights off the bf16
         # grid), where the CPU baseline is timed
-        xs_t, w_t, e16_t, e32_t, p_t, unique_t = trained
+        xs_t, w_t, e16_t, e32_t, p_t, unique_t, est_t = trained
         cpu, e_or_t = cpu_baseline(cfg, p_t, xs_t, "the trained model's samples")
         Et = lambda e: float(np.real(np.sum(w_t * e) / np.sum(w_t)))
         precision["trained"] = {
@@ -623,7 +641,7 @@ def main():
             "E_oracle_top": Et(e_or_t), "E_bf16_top": Et(e16_t), "E_fp32_top": Et(e32_t),
             "abs_diff_bf16_oracle_top_ha": abs(Et(e16_t) - Et(e_or_t)),
             "abs_diff_fp32_oracle_top_ha": abs(Et(e32_t) - Et(e_or_t)),
-            "max_abs_eloc_diff_bf16_oracle_ha": float(np.max(np.abs(e16_t - e_or_t)))}
+            "max_abs_eloc_diff_bf16_oracle_ha": float(np.max(np.abs(e16_t - e_or_t))), **est_t}
     elif not args.no_cpu:
         x0, c0 = first
         top = torch.argsort(c0, descending=True)[:args.cpu_sample]
