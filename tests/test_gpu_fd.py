@@ -79,7 +79,8 @@ def test_fd_gradient_fp64(step):
     # central-difference truncation (h^2 L''') and the rounding of L (~1e-16 |L| / h) together
     # stay far below 1e-6 of the largest component; relative 1e-6 on every sizeable component
     assert np.all(err <= 1e-6 * np.maximum(np.abs(g[idx]), 1e-3 * scale))
-    # the mixed-precision backward (bf16 weights, FP32 layers) on the same weights: reported
+    # the bf16 model's backward (split-bf16 MFMA products, fp32 layer norms and attention)
+    # on the same weights: reported
     m16 = nqs.Model(nqs.MODEL_TRANSFORMER, step["m64"].dims, flat, "bf16")
     g16 = nqs.amp_backward(m16, x, gl, gp).double().cpu().numpy()
     e16 = np.abs(g16[idx] - fd)
