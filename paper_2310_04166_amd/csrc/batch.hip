@@ -242,6 +242,9 @@ __global__ void __launch_bounds__(256) pairs_kernel(
 
 // E_loc(x_s) = hdiag_s + sum_j H_j exp((la'_j - la_s) + i (ph'_j - ph_s)) over the
 // sample's pairs in group order; one wave per sample, fixed-order reduction.
+// F: the type of the ratio's exp / sincos (float for the bf16 step: the
+// log-amplitude differences in fp32; double otherwise); sums in double.
+template <class F>
 __global__ void __launch_bounds__(256) accumulate_kernel(
     const StepDesc *__restrict__ desc, const MolTab *__restrict__ tabs,
     const uint64_t *__restrict__ x, int n_mol, const uint32_t *__restrict__ slot,
@@ -271,11 +274,16 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
       const uint32_t sl = slot[j];
       if (sl == kNoSlot) continue;
       const uint32_t u = ids[sl];
-      const double a = exp(la_p[u] - lx);
-      double sn, cs;
-      sincos(ph_p[u] - px, &sn, &cs);
-      re += hval[j] * a * cs;
-      im += hval[j] * a * sn;
+      F a, sn, cs;
+      if constexpr (sizeof(F) == 4) {
+        a = expf(F(la_p[u] - lx));
+        sincosf(F(ph_p[u] - px), &sn, &cs);
+      } else {
+        a = exp(la_p[u] - lx);
+        sincos(ph_p[u] - px, &sn, &cs);
+      }
+      re += hval[j] * double(a) * double(cs);
+      im += hval[j] * double(a) * double(sn);
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
       re += __shfl_xor(re, o);
@@ -478,7 +486,7 @@ void enqueue(nqs_batch &b, bool psi_x, hipStream_t s) {
   fused_forward(m, b.ukeys.as<uint64_t>(), b.p_cap, b.la.as<double>(), b.ph.as<double>(), nullptr,
                 -1, s, &ctr->distinct, b.xp_tile);
   HIP_OK(hipEventRecord(b.ev1, s));
-  hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(b.acc_blocks)), dim3(256), 0, s, desc,
+  hipLaunchKernelGGL(accumulate_kernel<float>, dim3(unsigned(b.acc_blocks)), dim3(256), 0, s, desc,
                      b.tabs.as<MolTab>(), b.x.as<uint64_t>(), b.n_mol, b.slot.as<uint32_t>(),
                      b.ids.as<uint32_t>(), b.hval.as<double>(), b.la.as<double>(),
                      b.ph.as<double>(), b.lax.as<double>(), b.phx.as<double>(),
@@ -797,7 +805,8 @@ extern "C" int batch_local_energy(nqs_batch *b, const uint64_t *x, const uint64_
       if (c.distinct > 0)
         model_forward(m, b->ukeys.as<uint64_t>(), c.distinct, b->la.as<double>(),
                       b->ph.as<double>(), nullptr, s);
-      hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(b->acc_blocks)), dim3(256), 0, s, desc,
+      hipLaunchKernelGGL(accumulate_kernel<double>, dim3(unsigned(b->acc_blocks)), dim3(256), 0, s,
+                         desc,
                          b->tabs.as<MolTab>(), b->x.as<uint64_t>(), b->n_mol,
                          b->slot.as<uint32_t>(),
                          b->ids.as<uint32_t>(), b->hval.as<double>(), b->la.as<double>(),

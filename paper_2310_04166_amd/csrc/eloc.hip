@@ -207,6 +207,11 @@ __global__ void __launch_bounds__(1024) tile_add_kernel(int64_t *__restrict__ ou
 // E_loc(x_i) = hdiag_i + sum_j H_ij exp((la'_j - la_i) + i (ph'_j - ph_i)), one
 // wave per x over its contiguous pairs, fixed-order reduction, double.  With
 // uid, the amplitudes of pair j are those of distinct configuration uid[j].
+// F: the type of the amplitude ratio's exp / sincos (float in the bf16 mode:
+// the log-amplitude differences are taken in double and evaluated in fp32,
+// about 1e-7 relative per term; double in the FP64 and FP32 modes); the
+// matrix-element products and their sums stay double.
+template <class F>
 __global__ void __launch_bounds__(256) accumulate_kernel(
     int64_t n, const int64_t *__restrict__ off, const double *__restrict__ hval,
     const uint32_t *__restrict__ uid, const double *__restrict__ la_p,
@@ -221,11 +226,16 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
   double re = 0.0, im = 0.0;
   for (int64_t j = j0 + lane; j < j1; j += kWave) {
     const int64_t u = uid ? int64_t(uid[j]) : j;
-    const double a = exp(la_p[u] - lx);
-    double s, c;
-    sincos(ph_p[u] - px, &s, &c);
-    re += hval[j] * a * c;
-    im += hval[j] * a * s;
+    F a, s, c;
+    if constexpr (sizeof(F) == 4) {
+      a = expf(F(la_p[u] - lx));
+      sincosf(F(ph_p[u] - px), &s, &c);
+    } else {
+      a = exp(la_p[u] - lx);
+      sincos(ph_p[u] - px, &s, &c);
+    }
+    re += hval[j] * double(a) * double(c);
+    im += hval[j] * double(a) * double(s);
   }
   for (int s = kWave / 2; s > 0; s >>= 1) {
     re += __shfl_xor(re, s);
@@ -354,10 +364,16 @@ void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream
 
 void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,
                        const double *la_p, const double *ph_p, const double *la_x,
-                       const double *ph_x, const double *hdiag, double *eloc, hipStream_t s) {
+                       const double *ph_x, const double *hdiag, double *eloc, hipStream_t s,
+                       bool fp32_ratio) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned(ceil_div(n, kWavesPerBlock))), dim3(256), 0,
-                     s, n, off, hval, uid, la_p, ph_p, la_x, ph_x, hdiag, eloc);
+  const dim3 grid(unsigned(ceil_div(n, kWavesPerBlock)));
+  if (fp32_ratio)
+    hipLaunchKernelGGL(accumulate_kernel<float>, grid, dim3(256), 0, s, n, off, hval, uid, la_p,
+                       ph_p, la_x, ph_x, hdiag, eloc);
+  else
+    hipLaunchKernelGGL(accumulate_kernel<double>, grid, dim3(256), 0, s, n, off, hval, uid, la_p,
+                       ph_p, la_x, ph_x, hdiag, eloc);
   HIP_LAUNCH_OK();
 }
 
