@@ -641,7 +641,11 @@ def main():
             "E_oracle_top": Et(e_or_t), "E_bf16_top": Et(e16_t), "E_fp32_top": Et(e32_t),
             "abs_diff_bf16_oracle_top_ha": abs(Et(e16_t) - Et(e_or_t)),
             "abs_diff_fp32_oracle_top_ha": abs(Et(e32_t) - Et(e_or_t)),
-            "max_abs_eloc_diff_bf16_oracle_ha": float(np.max(np.abs(e16_t - e_or_t))), **est_t}
+            "max_abs_eloc_diff_bf16_oracle_ha": float(np.max(np.abs(e16_t - e_or_t))),
+            # the noise of that energy: the standard error of its per-sample errors
+            "std_err_bf16_oracle_top_ha": float(np.sqrt(np.sum(w_t ** 2 * np.real(e16_t - e_or_t) ** 2))
+                                                / np.sum(w_t)),
+            **est_t}
     elif not args.no_cpu:
         x0, c0 = first
         top = torch.argsort(c0, descending=True)[:args.cpu_sample]
