@@ -474,7 +474,8 @@ __global__ void __launch_bounds__(256) layernorm_bwd_kernel(const T *x, const T 
 }
 
 // The layer-norm backward with its parameters' gradients: rows of a block's
-// contiguous range taken by its four waves in turn (wave w: rows w, w + 4, ..),
+// contiguous range taken by its four waves in turn (wave w: rows w, w + 4, ..,
+// two at a time),
 // each lane owning columns lane + 64 k (k < CPL); per-lane double sums of
 // dy * xhat (gain) and dy (bias) over the rows, combined over the waves in
 // order into gpart[block][j], bpart[block][j].
@@ -495,31 +496,50 @@ __global__ void __launch_bounds__(256) layernorm_bwd_acc_kernel(
     ga[k] = ba[k] = 0.0;
     gj[k] = g[lane + 64 * k];
   }
-  for (int64_t r = r0 + w; r < r1; r += 4) {
-    const T mu = mean[r], rs = rstd[r];
-    T xh[CPL], dyv[CPL], s1 = 0, s2 = 0;
+  // two rows (r, r + 4) per iteration, every load of both issued first
+  for (int64_t r = r0 + w; r < r1; r += 8) {
+    constexpr int RW = 2;
+    T xv[RW][CPL], dyv[RW][CPL], dxo[RW][CPL], mu[RW], rs[RW];
+    bool in[RW];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-      const int64_t e = r * d + lane + 64 * k;
-      xh[k] = (x[e] - mu) * rs;
-      dyv[k] = dy[e];
-      const T gy = dyv[k] * gj[k];
-      s1 += gy;
-      s2 += gy * xh[k];
-      ga[k] += double(dyv[k] * xh[k]);
-      ba[k] += double(dyv[k]);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      s1 += __shfl_xor(s1, o);
-      s2 += __shfl_xor(s2, o);
-    }
-    s1 /= T(d);
-    s2 /= T(d);
+    for (int q = 0; q < RW; ++q) {
+      const int64_t rq = r + 4 * q;
+      in[q] = rq < r1;
+      mu[q] = in[q] ? mean[rq] : T(0);
+      rs[q] = in[q] ? rstd[rq] : T(0);
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-      const int64_t e = r * d + lane + 64 * k;
-      const T v = rs * (dyv[k] * gj[k] - s1 - xh[k] * s2);
-      dx[e] = accumulate ? dx[e] + v : v;
+      for (int k = 0; k < CPL; ++k) {
+        const int64_t e = rq * d + lane + 64 * k;
+        xv[q][k] = in[q] ? x[e] : T(0);
+        dyv[q][k] = in[q] ? dy[e] : T(0);
+        dxo[q][k] = in[q] && accumulate ? dx[e] : T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      if (!in[q]) continue;
+      const int64_t rq = r + 4 * q;
+      T xh[CPL], s1 = 0, s2 = 0;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        xh[k] = (xv[q][k] - mu[q]) * rs[q];
+        const T gy = dyv[q][k] * gj[k];
+        s1 += gy;
+        s2 += gy * xh[k];
+        ga[k] += double(dyv[q][k] * xh[k]);
+        ba[k] += double(dyv[q][k]);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+      }
+      s1 /= T(d);
+      s2 /= T(d);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        const T v = rs[q] * (dyv[q][k] * gj[k] - s1 - xh[k] * s2);
+        dx[rq * d + lane + 64 * k] = accumulate ? dxo[q][k] + v : v;
+      }
     }
   }
 #pragma unroll
