@@ -270,20 +270,39 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
     const int64_t j0 = desc->p_off[mol] + (s - desc->u_off[mol]) * K;
     const double lx = la_x[s], px = ph_x[s];
     double re = 0.0, im = 0.0;
-    for (int64_t j = j0 + lane; j < j0 + K; j += kWave) {
-      const uint32_t sl = slot[j];
-      if (sl == kNoSlot) continue;
-      const uint32_t u = ids[sl];
-      F a, sn, cs;
-      if constexpr (sizeof(F) == 4) {
-        a = expf(F(la_p[u] - lx));
-        sincosf(F(ph_p[u] - px), &sn, &cs);
-      } else {
-        a = exp(la_p[u] - lx);
-        sincos(ph_p[u] - px, &sn, &cs);
+    // four pairs per lane and iteration, loads issued before any is used;
+    // each lane still adds its pairs in order
+    constexpr int Q = 4;
+    for (int64_t j = j0 + lane; j < j0 + K; j += Q * kWave) {
+      uint32_t sl[Q], u[Q];
+      double hv[Q], lp[Q], pp[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t jq = j + q * kWave;
+        sl[q] = jq < j0 + K ? slot[jq] : kNoSlot;
+        hv[q] = jq < j0 + K ? hval[jq] : 0.0;
       }
-      re += hval[j] * double(a) * double(cs);
-      im += hval[j] * double(a) * double(sn);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) u[q] = sl[q] != kNoSlot ? ids[sl[q]] : 0u;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        lp[q] = sl[q] != kNoSlot ? la_p[u[q]] : lx;
+        pp[q] = sl[q] != kNoSlot ? ph_p[u[q]] : px;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (sl[q] == kNoSlot) continue;
+        F a, sn, cs;
+        if constexpr (sizeof(F) == 4) {
+          a = expf(F(lp[q] - lx));
+          sincosf(F(pp[q] - px), &sn, &cs);
+        } else {
+          a = exp(lp[q] - lx);
+          sincos(pp[q] - px, &sn, &cs);
+        }
+        re += hv[q] * double(a) * double(cs);
+        im += hv[q] * double(a) * double(sn);
+      }
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
       re += __shfl_xor(re, o);

@@ -224,18 +224,37 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
   const int64_t j0 = off[i] - off[0], j1 = off[i + 1] - off[0];
   const double lx = la_x[i], px = ph_x[i];
   double re = 0.0, im = 0.0;
-  for (int64_t j = j0 + lane; j < j1; j += kWave) {
-    const int64_t u = uid ? int64_t(uid[j]) : j;
-    F a, s, c;
-    if constexpr (sizeof(F) == 4) {
-      a = expf(F(la_p[u] - lx));
-      sincosf(F(ph_p[u] - px), &s, &c);
-    } else {
-      a = exp(la_p[u] - lx);
-      sincos(ph_p[u] - px, &s, &c);
+  // four pairs per lane and iteration, their index and amplitude loads issued
+  // before any is used; each lane still adds its pairs in order
+  constexpr int Q = 4;
+  for (int64_t j = j0 + lane; j < j1; j += Q * kWave) {
+    int64_t u[Q];
+    double hv[Q], lp[Q], pp[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t jq = j + q * kWave;
+      u[q] = jq < j1 ? (uid ? int64_t(uid[jq]) : jq) : -1;
+      hv[q] = jq < j1 ? hval[jq] : 0.0;
     }
-    re += hval[j] * double(a) * double(c);
-    im += hval[j] * double(a) * double(s);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      lp[q] = u[q] >= 0 ? la_p[u[q]] : lx;
+      pp[q] = u[q] >= 0 ? ph_p[u[q]] : px;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (u[q] < 0) continue;
+      F a, s, c;
+      if constexpr (sizeof(F) == 4) {
+        a = expf(F(lp[q] - lx));
+        sincosf(F(pp[q] - px), &s, &c);
+      } else {
+        a = exp(lp[q] - lx);
+        sincos(pp[q] - px, &s, &c);
+      }
+      re += hv[q] * double(a) * double(c);
+      im += hv[q] * double(a) * double(s);
+    }
   }
   for (int s = kWave / 2; s > 0; s >>= 1) {
     re += __shfl_xor(re, s);
