@@ -40,19 +40,28 @@ __global__ void prefix_key_kernel(uint64_t *__restrict__ k, int64_t n, int key_b
   if (i < n) k[i] = prefix_key(k[i], key_bits, pm);
 }
 
-__global__ void head_kernel(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ head) {
+// keys of at most 32 bits: the (reordered) key of every pair as uint32
+__global__ void narrow_key_kernel(const uint64_t *__restrict__ xp, int64_t n, int key_bits, int pm,
+                                  uint32_t *__restrict__ k) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) k[i] = uint32_t(pm > 0 ? prefix_key(xp[i], key_bits, pm) : xp[i]);
+}
+
+template <class K>
+__global__ void head_kernel(const K *__restrict__ keys, int64_t n, uint32_t *__restrict__ head) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
 }
 
-__global__ void scatter_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+template <class K>
+__global__ void scatter_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                const uint32_t *__restrict__ head, const uint32_t *__restrict__ run,
                                int64_t n, int key_bits, int pm, uint64_t *__restrict__ ukeys,
                                uint32_t *__restrict__ pair_uid) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t id = run[i] - 1u;
-  if (head[i]) ukeys[id] = pm == 0 ? keys[i] : prefix_key_inverse(keys[i], key_bits, pm);
+  if (head[i]) ukeys[id] = pm == 0 ? uint64_t(keys[i]) : prefix_key_inverse(keys[i], key_bits, pm);
   pair_uid[vals[i]] = id;
 }
 
@@ -61,9 +70,11 @@ inline dim3 g1(int64_t n) { return dim3(unsigned(ceil_div(n, 256))); }
 }  // namespace
 
 // Returns the number of distinct keys U; ukeys[0..U) ascending (in the
-// reordered key when pm > 0: then xp is reordered in place), pair_uid[p] =
-// index of xp[p] in ukeys.  All buffers are caller-provided workspaces sized
-// for n pairs; tmp is grown as needed.
+// reordered key when pm > 0), pair_uid[p] = index of xp[p] in ukeys.  All
+// buffers are caller-provided workspaces sized for n pairs; tmp is grown as
+// needed.  Keys of at most 32 bits are sorted as uint32 (in the two halves of
+// keys_sorted; xp is left as it is), wider keys as uint64 (xp reordered in
+// place when pm > 0).
 int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *keys_sorted,
                      uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
                      uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s) {
@@ -71,24 +82,45 @@ int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *ke
   NQS_REQUIRE(n < (int64_t(1) << 31), NQS_EUNSUPPORTED, "dedupe: slice too large");
   NQS_REQUIRE(pm == 0 || (pm >= 16 && pm < key_bits), NQS_EINVAL, "dedupe: prefix fields");
   const int ni = int(n);
+  hipLaunchKernelGGL(iota_kernel, g1(n), dim3(256), 0, s, vals_in, n);
+  HIP_LAUNCH_OK();
+  size_t sort_bytes = 0, scan_bytes = 0;
+  if (key_bits <= 32) {
+    uint32_t *k_in = reinterpret_cast<uint32_t *>(keys_sorted), *k_out = k_in + n;
+    hipLaunchKernelGGL(narrow_key_kernel, g1(n), dim3(256), 0, s, xp, n, key_bits, pm, k_in);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, k_in, k_out, vals_in,
+                                              vals_sorted, ni, 0, key_bits, s));
+    HIP_OK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, head, run, ni, s));
+    void *t = tmp.reserve(std::max(sort_bytes, scan_bytes) + 256);
+    HIP_OK(hipcub::DeviceRadixSort::SortPairs(t, sort_bytes, k_in, k_out, vals_in, vals_sorted,
+                                              ni, 0, key_bits, s));
+    hipLaunchKernelGGL(head_kernel<uint32_t>, g1(n), dim3(256), 0, s, k_out, n, head);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipcub::DeviceScan::InclusiveSum(t, scan_bytes, head, run, ni, s));
+    hipLaunchKernelGGL(scatter_kernel<uint32_t>, g1(n), dim3(256), 0, s, k_out, vals_sorted, head,
+                       run, n, key_bits, pm, ukeys, pair_uid);
+    HIP_LAUNCH_OK();
+    uint32_t u = 0;
+    HIP_OK(hipMemcpyAsync(&u, run + (n - 1), 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return int64_t(u);
+  }
   if (pm > 0) {
     hipLaunchKernelGGL(prefix_key_kernel, g1(n), dim3(256), 0, s, xp, n, key_bits, pm);
     HIP_LAUNCH_OK();
   }
-  hipLaunchKernelGGL(iota_kernel, g1(n), dim3(256), 0, s, vals_in, n);
-  HIP_LAUNCH_OK();
-  size_t sort_bytes = 0, scan_bytes = 0;
   HIP_OK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, xp, keys_sorted, vals_in,
                                             vals_sorted, ni, 0, key_bits, s));
   HIP_OK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, head, run, ni, s));
   void *t = tmp.reserve(std::max(sort_bytes, scan_bytes) + 256);
   HIP_OK(hipcub::DeviceRadixSort::SortPairs(t, sort_bytes, xp, keys_sorted, vals_in, vals_sorted,
                                             ni, 0, key_bits, s));
-  hipLaunchKernelGGL(head_kernel, g1(n), dim3(256), 0, s, keys_sorted, n, head);
+  hipLaunchKernelGGL(head_kernel<uint64_t>, g1(n), dim3(256), 0, s, keys_sorted, n, head);
   HIP_LAUNCH_OK();
   HIP_OK(hipcub::DeviceScan::InclusiveSum(t, scan_bytes, head, run, ni, s));
-  hipLaunchKernelGGL(scatter_kernel, g1(n), dim3(256), 0, s, keys_sorted, vals_sorted, head, run,
-                     n, key_bits, pm, ukeys, pair_uid);
+  hipLaunchKernelGGL(scatter_kernel<uint64_t>, g1(n), dim3(256), 0, s, keys_sorted, vals_sorted,
+                     head, run, n, key_bits, pm, ukeys, pair_uid);
   HIP_LAUNCH_OK();
   uint32_t u = 0;
   HIP_OK(hipMemcpyAsync(&u, run + (n - 1), 4, hipMemcpyDeviceToHost, s));
