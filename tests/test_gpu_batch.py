@@ -274,6 +274,37 @@ def test_batch_weights_and_backward_fp64(nqs):
     assert err < 1e-10 * np.max(np.abs(g_ref))
 
 
+def test_batch_backward_bf16_split_products(nqs):
+    """The shared bf16 model's backward over three molecules of different
+    lengths (tagged configurations) on split-bf16 MFMA products, against the
+    same backward on fp32 library products and against the oracle's autograd
+    of the sum of the molecules' surrogates (bound 1e-4 of max |g| for both)."""
+    mols = small_molecules()[:3]
+    params = batching_params()
+    m, b, _ = make(nqs, mols, "bf16", params)
+    x, c, off, _ = nqs.sample_unique_batch(m, [400, 300, 500], 4)
+    eloc, sums, _ = b.local_energy(x, c, off)
+    gl, gp = nqs.vmc_weights_batch(eloc, c, x, sums)
+    g = nqs.amp_backward(m, x, gl, gp).double().cpu().numpy()
+    m.set_mixed_backward(False)
+    g32 = nqs.amp_backward(m, x, gl, gp).double().cpu().numpy()
+    m.set_mixed_backward(True)
+    occ = split(x, off)
+    el = eloc.cpu().numpy()
+    g_ref = np.zeros_like(g)
+    for i, mm in enumerate(mols):
+        cnt = c[off[i]:off[i + 1]].cpu().numpy()
+        ref = TransformerModel(params, Sector(mm["n"], mm["n_alpha"], mm["n_beta"]),
+                               C4["n_heads"], requires_grad=True)
+        g_ref += gradient(ref, occ[i], cnt, el[off[i]:off[i + 1]], SPEC)
+    scale = np.max(np.abs(g_ref))
+    e32, eor = np.max(np.abs(g - g32)), np.max(np.abs(g - g_ref))
+    log(f"batch bf16 backward: max|g| {scale:.3e}, split vs fp32 products {e32:.2e}, "
+        f"vs oracle {eor:.2e}")
+    assert e32 <= 1e-4 * np.max(np.abs(g32))
+    assert eor <= 1e-4 * scale
+
+
 def test_batch_full_workload(nqs):
     """All 64 molecules (12..28 spin-orbitals) in one graph-captured bf16 step:
     sizes exact, every molecule's energy finite and variational-looking, and a
