@@ -50,7 +50,7 @@ def rows_flop(t0, t1, d, n_layers, ffn, ph, phase):
                 + pos * 4 * d + ((ph * ph + ph) if phase else 0))
 
 # The per-qubit ansatz (workload "nade") is bound by its elementwise VALU work.
-# Peak VALU issue of MI355X without packed fp32 (disabled in this build):
+# Peak VALU issue of MI355X without packed fp32 (the library is compiled without it):
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second, a
 # transcendental (exp2, log2, sin, cos, reciprocal) taking 4 issue slots.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12

@@ -19,7 +19,7 @@ conditional is the network's; after an unphysical prefix both are 0.  Levels
 of tokens p >= ``mask_levels`` (qubits 2p, 2p + 1) are left unmasked
 (Discard-Unphysical / MU-d, d counted in tokens as for the other models).
 
-The sampler of this build splits samples over a token's four children at
+The library's sampler splits samples over a token's four children at
 once, so the model also gives token log-probabilities
     log p(a, b | x_<2p) = 2 Re log psi_2p(a) + 2 Re log psi_2p+1(b | a)
 and token phases Im log psi_2p(a) + Im log psi_2p+1(b | a); the product of the
