@@ -574,13 +574,17 @@ def main():
                     "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)}
     else:
         n, d, nl, nh = cfg["n"], cfg["d"], cfg["n_layers"], cfg["n_heads"]
-        pm = n - 4
+        # middle split of the three-level forward: the models here mask every
+        # level (MU), so the sector fixes the last token (its conditional is a
+        # membership test) and from 14 tokens on TAIL evaluates positions
+        # n-5 .. n-2, the middle level (n-5)-token prefixes
+        pm = n - 5 if n >= 14 else n - 4
         # rows each layout evaluates: (first position, last + 1, phase MLP, executed kind)
-        rows = {"tail": (pm, n, True, "tail"), "mid": (TRUNK, pm, False, "mid"),
+        rows = {"tail": (pm, pm + 4, True, "tail"), "mid": (TRUNK, pm, False, "mid"),
                 "suffix": (TRUNK, n, True, "suffix"), "trunk": (0, TRUNK, False, "trunk"),
                 "rest": (0, n, True, "plain")}
-        names = {"tail": "fused_kernel<128, TAIL> (bf16 amplitude network, the last four "
-                         "positions of each configuration)",
+        names = {"tail": f"fused_kernel<128, TAIL> (bf16 amplitude network, positions "
+                         f"{pm}..{pm + 3} of each configuration)",
                  "mid": f"fused_kernel<128, MID> (positions 8..{pm - 1} once per distinct "
                         f"{pm}-token prefix)",
                  "suffix": "fused_kernel<128, SUFFIX> (positions 8..15 of each configuration)",

@@ -702,7 +702,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
       launch_emit_pairs(*H, x + i0, i1 - i0, off + i0, xp, hv, nullptr, hdiag + i0, 0, s);
       // grouped by the prefixes of the prefix-shared forward
       const int levels = fused_shared_levels(*m);
-      const int pm = levels == 3 ? 2 * (m->n - 4) : levels == 2 ? 16 : 0;
+      const int pm = levels == 3 ? 2 * fused_shared_pm(*m) : levels == 2 ? 16 : 0;
       const int64_t nu = dedupe_pairs(xp, np, H->N, pm, keys, vin, vsort, head, run, ukeys, uid,
                                       H->w_tmp, s);
       H->last_distinct += nu;

@@ -176,10 +176,13 @@ bool fused_shared_supported(const nqs_model &m);
 void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
                           double *phase, hipStream_t s);
 // 2 or 3 (13..16 tokens) levels of the shared forward, 0 if it does not apply.
-// Three levels: positions 0..7 per 8-token prefix, 8 .. n-5 per (n-4)-token
-// prefix, the last four per configuration; x must be sorted by those prefixes
-// (dedupe_pairs with pm = 2 (n - 4) bits).
+// Three levels: positions 0..7 per 8-token prefix, 8 .. pm-1 per pm-token
+// prefix, pm .. pm+3 per configuration; x must be sorted by those prefixes
+// (dedupe_pairs with 2 pm bits).
 int fused_shared_levels(const nqs_model &m);
+// The middle split pm: n - 5 when the sector fixes the last token (14..16
+// tokens; that position's conditional is then a membership test), else n - 4.
+int fused_shared_pm(const nqs_model &m);
 void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
                            double *phase, hipStream_t s);
 // explicit psi over a basis (table.hip): install the basis (host, ascending),

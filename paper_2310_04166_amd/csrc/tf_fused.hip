@@ -87,13 +87,19 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // states, keys and values are the same for every configuration with the same
 // first 8 tokens; distinct x' of one step share few such prefixes (at most
 // 4^8), so TRUNK + SUFFIX do about half the work of PLAIN per configuration.
-//   MID     R = 4:  positions 8..pm-1 (pm = n - 4 <= 12; rows up to 11) of 8
+//   MID     R = 4:  positions 8..pm-1 (pm <= 12; rows up to 11) of 8
 //                   distinct pm-token prefixes (all with one 8-token prefix),
 //                   attending to the 8-token prefix's keys and values; stores
 //                   its own keys and values and the log-probability of tokens
 //                   8..pm-1 per pm-token prefix;
-//   TAIL    R = 4:  the last four positions pm..pm+3 of 8 configurations (one
-//                   8-token prefix), attending to both stored levels.
+//   TAIL    R = 4:  positions pm..pm+3 of 8 configurations (one 8-token
+//                   prefix), attending to both stored levels.
+// pm = n - 4 makes TAIL the last four positions.  When the sector leaves one
+// token at the last position its masked conditional is 1 or 0 (a membership
+// test, no network), so pm = n - 5: TAIL takes the four positions before the
+// last, a small kernel applies the test, and the middle level holds
+// (n-5)-token prefixes, ~2.4x fewer than (n-4)-token ones on the
+// 30-spin-orbital system.
 // MID / TAIL take their items through an index list (a.src; -1 = padding)
 // in which every 8-token prefix starts a new pass.
 enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5 };
@@ -1371,6 +1377,23 @@ __global__ void prefix_maps_kernel(int64_t B, const int64_t *__restrict__ hm,
   if (hm[i]) mid[start_m[g] + prem[i] - firstm[g]] = i;
 }
 
+// Position n - 1 when the sector leaves at most one token there: its masked
+// conditional is 1 if the configuration's last token is allowed, else 0.  The
+// tail rows stop at n - 2; this applies the last factor to log|psi|.
+__global__ void last_token_kernel(Sectors sec, const uint64_t *__restrict__ x, int64_t B,
+                                  double *__restrict__ logabs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t v = x[i];
+  const nqs_sector_info &si = sector_of(sec, v);
+  const int t = si.n - 1;
+  const uint64_t below = ~0ull >> (64 - 2 * t);
+  const int na = __popcll(v & below & 0x5555555555555555ull);
+  const int nb = __popcll(v & below & 0xAAAAAAAAAAAAAAAAull);
+  const int allow = phys_mask(sec, si, t, na, nb, v);
+  if (!((allow >> int((v >> (2 * t)) & 3ull)) & 1)) logabs[i] = -INFINITY;
+}
+
 }  // namespace
 
 bool fused_supported(const nqs_model &m) {
@@ -1385,6 +1408,38 @@ bool fused_shared_supported(const nqs_model &m) {
 
 int fused_shared_levels(const nqs_model &m) {
   return !fused_shared_supported(m) ? 0 : m.n >= 13 ? 3 : 2;
+}
+
+// Whether every sector's mask leaves at most one token at the last position
+// (particle numbers do, and so do Z2 parities and additive symmetries whose
+// four token contributions differ there); then that position's conditional is
+// 1 for an allowed token and 0 otherwise, whatever the network computes.
+bool last_token_fixed(const nqs_model &m) {
+  if (m.sec_host.empty()) return false;
+  for (const nqs_sector_info &si : m.sec_host) {
+    if (si.mask_levels < si.n) return false;
+    const int t = si.n - 1;
+    if (si.general) {
+      // level t's states are g[t] .. g[t + 1] - 1, four children each
+      const int32_t *g = reinterpret_cast<const int32_t *>(m.phys_host.data() + si.phys_off);
+      const int32_t *kids = g + si.n + 1;
+      for (int32_t id = g[t]; id < g[t + 1]; ++id) {
+        int k = 0;
+        for (int j = 0; j < 4; ++j) k += kids[4 * int64_t(id) + j] >= 0;
+        if (k > 1) return false;
+      }
+    } else {
+      const int64_t per = (int64_t(si.n + 1) * (si.n + 1)) << si.nz2;
+      const uint8_t *e = m.phys_host.data() + si.phys_off + int64_t(t) * per;
+      for (int64_t i = 0; i < per; ++i)
+        if (__builtin_popcount(unsigned(e[i]) & 0xFu) > 1) return false;
+    }
+  }
+  return true;
+}
+
+int fused_shared_pm(const nqs_model &m) {
+  return m.n >= 14 && last_token_fixed(m) ? m.n - 5 : m.n - 4;
 }
 
 void fused_pack(nqs_model &m, hipStream_t s) {
@@ -1599,7 +1654,7 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
   NQS_REQUIRE(fused_shared_levels(m) == 3, NQS_EUNSUPPORTED, "shared forward: unsupported model");
   if (B <= 0) return;
   constexpr int64_t K = int64_t(1) << 16;      // 8-token prefixes
-  const int pm = m.n - 4;                      // TAIL: the last four positions
+  const int pm = fused_shared_pm(m);           // TAIL: positions pm .. pm + 3
   const uint64_t mmask = (1ull << (2 * pm)) - 1;
   const int64_t kv_bytes = int64_t(m.L) * (m.d / 32) * 1024;
   const int64_t kv2_bytes = int64_t(m.L) * (m.d / 32) * 512;
@@ -1689,6 +1744,10 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
     a.phase = phase;
     launch_fused(m, TAIL, a, a.B, s, nullptr, 0, 0);
     g0 = g1;
+  }
+  if (pm + 4 < m.n) {
+    hipLaunchKernelGGL(last_token_kernel, g1(B), dim3(256), 0, s, m.sectors(), x, B, logabs);
+    HIP_LAUNCH_OK();
   }
 }
 

@@ -61,8 +61,9 @@ def test_distinct_prefixes_of_one_step():
 ])
 def test_three_levels_vs_unshared_and_oracle(n, na, nb, d, L, samples):
     """13..16 tokens: the local energy evaluates positions 0..7 once per 8-token
-    prefix, 8 .. n-5 once per (n-4)-token prefix and the last four per
-    configuration (slices, padding to whole passes per 8-token prefix).  Its
+    prefix, 8 .. pm-1 once per pm-token prefix and pm .. pm+3 per configuration
+    (slices, padding to whole passes per 8-token prefix; pm = n - 4 at 13
+    tokens, n - 5 from 14 on, where the sector fixes the last token).  Its
     energy against the per-configuration evaluation (same bf16 operands) and,
     on the four highest-count samples, every local energy against the FP64
     oracle within 1.5 x its first-order bound (tests/eloc_bound.py)."""
@@ -93,6 +94,88 @@ def test_three_levels_vs_unshared_and_oracle(n, na, nb, d, L, samples):
           flush=True)
     assert abs(E3 - Eu) < 1e-5
     ref = TransformerModel(params, Sector(n, na, nb), d // 16)
+    cv = c.cpu().numpy()
+    top = list(np.argsort(-cv, kind="stable")[:4])
+    xv = x.cpu().numpy().view(np.uint64)
+    e = e3.cpu().numpy()
+    res = eloc_bound.check(ref, h, eri, [int(xv[i]) for i in top], eloc_bound.gpu_amplitudes(nqs, m))
+    for i, (want, A, eps) in zip(top, res):
+        err = abs(e[i] - want)
+        print(f"  x={int(xv[i]):#x} count={cv[i]} err {err:.2e} bound {2 * eps * A:.2e}", flush=True)
+        assert err <= 1.5 * 2 * eps * A + 1e-9
+
+
+def expected_items(u, pm):
+    """Items of the MID and TAIL launches over the distinct x' u: per 8-token
+    prefix its distinct pm-token prefixes (MID) and its configurations (TAIL),
+    each padded to a multiple of 8."""
+    u = np.unique(np.asarray(u, dtype=np.uint64))
+    pad = lambda k: int(np.sum((k + 7) // 8 * 8))
+    gm = np.unique(u & np.uint64((1 << (2 * pm)) - 1))
+    _, k_mid = np.unique(gm & np.uint64(0xFFFF), return_counts=True)
+    _, k_tail = np.unique(u & np.uint64(0xFFFF), return_counts=True)
+    return pad(k_mid), pad(k_tail)
+
+
+# (n, n_alpha, n_beta, strategy, general symmetries, middle split): the split
+# moves to n - 5 exactly when every level is masked and the sector leaves one
+# token at the last position - particle numbers (table or general symmetries)
+# do; masks that stop 2 levels early (MU-d) or 2 S_z alone (an empty and a
+# doubly occupied orbital add the same) do not
+@pytest.mark.parametrize("n,na,nb,strategy,general,pm", [
+    (14, 3, 3, "MU", None, 9),
+    (14, 3, 3, "MUd", None, 10),
+    (15, 3, 2, "MU", "n_sz", 10),
+    (15, 3, 2, "MU", "sz", 11),
+])
+def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
+    """The middle split the library takes (counted from the MID launches'
+    items) and the local energy it gives, against the per-configuration
+    evaluation and the FP64 oracle (as above)."""
+    import eloc_bound
+    from oracle.model import TransformerModel
+    from oracle.sector import GeneralSector, Sector, particle_number_eigs, two_sz_eigs
+    from paper_2310_04166_amd import nqs
+    from synth import make_integrals, make_transformer_params
+    nqs.lib()
+    d, L = 64, 1
+    h, eri = make_integrals(n, n, 70 + n)
+    params = make_transformer_params(n, na, nb, d, L, seed=n + 1, std=0.05, hf_bias=1.0,
+                                     round_to="bf16", bias_std=0.02)
+    spec = transformer_param_spec(n, d, L, 4 * d, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, L, d // 16, 4 * d, 256],
+                  flatten_params(params, spec), "bf16", strategy, 2 if strategy == "MUd" else 0)
+    sec = Sector(n, na, nb)
+    if general is not None:
+        eig = [two_sz_eigs(n)] if general == "sz" else [particle_number_eigs(n), two_sz_eigs(n)]
+        tgt = [na - nb] if general == "sz" else [na + nb, na - nb]
+        m.set_symmetries(eig, tgt)
+        sec = GeneralSector(n, eig, tgt)
+    H = nqs.ham_compile(h, eri, na, nb)
+    x, c, _ = nqs.sample_unique(m, 20_000, 5)
+    _, xp, _, _ = nqs.connected_pairs(H, x)
+    u = torch.unique(xp).cpu().numpy().view(np.uint64)
+    mid_want, tail_want = expected_items(u, pm)
+    nqs.timing_read()                       # drop older records
+    nqs.timing_enable(True)
+    try:
+        e3, s3, _ = nqs.local_energy(H, m, x, c)
+        torch.cuda.synchronize()
+        assert nqs.local_energy_stats(H)[1] == len(u)
+        _, _, mid_items = nqs.timing_read(nqs.TIMING_MID)
+        _, _, tail_items = nqs.timing_read(nqs.TIMING_TAIL)
+    finally:
+        nqs.timing_enable(False)
+        nqs.timing_read()
+    print(f"n={n} {strategy} {general}: {x.numel()} samples, {len(u)} distinct x'; MID items "
+          f"{mid_items} (split {pm}: {mid_want}), TAIL items {tail_items} ({tail_want})", flush=True)
+    assert (mid_items, tail_items) == (mid_want, tail_want)
+    m.set_prefix_sharing(False)
+    eu, su, _ = nqs.local_energy(H, m, x, c)
+    m.set_prefix_sharing(True)
+    s3, su = s3.cpu().numpy(), su.cpu().numpy()
+    assert abs(s3[1] / s3[0] - su[1] / su[0]) < 1e-5
+    ref = TransformerModel(params, sec, d // 16)
     cv = c.cpu().numpy()
     top = list(np.argsort(-cv, kind="stable")[:4])
     xv = x.cpu().numpy().view(np.uint64)
