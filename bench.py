@@ -60,7 +60,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 NADE_SLOTS = {"ctanh": 4 * 4 + 11, "lerelu": 2, "normaliser": 3 * 4 + 6}
 
 
-def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph, t0=0):
+def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph, t0=0, phase=True):
     """Algorithmic VALU slots of one transformer evaluation of an n-token
     configuration (same accounting as NADE_SLOTS): per layer and token two layer
     norms (5 per feature + a reciprocal square root), two residual additions
@@ -71,13 +71,14 @@ def tf_valu_slots(n, d, n_layers, n_heads, ffn, ph, t0=0):
     log-softmax of 4 logits per token (28); the phase MLP (its first layer a sum
     of n rows, two GELU layers, the final dot product).  Bias additions ride in
     the MFMA accumulators and are not counted; neither are bf16 conversions.
-    With t0 > 0: positions t0 .. n - 1 only (a suffix over a shared prefix)."""
+    With t0 > 0: positions t0 .. n - 1 only (a suffix over a shared prefix);
+    phase=False leaves the phase MLP out."""
     ln = 5 * d + 4
     pos = n - t0
     keys = sum(t + 1 for t in range(t0, n))
     per_layer = pos * (2 * ln + 2 * d + 13 * ffn) + n_heads * keys * 8 + n_heads * pos * 4
     return (n_layers * per_layer + pos * d + pos * ln + pos * 28
-            + n * ph + 2 * 13 * ph + ph)
+            + ((n * ph + 2 * 13 * ph + ph) if phase else 0))
 
 
 def nade_work(n_qubits, hidden):
@@ -289,16 +290,21 @@ def executed_flop_per_config(n_layers, d, ph, mode="plain"):
     attend to their prefix's 8 keys ("suffix": per head pair two more score and
     eight more probability-value products), 8 prefixes of 4 positions that also
     attend to the 8-token prefix ("mid": two more scores and four more
-    probability-value products, no phase MLP) or 8 configurations of 4 positions
+    probability-value products, no phase MLP), 8 configurations of 4 positions
     that attend to both levels ("tail": four more scores, twelve more
-    probability-value products)."""
+    probability-value products) or 8 slots of 4 rows that attend to both levels
+    ("tree", per slot, no phase MLP); "phase" is the phase MLP alone."""
     nb, ks, fb = d // 32, d // 16, 4 * d // 32
-    extra = {"plain": 0, "trunk": 0, "suffix": 2 + 8, "mid": 2 + 4, "tail": 4 + 12}[mode]
+    phase = 2 * (ph // 32) * (ph // 16) * 32768 / 32
+    if mode == "phase":
+        return phase
+    extra = {"plain": 0, "trunk": 0, "suffix": 2 + 8, "mid": 2 + 4, "tail": 4 + 12,
+             "tree": 4 + 12}[mode]
     per_head_pair = 2 * (3 * ks) + 2 + 2 * 4 + 3 * ks + extra   # QKV hi+lo, S, PV, O-proj
     per_layer = nb * per_head_pair + 2 * fb * ks                # + FFN W1, W2
     tile = n_layers * per_layer * 32768
-    phase = 0 if mode in ("trunk", "mid") else 2 * (ph // 32) * (ph // 16) * 32768 / 32
-    per_tile = {"plain": 2, "trunk": 4, "suffix": 4, "mid": 8, "tail": 8}[mode]
+    phase = 0 if mode in ("trunk", "mid", "tree") else phase
+    per_tile = {"plain": 2, "trunk": 4, "suffix": 4, "mid": 8, "tail": 8, "tree": 8}[mode]
     return tile / per_tile + phase
 
 
@@ -524,6 +530,7 @@ def main():
     first = None
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    tree0 = model.tree_rows()
     ev0.record()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -552,9 +559,10 @@ def main():
     # with three levels, SUFFIX with two), the shared levels, every other
     # launch (the sampler's, and the samples' own forward without sharing)
     rec = {k: nqs.timing_read(getattr(nqs, "TIMING_" + k.upper()))
-           for k in ("tail", "mid", "suffix", "trunk")}
+           for k in ("tail", "tree", "phase", "mid", "suffix", "trunk")}
     rec["rest"] = nqs.timing_read()
     nqs.timing_enable(False)
+    tree_q, tree_q1 = (b - a for a, b in zip(tree0, model.tree_rows()))
 
     value = total_pairs / elapsed
     nade = cfg["model"] == "nade"
@@ -576,28 +584,47 @@ def main():
         n, d, nl, nh = cfg["n"], cfg["d"], cfg["n_layers"], cfg["n_heads"]
         # middle split of the three-level forward: the models here mask every
         # level (MU), so the sector fixes the last token (its conditional is a
-        # membership test) and from 14 tokens on TAIL evaluates positions
-        # n-5 .. n-2, the middle level (n-5)-token prefixes
-        pm = n - 5 if n >= 14 else n - 4
+        # membership test).  With the tree tail (13..15 tokens) the middle level
+        # covers positions 8 .. n-4 per (n-4)-token prefix and TREE positions
+        # n-3 and n-2 once per distinct prefix; otherwise from 14 tokens on TAIL
+        # evaluates positions n-5 .. n-2, the middle level (n-5)-token prefixes
+        tree = rec["tree"][1] > 0
+        q = n - 3
+        pm = q if tree else n - 5 if n >= 14 else n - 4
         # rows each layout evaluates: (first position, last + 1, phase MLP, executed kind)
         rows = {"tail": (pm, pm + 4, True, "tail"), "mid": (TRUNK, pm, False, "mid"),
+                "tree": (q, q + 2, False, "tree"), "phase": (0, 0, True, "phase"),
                 "suffix": (TRUNK, n, True, "suffix"), "trunk": (0, TRUNK, False, "trunk"),
                 "rest": (0, n, True, "plain")}
         names = {"tail": f"fused_kernel<128, TAIL> (bf16 amplitude network, positions "
                          f"{pm}..{pm + 3} of each configuration)",
                  "mid": f"fused_kernel<128, MID> (positions 8..{pm - 1} once per distinct "
-                        f"{pm}-token prefix)",
+                        f"{pm if not tree else pm - 1}-token prefix)",
+                 "tree": f"fused_kernel<128, TREE> (bf16 amplitude network: position {q} once "
+                         f"per distinct {q}-token prefix, {q + 1} once per distinct "
+                         f"{q + 1}-token prefix, slots of four rows)",
+                 "phase": "fused_kernel<128, PHASE> (the phase MLP of each configuration)",
                  "suffix": "fused_kernel<128, SUFFIX> (positions 8..15 of each configuration)",
                  "trunk": "fused_kernel<128, TRUNK> (positions 0..7 once per distinct "
                           "8-token prefix)",
                  "rest": "fused_kernel<128, PLAIN> (bf16 amplitude network)"}
-        dom = max(("tail", "suffix", "rest"), key=lambda k: rec[k][0])
+        dom = "tree" if tree else max(("tail", "suffix", "rest"), key=lambda k: rec[k][0])
         k_ms, k_launches, k_cfgs = rec[dom]
         t0, t1, ph, kind = rows[dom]
-        slots_cfg = tf_valu_slots(t1, d, nl, nh, 4 * d, 256, t0)
-        flop_cfg = rows_flop(t0, t1, d, nl, 4 * d, 256, ph)
         exe_cfg = executed_flop_per_config(nl, d, 256, kind)
-        roofline = tf_roofline(k_cfgs * flop_cfg, k_cfgs * slots_cfg, k_ms, k_cfgs * exe_cfg)
+        if tree:
+            # algorithmic work: one row per distinct q- and (q+1)-token prefix
+            f_q, f_q1 = (rows_flop(t, t + 1, d, nl, 4 * d, 256, False) for t in (q, q + 1))
+            s_q, s_q1 = (tf_valu_slots(t + 1, d, nl, nh, 4 * d, 256, t, phase=False)
+                         for t in (q, q + 1))
+            roofline = tf_roofline(tree_q * f_q + tree_q1 * f_q1, tree_q * s_q + tree_q1 * s_q1,
+                                   k_ms, k_cfgs * exe_cfg)
+            flop_cfg = {"row_q": f_q, "row_q1": f_q1, "rows_q": tree_q, "rows_q1": tree_q1}
+            slots_cfg = {"row_q": s_q, "row_q1": s_q1}
+        else:
+            slots_cfg = tf_valu_slots(t1, d, nl, nh, 4 * d, 256, t0)
+            flop_cfg = rows_flop(t0, t1, d, nl, 4 * d, 256, ph)
+            roofline = tf_roofline(k_cfgs * flop_cfg, k_cfgs * slots_cfg, k_ms, k_cfgs * exe_cfg)
         roofline.update({"traffic": fused_traffic() if args.workload == "precision" else None,
                          "traffic_unit": "bytes per launch",
                          "kernel": names[dom],
@@ -609,7 +636,7 @@ def main():
                          "valu_slots_per_config": slots_cfg,
                          "kernel_share_of_steps": round(k_ms / max(gpu_ms, 1e-9), 4)})
         others = {}
-        for k in ("mid", "trunk", "suffix", "tail", "rest"):
+        for k in ("mid", "trunk", "suffix", "tail", "tree", "phase", "rest"):
             ms, nlaunch, cfgs = rec[k]
             if k == dom or nlaunch == 0:
                 continue

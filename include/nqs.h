@@ -256,21 +256,37 @@ int amp_model_set_z2(nqs_model *m, int n_gen, const uint64_t *masks, const int32
 
 /*
  * amp_model_set_prefix_sharing - evaluate batches of a bf16 transformer with
- * 9..16 tokens (one molecule) by shared prefixes (on = 1, the default) or
- * configuration by configuration (on = 0).  Paper: ANQS product rule (the
+ * 9..16 tokens (one molecule) by shared prefixes (on = 1, the default; on = 2
+ * the same without the tree tail below) or configuration by configuration
+ * (on = 0).  Paper: ANQS product rule (the
  * network is causal: the hidden states of positions 0..7 depend only on tokens
  * 0..6).  Shared: the distinct 8-token prefixes of a batch are evaluated once
  * (positions 0..7; keys and values of every layer kept in a model-owned
  * buffer of up to 65,536 entries of L * d * 32 bytes), then positions 8..15 of
  * every configuration attend to its prefix's keys and values (amp_forward).
  * local_energy, whose distinct x' it sorts by prefix, shares a second level
- * for 13..16 tokens: positions 8 .. n-5 once per distinct (n-4)-token prefix
- * (entries of L * d * 16 bytes, in slices of at most 2 GiB), the last four
- * positions per configuration.  The sampler's conditionals are unaffected.
- * Results agree with the unshared evaluation up to the order of fp32 sums.
- * Errors: NQS_EINVAL (null handle).
+ * for 13..16 tokens: positions 8 .. m-1 once per distinct m-token prefix
+ * (entries of L * d * 16 bytes, in slices of at most 2 GiB), positions
+ * m .. m+3 per configuration, with m = n - 4, or m = n - 5 when every level is
+ * masked and the sector leaves one token at the last position (its
+ * conditional is then a membership test).  The tree tail (on = 1, 13..15
+ * tokens, that same kind of sector) goes further: positions 8 .. n-4 once per
+ * distinct (n-4)-token prefix, position n-3 once per distinct (n-3)-token
+ * prefix, n-2 once per distinct (n-2)-token prefix, each keeping its masked
+ * conditional, summed per configuration afterwards.  The sampler's
+ * conditionals are unaffected.  Results agree with the unshared evaluation up
+ * to the order of fp32 sums.
+ * Errors: NQS_EINVAL (null handle, on not 0..2).
  */
 int amp_model_set_prefix_sharing(nqs_model *m, int on);
+
+/*
+ * amp_model_tree_rows - how many distinct (n-3)-token (rows_q) and
+ * (n-2)-token (rows_q1) prefixes the tree tail of local_energy has evaluated
+ * with this model since it was created (one row each; cumulative, for rates).
+ * Errors: NQS_EINVAL (null handle or pointer).
+ */
+int amp_model_tree_rows(const nqs_model *m, int64_t *rows_q, int64_t *rows_q1);
 
 /*
  * amp_model_set_mixed_backward - products of a bf16 transformer's backward

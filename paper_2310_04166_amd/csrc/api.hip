@@ -511,7 +511,17 @@ extern "C" void amp_model_destroy(nqs_model *m) { delete m; }
 extern "C" int amp_model_set_prefix_sharing(nqs_model *m, int on) {
   return guarded([&] {
     NQS_REQUIRE(m, NQS_EINVAL, "amp_model_set_prefix_sharing: null handle");
+    NQS_REQUIRE(on >= 0 && on <= 2, NQS_EINVAL, "amp_model_set_prefix_sharing: on not 0..2");
     m->prefix_share = on != 0;
+    m->tail_tree = on == 1;
+  });
+}
+
+extern "C" int amp_model_tree_rows(const nqs_model *m, int64_t *rows_q, int64_t *rows_q1) {
+  return guarded([&] {
+    NQS_REQUIRE(m && rows_q && rows_q1, NQS_EINVAL, "amp_model_tree_rows: null pointer");
+    *rows_q = m->tree_rows_q;
+    *rows_q1 = m->tree_rows_q1;
   });
 }
 
@@ -702,12 +712,14 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
       launch_emit_pairs(*H, x + i0, i1 - i0, off + i0, xp, hv, nullptr, hdiag + i0, 0, s);
       // grouped by the prefixes of the prefix-shared forward
       const int levels = fused_shared_levels(*m);
-      const int pm = levels == 3 ? 2 * fused_shared_pm(*m) : levels == 2 ? 16 : 0;
+      const bool tree = levels == 3 && fused_tree(*m);
+      const int pm = tree ? -1 : levels == 3 ? 2 * fused_shared_pm(*m) : levels == 2 ? 16 : 0;
       const int64_t nu = dedupe_pairs(xp, np, H->N, pm, keys, vin, vsort, head, run, ukeys, uid,
                                       H->w_tmp, s);
       H->last_distinct += nu;
       if (nu > 0) {
-        if (levels == 3) fused_forward_shared3(*m, ukeys, nu, la, ph, s);
+        if (tree) fused_forward_tree(*m, ukeys, nu, la, ph, s);
+        else if (levels == 3) fused_forward_shared3(*m, ukeys, nu, la, ph, s);
         else if (m->precision == NQS_BF16) bf16_forward(*m, ukeys, nu, la, ph, s);
         else model_forward(*m, ukeys, nu, la, ph, nullptr, s);
       }

@@ -11,7 +11,9 @@
 // most significant, then bits 16 .. pm-1, then the rest - and restored in the
 // output, so that the distinct x' come out grouped by their first 8 tokens and
 // within those by their first pm / 2 tokens (the prefix-shared forward reads
-// one prefix's keys and values for consecutive configurations).
+// one prefix's keys and values for consecutive configurations); pm = -1 orders
+// tokens 8, 9, ... lexicographically after the first 8, so that the x' sharing
+// any prefix of 8 or more tokens are consecutive.
 #include <algorithm>
 
 #include <hipcub/hipcub.hpp>
@@ -35,16 +37,36 @@ __device__ inline uint64_t prefix_key_inverse(uint64_t k, int N, int pm) {
   return (k >> (N - 16)) | (((k >> (N - pm)) & low_bits(pm - 16)) << 16) |
          ((k & low_bits(N - pm)) << pm);
 }
+// the w 2-bit tokens of v in reverse order (an involution)
+__device__ inline uint64_t reverse_tokens(uint64_t v, int w) {
+  uint64_t r = 0;
+  for (int i = 0; i < w; ++i) r |= ((v >> (2 * i)) & 3ull) << (2 * (w - 1 - i));
+  return r;
+}
+// pm = -1: bits 0..15 most significant, then token 8, token 9, ... in that
+// order of significance, so every prefix of 8 or more tokens is contiguous
+__device__ inline uint64_t token_key(uint64_t v, int N) {
+  return ((v & 0xFFFFull) << (N - 16)) | reverse_tokens(v >> 16, (N - 16) / 2);
+}
+__device__ inline uint64_t token_key_inverse(uint64_t k, int N) {
+  return (k >> (N - 16)) | (reverse_tokens(k & low_bits(N - 16), (N - 16) / 2) << 16);
+}
+__device__ inline uint64_t sort_key(uint64_t v, int N, int pm) {
+  return pm > 0 ? prefix_key(v, N, pm) : pm < 0 ? token_key(v, N) : v;
+}
+__device__ inline uint64_t sort_key_inverse(uint64_t k, int N, int pm) {
+  return pm > 0 ? prefix_key_inverse(k, N, pm) : pm < 0 ? token_key_inverse(k, N) : k;
+}
 __global__ void prefix_key_kernel(uint64_t *__restrict__ k, int64_t n, int key_bits, int pm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) k[i] = prefix_key(k[i], key_bits, pm);
+  if (i < n) k[i] = sort_key(k[i], key_bits, pm);
 }
 
 // keys of at most 32 bits: the (reordered) key of every pair as uint32
 __global__ void narrow_key_kernel(const uint64_t *__restrict__ xp, int64_t n, int key_bits, int pm,
                                   uint32_t *__restrict__ k) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) k[i] = uint32_t(pm > 0 ? prefix_key(xp[i], key_bits, pm) : xp[i]);
+  if (i < n) k[i] = uint32_t(sort_key(xp[i], key_bits, pm));
 }
 
 template <class K>
@@ -61,7 +83,7 @@ __global__ void scatter_kernel(const K *__restrict__ keys, const uint32_t *__res
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t id = run[i] - 1u;
-  if (head[i]) ukeys[id] = pm == 0 ? uint64_t(keys[i]) : prefix_key_inverse(keys[i], key_bits, pm);
+  if (head[i]) ukeys[id] = sort_key_inverse(uint64_t(keys[i]), key_bits, pm);
   pair_uid[vals[i]] = id;
 }
 
@@ -80,7 +102,8 @@ int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *ke
                      uint64_t *ukeys, uint32_t *pair_uid, DevBuf &tmp, hipStream_t s) {
   if (n <= 0) return 0;
   NQS_REQUIRE(n < (int64_t(1) << 31), NQS_EUNSUPPORTED, "dedupe: slice too large");
-  NQS_REQUIRE(pm == 0 || (pm >= 16 && pm < key_bits), NQS_EINVAL, "dedupe: prefix fields");
+  NQS_REQUIRE(pm == 0 || (pm >= 16 && pm < key_bits) || (pm == -1 && key_bits > 16 && key_bits % 2 == 0),
+              NQS_EINVAL, "dedupe: prefix fields");
   const int ni = int(n);
   hipLaunchKernelGGL(iota_kernel, g1(n), dim3(256), 0, s, vals_in, n);
   HIP_LAUNCH_OK();
@@ -106,7 +129,7 @@ int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *ke
     HIP_OK(hipStreamSynchronize(s));
     return int64_t(u);
   }
-  if (pm > 0) {
+  if (pm != 0) {
     hipLaunchKernelGGL(prefix_key_kernel, g1(n), dim3(256), 0, s, xp, n, key_bits, pm);
     HIP_LAUNCH_OK();
   }

@@ -97,6 +97,8 @@ struct nqs_model {
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
   nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
   int prefix_share = 1;               // bf16 transformer: prefix-shared evaluation of batches
+  int tail_tree = 1;                  // local energy: the tree tail where the sector allows it
+  int64_t tree_rows_q = 0, tree_rows_q1 = 0;  // distinct prefixes evaluated by the tree tail
   int mixed_backward = 1;             // bf16 transformer: backward on split-bf16 MFMA products
   nqs::DevBuf mx_w;                   // their weight images
   nqs::DevBuf pf_tab, pf_list, pf_logp, pf_kv, pf_scan;  // its prefix table, keys and values
@@ -183,6 +185,14 @@ int fused_shared_levels(const nqs_model &m);
 // The middle split pm: n - 5 when the sector fixes the last token (14..16
 // tokens; that position's conditional is then a membership test), else n - 4.
 int fused_shared_pm(const nqs_model &m);
+// Three levels with the tree tail (13..15 tokens, the sector fixes the last
+// token, tail_tree on): positions 8 .. n-4 once per (n-4)-token prefix, n-3
+// once per (n-3)-token prefix and n-2 once per (n-2)-token prefix, three of
+// the latter with their parent in a slot of four rows; x must be sorted by
+// tokens (dedupe_pairs with pm = -1).
+bool fused_tree(const nqs_model &m);
+void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                        double *phase, hipStream_t s);
 void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
                            double *phase, hipStream_t s);
 // explicit psi over a basis (table.hip): install the basis (host, ascending),

@@ -100,14 +100,34 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // last, a small kernel applies the test, and the middle level holds
 // (n-5)-token prefixes, ~2.4x fewer than (n-4)-token ones on the
 // 30-spin-orbital system.
-// MID / TAIL take their items through an index list (a.src; -1 = padding)
-// in which every 8-token prefix starts a new pass.
-enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5 };
+//   TREE    R = 4:  when the sector fixes the last token (q = n - 3, and
+//                   pm = q - 1): each item is a slot of four rows, one distinct
+//                   q-token prefix (row 0, position q) and up to three of its
+//                   distinct (q+1)-token extensions (rows 1..3, position q + 1);
+//                   a row attends to the 8-token prefix, the
+//                   middle level and, in its slot, to row 0 and itself.  Each
+//                   row stores its masked conditional (4 log-probabilities) per
+//                   prefix; a gather over the configurations adds them up with
+//                   MID's (which also stores the conditional of its row pm) and
+//                   applies the last token's membership test.
+//   PHASE:          no transformer rows: the phase MLP of every configuration.
+// At 15 tokens a configuration's rows 12 and 13 are shared by the ~2.1 x'
+// per 12-token prefix and ~1.5 per 13-token prefix, so TREE evaluates ~3.1e6
+// slots instead of TAIL's 7.7e6 configurations (MID then covers the 11-token
+// prefixes, 1.4e6 instead of 5.9e5).
+// MID / TAIL / TREE take their items through an index list (a.src; -1 =
+// padding; TREE: four entries per slot, one per row) in which every 8-token
+// prefix starts a new pass.
+enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5, TREE = 6, PHASE = 7 };
 template <int MODE>
 struct Rows {
   static constexpr int R = MODE == PLAIN ? 16 : MODE == WIDE ? 32 : MODE <= SUFFIX ? 8 : 4;
   static constexpr int CPT = 32 / R;            // configurations per pass
   static constexpr int P0 = MODE == SUFFIX || MODE == MID ? kTrunk : MODE == TAIL ? 12 : 0;
+  // layouts that attend to both stored levels (8-token prefix and middle)
+  static constexpr bool TAILS = MODE == TAIL || MODE == TREE;
+  // layouts that read the 8-token prefix's stored entry through an item list
+  static constexpr bool LISTED = MODE == MID || TAILS;
   static constexpr int MAXP = 32 / CPT;         // passes per chunk of 32 configurations
 };
 // Fragment sets (1 = hi, 2 = hi and lo) of the attention matrices (Q, K, V,
@@ -161,6 +181,12 @@ struct FusedArgs {
   int64_t j0;                       // first pm-token prefix entry held in kv2 (a slice)
   float *plogp2;
   int pm;                           // MID covers positions 8 .. pm - 1, TAIL pm .. pm + 3
+  // TREE (pm = q - 1): the masked conditionals, 4 floats per prefix: of MID's
+  // row pm per pm-token prefix (lp_mid; MID stores it when set), of row q per
+  // q-token prefix (lp_q) and of row q + 1 per (q+1)-token prefix (lp_q1), whose
+  // indices for configuration i are preq[i + 1] - 1 and preq1[i + 1] - 1
+  float *lp_mid, *lp_q, *lp_q1;
+  const int64_t *preq, *preq1;
 };
 
 // A buffer store whose per-lane offset is at least the resource's size is
@@ -516,7 +542,8 @@ fused_kernel(FusedArgs a) {
   }
   if (bc0 * block_cfgs >= B) return;
   const int c = r / R;               // configuration of this lane's row within the pass
-  const int t = (MODE == TAIL ? a.pm : P0) + r % R;   // position of this lane's row
+  // position of this lane's row (TREE: row 0 of a slot at q = pm + 1, rows 1..3 at q + 1)
+  const int t = MODE == TAIL ? a.pm + r % R : MODE == TREE ? a.pm + 1 + (r % R != 0) : P0 + r % R;
   const int n = a.n;
   const bf16x8 *pk = a.pk + lane;
   const float *vec = a.vec;
@@ -540,12 +567,15 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     const int kp = R == 4 ? i : R == 8 ? h * 4 + i : (i / 4) * 8 + h * 4 + (i % 4);   // key position - P0
-    madd[i] = kp <= r % R && (R != 4 || own_half) ? 0.f : -INFINITY;
+    // TREE: row 0 of a slot sees itself, rows 1..3 row 0 and themselves
+    const bool causal = MODE == TREE ? i == 0 || i == r % R : kp <= r % R;
+    madd[i] = causal && (R != 4 || own_half) ? 0.f : -INFINITY;
   }
-  // TAIL: the middle level's keys (positions 8 + i, those below pm)
+  // TAIL: the middle level's keys (positions 8 + i, those below pm; TREE: up to pm)
   float madd_mid[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) madd_mid[i] = own_half && 8 + i < a.pm ? 0.f : -INFINITY;
+  for (int i = 0; i < 4; ++i)
+    madd_mid[i] = own_half && 8 + i < a.pm + (MODE == TREE) ? 0.f : -INFINITY;
   // prefix entries (TRUNK .. TAIL), read and written through buffer resources
   const __amdgpu_buffer_rsrc_t kvr =
       __builtin_amdgcn_make_buffer_rsrc(a.kv, 0, int(uint32_t(a.kv_total)), 0x00020000);
@@ -587,12 +617,16 @@ fused_kernel(FusedArgs a) {
   for (int64_t bc = bc0; bc * block_cfgs < B; bc += gridDim.x) {
   const int64_t c_base = bc * block_cfgs + int64_t(wv) * CPT * passes;
   for (int pass = 0; pass < passes; ++pass) {
+    if constexpr (MODE == PHASE) break;             // no transformer rows
     const int64_t cfg0 = c_base + CPT * pass;
     if (bc * block_cfgs + CPT * pass >= B) break;   // uniform over the block
-    // MID / TAIL: item cfg0 + c stands for configuration src (-1: padding)
-    const int64_t src = MODE >= MID ? (cfg0 + c < B ? a.src[cfg0 + c] : -1) : cfg0 + c;
-    const int64_t cfg = MODE >= MID ? src : cfg0 + c;
-    const bool live = MODE >= MID ? src >= 0 : cfg < B;
+    // MID / TAIL: item cfg0 + c stands for configuration src (-1: padding);
+    // TREE: row r % 4 of slot cfg0 + c for src, its row 0 for src0
+    constexpr int ST = MODE == TREE ? 4 : 1;        // list entries per item
+    const int64_t src0 = Rows<MODE>::LISTED ? (cfg0 + c < B ? a.src[ST * (cfg0 + c)] : -1) : cfg0 + c;
+    const int64_t src = MODE == TREE ? (cfg0 + c < B ? a.src[ST * (cfg0 + c) + r % 4] : -1) : src0;
+    const int64_t cfg = Rows<MODE>::LISTED ? src : cfg0 + c;
+    const bool live = Rows<MODE>::LISTED ? src >= 0 : cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
     // prefix entries: of this lane's configuration (keys, log-probability) and
     // of the pass's four configurations (values)
@@ -621,15 +655,17 @@ fused_kernel(FusedArgs a) {
     int64_t ent8 = 0, ent12 = 0;
     uint32_t kv8_off = 0, mid_own = 0, mid_e[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t mid_live = 0;             // bit k: item k of the pass is not padding
-    if constexpr (MODE >= MID) {
-      ent8 = a.pre8[a.src[cfg0] + 1] - 1;
+    if constexpr (Rows<MODE>::LISTED) {
+      // (waves past the end of the items read nothing and store nothing)
+      const int64_t s8 = cfg0 < B ? a.src[ST * cfg0] : -1;
+      ent8 = s8 >= 0 ? a.pre8[s8 + 1] - 1 : 0;
       kv8_off = uint32_t(ent8 * a.kv_bytes);
-      ent12 = live ? a.pre12[src + 1] - 1 : a.j0;
+      ent12 = src0 >= 0 ? a.pre12[src0 + 1] - 1 : a.j0;
       mid_own = uint32_t((ent12 - a.j0) * a.kv2_bytes);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int64_t it = cfg0 + k;
-        const int64_t sc = it < B ? a.src[it] : -1;
+        const int64_t sc = it < B ? a.src[ST * it] : -1;
         mid_live |= sc >= 0 ? (1u << k) : 0u;
         mid_e[k] = uint32_t((sc >= 0 ? a.pre12[sc + 1] - 1 - a.j0 : 0) * a.kv2_bytes);
       }
@@ -708,27 +744,27 @@ fused_kernel(FusedArgs a) {
         // configuration 4s + h, slots 4..7 from 4s + 2 + h), all read while Q,
         // K and V are computed
         bf16x8 Vt, Vm[2], Kt[2], Km[2];
-        if constexpr (MODE >= MID) {
+        if constexpr (Rows<MODE>::LISTED) {
 #pragma unroll
           for (int e = 0; e < 2; ++e)
             Kt[e] = __builtin_bit_cast(
                 bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv8_off + kv_key_lane,
                                                               kv_key_off<NB>(l, b, e), 0));
         }
-        if constexpr (MODE == TAIL) {
+        if constexpr (Rows<MODE>::TAILS) {
 #pragma unroll
           for (int e = 0; e < 2; ++e)
             Km[e] = __builtin_bit_cast(
                 bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kv2r, mid_own + mk_lane,
                                                               mk_off<NB>(l, b, e), 0));
         }
-        if constexpr (MODE >= MID) {
+        if constexpr (Rows<MODE>::LISTED) {
           const i32x2 v = __builtin_bit_cast(
               i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8_off + kv_val_lane,
                                                           kv_val_off<NB>(l, b), 0));
           Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], 0, 0});
         }
-        if constexpr (MODE == TAIL) {
+        if constexpr (Rows<MODE>::TAILS) {
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const i32x2 v0 = __builtin_bit_cast(
@@ -823,7 +859,7 @@ fused_kernel(FusedArgs a) {
           constexpr int NO = R == 4 ? 4 : R / 2;       // own keys per lane
           // prefix keys per lane: SUFFIX 4 of the 8-token prefix; MID those 4;
           // TAIL also 4 of the middle level
-          constexpr int NK = MODE == SUFFIX || MODE == MID ? 4 : MODE == TAIL ? 8 : 0;
+          constexpr int NK = MODE == SUFFIX || MODE == MID ? 4 : Rows<MODE>::TAILS ? 8 : 0;
           float p[NO + NK];
           float mx = -INFINITY;
           constexpr float kScale = 0.25f * 1.4426950408889634f;   // 1/sqrt(16), base 2
@@ -848,7 +884,7 @@ fused_kernel(FusedArgs a) {
               mx = fmaxf(mx, p[NO + i]);
             }
           }
-          if constexpr (MODE >= MID) {
+          if constexpr (Rows<MODE>::LISTED) {
             __builtin_amdgcn_sched_barrier(0);
             // the 8-token prefix's keys of this lane half: positions 4h + i in slots 0..3
             const f32x16 St = mfma(Kt[e], Qe, f32x16{});
@@ -858,7 +894,7 @@ fused_kernel(FusedArgs a) {
               mx = fmaxf(mx, p[NO + i]);
             }
           }
-          if constexpr (MODE == TAIL) {
+          if constexpr (Rows<MODE>::TAILS) {
             __builtin_amdgcn_sched_barrier(0);
             const f32x16 Sm = mfma(Km[e], Qe, f32x16{});
 #pragma unroll
@@ -930,7 +966,7 @@ fused_kernel(FusedArgs a) {
             pack4_hilo(p + NO, hw, lw);
             Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(hw[0]), int(hw[1]), 0, 0}), Oe);
             Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(lw[0]), int(lw[1]), 0, 0}), Oe);
-            if constexpr (MODE == TAIL) {
+            if constexpr (Rows<MODE>::TAILS) {
               pack4_hilo(p + NO + 4, hw, lw);
               Oe = mfma(Vm[0], place(hw, 0), Oe);
               Oe = mfma(Vm[1], place(hw, 1), Oe);
@@ -1092,8 +1128,11 @@ fused_kernel(FusedArgs a) {
       }
     }
     const nqs_sector_info &si = sector_of(a.sec, x);
-    // (MID: its rows from pm on belong to TAIL)
-    if (t < si.n && (MODE != MID || t < a.pm)) {
+    // rows whose whole masked conditional is kept: every TREE row, MID's row
+    // pm when TREE follows (its token varies within the pm-token prefix)
+    const bool cond_row = MODE == TREE || (MODE == MID && a.lp_mid != nullptr && t == a.pm);
+    // (MID: its rows from pm on belong to TAIL / TREE)
+    if (t < si.n && (MODE != MID || t < a.pm || cond_row)) {
       const uint64_t below = (t == 0) ? 0ull : (~0ull >> (64 - 2 * t));
       const int na = __popcll(x & below & 0x5555555555555555ull);
       const int nb = __popcll(x & below & 0xAAAAAAAAAAAAAAAAull);
@@ -1107,9 +1146,19 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if ((allow >> k) & 1) z += expf(lg[k] - mx);
-      logp = ((allow >> tk) & 1) ? lg[tk] - mx - logf(z) : -INFINITY;
+      const float lz = logf(z);
+      if (MODE != TREE && (MODE != MID || t < a.pm))
+        logp = ((allow >> tk) & 1) ? lg[tk] - mx - lz : -INFINITY;
+      if constexpr (MODE == TREE || MODE == MID) {
+        if (cond_row && h == 0 && live) {
+          float *dst = MODE == MID ? a.lp_mid : r % R == 0 ? a.lp_q : a.lp_q1;
+          const int64_t e = MODE == MID ? ent12 : (r % R == 0 ? a.preq : a.preq1)[src + 1] - 1;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dst[4 * e + k] = ((allow >> k) & 1) ? lg[k] - mx - lz : -INFINITY;
+        }
+      }
     }
-    if (MODE == TRUNK || MODE == MID || a.logabs) {
+    if (MODE == TRUNK || MODE == MID || (MODE != TREE && a.logabs)) {
       // sum over the configuration's R rows
 #pragma unroll
       for (int w = 1; w < R; w *= 2) logp += __shfl_xor(logp, w);
@@ -1130,7 +1179,7 @@ fused_kernel(FusedArgs a) {
   }
 
   // ---- phase MLP for the chunk's configurations (column = configuration)
-  if (MODE != TRUNK && MODE != MID && a.phase) {
+  if (MODE != TRUNK && MODE != MID && MODE != TREE && a.phase) {
     constexpr int PH = 256, PKS = PH / 16, PB = PH / 32;
     const int64_t item = c_base + r;
     const bool in = r < CPT * passes && item < B;
@@ -1295,7 +1344,9 @@ void launch_d(int mode, const FusedArgs &a, dim3 grid, size_t lds_bytes, hipStre
     case TRUNK: launch_mode<D, TRUNK>(a, grid, lds_bytes, s); break;
     case SUFFIX: launch_mode<D, SUFFIX>(a, grid, lds_bytes, s); break;
     case MID: launch_mode<D, MID>(a, grid, lds_bytes, s); break;
-    default: launch_mode<D, TAIL>(a, grid, lds_bytes, s); break;
+    case TAIL: launch_mode<D, TAIL>(a, grid, lds_bytes, s); break;
+    case TREE: launch_mode<D, TREE>(a, grid, lds_bytes, s); break;
+    default: launch_mode<D, PHASE>(a, grid, lds_bytes, s); break;
   }
 }
 
@@ -1375,6 +1426,112 @@ __global__ void prefix_maps_kernel(int64_t B, const int64_t *__restrict__ hm,
   const int64_t g = pre8[i + 1] - 1;
   tail[start_t[g] + i - first8[g]] = i;
   if (hm[i]) mid[start_m[g] + prem[i] - firstm[g]] = i;
+}
+
+// ---- tree tail (TREE) bookkeeping over x sorted by tokens (bits 0..15 first,
+// then token 8, 9, ...): every prefix of 8 or more tokens is a contiguous run.
+__host__ __device__ inline uint64_t low_mask(int b) { return b >= 64 ? ~0ull : (1ull << b) - 1; }
+// h8 / hm / hq / hq1[i] = 1 where configuration i starts a new 8-, m-, q- or
+// (q+1)-token prefix
+__global__ void tree_heads_kernel(const uint64_t *__restrict__ x, int64_t B, int m, int q,
+                                  int64_t *__restrict__ h8, int64_t *__restrict__ hm,
+                                  int64_t *__restrict__ hq, int64_t *__restrict__ hq1) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t d = i == 0 ? ~0ull : x[i] ^ x[i - 1];
+  h8[i] = (d & 0xFFFFull) != 0;
+  hm[i] = (d & low_mask(2 * m)) != 0;
+  hq[i] = (d & low_mask(2 * q)) != 0;
+  hq1[i] = (d & low_mask(2 * q + 2)) != 0;
+}
+// firstq[k] = first configuration of q-token prefix k
+__global__ void tree_firsts_kernel(const int64_t *__restrict__ hq, const int64_t *__restrict__ preq,
+                                   int64_t B, int64_t *__restrict__ firstq) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < B && hq[i]) firstq[preq[i]] = i;
+}
+// slots of q-token prefix k: its (q+1)-token extensions, three per slot
+__global__ void tree_nodes_kernel(const int64_t *__restrict__ firstq, int64_t Q, int64_t B,
+                                  const int64_t *__restrict__ preq1, int64_t *__restrict__ nslot) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= Q) return;
+  const int64_t i = firstq[k], inext = k + 1 < Q ? firstq[k + 1] : B;
+  nslot[k] = (preq1[inext] - preq1[i] + 2) / 3;
+}
+// per 8-token group g: slots and middle items padded to multiples of 8 (a
+// pass never mixes 8-token prefixes), zero beyond the last group
+__global__ void tree_pads_kernel(const int64_t *__restrict__ pre8, const int64_t *__restrict__ preq,
+                                 int64_t B, const int64_t *__restrict__ first8,
+                                 const int64_t *__restrict__ firstm, const int64_t *__restrict__ es,
+                                 int64_t K, int64_t *__restrict__ pad_s, int64_t *__restrict__ pad_m) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= K) return;
+  const int64_t G = pre8[B];
+  if (g >= G) {
+    pad_s[g] = 0;
+    pad_m[g] = 0;
+    return;
+  }
+  // first8[G] = B and preq[B] = the number of q-token prefixes
+  const int64_t k0 = preq[first8[g]], k1 = preq[first8[g + 1]];
+  pad_s[g] = (es[k1] - es[k0] + 7) / 8 * 8;
+  pad_m[g] = (firstm[g + 1] - firstm[g] + 7) / 8 * 8;
+}
+// item lists: mid[start_m[g] + j - firstm[g]] = first configuration of m-token
+// prefix j; slot entries tree[4 s + 0] = first configuration of the slot's
+// q-token prefix, tree[4 s + p] (p = 1..3) = first configuration of its
+// extension 3 (s - first slot of the prefix) + p - 1
+__global__ void tree_lists_kernel(int64_t B, const int64_t *__restrict__ hm,
+                                  const int64_t *__restrict__ hq1, const int64_t *__restrict__ pre8,
+                                  const int64_t *__restrict__ prem, const int64_t *__restrict__ preq,
+                                  const int64_t *__restrict__ preq1,
+                                  const int64_t *__restrict__ first8,
+                                  const int64_t *__restrict__ firstm,
+                                  const int64_t *__restrict__ firstq, const int64_t *__restrict__ es,
+                                  const int64_t *__restrict__ start_s,
+                                  const int64_t *__restrict__ start_m, int64_t *__restrict__ mid,
+                                  int64_t *__restrict__ tree) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const int64_t g = pre8[i + 1] - 1;
+  if (hm[i]) mid[start_m[g] + prem[i] - firstm[g]] = i;
+  if (hq1[i]) {
+    const int64_t k = preq[i + 1] - 1, iq = firstq[k];
+    const int64_t rank = preq1[i] - preq1[iq];
+    const int64_t slot = start_s[g] + (es[k] - es[preq[first8[g]]]) + rank / 3;
+    const int p = 1 + int(rank % 3);
+    tree[4 * slot + p] = i;
+    if (p == 1) tree[4 * slot] = iq;
+  }
+}
+// log|psi| of every configuration from the stored conditionals: tokens 0..7
+// (plogp), 8..m-1 (plogp2), token m = q - 1 (lp_mid), q (lp_q), q + 1 (lp_q1)
+// and the membership test of the last token, q + 2 = n - 1
+__global__ void tree_gather_kernel(Sectors sec, const uint64_t *__restrict__ x, int64_t B, int q,
+                                   const int64_t *__restrict__ pre8, const int64_t *__restrict__ prem,
+                                   const int64_t *__restrict__ preq,
+                                   const int64_t *__restrict__ preq1,
+                                   const float *__restrict__ plogp, const float *__restrict__ plogp2,
+                                   const float *__restrict__ lp_mid, const float *__restrict__ lp_q,
+                                   const float *__restrict__ lp_q1, double *__restrict__ logabs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t v = x[i];
+  const int64_t g = pre8[i + 1] - 1, j = prem[i + 1] - 1, k = preq[i + 1] - 1, c = preq1[i + 1] - 1;
+  const int tm = int((v >> (2 * (q - 1))) & 3ull), tq = int((v >> (2 * q)) & 3ull),
+            tq1 = int((v >> (2 * q + 2)) & 3ull);
+  float lp = plogp[g] + plogp2[j];
+  lp += lp_mid[4 * j + tm];
+  lp += lp_q[4 * k + tq];
+  lp += lp_q1[4 * c + tq1];
+  const nqs_sector_info &si = sector_of(sec, v);
+  const int t = si.n - 1;
+  const uint64_t below = ~0ull >> (64 - 2 * t);
+  const int na = __popcll(v & below & 0x5555555555555555ull);
+  const int nb = __popcll(v & below & 0xAAAAAAAAAAAAAAAAull);
+  const int allow = phys_mask(sec, si, t, na, nb, v);
+  if (!((allow >> int((v >> (2 * t)) & 3ull)) & 1)) lp = -INFINITY;
+  logabs[i] = 0.5 * double(lp);
 }
 
 // Position n - 1 when the sector leaves at most one token there: its masked
@@ -1749,6 +1906,144 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
     hipLaunchKernelGGL(last_token_kernel, g1(B), dim3(256), 0, s, m.sectors(), x, B, logabs);
     HIP_LAUNCH_OK();
   }
+}
+
+bool fused_tree(const nqs_model &m) {
+  return m.tail_tree && fused_shared_levels(m) == 3 && m.n <= 15 && last_token_fixed(m);
+}
+
+void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
+                        double *phase, hipStream_t s) {
+  NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
+  NQS_REQUIRE(fused_tree(m), NQS_EUNSUPPORTED, "tree forward: unsupported model");
+  if (B <= 0) return;
+  constexpr int64_t K = int64_t(1) << 16;      // 8-token prefixes
+  const int q = m.n - 3, pm = q - 1;           // TREE rows at q and q + 1
+  const int64_t kv_bytes = int64_t(m.L) * (m.d / 32) * 1024;
+  const int64_t kv2_bytes = int64_t(m.L) * (m.d / 32) * 512;
+  const int64_t cap8 = std::min(K, B), items = B + 7 * cap8;
+  // workspaces: flags, their scans, first configurations of the q-token
+  // prefixes, slots per prefix and their scan, groups, pads and their scans,
+  // item lists (middle: one entry per item; tree: four per slot)
+  const int64_t B1 = B + 1, K1 = K + 1;
+  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(11 * B1 + 6 * K1 + 5 * items) * 8));
+  int64_t *h8 = w, *hm = h8 + B1, *hq = hm + B1, *hq1 = hq + B1;
+  int64_t *pre8 = hq1 + B1, *prem = pre8 + B1, *preq = prem + B1, *preq1 = preq + B1;
+  int64_t *firstq = preq1 + B1, *nslot = firstq + B1, *es = nslot + B1;
+  int64_t *first8 = es + B1, *firstm = first8 + K1, *pad_s = firstm + K1, *pad_m = pad_s + K1;
+  int64_t *start_s = pad_m + K1, *start_m = start_s + K1;
+  int64_t *mid = start_m + K1, *tree = mid + items;
+  auto *list8 = static_cast<uint64_t *>(m.pf_list.reserve(size_t(cap8) * 8));
+  auto *plogp = static_cast<float *>(m.pf_logp.reserve(size_t(cap8) * 4));
+  auto *kv = static_cast<uint8_t *>(m.pf_kv.reserve(size_t(cap8) * size_t(kv_bytes)));
+  // per-prefix floats: plogp2 (B), lp_mid, lp_q, lp_q1 (4 B each)
+  auto *fl = static_cast<float *>(m.pf3_logp.reserve(size_t(13 * B) * 4));
+  float *plogp2 = fl, *lp_mid = fl + B, *lp_q = lp_mid + 4 * B, *lp_q1 = lp_q + 4 * B;
+  hipLaunchKernelGGL(tree_heads_kernel, g1(B), dim3(256), 0, s, x, B, pm, q, h8, hm, hq, hq1);
+  HIP_LAUNCH_OK();
+  launch_exclusive_scan(h8, pre8, B, s, m.pf_scan);
+  launch_exclusive_scan(hm, prem, B, s, m.pf_scan);
+  launch_exclusive_scan(hq, preq, B, s, m.pf_scan);
+  launch_exclusive_scan(hq1, preq1, B, s, m.pf_scan);
+  hipLaunchKernelGGL(prefix_groups_kernel, g1(B), dim3(256), 0, s, x, B, h8, pre8, prem, first8,
+                     firstm, list8);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(tree_firsts_kernel, g1(B), dim3(256), 0, s, hq, preq, B, firstq);
+  HIP_LAUNCH_OK();
+  int64_t cnt[4] = {0, 0, 0, 0};
+  HIP_OK(hipMemcpyAsync(&cnt[0], pre8 + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&cnt[1], prem + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&cnt[2], preq + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&cnt[3], preq1 + B, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int64_t G = cnt[0], PM = cnt[1], Q = cnt[2], Q1 = cnt[3];
+  NQS_REQUIRE(G >= 1 && G <= cap8 && PM >= G && Q >= PM && Q1 >= Q && Q1 <= B, NQS_EINVAL,
+              "tree forward: prefix count");
+  m.tree_rows_q += Q;
+  m.tree_rows_q1 += Q1;
+  hipLaunchKernelGGL(tree_nodes_kernel, g1(Q), dim3(256), 0, s, firstq, Q, B, preq1, nslot);
+  HIP_LAUNCH_OK();
+  launch_exclusive_scan(nslot, es, Q, s, m.pf_scan);
+  hipLaunchKernelGGL(tree_pads_kernel, g1(K), dim3(256), 0, s, pre8, preq, B, first8, firstm, es,
+                     K, pad_s, pad_m);
+  HIP_LAUNCH_OK();
+  launch_exclusive_scan(pad_s, start_s, K, s, m.pf_scan);
+  launch_exclusive_scan(pad_m, start_m, K, s, m.pf_scan);
+  hipLaunchKernelGGL(fill_i64_kernel, g1(5 * items), dim3(256), 0, s, mid, 5 * items, int64_t(-1));
+  HIP_LAUNCH_OK();
+  std::vector<int64_t> st_s(size_t(G) + 1), st_m(size_t(G) + 1), fm(size_t(G) + 1);
+  HIP_OK(hipMemcpyAsync(st_s.data(), start_s, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(st_m.data(), start_m, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(fm.data(), firstm, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  // the lists' sizes are bounded by the allocation before any entry is written
+  NQS_REQUIRE(st_s[size_t(G)] <= items && st_m[size_t(G)] <= items && st_s[size_t(G)] >= Q &&
+                  st_m[size_t(G)] >= PM,
+              NQS_EINVAL, "tree forward: item lists");
+  hipLaunchKernelGGL(tree_lists_kernel, g1(B), dim3(256), 0, s, B, hm, hq1, pre8, prem, preq, preq1,
+                     first8, firstm, firstq, es, start_s, start_m, mid, tree);
+  HIP_LAUNCH_OK();
+
+  Layout L = plan(m);
+  FusedArgs a = L.a;
+  a.pk = m.packed.as<bf16x8>();
+  a.vec = m.packed_vec.as<float>();
+  a.sec = m.sectors();
+  a.n = m.n;
+  a.L = m.L;
+  a.cond_p = -1;
+  a.cond = nullptr;
+  a.kv = kv;
+  a.kv_bytes = kv_bytes;
+  a.kv_total = cap8 * kv_bytes;
+  a.plogp = plogp;
+  a.pre8 = pre8;
+  a.pre12 = prem;
+  a.kv2_bytes = kv2_bytes;
+  a.plogp2 = plogp2;
+  a.pm = pm;
+  a.lp_mid = lp_mid;
+  a.lp_q = lp_q;
+  a.lp_q1 = lp_q1;
+  a.preq = preq;
+  a.preq1 = preq1;
+  a.logabs = nullptr;
+  a.phase = nullptr;
+  // positions 0..7 once per 8-token prefix (entry g = group g)
+  a.x = list8;
+  a.B = G;
+  launch_fused(m, TRUNK, a, G, s, nullptr, 0, 0);
+  // positions 8 .. pm once per pm-token prefix, then the slots (positions q
+  // and q + 1), in slices of whole groups whose middle entries fit in 32-bit
+  // offsets
+  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  auto *kv2 = static_cast<uint8_t *>(m.pf3_kv.reserve(size_t(slice) * size_t(kv2_bytes)));
+  a.kv2 = kv2;
+  a.kv2_total = slice * kv2_bytes;
+  a.x = x;
+  for (int64_t g0 = 0; g0 < G;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
+    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "tree forward: slice");
+    a.j0 = fm[size_t(g0)];
+    a.src = mid + st_m[size_t(g0)];
+    a.B = st_m[size_t(g1)] - st_m[size_t(g0)];
+    launch_fused(m, MID, a, a.B, s, nullptr, 0, 0);
+    a.src = tree + 4 * st_s[size_t(g0)];
+    a.B = st_s[size_t(g1)] - st_s[size_t(g0)];
+    launch_fused(m, TREE, a, a.B, s, nullptr, 0, 0);
+    g0 = g1;
+  }
+  // the phase MLP of every configuration
+  if (phase) {
+    a.src = nullptr;
+    a.B = B;
+    a.phase = phase;
+    launch_fused(m, PHASE, a, B, s, nullptr, 0, 0);
+  }
+  hipLaunchKernelGGL(tree_gather_kernel, g1(B), dim3(256), 0, s, a.sec, x, B, q, pre8, prem, preq,
+                     preq1, plogp, plogp2, lp_mid, lp_q, lp_q1, logabs);
+  HIP_LAUNCH_OK();
 }
 
 bool timing_on() { return g_timing; }

@@ -78,6 +78,7 @@ _SIGS = {
     "amp_model_set_sectors": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "amp_model_set_z2": ([_vp, C.c_int, _vp, _vp], C.c_int),
     "amp_model_set_prefix_sharing": ([_vp, C.c_int], C.c_int),
+    "amp_model_tree_rows": ([_vp, C.POINTER(_i64), C.POINTER(_i64)], C.c_int),
     "amp_model_set_mixed_backward": ([_vp, C.c_int], C.c_int),
     "amp_model_set_symmetries": ([_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp], C.c_int),
     "sample_unique_batch": ([_vp, C.c_int, _vp, _u64, _vp, _vp, _i64, C.POINTER(_i64), _vp,
@@ -238,10 +239,18 @@ class Model:
         _check(lib().amp_model_set_sectors(self.handle, a.shape[1], _ptr(a[0].copy()),
                                            _ptr(a[1].copy()), _ptr(a[2].copy())))
 
-    def set_prefix_sharing(self, on):
-        """bf16 transformer batches by shared 8-token prefixes (default) or
-        configuration by configuration (``amp_model_set_prefix_sharing``)."""
-        _check(lib().amp_model_set_prefix_sharing(self.handle, 1 if on else 0))
+    def set_prefix_sharing(self, on, tree=True):
+        """bf16 transformer batches by shared prefixes (default; ``tree``: the
+        local energy's tree tail where the sector allows it) or configuration
+        by configuration (``amp_model_set_prefix_sharing``)."""
+        _check(lib().amp_model_set_prefix_sharing(self.handle, (1 if tree else 2) if on else 0))
+
+    def tree_rows(self):
+        """Distinct (n-3)- and (n-2)-token prefixes evaluated so far by the
+        local energy's tree tail (``amp_model_tree_rows``)."""
+        q, q1 = _i64(), _i64()
+        _check(lib().amp_model_tree_rows(self.handle, C.byref(q), C.byref(q1)))
+        return q.value, q1.value
 
     def set_mixed_backward(self, on):
         """bf16 transformer backward on split-bf16 MFMA products (default) or
@@ -539,6 +548,7 @@ def sampler_device_walk(on=True):
 
 
 TIMING_PLAIN, TIMING_WIDE, TIMING_TRUNK, TIMING_SUFFIX, TIMING_MID, TIMING_TAIL = 0, 1, 2, 3, 4, 5
+TIMING_TREE, TIMING_PHASE = 6, 7
 TIMING_NADE = -1
 
 

@@ -145,6 +145,7 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
     spec = transformer_param_spec(n, d, L, 4 * d, 256)
     m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, L, d // 16, 4 * d, 256],
                   flatten_params(params, spec), "bf16", strategy, 2 if strategy == "MUd" else 0)
+    m.set_prefix_sharing(True, tree=False)    # the middle split of the TAIL layout
     sec = Sector(n, na, nb)
     if general is not None:
         eig = [two_sz_eigs(n)] if general == "sz" else [particle_number_eigs(n), two_sz_eigs(n)]
@@ -172,7 +173,7 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
     assert (mid_items, tail_items) == (mid_want, tail_want)
     m.set_prefix_sharing(False)
     eu, su, _ = nqs.local_energy(H, m, x, c)
-    m.set_prefix_sharing(True)
+    m.set_prefix_sharing(True, tree=False)
     s3, su = s3.cpu().numpy(), su.cpu().numpy()
     assert abs(s3[1] / s3[0] - su[1] / su[0]) < 1e-5
     ref = TransformerModel(params, sec, d // 16)
@@ -180,6 +181,107 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
     top = list(np.argsort(-cv, kind="stable")[:4])
     xv = x.cpu().numpy().view(np.uint64)
     e = e3.cpu().numpy()
+    res = eloc_bound.check(ref, h, eri, [int(xv[i]) for i in top], eloc_bound.gpu_amplitudes(nqs, m))
+    for i, (want, A, eps) in zip(top, res):
+        err = abs(e[i] - want)
+        print(f"  x={int(xv[i]):#x} count={cv[i]} err {err:.2e} bound {2 * eps * A:.2e}", flush=True)
+        assert err <= 1.5 * 2 * eps * A + 1e-9
+
+
+def expected_tree_items(u, n):
+    """Items of the MID and TREE launches of the tree tail over the distinct x'
+    u (q = n - 3): per 8-token prefix its distinct (q-1)-token prefixes (MID)
+    and, per distinct q-token prefix, one slot for every three of its distinct
+    (q+1)-token extensions (TREE), each padded to a multiple of 8."""
+    q = n - 3
+    u = np.unique(np.asarray(u, dtype=np.uint64))
+    pad = lambda k: int(np.sum((k + 7) // 8 * 8))
+    gm = np.unique(u & np.uint64((1 << (2 * (q - 1))) - 1))
+    _, k_mid = np.unique(gm & np.uint64(0xFFFF), return_counts=True)
+    g1 = np.unique(u & np.uint64((1 << (2 * (q + 1))) - 1))
+    nq, ch = np.unique(g1 & np.uint64((1 << (2 * q)) - 1), return_counts=True)
+    slots = (ch + 2) // 3
+    g8 = nq & np.uint64(0xFFFF)
+    groups, inv = np.unique(g8, return_inverse=True)
+    per = np.bincount(inv, weights=slots).astype(np.int64)
+    return pad(k_mid), pad(per)
+
+
+# (n, n_alpha, n_beta, d, layers, samples, strategy, general symmetries, tree):
+# the tree tail where every level is masked and the last token is fixed (13..15
+# tokens, particle-number tables or general symmetries), not otherwise
+@pytest.mark.parametrize("n,na,nb,d,L,samples,strategy,general,tree", [
+    (13, 3, 3, 64, 2, 20_000, "MU", None, True),
+    (14, 2, 3, 128, 2, 50_000, "MU", None, True),
+    (15, 3, 2, 64, 1, 20_000, "MU", "n_sz", True),
+    (15, 3, 2, 64, 1, 20_000, "MU", "sz", False),
+    (14, 3, 3, 64, 1, 20_000, "MUd", None, False),
+])
+def test_tree_tail_vs_tail_unshared_and_oracle(n, na, nb, d, L, samples, strategy, general, tree):
+    """The local energy through the tree tail (each of positions n-3 and n-2
+    once per distinct prefix, their masked conditionals gathered per x')
+    against the per-configuration tail rows and the unshared evaluation (same
+    bf16 operands), its launches' items against the prefix counts, and on the
+    four highest-count samples against the FP64 oracle."""
+    import eloc_bound
+    from oracle.model import TransformerModel
+    from oracle.sector import GeneralSector, Sector, particle_number_eigs, two_sz_eigs
+    from paper_2310_04166_amd import nqs
+    from synth import make_integrals, make_transformer_params
+    nqs.lib()
+    h, eri = make_integrals(n, n, 90 + n)
+    params = make_transformer_params(n, na, nb, d, L, seed=n + 7, std=0.05, hf_bias=1.0,
+                                     round_to="bf16", bias_std=0.02)
+    spec = transformer_param_spec(n, d, L, 4 * d, 256)
+    m = nqs.Model(nqs.MODEL_TRANSFORMER, [n, na, nb, d, L, d // 16, 4 * d, 256],
+                  flatten_params(params, spec), "bf16", strategy, 2 if strategy == "MUd" else 0)
+    sec = Sector(n, na, nb)
+    if general is not None:
+        eig = [two_sz_eigs(n)] if general == "sz" else [particle_number_eigs(n), two_sz_eigs(n)]
+        tgt = [na - nb] if general == "sz" else [na + nb, na - nb]
+        m.set_symmetries(eig, tgt)
+        sec = GeneralSector(n, eig, tgt)
+    H = nqs.ham_compile(h, eri, na, nb)
+    x, c, _ = nqs.sample_unique(m, samples, 9)
+    _, xp, _, _ = nqs.connected_pairs(H, x)
+    u = torch.unique(xp).cpu().numpy().view(np.uint64)
+    nqs.timing_read()
+    nqs.timing_enable(True)
+    try:
+        et, st, _ = nqs.local_energy(H, m, x, c)
+        torch.cuda.synchronize()
+        assert nqs.local_energy_stats(H)[1] == len(u)
+        _, _, mid_items = nqs.timing_read(nqs.TIMING_MID)
+        _, _, tree_items = nqs.timing_read(nqs.TIMING_TREE)
+        _, _, tail_items = nqs.timing_read(nqs.TIMING_TAIL)
+        _, _, phase_items = nqs.timing_read(nqs.TIMING_PHASE)
+    finally:
+        nqs.timing_enable(False)
+        nqs.timing_read()
+    print(f"n={n} {strategy} {general}: {x.numel()} samples, {len(u)} distinct x'; items MID "
+          f"{mid_items} TREE {tree_items} TAIL {tail_items} PHASE {phase_items}", flush=True)
+    if tree:
+        want_mid, want_tree = expected_tree_items(u, n)
+        print(f"  expected MID {want_mid} TREE {want_tree}", flush=True)
+        assert (mid_items, tree_items, tail_items, phase_items) == (want_mid, want_tree, 0, len(u))
+    else:
+        assert tree_items == 0 and tail_items > 0
+    m.set_prefix_sharing(True, tree=False)
+    e3, s3, _ = nqs.local_energy(H, m, x, c)
+    m.set_prefix_sharing(False)
+    eu, su, _ = nqs.local_energy(H, m, x, c)
+    m.set_prefix_sharing(True)
+    st, s3, su = st.cpu().numpy(), s3.cpu().numpy(), su.cpu().numpy()
+    Et, E3, Eu = st[1] / st[0], s3[1] / s3[0], su[1] / su[0]
+    d_t = np.abs(et.cpu().numpy() - eu.cpu().numpy())
+    print(f"  energy tree {Et:.8f} tail {E3:.8f} unshared {Eu:.8f}; per-sample |tree - "
+          f"unshared| median {np.median(d_t):.1e} max {d_t.max():.1e}", flush=True)
+    assert abs(Et - Eu) < 1e-5 and abs(Et - E3) < 1e-5
+    ref = TransformerModel(params, sec, d // 16)
+    cv = c.cpu().numpy()
+    top = list(np.argsort(-cv, kind="stable")[:4])
+    xv = x.cpu().numpy().view(np.uint64)
+    e = et.cpu().numpy()
     res = eloc_bound.check(ref, h, eri, [int(xv[i]) for i in top], eloc_bound.gpu_amplitudes(nqs, m))
     for i, (want, A, eps) in zip(top, res):
         err = abs(e[i] - want)
