@@ -95,12 +95,12 @@ def nade_work(n_qubits, hidden):
 # size on a copy of the model before comparing with the oracle.
 TRAIN_STEPS, TRAIN_LR = 5, 1e-3
 
-# HBM bytes per launch of the dominant fused kernel (positions 10..13 of every
-# configuration, the mean of a step's three launches) on this workload, from two rocprofv3
+# HBM bytes per launch of the dominant fused kernel (TREE: positions 12 and 13
+# once per distinct prefix, the mean of a step's six launches) on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid only for the kernel source they were
 # taken on (sha256 prefix), otherwise the roofline reports null.
-FUSED_TRAFFIC = {"source_sha256_prefix": "df21d09fbd450593", "bytes_per_launch": 13.439e9,
+FUSED_TRAFFIC = {"source_sha256_prefix": "a74adbeff7591181", "bytes_per_launch": 4.454e9,
                  "profile": "profiles/fused_kernel_precision_traffic.md"}
 
 
