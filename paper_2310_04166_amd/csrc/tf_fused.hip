@@ -542,8 +542,8 @@ fused_kernel(FusedArgs a) {
   }
   if (bc0 * block_cfgs >= B) return;
   const int c = r / R;               // configuration of this lane's row within the pass
-  // position of this lane's row (TREE: row 0 of a slot at q = pm + 1, rows 1..3 at q + 1)
-  const int t = MODE == TAIL ? a.pm + r % R : MODE == TREE ? a.pm + 1 + (r % R != 0) : P0 + r % R;
+  // position of this lane's row (TREE: per slot, below)
+  const int t_lane = MODE == TAIL ? a.pm + r % R : P0 + r % R;
   const int n = a.n;
   const bf16x8 *pk = a.pk + lane;
   const float *vec = a.vec;
@@ -567,9 +567,7 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     const int kp = R == 4 ? i : R == 8 ? h * 4 + i : (i / 4) * 8 + h * 4 + (i % 4);   // key position - P0
-    // TREE: row 0 of a slot sees itself, rows 1..3 row 0 and themselves
-    const bool causal = MODE == TREE ? i == 0 || i == r % R : kp <= r % R;
-    madd[i] = causal && (R != 4 || own_half) ? 0.f : -INFINITY;
+    madd[i] = kp <= r % R && (R != 4 || own_half) ? 0.f : -INFINITY;   // (TREE: per slot)
   }
   // TAIL: the middle level's keys (positions 8 + i, those below pm; TREE: up to pm)
   float madd_mid[4];
@@ -621,13 +619,26 @@ fused_kernel(FusedArgs a) {
     const int64_t cfg0 = c_base + CPT * pass;
     if (bc * block_cfgs + CPT * pass >= B) break;   // uniform over the block
     // MID / TAIL: item cfg0 + c stands for configuration src (-1: padding);
-    // TREE: row r % 4 of slot cfg0 + c for src, its row 0 for src0
+    // TREE: row r % 4 of slot cfg0 + c for src (bits 48.. of the entry: the
+    // slot row of its parent, itself for a q-token prefix), its row 0 for src0
     constexpr int ST = MODE == TREE ? 4 : 1;        // list entries per item
-    const int64_t src0 = Rows<MODE>::LISTED ? (cfg0 + c < B ? a.src[ST * (cfg0 + c)] : -1) : cfg0 + c;
-    const int64_t src = MODE == TREE ? (cfg0 + c < B ? a.src[ST * (cfg0 + c) + r % 4] : -1) : src0;
+    constexpr int64_t kSrcBits = (int64_t(1) << 48) - 1;
+    // (padding entries are -1: masked only when not negative)
+    const int64_t raw0 = Rows<MODE>::LISTED ? (cfg0 + c < B ? a.src[ST * (cfg0 + c)] : -1) : cfg0 + c;
+    const int64_t src0 = MODE == TREE && raw0 >= 0 ? raw0 & kSrcBits : raw0;
+    const int64_t raw = MODE == TREE ? (cfg0 + c < B ? a.src[ST * (cfg0 + c) + r % 4] : -1) : src0;
+    const int64_t src = MODE == TREE ? (raw >= 0 ? raw & kSrcBits : -1) : raw;
+    const int parent = MODE == TREE && raw >= 0 ? int(raw >> 48) : r % R;
     const int64_t cfg = Rows<MODE>::LISTED ? src : cfg0 + c;
     const bool live = Rows<MODE>::LISTED ? src >= 0 : cfg < B;
     const uint64_t x = live ? a.x[cfg] : 0ull;
+    // TREE: a q-token prefix at position q = pm + 1 sees itself, an extension
+    // at q + 1 its parent's row and itself
+    const int t = MODE == TREE ? a.pm + 1 + (parent != r % R) : t_lane;
+    if constexpr (MODE == TREE) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) madd[i] = (i == r % R || i == parent) && own_half ? 0.f : -INFINITY;
+    }
     // prefix entries: of this lane's configuration (keys, log-probability) and
     // of the pass's four configurations (values)
     // (byte offsets in a.kv, below 2^31)
@@ -657,6 +668,7 @@ fused_kernel(FusedArgs a) {
     uint32_t mid_live = 0;             // bit k: item k of the pass is not padding
     if constexpr (Rows<MODE>::LISTED) {
       // (waves past the end of the items read nothing and store nothing)
+      // (row 0 of a TREE slot is a q-token prefix: its parent bits are zero)
       const int64_t s8 = cfg0 < B ? a.src[ST * cfg0] : -1;
       ent8 = s8 >= 0 ? a.pre8[s8 + 1] - 1 : 0;
       kv8_off = uint32_t(ent8 * a.kv_bytes);
@@ -1151,8 +1163,9 @@ fused_kernel(FusedArgs a) {
         logp = ((allow >> tk) & 1) ? lg[tk] - mx - lz : -INFINITY;
       if constexpr (MODE == TREE || MODE == MID) {
         if (cond_row && h == 0 && live) {
-          float *dst = MODE == MID ? a.lp_mid : r % R == 0 ? a.lp_q : a.lp_q1;
-          const int64_t e = MODE == MID ? ent12 : (r % R == 0 ? a.preq : a.preq1)[src + 1] - 1;
+          const bool root = parent == r % R;
+          float *dst = MODE == MID ? a.lp_mid : root ? a.lp_q : a.lp_q1;
+          const int64_t e = MODE == MID ? ent12 : (root ? a.preq : a.preq1)[src + 1] - 1;
 #pragma unroll
           for (int k = 0; k < 4; ++k) dst[4 * e + k] = ((allow >> k) & 1) ? lg[k] - mx - lz : -INFINITY;
         }
@@ -1444,65 +1457,95 @@ __global__ void tree_heads_kernel(const uint64_t *__restrict__ x, int64_t B, int
   hq[i] = (d & low_mask(2 * q)) != 0;
   hq1[i] = (d & low_mask(2 * q + 2)) != 0;
 }
-// firstq[k] = first configuration of q-token prefix k
-__global__ void tree_firsts_kernel(const int64_t *__restrict__ hq, const int64_t *__restrict__ preq,
-                                   int64_t B, int64_t *__restrict__ firstq) {
+// first configurations of the m-, q- and (q+1)-token prefixes
+__global__ void tree_firsts_kernel(int64_t B, const int64_t *__restrict__ hm,
+                                   const int64_t *__restrict__ hq, const int64_t *__restrict__ hq1,
+                                   const int64_t *__restrict__ prem, const int64_t *__restrict__ preq,
+                                   const int64_t *__restrict__ preq1, int64_t *__restrict__ firstm_cfg,
+                                   int64_t *__restrict__ firstq, int64_t *__restrict__ firstq1) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < B && hq[i]) firstq[preq[i]] = i;
+  if (i >= B) return;
+  if (hm[i]) firstm_cfg[prem[i]] = i;
+  if (hq[i]) firstq[preq[i]] = i;
+  if (hq1[i]) firstq1[preq1[i]] = i;
 }
-// slots of q-token prefix k: its (q+1)-token extensions, three per slot
-__global__ void tree_nodes_kernel(const int64_t *__restrict__ firstq, int64_t Q, int64_t B,
+// The slots of m-token prefix j: its q-token prefixes in order, each with its
+// (q+1)-token extensions, as pieces of a root row and up to three extension
+// rows; a piece goes into the current slot when it fits in its four rows,
+// else it opens the next one (a prefix with four extensions takes two
+// pieces, its root row repeated).  All rows of a slot share prefix j's middle
+// entry.  With `tree` null only the number of slots is returned; otherwise
+// the rows are written from slot `base` on: entry = first configuration |
+// (slot row of the parent) << 48.
+__device__ inline int64_t tree_pack(int64_t j, int64_t PM, int64_t Q, int64_t B,
+                                    const int64_t *__restrict__ firstm_cfg,
+                                    const int64_t *__restrict__ firstq,
+                                    const int64_t *__restrict__ firstq1,
+                                    const int64_t *__restrict__ preq,
+                                    const int64_t *__restrict__ preq1, int64_t base,
+                                    int64_t *__restrict__ tree) {
+  const int64_t i0 = firstm_cfg[j], i1 = j + 1 < PM ? firstm_cfg[j + 1] : B;
+  int64_t slot = -1;
+  int used = 4;                                  // rows used in the current slot
+  for (int64_t k = preq[i0]; k < preq[i1]; ++k) {
+    const int64_t c0 = preq1[firstq[k]], c1 = k + 1 < Q ? preq1[firstq[k + 1]] : preq1[B];
+    for (int64_t c = c0; c < c1;) {
+      const int piece = 1 + int(c1 - c < 3 ? c1 - c : 3);
+      if (used + piece > 4) {
+        ++slot;
+        used = 0;
+      }
+      if (tree) {
+        int64_t *row = tree + 4 * (base + slot);
+        row[used] = firstq[k] | (int64_t(used) << 48);
+        for (int e = 1; e < piece; ++e) row[used + e] = firstq1[c + e - 1] | (int64_t(used) << 48);
+      }
+      used += piece;
+      c += piece - 1;
+    }
+  }
+  return slot + 1;
+}
+__global__ void tree_count_kernel(int64_t PM, int64_t Q, int64_t B,
+                                  const int64_t *__restrict__ firstm_cfg,
+                                  const int64_t *__restrict__ firstq,
+                                  const int64_t *__restrict__ firstq1,
+                                  const int64_t *__restrict__ preq,
                                   const int64_t *__restrict__ preq1, int64_t *__restrict__ nslot) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= Q) return;
-  const int64_t i = firstq[k], inext = k + 1 < Q ? firstq[k + 1] : B;
-  nslot[k] = (preq1[inext] - preq1[i] + 2) / 3;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < PM) nslot[j] = tree_pack(j, PM, Q, B, firstm_cfg, firstq, firstq1, preq, preq1, 0, nullptr);
 }
 // per 8-token group g: slots and middle items padded to multiples of 8 (a
 // pass never mixes 8-token prefixes), zero beyond the last group
-__global__ void tree_pads_kernel(const int64_t *__restrict__ pre8, const int64_t *__restrict__ preq,
-                                 int64_t B, const int64_t *__restrict__ first8,
+__global__ void tree_pads_kernel(const int64_t *__restrict__ pre8, int64_t B,
                                  const int64_t *__restrict__ firstm, const int64_t *__restrict__ es,
                                  int64_t K, int64_t *__restrict__ pad_s, int64_t *__restrict__ pad_m) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= K) return;
   const int64_t G = pre8[B];
-  if (g >= G) {
-    pad_s[g] = 0;
-    pad_m[g] = 0;
-    return;
-  }
-  // first8[G] = B and preq[B] = the number of q-token prefixes
-  const int64_t k0 = preq[first8[g]], k1 = preq[first8[g + 1]];
-  pad_s[g] = (es[k1] - es[k0] + 7) / 8 * 8;
-  pad_m[g] = (firstm[g + 1] - firstm[g] + 7) / 8 * 8;
+  // firstm[G] = the number of m-token prefixes
+  pad_s[g] = g < G ? (es[firstm[g + 1]] - es[firstm[g]] + 7) / 8 * 8 : 0;
+  pad_m[g] = g < G ? (firstm[g + 1] - firstm[g] + 7) / 8 * 8 : 0;
 }
 // item lists: mid[start_m[g] + j - firstm[g]] = first configuration of m-token
-// prefix j; slot entries tree[4 s + 0] = first configuration of the slot's
-// q-token prefix, tree[4 s + p] (p = 1..3) = first configuration of its
-// extension 3 (s - first slot of the prefix) + p - 1
-__global__ void tree_lists_kernel(int64_t B, const int64_t *__restrict__ hm,
-                                  const int64_t *__restrict__ hq1, const int64_t *__restrict__ pre8,
-                                  const int64_t *__restrict__ prem, const int64_t *__restrict__ preq,
-                                  const int64_t *__restrict__ preq1,
-                                  const int64_t *__restrict__ first8,
+// prefix j, and its slots from start_s[g] + es[j] - es[firstm[g]]
+__global__ void tree_lists_kernel(int64_t PM, int64_t Q, int64_t B,
+                                  const int64_t *__restrict__ pre8,
                                   const int64_t *__restrict__ firstm,
-                                  const int64_t *__restrict__ firstq, const int64_t *__restrict__ es,
+                                  const int64_t *__restrict__ firstm_cfg,
+                                  const int64_t *__restrict__ firstq,
+                                  const int64_t *__restrict__ firstq1,
+                                  const int64_t *__restrict__ preq,
+                                  const int64_t *__restrict__ preq1, const int64_t *__restrict__ es,
                                   const int64_t *__restrict__ start_s,
                                   const int64_t *__restrict__ start_m, int64_t *__restrict__ mid,
                                   int64_t *__restrict__ tree) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  const int64_t g = pre8[i + 1] - 1;
-  if (hm[i]) mid[start_m[g] + prem[i] - firstm[g]] = i;
-  if (hq1[i]) {
-    const int64_t k = preq[i + 1] - 1, iq = firstq[k];
-    const int64_t rank = preq1[i] - preq1[iq];
-    const int64_t slot = start_s[g] + (es[k] - es[preq[first8[g]]]) + rank / 3;
-    const int p = 1 + int(rank % 3);
-    tree[4 * slot + p] = i;
-    if (p == 1) tree[4 * slot] = iq;
-  }
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= PM) return;
+  const int64_t i = firstm_cfg[j], g = pre8[i + 1] - 1;
+  mid[start_m[g] + j - firstm[g]] = i;
+  tree_pack(j, PM, Q, B, firstm_cfg, firstq, firstq1, preq, preq1,
+            start_s[g] + es[j] - es[firstm[g]], tree);
 }
 // log|psi| of every configuration from the stored conditionals: tokens 0..7
 // (plogp), 8..m-1 (plogp2), token m = q - 1 (lp_mid), q (lp_q), q + 1 (lp_q1)
@@ -1926,10 +1969,11 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   // prefixes, slots per prefix and their scan, groups, pads and their scans,
   // item lists (middle: one entry per item; tree: four per slot)
   const int64_t B1 = B + 1, K1 = K + 1;
-  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(11 * B1 + 6 * K1 + 5 * items) * 8));
+  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(13 * B1 + 6 * K1 + 5 * items) * 8));
   int64_t *h8 = w, *hm = h8 + B1, *hq = hm + B1, *hq1 = hq + B1;
   int64_t *pre8 = hq1 + B1, *prem = pre8 + B1, *preq = prem + B1, *preq1 = preq + B1;
-  int64_t *firstq = preq1 + B1, *nslot = firstq + B1, *es = nslot + B1;
+  int64_t *firstm_cfg = preq1 + B1, *firstq = firstm_cfg + B1, *firstq1 = firstq + B1;
+  int64_t *nslot = firstq1 + B1, *es = nslot + B1;
   int64_t *first8 = es + B1, *firstm = first8 + K1, *pad_s = firstm + K1, *pad_m = pad_s + K1;
   int64_t *start_s = pad_m + K1, *start_m = start_s + K1;
   int64_t *mid = start_m + K1, *tree = mid + items;
@@ -1948,7 +1992,8 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   hipLaunchKernelGGL(prefix_groups_kernel, g1(B), dim3(256), 0, s, x, B, h8, pre8, prem, first8,
                      firstm, list8);
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(tree_firsts_kernel, g1(B), dim3(256), 0, s, hq, preq, B, firstq);
+  hipLaunchKernelGGL(tree_firsts_kernel, g1(B), dim3(256), 0, s, B, hm, hq, hq1, prem, preq, preq1,
+                     firstm_cfg, firstq, firstq1);
   HIP_LAUNCH_OK();
   int64_t cnt[4] = {0, 0, 0, 0};
   HIP_OK(hipMemcpyAsync(&cnt[0], pre8 + B, 8, hipMemcpyDeviceToHost, s));
@@ -1961,11 +2006,12 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
               "tree forward: prefix count");
   m.tree_rows_q += Q;
   m.tree_rows_q1 += Q1;
-  hipLaunchKernelGGL(tree_nodes_kernel, g1(Q), dim3(256), 0, s, firstq, Q, B, preq1, nslot);
+  hipLaunchKernelGGL(tree_count_kernel, g1(PM), dim3(256), 0, s, PM, Q, B, firstm_cfg, firstq,
+                     firstq1, preq, preq1, nslot);
   HIP_LAUNCH_OK();
-  launch_exclusive_scan(nslot, es, Q, s, m.pf_scan);
-  hipLaunchKernelGGL(tree_pads_kernel, g1(K), dim3(256), 0, s, pre8, preq, B, first8, firstm, es,
-                     K, pad_s, pad_m);
+  launch_exclusive_scan(nslot, es, PM, s, m.pf_scan);
+  hipLaunchKernelGGL(tree_pads_kernel, g1(K), dim3(256), 0, s, pre8, B, firstm, es, K, pad_s,
+                     pad_m);
   HIP_LAUNCH_OK();
   launch_exclusive_scan(pad_s, start_s, K, s, m.pf_scan);
   launch_exclusive_scan(pad_m, start_m, K, s, m.pf_scan);
@@ -1977,11 +2023,13 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   HIP_OK(hipMemcpyAsync(fm.data(), firstm, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   // the lists' sizes are bounded by the allocation before any entry is written
-  NQS_REQUIRE(st_s[size_t(G)] <= items && st_m[size_t(G)] <= items && st_s[size_t(G)] >= Q &&
+  // (a slot holds at least one q-token prefix, and every one of those has a
+  // slot; both lists within the allocation before any entry is written)
+  NQS_REQUIRE(st_s[size_t(G)] <= items && st_m[size_t(G)] <= items && st_s[size_t(G)] * 4 >= Q &&
                   st_m[size_t(G)] >= PM,
               NQS_EINVAL, "tree forward: item lists");
-  hipLaunchKernelGGL(tree_lists_kernel, g1(B), dim3(256), 0, s, B, hm, hq1, pre8, prem, preq, preq1,
-                     first8, firstm, firstq, es, start_s, start_m, mid, tree);
+  hipLaunchKernelGGL(tree_lists_kernel, g1(PM), dim3(256), 0, s, PM, Q, B, pre8, firstm, firstm_cfg,
+                     firstq, firstq1, preq, preq1, es, start_s, start_m, mid, tree);
   HIP_LAUNCH_OK();
 
   Layout L = plan(m);

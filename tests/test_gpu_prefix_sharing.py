@@ -191,20 +191,36 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
 def expected_tree_items(u, n):
     """Items of the MID and TREE launches of the tree tail over the distinct x'
     u (q = n - 3): per 8-token prefix its distinct (q-1)-token prefixes (MID)
-    and, per distinct q-token prefix, one slot for every three of its distinct
-    (q+1)-token extensions (TREE), each padded to a multiple of 8."""
+    and their slots (TREE), each padded to a multiple of 8.  The slots of a
+    (q-1)-token prefix: its q-token prefixes in token order, each a root row
+    with its distinct (q+1)-token extensions in pieces of up to three; a piece
+    goes into the current slot of four rows if it fits, else opens the next."""
     q = n - 3
     u = np.unique(np.asarray(u, dtype=np.uint64))
     pad = lambda k: int(np.sum((k + 7) // 8 * 8))
     gm = np.unique(u & np.uint64((1 << (2 * (q - 1))) - 1))
     _, k_mid = np.unique(gm & np.uint64(0xFFFF), return_counts=True)
     g1 = np.unique(u & np.uint64((1 << (2 * (q + 1))) - 1))
-    nq, ch = np.unique(g1 & np.uint64((1 << (2 * q)) - 1), return_counts=True)
-    slots = (ch + 2) // 3
-    g8 = nq & np.uint64(0xFFFF)
-    groups, inv = np.unique(g8, return_inverse=True)
-    per = np.bincount(inv, weights=slots).astype(np.int64)
-    return pad(k_mid), pad(per)
+    nq, ext = np.unique(g1 & np.uint64((1 << (2 * q)) - 1), return_counts=True)
+    parent = nq & np.uint64((1 << (2 * (q - 1))) - 1)
+    token = (nq >> np.uint64(2 * (q - 1))) & np.uint64(3)
+    order = np.lexsort((token, parent))
+    slots = {}
+    used = {}
+    for k in order:
+        j = int(parent[k])
+        c = int(ext[k])
+        while c > 0:
+            piece = 1 + min(3, c)
+            if used.get(j, 4) + piece > 4:
+                slots[j] = slots.get(j, 0) + 1
+                used[j] = 0
+            used[j] += piece
+            c -= piece - 1
+    groups = {}
+    for j, ns in slots.items():
+        groups[j & 0xFFFF] = groups.get(j & 0xFFFF, 0) + ns
+    return pad(k_mid), pad(np.array(list(groups.values()), dtype=np.int64))
 
 
 # (n, n_alpha, n_beta, d, layers, samples, strategy, general symmetries, tree):
