@@ -155,6 +155,8 @@ struct FusedArgs {
   int64_t ln1g[kMaxLayers], ln1b[kMaxLayers], bq[kMaxLayers], bk[kMaxLayers], bv[kMaxLayers],
       bo[kMaxLayers], ln2g[kMaxLayers], ln2b[kMaxLayers], b1[kMaxLayers], b2[kMaxLayers];
   int64_t p2, p2lo;                 // phase W2 fragments (hi, lo)
+  int64_t p1, p1lo;                 // phase W1 fragments (hi, lo; PHASE): rows 4t + token, then zeros
+  int ks1;                          // k-steps of the phase W1 fragments (4 n rows)
   int64_t lnfg, lnfb, whead, bhead, lbias, tok, pos, pb1, pb2, pw3, pb3, pw1;  // vec offsets
   Sectors sec;                      // molecule(s) of the configurations
   const uint64_t *x;
@@ -1204,9 +1206,32 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       f32x16 z = lds16(svec + a.pb1 + (b * 2 + h) * 16);
-      for (int tt = 0; tt < nx; ++tt) {
-        const int row = 4 * tt + int((x >> (2 * tt)) & 3ull);
-        z += load16(vec + a.pw1 + int64_t(row) * PH + (b * 2 + h) * 16);
+      if constexpr (MODE == PHASE) {
+        // first layer on MFMA: the one-hot tokens (k = 4 t + token) times W1
+        // (hi + lo); slot i of lane half h in k-step s is token position
+        // 4 s + 2 (i / 4) + h, value i % 4 (built per k-step: a held operand
+        // array, or an unrolled k loop, spilled the registers; after the
+        // transformer rows of the other layouts it spilled them too, so those
+        // keep the row gathers below)
+        const bf16x8 *w1 = pk + a.p1 + int64_t(b) * a.ks1 * 64;
+        const bf16x8 *w1l = pk + a.p1lo + int64_t(b) * a.ks1 * 64;
+#pragma unroll 1
+        for (int s1 = 0; s1 < a.ks1; ++s1) {
+          bf16x8 oh;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int tt = 4 * s1 + 2 * (i / 4) + h;
+            oh[i] = tt < nx && int((x >> (2 * tt)) & 3ull) == i % 4 ? __bf16(1.0f) : __bf16(0.0f);
+          }
+          z = mfma(w1[s1 * 64], oh, z);
+          z = mfma(w1l[s1 * 64], oh, z);
+        }
+      } else {
+        // first layer: the sum of the configuration's token rows of W1 (fp32)
+        for (int tt = 0; tt < nx; ++tt) {
+          const int row = 4 * tt + int((x >> (2 * tt)) & 3ull);
+          z += load16(vec + a.pw1 + int64_t(row) * PH + (b * 2 + h) * 16);
+        }
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) z[j] = gelu(z[j]);
@@ -1238,15 +1263,16 @@ fused_kernel(FusedArgs a) {
 // Fragment order: (block ob, k-step s, lane l, slot i) <- W[16 s + pi_h(i)][32 ob + l%32],
 // W row-major with leading dimension ld, starting at column col0.
 // lo = 0 writes hi = bf16(w), lo = 1 writes bf16(w - hi) (w - hi is exact in fp32).
+// Rows from k_rows on read as zero.
 __global__ void pack_frag_kernel(const float *W, int64_t ld, int col0, int n_ob, int n_ks, int lo,
-                                 __bf16 *out) {
+                                 int k_rows, __bf16 *out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(n_ob) * n_ks * 64 * 8) return;
   const int i = int(idx % 8), l = int((idx / 8) % 64);
   const int64_t s = (idx / 512) % n_ks, ob = idx / (512 * int64_t(n_ks));
   const int hh = l / 32;
   const int krow = int(16 * s) + (i / 4) * 8 + hh * 4 + (i % 4);
-  const float w = W[int64_t(krow) * ld + col0 + 32 * ob + (l % 32)];
+  const float w = krow < k_rows ? W[int64_t(krow) * ld + col0 + 32 * ob + (l % 32)] : 0.f;
   const __bf16 hi = __bf16(w);
   out[idx] = lo ? __bf16(w - float(hi)) : hi;
 }
@@ -1323,6 +1349,9 @@ Layout plan(const nqs_model &m) {
   }
   L.a.p2 = frag(PH / 32, PH / 16);
   L.a.p2lo = frag(PH / 32, PH / 16);
+  L.a.ks1 = (4 * m.n + 15) / 16;
+  L.a.p1 = frag(PH / 32, L.a.ks1);
+  L.a.p1lo = frag(PH / 32, L.a.ks1);
   L.a.lnfg = vec(D);
   L.a.lnfb = vec(D);
   L.a.whead = vec(4 * D);
@@ -1674,7 +1703,7 @@ void fused_pack(nqs_model &m, hipStream_t s) {
                   int64_t lo_off, int sets) {
     for (int p = 0; p < sets; ++p) {
       hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(n_ob) * n_ks * 512), dim3(256), 0, s, src,
-                         ld, col0, n_ob, n_ks, p, pk + (o + p * lo_off) * 8);
+                         ld, col0, n_ob, n_ks, p, 16 * n_ks, pk + (o + p * lo_off) * 8);
       HIP_LAUNCH_OK();
     }
   };
@@ -1722,6 +1751,13 @@ void fused_pack(nqs_model &m, hipStream_t s) {
   perm(P(tf_tail(Lm, TF_PW3)), PH, 1, L.a.pw3);
   copy(P(tf_tail(Lm, TF_PB3)), 1, L.a.pb3);
   perm(P(tf_tail(Lm, TF_PW1)), PH, 4 * n, L.a.pw1);
+  // phase W1 (4 n rows) as MFMA fragments, rows past 4 n zero
+  for (int p = 0; p < NP; ++p) {
+    hipLaunchKernelGGL(pack_frag_kernel, g1(int64_t(PH / 32) * L.a.ks1 * 512), dim3(256), 0, s,
+                       P(tf_tail(Lm, TF_PW1)), int64_t(PH), 0, PH / 32, L.a.ks1, p, 4 * n,
+                       pk + (p == 0 ? L.a.p1 : L.a.p1lo) * 8);
+    HIP_LAUNCH_OK();
+  }
   m.packed_valid = true;
 }
 
