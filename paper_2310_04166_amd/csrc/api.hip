@@ -20,11 +20,12 @@ thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 // defined in eloc.hip
-// fp32_ratio: psi(x') / psi(x) from the log-amplitude differences in fp32 (bf16 mode)
+// fp32_ratio: psi(x') / psi(x) from the log-amplitude differences in fp32 (bf16 mode),
+// the n_amp distinct amplitudes packed as fp32 pairs into lp2_ws first (when given)
 void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,
                        const double *la_p, const double *ph_p, const double *la_x,
                        const double *ph_x, const double *hdiag, double *eloc, hipStream_t s,
-                       bool fp32_ratio);
+                       bool fp32_ratio, int64_t n_amp = 0, float2 *lp2_ws = nullptr);
 // defined in dedupe.hip
 int64_t dedupe_pairs(uint64_t *xp, int64_t n, int key_bits, int pm, uint64_t *keys_sorted,
                      uint32_t *vals_in, uint32_t *vals_sorted, uint32_t *head, uint32_t *run,
@@ -698,6 +699,8 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
     auto *hv = static_cast<double *>(H->w_h.reserve(size_t(slice) * 8));
     auto *la = static_cast<double *>(H->w_la.reserve(size_t(slice) * 8));
     auto *ph = static_cast<double *>(H->w_ph.reserve(size_t(slice) * 8));
+    auto *lp2 = m->precision == NQS_BF16 ? static_cast<float2 *>(H->w_lp2.reserve(size_t(slice) * 8))
+                                         : nullptr;
     auto *keys = static_cast<uint64_t *>(H->w_keys.reserve(size_t(slice) * 8));
     auto *ukeys = static_cast<uint64_t *>(H->w_ukeys.reserve(size_t(slice) * 8));
     auto *u32 = static_cast<uint32_t *>(H->w_u32.reserve(size_t(slice) * 4 * 5));
@@ -724,7 +727,7 @@ extern "C" int local_energy(nqs_ham *H, nqs_model *m, const uint64_t *x, const u
         else model_forward(*m, ukeys, nu, la, ph, nullptr, s);
       }
       launch_accumulate(i1 - i0, off + i0, hv, np > 0 ? uid : nullptr, la, ph, lax + i0,
-                        phx + i0, hdiag + i0, eloc + 2 * i0, s, m->precision == NQS_BF16);
+                        phx + i0, hdiag + i0, eloc + 2 * i0, s, m->precision == NQS_BF16, nu, lp2);
       i0 = i1;
     }
     launch_reduce(eloc, counts, n, sums, s);

@@ -211,13 +211,16 @@ __global__ void __launch_bounds__(1024) tile_add_kernel(int64_t *__restrict__ ou
 // the log-amplitude differences are taken in double and evaluated in fp32,
 // about 1e-7 relative per term; double in the FP64 and FP32 modes); the
 // matrix-element products and their sums stay double.
+// lp2 (optional, bf16 mode): the distinct x' log|psi| and phase as one fp32
+// pair, one 8-byte gather per pair instead of two (the fused network computes
+// both in fp32, so the pair holds them exactly).
 template <class F>
 __global__ void __launch_bounds__(256) accumulate_kernel(
     int64_t n, const int64_t *__restrict__ off, const double *__restrict__ hval,
     const uint32_t *__restrict__ uid, const double *__restrict__ la_p,
-    const double *__restrict__ ph_p, const double *__restrict__ la_x,
-    const double *__restrict__ ph_x, const double *__restrict__ hdiag,
-    double *__restrict__ eloc) {
+    const double *__restrict__ ph_p, const float2 *__restrict__ lp2,
+    const double *__restrict__ la_x, const double *__restrict__ ph_x,
+    const double *__restrict__ hdiag, double *__restrict__ eloc) {
   const int lane = threadIdx.x % kWave;
   const int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   if (i >= n) return;
@@ -236,10 +239,19 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
       u[q] = jq < j1 ? (uid ? int64_t(uid[jq]) : jq) : -1;
       hv[q] = jq < j1 ? hval[jq] : 0.0;
     }
+    if (lp2) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      lp[q] = u[q] >= 0 ? la_p[u[q]] : lx;
-      pp[q] = u[q] >= 0 ? ph_p[u[q]] : px;
+      for (int q = 0; q < Q; ++q) {
+        const float2 v = u[q] >= 0 ? lp2[u[q]] : float2{0.f, 0.f};
+        lp[q] = u[q] >= 0 ? double(v.x) : lx;
+        pp[q] = u[q] >= 0 ? double(v.y) : px;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        lp[q] = u[q] >= 0 ? la_p[u[q]] : lx;
+        pp[q] = u[q] >= 0 ? ph_p[u[q]] : px;
+      }
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -264,6 +276,12 @@ __global__ void __launch_bounds__(256) accumulate_kernel(
     eloc[2 * i] = hdiag[i] + re;
     eloc[2 * i + 1] = im;
   }
+}
+
+__global__ void pack_amp_kernel(const double *__restrict__ la, const double *__restrict__ ph,
+                                int64_t n, float2 *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = float2{float(la[i]), float(ph[i])};
 }
 
 // sums = {W, sum n Re E, sum n Im E, sum n |E|^2}; one block, fixed order.
@@ -384,15 +402,23 @@ void launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream
 void launch_accumulate(int64_t n, const int64_t *off, const double *hval, const uint32_t *uid,
                        const double *la_p, const double *ph_p, const double *la_x,
                        const double *ph_x, const double *hdiag, double *eloc, hipStream_t s,
-                       bool fp32_ratio) {
+                       bool fp32_ratio, int64_t n_amp, float2 *lp2_ws) {
   if (n <= 0) return;
   const dim3 grid(unsigned(ceil_div(n, kWavesPerBlock)));
-  if (fp32_ratio)
+  if (fp32_ratio) {
+    // distinct x' (uid set): their amplitudes packed as fp32 pairs first
+    const bool packed = uid && lp2_ws && n_amp > 0;
+    if (packed) {
+      hipLaunchKernelGGL(pack_amp_kernel, dim3(unsigned(ceil_div(n_amp, 256))), dim3(256), 0, s,
+                         la_p, ph_p, n_amp, lp2_ws);
+      HIP_LAUNCH_OK();
+    }
     hipLaunchKernelGGL(accumulate_kernel<float>, grid, dim3(256), 0, s, n, off, hval, uid, la_p,
-                       ph_p, la_x, ph_x, hdiag, eloc);
-  else
+                       ph_p, packed ? lp2_ws : nullptr, la_x, ph_x, hdiag, eloc);
+  } else {
     hipLaunchKernelGGL(accumulate_kernel<double>, grid, dim3(256), 0, s, n, off, hval, uid, la_p,
-                       ph_p, la_x, ph_x, hdiag, eloc);
+                       ph_p, nullptr, la_x, ph_x, hdiag, eloc);
+  }
   HIP_LAUNCH_OK();
 }
 

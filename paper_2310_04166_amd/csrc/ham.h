@@ -22,6 +22,7 @@ struct nqs_ham {
   // local_energy workspaces
   nqs::DevBuf w_cnt, w_off, w_xp, w_h, w_owner, w_la, w_ph, w_diag, w_lax, w_phx;
   nqs::DevBuf w_keys, w_ukeys, w_u32, w_tmp;   // distinct-x' workspaces
+  nqs::DevBuf w_lp2;                           // their amplitudes as fp32 pairs (bf16 models)
   nqs::DevBuf w_scan;                          // tile totals of the multi-block scan
   int64_t last_distinct = 0;                   // distinct x' of the last local_energy call
   int64_t last_pairs = 0;                      // (x, x') pairs of the last local_energy call
