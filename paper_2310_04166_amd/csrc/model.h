@@ -185,6 +185,9 @@ int fused_shared_levels(const nqs_model &m);
 // The middle split pm: n - 5 when the sector fixes the last token (14..16
 // tokens; that position's conditional is then a membership test), else n - 4.
 int fused_shared_pm(const nqs_model &m);
+// Whether every sector masks every level and leaves at most one token at its
+// last position (whose conditional is then 1 for that token).
+bool last_token_fixed(const nqs_model &m);
 // Three levels with the tree tail (13..15 tokens, the sector fixes the last
 // token, tail_tree on): positions 8 .. n-4 once per (n-4)-token prefix, n-3
 // once per (n-3)-token prefix and n-2 once per (n-2)-token prefix, three of

@@ -213,6 +213,20 @@ __global__ void compact_kernel(const uint64_t *__restrict__ prefix,
 }
 
 __global__ void init_kernel(unsigned long long *lost) { *lost = 0; }
+__global__ void zero_f64_kernel(double *__restrict__ p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+// The conditional logits of level p.  At the last level of a sector that
+// leaves one token there (every level masked) the split sends all counts to
+// that token whatever the logits, so the network is not evaluated: finite
+// zeros stand in for them.
+bool level_is_fixed(const nqs_model &m, int p) { return p == m.n - 1 && last_token_fixed(m); }
+void zero_logits(double *cond, int64_t B, hipStream_t s) {
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(unsigned(ceil_div(4 * B, 256))), dim3(256), 0, s, cond,
+                     4 * B);
+  HIP_LAUNCH_OK();
+}
 
 // offsets[i] = first leaf of molecule i (leaves are grouped by molecule in
 // ascending order); offsets[n_mol] = B.
@@ -247,7 +261,8 @@ int64_t walk_trees(nqs_model &m, const std::vector<uint64_t> &root_pre,
   }
   for (int p = 0; p < m.n && B > 0; ++p) {
     double *cond = static_cast<double *>(m.s_cond.reserve(size_t(B) * 4 * 8));
-    model_cond_logits(m, m.s_pre[cur].as<uint64_t>(), B, p, cond, s);
+    if (level_is_fixed(m, p)) zero_logits(cond, B, s);
+    else model_cond_logits(m, m.s_pre[cur].as<uint64_t>(), B, p, cond, s);
     auto *child = static_cast<uint64_t *>(m.s_child.reserve(size_t(B) * 4 * 8));
     auto *flag = static_cast<int64_t *>(m.s_flag.reserve(size_t(B) * 4 * 8));
     auto *off = static_cast<int64_t *>(m.s_off.reserve(size_t(B * 4 + 1) * 8));
@@ -326,7 +341,8 @@ int64_t walk_trees_device(nqs_model &m, const std::vector<uint64_t> &root_pre,
   for (int p = 0; p < m.n && cap[size_t(p)] > 0; ++p) {
     const int64_t B = cap[size_t(p)];
     const int64_t *count = p == 0 ? nullptr : nb_d + p;   // level 0: B0 nodes (host)
-    fused_forward(m, m.s_pre[cur].as<uint64_t>(), B, nullptr, nullptr, cond, p, s, count);
+    if (level_is_fixed(m, p)) zero_logits(cond, B, s);
+    else fused_forward(m, m.s_pre[cur].as<uint64_t>(), B, nullptr, nullptr, cond, p, s, count);
     hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
                        m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, count,
                        p, m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);
