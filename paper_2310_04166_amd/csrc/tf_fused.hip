@@ -660,29 +660,37 @@ fused_kernel(FusedArgs a) {
       ent_own = c == 0 ? ent[0] : c == 1 ? ent[1] : c == 2 ? ent[2] : ent[3];
       kv_own = uint32_t(ent_own * a.kv_bytes);
     }
-    // MID / TAIL: the pass's one 8-token prefix entry (its first item is never
-    // padding), the lane's pm-token prefix entry, and TAIL's value sources:
-    // the entries of configurations 4s + h (slots 0..3) and 4s + 2 + h (4..7)
-    // (the pass's eight entries are wave-uniform: scalar registers; a lane picks
-    // its two with h)
+    // MID / TAIL / TREE: the pass's items come from at most two 8-token
+    // prefixes, a (its first item, never padding) and b (its last live item);
+    // ent8 is the lane's own, m_b8 set when that is b.  The lane's pm-token
+    // prefix entry, and TAIL's value sources: the entries of configurations
+    // 4s + h (slots 0..3) and 4s + 2 + h (4..7) (the pass's eight entries are
+    // wave-uniform: scalar registers; a lane picks its two with h)
     int64_t ent8 = 0, ent12 = 0;
-    uint32_t kv8_off = 0, mid_own = 0, mid_e[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t kv8_off = 0, kv8b_off = 0, m_b8 = 0u;
+    uint32_t mid_own = 0, mid_e[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t mid_live = 0;             // bit k: item k of the pass is not padding
     if constexpr (Rows<MODE>::LISTED) {
       // (waves past the end of the items read nothing and store nothing)
       // (row 0 of a TREE slot is a q-token prefix: its parent bits are zero)
       const int64_t s8 = cfg0 < B ? a.src[ST * cfg0] : -1;
-      ent8 = s8 >= 0 ? a.pre8[s8 + 1] - 1 : 0;
-      kv8_off = uint32_t(ent8 * a.kv_bytes);
+      const int64_t e8a = s8 >= 0 ? a.pre8[s8 + 1] - 1 : 0;
       ent12 = src0 >= 0 ? a.pre12[src0 + 1] - 1 : a.j0;
       mid_own = uint32_t((ent12 - a.j0) * a.kv2_bytes);
+      int64_t s8b = -1;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int64_t it = cfg0 + k;
         const int64_t sc = it < B ? a.src[ST * it] : -1;
         mid_live |= sc >= 0 ? (1u << k) : 0u;
         mid_e[k] = uint32_t((sc >= 0 ? a.pre12[sc + 1] - 1 - a.j0 : 0) * a.kv2_bytes);
+        s8b = sc >= 0 ? sc : s8b;
       }
+      const int64_t e8b = s8b >= 0 ? a.pre8[s8b + 1] - 1 : e8a;
+      kv8_off = uint32_t(e8a * a.kv_bytes);
+      kv8b_off = uint32_t(e8b * a.kv_bytes);
+      ent8 = src0 >= 0 ? a.pre8[src0 + 1] - 1 : e8a;
+      m_b8 = ent8 != e8a ? 0xFFFFFFFFu : 0u;
     }
     // entry of item 4s + 2k + h (the values of slots 4k .. 4k+3 of k-step s)
     auto mid_v = [&](int s2, int k2) { return h ? mid_e[4 * s2 + 2 * k2 + 1] : mid_e[4 * s2 + 2 * k2]; };
@@ -750,9 +758,10 @@ fused_kernel(FusedArgs a) {
             Vk[s] = __builtin_bit_cast(bf16x8, w);
           }
         }
-        // MID / TAIL: the 8-token prefix's keys (key row r = position r % 8;
-        // rows 8..31 repeat them and are never selected) and values (slots 0..3
-        // of k-step 0 = positions 4h .. 4h+3, the rest zero); TAIL also the
+        // MID / TAIL: the 8-token prefixes' keys (key row r = position r % 8
+        // of prefix a, of prefix b for rows 8..15; rows 16..31 repeat a and are
+        // never selected) and values (k-step 0: slots 0..3 = positions
+        // 4h .. 4h+3 of a, slots 4..7 those of b); TAIL also the
         // middle level's keys (key row r = configuration r / 4, position r % 4)
         // and values (as the own values: slots 0..3 of k-step s from
         // configuration 4s + h, slots 4..7 from 4s + 2 + h), all read while Q,
@@ -762,7 +771,7 @@ fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int e = 0; e < 2; ++e)
             Kt[e] = __builtin_bit_cast(
-                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, kv8_off + kv_key_lane,
+                bf16x8, __builtin_amdgcn_raw_buffer_load_b128(kvr, ((r >> 3) == 1 ? kv8b_off : kv8_off) + kv_key_lane,
                                                               kv_key_off<NB>(l, b, e), 0));
         }
         if constexpr (Rows<MODE>::TAILS) {
@@ -776,7 +785,10 @@ fused_kernel(FusedArgs a) {
           const i32x2 v = __builtin_bit_cast(
               i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8_off + kv_val_lane,
                                                           kv_val_off<NB>(l, b), 0));
-          Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], 0, 0});
+          const i32x2 vb = __builtin_bit_cast(
+              i32x2, __builtin_amdgcn_raw_buffer_load_b64(kvr, kv8b_off + kv_val_lane,
+                                                          kv_val_off<NB>(l, b), 0));
+          Vt = __builtin_bit_cast(bf16x8, i32x4{v[0], v[1], vb[0], vb[1]});
         }
         if constexpr (Rows<MODE>::TAILS) {
 #pragma unroll
@@ -904,7 +916,7 @@ fused_kernel(FusedArgs a) {
             const f32x16 St = mfma(Kt[e], Qe, f32x16{});
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              p[NO + i] = St[i] * kScale;
+              p[NO + i] = bsel(St[i], St[4 + i], m_b8) * kScale;
               mx = fmaxf(mx, p[NO + i]);
             }
           }
@@ -978,8 +990,10 @@ fused_kernel(FusedArgs a) {
             Oe = mfma(V0, place(lw, 0), Oe);
             Oe = mfma(V1, place(lw, 1), Oe);
             pack4_hilo(p + NO, hw, lw);
-            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(hw[0]), int(hw[1]), 0, 0}), Oe);
-            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(lw[0]), int(lw[1]), 0, 0}), Oe);
+            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(hw[0] & ~m_b8), int(hw[1] & ~m_b8),
+                                                           int(hw[0] & m_b8), int(hw[1] & m_b8)}), Oe);
+            Oe = mfma(Vt, __builtin_bit_cast(bf16x8, i32x4{int(lw[0] & ~m_b8), int(lw[1] & ~m_b8),
+                                                           int(lw[0] & m_b8), int(lw[1] & m_b8)}), Oe);
             if constexpr (Rows<MODE>::TAILS) {
               pack4_hilo(p + NO + 4, hw, lw);
               Oe = mfma(Vm[0], place(hw, 0), Oe);
@@ -1544,17 +1558,15 @@ __global__ void tree_count_kernel(int64_t PM, int64_t Q, int64_t B,
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j < PM) nslot[j] = tree_pack(j, PM, Q, B, firstm_cfg, firstq, firstq1, preq, preq1, 0, nullptr);
 }
-// per 8-token group g: slots and middle items padded to multiples of 8 (a
-// pass never mixes 8-token prefixes), zero beyond the last group
-__global__ void tree_pads_kernel(const int64_t *__restrict__ pre8, int64_t B,
-                                 const int64_t *__restrict__ firstm, const int64_t *__restrict__ es,
-                                 int64_t K, int64_t *__restrict__ pad_s, int64_t *__restrict__ pad_m) {
+// per 8-token group g < G: its slots and middle items
+__global__ void tree_counts_kernel(int64_t G, const int64_t *__restrict__ firstm,
+                                   const int64_t *__restrict__ es, int64_t *__restrict__ cnt_s,
+                                   int64_t *__restrict__ cnt_m) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= K) return;
-  const int64_t G = pre8[B];
+  if (g >= G) return;
   // firstm[G] = the number of m-token prefixes
-  pad_s[g] = g < G ? (es[firstm[g + 1]] - es[firstm[g]] + 7) / 8 * 8 : 0;
-  pad_m[g] = g < G ? (firstm[g + 1] - firstm[g] + 7) / 8 * 8 : 0;
+  cnt_s[g] = es[firstm[g + 1]] - es[firstm[g]];
+  cnt_m[g] = firstm[g + 1] - firstm[g];
 }
 // item lists: mid[start_m[g] + j - firstm[g]] = first configuration of m-token
 // prefix j, and its slots from start_s[g] + es[j] - es[firstm[g]]
@@ -1987,6 +1999,31 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
   }
 }
 
+// Item list starts of the groups (cnt[g] items each) when a pass of 8 items
+// may hold two 8-token prefixes: a group follows the previous one unless the
+// pass it would start in already holds two, and every slice (cut[g] set)
+// starts a new pass.  Returns the end of the list.
+int64_t pack_group_starts(const std::vector<int64_t> &cnt, const std::vector<char> &cut,
+                          std::vector<int64_t> &start) {
+  const size_t G = cnt.size();
+  start.assign(G + 1, 0);
+  int64_t pos = 0;
+  int groups = 0;                     // groups in the pass holding pos, when pos % 8 != 0
+  for (size_t g = 0; g < G; ++g) {
+    if (pos % 8 != 0 && (cut[g] || groups >= 2)) {
+      pos = (pos + 7) / 8 * 8;
+      groups = 0;
+    }
+    start[g] = pos;
+    const int64_t end = pos + cnt[g];
+    groups = (end - 1) / 8 == pos / 8 ? (pos % 8 == 0 ? 1 : groups + 1) : 1;
+    pos = end;
+    if (pos % 8 == 0) groups = 0;
+  }
+  start[G] = pos;
+  return pos;
+}
+
 bool fused_tree(const nqs_model &m) {
   return m.tail_tree && fused_shared_levels(m) == 3 && m.n <= 15 && last_token_fixed(m);
 }
@@ -2046,24 +2083,39 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
                      firstq1, preq, preq1, nslot);
   HIP_LAUNCH_OK();
   launch_exclusive_scan(nslot, es, PM, s, m.pf_scan);
-  hipLaunchKernelGGL(tree_pads_kernel, g1(K), dim3(256), 0, s, pre8, B, firstm, es, K, pad_s,
-                     pad_m);
+  hipLaunchKernelGGL(tree_counts_kernel, g1(G), dim3(256), 0, s, G, firstm, es, pad_s, pad_m);
   HIP_LAUNCH_OK();
-  launch_exclusive_scan(pad_s, start_s, K, s, m.pf_scan);
-  launch_exclusive_scan(pad_m, start_m, K, s, m.pf_scan);
   hipLaunchKernelGGL(fill_i64_kernel, g1(5 * items), dim3(256), 0, s, mid, 5 * items, int64_t(-1));
   HIP_LAUNCH_OK();
-  std::vector<int64_t> st_s(size_t(G) + 1), st_m(size_t(G) + 1), fm(size_t(G) + 1);
-  HIP_OK(hipMemcpyAsync(st_s.data(), start_s, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(st_m.data(), start_m, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  std::vector<int64_t> cnt_s(static_cast<size_t>(G)), cnt_m(static_cast<size_t>(G)),
+      fm(static_cast<size_t>(G) + 1);
+  HIP_OK(hipMemcpyAsync(cnt_s.data(), pad_s, size_t(G) * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(cnt_m.data(), pad_m, size_t(G) * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(fm.data(), firstm, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  // the lists' sizes are bounded by the allocation before any entry is written
-  // (a slot holds at least one q-token prefix, and every one of those has a
-  // slot; both lists within the allocation before any entry is written)
-  NQS_REQUIRE(st_s[size_t(G)] <= items && st_m[size_t(G)] <= items && st_s[size_t(G)] * 4 >= Q &&
-                  st_m[size_t(G)] >= PM,
-              NQS_EINVAL, "tree forward: item lists");
+  // slices of whole groups whose middle entries fit in 32-bit offsets, each
+  // starting a new pass; then the lists' group starts, two groups per pass
+  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  std::vector<int64_t> cuts;          // first group of every slice, then G
+  std::vector<char> cut(size_t(G), 0);
+  for (int64_t g0 = 0; g0 < G;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
+    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "tree forward: slice");
+    cuts.push_back(g0);
+    cut[size_t(g0)] = 1;
+    g0 = g1;
+  }
+  cuts.push_back(G);
+  std::vector<int64_t> st_s, st_m;
+  const int64_t n_s = pack_group_starts(cnt_s, cut, st_s);
+  const int64_t n_m = pack_group_starts(cnt_m, cut, st_m);
+  // (a slot holds at least one q-token prefix; both lists within the
+  // allocation before any entry is written)
+  NQS_REQUIRE(n_s <= items && n_m <= items && n_s * 4 >= Q && n_m >= PM, NQS_EINVAL,
+              "tree forward: item lists");
+  HIP_OK(hipMemcpyAsync(start_s, st_s.data(), size_t(G + 1) * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(start_m, st_m.data(), size_t(G + 1) * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(tree_lists_kernel, g1(PM), dim3(256), 0, s, PM, Q, B, pre8, firstm, firstm_cfg,
                      firstq, firstq1, preq, preq1, es, start_s, start_m, mid, tree);
   HIP_LAUNCH_OK();
@@ -2098,25 +2150,20 @@ void fused_forward_tree(nqs_model &m, const uint64_t *x, int64_t B, double *loga
   a.B = G;
   launch_fused(m, TRUNK, a, G, s, nullptr, 0, 0);
   // positions 8 .. pm once per pm-token prefix, then the slots (positions q
-  // and q + 1), in slices of whole groups whose middle entries fit in 32-bit
-  // offsets
-  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  // and q + 1), slice by slice (a slice's items end where its last group's do)
   auto *kv2 = static_cast<uint8_t *>(m.pf3_kv.reserve(size_t(slice) * size_t(kv2_bytes)));
   a.kv2 = kv2;
   a.kv2_total = slice * kv2_bytes;
   a.x = x;
-  for (int64_t g0 = 0; g0 < G;) {
-    int64_t g1 = g0 + 1;
-    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
-    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "tree forward: slice");
-    a.j0 = fm[size_t(g0)];
-    a.src = mid + st_m[size_t(g0)];
-    a.B = st_m[size_t(g1)] - st_m[size_t(g0)];
+  for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+    const size_t g0 = size_t(cuts[c]), gl = size_t(cuts[c + 1]) - 1;
+    a.j0 = fm[g0];
+    a.src = mid + st_m[g0];
+    a.B = st_m[gl] + cnt_m[gl] - st_m[g0];
     launch_fused(m, MID, a, a.B, s, nullptr, 0, 0);
-    a.src = tree + 4 * st_s[size_t(g0)];
-    a.B = st_s[size_t(g1)] - st_s[size_t(g0)];
+    a.src = tree + 4 * st_s[g0];
+    a.B = st_s[gl] + cnt_s[gl] - st_s[g0];
     launch_fused(m, TREE, a, a.B, s, nullptr, 0, 0);
-    g0 = g1;
   }
   // the phase MLP of every configuration
   if (phase) {

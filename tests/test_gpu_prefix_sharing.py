@@ -191,13 +191,13 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
 def expected_tree_items(u, n):
     """Items of the MID and TREE launches of the tree tail over the distinct x'
     u (q = n - 3): per 8-token prefix its distinct (q-1)-token prefixes (MID)
-    and their slots (TREE), each padded to a multiple of 8.  The slots of a
+    and their slots (TREE), a pass of 8 holding at most two 8-token prefixes.
+    The slots of a
     (q-1)-token prefix: its q-token prefixes in token order, each a root row
     with its distinct (q+1)-token extensions in pieces of up to three; a piece
     goes into the current slot of four rows if it fits, else opens the next."""
     q = n - 3
     u = np.unique(np.asarray(u, dtype=np.uint64))
-    pad = lambda k: int(np.sum((k + 7) // 8 * 8))
     gm = np.unique(u & np.uint64((1 << (2 * (q - 1))) - 1))
     _, k_mid = np.unique(gm & np.uint64(0xFFFF), return_counts=True)
     g1 = np.unique(u & np.uint64((1 << (2 * (q + 1))) - 1))
@@ -220,7 +220,21 @@ def expected_tree_items(u, n):
     groups = {}
     for j, ns in slots.items():
         groups[j & 0xFFFF] = groups.get(j & 0xFFFF, 0) + ns
-    return pad(k_mid), pad(np.array(list(groups.values()), dtype=np.int64))
+    # the lists: groups in ascending order (the 8-token prefix is the most
+    # significant part of the sort key), following each other unless the pass
+    # of 8 a group would start in already holds two groups (one slice)
+    def list_end(counts):
+        pos, held = 0, 0
+        for k in counts:
+            if pos % 8 and held >= 2:
+                pos, held = (pos + 7) // 8 * 8, 0
+            end = pos + int(k)
+            held = (1 if pos % 8 == 0 else held + 1) if (end - 1) // 8 == pos // 8 else 1
+            pos = end
+            if pos % 8 == 0:
+                held = 0
+        return pos
+    return list_end(k_mid), list_end([groups[g] for g in sorted(groups)])
 
 
 # (n, n_alpha, n_beta, d, layers, samples, strategy, general symmetries, tree):
