@@ -88,12 +88,13 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // first 8 tokens; distinct x' of one step share few such prefixes (at most
 // 4^8), so TRUNK + SUFFIX do about half the work of PLAIN per configuration.
 //   MID     R = 4:  positions 8..pm-1 (pm <= 12; rows up to 11) of 8
-//                   distinct pm-token prefixes (all with one 8-token prefix),
-//                   attending to the 8-token prefix's keys and values; stores
+//                   distinct pm-token prefixes (of at most two 8-token
+//                   prefixes), attending to their 8-token prefix's keys and
+//                   values; stores
 //                   its own keys and values and the log-probability of tokens
 //                   8..pm-1 per pm-token prefix;
-//   TAIL    R = 4:  positions pm..pm+3 of 8 configurations (one 8-token
-//                   prefix), attending to both stored levels.
+//   TAIL    R = 4:  positions pm..pm+3 of 8 configurations (of at most two
+//                   8-token prefixes), attending to both stored levels.
 // pm = n - 4 makes TAIL the last four positions.  When the sector leaves one
 // token at the last position its masked conditional is 1 or 0 (a membership
 // test, no network), so pm = n - 5: TAIL takes the four positions before the
@@ -116,8 +117,10 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // slots instead of TAIL's 7.7e6 configurations (MID then covers the 11-token
 // prefixes, 1.4e6 instead of 5.9e5).
 // MID / TAIL / TREE take their items through an index list (a.src; -1 =
-// padding; TREE: four entries per slot, one per row) in which every 8-token
-// prefix starts a new pass.
+// padding; TREE: four entries per slot, one per row) in which a pass of 8
+// items holds at most two 8-token prefixes: the second one's keys take score
+// rows 8..15 and its values the k-slots 4..7 of the prefix's value step, so
+// a pass costs the same with one or two.
 enum Mode : int { PLAIN = 0, WIDE = 1, TRUNK = 2, SUFFIX = 3, MID = 4, TAIL = 5, TREE = 6, PHASE = 7 };
 template <int MODE>
 struct Rows {
@@ -1451,8 +1454,8 @@ __global__ void prefix_groups_kernel(const uint64_t *__restrict__ x, int64_t B,
     firstm[pre8[B]] = prem[B];
   }
 }
-// padded sizes of the groups' item lists (multiples of 8: a pass never mixes
-// 8-token prefixes), zero beyond the last group
+// padded sizes of the groups' item lists (multiples of 8: every 8-token
+// prefix starts a new pass on the TAIL path), zero beyond the last group
 __global__ void prefix_pads_kernel(const int64_t *__restrict__ pre8, int64_t B,
                                    const int64_t *__restrict__ first8,
                                    const int64_t *__restrict__ firstm, int64_t K,
