@@ -96,6 +96,7 @@ struct nqs_model {
   nqs::DevBuf ws, ws2, grad_acc, part, logit_buf, la_tmp, ph_tmp;  // workspaces
   nqs::DevBuf s_pre[2], s_cnt[2], s_child, s_flag, s_off, s_cond, s_lost;  // sampler
   nqs::DevBuf s_scan;                 // sampler: tile totals of the multi-block scan
+  nqs::DevBuf s_early;                // sampler: every short prefix and its conditionals
   int prefix_share = 1;               // bf16 transformer: prefix-shared evaluation of batches
   int tail_tree = 1;                  // local energy: the tree tail where the sector allows it
   int64_t tree_rows_q = 0, tree_rows_q1 = 0;  // distinct prefixes evaluated by the tree tail

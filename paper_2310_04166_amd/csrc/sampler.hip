@@ -222,6 +222,33 @@ __global__ void zero_f64_kernel(double *__restrict__ p, int64_t n) {
 // that token whatever the logits, so the network is not evaluated: finite
 // zeros stand in for them.
 bool level_is_fixed(const nqs_model &m, int p) { return p == m.n - 1 && last_token_fixed(m); }
+
+// The first levels: row p of a configuration depends on its tokens 0..p-1
+// only, so one evaluation of every (P-1)-token prefix (P = 7: 4,096 words)
+// gives the conditionals of levels 0..P-1 for every node there, each level
+// then a lookup instead of a network pass of its own (the same arithmetic per
+// row, so the same logits).  Fused bf16 transformers of one molecule.
+int early_levels(const nqs_model &m) {
+  return m.kind == NQS_MODEL_TRANSFORMER && m.precision == NQS_BF16 && !m.tagged &&
+                 fused_supported(m)
+             ? std::min(7, m.n - 1)
+             : 0;
+}
+__global__ void iota_u64_kernel(uint64_t *__restrict__ w, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = uint64_t(i);
+}
+// cond of level p < P for the frontier: the node's word holds tokens 0..p-1
+// and zeros beyond, so it is its own index among the (P-1)-token prefixes
+__global__ void early_cond_kernel(const uint64_t *__restrict__ pre, int64_t B,
+                                  const int64_t *__restrict__ count,
+                                  const double *__restrict__ early, int P, int p, uint64_t mask,
+                                  double *__restrict__ cond) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= B || (count && i >= *count)) return;
+  const int64_t idx = int64_t(pre[i] & mask);
+  for (int k = 0; k < 4; ++k) cond[4 * i + k] = early[(idx * P + p) * 4 + k];
+}
 void zero_logits(double *cond, int64_t B, hipStream_t s) {
   hipLaunchKernelGGL(zero_f64_kernel, dim3(unsigned(ceil_div(4 * B, 256))), dim3(256), 0, s, cond,
                      4 * B);
@@ -337,12 +364,33 @@ int64_t walk_trees_device(nqs_model &m, const std::vector<uint64_t> &root_pre,
     HIP_OK(hipMemcpyAsync(m.s_pre[0].ptr, root_pre.data(), size_t(B0) * 8, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(m.s_cnt[0].ptr, root_cnt.data(), size_t(B0) * 8, hipMemcpyHostToDevice, s));
   }
+  // the conditionals of levels 0..P-1 for every prefix of P-1 tokens
+  const int P = early_levels(m);
+  const int64_t n_early = P > 0 ? int64_t(1) << (2 * (P - 1)) : 0;
+  double *early = nullptr;
+  if (P > 0) {
+    auto *words = static_cast<uint64_t *>(
+        m.s_early.reserve(size_t(n_early) * 8 + size_t(n_early) * size_t(P) * 4 * 8));
+    early = reinterpret_cast<double *>(words + n_early);
+    hipLaunchKernelGGL(iota_u64_kernel, dim3(unsigned(ceil_div(n_early, 256))), dim3(256), 0, s,
+                       words, n_early);
+    HIP_LAUNCH_OK();
+    fused_forward(m, words, n_early, nullptr, nullptr, early, -P, s, nullptr);
+  }
   int64_t last = 0;   // level whose count is the result
   for (int p = 0; p < m.n && cap[size_t(p)] > 0; ++p) {
     const int64_t B = cap[size_t(p)];
     const int64_t *count = p == 0 ? nullptr : nb_d + p;   // level 0: B0 nodes (host)
-    if (level_is_fixed(m, p)) zero_logits(cond, B, s);
-    else fused_forward(m, m.s_pre[cur].as<uint64_t>(), B, nullptr, nullptr, cond, p, s, count);
+    if (level_is_fixed(m, p)) {
+      zero_logits(cond, B, s);
+    } else if (p < P) {
+      hipLaunchKernelGGL(early_cond_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
+                         m.s_pre[cur].as<uint64_t>(), B, count, early, P, p,
+                         (uint64_t(1) << (2 * (P - 1))) - 1, cond);
+      HIP_LAUNCH_OK();
+    } else {
+      fused_forward(m, m.s_pre[cur].as<uint64_t>(), B, nullptr, nullptr, cond, p, s, count);
+    }
     hipLaunchKernelGGL(split_kernel, dim3(unsigned(ceil_div(B, 256))), dim3(256), 0, s,
                        m.s_pre[cur].as<uint64_t>(), m.s_cnt[cur].as<uint64_t>(), cond, B, count,
                        p, m.sectors(), seed, child, reinterpret_cast<uint64_t *>(flag), lost_d);

@@ -165,7 +165,7 @@ struct FusedArgs {
   const uint64_t *x;
   int64_t B;                        // configurations (capacity when `count` is given)
   const int64_t *count;             // optional device-side count (persistent launches)
-  int n, L, cond_p;                 // n = positions of the model
+  int n, L, cond_p;                 // n = positions of the model; cond_p: see the logit store
   int passes;                       // passes per chunk (32 / R configurations each; 0: from *count)
   int lds_floats;                   // vec[0 .. lds_floats) is staged in LDS (all but pw1)
   double *logabs, *phase, *cond;
@@ -1153,9 +1153,12 @@ fused_kernel(FusedArgs a) {
     if (t < n) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) lg[k] += svec[a.bhead + k] + svec[a.lbias + t * 4 + k];
-      if (MODE <= WIDE && a.cond && t == a.cond_p && h == 0 && live) {
+      // the conditional logits of row cond_p, or (cond_p = -P) of rows 0..P-1
+      // at cond[(cfg P + t) 4 + k]
+      if (MODE <= WIDE && a.cond && (t == a.cond_p || t < -a.cond_p) && h == 0 && live) {
+        const int64_t o = a.cond_p < 0 ? cfg * (-a.cond_p) + t : cfg;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a.cond[cfg * 4 + k] = double(lg[k]);
+        for (int k = 0; k < 4; ++k) a.cond[o * 4 + k] = double(lg[k]);
       }
     }
     const nqs_sector_info &si = sector_of(a.sec, x);
