@@ -102,11 +102,12 @@ constexpr int64_t kMidSliceBytes = int64_t(1) << 31;
 // (n-5)-token prefixes, ~2.4x fewer than (n-4)-token ones on the
 // 30-spin-orbital system.
 //   TREE    R = 4:  when the sector fixes the last token (q = n - 3, and
-//                   pm = q - 1): each item is a slot of four rows, one distinct
-//                   q-token prefix (row 0, position q) and up to three of its
-//                   distinct (q+1)-token extensions (rows 1..3, position q + 1);
-//                   a row attends to the 8-token prefix, the
-//                   middle level and, in its slot, to row 0 and itself.  Each
+//                   pm = q - 1): each item is a slot of four rows holding
+//                   subtrees of one (q-1)-token prefix: root rows (distinct
+//                   q-token prefixes, position q), each followed by some of its
+//                   distinct (q+1)-token extensions (position q + 1); a row
+//                   attends to the 8-token prefix, the middle level and, in
+//                   its slot, to its root row and itself.  Each
 //                   row stores its masked conditional (4 log-probabilities) per
 //                   prefix; a gather over the configurations adds them up with
 //                   MID's (which also stores the conditional of its row pm) and
@@ -1523,10 +1524,11 @@ __global__ void tree_firsts_kernel(int64_t B, const int64_t *__restrict__ hm,
   if (hq1[i]) firstq1[preq1[i]] = i;
 }
 // The slots of m-token prefix j: its q-token prefixes in order, each with its
-// (q+1)-token extensions, as pieces of a root row and up to three extension
-// rows; a piece goes into the current slot when it fits in its four rows,
-// else it opens the next one (a prefix with four extensions takes two
-// pieces, its root row repeated).  All rows of a slot share prefix j's middle
+// (q+1)-token extensions, as pieces of a root row and extension rows; while
+// two or more of the current slot's four rows are free, the next piece takes
+// the root and as many extensions as fit, else the next slot opens (a prefix
+// whose extensions span two slots has its root row repeated in the second;
+// filling the free rows this way costs a repeated root row but wastes none).  All rows of a slot share prefix j's middle
 // entry.  With `tree` null only the number of slots is returned; otherwise
 // the rows are written from slot `base` on: entry = first configuration |
 // (slot row of the parent) << 48, | 1 << 47 on a repeated root (which must
@@ -1546,11 +1548,13 @@ __device__ inline int64_t tree_pack(int64_t j, int64_t PM, int64_t Q, int64_t B,
   for (int64_t k = preq[i0]; k < preq[i1]; ++k) {
     const int64_t c0 = preq1[firstq[k]], c1 = k + 1 < Q ? preq1[firstq[k + 1]] : preq1[B];
     for (int64_t c = c0; c < c1;) {
-      const int piece = 1 + int(c1 - c < 3 ? c1 - c : 3);
-      if (used + piece > 4) {
+      // fill the current slot: with two rows free or more, the root and as many
+      // extensions as fit go in, and the rest follow under a repeated root
+      if (used > 2) {
         ++slot;
         used = 0;
       }
+      const int piece = 1 + int(c1 - c < 3 - used ? c1 - c : 3 - used);
       if (tree) {
         int64_t *row = tree + 4 * (base + slot);
         // a root repeated for its later extensions: bit 47, no second store

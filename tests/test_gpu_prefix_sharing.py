@@ -194,8 +194,9 @@ def expected_tree_items(u, n):
     and their slots (TREE), a pass of 8 holding at most two 8-token prefixes.
     The slots of a
     (q-1)-token prefix: its q-token prefixes in token order, each a root row
-    with its distinct (q+1)-token extensions in pieces of up to three; a piece
-    goes into the current slot of four rows if it fits, else opens the next."""
+    with its distinct (q+1)-token extensions; with two of the current slot's
+    four rows free or more, the root and as many extensions as fit go in (the
+    rest follow under a repeated root), else the next slot opens."""
     q = n - 3
     u = np.unique(np.asarray(u, dtype=np.uint64))
     gm = np.unique(u & np.uint64((1 << (2 * (q - 1))) - 1))
@@ -211,12 +212,12 @@ def expected_tree_items(u, n):
         j = int(parent[k])
         c = int(ext[k])
         while c > 0:
-            piece = 1 + min(3, c)
-            if used.get(j, 4) + piece > 4:
+            if used.get(j, 4) > 2:
                 slots[j] = slots.get(j, 0) + 1
                 used[j] = 0
-            used[j] += piece
-            c -= piece - 1
+            take = min(c, 3 - used[j])
+            used[j] += 1 + take
+            c -= take
     groups = {}
     for j, ns in slots.items():
         groups[j & 0xFFFF] = groups.get(j & 0xFFFF, 0) + ns
