@@ -1462,18 +1462,6 @@ __global__ void prefix_groups_kernel(const uint64_t *__restrict__ x, int64_t B,
     firstm[pre8[B]] = prem[B];
   }
 }
-// padded sizes of the groups' item lists (multiples of 8: every 8-token
-// prefix starts a new pass on the TAIL path), zero beyond the last group
-__global__ void prefix_pads_kernel(const int64_t *__restrict__ pre8, int64_t B,
-                                   const int64_t *__restrict__ first8,
-                                   const int64_t *__restrict__ firstm, int64_t K,
-                                   int64_t *__restrict__ pad_t, int64_t *__restrict__ pad_m) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= K) return;
-  const int64_t G = pre8[B];
-  pad_t[g] = g < G ? (first8[g + 1] - first8[g] + 7) / 8 * 8 : 0;
-  pad_m[g] = g < G ? (firstm[g + 1] - firstm[g] + 7) / 8 * 8 : 0;
-}
 __global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1914,6 +1902,9 @@ void fused_forward_shared(nqs_model &m, const uint64_t *x, int64_t B, double *lo
   launch_fused(m, SUFFIX, a, B, s, nullptr, 0, 0);
 }
 
+int64_t pack_group_starts(const std::vector<int64_t> &cnt, const std::vector<char> &cut,
+                          std::vector<int64_t> &start);
+
 void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *logabs,
                            double *phase, hipStream_t s) {
   NQS_REQUIRE(m.packed_valid, NQS_EINVAL, "fused forward: weights not packed");
@@ -1925,11 +1916,11 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
   const int64_t kv_bytes = int64_t(m.L) * (m.d / 32) * 1024;
   const int64_t kv2_bytes = int64_t(m.L) * (m.d / 32) * 512;
   const int64_t cap8 = std::min(K, B), items = B + 7 * cap8;
-  // workspaces: flags and their scans, groups, pads and their scans, item lists
-  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(4 * (B + 1) + 6 * (K + 1) + 2 * items) * 8));
+  // workspaces: flags and their scans, groups, list starts, item lists
+  int64_t *w = static_cast<int64_t *>(m.pf3_ws.reserve(size_t(4 * (B + 1) + 4 * (K + 1) + 2 * items) * 8));
   int64_t *h8 = w, *hm = h8 + (B + 1), *pre8 = hm + (B + 1), *prem = pre8 + (B + 1);
-  int64_t *first8 = prem + (B + 1), *firstm = first8 + (K + 1), *pad_t = firstm + (K + 1);
-  int64_t *pad_m = pad_t + (K + 1), *start_t = pad_m + (K + 1), *start_m = start_t + (K + 1);
+  int64_t *first8 = prem + (B + 1), *firstm = first8 + (K + 1), *start_t = firstm + (K + 1);
+  int64_t *start_m = start_t + (K + 1);
   int64_t *tail = start_m + (K + 1), *mid = tail + items;
   auto *list8 = static_cast<uint64_t *>(m.pf_list.reserve(size_t(cap8) * 8));
   auto *plogp = static_cast<float *>(m.pf_logp.reserve(size_t(cap8) * 4));
@@ -1942,27 +1933,49 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
   hipLaunchKernelGGL(prefix_groups_kernel, g1(B), dim3(256), 0, s, x, B, h8, pre8, prem, first8,
                      firstm, list8);
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(prefix_pads_kernel, g1(K), dim3(256), 0, s, pre8, B, first8, firstm, K,
-                     pad_t, pad_m);
-  HIP_LAUNCH_OK();
-  launch_exclusive_scan(pad_t, start_t, K, s, m.pf_scan);
-  launch_exclusive_scan(pad_m, start_m, K, s, m.pf_scan);
-  hipLaunchKernelGGL(fill_i64_kernel, g1(2 * items), dim3(256), 0, s, tail, 2 * items, int64_t(-1));
-  HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(prefix_maps_kernel, g1(B), dim3(256), 0, s, B, hm, pre8, prem, first8,
-                     firstm, start_t, start_m, tail, mid);
-  HIP_LAUNCH_OK();
   int64_t cnt[2] = {0, 0};
   HIP_OK(hipMemcpyAsync(&cnt[0], pre8 + B, 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(&cnt[1], prem + B, 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const int64_t G = cnt[0], PM = cnt[1];
   NQS_REQUIRE(G >= 1 && G <= cap8 && PM >= G && PM <= B, NQS_EINVAL, "shared forward: prefix count");
-  std::vector<int64_t> st_t(size_t(G) + 1), st_m(size_t(G) + 1), fm(size_t(G) + 1);
-  HIP_OK(hipMemcpyAsync(st_t.data(), start_t, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(st_m.data(), start_m, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
+  std::vector<int64_t> f8(size_t(G) + 1), fm(size_t(G) + 1);
+  HIP_OK(hipMemcpyAsync(f8.data(), first8, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(fm.data(), firstm, size_t(G + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  // slices of whole groups whose middle entries fit in 32-bit offsets (at most
+  // kMidSlice entries), each starting a new pass; then the lists' group
+  // starts, a pass of 8 items holding up to two 8-token prefixes
+  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  std::vector<int64_t> cuts;          // first group of every slice, then G
+  std::vector<char> cut(size_t(G), 0);
+  for (int64_t g0 = 0; g0 < G;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
+    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "shared forward: slice");
+    cuts.push_back(g0);
+    cut[size_t(g0)] = 1;
+    g0 = g1;
+  }
+  cuts.push_back(G);
+  std::vector<int64_t> cnt_t(static_cast<size_t>(G)), cnt_m(static_cast<size_t>(G));
+  for (size_t g = 0; g < size_t(G); ++g) {
+    cnt_t[g] = f8[g + 1] - f8[g];
+    cnt_m[g] = fm[g + 1] - fm[g];
+  }
+  std::vector<int64_t> st_t, st_m;
+  const int64_t n_t = pack_group_starts(cnt_t, cut, st_t);
+  const int64_t n_m = pack_group_starts(cnt_m, cut, st_m);
+  // both lists within the allocation before any entry is written
+  NQS_REQUIRE(n_t <= items && n_m <= items && n_t >= B && n_m >= PM, NQS_EINVAL,
+              "shared forward: item lists");
+  HIP_OK(hipMemcpyAsync(start_t, st_t.data(), size_t(G + 1) * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(start_m, st_m.data(), size_t(G + 1) * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(fill_i64_kernel, g1(2 * items), dim3(256), 0, s, tail, 2 * items, int64_t(-1));
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(prefix_maps_kernel, g1(B), dim3(256), 0, s, B, hm, pre8, prem, first8,
+                     firstm, start_t, start_m, tail, mid);
+  HIP_LAUNCH_OK();
 
   Layout L = plan(m);
   FusedArgs a = L.a;
@@ -1987,29 +2000,24 @@ void fused_forward_shared3(nqs_model &m, const uint64_t *x, int64_t B, double *l
   a.B = G;
   launch_fused(m, TRUNK, a, G, s, nullptr, 0, 0);
   // positions 8 .. pm-1 once per pm-token prefix, then the last four of every
-  // configuration, in slices of whole groups whose middle entries fit in
-  // 32-bit offsets (at most kMidSlice entries)
-  const int64_t slice = std::min<int64_t>(PM, kMidSliceBytes / kv2_bytes);
+  // configuration, slice by slice (a slice's items end where its last group's do)
   auto *kv2 = static_cast<uint8_t *>(m.pf3_kv.reserve(size_t(slice) * size_t(kv2_bytes)));
   a.kv2 = kv2;
   a.kv2_total = slice * kv2_bytes;
   a.x = x;
-  for (int64_t g0 = 0; g0 < G;) {
-    int64_t g1 = g0 + 1;
-    while (g1 < G && fm[size_t(g1 + 1)] - fm[size_t(g0)] <= slice) ++g1;
-    NQS_REQUIRE(fm[size_t(g1)] - fm[size_t(g0)] <= slice, NQS_EINVAL, "shared forward: slice");
-    a.j0 = fm[size_t(g0)];
-    a.src = mid + st_m[size_t(g0)];
-    a.B = st_m[size_t(g1)] - st_m[size_t(g0)];
+  for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+    const size_t g0 = size_t(cuts[c]), gl = size_t(cuts[c + 1]) - 1;
+    a.j0 = fm[g0];
+    a.src = mid + st_m[g0];
+    a.B = st_m[gl] + cnt_m[gl] - st_m[g0];
     a.logabs = nullptr;
     a.phase = nullptr;
     launch_fused(m, MID, a, a.B, s, nullptr, 0, 0);
-    a.src = tail + st_t[size_t(g0)];
-    a.B = st_t[size_t(g1)] - st_t[size_t(g0)];
+    a.src = tail + st_t[g0];
+    a.B = st_t[gl] + cnt_t[gl] - st_t[g0];
     a.logabs = logabs;
     a.phase = phase;
     launch_fused(m, TAIL, a, a.B, s, nullptr, 0, 0);
-    g0 = g1;
   }
   if (pm + 4 < m.n) {
     hipLaunchKernelGGL(last_token_kernel, g1(B), dim3(256), 0, s, m.sectors(), x, B, logabs);

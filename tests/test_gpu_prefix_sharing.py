@@ -62,7 +62,7 @@ def test_distinct_prefixes_of_one_step():
 def test_three_levels_vs_unshared_and_oracle(n, na, nb, d, L, samples):
     """13..16 tokens: the local energy evaluates positions 0..7 once per 8-token
     prefix, 8 .. pm-1 once per pm-token prefix and pm .. pm+3 per configuration
-    (slices, padding to whole passes per 8-token prefix; pm = n - 4 at 13
+    (slices, passes of 8 items holding up to two 8-token prefixes; pm = n - 4 at 13
     tokens, n - 5 from 14 on, where the sector fixes the last token).  Its
     energy against the per-configuration evaluation (same bf16 operands) and,
     on the four highest-count samples, every local energy against the FP64
@@ -105,16 +105,52 @@ def test_three_levels_vs_unshared_and_oracle(n, na, nb, d, L, samples):
         assert err <= 1.5 * 2 * eps * A + 1e-9
 
 
-def expected_items(u, pm):
+# the lists: groups in ascending order (the 8-token prefix is the most
+# significant part of the sort key), following each other unless the pass
+# of 8 a group would start in already holds two groups (one slice)
+def list_end(counts):
+    pos, held = 0, 0
+    for k in counts:
+        if pos % 8 and held >= 2:
+            pos, held = (pos + 7) // 8 * 8, 0
+        end = pos + int(k)
+        held = (1 if pos % 8 == 0 else held + 1) if (end - 1) // 8 == pos // 8 else 1
+        pos = end
+        if pos % 8 == 0:
+            held = 0
+    return pos
+
+
+def slice_cuts(k_mid, entry_bytes):
+    """First group of every slice: whole groups whose middle entries
+    (entry_bytes each) fit in 2 GiB, then the number of groups."""
+    cap = min(int(np.sum(k_mid)), (1 << 31) // entry_bytes)
+    cuts, g0, G = [], 0, len(k_mid)
+    while g0 < G:
+        g1, tot = g0 + 1, int(k_mid[g0])
+        while g1 < G and tot + int(k_mid[g1]) <= cap:
+            tot += int(k_mid[g1])
+            g1 += 1
+        cuts.append(g0)
+        g0 = g1
+    return cuts + [G]
+
+
+def sliced_items(counts, cuts):
+    """Items over all slices: each slice's list starts a new pass."""
+    return sum(list_end(counts[a:b]) for a, b in zip(cuts[:-1], cuts[1:]))
+
+
+def expected_items(u, pm, entry_bytes):
     """Items of the MID and TAIL launches over the distinct x' u: per 8-token
     prefix its distinct pm-token prefixes (MID) and its configurations (TAIL),
-    each padded to a multiple of 8."""
+    a pass of 8 holding at most two 8-token prefixes, slice by slice."""
     u = np.unique(np.asarray(u, dtype=np.uint64))
-    pad = lambda k: int(np.sum((k + 7) // 8 * 8))
     gm = np.unique(u & np.uint64((1 << (2 * pm)) - 1))
     _, k_mid = np.unique(gm & np.uint64(0xFFFF), return_counts=True)
     _, k_tail = np.unique(u & np.uint64(0xFFFF), return_counts=True)
-    return pad(k_mid), pad(k_tail)
+    cuts = slice_cuts(k_mid, entry_bytes)
+    return sliced_items(k_mid, cuts), sliced_items(k_tail, cuts)
 
 
 # (n, n_alpha, n_beta, strategy, general symmetries, middle split): the split
@@ -156,7 +192,7 @@ def test_three_level_split_follows_the_sector(n, na, nb, strategy, general, pm):
     x, c, _ = nqs.sample_unique(m, 20_000, 5)
     _, xp, _, _ = nqs.connected_pairs(H, x)
     u = torch.unique(xp).cpu().numpy().view(np.uint64)
-    mid_want, tail_want = expected_items(u, pm)
+    mid_want, tail_want = expected_items(u, pm, L * (d // 32) * 512)
     nqs.timing_read()                       # drop older records
     nqs.timing_enable(True)
     try:
@@ -221,20 +257,6 @@ def expected_tree_items(u, n):
     groups = {}
     for j, ns in slots.items():
         groups[j & 0xFFFF] = groups.get(j & 0xFFFF, 0) + ns
-    # the lists: groups in ascending order (the 8-token prefix is the most
-    # significant part of the sort key), following each other unless the pass
-    # of 8 a group would start in already holds two groups (one slice)
-    def list_end(counts):
-        pos, held = 0, 0
-        for k in counts:
-            if pos % 8 and held >= 2:
-                pos, held = (pos + 7) // 8 * 8, 0
-            end = pos + int(k)
-            held = (1 if pos % 8 == 0 else held + 1) if (end - 1) // 8 == pos // 8 else 1
-            pos = end
-            if pos % 8 == 0:
-                held = 0
-        return pos
     return list_end(k_mid), list_end([groups[g] for g in sorted(groups)])
 
 
